@@ -1,0 +1,183 @@
+/*
+ * fsi_mg.h -- C ABI of the MI355X (gfx950) linear-solve hot path of a
+ * monolithic ALE Newton-Krylov FSI solver (Aulisa, Bna, Bornia, 2017).
+ *
+ * Solves J x = b, the linear system of one Newton step (section "Structure of
+ * the Jacobian": J e = -r), with right-preconditioned flexible GMRES whose
+ * preconditioner is one geometric multigrid V-cycle (section "Geometric
+ * Multigrid preconditioner") with Galerkin coarse operators supplied by the
+ * caller, a Richardson smoother preconditioned by restricted additive Schwarz
+ * on element patches split along the fluid/solid interface (section
+ * "Richardson-Schwarz smoother", B^{-1} = sum_k (R^0_k)^T B_k^{-1} R^delta_k)
+ * and a direct solve on the coarsest level.
+ *
+ * Conventions
+ *   - Every call returns fsi_status (0 = OK, > 0 informational, < 0 error).
+ *     No C++ exception crosses the ABI.  fsi_last_error() gives a
+ *     thread-local message for the last failure of the calling thread.
+ *   - Host pointers are borrowed for the duration of the call only (copied).
+ *   - Device pointers (suffix _dev) are borrowed and stream-ordered on the
+ *     HIP stream passed in (NULL = the library's own stream of the handle).
+ *   - Handles own all device memory they allocate; the library never frees
+ *     caller memory.  One fsi_mg handle is used by one thread at a time.
+ *   - Levels are indexed 0 = coarsest ... nlevels-1 = finest.
+ *   - CSR: 0-based, int64 row offsets, int32 column indices strictly
+ *     increasing within each row, FP64 values.
+ */
+#ifndef FSI_MG_H
+#define FSI_MG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FSI_ABI_VERSION 1
+
+typedef int32_t fsi_status;
+enum {
+  FSI_OK = 0,
+  FSI_NOT_CONVERGED = 1,   /* iteration limit reached; x holds the last iterate */
+  FSI_PENDING = 2,         /* serving: request not finished yet */
+  FSI_E_INVALID = -1,      /* malformed input (message says which) */
+  FSI_E_OOM = -2,          /* device allocation failed */
+  FSI_E_SINGULAR = -3,     /* zero or non-finite pivot in a block or the coarse operator */
+  FSI_E_DEVICE = -4,       /* HIP runtime error */
+  FSI_E_NONFINITE = -5,    /* NaN/Inf in the right-hand side */
+  FSI_E_CAPACITY = -6,     /* serving: request larger than the memory budget */
+  FSI_E_UNKNOWN_TICKET = -7
+};
+
+/* Precision of the V-cycle (the Krylov method, the true residual and the
+ * coarsest solve are always FP64).  MIXED_*: V-cycle vectors, operators and
+ * transfers in FP32; the owned rows of every block inverse stored in the
+ * named 16-bit type (per-row FP32 scale) and applied with FP32
+ * accumulation, followed by `refine_sweeps` FP32 refinement sweeps of the
+ * local solve; MIXED_FP32: block inverses stored in FP32. */
+enum { FSI_PREC_FP64 = 0, FSI_PREC_MIXED_BF16 = 1, FSI_PREC_MIXED_FP16 = 2, FSI_PREC_MIXED_FP32 = 3 };
+
+typedef struct {
+  int32_t nrows, ncols;
+  int64_t nnz;
+  const int64_t *rowptr;   /* nrows+1 */
+  const int32_t *colind;   /* nnz, strictly increasing per row, in [0, ncols) */
+  const double *val;       /* nnz */
+} fsi_csr;
+
+/* Schwarz patches of one level (section "Richardson-Schwarz smoother"). */
+typedef struct {
+  int32_t npatch;
+  const int64_t *ptr;      /* npatch+1 offsets into dof/owned */
+  const int32_t *dof;      /* R^delta_k: dofs of patch k, strictly increasing */
+  const uint8_t *owned;    /* 1 where patch k writes its result back (R^0_k); every
+                              free dof owned by exactly one patch */
+  const uint8_t *kind;     /* per patch: 0 fluid, 1 solid (precision policy) */
+} fsi_patches;
+
+typedef struct {
+  fsi_csr J;               /* level operator (finest: exact Jacobian, coarser: R J P) */
+  fsi_csr P;               /* n_l x n_{l-1} prolongation; ignored on level 0 */
+  fsi_csr R;               /* n_{l-1} x n_l restriction; ignored on level 0 */
+  fsi_patches patches;     /* ignored on level 0 (direct solve) */
+} fsi_level;
+
+typedef struct {
+  int32_t nu_pre, nu_post; /* Richardson sweeps before / after the coarse correction */
+  double omega;            /* Richardson damping (the paper uses 0.7) */
+  int32_t precision;       /* FSI_PREC_* */
+  int32_t solid_precision; /* precision of solid patches; -1 = same as `precision` */
+  int32_t refine_sweeps;   /* mixed only: FP32 refinement sweeps of each local solve */
+  int32_t use_graph;       /* capture the V-cycle in a hipGraph */
+} fsi_mg_opts;
+
+typedef struct {
+  int32_t restart;         /* FGMRES(m) restart length */
+  double rtol;             /* stop when |b - J x| <= rtol |b| */
+  int32_t maxit;           /* total preconditioner applications */
+  int32_t fixed_iters;     /* > 0: run exactly this many iterations, ignore rtol */
+  double *history;         /* optional host buffer of maxit+1 residual estimates */
+} fsi_krylov_opts;
+
+typedef struct {
+  int32_t iters, restarts, converged;
+  double true_relres, est_relres;
+  double setup_ms, solve_ms;
+} fsi_solve_info;
+
+struct fsi_mg;
+
+int32_t fsi_abi_version(void);
+const char *fsi_status_string(fsi_status s);
+const char *fsi_last_error(void);
+
+/* Uploads the hierarchy, extracts B_k = J_l[I_k, I_k] for every patch, inverts
+ * it (Gauss-Jordan, partial pivoting; the paper's local direct solve) keeping
+ * the rows selected by R^0_k, and inverts the coarsest operator.  Errors:
+ * FSI_E_INVALID (malformed CSR/patch lists, dimension mismatch, owned sets
+ * not a partition of the covered dofs), FSI_E_SINGULAR (message names level
+ * and patch), FSI_E_OOM, FSI_E_DEVICE. */
+fsi_status fsi_mg_setup(const fsi_level *levels, int32_t nlevels, const fsi_mg_opts *opts,
+                        void *hip_stream, struct fsi_mg **out);
+
+/* z = M^{-1} r: one V-cycle from the finest level, FP64 in and out (n_finest doubles each). */
+fsi_status fsi_mg_vcycle(struct fsi_mg *mg, const double *r_dev, double *z_dev, void *hip_stream);
+
+/* FGMRES(restart) with CGS2 on J_finest x = b; x_dev holds x0 on entry when
+ * x0_nonzero, else it is overwritten.  Returns FSI_OK, FSI_NOT_CONVERGED or
+ * an error; info (may be NULL) is filled in every case it can be. */
+fsi_status fsi_fgmres_solve(struct fsi_mg *mg, const double *b_dev, double *x_dev, int32_t x0_nonzero,
+                            const fsi_krylov_opts *kopts, fsi_solve_info *info, void *hip_stream);
+
+/* Debug/parity: applies one operator of level `level` to x_dev (device, FP64):
+ * op 0: y = J x;  1: y = r - J x (r_dev given);  2: y = P x;  3: y = R x;
+ * 4: y = sum_k R^0_k^T B_k^{-1} R^delta_k x (one Schwarz application);
+ * 5: y = coarsest direct solve of x (level 0). */
+fsi_status fsi_mg_apply(struct fsi_mg *mg, int32_t level, int32_t op, const double *x_dev,
+                        const double *r_dev, double *y_dev, void *hip_stream);
+
+/* Debug/parity: the patch lists as stored on the device (canonical order of
+ * the input) and, when blocks != NULL, the dense FP64 blocks B_k extracted
+ * on the device (row-major, concatenated, sum of m_k^2 doubles).  Host
+ * buffers sized by the caller from fsi_mg_level_info. */
+fsi_status fsi_mg_export_patches(struct fsi_mg *mg, int32_t level, int64_t *ptr, int32_t *dof,
+                                 uint8_t *owned, double *blocks);
+
+/* Sizes of level `level`: n, nnz(J), npatch, sum m_k, sum m_k^2, sum owned_k * m_k. */
+fsi_status fsi_mg_level_info(struct fsi_mg *mg, int32_t level, int64_t out[6]);
+
+fsi_status fsi_mg_destroy(struct fsi_mg *mg);
+
+/* ---------------------------------------------------------------- serving
+ * A server keeps the hierarchies of admitted systems resident on the device,
+ * admits queued requests in arrival order while their estimated device
+ * footprint fits the budget and a slot is free, and advances every active
+ * system by one FGMRES iteration per scheduling tick, the systems' kernels
+ * overlapping on the device; a converged system is retired (result copied to
+ * host, memory freed) and the next request admitted. */
+typedef struct {
+  int64_t hbm_budget_bytes; /* admission budget of device memory */
+  int32_t max_slots;        /* maximum co-resident systems */
+  int32_t device;           /* HIP device ordinal */
+} fsi_server_opts;
+
+struct fsi_server;
+
+fsi_status fsi_server_create(const fsi_server_opts *o, struct fsi_server **out);
+/* Copies the request (levels, b) and queues it; returns a ticket. */
+fsi_status fsi_serve_submit(struct fsi_server *s, const fsi_level *levels, int32_t nlevels,
+                            const double *b_host, const fsi_mg_opts *mo, const fsi_krylov_opts *ko,
+                            uint64_t *ticket);
+/* FSI_PENDING until the request finished; then copies x (n_finest doubles) to
+ * x_host and fills info; timing fields: setup_ms = queue + setup, solve_ms =
+ * solve; returns the solve's status.  A finished ticket is released. */
+fsi_status fsi_serve_poll(struct fsi_server *s, uint64_t ticket, double *x_host, fsi_solve_info *info);
+/* Server counters: [0] submitted, [1] finished, [2] active, [3] queued,
+ * [4] bytes in use, [5] peak bytes, [6] ticks, [7] max co-resident. */
+fsi_status fsi_server_stats(struct fsi_server *s, int64_t out[8]);
+fsi_status fsi_server_destroy(struct fsi_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSI_MG_H */

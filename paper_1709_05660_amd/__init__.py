@@ -1,0 +1,11 @@
+"""MI355X (gfx950) hot path of a monolithic ALE Newton-Krylov FSI solver.
+
+FGMRES preconditioned by a geometric multigrid V-cycle with a
+Richardson / restricted-additive-Schwarz smoother on interface-split patches
+(Aulisa, Bna, Bornia 2017), as hand-written HIP kernels behind a C ABI
+(include/fsi_mg.h); the host-side problem builder (include/fsi_problem.h)
+generates the linear systems.
+"""
+
+from ._lib import FsiError, lib  # noqa: F401
+from .solver import MG, Problem, mg_opts  # noqa: F401

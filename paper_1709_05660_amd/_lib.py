@@ -1,0 +1,146 @@
+"""ctypes binding of libfsimg.so (argument marshalling only).
+
+All computation happens in the native library; this module converts Python
+objects to the C structures of include/fsi_mg.h and include/fsi_problem.h.
+Loading fails loudly when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfsimg.so")
+
+FSI_OK, FSI_NOT_CONVERGED, FSI_PENDING = 0, 1, 2
+FSI_E_INVALID, FSI_E_OOM, FSI_E_SINGULAR, FSI_E_DEVICE = -1, -2, -3, -4
+FSI_E_NONFINITE, FSI_E_CAPACITY, FSI_E_UNKNOWN_TICKET = -5, -6, -7
+PREC = {"fp64": 0, "bf16": 1, "fp16": 2, "fp32": 3}
+
+
+class FsiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Csr(C.Structure):
+    _fields_ = [("nrows", C.c_int32), ("ncols", C.c_int32), ("nnz", C.c_int64),
+                ("rowptr", C.POINTER(C.c_int64)), ("colind", C.POINTER(C.c_int32)),
+                ("val", C.POINTER(C.c_double))]
+
+
+class Patches(C.Structure):
+    _fields_ = [("npatch", C.c_int32), ("ptr", C.POINTER(C.c_int64)), ("dof", C.POINTER(C.c_int32)),
+                ("owned", C.POINTER(C.c_uint8)), ("kind", C.POINTER(C.c_uint8))]
+
+
+class LevelC(C.Structure):
+    _fields_ = [("J", Csr), ("P", Csr), ("R", Csr), ("patches", Patches)]
+
+
+class MgOpts(C.Structure):
+    _fields_ = [("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("omega", C.c_double),
+                ("precision", C.c_int32), ("solid_precision", C.c_int32),
+                ("refine_sweeps", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class KrylovOpts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("rtol", C.c_double), ("maxit", C.c_int32),
+                ("fixed_iters", C.c_int32), ("history", C.POINTER(C.c_double))]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
+                ("true_relres", C.c_double), ("est_relres", C.c_double),
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ProblemSpecC(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("levels", C.c_int32), ("patch", C.c_int32),
+                ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
+                ("solid_lo", C.c_double * 3), ("solid_hi", C.c_double * 3),
+                ("rho", C.c_double), ("mu", C.c_double), ("mu_s", C.c_double),
+                ("u_peak", C.c_double), ("amp", C.c_double), ("kmax", C.c_int32),
+                ("coeffs", C.POINTER(C.c_double))]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("device", C.c_int32)]
+
+
+# every symbol the headers declare (checked by the CPU tests)
+EXPORTS = [
+    "fsi_abi_version", "fsi_status_string", "fsi_last_error", "fsi_mg_setup", "fsi_mg_vcycle",
+    "fsi_fgmres_solve", "fsi_mg_apply", "fsi_mg_export_patches", "fsi_mg_level_info",
+    "fsi_mg_destroy", "fsi_server_create", "fsi_serve_submit", "fsi_serve_poll",
+    "fsi_server_stats", "fsi_server_destroy",
+    "fsi_problem_build", "fsi_problem_nlevels", "fsi_problem_levels", "fsi_problem_vectors",
+    "fsi_problem_dirichlet", "fsi_problem_residual", "fsi_problem_destroy",
+]
+
+_lib = None
+
+
+def lib():
+    """The loaded native library (raises when it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"native library not built: {LIB_PATH} (run paper_1709_05660_amd.build)")
+    # torch's HIP runtime has the same SONAME as the one the library links;
+    # loading torch first makes the library bind to that single runtime.
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "fsi_abi_version": (C.c_int32, []),
+        "fsi_status_string": (C.c_char_p, [C.c_int32]),
+        "fsi_last_error": (C.c_char_p, []),
+        "fsi_mg_setup": (C.c_int32, [C.POINTER(LevelC), C.c_int32, C.POINTER(MgOpts), P, C.POINTER(P)]),
+        "fsi_mg_vcycle": (C.c_int32, [P, P, P, P]),
+        "fsi_fgmres_solve": (C.c_int32, [P, P, P, C.c_int32, C.POINTER(KrylovOpts), C.POINTER(SolveInfo), P]),
+        "fsi_mg_apply": (C.c_int32, [P, C.c_int32, C.c_int32, P, P, P, P]),
+        "fsi_mg_export_patches": (C.c_int32, [P, C.c_int32, P, P, P, P]),
+        "fsi_mg_level_info": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_int64)]),
+        "fsi_mg_destroy": (C.c_int32, [P]),
+        "fsi_server_create": (C.c_int32, [C.POINTER(ServerOpts), C.POINTER(P)]),
+        "fsi_serve_submit": (C.c_int32, [P, C.POINTER(LevelC), C.c_int32, P, C.POINTER(MgOpts),
+                                         C.POINTER(KrylovOpts), C.POINTER(C.c_uint64)]),
+        "fsi_serve_poll": (C.c_int32, [P, C.c_uint64, P, C.POINTER(SolveInfo)]),
+        "fsi_server_stats": (C.c_int32, [P, C.POINTER(C.c_int64)]),
+        "fsi_server_destroy": (C.c_int32, [P]),
+        "fsi_problem_build": (C.c_int32, [C.POINTER(ProblemSpecC), C.POINTER(P)]),
+        "fsi_problem_nlevels": (C.c_int32, [P]),
+        "fsi_problem_levels": (C.c_int32, [P, C.POINTER(LevelC)]),
+        "fsi_problem_vectors": (C.c_int32, [P, C.POINTER(C.POINTER(C.c_double)),
+                                            C.POINTER(C.POINTER(C.c_double)), C.POINTER(C.c_int64)]),
+        "fsi_problem_dirichlet": (C.c_int32, [P, C.c_int32, C.POINTER(C.POINTER(C.c_uint8))]),
+        "fsi_problem_residual": (C.c_int32, [P, P, P]),
+        "fsi_problem_destroy": (C.c_int32, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def check(status, what=""):
+    if status < 0:
+        msg = lib().fsi_last_error().decode()
+        raise FsiError(status, f"{what}: {msg}" if what else msg)
+    return status
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))

@@ -1,0 +1,125 @@
+// Internal host-side structures of the solver library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/fsi_mg.h"
+#include "fsi_kernels.h"
+
+namespace fsi {
+
+struct Error {
+  fsi_status code;
+  std::string msg;
+  Error(fsi_status c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+void set_error(const std::string &m);
+void hip_check(hipError_t e, const char *what);
+int pick_lpr(int64_t nnz, int64_t nrows);
+
+struct DevCsr {
+  int n = 0, m = 0, nnz = 0, lpr = 8;
+  int *rowptr = nullptr, *col = nullptr;
+  double *val = nullptr;
+  float *val32 = nullptr;
+  CsrView<double> v64() const { return CsrView<double>{n, m, nnz, rowptr, col, val}; }
+  CsrView<float> v32() const { return CsrView<float>{n, m, nnz, rowptr, col, val32}; }
+};
+
+struct Level {
+  int n = 0;
+  DevCsr J, P, R;
+  // Schwarz patches
+  int npatch = 0, mmax = 0, ntask = 0;
+  int64_t sum_m = 0, sum_m2 = 0, sum_om = 0, total_owned = 0, boff_total = 0, woff_total = 0;
+  std::vector<int64_t> h_ptr;
+  std::vector<int32_t> h_dof;
+  std::vector<uint8_t> h_owned, h_kind;
+  int *d_pm = nullptr, *d_po = nullptr, *d_dof = nullptr, *d_out_off = nullptr,
+      *d_own_local = nullptr, *d_out_idx = nullptr, *d_task_patch = nullptr,
+      *d_task_row0 = nullptr, *d_row_patch = nullptr, *d_row_local = nullptr,
+      *d_orow_patch = nullptr, *d_orow_r = nullptr;
+  int64_t *d_pdof_off = nullptr, *d_woff = nullptr, *d_boff = nullptr;
+  double *W64 = nullptr;
+  float *W32 = nullptr;
+  uint16_t *W16 = nullptr;
+  float *Wscale = nullptr;
+  int w16_kind = 0;
+  // coarsest level: column-major inverse
+  double *C0 = nullptr, *gemv_partial = nullptr;
+  // work vectors
+  double *r = nullptr, *e = nullptr, *s = nullptr;
+  float *r32 = nullptr, *e32 = nullptr, *s32 = nullptr;
+};
+
+struct Krylov {
+  int m = 0;
+  double *V = nullptr, *Z = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
+         *y = nullptr, *h1 = nullptr, *h2 = nullptr, *partial = nullptr, *npart = nullptr,
+         *nrm = nullptr, *flags = nullptr, *scal = nullptr, *w = nullptr;
+  double *pinned = nullptr;
+  std::vector<void *> owned;
+};
+
+struct GraphKey {
+  const double *r;
+  double *z;
+  bool operator<(const GraphKey &o) const { return r < o.r || (r == o.r && z < o.z); }
+};
+
+struct MG {
+  int nlevels = 0;
+  bool mixed = false;
+  fsi_mg_opts opts{};
+  std::vector<Level> lv;
+  std::vector<void *> owned;
+  hipStream_t own_stream = nullptr;
+  Krylov kry;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  double setup_ms = 0.0;
+};
+
+extern thread_local std::string g_last_error;
+
+MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipStream_t user_st,
+             hipStream_t own_st);
+void destroy_mg(MG *mg);
+void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts);
+void apply_vcycle(MG &mg, const double *r, double *z, hipStream_t st);
+void run_vcycle(MG &mg, const double *r, double *z, hipStream_t st);
+fsi_status fgmres(MG &mg, const double *b, double *x, int x0_nonzero, const fsi_krylov_opts &ko,
+                  fsi_solve_info *info, hipStream_t st);
+RasView ras_view(const Level &L);
+void ensure_krylov(MG &mg, int m);
+
+struct FgmresRun {
+  enum Phase { kFirst, kIter, kCheck, kDone };
+  MG *mg = nullptr;
+  const double *b = nullptr;
+  double *x = nullptr;
+  fsi_krylov_opts ko{};
+  hipStream_t st = nullptr;
+  Phase phase = kDone;
+  double bnorm = 0.0, beta = 0.0, est = 0.0;
+  int iters = 0, restarts = 0, j = 0, k = 0, limit = 0;
+  bool fixed = false, converged = false;
+  std::vector<double> hist;
+  std::chrono::steady_clock::time_point t0;
+  void start(MG &mg, const double *b, double *x, int x0_nonzero, const fsi_krylov_opts &ko,
+             hipStream_t st);
+  void enqueue();
+  bool complete();
+  void fill_info(fsi_solve_info *info) const;
+ private:
+  void enqueue_residual();
+  void finish_cycle();
+  void add_hist(double v);
+};
+
+}  // namespace fsi

@@ -1,0 +1,99 @@
+// Internal launch interface of the gfx950 kernels (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsi {
+
+constexpr int kWave = 64;
+constexpr int kMaxPatch = 800;      // largest Schwarz block handled by one wave's LDS slice
+constexpr int kMdotBlocks = 256;    // fixed number of partial sums in the Krylov reductions
+
+// CSR on the device: int32 offsets and columns (sizes checked at upload).
+template <typename T>
+struct CsrView {
+  int nrows, ncols, nnz;
+  const int *rowptr, *col;
+  const T *val;
+};
+
+// ---- sparse operators (a4, a6): y = A x | y = r - A x | y += A x
+enum SpmvMode { kSpmvSet = 0, kSpmvResid = 1, kSpmvAdd = 2 };
+template <typename T>
+void launch_spmv(const CsrView<T> &A, const T *x, const T *r, T *y, int mode, int lanes_per_row,
+                 hipStream_t st);
+
+// ---- setup (a1, a2, a3)
+void launch_fill_f64(double *x, int64_t n, double v, hipStream_t st);
+// B_k = J[I_k, I_k] (row-major, zero-filled beforehand)
+void launch_extract(const CsrView<double> &J, int npatch, const int *pm, const int64_t *pdof_off,
+                    const int *dof, const int64_t *boff, double *blocks, int64_t total_rows,
+                    const int *row_patch, const int *row_local, hipStream_t st);
+// in-place inverse of every block, one workgroup per block; status[k] = 0 ok, else 1 + failing step
+int gj_panel_width(int mmax);
+void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, int npatch, int mmax,
+                       int *status, hipStream_t st);
+// in-place inverse of one large matrix (row-major n x n), many workgroups per step
+void gj_large(double *A, int n, int *status_dev, double *work, hipStream_t st);
+// W_k[c * o_k + r] = Binv_k[own_row_r][c] (column-major owned rows), optional FP32/16-bit copies
+void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm, const int *po,
+                       const int64_t *woff, const int *own_off, const int *own_local, int npatch,
+                       int64_t total_owned, const int *orow_patch, const int *orow_r, double *W64,
+                       float *W32, uint16_t *W16, int w16_kind, float *wscale, hipStream_t st);
+void launch_transpose_colmajor(const double *A, int n, double *W, hipStream_t st);
+
+// ---- smoother (a5): e[out] += omega * W_k s[I_k] for every owned row
+struct RasView {
+  int ntask;
+  const int *task_patch, *task_row0;
+  const int *pm, *po;
+  const int64_t *pdof_off, *woff;
+  const int *dof, *out_off, *out_idx;
+};
+void launch_ras_f64(const RasView &v, const double *W, const double *s, double *e, double omega,
+                    hipStream_t st);
+void launch_ras_f32(const RasView &v, const float *W, const float *s, float *e, float omega,
+                    hipStream_t st);
+void launch_ras_16(const RasView &v, const uint16_t *W, int w16_kind, const float *wscale,
+                   const float *s, float *e, float omega, hipStream_t st);
+
+// ---- coarsest solve (a7): y = W x, W column-major n x n FP64
+void launch_dense_gemv(const double *W, int n, const double *x, double *y, double *partial,
+                       hipStream_t st);
+
+// ---- vectors
+void launch_cast_d2f(const double *x, float *y, int n, hipStream_t st);
+void launch_cast_f2d(const float *x, double *y, int n, hipStream_t st);
+void launch_fill_f32(float *x, int64_t n, float v, hipStream_t st);
+void launch_axpy_f64(int n, double a, const double *x, double *y, hipStream_t st);
+void launch_copy_f64(int n, const double *x, double *y, hipStream_t st);
+
+// ---- Krylov (a8, a9)
+// partial[b * ldp + i] = sum over rows of block b of V[i * ldv + row] * w[row], i < k
+void launch_mdot(int n, const double *V, int64_t ldv, int k, const double *w, double *partial,
+                 int ldp, hipStream_t st);
+// out[i] (= or +=) sum_b partial[b * ldp + i]
+void launch_mdot_finish(const double *partial, int ldp, int k, double *out, int accumulate,
+                        hipStream_t st);
+// w -= V h (k columns); if norm_partial != NULL also partial sums of w^2 (after update)
+void launch_mupdate(int n, const double *V, int64_t ldv, int k, const double *h, double *w,
+                    double *norm_partial, hipStream_t st);
+// Arnoldi column j: H[:, j] = h, hn = sqrt(nrm2), rotations, g; flags[0] = |g_{j+1}|,
+// flags[1] = breakdown, scal[0] = hn (v_{j+1} = w / hn)
+void launch_givens(double *H, int ldh, int j, const double *h, const double *nrm2, double *cs,
+                   double *sn, double *g, double *flags, double *scal, hipStream_t st);
+void launch_scale_to(int n, const double *w, const double *scal, double *v, hipStream_t st);
+// y = H^{-1} g (upper triangular k x k), then x += Z y
+void launch_backsolve(const double *H, int ldh, const double *g, int k, double *y, hipStream_t st);
+void launch_zupdate(int n, const double *Z, int64_t ldz, int k, const double *y, double *x,
+                    hipStream_t st);
+// v = r / beta with beta = sqrt(nrm2[0]); g = [beta, 0...]
+void launch_start_cycle(int n, const double *r, const double *nrm2, double *v, double *g, int m,
+                        hipStream_t st);
+
+}  // namespace fsi
+
+namespace fsi {
+// dense row-major n x n from CSR (A zero-filled beforehand)
+void launch_csr_to_dense(const CsrView<double> &A, double *dense, hipStream_t st);
+}  // namespace fsi

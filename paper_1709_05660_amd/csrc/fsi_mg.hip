@@ -1,0 +1,831 @@
+// Host side of the solver library: validation, device layouts, setup,
+// V-cycle orchestration, FGMRES, and the C ABI declared in include/fsi_mg.h.
+#include "fsi_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace fsi {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string &m) { g_last_error = m; }
+
+void hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+      throw Error(FSI_E_OOM, std::string(what) + ": " + hipGetErrorString(e));
+    throw Error(FSI_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+int pick_lpr(int64_t nnz, int64_t nrows) {
+  if (nrows <= 0) return 2;
+  const double avg = (double)nnz / (double)nrows;
+  int l = 2;
+  while (l < 64 && l * 4 < avg) l *= 2;
+  return l;
+}
+
+// ------------------------------------------------------------------ validation
+static void validate_csr(const fsi_csr &A, int64_t nrows, int64_t ncols, const char *name, int lev) {
+  char buf[256];
+  auto fail = [&](const char *why) {
+    snprintf(buf, sizeof buf, "level %d %s: %s", lev, name, why);
+    throw Error(FSI_E_INVALID, buf);
+  };
+  if (A.nrows != nrows || A.ncols != ncols) fail("dimension mismatch");
+  if (A.nnz < 0 || A.nnz >= (int64_t)1 << 31) fail("nnz out of range");
+  if (!A.rowptr || (A.nnz > 0 && (!A.colind || !A.val))) fail("null array");
+  if (A.rowptr[0] != 0 || A.rowptr[A.nrows] != A.nnz) fail("row offsets do not span nnz");
+  for (int64_t r = 0; r < A.nrows; ++r) {
+    if (A.rowptr[r + 1] < A.rowptr[r]) fail("row offsets not monotone");
+    for (int64_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p) {
+      const int32_t c = A.colind[p];
+      if (c < 0 || c >= ncols) fail("column index out of range");
+      if (p > A.rowptr[r] && c <= A.colind[p - 1]) fail("columns not strictly increasing");
+    }
+  }
+}
+
+static void validate_patches(const fsi_patches &P, int64_t n, int lev) {
+  char buf[256];
+  auto fail = [&](const char *why, int64_t k) {
+    snprintf(buf, sizeof buf, "level %d patches: %s (patch %lld)", lev, why, (long long)k);
+    throw Error(FSI_E_INVALID, buf);
+  };
+  if (P.npatch <= 0 || !P.ptr || !P.dof || !P.owned) fail("no patches", -1);
+  if (P.ptr[0] != 0) fail("ptr[0] != 0", 0);
+  std::vector<int> owner_count(n, 0), present(n, 0);
+  for (int k = 0; k < P.npatch; ++k) {
+    const int64_t a = P.ptr[k], b = P.ptr[k + 1];
+    if (b <= a) fail("empty patch", k);
+    if (b - a > kMaxPatch) fail("patch larger than the supported block size", k);
+    for (int64_t p = a; p < b; ++p) {
+      const int32_t d = P.dof[p];
+      if (d < 0 || d >= n) fail("dof out of range", k);
+      if (p > a && d <= P.dof[p - 1]) fail("dofs not strictly increasing", k);
+      present[d] = 1;
+      if (P.owned[p]) owner_count[d]++;
+    }
+  }
+  for (int64_t d = 0; d < n; ++d) {
+    if (owner_count[d] > 1) fail("dof owned by more than one patch", d);
+    if (present[d] && owner_count[d] == 0) fail("dof covered but owned by no patch", d);
+  }
+}
+
+// ------------------------------------------------------------------ device helpers
+template <typename T>
+T *dalloc(int64_t n, std::vector<void *> &owned) {
+  if (n <= 0) return nullptr;
+  void *p = nullptr;
+  hip_check(hipMalloc(&p, sizeof(T) * (size_t)n), "hipMalloc");
+  owned.push_back(p);
+  return static_cast<T *>(p);
+}
+template <typename T>
+T *dupload(const T *h, int64_t n, std::vector<void *> &owned, hipStream_t st) {
+  T *d = dalloc<T>(n, owned);
+  if (n > 0) hip_check(hipMemcpyAsync(d, h, sizeof(T) * (size_t)n, hipMemcpyHostToDevice, st), "H2D");
+  return d;
+}
+
+static void upload_csr(const fsi_csr &A, DevCsr &D, bool want32, std::vector<void *> &own,
+                       hipStream_t st) {
+  D.n = A.nrows;
+  D.m = A.ncols;
+  D.nnz = (int)A.nnz;
+  std::vector<int32_t> rp(A.nrows + 1);
+  for (int64_t i = 0; i <= A.nrows; ++i) rp[i] = (int32_t)A.rowptr[i];
+  D.rowptr = dupload(rp.data(), A.nrows + 1, own, st);
+  D.col = dupload(A.colind, A.nnz, own, st);
+  D.val = dupload(A.val, A.nnz, own, st);
+  if (want32) {
+    std::vector<float> v32(A.nnz);
+    for (int64_t i = 0; i < A.nnz; ++i) v32[i] = (float)A.val[i];
+    D.val32 = dupload(v32.data(), A.nnz, own, st);
+  }
+  D.lpr = pick_lpr(A.nnz, A.nrows);
+  hip_check(hipStreamSynchronize(st), "upload");
+}
+
+// ------------------------------------------------------------------ patch layout
+static void build_patch_layout(Level &L, const fsi_patches &P, MG &mg, hipStream_t st) {
+  L.npatch = P.npatch;
+  const int np = P.npatch;
+  L.h_ptr.assign(P.ptr, P.ptr + np + 1);
+  L.h_dof.assign(P.dof, P.dof + P.ptr[np]);
+  L.h_owned.assign(P.owned, P.owned + P.ptr[np]);
+  L.h_kind.assign(np, 0);
+  if (P.kind) L.h_kind.assign(P.kind, P.kind + np);
+  std::vector<int> pm(np), po(np), out_off(np + 1, 0), own_local, out_idx, task_patch, task_row0;
+  std::vector<int64_t> pdof_off(np), woff(np + 1, 0), boff(np + 1, 0);
+  std::vector<int> row_patch, row_local, orow_patch, orow_r;
+  L.mmax = 0;
+  L.sum_m = L.sum_m2 = L.sum_om = 0;
+  for (int k = 0; k < np; ++k) {
+    const int64_t a = P.ptr[k], b = P.ptr[k + 1];
+    pm[k] = (int)(b - a);
+    pdof_off[k] = a;
+    int o = 0;
+    for (int64_t p = a; p < b; ++p)
+      if (P.owned[p]) {
+        own_local.push_back((int)(p - a));
+        out_idx.push_back(P.dof[p]);
+        orow_patch.push_back(k);
+        orow_r.push_back(o);
+        ++o;
+      }
+    po[k] = o;
+    out_off[k + 1] = out_off[k] + o;
+    woff[k + 1] = woff[k] + (int64_t)o * pm[k];
+    boff[k + 1] = boff[k] + (int64_t)pm[k] * pm[k];
+    for (int i = 0; i < pm[k]; ++i) {
+      row_patch.push_back(k);
+      row_local.push_back(i);
+    }
+    for (int r0 = 0; r0 < o; r0 += 64) {
+      task_patch.push_back(k);
+      task_row0.push_back(r0);
+    }
+    L.mmax = std::max(L.mmax, pm[k]);
+    L.sum_m += pm[k];
+    L.sum_m2 += (int64_t)pm[k] * pm[k];
+    L.sum_om += (int64_t)o * pm[k];
+  }
+  L.total_owned = out_off[np];
+  L.ntask = (int)task_patch.size();
+  auto &own = mg.owned;
+  L.d_pm = dupload(pm.data(), np, own, st);
+  L.d_po = dupload(po.data(), np, own, st);
+  L.d_pdof_off = dupload(pdof_off.data(), np, own, st);
+  L.d_woff = dupload(woff.data(), np + 1, own, st);
+  L.d_boff = dupload(boff.data(), np + 1, own, st);
+  L.d_dof = dupload(P.dof, P.ptr[np], own, st);
+  L.d_out_off = dupload(out_off.data(), np + 1, own, st);
+  L.d_own_local = dupload(own_local.data(), (int64_t)own_local.size(), own, st);
+  L.d_out_idx = dupload(out_idx.data(), (int64_t)out_idx.size(), own, st);
+  L.d_task_patch = dupload(task_patch.data(), (int64_t)task_patch.size(), own, st);
+  L.d_task_row0 = dupload(task_row0.data(), (int64_t)task_row0.size(), own, st);
+  L.d_row_patch = dupload(row_patch.data(), (int64_t)row_patch.size(), own, st);
+  L.d_row_local = dupload(row_local.data(), (int64_t)row_local.size(), own, st);
+  L.d_orow_patch = dupload(orow_patch.data(), (int64_t)orow_patch.size(), own, st);
+  L.d_orow_r = dupload(orow_r.data(), (int64_t)orow_r.size(), own, st);
+  L.boff_total = boff[np];
+  L.woff_total = woff[np];
+  hip_check(hipStreamSynchronize(st), "patch layout");
+}
+
+RasView ras_view(const Level &L) {
+  RasView v;
+  v.ntask = L.ntask;
+  v.task_patch = L.d_task_patch;
+  v.task_row0 = L.d_task_row0;
+  v.pm = L.d_pm;
+  v.po = L.d_po;
+  v.pdof_off = L.d_pdof_off;
+  v.woff = L.d_woff;
+  v.dof = L.d_dof;
+  v.out_off = L.d_out_off;
+  v.out_idx = L.d_out_idx;
+  return v;
+}
+
+// B_k = J[I_k, I_k] for every patch into a fresh device buffer (Sum m_k^2 doubles)
+double *extract_blocks(MG &mg, Level &L, hipStream_t st, std::vector<void *> &tmp) {
+  double *B = dalloc<double>(L.boff_total, tmp);
+  launch_fill_f64(B, L.boff_total, 0.0, st);
+  launch_extract(L.J.v64(), L.npatch, L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff, B, L.sum_m,
+                 L.d_row_patch, L.d_row_local, st);
+  return B;
+}
+
+static void free_list(std::vector<void *> &v) {
+  for (void *p : v) (void)hipFree(p);
+  v.clear();
+}
+
+// inverse of every block, keep the owned rows in the storage precision of the level
+static void setup_level_blocks(MG &mg, Level &L, int lev, hipStream_t st) {
+  std::vector<void *> tmp;
+  try {
+    double *B = extract_blocks(mg, L, st, tmp);
+    int *status = dalloc<int>(L.npatch, tmp);
+    launch_gj_batched(B, L.d_boff, L.d_pm, L.npatch, L.mmax, status, st);
+    hip_check(hipGetLastError(), "gj launch");
+    std::vector<int> hs(L.npatch);
+    hip_check(hipMemcpyAsync(hs.data(), status, sizeof(int) * L.npatch, hipMemcpyDeviceToHost, st),
+              "D2H status");
+    hip_check(hipStreamSynchronize(st), "block inversion");
+    for (int k = 0; k < L.npatch; ++k)
+      if (hs[k]) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "level %d patch %d: zero or non-finite pivot at step %d", lev, k,
+                 hs[k] - 1);
+        throw Error(FSI_E_SINGULAR, buf);
+      }
+    const int prec = mg.opts.precision;
+    if (prec == FSI_PREC_FP64) {
+      L.W64 = dalloc<double>(L.woff_total, mg.owned);
+    } else if (prec == FSI_PREC_MIXED_FP32) {
+      L.W32 = dalloc<float>(L.woff_total, mg.owned);
+    } else {
+      L.W16 = dalloc<uint16_t>(L.woff_total, mg.owned);
+      L.Wscale = dalloc<float>(L.total_owned, mg.owned);
+      L.w16_kind = prec == FSI_PREC_MIXED_BF16 ? 1 : 2;
+    }
+    launch_pack_owned(B, L.d_boff, L.d_pm, L.d_po, L.d_woff, L.d_out_off, L.d_own_local, L.npatch,
+                      L.total_owned, L.d_orow_patch, L.d_orow_r, L.W64, L.W32, L.W16, L.w16_kind,
+                      L.Wscale, st);
+    hip_check(hipGetLastError(), "pack launch");
+    hip_check(hipStreamSynchronize(st), "pack");
+  } catch (...) {
+    free_list(tmp);
+    throw;
+  }
+  free_list(tmp);
+}
+
+static void setup_coarse(MG &mg, Level &L, hipStream_t st) {
+  const int n = L.n;
+  std::vector<void *> tmp;
+  try {
+    double *A = dalloc<double>((int64_t)n * n, tmp);
+    launch_fill_f64(A, (int64_t)n * n, 0.0, st);
+    launch_csr_to_dense(L.J.v64(), A, st);
+    double *work = dalloc<double>((int64_t)(2 + 16) * n + 64, tmp);
+    int *status = dalloc<int>(1, tmp);
+    hip_check(hipMemsetAsync(status, 0, sizeof(int), st), "memset");
+    gj_large(A, n, status, work, st);
+    hip_check(hipGetLastError(), "coarse gj launch");
+    int hs = 0;
+    hip_check(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, st), "D2H");
+    hip_check(hipStreamSynchronize(st), "coarse inversion");
+    if (hs) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "level 0 (coarsest): zero or non-finite pivot at step %d", hs - 1);
+      throw Error(FSI_E_SINGULAR, buf);
+    }
+    L.C0 = dalloc<double>((int64_t)n * n, mg.owned);
+    launch_transpose_colmajor(A, n, L.C0, st);
+    L.gemv_partial = dalloc<double>((int64_t)8 * n, mg.owned);
+    hip_check(hipStreamSynchronize(st), "coarse transpose");
+  } catch (...) {
+    free_list(tmp);
+    throw;
+  }
+  free_list(tmp);
+}
+
+// ------------------------------------------------------------------ V-cycle
+static void ras64(MG &mg, Level &L, const double *s, double *e, hipStream_t st) {
+  launch_ras_f64(ras_view(L), L.W64, s, e, mg.opts.omega, st);
+}
+static void ras32(MG &mg, Level &L, const float *s, float *e, hipStream_t st) {
+  if (L.W32)
+    launch_ras_f32(ras_view(L), L.W32, s, e, (float)mg.opts.omega, st);
+  else
+    launch_ras_16(ras_view(L), L.W16, L.w16_kind, L.Wscale, s, e, (float)mg.opts.omega, st);
+}
+
+// FP64 V-cycle on level l: input L.r, output L.e
+static void vcycle64(MG &mg, int l, hipStream_t st) {
+  Level &L = mg.lv[l];
+  if (l == 0) {
+    launch_dense_gemv(L.C0, L.n, L.r, L.e, L.gemv_partial, st);
+    return;
+  }
+  Level &C = mg.lv[l - 1];
+  const auto J = L.J.v64();
+  launch_fill_f64(L.e, L.n, 0.0, st);
+  for (int it = 0; it < mg.opts.nu_pre; ++it) {
+    if (it == 0) {
+      ras64(mg, L, L.r, L.e, st);
+    } else {
+      launch_spmv(J, L.e, L.r, L.s, kSpmvResid, L.J.lpr, st);
+      ras64(mg, L, L.s, L.e, st);
+    }
+  }
+  if (mg.opts.nu_pre == 0)
+    launch_copy_f64(L.n, L.r, L.s, st);
+  else
+    launch_spmv(J, L.e, L.r, L.s, kSpmvResid, L.J.lpr, st);
+  launch_spmv(L.R.v64(), L.s, (const double *)nullptr, C.r, kSpmvSet, L.R.lpr, st);
+  vcycle64(mg, l - 1, st);
+  launch_spmv(L.P.v64(), C.e, (const double *)nullptr, L.e, kSpmvAdd, L.P.lpr, st);
+  for (int it = 0; it < mg.opts.nu_post; ++it) {
+    launch_spmv(J, L.e, L.r, L.s, kSpmvResid, L.J.lpr, st);
+    ras64(mg, L, L.s, L.e, st);
+  }
+}
+
+// mixed V-cycle: FP32 on levels >= 1, FP64 coarsest solve
+static void vcycle32(MG &mg, int l, hipStream_t st) {
+  Level &L = mg.lv[l];
+  if (l == 0) {
+    launch_cast_f2d(L.r32, L.r, L.n, st);
+    launch_dense_gemv(L.C0, L.n, L.r, L.e, L.gemv_partial, st);
+    launch_cast_d2f(L.e, L.e32, L.n, st);
+    return;
+  }
+  Level &C = mg.lv[l - 1];
+  const auto J = L.J.v32();
+  launch_fill_f32(L.e32, L.n, 0.0f, st);
+  for (int it = 0; it < mg.opts.nu_pre; ++it) {
+    if (it == 0) {
+      ras32(mg, L, L.r32, L.e32, st);
+    } else {
+      launch_spmv(J, L.e32, L.r32, L.s32, kSpmvResid, L.J.lpr, st);
+      ras32(mg, L, L.s32, L.e32, st);
+    }
+  }
+  launch_spmv(J, L.e32, L.r32, L.s32, kSpmvResid, L.J.lpr, st);
+  launch_spmv(L.R.v32(), L.s32, (const float *)nullptr, C.r32, kSpmvSet, L.R.lpr, st);
+  vcycle32(mg, l - 1, st);
+  launch_spmv(L.P.v32(), C.e32, (const float *)nullptr, L.e32, kSpmvAdd, L.P.lpr, st);
+  for (int it = 0; it < mg.opts.nu_post; ++it) {
+    launch_spmv(J, L.e32, L.r32, L.s32, kSpmvResid, L.J.lpr, st);
+    ras32(mg, L, L.s32, L.e32, st);
+  }
+}
+
+// z = M^{-1} r (device FP64 vectors of the finest size)
+void apply_vcycle(MG &mg, const double *r, double *z, hipStream_t st) {
+  Level &F = mg.lv.back();
+  if (mg.mixed) {
+    launch_cast_d2f(r, F.r32, F.n, st);
+    vcycle32(mg, mg.nlevels - 1, st);
+    launch_cast_f2d(F.e32, z, F.n, st);
+  } else {
+    launch_copy_f64(F.n, r, F.r, st);
+    vcycle64(mg, mg.nlevels - 1, st);
+    launch_copy_f64(F.n, F.e, z, st);
+  }
+}
+
+void run_vcycle(MG &mg, const double *r, double *z, hipStream_t st) {
+  if (mg.opts.use_graph) {
+    // one graph per (input, output) pair; the Krylov loop reuses a small set of pairs
+    GraphKey key{r, z};
+    auto it = mg.graphs.find(key);
+    if (it == mg.graphs.end()) {
+      hipGraph_t g;
+      hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+      apply_vcycle(mg, r, z, st);
+      hip_check(hipStreamEndCapture(st, &g), "end capture");
+      hipGraphExec_t ex;
+      hip_check(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "instantiate");
+      (void)hipGraphDestroy(g);
+      it = mg.graphs.emplace(key, ex).first;
+    }
+    hip_check(hipGraphLaunch(it->second, st), "graph launch");
+  } else {
+    apply_vcycle(mg, r, z, st);
+  }
+}
+
+// ------------------------------------------------------------------ setup
+void alloc_level_vectors(MG &mg, Level &L) {
+  L.r = dalloc<double>(L.n, mg.owned);
+  L.e = dalloc<double>(L.n, mg.owned);
+  L.s = dalloc<double>(L.n, mg.owned);
+  if (mg.mixed) {
+    L.r32 = dalloc<float>(L.n, mg.owned);
+    L.e32 = dalloc<float>(L.n, mg.owned);
+    L.s32 = dalloc<float>(L.n, mg.owned);
+  }
+}
+
+// host-side checks of the whole hierarchy (no device call)
+void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts) {
+  if (!levels || nlevels < 1) throw Error(FSI_E_INVALID, "no levels");
+  if (!opts) throw Error(FSI_E_INVALID, "no options");
+  if (opts->nu_pre < 0 || opts->nu_post < 0 || !(opts->omega > 0.0) ||
+      opts->precision < FSI_PREC_FP64 || opts->precision > FSI_PREC_MIXED_FP32)
+    throw Error(FSI_E_INVALID, "invalid multigrid options");
+  std::vector<int64_t> n(nlevels);
+  for (int l = 0; l < nlevels; ++l) n[l] = levels[l].J.nrows;
+  for (int l = 0; l < nlevels; ++l) {
+    if (n[l] < 1) throw Error(FSI_E_INVALID, "empty level");
+    validate_csr(levels[l].J, n[l], n[l], "J", l);
+    if (l > 0) {
+      validate_csr(levels[l].P, n[l], n[l - 1], "P", l);
+      validate_csr(levels[l].R, n[l - 1], n[l], "R", l);
+      validate_patches(levels[l].patches, n[l], l);
+    }
+  }
+}
+
+MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipStream_t user_st,
+             hipStream_t own_st) {
+  auto t0 = std::chrono::steady_clock::now();
+  validate_levels(levels, nlevels, opts);
+  std::vector<int64_t> n(nlevels);
+  for (int l = 0; l < nlevels; ++l) n[l] = levels[l].J.nrows;
+  MG *mg = new MG();
+  mg->opts = *opts;
+  mg->nlevels = nlevels;
+  mg->mixed = opts->precision != FSI_PREC_FP64;
+  mg->own_stream = own_st;
+  hipStream_t st = user_st ? user_st : own_st;
+  try {
+    mg->lv.resize(nlevels);
+    for (int l = 0; l < nlevels; ++l) {
+      Level &L = mg->lv[l];
+      L.n = (int)n[l];
+      upload_csr(levels[l].J, L.J, mg->mixed && l > 0, mg->owned, st);
+      if (l > 0) {
+        upload_csr(levels[l].P, L.P, mg->mixed, mg->owned, st);
+        upload_csr(levels[l].R, L.R, mg->mixed, mg->owned, st);
+        build_patch_layout(L, levels[l].patches, *mg, st);
+      }
+      alloc_level_vectors(*mg, L);
+    }
+    setup_coarse(*mg, mg->lv[0], st);
+    for (int l = 1; l < nlevels; ++l) setup_level_blocks(*mg, mg->lv[l], l, st);
+    hip_check(hipStreamSynchronize(st), "setup");
+  } catch (...) {
+    destroy_mg(mg);
+    throw;
+  }
+  mg->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return mg;
+}
+
+void destroy_mg(MG *mg) {
+  if (!mg) return;
+  for (auto &kv : mg->graphs) (void)hipGraphExecDestroy(kv.second);
+  mg->graphs.clear();
+  free_list(mg->owned);
+  free_list(mg->kry.owned);
+  if (mg->kry.pinned) (void)hipHostFree(mg->kry.pinned);
+  delete mg;
+}
+
+// ------------------------------------------------------------------ FGMRES
+void ensure_krylov(MG &mg, int m) {
+  Krylov &K = mg.kry;
+  const int n = mg.lv.back().n;
+  if (K.m == m && K.V) return;
+  free_list(K.owned);
+  K.m = m;
+  K.V = dalloc<double>((int64_t)n * (m + 1), K.owned);
+  K.Z = dalloc<double>((int64_t)n * m, K.owned);
+  K.H = dalloc<double>((int64_t)(m + 1) * m, K.owned);
+  K.cs = dalloc<double>(m + 1, K.owned);
+  K.sn = dalloc<double>(m + 1, K.owned);
+  K.g = dalloc<double>(m + 2, K.owned);
+  K.y = dalloc<double>(m + 1, K.owned);
+  K.h1 = dalloc<double>(m + 2, K.owned);
+  K.h2 = dalloc<double>(m + 2, K.owned);
+  K.partial = dalloc<double>((int64_t)kMdotBlocks * (m + 2), K.owned);
+  K.npart = dalloc<double>(kMdotBlocks, K.owned);
+  K.nrm = dalloc<double>(4, K.owned);
+  K.flags = dalloc<double>(4, K.owned);
+  K.scal = dalloc<double>(4, K.owned);
+  K.w = dalloc<double>(n, K.owned);
+  if (!K.pinned) hip_check(hipHostMalloc((void **)&K.pinned, 8 * sizeof(double), 0), "pinned");
+}
+
+// ---- FGMRES as a host state machine: enqueue() puts the next unit of work on
+// the stream (ending with a small D2H copy into pinned memory), complete()
+// runs after the stream has drained and decides what comes next.  The
+// synchronous solve alternates the two; the server interleaves many systems.
+void FgmresRun::start(MG &mg_, const double *b_, double *x_, int x0_nonzero,
+                      const fsi_krylov_opts &ko_, hipStream_t st_) {
+  mg = &mg_;
+  b = b_;
+  x = x_;
+  ko = ko_;
+  st = st_;
+  const int m = ko.restart;
+  if (m < 1 || m > 60) throw Error(FSI_E_INVALID, "restart must be in [1, 60]");
+  if (!(ko.rtol >= 0.0) || ko.maxit < 1) throw Error(FSI_E_INVALID, "invalid Krylov options");
+  t0 = std::chrono::steady_clock::now();
+  ensure_krylov(*mg, m);
+  Krylov &K = mg->kry;
+  Level &F = mg->lv.back();
+  const int n = F.n;
+  fixed = ko.fixed_iters > 0;
+  limit = fixed ? ko.fixed_iters : ko.maxit;
+  iters = restarts = j = k = 0;
+  converged = false;
+  hist.clear();
+  est = NAN;
+  if (!x0_nonzero) launch_fill_f64(x, n, 0.0, st);
+  // |b|^2 and |b - J x|^2
+  launch_mdot(n, b, n, 1, b, K.partial, 1, st);
+  launch_mdot_finish(K.partial, 1, 1, K.nrm + 1, 0, st);
+  enqueue_residual();
+  hip_check(hipMemcpyAsync(K.pinned, K.nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "D2H");
+  phase = kFirst;
+}
+
+void FgmresRun::enqueue_residual() {
+  Krylov &K = mg->kry;
+  Level &F = mg->lv.back();
+  const int n = F.n;
+  launch_spmv(F.J.v64(), x, b, K.w, kSpmvResid, F.J.lpr, st);
+  launch_mdot(n, K.w, n, 1, K.w, K.partial, 1, st);
+  launch_mdot_finish(K.partial, 1, 1, K.nrm, 0, st);
+}
+
+void FgmresRun::enqueue() {
+  if (phase != kIter) return;
+  Krylov &K = mg->kry;
+  Level &F = mg->lv.back();
+  const int n = F.n, m = ko.restart;
+  const auto J = F.J.v64();
+  if (j == 0) launch_start_cycle(n, K.w, K.nrm, K.V, K.g, m, st);
+  double *vj = K.V + (int64_t)j * n;
+  double *zj = K.Z + (int64_t)j * n;
+  run_vcycle(*mg, vj, zj, st);
+  launch_spmv(J, zj, (const double *)nullptr, K.w, kSpmvSet, F.J.lpr, st);
+  // classical Gram-Schmidt, twice
+  launch_mdot(n, K.V, n, j + 1, K.w, K.partial, m + 2, st);
+  launch_mdot_finish(K.partial, m + 2, j + 1, K.h1, 0, st);
+  launch_mupdate(n, K.V, n, j + 1, K.h1, K.w, nullptr, st);
+  launch_mdot(n, K.V, n, j + 1, K.w, K.partial, m + 2, st);
+  launch_mdot_finish(K.partial, m + 2, j + 1, K.h2, 0, st);
+  launch_mupdate(n, K.V, n, j + 1, K.h2, K.w, K.npart, st);
+  launch_mdot_finish(K.partial, m + 2, j + 1, K.h1, 1, st);  // h1 += h2
+  launch_mdot_finish(K.npart, 1, 1, K.nrm + 2, 0, st);
+  launch_givens(K.H, m + 1, j, K.h1, K.nrm + 2, K.cs, K.sn, K.g, K.flags, K.scal, st);
+  launch_scale_to(n, K.w, K.scal, K.V + (int64_t)(j + 1) * n, st);
+  hip_check(hipGetLastError(), "arnoldi launch");
+  hip_check(hipMemcpyAsync(K.pinned, K.flags, 2 * sizeof(double), hipMemcpyDeviceToHost, st),
+            "D2H flags");
+}
+
+void FgmresRun::finish_cycle() {
+  Krylov &K = mg->kry;
+  Level &F = mg->lv.back();
+  launch_backsolve(K.H, ko.restart + 1, K.g, k, K.y, st);
+  launch_zupdate(F.n, K.Z, F.n, k, K.y, x, st);
+  ++restarts;
+  enqueue_residual();
+  hip_check(hipMemcpyAsync(K.pinned, K.nrm, sizeof(double), hipMemcpyDeviceToHost, st), "D2H");
+  phase = kCheck;
+}
+
+void FgmresRun::add_hist(double v) {
+  if (ko.history && (int)hist.size() <= ko.maxit) ko.history[hist.size()] = v;
+  hist.push_back(v);
+}
+
+// decide after the stream drained; returns true when the solve is over
+bool FgmresRun::complete() {
+  Krylov &K = mg->kry;
+  const double tol = ko.rtol * bnorm;
+  if (phase == kFirst) {
+    const double bn2 = K.pinned[1];
+    if (!std::isfinite(bn2)) throw Error(FSI_E_NONFINITE, "right-hand side has NaN/Inf");
+    bnorm = std::sqrt(bn2);
+    beta = std::sqrt(K.pinned[0]);
+    add_hist(beta);
+    const double tol0 = ko.rtol * bnorm;
+    if ((!fixed && beta <= tol0) || iters >= limit || beta == 0.0) {
+      converged = beta <= tol0;
+      est = bnorm > 0 ? beta / bnorm : 0.0;
+      phase = kDone;
+      return true;
+    }
+    j = 0;
+    phase = kIter;
+    return false;
+  }
+  if (phase == kIter) {
+    const double gj = K.pinned[0];
+    const bool breakdown = K.pinned[1] != 0.0;
+    if (!std::isfinite(gj)) throw Error(FSI_E_NONFINITE, "non-finite Krylov residual estimate");
+    ++iters;
+    est = gj / bnorm;
+    add_hist(gj);
+    k = j + 1;
+    if ((!fixed && gj <= tol) || breakdown || iters >= limit || k == ko.restart) {
+      finish_cycle();
+    } else {
+      ++j;
+    }
+    return false;
+  }
+  if (phase == kCheck) {
+    beta = std::sqrt(K.pinned[0]);
+    if ((!fixed && beta <= tol) || iters >= limit || beta == 0.0) {
+      converged = beta <= tol;
+      phase = kDone;
+      return true;
+    }
+    j = 0;
+    phase = kIter;
+    return false;
+  }
+  return phase == kDone;
+}
+
+void FgmresRun::fill_info(fsi_solve_info *info) const {
+  if (!info) return;
+  info->iters = iters;
+  info->restarts = restarts;
+  info->converged = converged ? 1 : 0;
+  info->true_relres = bnorm > 0 ? beta / bnorm : 0.0;
+  info->est_relres = est;
+  info->setup_ms = mg->setup_ms;
+  info->solve_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+fsi_status fgmres(MG &mg, const double *b, double *x, int x0_nonzero, const fsi_krylov_opts &ko,
+                  fsi_solve_info *info, hipStream_t st) {
+  FgmresRun run;
+  run.start(mg, b, x, x0_nonzero, ko, st);
+  hip_check(hipStreamSynchronize(st), "fgmres start");
+  while (!run.complete()) {
+    run.enqueue();
+    hip_check(hipStreamSynchronize(st), "fgmres step");
+  }
+  run.fill_info(info);
+  return run.converged ? FSI_OK : FSI_NOT_CONVERGED;
+}
+
+}  // namespace fsi
+
+// ==================================================================== C ABI
+using namespace fsi;
+
+#define FSI_GUARD(body)                               \
+  try {                                               \
+    body                                              \
+  } catch (const Error &e) {                          \
+    set_error(e.msg);                                 \
+    return e.code;                                    \
+  } catch (const std::exception &e) {                 \
+    set_error(std::string("internal error: ") + e.what()); \
+    return FSI_E_DEVICE;                              \
+  }
+
+extern "C" {
+
+int32_t fsi_abi_version(void) { return FSI_ABI_VERSION; }
+
+const char *fsi_status_string(fsi_status s) {
+  switch (s) {
+    case FSI_OK: return "ok";
+    case FSI_NOT_CONVERGED: return "not converged";
+    case FSI_PENDING: return "pending";
+    case FSI_E_INVALID: return "invalid argument";
+    case FSI_E_OOM: return "out of device memory";
+    case FSI_E_SINGULAR: return "singular block";
+    case FSI_E_DEVICE: return "device error";
+    case FSI_E_NONFINITE: return "non-finite input";
+    case FSI_E_CAPACITY: return "request exceeds capacity";
+    case FSI_E_UNKNOWN_TICKET: return "unknown ticket";
+    default: return "unknown status";
+  }
+}
+
+const char *fsi_last_error(void) { return g_last_error.c_str(); }
+
+fsi_status fsi_mg_setup(const fsi_level *levels, int32_t nlevels, const fsi_mg_opts *opts,
+                        void *hip_stream, struct fsi_mg **out) {
+  FSI_GUARD({
+    if (!out) throw Error(FSI_E_INVALID, "null output handle");
+    *out = nullptr;
+    validate_levels(levels, nlevels, opts);
+    hipStream_t own = nullptr;
+    hip_check(hipStreamCreate(&own), "stream");
+    try {
+      MG *mg = mg_setup(levels, nlevels, opts, (hipStream_t)hip_stream, own);
+      *out = reinterpret_cast<fsi_mg *>(mg);
+    } catch (...) {
+      (void)hipStreamDestroy(own);
+      throw;
+    }
+    return FSI_OK;
+  })
+}
+
+fsi_status fsi_mg_vcycle(struct fsi_mg *h, const double *r_dev, double *z_dev, void *hip_stream) {
+  FSI_GUARD({
+    MG *mg = reinterpret_cast<MG *>(h);
+    if (!mg || !r_dev || !z_dev) throw Error(FSI_E_INVALID, "null argument");
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
+    run_vcycle(*mg, r_dev, z_dev, st);
+    hip_check(hipGetLastError(), "vcycle launch");
+    return FSI_OK;
+  })
+}
+
+fsi_status fsi_fgmres_solve(struct fsi_mg *h, const double *b_dev, double *x_dev,
+                            int32_t x0_nonzero, const fsi_krylov_opts *kopts, fsi_solve_info *info,
+                            void *hip_stream) {
+  FSI_GUARD({
+    MG *mg = reinterpret_cast<MG *>(h);
+    if (!mg || !b_dev || !x_dev || !kopts) throw Error(FSI_E_INVALID, "null argument");
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
+    return fgmres(*mg, b_dev, x_dev, x0_nonzero, *kopts, info, st);
+  })
+}
+
+fsi_status fsi_mg_apply(struct fsi_mg *h, int32_t level, int32_t op, const double *x_dev,
+                        const double *r_dev, double *y_dev, void *hip_stream) {
+  FSI_GUARD({
+    MG *mg = reinterpret_cast<MG *>(h);
+    if (!mg || !x_dev || !y_dev) throw Error(FSI_E_INVALID, "null argument");
+    if (level < 0 || level >= mg->nlevels) throw Error(FSI_E_INVALID, "level out of range");
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
+    Level &L = mg->lv[level];
+    switch (op) {
+      case 0: launch_spmv(L.J.v64(), x_dev, (const double *)nullptr, y_dev, kSpmvSet, L.J.lpr, st); break;
+      case 1:
+        if (!r_dev) throw Error(FSI_E_INVALID, "r required");
+        launch_spmv(L.J.v64(), x_dev, r_dev, y_dev, kSpmvResid, L.J.lpr, st);
+        break;
+      case 2:
+        if (level == 0) throw Error(FSI_E_INVALID, "no prolongation on level 0");
+        launch_spmv(L.P.v64(), x_dev, (const double *)nullptr, y_dev, kSpmvSet, L.P.lpr, st);
+        break;
+      case 3:
+        if (level == 0) throw Error(FSI_E_INVALID, "no restriction on level 0");
+        launch_spmv(L.R.v64(), x_dev, (const double *)nullptr, y_dev, kSpmvSet, L.R.lpr, st);
+        break;
+      case 4:
+        if (level == 0) throw Error(FSI_E_INVALID, "no patches on level 0");
+        if (!L.W64) throw Error(FSI_E_INVALID, "op 4 needs the FP64 precision");
+        launch_fill_f64(y_dev, L.n, 0.0, st);
+        launch_ras_f64(ras_view(L), L.W64, x_dev, y_dev, 1.0, st);
+        break;
+      case 5:
+        if (level != 0) throw Error(FSI_E_INVALID, "direct solve only on level 0");
+        launch_dense_gemv(L.C0, L.n, x_dev, y_dev, L.gemv_partial, st);
+        break;
+      default: throw Error(FSI_E_INVALID, "unknown op");
+    }
+    hip_check(hipGetLastError(), "apply launch");
+    return FSI_OK;
+  })
+}
+
+fsi_status fsi_mg_level_info(struct fsi_mg *h, int32_t level, int64_t out[6]) {
+  FSI_GUARD({
+    MG *mg = reinterpret_cast<MG *>(h);
+    if (!mg || !out || level < 0 || level >= mg->nlevels) throw Error(FSI_E_INVALID, "bad argument");
+    Level &L = mg->lv[level];
+    out[0] = L.n;
+    out[1] = L.J.nnz;
+    out[2] = L.npatch;
+    out[3] = L.sum_m;
+    out[4] = L.sum_m2;
+    out[5] = L.sum_om;
+    return FSI_OK;
+  })
+}
+
+fsi_status fsi_mg_export_patches(struct fsi_mg *h, int32_t level, int64_t *ptr, int32_t *dof,
+                                 uint8_t *owned, double *blocks) {
+  FSI_GUARD({
+    MG *mg = reinterpret_cast<MG *>(h);
+    if (!mg || level < 1 || level >= mg->nlevels) throw Error(FSI_E_INVALID, "bad level");
+    Level &L = mg->lv[level];
+    hipStream_t st = mg->own_stream;
+    if (ptr) std::copy(L.h_ptr.begin(), L.h_ptr.end(), ptr);
+    if (dof)
+      hip_check(hipMemcpy(dof, L.d_dof, sizeof(int32_t) * L.h_dof.size(), hipMemcpyDeviceToHost),
+                "D2H dof");
+    if (owned) std::copy(L.h_owned.begin(), L.h_owned.end(), owned);
+    if (blocks) {
+      std::vector<void *> tmp;
+      try {
+        double *B = extract_blocks(*mg, L, st, tmp);
+        hip_check(hipMemcpyAsync(blocks, B, sizeof(double) * L.boff_total, hipMemcpyDeviceToHost, st),
+                  "D2H blocks");
+        hip_check(hipStreamSynchronize(st), "export");
+      } catch (...) {
+        free_list(tmp);
+        throw;
+      }
+      free_list(tmp);
+    }
+    return FSI_OK;
+  })
+}
+
+fsi_status fsi_mg_destroy(struct fsi_mg *h) {
+  FSI_GUARD({
+    MG *mg = reinterpret_cast<MG *>(h);
+    if (!mg) return FSI_OK;
+    hipStream_t own = mg->own_stream;
+    (void)hipStreamSynchronize(own);
+    destroy_mg(mg);
+    (void)hipStreamDestroy(own);
+    return FSI_OK;
+  })
+}
+
+}  // extern "C"

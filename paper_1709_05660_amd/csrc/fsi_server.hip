@@ -1,0 +1,351 @@
+// Solve server: continuous batching of independent systems on one GPU.
+//
+// A scheduler thread admits queued requests in arrival order while a slot is
+// free and the estimated device footprint fits the budget, keeps each
+// admitted hierarchy resident, and advances every active system by one unit
+// of FGMRES work per tick, each system on its own stream so that their
+// kernels overlap on the device.  A system that finishes is retired (result
+// copied to host, device memory released) and the next request admitted.
+#include <atomic>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <thread>
+
+#include "fsi_internal.h"
+
+namespace fsi {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  uint64_t ticket = 0;
+  std::vector<std::vector<int64_t>> i64;
+  std::vector<std::vector<int32_t>> i32;
+  std::vector<std::vector<double>> f64;
+  std::vector<std::vector<uint8_t>> u8;
+  std::vector<fsi_level> levels;
+  std::vector<double> b;
+  fsi_mg_opts mo{};
+  fsi_krylov_opts ko{};
+  int64_t footprint = 0;
+  Clock::time_point t_submit;
+};
+
+struct Active {
+  std::unique_ptr<Request> req;
+  MG *mg = nullptr;
+  hipStream_t st = nullptr;
+  double *d_b = nullptr, *d_x = nullptr;
+  FgmresRun run;
+  Clock::time_point t_ready;
+};
+
+struct Done {
+  std::vector<double> x;
+  fsi_solve_info info{};
+  fsi_status status = FSI_OK;
+  std::string msg;
+};
+
+struct Server {
+  fsi_server_opts o{};
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<std::unique_ptr<Request>> queue;
+  std::map<uint64_t, Done> done;
+  std::set<uint64_t> live;
+  std::vector<std::unique_ptr<Active>> active;
+  std::thread worker;
+  std::atomic<bool> stop{false};
+  uint64_t next_ticket = 1;
+  int64_t used = 0, peak = 0, submitted = 0, finished = 0, ticks = 0, max_coresident = 0;
+  std::atomic<int64_t> n_active{0};
+};
+
+// device bytes of one system: operators, block inverses, coarse inverse,
+// vectors and the Krylov basis; plus the transient dense blocks of the setup
+static int64_t footprint(const fsi_level *lv, int nl, const fsi_mg_opts &mo,
+                         const fsi_krylov_opts &ko) {
+  const bool mixed = mo.precision != FSI_PREC_FP64;
+  const int wbytes = mo.precision == FSI_PREC_FP64 ? 8 : (mo.precision == FSI_PREC_MIXED_FP32 ? 4 : 2);
+  int64_t res = 0, transient = 0;
+  for (int l = 0; l < nl; ++l) {
+    const int64_t n = lv[l].J.nrows;
+    auto csr = [&](const fsi_csr &A) { return (A.nrows + 1) * 4 + A.nnz * (4 + 8 + (mixed ? 4 : 0)); };
+    res += csr(lv[l].J) + 6 * n * 8;
+    if (l == 0) {
+      res += n * n * 8 + 8 * n * 8;
+      transient = std::max<int64_t>(transient, n * n * 8 + 18 * n * 8);
+      continue;
+    }
+    res += csr(lv[l].P) + csr(lv[l].R);
+    const fsi_patches &P = lv[l].patches;
+    int64_t om = 0, m2 = 0;
+    for (int k = 0; k < P.npatch; ++k) {
+      const int64_t m = P.ptr[k + 1] - P.ptr[k];
+      int64_t o = 0;
+      for (int64_t p = P.ptr[k]; p < P.ptr[k + 1]; ++p) o += P.owned[p] ? 1 : 0;
+      om += o * m;
+      m2 += m * m;
+    }
+    res += om * wbytes + P.ptr[P.npatch] * 40;
+    transient = std::max<int64_t>(transient, m2 * 8);
+  }
+  const int64_t nf = lv[nl - 1].J.nrows;
+  res += nf * 8 * (2 * (int64_t)ko.restart + 4) + 2 * nf * 8;
+  return res + transient;
+}
+
+static std::unique_ptr<Request> copy_request(const fsi_level *lv, int nl, const double *b,
+                                             const fsi_mg_opts &mo, const fsi_krylov_opts &ko) {
+  std::unique_ptr<Request> r(new Request());
+  r->levels.resize(nl);
+  auto cp_csr = [&](const fsi_csr &A) {
+    fsi_csr c = A;
+    r->i64.emplace_back(A.rowptr, A.rowptr + A.nrows + 1);
+    r->i32.emplace_back(A.colind, A.colind + A.nnz);
+    r->f64.emplace_back(A.val, A.val + A.nnz);
+    c.rowptr = r->i64.back().data();
+    c.colind = r->i32.back().data();
+    c.val = r->f64.back().data();
+    return c;
+  };
+  // reserve so that data() pointers stay valid while emplacing
+  r->i64.reserve(4 * nl);
+  r->i32.reserve(4 * nl);
+  r->f64.reserve(4 * nl);
+  r->u8.reserve(2 * nl);
+  for (int l = 0; l < nl; ++l) {
+    fsi_level &L = r->levels[l];
+    std::memset(&L, 0, sizeof L);
+    L.J = cp_csr(lv[l].J);
+    if (l > 0) {
+      L.P = cp_csr(lv[l].P);
+      L.R = cp_csr(lv[l].R);
+      const fsi_patches &P = lv[l].patches;
+      if (!P.ptr || P.npatch <= 0) throw Error(FSI_E_INVALID, "missing patches");
+      const int64_t tot = P.ptr[P.npatch];
+      L.patches.npatch = P.npatch;
+      r->i64.emplace_back(P.ptr, P.ptr + P.npatch + 1);
+      L.patches.ptr = r->i64.back().data();
+      r->i32.emplace_back(P.dof, P.dof + tot);
+      L.patches.dof = r->i32.back().data();
+      r->u8.emplace_back(P.owned, P.owned + tot);
+      L.patches.owned = r->u8.back().data();
+      if (P.kind) {
+        r->u8.emplace_back(P.kind, P.kind + P.npatch);
+        L.patches.kind = r->u8.back().data();
+      }
+    }
+  }
+  r->b.assign(b, b + lv[nl - 1].J.nrows);
+  r->mo = mo;
+  r->ko = ko;
+  r->ko.history = nullptr;
+  return r;
+}
+
+static void finish(Server &S, Active &a, fsi_status st, const std::string &msg, bool have_x) {
+  Done d;
+  d.status = st;
+  d.msg = msg;
+  const int n = (int)a.req->b.size();
+  if (have_x) {
+    d.x.resize(n);
+    if (hipMemcpyAsync(d.x.data(), a.d_x, sizeof(double) * n, hipMemcpyDeviceToHost, a.st) != hipSuccess ||
+        hipStreamSynchronize(a.st) != hipSuccess) {
+      d.status = FSI_E_DEVICE;
+      d.msg = "result copy failed";
+    }
+    a.run.fill_info(&d.info);
+  }
+  const auto now = Clock::now();
+  d.info.setup_ms = std::chrono::duration<double, std::milli>(a.t_ready - a.req->t_submit).count();
+  d.info.solve_ms = std::chrono::duration<double, std::milli>(now - a.t_ready).count();
+  if (a.mg) destroy_mg(a.mg);
+  if (a.d_b) (void)hipFree(a.d_b);
+  if (a.d_x) (void)hipFree(a.d_x);
+  if (a.st) (void)hipStreamDestroy(a.st);
+  std::lock_guard<std::mutex> lk(S.mu);
+  S.used -= a.req->footprint;
+  S.done[a.req->ticket] = std::move(d);
+  S.finished++;
+  S.cv.notify_all();
+}
+
+static void worker_loop(Server *S) {
+  (void)hipSetDevice(S->o.device);
+  while (!S->stop.load()) {
+    // admission (FIFO): slot free and footprint within the budget
+    while (true) {
+      std::unique_ptr<Request> req;
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->queue.empty() || (int)S->active.size() >= S->o.max_slots) break;
+        if (S->used + S->queue.front()->footprint > S->o.hbm_budget_bytes) break;
+        req = std::move(S->queue.front());
+        S->queue.pop_front();
+        S->used += req->footprint;
+        S->peak = std::max(S->peak, S->used);
+      }
+      std::unique_ptr<Active> a(new Active());
+      a->req = std::move(req);
+      const int n = (int)a->req->b.size();
+      try {
+        hip_check(hipStreamCreate(&a->st), "stream");
+        a->mg = mg_setup(a->req->levels.data(), (int)a->req->levels.size(), &a->req->mo, a->st, a->st);
+        hip_check(hipMalloc(&a->d_b, sizeof(double) * n), "hipMalloc");
+        hip_check(hipMalloc(&a->d_x, sizeof(double) * n), "hipMalloc");
+        hip_check(hipMemcpyAsync(a->d_b, a->req->b.data(), sizeof(double) * n, hipMemcpyHostToDevice, a->st), "H2D");
+        a->run.start(*a->mg, a->d_b, a->d_x, 0, a->req->ko, a->st);
+        a->t_ready = Clock::now();
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->active.push_back(std::move(a));
+        S->max_coresident = std::max<int64_t>(S->max_coresident, (int64_t)S->active.size());
+        S->n_active = (int64_t)S->active.size();
+      } catch (const Error &e) {
+        a->t_ready = Clock::now();
+        finish(*S, *a, e.code, e.msg, false);
+      }
+    }
+    std::vector<Active *> cur;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      if (S->active.empty()) {
+        S->cv.wait_for(lk, std::chrono::milliseconds(2),
+                       [&] { return S->stop.load() || !S->queue.empty(); });
+        continue;
+      }
+      for (auto &p : S->active) cur.push_back(p.get());
+      S->ticks++;
+    }
+    // one tick: every active system advances by one unit of work; the others'
+    // work stays in flight on their streams while one is being synchronised
+    std::vector<Active *> retired;
+    for (Active *a : cur) {
+      try {
+        hip_check(hipStreamSynchronize(a->st), "tick");
+        if (a->run.complete()) {
+          finish(*S, *a, a->run.converged ? FSI_OK : FSI_NOT_CONVERGED, "", true);
+          retired.push_back(a);
+        } else {
+          a->run.enqueue();
+        }
+      } catch (const Error &e) {
+        finish(*S, *a, e.code, e.msg, false);
+        retired.push_back(a);
+      }
+    }
+    if (!retired.empty()) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (Active *r : retired)
+        for (size_t i = 0; i < S->active.size(); ++i)
+          if (S->active[i].get() == r) {
+            S->active.erase(S->active.begin() + i);
+            break;
+          }
+      S->n_active = (int64_t)S->active.size();
+    }
+  }
+  // drain on shutdown
+  for (auto &a : S->active) {
+    (void)hipStreamSynchronize(a->st);
+    finish(*S, *a, FSI_E_DEVICE, "server destroyed", false);
+  }
+  S->active.clear();
+}
+
+}  // namespace fsi
+
+using namespace fsi;
+
+extern "C" {
+
+fsi_status fsi_server_create(const fsi_server_opts *o, struct fsi_server **out) {
+  try {
+    if (!o || !out || o->max_slots < 1 || o->hbm_budget_bytes <= 0)
+      throw Error(FSI_E_INVALID, "invalid server options");
+    Server *S = new Server();
+    S->o = *o;
+    S->worker = std::thread(worker_loop, S);
+    *out = reinterpret_cast<fsi_server *>(S);
+    return FSI_OK;
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+fsi_status fsi_serve_submit(struct fsi_server *h, const fsi_level *levels, int32_t nlevels,
+                            const double *b_host, const fsi_mg_opts *mo, const fsi_krylov_opts *ko,
+                            uint64_t *ticket) {
+  try {
+    Server *S = reinterpret_cast<Server *>(h);
+    if (!S || !levels || nlevels < 1 || !b_host || !mo || !ko || !ticket)
+      throw Error(FSI_E_INVALID, "null argument");
+    const int64_t fp = footprint(levels, nlevels, *mo, *ko);
+    if (fp > S->o.hbm_budget_bytes) throw Error(FSI_E_CAPACITY, "request larger than the memory budget");
+    std::unique_ptr<Request> r = copy_request(levels, nlevels, b_host, *mo, *ko);
+    r->footprint = fp;
+    r->t_submit = Clock::now();
+    std::lock_guard<std::mutex> lk(S->mu);
+    r->ticket = S->next_ticket++;
+    *ticket = r->ticket;
+    S->live.insert(r->ticket);
+    S->queue.push_back(std::move(r));
+    S->submitted++;
+    S->cv.notify_all();
+    return FSI_OK;
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+fsi_status fsi_serve_poll(struct fsi_server *h, uint64_t ticket, double *x_host, fsi_solve_info *info) {
+  Server *S = reinterpret_cast<Server *>(h);
+  if (!S) return FSI_E_INVALID;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->done.find(ticket);
+  if (it == S->done.end()) return S->live.count(ticket) ? FSI_PENDING : FSI_E_UNKNOWN_TICKET;
+  Done &d = it->second;
+  if (x_host && !d.x.empty()) std::copy(d.x.begin(), d.x.end(), x_host);
+  if (info) *info = d.info;
+  const fsi_status st = d.status;
+  if (st < 0) set_error(d.msg);
+  S->done.erase(it);
+  S->live.erase(ticket);
+  return st;
+}
+
+fsi_status fsi_server_stats(struct fsi_server *h, int64_t out[8]) {
+  Server *S = reinterpret_cast<Server *>(h);
+  if (!S || !out) return FSI_E_INVALID;
+  std::lock_guard<std::mutex> lk(S->mu);
+  out[0] = S->submitted;
+  out[1] = S->finished;
+  out[2] = (int64_t)S->active.size();
+  out[3] = (int64_t)S->queue.size();
+  out[4] = S->used;
+  out[5] = S->peak;
+  out[6] = S->ticks;
+  out[7] = S->max_coresident;
+  return FSI_OK;
+}
+
+fsi_status fsi_server_destroy(struct fsi_server *h) {
+  Server *S = reinterpret_cast<Server *>(h);
+  if (!S) return FSI_OK;
+  S->stop = true;
+  S->cv.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  delete S;
+  return FSI_OK;
+}
+
+}  // extern "C"

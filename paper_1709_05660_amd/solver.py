@@ -1,0 +1,187 @@
+"""Python front end of the native FSI multigrid/FGMRES library.
+
+PyTorch supplies device memory (tensors on cuda) and the HIP stream; every
+step of the solve runs in the library's kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """A generated multigrid hierarchy (host arrays owned by the native builder)."""
+
+    def __init__(self, spec, coeffs):
+        lib = L.lib()
+        c = np.ascontiguousarray(coeffs, dtype=np.float64).ravel()
+        self._coeffs = c
+        ps = L.ProblemSpecC()
+        ps.dim, ps.nx, ps.ny, ps.nz = spec.dim, spec.nx, spec.ny, spec.nz
+        ps.levels, ps.patch = spec.levels, spec.patch
+        ps.lx, ps.ly, ps.lz = spec.lx, spec.ly, spec.lz
+        for d in range(3):
+            ps.solid_lo[d] = spec.solid_lo[d]
+            ps.solid_hi[d] = spec.solid_hi[d]
+        ps.rho, ps.mu, ps.mu_s, ps.u_peak, ps.amp = spec.rho, spec.mu, spec.mu_s, spec.u_peak, spec.amp
+        ps.kmax = int(round(c.size / spec.dim) ** (1.0 / spec.dim))
+        ps.coeffs = L._ptr(c, C.c_double)
+        h = C.c_void_p()
+        st = lib.fsi_problem_build(C.byref(ps), C.byref(h))
+        if st != 0:
+            raise L.FsiError(st, "problem build failed")
+        self.h = h
+        self.spec = spec
+        self.nlevels = lib.fsi_problem_nlevels(h)
+        self.levels = (L.LevelC * self.nlevels)()
+        L.check(lib.fsi_problem_levels(h, self.levels), "levels")
+        bp = C.POINTER(C.c_double)()
+        yp = C.POINTER(C.c_double)()
+        n = C.c_int64()
+        L.check(lib.fsi_problem_vectors(h, C.byref(bp), C.byref(yp), C.byref(n)))
+        self.n = n.value
+        self.b = np.ctypeslib.as_array(bp, shape=(self.n,)).copy()
+        self.y = np.ctypeslib.as_array(yp, shape=(self.n,)).copy()
+
+    def dirichlet(self, level):
+        fp = C.POINTER(C.c_uint8)()
+        L.check(L.lib().fsi_problem_dirichlet(self.h, level, C.byref(fp)))
+        n = self.levels[level].J.nrows
+        return np.ctypeslib.as_array(fp, shape=(n,)).astype(bool)
+
+    def csr(self, level, which="J"):
+        """(rowptr, colind, val, shape) copies of J, P or R of a level."""
+        A = getattr(self.levels[level], which)
+        nnz = A.nnz
+        rp = np.ctypeslib.as_array(A.rowptr, shape=(A.nrows + 1,)).copy()
+        ci = np.ctypeslib.as_array(A.colind, shape=(max(nnz, 1),))[:nnz].copy()
+        v = np.ctypeslib.as_array(A.val, shape=(max(nnz, 1),))[:nnz].copy()
+        return rp, ci, v, (A.nrows, A.ncols)
+
+    def patches(self, level):
+        P = self.levels[level].patches
+        ptr = np.ctypeslib.as_array(P.ptr, shape=(P.npatch + 1,)).copy()
+        tot = int(ptr[-1])
+        dof = np.ctypeslib.as_array(P.dof, shape=(tot,)).copy()
+        owned = np.ctypeslib.as_array(P.owned, shape=(tot,)).copy()
+        kind = np.ctypeslib.as_array(P.kind, shape=(P.npatch,)).copy()
+        return ptr, dof, owned, kind
+
+    def residual(self, y):
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        r = np.empty(self.n)
+        L.check(L.lib().fsi_problem_residual(self.h, y.ctypes.data_as(C.c_void_p),
+                                             r.ctypes.data_as(C.c_void_p)))
+        return r
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.lib().fsi_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mg_opts(nu_pre=2, nu_post=2, omega=0.7, precision="fp64", solid_precision=None,
+            refine_sweeps=0, use_graph=False):
+    o = L.MgOpts()
+    o.nu_pre, o.nu_post, o.omega = nu_pre, nu_post, omega
+    o.precision = L.PREC[precision]
+    o.solid_precision = -1 if solid_precision is None else L.PREC[solid_precision]
+    o.refine_sweeps = refine_sweeps
+    o.use_graph = 1 if use_graph else 0
+    return o
+
+
+class MG:
+    """Device-resident multigrid hierarchy: V-cycle and FGMRES on the GPU."""
+
+    def __init__(self, problem, **opts):
+        import torch
+        self.problem = problem       # keeps the host arrays alive during setup
+        self.opts = mg_opts(**opts)
+        h = C.c_void_p()
+        st = L.lib().fsi_mg_setup(problem.levels, problem.nlevels, C.byref(self.opts), _stream(), C.byref(h))
+        L.check(st, "fsi_mg_setup")
+        self.h = h
+        self.n = problem.n
+        self.nlevels = problem.nlevels
+        self.device = torch.device("cuda")
+
+    def level_info(self, level):
+        out = (C.c_int64 * 6)()
+        L.check(L.lib().fsi_mg_level_info(self.h, level, out))
+        return dict(zip(["n", "nnz", "npatch", "sum_m", "sum_m2", "sum_om"], list(out)))
+
+    def vcycle(self, r, z=None):
+        import torch
+        if z is None:
+            z = torch.empty_like(r)
+        L.check(L.lib().fsi_mg_vcycle(self.h, _dptr(r), _dptr(z), _stream()), "vcycle")
+        return z
+
+    def apply(self, level, op, x, r=None, y=None):
+        import torch
+        n = self.level_info(level)["n"]
+        if y is None:
+            y = torch.empty(n if op != 3 else self.level_info(level - 1)["n"], dtype=torch.float64,
+                            device=x.device)
+        L.check(L.lib().fsi_mg_apply(self.h, level, op, _dptr(x), _dptr(r) if r is not None else None,
+                                     _dptr(y), _stream()), "apply")
+        return y
+
+    def fgmres(self, b, x=None, restart=30, rtol=1e-10, maxit=1000, fixed_iters=0, x0=False):
+        import torch
+        if x is None:
+            x = torch.zeros_like(b)
+        hist = np.zeros(maxit + 2)
+        ko = L.KrylovOpts()
+        ko.restart, ko.rtol, ko.maxit, ko.fixed_iters = restart, rtol, maxit, fixed_iters
+        ko.history = L._ptr(hist, C.c_double)
+        info = L.SolveInfo()
+        st = L.lib().fsi_fgmres_solve(self.h, _dptr(b), _dptr(x), 1 if x0 else 0, C.byref(ko),
+                                      C.byref(info), _stream())
+        L.check(st, "fgmres")
+        d = info.as_dict()
+        d["status"] = st
+        d["history"] = hist[: d["iters"] + 1].copy()
+        return x, d
+
+    def export_patches(self, level, blocks=False):
+        info = self.level_info(level)
+        ptr = np.zeros(info["npatch"] + 1, np.int64)
+        dof = np.zeros(info["sum_m"], np.int32)
+        owned = np.zeros(info["sum_m"], np.uint8)
+        B = np.zeros(info["sum_m2"]) if blocks else None
+        L.check(L.lib().fsi_mg_export_patches(
+            self.h, level, ptr.ctypes.data_as(C.c_void_p), dof.ctypes.data_as(C.c_void_p),
+            owned.ctypes.data_as(C.c_void_p), B.ctypes.data_as(C.c_void_p) if blocks else None))
+        return ptr, dof, owned, B
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.lib().fsi_mg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

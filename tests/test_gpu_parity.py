@@ -1,0 +1,231 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 checker.
+
+Inputs come from the native problem builder; expected values from the
+checker, either run on the same matrices (kernel-level parity) or on its own
+independently assembled system (end-to-end parity).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import csr_of, dev, host, oracle_hierarchy, oracle_on_product, product_problem
+from oracle import problem as oprob
+from oracle import solver as osolver
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def c0():
+    from paper_1709_05660_amd import MG
+    _say("setup c0_2d_16x4 fp64")
+    p = product_problem("c0_2d_16x4")
+    mg = MG(p, precision="fp64")
+    yield p, mg
+    mg.close()
+
+
+def test_patch_lists_bit_exact(c0):
+    """Device patch lists == the checker's independently built lists; device-
+    extracted blocks == J[I_k, I_k] of the same matrix, bit for bit."""
+    p, mg = c0
+    oh = oracle_hierarchy("c0_2d_16x4")
+    for l in range(1, p.nlevels):
+        ptr, dof, owned, B = mg.export_patches(l, blocks=True)
+        lv = oh.levels[l]
+        assert np.array_equal(ptr, lv.ptr)
+        assert np.array_equal(dof, lv.dof)
+        assert np.array_equal(owned, lv.owned)
+        J = csr_of(p, l)
+        off = 0
+        for k in range(len(ptr) - 1):
+            I = dof[ptr[k]:ptr[k + 1]]
+            m = I.size
+            ref = osolver.extract_block(J, I)
+            got = B[off:off + m * m].reshape(m, m)
+            assert np.array_equal(got, ref), f"block {k}"
+            off += m * m
+
+
+@pytest.mark.parametrize("op", [0, 1, 2, 3])
+def test_sparse_operators(c0, op):
+    """J x, r - J x, P x, R x per entry within 1e-13 of (|A| |x|)."""
+    p, mg = c0
+    rng = np.random.default_rng(10 + op)
+    for l in range(p.nlevels):
+        if op >= 2 and l == 0:
+            continue
+        A = csr_of(p, l, "J" if op < 2 else ("P" if op == 2 else "R"))
+        x = rng.standard_normal(A.shape[1])
+        r = rng.standard_normal(A.shape[0])
+        y = host(mg.apply(l, op, dev(x), dev(r) if op == 1 else None))
+        ref = A @ x
+        if op == 1:
+            ref = r - ref
+        scale = abs(A) @ abs(x) + (abs(r) if op == 1 else 0)
+        assert np.all(np.abs(y - ref) <= 1e-13 * scale + 1e-300)
+
+
+def test_schwarz_application(c0):
+    """sum_k R0_k^T B_k^{-1} R^delta_k s: GPU (owned rows of the GJ inverse) vs
+    the checker (LU solves) on the same matrices."""
+    p, mg = c0
+    oh = oracle_on_product("c0_2d_16x4")
+    rng = np.random.default_rng(3)
+    for l in range(1, p.nlevels):
+        s = rng.standard_normal(csr_of(p, l).shape[0])
+        y = host(mg.apply(l, 4, dev(s)))
+        ref = osolver.ras(oh.levels[l], s)
+        assert np.linalg.norm(y - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_coarsest_solve(c0):
+    p, mg = c0
+    A = csr_of(p, 0).toarray()
+    rng = np.random.default_rng(4)
+    r = rng.standard_normal(A.shape[0])
+    y = host(mg.apply(0, 5, dev(r)))
+    ref = np.linalg.solve(A, r)
+    assert np.linalg.norm(y - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_vcycle_parity_c0(c0):
+    p, mg = c0
+    oh = oracle_on_product("c0_2d_16x4")
+    s = oh.spec
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(p.n)
+    z = host(mg.vcycle(dev(r)))
+    ref = osolver.vcycle(oh.levels, len(oh.levels) - 1, r, s.nu_pre, s.nu_post, s.omega)
+    assert np.linalg.norm(z - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_fgmres_parity_c0(c0):
+    """FP64 solution vs the checker's own system: 1e-10 relative at the checker's
+    iteration count, converged counts within 1, true residual <= rtol."""
+    p, mg = c0
+    oh = oracle_hierarchy("c0_2d_16x4")
+    s = oh.spec
+    x_o, info_o = oprob.solve(oh)
+    k = info_o.iters
+    x_fix, _ = oprob.solve(oh, fixed_iters=k)
+    xg, ig = mg.fgmres(dev(p.b), restart=s.restart, rtol=s.rtol, fixed_iters=k)
+    xg = host(xg)
+    _say("c0 oracle iters", k, "gpu fixed-iter rel diff",
+         np.linalg.norm(xg - x_fix) / np.linalg.norm(x_fix))
+    assert np.linalg.norm(xg - x_fix) <= 1e-10 * np.linalg.norm(x_fix)
+    x2, i2 = mg.fgmres(dev(p.b), restart=s.restart, rtol=s.rtol)
+    x2 = host(x2)
+    assert i2["converged"] == 1 and i2["true_relres"] <= s.rtol
+    assert abs(i2["iters"] - k) <= 1
+    assert np.linalg.norm(x2 - x_o) <= 1e-10 * np.linalg.norm(x_o)
+    J = csr_of(p, p.nlevels - 1)
+    assert np.linalg.norm(p.b - J @ x2) <= s.rtol * np.linalg.norm(p.b) * 1.0001
+
+
+def test_fgmres_error_paths(c0):
+    import torch
+    from paper_1709_05660_amd import FsiError
+    p, mg = c0
+    b = dev(p.b)
+    x, info = mg.fgmres(b, restart=30, rtol=1e-10, maxit=1)
+    assert info["status"] == 1 and info["iters"] == 1 and info["converged"] == 0
+    bad = b.clone()
+    bad[5] = float("nan")
+    with pytest.raises(FsiError) as e:
+        mg.fgmres(bad)
+    assert e.value.status == -5
+    torch.cuda.synchronize()
+
+
+def test_singular_block_is_reported():
+    """A zero row inside a patch block makes setup fail with FSI_E_SINGULAR."""
+    import ctypes as C
+    from paper_1709_05660_amd import FsiError, MG
+    p = product_problem("c0_2d_16x4")
+    J = p.levels[p.nlevels - 1].J
+    ptr, dof, owned, kind = p.patches(p.nlevels - 1)
+    row = int(dof[ptr[3] + 2])                       # a dof inside patch 3
+    vals = np.ctypeslib.as_array(J.val, shape=(J.nnz,))
+    rp = np.ctypeslib.as_array(J.rowptr, shape=(J.nrows + 1,))
+    saved = vals[rp[row]:rp[row + 1]].copy()
+    vals[rp[row]:rp[row + 1]] = 0.0
+    try:
+        with pytest.raises(FsiError) as e:
+            MG(p, precision="fp64")
+        assert e.value.status == -3
+    finally:
+        vals[rp[row]:rp[row + 1]] = saved
+
+
+def test_graph_vcycle_matches_eager(c0):
+    from paper_1709_05660_amd import MG
+    p, mg = c0
+    mgg = MG(p, precision="fp64", use_graph=True)
+    rng = np.random.default_rng(6)
+    for _ in range(3):
+        r = dev(rng.standard_normal(p.n))
+        z1 = host(mg.vcycle(r))
+        z2 = host(mgg.vcycle(r))
+        assert np.array_equal(z1, z2)
+    mgg.close()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    from paper_1709_05660_amd import MG
+    _say("setup c1_2d_128x32 fp64")
+    p = product_problem("c1_2d_128x32")
+    mg = MG(p, precision="fp64")
+    yield p, mg
+    mg.close()
+
+
+def test_vcycle_parity_c1(c1):
+    p, mg = c1
+    oh = oracle_on_product("c1_2d_128x32")
+    s = oh.spec
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal(p.n)
+    z = host(mg.vcycle(dev(r)))
+    ref = osolver.vcycle(oh.levels, len(oh.levels) - 1, r, s.nu_pre, s.nu_post, s.omega)
+    _say("c1 vcycle rel diff", np.linalg.norm(z - ref) / np.linalg.norm(ref))
+    assert np.linalg.norm(z - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_fgmres_parity_c1(c1):
+    p, mg = c1
+    oh = oracle_hierarchy("c1_2d_128x32")
+    s = oh.spec
+    x_o, info_o = oprob.solve(oh)
+    xg, ig = mg.fgmres(dev(p.b), restart=s.restart, rtol=s.rtol)
+    xg = host(xg)
+    rel = np.linalg.norm(xg - x_o) / np.linalg.norm(x_o)
+    _say("c1 iters gpu", ig["iters"], "oracle", info_o.iters, "rel diff", rel, "true", ig["true_relres"])
+    assert ig["converged"] == 1 and ig["true_relres"] <= s.rtol
+    assert abs(ig["iters"] - info_o.iters) <= 1
+    assert rel <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_mixed_precision_c1(c1, prec):
+    """Mixed V-cycle (FP32 operators, 16-bit or FP32 block inverses), FP64 Krylov:
+    true relative residual <= 1e-8; error against the FP64 solution reported."""
+    from paper_1709_05660_amd import MG
+    p, mg64 = c1
+    mg = MG(p, precision=prec)
+    x, info = mg.fgmres(dev(p.b), restart=30, rtol=1e-8)
+    x = host(x)
+    x64, i64 = mg64.fgmres(dev(p.b), restart=30, rtol=1e-8)
+    x64 = host(x64)
+    _say(prec, "iters", info["iters"], "fp64 iters", i64["iters"], "true", info["true_relres"],
+         "err vs fp64", np.linalg.norm(x - x64) / np.linalg.norm(x64))
+    assert info["converged"] == 1 and info["true_relres"] <= 1e-8
+    mg.close()
