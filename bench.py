@@ -1,0 +1,186 @@
+#!/usr/bin/env python
+"""Benchmark of the FSI Newton-step linear solve on one MI355X.
+
+One step = the whole hot path for one Newton Jacobian of the 2D 128x32
+four-level system (79,108 unknowns, Q2-P1disc, 4x4-element Schwarz blocks):
+extraction and Gauss-Jordan inversion of every Schwarz block and of the
+coarsest operator from the device-resident operators, then FGMRES(30) with
+the multigrid V-cycle to rtol 1e-10 in FP64.  Inputs are resident in HBM when
+the timed region starts.  Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "V-cycle ms & FGMRES solves/s, FP64 vs mixed; served solves/s + p50/p99 latency"
+WORKLOAD = "c1_2d_128x32"
+
+
+def ras_bytes(info, wbytes, vbytes):
+    """Algorithmic bytes of one finest-level Schwarz launch: the owned rows of
+    every block inverse once, the gathered residual entries (index + value),
+    and the owned corrections (index, read, write)."""
+    return wbytes * info["sum_om"] + (4 + vbytes) * info["sum_m"] + (4 + 2 * vbytes) * info["n_owned"]
+
+
+def gpu_leg(args):
+    import torch
+
+    from paper_1709_05660_amd import MG, Problem
+    from synth import config, fourier_coefficients
+
+    spec = config(WORKLOAD)
+    t = time.time()
+    p = Problem(spec, fourier_coefficients(spec.dim, spec.seed))
+    build_s = time.time() - t
+    stream = torch.cuda.Stream()
+    out = {}
+    with torch.cuda.stream(stream):
+        b = torch.as_tensor(p.b).to("cuda")
+        x = torch.zeros_like(b)
+
+        def timed_steps(mg, k, rtol):
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            infos = []
+            for _ in range(k):
+                mg.refactor()
+                _, info = mg.fgmres(b, x, restart=spec.restart, rtol=rtol, maxit=spec.maxit)
+                infos.append(info)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            return ev0.elapsed_time(ev1), infos
+
+        def vcycle_ms(mg, reps=50):
+            r = torch.randn(p.n, dtype=torch.float64, device="cuda")
+            z = torch.empty_like(r)
+            for _ in range(3):
+                mg.vcycle(r, z)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for _ in range(reps):
+                mg.vcycle(r, z)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            return ev0.elapsed_time(ev1) / reps
+
+        # ---- FP64 (the workload's precision): value
+        t = time.time()
+        mg = MG(p, precision="fp64", use_graph=True)
+        setup_upload_ms = (time.time() - t) * 1e3
+        _, warm = timed_steps(mg, args.warmup, spec.rtol)
+        total_ms, infos = timed_steps(mg, args.steps, spec.rtol)
+        out["ms_per_step"] = total_ms / args.steps
+        out["iters"] = infos[-1]["iters"]
+        out["true_relres"] = infos[-1]["true_relres"]
+        out["converged"] = all(i["converged"] == 1 for i in infos)
+        out["vcycle_ms_fp64"] = vcycle_ms(mg)
+        out["refactor_ms_fp64"] = infos[-1]["setup_ms"]
+        out["solve_ms_fp64"] = infos[-1]["solve_ms"]
+        out["setup_with_upload_ms"] = setup_upload_ms
+        out["build_s"] = build_s
+        # ---- dominant kernel: finest-level Schwarz GEMV, event-timed on its stream
+        fine = mg.level_info(p.nlevels - 1)
+        ptr, dof, owned, _ = mg.export_patches(p.nlevels - 1)
+        fine["n_owned"] = int(owned.sum())
+        mg.profile_start()
+        for _ in range(args.prof_steps):
+            mg.fgmres(b, x, restart=spec.restart, rtol=spec.rtol, maxit=spec.maxit)
+        kms, cnt = mg.profile_stop()
+        avg_ms = kms / max(cnt, 1)
+        bytes_per_launch = ras_bytes(fine, 8, 8)
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": "k_ras<double> (finest level)",
+                           "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                           "frac": round(achieved / 8000.0, 4), "traffic": None,
+                           "avg_launch_us": round(avg_ms * 1e3, 2), "launches": cnt,
+                           "bytes_per_launch": int(bytes_per_launch)}
+        mg.close()
+        # ---- mixed precision form (FP32 V-cycle, BF16 block inverses, FP64 Krylov)
+        if not args.no_mixed:
+            mgm = MG(p, precision=args.mixed, use_graph=True)
+            timed_steps(mgm, args.warmup, 1e-8)
+            tm, im = timed_steps(mgm, args.steps, 1e-8)
+            out["mixed"] = {"precision": args.mixed, "rtol": 1e-8, "ms_per_step": tm / args.steps,
+                            "solves_per_s": args.steps / (tm * 1e-3), "iters": im[-1]["iters"],
+                            "true_relres": im[-1]["true_relres"], "vcycle_ms": vcycle_ms(mgm)}
+            mgm.close()
+    out["n"] = p.n
+    return out
+
+
+def cpu_leg(args):
+    """The checker as it stands, on a bounded sample: the same step (block and
+    coarse factorisation + FGMRES solve) of the same system."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import problem as oprob
+    from oracle import solver as osolver
+    from synth import config, fourier_coefficients
+
+    spec = config(WORKLOAD)
+    h = oprob.build(spec, fourier_coefficients(spec.dim, spec.seed), factor=False)
+    t = time.time()
+    steps = 0
+    while steps < args.cpu_steps:
+        osolver.setup_factors(h.levels)
+        oprob.solve(h)
+        steps += 1
+    dt = time.time() - t
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": round(steps / dt, 4), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{steps} full steps (block LU + coarse LU + FGMRES to 1e-10) of {WORKLOAD}, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prof-steps", type=int, default=2)
+    ap.add_argument("--mixed", default="bf16")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+    g = gpu_leg(args)
+    value = args.steps / (g["ms_per_step"] * args.steps * 1e-3)
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(g["ms_per_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D steady FSI 128x32 Q2-P1disc, 4 MG levels, 4x4 Schwarz blocks, "
+                               "FGMRES(30) rtol 1e-10, FP64 (one Newton step: block inversion + solve)",
+                   "unknowns": g["n"]},
+        "roofline": g["roofline"],
+        "fgmres_iters": g["iters"], "true_relres": g["true_relres"], "converged": g["converged"],
+        "vcycle_ms_fp64": round(g["vcycle_ms_fp64"], 4),
+        "refactor_ms_fp64": round(g["refactor_ms_fp64"], 3), "solve_ms_fp64": round(g["solve_ms_fp64"], 3),
+        "dof_per_s": round(value * g["n"], 1),
+    }
+    if "mixed" in g:
+        line["mixed"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in g["mixed"].items()}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_leg(args)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -143,6 +143,20 @@ fsi_status fsi_mg_apply(struct fsi_mg *mg, int32_t level, int32_t op, const doub
 fsi_status fsi_mg_export_patches(struct fsi_mg *mg, int32_t level, int64_t *ptr, int32_t *dof,
                                  uint8_t *owned, double *blocks);
 
+/* Recomputes the block inverses and the coarsest inverse from the operator
+ * values resident on the device (a new Newton Jacobian with the same
+ * sparsity, written through fsi_mg_jvalues).  Same errors as setup. */
+fsi_status fsi_mg_refactor(struct fsi_mg *mg, void *hip_stream);
+
+/* Device pointer to the FP64 values of J on `level` (the input CSR order),
+ * owned by the handle; callers may overwrite them before fsi_mg_refactor. */
+fsi_status fsi_mg_jvalues(struct fsi_mg *mg, int32_t level, double **val_dev);
+
+/* Profiling of the finest-level Schwarz kernel with HIP events on its stream:
+ * enable = 1 starts (V-cycles then run without graphs), enable = 0 stops and
+ * writes out[0] = total kernel milliseconds, out[1] = number of launches. */
+fsi_status fsi_mg_profile(struct fsi_mg *mg, int32_t enable, double out[2]);
+
 /* Sizes of level `level`: n, nnz(J), npatch, sum m_k, sum m_k^2, sum owned_k * m_k. */
 fsi_status fsi_mg_level_info(struct fsi_mg *mg, int32_t level, int64_t out[6]);
 

@@ -61,6 +61,8 @@ fsi_status fsi_problem_dirichlet(const struct fsi_problem *p, int32_t level, con
 /* element residual of the finest level at state y (for tests): r (n doubles) */
 fsi_status fsi_problem_residual(const struct fsi_problem *p, const double *y, double *r);
 fsi_status fsi_problem_destroy(struct fsi_problem *p);
+/* thread-local message of the last failed fsi_problem_build of the calling thread */
+const char *fsi_problem_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -80,10 +80,11 @@ class ServerOpts(C.Structure):
 EXPORTS = [
     "fsi_abi_version", "fsi_status_string", "fsi_last_error", "fsi_mg_setup", "fsi_mg_vcycle",
     "fsi_fgmres_solve", "fsi_mg_apply", "fsi_mg_export_patches", "fsi_mg_level_info",
+    "fsi_mg_refactor", "fsi_mg_jvalues", "fsi_mg_profile",
     "fsi_mg_destroy", "fsi_server_create", "fsi_serve_submit", "fsi_serve_poll",
     "fsi_server_stats", "fsi_server_destroy",
     "fsi_problem_build", "fsi_problem_nlevels", "fsi_problem_levels", "fsi_problem_vectors",
-    "fsi_problem_dirichlet", "fsi_problem_residual", "fsi_problem_destroy",
+    "fsi_problem_dirichlet", "fsi_problem_residual", "fsi_problem_destroy", "fsi_problem_last_error",
 ]
 
 _lib = None
@@ -112,6 +113,9 @@ def lib():
         "fsi_mg_export_patches": (C.c_int32, [P, C.c_int32, P, P, P, P]),
         "fsi_mg_level_info": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_int64)]),
         "fsi_mg_destroy": (C.c_int32, [P]),
+        "fsi_mg_refactor": (C.c_int32, [P, P]),
+        "fsi_mg_jvalues": (C.c_int32, [P, C.c_int32, C.POINTER(C.POINTER(C.c_double))]),
+        "fsi_mg_profile": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_double)]),
         "fsi_server_create": (C.c_int32, [C.POINTER(ServerOpts), C.POINTER(P)]),
         "fsi_serve_submit": (C.c_int32, [P, C.POINTER(LevelC), C.c_int32, P, C.POINTER(MgOpts),
                                          C.POINTER(KrylovOpts), C.POINTER(C.c_uint64)]),
@@ -126,6 +130,7 @@ def lib():
         "fsi_problem_dirichlet": (C.c_int32, [P, C.c_int32, C.POINTER(C.POINTER(C.c_uint8))]),
         "fsi_problem_residual": (C.c_int32, [P, P, P]),
         "fsi_problem_destroy": (C.c_int32, [P]),
+        "fsi_problem_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -38,7 +38,8 @@ struct Level {
   // Schwarz patches
   int npatch = 0, mmax = 0, ntask = 0;
   int64_t sum_m = 0, sum_m2 = 0, sum_om = 0, total_owned = 0, boff_total = 0, woff_total = 0;
-  std::vector<int64_t> h_ptr;
+  std::vector<int64_t> h_ptr, h_boff;
+  int64_t blk_base = 0;   // offset of this level's blocks in the shared scratch
   std::vector<int32_t> h_dof;
   std::vector<uint8_t> h_owned, h_kind;
   int *d_pm = nullptr, *d_po = nullptr, *d_dof = nullptr, *d_out_off = nullptr,
@@ -49,7 +50,7 @@ struct Level {
   double *W64 = nullptr;
   float *W32 = nullptr;
   uint16_t *W16 = nullptr;
-  float *Wscale = nullptr;
+  float *Wscale = nullptr, *Cscale = nullptr;
   int w16_kind = 0;
   // coarsest level: column-major inverse
   double *C0 = nullptr, *gemv_partial = nullptr;
@@ -83,6 +84,19 @@ struct MG {
   Krylov kry;
   std::map<GraphKey, hipGraphExec_t> graphs;
   double setup_ms = 0.0;
+  // persistent setup scratch: dense blocks, pivot status, coarse dense matrix, GJ work
+  double *blk_scratch = nullptr, *dense_scratch = nullptr, *gj_work = nullptr;
+  int *status = nullptr, *status0 = nullptr;
+  int64_t blk_total = 0;
+  int64_t *all_boff = nullptr;
+  int *all_pm = nullptr;
+  int npatch_all = 0, mmax_all = 1;
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // event timing of the finest-level Schwarz kernel
+  bool prof_on = false;
+  size_t prof_used = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
 };
 
 extern thread_local std::string g_last_error;
@@ -97,6 +111,7 @@ fsi_status fgmres(MG &mg, const double *b, double *x, int x0_nonzero, const fsi_
                   fsi_solve_info *info, hipStream_t st);
 RasView ras_view(const Level &L);
 void ensure_krylov(MG &mg, int m);
+void refactor(MG &mg, hipStream_t st);
 
 struct FgmresRun {
   enum Phase { kFirst, kIter, kCheck, kDone };

@@ -39,23 +39,31 @@ void gj_large(double *A, int n, int *status_dev, double *work, hipStream_t st);
 void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm, const int *po,
                        const int64_t *woff, const int *own_off, const int *own_local, int npatch,
                        int64_t total_owned, const int *orow_patch, const int *orow_r, double *W64,
-                       float *W32, uint16_t *W16, int w16_kind, float *wscale, hipStream_t st);
+                       float *W32, uint16_t *W16, int w16_kind, float *wscale,
+                       const int64_t *pdof_off, const float *cscale, hipStream_t st);
+// 16-bit storage: per-column scales of the owned rows of every block inverse
+void launch_colscale(const double *blocks, const int64_t *boff, const int *pm, const int *po,
+                     const int *own_off, const int *own_local, const int64_t *pdof_off,
+                     int64_t total_cols, const int *col_patch, const int *col_local, float *cscale,
+                     hipStream_t st);
 void launch_transpose_colmajor(const double *A, int n, double *W, hipStream_t st);
 
 // ---- smoother (a5): e[out] += omega * W_k s[I_k] for every owned row
+//      (16-bit: W_k = diag(rs) W16 diag(cs), two-sided scaling)
 struct RasView {
   int ntask;
   const int *task_patch, *task_row0;
   const int *pm, *po;
   const int64_t *pdof_off, *woff;
   const int *dof, *out_off, *out_idx;
+  const float *cscale;   // 16-bit storage: column scales (per patch dof), else null
 };
 void launch_ras_f64(const RasView &v, const double *W, const double *s, double *e, double omega,
-                    hipStream_t st);
+                    bool finest, hipStream_t st);
 void launch_ras_f32(const RasView &v, const float *W, const float *s, float *e, float omega,
-                    hipStream_t st);
+                    bool finest, hipStream_t st);
 void launch_ras_16(const RasView &v, const uint16_t *W, int w16_kind, const float *wscale,
-                   const float *s, float *e, float omega, hipStream_t st);
+                   const float *s, float *e, float omega, bool finest, hipStream_t st);
 
 // ---- coarsest solve (a7): y = W x, W column-major n x n FP64
 void launch_dense_gemv(const double *W, int n, const double *x, double *y, double *partial,

@@ -197,116 +197,190 @@ __device__ inline Argmax wave_argmax(Argmax a) {
   return a;
 }
 
-// Panel phase on a panel P (row stride ps) of m rows and w columns whose
-// column t corresponds to pivot p0 + t.  fcol: m scratch doubles.  Executed
-// by one workgroup of nthr threads.  Returns 0 or 1 + failing pivot.
-template <int NTHR>
-__device__ int panel_phase(double *P, int ps, int m, int p0, int w, double *fcol, int *swaps,
-                           Argmax *red, int *s_flag) {
-  const int tid = threadIdx.x;
-  for (int t = 0; t < w; ++t) {
-    const int p = p0 + t;
-    Argmax best{-1.0, 0x7fffffff};
-    for (int i = p + tid; i < m; i += NTHR) {
-      const double a = fabs(P[(int64_t)i * ps + t]);
-      best = better(best, Argmax{a != a ? INFINITY : a, i});
+// Panel pivot steps executed by ONE wavefront: lane l owns the panel rows
+// i = l, l + 64, ...; the pivot search is a shuffle argmax; the pivot-row
+// swap, the broadcast of the pivot row and the updates are LDS accesses of
+// that single wave, which the LDS serves in program order, so a step needs
+// no workgroup barrier.  Panel element (i, c) at P[i * ps + c].  TC >= 0:
+// the step's pivot column is the compile-time TC of a full-width panel.
+template <int NB, int TC>
+__device__ __forceinline__ int pivot_step(double *P, int ps, int m, int p0, int w, int t_rt,
+                                          int *swaps) {
+  constexpr bool FULL = TC >= 0;
+  const int t = FULL ? TC : t_rt;
+  const int lane = threadIdx.x & 63;
+  const int p = p0 + t;
+  Argmax best{-1.0, 0x7fffffff};
+  for (int i = p + lane; i < m; i += 64) {
+    const double a = fabs(P[i * ps + t]);
+    best = better(best, Argmax{a != a ? INFINITY : a, i});
+  }
+  best = wave_argmax(best);
+  if (!(best.v > 0.0) || isinf(best.v)) return p + 1;
+  const int piv = best.i;
+  if (lane == 0) swaps[p] = piv;
+  if (piv != p && lane < (FULL ? NB : w)) {
+    const double a = P[p * ps + lane];
+    P[p * ps + lane] = P[piv * ps + lane];
+    P[piv * ps + lane] = a;
+  }
+  const double d = 1.0 / P[p * ps + t];
+  double prow[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) prow[c] = ((FULL || c < w) && c != t) ? P[p * ps + c] * d : 0.0;
+  for (int i = lane; i < m; i += 64) {
+    double *row = P + i * ps;
+    double v[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) v[c] = (FULL || c < w) ? row[c] : 0.0;
+    if (i == p) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) v[c] = (c == t) ? d : prow[c];
+    } else {
+      const double f = FULL ? v[FULL ? TC : 0] : row[t];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) v[c] = (c == t) ? -f * d : v[c] - f * prow[c];
     }
-    best = wave_argmax(best);
-    if ((tid & 63) == 0) red[tid >> 6] = best;
-    __syncthreads();
-    if (tid == 0) {
-      Argmax b = red[0];
-      for (int q = 1; q < NTHR / 64; ++q) b = better(b, red[q]);
-      swaps[p] = b.i;
-      s_flag[0] = (!(b.v > 0.0) || isinf(b.v)) ? p + 1 : 0;
-    }
-    __syncthreads();
-    if (s_flag[0]) return s_flag[0];
-    const int piv = swaps[p];
-    if (piv != p) {
-      for (int c = tid; c < w; c += NTHR) {
-        const double a = P[(int64_t)p * ps + c];
-        P[(int64_t)p * ps + c] = P[(int64_t)piv * ps + c];
-        P[(int64_t)piv * ps + c] = a;
-      }
-    }
-    __syncthreads();
-    const double d = 1.0 / P[(int64_t)p * ps + t];
-    for (int i = tid; i < m; i += NTHR) fcol[i] = P[(int64_t)i * ps + t];
-    __syncthreads();
-    for (int c = tid; c < w; c += NTHR)
-      P[(int64_t)p * ps + c] = (c == t) ? d : P[(int64_t)p * ps + c] * d;
-    __syncthreads();
-    for (int64_t idx = tid; idx < (int64_t)m * w; idx += NTHR) {
-      const int i = (int)(idx / w);
-      const int c = (int)(idx % w);
-      if (i == p) continue;
-      const double f = fcol[i];
-      P[(int64_t)i * ps + c] = (c == t) ? -f * d : P[(int64_t)i * ps + c] - f * P[(int64_t)p * ps + c];
-    }
-    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (FULL || c < w) row[c] = v[c];
   }
   return 0;
 }
 
+template <int NB, int T>
+__device__ __forceinline__ int full_steps(double *P, int ps, int m, int p0, int *swaps) {
+  if constexpr (T < NB) {
+    const int f = pivot_step<NB, T>(P, ps, m, p0, NB, T, swaps);
+    if (f) return f;
+    return full_steps<NB, T + 1>(P, ps, m, p0, swaps);
+  } else {
+    return 0;
+  }
+}
+
 template <int NB>
-__global__ __launch_bounds__(256) void k_gj_batched(double *blocks, const int64_t *boff,
-                                                    const int *pm, int *status) {
+__device__ int panel_wave(double *P, int ps, int m, int p0, int w, int *swaps) {
+  if (w == NB) return full_steps<NB, 0>(P, ps, m, p0, swaps);
+  for (int t = 0; t < w; ++t) {
+    const int f = pivot_step<NB, -1>(P, ps, m, p0, w, t, swaps);
+    if (f) return f;
+  }
+  return 0;
+}
+
+// The panel's row swaps (p0+t <-> swaps[p0+t], in order) as one permutation
+// of at most 2 w rows: dst[k] receives the old row src[k].  One thread.
+template <int NB>
+__device__ int row_permutation(const int *swaps, int p0, int w, int *dst, int *src, int *pos,
+                               int *cur) {
+  int cnt = 0;
+  auto slot = [&](int r) {
+    for (int q = 0; q < cnt; ++q)
+      if (pos[q] == r) return q;
+    pos[cnt] = r;
+    cur[cnt] = r;
+    return cnt++;
+  };
+  for (int t = 0; t < w; ++t) {
+    const int a = slot(p0 + t), b = slot(swaps[p0 + t]);
+    const int tmp = cur[a];
+    cur[a] = cur[b];
+    cur[b] = tmp;
+  }
+  int n = 0;
+  for (int q = 0; q < cnt; ++q)
+    if (cur[q] != pos[q]) {
+      dst[n] = pos[q];
+      src[n] = cur[q];
+      ++n;
+    }
+  return n;
+}
+
+// One workgroup per block (all smoothing levels in one launch); the m x NB
+// panel lives in LDS, its pivot steps run on the first wave, then all waves
+// apply the rank-w update to the other columns over (column, chunk of NB
+// rows) items: all rows but the pivot chunk first, then the pivot chunk
+// (whose old values are the update's right factor X).  Each item issues its
+// 2 NB loads before its FMAs.
+template <int NB, int NT>
+__global__ __launch_bounds__(NT) void k_gj_batched(double *blocks, const int64_t *boff,
+                                                   const int *pm, int *status) {
   extern __shared__ double lds[];
   __shared__ int swaps[kMaxPatch];
-  __shared__ Argmax red[4];
-  __shared__ int s_flag[1];
+  __shared__ int s_flag[1], s_nperm[1], s_dst[2 * NB], s_src[2 * NB], s_pos[2 * NB], s_cur[2 * NB];
   const int k = blockIdx.x;
   const int m = pm[k];
   double *A = blocks + boff[k];
-  double *P = lds;             // m x NB panel
-  double *fcol = lds + (int64_t)m * NB;
+  constexpr int PS = NB + 1;                // padded row stride: lane-owned rows hit distinct banks
+  double *P = lds;                          // m x NB, row-major, stride PS
   const int tid = threadIdx.x;
+  const int nchunk = (m + NB - 1) / NB;
   int fail = 0;
   for (int p0 = 0; p0 < m && !fail; p0 += NB) {
     const int w = min(NB, m - p0);
-    for (int64_t idx = tid; idx < (int64_t)m * w; idx += 256) {
-      const int i = (int)(idx / w), c = (int)(idx % w);
-      P[i * NB + c] = A[(int64_t)i * m + p0 + c];
+    const int rstep = NT / w;
+    if (tid < rstep * w)
+      for (int i = tid / w, c = tid % w; i < m; i += rstep) P[i * PS + c] = A[i * m + p0 + c];
+    __syncthreads();
+    if (tid < 64) {
+      const int f = panel_wave<NB>(P, PS, m, p0, w, swaps);
+      if (tid == 0) s_flag[0] = f;
     }
     __syncthreads();
-    fail = panel_phase<256>(P, NB, m, p0, w, fcol, swaps, red, s_flag);
+    fail = s_flag[0];
     if (fail) break;
-    for (int64_t idx = tid; idx < (int64_t)m * w; idx += 256) {
-      const int i = (int)(idx / w), c = (int)(idx % w);
-      A[(int64_t)i * m + p0 + c] = P[i * NB + c];
-    }
-    // rank-w update of the other columns (threads own columns: coalesced rows)
-    for (int j = tid; j < m; j += 256) {
-      if (j >= p0 && j < p0 + w) continue;
-      double X[NB];
+    if (tid < rstep * w)
+      for (int i = tid / w, c = tid % w; i < m; i += rstep) A[i * m + p0 + c] = P[i * PS + c];
+    const int ncol = m - w;
+    if (tid == 0) s_nperm[0] = row_permutation<NB>(swaps, p0, w, s_dst, s_src, s_pos, s_cur);
+    __syncthreads();
+    // row swaps of this panel on the other columns: independent loads, then stores
+    const int nperm = s_nperm[0];
+    for (int q = tid; q < ncol; q += NT) {
+      const int j = q < p0 ? q : q + w;
+      double vals[2 * NB];
 #pragma unroll
-      for (int t = 0; t < NB; ++t) {
-        if (t < w) {
-          const int pr = p0 + t, sw = swaps[pr];
-          if (sw != pr) {
-            const double a = A[(int64_t)pr * m + j];
-            A[(int64_t)pr * m + j] = A[(int64_t)sw * m + j];
-            A[(int64_t)sw * m + j] = a;
-          }
-        }
-      }
+      for (int k2 = 0; k2 < 2 * NB; ++k2) vals[k2] = (k2 < nperm) ? A[(int64_t)s_src[k2] * m + j] : 0.0;
 #pragma unroll
-      for (int t = 0; t < NB; ++t) X[t] = (t < w) ? A[(int64_t)(p0 + t) * m + j] : 0.0;
-      for (int i = 0; i < m; ++i) {
-        double acc = (i >= p0 && i < p0 + w) ? 0.0 : A[(int64_t)i * m + j];
-        const double *Pi = P + i * NB;
-#pragma unroll
-        for (int t = 0; t < NB; ++t) acc += Pi[t] * X[t];
-        A[(int64_t)i * m + j] = acc;
-      }
+      for (int k2 = 0; k2 < 2 * NB; ++k2)
+        if (k2 < nperm) A[(int64_t)s_dst[k2] * m + j] = vals[k2];
     }
     __threadfence_block();
     __syncthreads();
+    const int cp = p0 / NB;
+    for (int pass = 0; pass < 2; ++pass) {
+      const int nitem = pass == 0 ? ncol * (nchunk - 1) : ncol;
+      // item -> (chunk, column); the division happens once per item, not per FMA
+      for (int it = tid; it < nitem; it += NT) {
+        int chunk = pass == 0 ? it / ncol : cp;
+        if (pass == 0 && chunk >= cp) ++chunk;
+        const int q = it - (pass == 0 ? (it / ncol) * ncol : 0);
+        const int j = q < p0 ? q : q + w;
+        const int i0 = chunk * NB, i1 = min(m, i0 + NB);
+        double X[NB], Ac[NB];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) X[t] = (t < w) ? A[(int64_t)(p0 + t) * m + j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) Ac[u] = (pass == 0 && i0 + u < i1) ? A[(int64_t)(i0 + u) * m + j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+          if (i0 + u < i1) {
+            const double *Pi = P + (i0 + u) * PS;
+            double acc = Ac[u];
+#pragma unroll
+            for (int t = 0; t < NB; ++t) acc += Pi[t] * X[t];
+            A[(int64_t)(i0 + u) * m + j] = acc;
+          }
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
   }
   if (!fail) {
-    // un-permute columns in reverse order of the row swaps (threads own rows)
-    for (int i = tid; i < m; i += 256) {
+    for (int i = tid; i < m; i += NT) {
       double *Ai = A + (int64_t)i * m;
       for (int p = m - 1; p >= 0; --p) {
         const int sw = swaps[p];
@@ -321,82 +395,106 @@ __global__ __launch_bounds__(256) void k_gj_batched(double *blocks, const int64_
   if (tid == 0) status[k] = fail;
 }
 
+// panel width: 16 keeps the rank-w update's operands in registers (no spills)
 int gj_panel_width(int mmax) {
   const int64_t budget = 150 * 1024;
-  if ((int64_t)mmax * 33 * 8 <= budget) return 32;
   if ((int64_t)mmax * 17 * 8 <= budget) return 16;
   return 8;
+}
+
+template <int NB>
+static void launch_gj_nb(double *blocks, const int64_t *boff, const int *pm, int npatch, int mmax,
+                         int *status, hipStream_t st) {
+  const size_t shm = (size_t)mmax * (NB + 1) * sizeof(double);
+  (void)hipFuncSetAttribute((const void *)k_gj_batched<NB, 512>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  k_gj_batched<NB, 512><<<npatch, 512, shm, st>>>(blocks, boff, pm, status);
 }
 
 void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, int npatch, int mmax,
                        int *status, hipStream_t st) {
   if (npatch == 0) return;
   const int nb = gj_panel_width(mmax);
-  const size_t shm = (size_t)mmax * (nb + 1) * sizeof(double);
-  if (nb == 32) {
-    (void)hipFuncSetAttribute((const void *)k_gj_batched<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)shm);
-    k_gj_batched<32><<<npatch, 256, shm, st>>>(blocks, boff, pm, status);
-  } else if (nb == 16) {
-    (void)hipFuncSetAttribute((const void *)k_gj_batched<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)shm);
-    k_gj_batched<16><<<npatch, 256, shm, st>>>(blocks, boff, pm, status);
-  } else {
-    (void)hipFuncSetAttribute((const void *)k_gj_batched<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)shm);
-    k_gj_batched<8><<<npatch, 256, shm, st>>>(blocks, boff, pm, status);
-  }
+  if (nb == 16)
+    launch_gj_nb<16>(blocks, boff, pm, npatch, mmax, status, st);
+  else
+    launch_gj_nb<8>(blocks, boff, pm, npatch, mmax, status, st);
 }
 
-// ---- large single matrix (coarsest operator): panel in global memory, many
-// workgroups for the rank-w update.
-constexpr int kLargeNB = 16;
-__global__ __launch_bounds__(1024) void k_gj_large_panel(double *A, int n, int p0, int w,
-                                                         double *fcol, int *swaps, int *status) {
-  __shared__ Argmax red[16];
-  __shared__ int s_flag[1];
+// ---- large single matrix (coarsest operator): the panel lives in LDS
+// (column-major, contiguous pivot searches), one workgroup; the same kernel
+// applies the panel's row swaps to the other columns and copies their pivot
+// rows to X; the rank-w update then runs on many workgroups.
+template <int NB>
+__global__ __launch_bounds__(512) void k_gj_large_panel(double *A, int n, int p0, int w, int *swaps,
+                                                         double *X, int *status) {
+  extern __shared__ double lds[];
+  __shared__ int s_flag[1], s_nperm[1], s_dst[2 * NB], s_src[2 * NB], s_pos[2 * NB], s_cur[2 * NB];
   if (status[0]) return;
-  const int f = panel_phase<1024>(A + p0, n, n, p0, w, fcol, swaps, red, s_flag);
-  if (threadIdx.x == 0 && f) status[0] = f;
-}
-// apply the panel's swaps to the non-panel columns and copy the pivot rows to X (w x n)
-__global__ void k_gj_large_swap(double *A, int n, int p0, int w, const int *swaps, double *X,
-                                const int *status) {
-  if (status[0]) return;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n || (j >= p0 && j < p0 + w)) return;
-  for (int t = 0; t < w; ++t) {
-    const int pr = p0 + t, sw = swaps[pr];
-    if (sw != pr) {
-      const double a = A[(int64_t)pr * n + j];
-      A[(int64_t)pr * n + j] = A[(int64_t)sw * n + j];
-      A[(int64_t)sw * n + j] = a;
-    }
+  constexpr int PS = NB + 1;                // padded row stride (bank spread)
+  double *P = lds;                          // n x NB, row-major, stride PS
+  const int tid = threadIdx.x;
+  const int rstep = 512 / w;
+  if (tid < rstep * w)
+    for (int i = tid / w, c = tid % w; i < n; i += rstep) P[i * PS + c] = A[(int64_t)i * n + p0 + c];
+  __syncthreads();
+  if (tid < 64) {
+    const int f = panel_wave<NB>(P, PS, n, p0, w, swaps);
+    if (tid == 0) s_flag[0] = f;
   }
-  for (int t = 0; t < w; ++t) X[(int64_t)t * n + j] = A[(int64_t)(p0 + t) * n + j];
+  __syncthreads();
+  if (s_flag[0]) {
+    if (tid == 0) status[0] = s_flag[0];
+    return;
+  }
+  if (tid < rstep * w)
+    for (int i = tid / w, c = tid % w; i < n; i += rstep) A[(int64_t)i * n + p0 + c] = P[i * PS + c];
+  if (tid == 0) s_nperm[0] = row_permutation<NB>(swaps, p0, w, s_dst, s_src, s_pos, s_cur);
+  __syncthreads();
+  const int nperm = s_nperm[0];
+  for (int j = tid; j < n; j += 512) {
+    if (j >= p0 && j < p0 + w) continue;
+    double vals[2 * NB];
+#pragma unroll
+    for (int k2 = 0; k2 < 2 * NB; ++k2) vals[k2] = (k2 < nperm) ? A[(int64_t)s_src[k2] * n + j] : 0.0;
+#pragma unroll
+    for (int k2 = 0; k2 < 2 * NB; ++k2)
+      if (k2 < nperm) A[(int64_t)s_dst[k2] * n + j] = vals[k2];
+    for (int t = 0; t < w; ++t) X[(int64_t)t * n + j] = A[(int64_t)(p0 + t) * n + j];
+  }
 }
 // rows split over blockIdx.y, columns over threads
+template <int NB>
 __global__ __launch_bounds__(256) void k_gj_large_update(double *A, int n, int p0, int w,
                                                          const double *X, const int *status) {
   if (status[0]) return;
-  __shared__ double Pn[64 * kLargeNB];
+  __shared__ double Pn[64 * NB];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i0 = blockIdx.y * 64;
   const int i1 = min(n, i0 + 64);
   for (int idx = threadIdx.x; idx < (i1 - i0) * w; idx += blockDim.x) {
     const int i = idx / w, t = idx % w;
-    Pn[i * kLargeNB + t] = A[(int64_t)(i0 + i) * n + p0 + t];
+    Pn[i * NB + t] = A[(int64_t)(i0 + i) * n + p0 + t];
   }
   __syncthreads();
   if (j >= n || (j >= p0 && j < p0 + w)) return;
-  double Xr[kLargeNB];
+  double Xr[NB];
 #pragma unroll
-  for (int t = 0; t < kLargeNB; ++t) Xr[t] = (t < w) ? X[(int64_t)t * n + j] : 0.0;
-  for (int i = i0; i < i1; ++i) {
-    double acc = (i >= p0 && i < p0 + w) ? 0.0 : A[(int64_t)i * n + j];
+  for (int t = 0; t < NB; ++t) Xr[t] = (t < w) ? X[(int64_t)t * n + j] : 0.0;
+  for (int i = i0; i < i1; i += 8) {
+    double v[8];
 #pragma unroll
-    for (int t = 0; t < kLargeNB; ++t) acc += Pn[(i - i0) * kLargeNB + t] * Xr[t];
-    A[(int64_t)i * n + j] = acc;
+    for (int u = 0; u < 8; ++u)
+      v[u] = (i + u < i1 && !(i + u >= p0 && i + u < p0 + w)) ? A[(int64_t)(i + u) * n + j] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (i + u < i1) {
+        double acc = v[u];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) acc += Pn[(i + u - i0) * NB + t] * Xr[t];
+        A[(int64_t)(i + u) * n + j] = acc;
+      }
+    }
   }
 }
 __global__ void k_gj_large_unpermute(double *A, int n, const int *swaps, const int *status) {
@@ -414,19 +512,31 @@ __global__ void k_gj_large_unpermute(double *A, int n, const int *swaps, const i
   }
 }
 
-// work: n (fcol) + n (swaps as int, stored in doubles' space) + kLargeNB * n (X)
-void gj_large(double *A, int n, int *status_dev, double *work, hipStream_t st) {
-  double *fcol = work;
-  int *swaps = reinterpret_cast<int *>(work + n);
-  double *X = work + 2 * (int64_t)n;
-  for (int p0 = 0; p0 < n; p0 += kLargeNB) {
-    const int w = std::min(kLargeNB, n - p0);
-    k_gj_large_panel<<<1, 1024, 0, st>>>(A, n, p0, w, fcol, swaps, status_dev);
-    k_gj_large_swap<<<cdiv(n, 256), 256, 0, st>>>(A, n, p0, w, swaps, X, status_dev);
+template <int NB>
+static void gj_large_nb(double *A, int n, int *status_dev, double *work, hipStream_t st) {
+  int *swaps = reinterpret_cast<int *>(work);
+  double *X = work + n;
+  const size_t shm = (size_t)(NB + 1) * n * sizeof(double);
+  (void)hipFuncSetAttribute((const void *)k_gj_large_panel<NB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  for (int p0 = 0; p0 < n; p0 += NB) {
+    const int w = std::min(NB, n - p0);
+    k_gj_large_panel<NB><<<1, 512, shm, st>>>(A, n, p0, w, swaps, X, status_dev);
     dim3 grid(cdiv(n, 256), cdiv(n, 64));
-    k_gj_large_update<<<grid, 256, 0, st>>>(A, n, p0, w, X, status_dev);
+    k_gj_large_update<NB><<<grid, 256, 0, st>>>(A, n, p0, w, X, status_dev);
   }
   k_gj_large_unpermute<<<cdiv(n, 256), 256, 0, st>>>(A, n, swaps, status_dev);
+}
+
+// work: n ints (swaps, in n doubles) + 16 n doubles (X)
+void gj_large(double *A, int n, int *status_dev, double *work, hipStream_t st) {
+  const int64_t budget = 150 * 1024;
+  if ((int64_t)n * 17 * 8 <= budget)
+    gj_large_nb<16>(A, n, status_dev, work, st);
+  else if ((int64_t)n * 9 * 8 <= budget)
+    gj_large_nb<8>(A, n, status_dev, work, st);
+  else
+    gj_large_nb<4>(A, n, status_dev, work, st);
 }
 
 // ------------------------------------------------------------------ packing of owned rows
@@ -458,7 +568,8 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
                                                     const int *__restrict__ orow_patch,
                                                     const int *__restrict__ orow_r, double *W64,
                                                     float *W32, uint16_t *W16, int w16_kind,
-                                                    float *wscale) {
+                                                    float *wscale, const int64_t *__restrict__ pdof_off,
+                                                    const float *__restrict__ cscale) {
   const int64_t t = blockIdx.x * 4 + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (t >= total_owned) return;
@@ -466,9 +577,10 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
   const int r = orow_r[t];
   const int m = pm[k], o = po[k];
   const double *row = blocks + boff[k] + (int64_t)own_local[own_off[k] + r] * m;
+  const float *cs = W16 ? cscale + pdof_off[k] : nullptr;
   double mx = 0.0;
   if (W16) {
-    for (int c = lane; c < m; c += 64) mx = fmax(mx, fabs(row[c]));
+    for (int c = lane; c < m; c += 64) mx = fmax(mx, fabs(row[c]) / (double)cs[c]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
     if (mx == 0.0) mx = 1.0;
@@ -479,19 +591,50 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
     const double v = row[c];
     if (W64) W64[dst] = v;
     if (W32) W32[dst] = (float)v;
-    if (W16) W16[dst] = w16_kind == 1 ? to_bf16((float)(v / mx)) : to_fp16((float)(v / mx));
+    if (W16) {
+      const float q = (float)(v / ((double)cs[c] * mx));
+      W16[dst] = w16_kind == 1 ? to_bf16(q) : to_fp16(q);
+    }
   }
+}
+
+// column scales of the owned rows of every block inverse: cs = max_r |Binv[own_r][c]|
+__global__ void k_colscale(const double *__restrict__ blocks, const int64_t *__restrict__ boff,
+                           const int *__restrict__ pm, const int *__restrict__ po,
+                           const int *__restrict__ own_off, const int *__restrict__ own_local,
+                           const int64_t *__restrict__ pdof_off, int64_t total_cols,
+                           const int *__restrict__ col_patch, const int *__restrict__ col_local,
+                           float *cscale) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= total_cols) return;
+  const int k = col_patch[t], c = col_local[t];
+  const int m = pm[k], o = po[k];
+  const double *B = blocks + boff[k];
+  double mx = 0.0;
+  for (int r = 0; r < o; ++r) mx = fmax(mx, fabs(B[(int64_t)own_local[own_off[k] + r] * m + c]));
+  cscale[pdof_off[k] + c] = mx > 0.0 ? (float)mx : 1.0f;
+}
+void launch_colscale(const double *blocks, const int64_t *boff, const int *pm, const int *po,
+                     const int *own_off, const int *own_local, const int64_t *pdof_off,
+                     int64_t total_cols, const int *col_patch, const int *col_local, float *cscale,
+                     hipStream_t st) {
+  if (total_cols == 0) return;
+  k_colscale<<<cdiv(total_cols, 256), 256, 0, st>>>(blocks, boff, pm, po, own_off, own_local,
+                                                     pdof_off, total_cols, col_patch, col_local,
+                                                     cscale);
 }
 
 void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm, const int *po,
                        const int64_t *woff, const int *own_off, const int *own_local, int npatch,
                        int64_t total_owned, const int *orow_patch, const int *orow_r, double *W64,
-                       float *W32, uint16_t *W16, int w16_kind, float *wscale, hipStream_t st) {
+                       float *W32, uint16_t *W16, int w16_kind, float *wscale,
+                       const int64_t *pdof_off, const float *cscale, hipStream_t st) {
   (void)npatch;
   if (total_owned == 0) return;
   k_pack_owned<<<cdiv(total_owned, 4), 256, 0, st>>>(blocks, boff, pm, po, woff, own_off,
                                                       own_local, total_owned, orow_patch, orow_r,
-                                                      W64, W32, W16, w16_kind, wscale);
+                                                      W64, W32, W16, w16_kind, wscale, pdof_off,
+                                                      cscale);
 }
 
 __global__ void k_transpose(const double *A, int n, double *W) {
@@ -505,93 +648,96 @@ void launch_transpose_colmajor(const double *A, int n, double *W, hipStream_t st
 }
 
 // ------------------------------------------------------------------ restricted Schwarz
-// One wave per (patch, 64 owned rows): the patch's residual entries are
-// gathered into the wave's LDS slice, then each lane accumulates one owned
-// row of B_k^{-1} (stored column-major, so a step over a column is one
-// coalesced 64-row load) and adds omega times it to its owned dof.
-template <typename WT>
-__device__ inline float w16val(WT v, int kind);
-template <>
-__device__ inline float w16val<uint16_t>(uint16_t v, int kind) {
+// One workgroup per (patch, 64 owned rows).  The patch's residual entries
+// are gathered once into LDS; each of the four waves accumulates its quarter
+// of the columns of the owned rows of B_k^{-1} (stored column-major, so one
+// step over a column is one coalesced 64-row load, eight loads in flight per
+// lane), the partial sums meet in LDS and lane r of the first wave adds
+// omega times row r to its owned dof.  TAG only names the finest-level launch.
+__device__ inline float w16val(uint16_t v, int kind) {
   return kind == 1 ? from_bf16(v) : from_fp16(v);
 }
 
-template <typename WT, typename VT, typename AT, bool IS16>
+template <typename WT, typename AT, bool IS16>
+__device__ inline AT wload(const WT *w, int64_t idx, int kind) {
+  if constexpr (IS16)
+    return (AT)w16val(w[idx], kind);
+  else
+    return (AT)w[idx];
+}
+
+template <typename WT, typename VT, typename AT, bool IS16, int TAG>
 __global__ __launch_bounds__(256) void k_ras(RasView v, const WT *__restrict__ W, int w16_kind,
                                              const float *__restrict__ wscale,
                                              const VT *__restrict__ s, VT *__restrict__ e,
                                              AT omega) {
-  __shared__ AT xs[4][kMaxPatch];
+  __shared__ AT xs[kMaxPatch];
+  __shared__ AT red[3][64];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int task = blockIdx.x * 4 + wave;
-  const bool valid = task < v.ntask;
-  int k = 0, r0 = 0, m = 0, o = 0;
-  if (valid) {
-    k = v.task_patch[task];
-    r0 = v.task_row0[task];
-    m = v.pm[k];
-    o = v.po[k];
-    const int *d = v.dof + v.pdof_off[k];
-    for (int c = lane; c < m; c += 64) xs[wave][c] = (AT)s[d[c]];
+  const int task = blockIdx.x;
+  const int k = v.task_patch[task];
+  const int r0 = v.task_row0[task];
+  const int m = v.pm[k], o = v.po[k];
+  const int *d = v.dof + v.pdof_off[k];
+  if constexpr (IS16) {
+    const float *cs = v.cscale + v.pdof_off[k];
+    for (int c = threadIdx.x; c < m; c += 256) xs[c] = (AT)s[d[c]] * (AT)cs[c];
+  } else {
+    for (int c = threadIdx.x; c < m; c += 256) xs[c] = (AT)s[d[c]];
   }
   __syncthreads();
-  if (!valid) return;
   const int row = r0 + lane;
-  if (row >= o) return;
-  const WT *w = W + v.woff[k] + row;
-  const AT *x = xs[wave];
-  AT a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-  int c = 0;
-  for (; c + 4 <= m; c += 4) {
-    AT w0, w1, w2, w3;
-    if constexpr (IS16) {
-      w0 = w16val<WT>(w[(int64_t)c * o], w16_kind);
-      w1 = w16val<WT>(w[(int64_t)(c + 1) * o], w16_kind);
-      w2 = w16val<WT>(w[(int64_t)(c + 2) * o], w16_kind);
-      w3 = w16val<WT>(w[(int64_t)(c + 3) * o], w16_kind);
-    } else {
-      w0 = (AT)w[(int64_t)c * o];
-      w1 = (AT)w[(int64_t)(c + 1) * o];
-      w2 = (AT)w[(int64_t)(c + 2) * o];
-      w3 = (AT)w[(int64_t)(c + 3) * o];
+  const int quarter = (m + 3) >> 2;
+  const int c0 = wave * quarter, c1 = min(m, c0 + quarter);
+  AT acc = 0;
+  if (row < o) {
+    const WT *w = W + v.woff[k] + row;
+    AT a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int c = c0;
+    for (; c + 8 <= c1; c += 8) {
+      AT wv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) wv[u] = wload<WT, AT, IS16>(w, (int64_t)(c + u) * o, w16_kind);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += wv[u] * xs[c + u];
     }
-    a0 += w0 * x[c];
-    a1 += w1 * x[c + 1];
-    a2 += w2 * x[c + 2];
-    a3 += w3 * x[c + 3];
+    for (; c < c1; ++c) a[0] += wload<WT, AT, IS16>(w, (int64_t)c * o, w16_kind) * xs[c];
+    acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
-  for (; c < m; ++c) {
-    AT wv;
-    if constexpr (IS16)
-      wv = w16val<WT>(w[(int64_t)c * o], w16_kind);
-    else
-      wv = (AT)w[(int64_t)c * o];
-    a0 += wv * x[c];
+  if (wave > 0) red[wave - 1][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && row < o) {
+    acc = ((acc + red[0][lane]) + red[1][lane]) + red[2][lane];
+    if constexpr (IS16) acc *= (AT)wscale[v.out_off[k] + row];
+    const int g = v.out_idx[v.out_off[k] + row];
+    e[g] = e[g] + (VT)(omega * acc);
   }
-  AT acc = (a0 + a1) + (a2 + a3);
-  if constexpr (IS16) acc *= (AT)wscale[v.out_off[k] + row];
-  const int g = v.out_idx[v.out_off[k] + row];
-  e[g] = e[g] + (VT)(omega * acc);
 }
 
 void launch_ras_f64(const RasView &v, const double *W, const double *s, double *e, double omega,
-                    hipStream_t st) {
+                    bool finest, hipStream_t st) {
   if (v.ntask == 0) return;
-  k_ras<double, double, double, false><<<cdiv(v.ntask, 4), 256, 0, st>>>(v, W, 0, nullptr, s, e,
-                                                                          omega);
+  if (finest)
+    k_ras<double, double, double, false, 1><<<v.ntask, 256, 0, st>>>(v, W, 0, nullptr, s, e, omega);
+  else
+    k_ras<double, double, double, false, 0><<<v.ntask, 256, 0, st>>>(v, W, 0, nullptr, s, e, omega);
 }
 void launch_ras_f32(const RasView &v, const float *W, const float *s, float *e, float omega,
-                    hipStream_t st) {
+                    bool finest, hipStream_t st) {
   if (v.ntask == 0) return;
-  k_ras<float, float, float, false><<<cdiv(v.ntask, 4), 256, 0, st>>>(v, W, 0, nullptr, s, e,
-                                                                       omega);
+  if (finest)
+    k_ras<float, float, float, false, 1><<<v.ntask, 256, 0, st>>>(v, W, 0, nullptr, s, e, omega);
+  else
+    k_ras<float, float, float, false, 0><<<v.ntask, 256, 0, st>>>(v, W, 0, nullptr, s, e, omega);
 }
 void launch_ras_16(const RasView &v, const uint16_t *W, int w16_kind, const float *wscale,
-                   const float *s, float *e, float omega, hipStream_t st) {
+                   const float *s, float *e, float omega, bool finest, hipStream_t st) {
   if (v.ntask == 0) return;
-  k_ras<uint16_t, float, float, true><<<cdiv(v.ntask, 4), 256, 0, st>>>(v, W, w16_kind, wscale,
-                                                                         s, e, omega);
+  if (finest)
+    k_ras<uint16_t, float, float, true, 1><<<v.ntask, 256, 0, st>>>(v, W, w16_kind, wscale, s, e, omega);
+  else
+    k_ras<uint16_t, float, float, true, 0><<<v.ntask, 256, 0, st>>>(v, W, w16_kind, wscale, s, e, omega);
 }
 
 // ------------------------------------------------------------------ coarsest solve GEMV

@@ -179,6 +179,7 @@ static void build_patch_layout(Level &L, const fsi_patches &P, MG &mg, hipStream
   L.d_orow_r = dupload(orow_r.data(), (int64_t)orow_r.size(), own, st);
   L.boff_total = boff[np];
   L.woff_total = woff[np];
+  L.h_boff = boff;
   hip_check(hipStreamSynchronize(st), "patch layout");
 }
 
@@ -194,16 +195,8 @@ RasView ras_view(const Level &L) {
   v.dof = L.d_dof;
   v.out_off = L.d_out_off;
   v.out_idx = L.d_out_idx;
+  v.cscale = L.Cscale;
   return v;
-}
-
-// B_k = J[I_k, I_k] for every patch into a fresh device buffer (Sum m_k^2 doubles)
-double *extract_blocks(MG &mg, Level &L, hipStream_t st, std::vector<void *> &tmp) {
-  double *B = dalloc<double>(L.boff_total, tmp);
-  launch_fill_f64(B, L.boff_total, 0.0, st);
-  launch_extract(L.J.v64(), L.npatch, L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff, B, L.sum_m,
-                 L.d_row_patch, L.d_row_local, st);
-  return B;
 }
 
 static void free_list(std::vector<void *> &v) {
@@ -211,87 +204,116 @@ static void free_list(std::vector<void *> &v) {
   v.clear();
 }
 
-// inverse of every block, keep the owned rows in the storage precision of the level
-static void setup_level_blocks(MG &mg, Level &L, int lev, hipStream_t st) {
-  std::vector<void *> tmp;
-  try {
-    double *B = extract_blocks(mg, L, st, tmp);
-    int *status = dalloc<int>(L.npatch, tmp);
-    launch_gj_batched(B, L.d_boff, L.d_pm, L.npatch, L.mmax, status, st);
-    hip_check(hipGetLastError(), "gj launch");
-    std::vector<int> hs(L.npatch);
-    hip_check(hipMemcpyAsync(hs.data(), status, sizeof(int) * L.npatch, hipMemcpyDeviceToHost, st),
-              "D2H status");
-    hip_check(hipStreamSynchronize(st), "block inversion");
-    for (int k = 0; k < L.npatch; ++k)
-      if (hs[k]) {
-        char buf[160];
-        snprintf(buf, sizeof buf, "level %d patch %d: zero or non-finite pivot at step %d", lev, k,
-                 hs[k] - 1);
-        throw Error(FSI_E_SINGULAR, buf);
-      }
-    const int prec = mg.opts.precision;
-    if (prec == FSI_PREC_FP64) {
-      L.W64 = dalloc<double>(L.woff_total, mg.owned);
-    } else if (prec == FSI_PREC_MIXED_FP32) {
-      L.W32 = dalloc<float>(L.woff_total, mg.owned);
-    } else {
+// owned rows of every block inverse in the storage precision of the level
+// (the inverted blocks of level L sit at mg.blk_scratch + L.blk_base)
+static void pack_level(MG &mg, Level &L, hipStream_t st) {
+  const double *B = mg.blk_scratch + L.blk_base;
+  const int prec = mg.opts.precision;
+  if (prec == FSI_PREC_FP64) {
+    if (!L.W64) L.W64 = dalloc<double>(L.woff_total, mg.owned);
+  } else if (prec == FSI_PREC_MIXED_FP32) {
+    if (!L.W32) L.W32 = dalloc<float>(L.woff_total, mg.owned);
+  } else {
+    if (!L.W16) {
       L.W16 = dalloc<uint16_t>(L.woff_total, mg.owned);
       L.Wscale = dalloc<float>(L.total_owned, mg.owned);
-      L.w16_kind = prec == FSI_PREC_MIXED_BF16 ? 1 : 2;
+      L.Cscale = dalloc<float>(L.sum_m, mg.owned);
     }
-    launch_pack_owned(B, L.d_boff, L.d_pm, L.d_po, L.d_woff, L.d_out_off, L.d_own_local, L.npatch,
-                      L.total_owned, L.d_orow_patch, L.d_orow_r, L.W64, L.W32, L.W16, L.w16_kind,
-                      L.Wscale, st);
-    hip_check(hipGetLastError(), "pack launch");
-    hip_check(hipStreamSynchronize(st), "pack");
-  } catch (...) {
-    free_list(tmp);
-    throw;
+    L.w16_kind = prec == FSI_PREC_MIXED_BF16 ? 1 : 2;
+    launch_colscale(B, L.d_boff, L.d_pm, L.d_po, L.d_out_off, L.d_own_local, L.d_pdof_off,
+                    L.sum_m, L.d_row_patch, L.d_row_local, L.Cscale, st);
   }
-  free_list(tmp);
+  launch_pack_owned(B, L.d_boff, L.d_pm, L.d_po, L.d_woff, L.d_out_off, L.d_own_local, L.npatch,
+                    L.total_owned, L.d_orow_patch, L.d_orow_r, L.W64, L.W32, L.W16, L.w16_kind,
+                    L.Wscale, L.d_pdof_off, L.Cscale, st);
+  hip_check(hipGetLastError(), "pack launch");
 }
 
-static void setup_coarse(MG &mg, Level &L, hipStream_t st) {
+// coarsest operator: dense copy, Gauss-Jordan inverse, column-major for the GEMV (no sync)
+static void enqueue_coarse(MG &mg, Level &L, hipStream_t st) {
   const int n = L.n;
-  std::vector<void *> tmp;
-  try {
-    double *A = dalloc<double>((int64_t)n * n, tmp);
-    launch_fill_f64(A, (int64_t)n * n, 0.0, st);
-    launch_csr_to_dense(L.J.v64(), A, st);
-    double *work = dalloc<double>((int64_t)(2 + 16) * n + 64, tmp);
-    int *status = dalloc<int>(1, tmp);
-    hip_check(hipMemsetAsync(status, 0, sizeof(int), st), "memset");
-    gj_large(A, n, status, work, st);
-    hip_check(hipGetLastError(), "coarse gj launch");
-    int hs = 0;
-    hip_check(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, st), "D2H");
-    hip_check(hipStreamSynchronize(st), "coarse inversion");
-    if (hs) {
+  double *A = mg.dense_scratch;
+  launch_fill_f64(A, (int64_t)n * n, 0.0, st);
+  launch_csr_to_dense(L.J.v64(), A, st);
+  hip_check(hipMemsetAsync(mg.status0, 0, sizeof(int), st), "memset");
+  gj_large(A, n, mg.status0, mg.gj_work, st);
+  launch_transpose_colmajor(A, n, L.C0, st);
+  hip_check(hipGetLastError(), "coarse launch");
+}
+
+// setup of a1-a3 from the device-resident operator values: the coarsest
+// inversion runs on a second stream while all smoothing levels' blocks are
+// extracted and inverted in one launch on the main stream
+void refactor(MG &mg, hipStream_t st) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (mg.mixed)
+    for (int l = 1; l < mg.nlevels; ++l) launch_cast_d2f(mg.lv[l].J.val, mg.lv[l].J.val32, mg.lv[l].J.nnz, st);
+  hip_check(hipEventRecord(mg.ev_fork, st), "fork");
+  hip_check(hipStreamWaitEvent(mg.side_stream, mg.ev_fork, 0), "fork wait");
+  enqueue_coarse(mg, mg.lv[0], mg.side_stream);
+  hip_check(hipEventRecord(mg.ev_join, mg.side_stream), "join");
+  if (mg.nlevels > 1) {
+    launch_fill_f64(mg.blk_scratch, mg.blk_total, 0.0, st);
+    for (int l = 1; l < mg.nlevels; ++l) {
+      Level &L = mg.lv[l];
+      launch_extract(L.J.v64(), L.npatch, L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff,
+                     mg.blk_scratch + L.blk_base, L.sum_m, L.d_row_patch, L.d_row_local, st);
+    }
+    launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.npatch_all, mg.mmax_all, mg.status, st);
+    hip_check(hipGetLastError(), "gj launch");
+    for (int l = 1; l < mg.nlevels; ++l) pack_level(mg, mg.lv[l], st);
+  }
+  hip_check(hipStreamWaitEvent(st, mg.ev_join, 0), "join wait");
+  std::vector<int> hs(mg.npatch_all + 1, 0);
+  if (mg.npatch_all)
+    hip_check(hipMemcpyAsync(hs.data(), mg.status, sizeof(int) * mg.npatch_all, hipMemcpyDeviceToHost, st),
+              "D2H status");
+  hip_check(hipMemcpyAsync(hs.data() + mg.npatch_all, mg.status0, sizeof(int), hipMemcpyDeviceToHost, st),
+            "D2H status");
+  hip_check(hipStreamSynchronize(st), "refactor");
+  if (hs[mg.npatch_all]) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "level 0 (coarsest): zero or non-finite pivot at step %d", hs[mg.npatch_all] - 1);
+    throw Error(FSI_E_SINGULAR, buf);
+  }
+  for (int q = 0; q < mg.npatch_all; ++q)
+    if (hs[q]) {
+      int l = 1, k = q;
+      while (l < mg.nlevels - 1 && k >= mg.lv[l].npatch) k -= mg.lv[l++].npatch;
       char buf[160];
-      snprintf(buf, sizeof buf, "level 0 (coarsest): zero or non-finite pivot at step %d", hs - 1);
+      snprintf(buf, sizeof buf, "level %d patch %d: zero or non-finite pivot at step %d", l, k, hs[q] - 1);
       throw Error(FSI_E_SINGULAR, buf);
     }
-    L.C0 = dalloc<double>((int64_t)n * n, mg.owned);
-    launch_transpose_colmajor(A, n, L.C0, st);
-    L.gemv_partial = dalloc<double>((int64_t)8 * n, mg.owned);
-    hip_check(hipStreamSynchronize(st), "coarse transpose");
-  } catch (...) {
-    free_list(tmp);
-    throw;
-  }
-  free_list(tmp);
+  mg.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
 // ------------------------------------------------------------------ V-cycle
+// event pair around the finest-level Schwarz kernel while profiling
+static hipEvent_t *prof_pair(MG &mg, Level &L) {
+  if (!mg.prof_on || &L != &mg.lv.back()) return nullptr;
+  if (mg.prof_used == mg.prof_ev.size()) {
+    hipEvent_t a, b;
+    hip_check(hipEventCreate(&a), "event");
+    hip_check(hipEventCreate(&b), "event");
+    mg.prof_ev.push_back({a, b});
+  }
+  return &mg.prof_ev[mg.prof_used++].first;
+}
 static void ras64(MG &mg, Level &L, const double *s, double *e, hipStream_t st) {
-  launch_ras_f64(ras_view(L), L.W64, s, e, mg.opts.omega, st);
+  hipEvent_t *ev = prof_pair(mg, L);
+  if (ev) hip_check(hipEventRecord(ev[0], st), "record");
+  launch_ras_f64(ras_view(L), L.W64, s, e, mg.opts.omega, &L == &mg.lv.back(), st);
+  if (ev) hip_check(hipEventRecord(ev[1], st), "record");
 }
 static void ras32(MG &mg, Level &L, const float *s, float *e, hipStream_t st) {
+  hipEvent_t *ev = prof_pair(mg, L);
+  if (ev) hip_check(hipEventRecord(ev[0], st), "record");
   if (L.W32)
-    launch_ras_f32(ras_view(L), L.W32, s, e, (float)mg.opts.omega, st);
+    launch_ras_f32(ras_view(L), L.W32, s, e, (float)mg.opts.omega, &L == &mg.lv.back(), st);
   else
-    launch_ras_16(ras_view(L), L.W16, L.w16_kind, L.Wscale, s, e, (float)mg.opts.omega, st);
+    launch_ras_16(ras_view(L), L.W16, L.w16_kind, L.Wscale, s, e, (float)mg.opts.omega,
+                  &L == &mg.lv.back(), st);
+  if (ev) hip_check(hipEventRecord(ev[1], st), "record");
 }
 
 // FP64 V-cycle on level l: input L.r, output L.e
@@ -370,7 +392,7 @@ void apply_vcycle(MG &mg, const double *r, double *z, hipStream_t st) {
 }
 
 void run_vcycle(MG &mg, const double *r, double *z, hipStream_t st) {
-  if (mg.opts.use_graph) {
+  if (mg.opts.use_graph && !mg.prof_on) {
     // one graph per (input, output) pair; the Krylov loop reuses a small set of pairs
     GraphKey key{r, z};
     auto it = mg.graphs.find(key);
@@ -447,9 +469,38 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
       }
       alloc_level_vectors(*mg, L);
     }
-    setup_coarse(*mg, mg->lv[0], st);
-    for (int l = 1; l < nlevels; ++l) setup_level_blocks(*mg, mg->lv[l], l, st);
-    hip_check(hipStreamSynchronize(st), "setup");
+    // all levels' blocks in one scratch; one offset/size table for the batched inversion
+    std::vector<int64_t> all_boff;
+    std::vector<int> all_pm;
+    int64_t base = 0;
+    mg->mmax_all = 1;
+    for (int l = 1; l < nlevels; ++l) {
+      Level &L = mg->lv[l];
+      L.blk_base = base;
+      for (int k = 0; k < L.npatch; ++k) {
+        all_boff.push_back(base + L.h_boff[k]);
+        all_pm.push_back((int)(L.h_ptr[k + 1] - L.h_ptr[k]));
+      }
+      base += L.boff_total;
+      mg->mmax_all = std::max(mg->mmax_all, L.mmax);
+    }
+    mg->blk_total = base;
+    mg->npatch_all = (int)all_pm.size();
+    const int64_t n0 = mg->lv[0].n;
+    mg->blk_scratch = dalloc<double>(std::max<int64_t>(base, 1), mg->owned);
+    mg->all_boff = dupload(all_boff.data(), (int64_t)all_boff.size(), mg->owned, st);
+    mg->all_pm = dupload(all_pm.data(), (int64_t)all_pm.size(), mg->owned, st);
+    mg->status = dalloc<int>(std::max(mg->npatch_all, 1), mg->owned);
+    mg->status0 = dalloc<int>(1, mg->owned);
+    mg->dense_scratch = dalloc<double>(n0 * n0, mg->owned);
+    mg->gj_work = dalloc<double>((2 + 16) * n0 + 64, mg->owned);
+    mg->lv[0].C0 = dalloc<double>(n0 * n0, mg->owned);
+    mg->lv[0].gemv_partial = dalloc<double>(8 * n0, mg->owned);
+    hip_check(hipStreamCreateWithFlags(&mg->side_stream, hipStreamNonBlocking), "side stream");
+    hip_check(hipEventCreateWithFlags(&mg->ev_fork, hipEventDisableTiming), "event");
+    hip_check(hipEventCreateWithFlags(&mg->ev_join, hipEventDisableTiming), "event");
+    hip_check(hipStreamSynchronize(st), "upload");
+    refactor(*mg, st);
   } catch (...) {
     destroy_mg(mg);
     throw;
@@ -460,6 +511,16 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
 
 void destroy_mg(MG *mg) {
   if (!mg) return;
+  if (mg->side_stream) {
+    (void)hipStreamSynchronize(mg->side_stream);
+    (void)hipStreamDestroy(mg->side_stream);
+  }
+  if (mg->ev_fork) (void)hipEventDestroy(mg->ev_fork);
+  if (mg->ev_join) (void)hipEventDestroy(mg->ev_join);
+  for (auto &p : mg->prof_ev) {
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
   for (auto &kv : mg->graphs) (void)hipGraphExecDestroy(kv.second);
   mg->graphs.clear();
   free_list(mg->owned);
@@ -759,7 +820,7 @@ fsi_status fsi_mg_apply(struct fsi_mg *h, int32_t level, int32_t op, const doubl
         if (level == 0) throw Error(FSI_E_INVALID, "no patches on level 0");
         if (!L.W64) throw Error(FSI_E_INVALID, "op 4 needs the FP64 precision");
         launch_fill_f64(y_dev, L.n, 0.0, st);
-        launch_ras_f64(ras_view(L), L.W64, x_dev, y_dev, 1.0, st);
+        launch_ras_f64(ras_view(L), L.W64, x_dev, y_dev, 1.0, level == mg->nlevels - 1, st);
         break;
       case 5:
         if (level != 0) throw Error(FSI_E_INVALID, "direct solve only on level 0");
@@ -768,6 +829,51 @@ fsi_status fsi_mg_apply(struct fsi_mg *h, int32_t level, int32_t op, const doubl
       default: throw Error(FSI_E_INVALID, "unknown op");
     }
     hip_check(hipGetLastError(), "apply launch");
+    return FSI_OK;
+  })
+}
+
+fsi_status fsi_mg_refactor(struct fsi_mg *h, void *hip_stream) {
+  FSI_GUARD({
+    MG *mg = reinterpret_cast<MG *>(h);
+    if (!mg) throw Error(FSI_E_INVALID, "null handle");
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
+    refactor(*mg, st);
+    return FSI_OK;
+  })
+}
+
+fsi_status fsi_mg_jvalues(struct fsi_mg *h, int32_t level, double **val_dev) {
+  FSI_GUARD({
+    MG *mg = reinterpret_cast<MG *>(h);
+    if (!mg || !val_dev || level < 0 || level >= mg->nlevels) throw Error(FSI_E_INVALID, "bad argument");
+    *val_dev = mg->lv[level].J.val;
+    return FSI_OK;
+  })
+}
+
+fsi_status fsi_mg_profile(struct fsi_mg *h, int32_t enable, double out[2]) {
+  FSI_GUARD({
+    MG *mg = reinterpret_cast<MG *>(h);
+    if (!mg) throw Error(FSI_E_INVALID, "null handle");
+    if (enable) {
+      mg->prof_on = true;
+      mg->prof_used = 0;
+      return FSI_OK;
+    }
+    double tot = 0.0;
+    for (size_t i = 0; i < mg->prof_used; ++i) {
+      hip_check(hipEventSynchronize(mg->prof_ev[i].second), "event sync");
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, mg->prof_ev[i].first, mg->prof_ev[i].second), "elapsed");
+      tot += ms;
+    }
+    if (out) {
+      out[0] = tot;
+      out[1] = (double)mg->prof_used;
+    }
+    mg->prof_on = false;
+    mg->prof_used = 0;
     return FSI_OK;
   })
 }
@@ -800,17 +906,13 @@ fsi_status fsi_mg_export_patches(struct fsi_mg *h, int32_t level, int64_t *ptr, 
                 "D2H dof");
     if (owned) std::copy(L.h_owned.begin(), L.h_owned.end(), owned);
     if (blocks) {
-      std::vector<void *> tmp;
-      try {
-        double *B = extract_blocks(*mg, L, st, tmp);
-        hip_check(hipMemcpyAsync(blocks, B, sizeof(double) * L.boff_total, hipMemcpyDeviceToHost, st),
-                  "D2H blocks");
-        hip_check(hipStreamSynchronize(st), "export");
-      } catch (...) {
-        free_list(tmp);
-        throw;
-      }
-      free_list(tmp);
+      double *B = mg->blk_scratch + L.blk_base;
+      launch_fill_f64(B, L.boff_total, 0.0, st);
+      launch_extract(L.J.v64(), L.npatch, L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff, B, L.sum_m,
+                     L.d_row_patch, L.d_row_local, st);
+      hip_check(hipMemcpyAsync(blocks, B, sizeof(double) * L.boff_total, hipMemcpyDeviceToHost, st),
+                "D2H blocks");
+      hip_check(hipStreamSynchronize(st), "export");
     }
     return FSI_OK;
   })

@@ -27,7 +27,11 @@ class Problem:
 
     def __init__(self, spec, coeffs):
         lib = L.lib()
-        c = np.ascontiguousarray(coeffs, dtype=np.float64).ravel()
+        coeffs = np.asarray(coeffs, dtype=np.float64)
+        kmax = coeffs.shape[1] if coeffs.ndim > 1 else int(round((coeffs.size / spec.dim) ** (1.0 / spec.dim)))
+        if coeffs.size != spec.dim * kmax ** spec.dim:
+            raise ValueError("coefficient array must hold dim * kmax^dim values")
+        c = np.ascontiguousarray(coeffs).ravel()
         self._coeffs = c
         ps = L.ProblemSpecC()
         ps.dim, ps.nx, ps.ny, ps.nz = spec.dim, spec.nx, spec.ny, spec.nz
@@ -37,12 +41,12 @@ class Problem:
             ps.solid_lo[d] = spec.solid_lo[d]
             ps.solid_hi[d] = spec.solid_hi[d]
         ps.rho, ps.mu, ps.mu_s, ps.u_peak, ps.amp = spec.rho, spec.mu, spec.mu_s, spec.u_peak, spec.amp
-        ps.kmax = int(round(c.size / spec.dim) ** (1.0 / spec.dim))
+        ps.kmax = kmax
         ps.coeffs = L._ptr(c, C.c_double)
         h = C.c_void_p()
         st = lib.fsi_problem_build(C.byref(ps), C.byref(h))
         if st != 0:
-            raise L.FsiError(st, "problem build failed")
+            raise L.FsiError(st, "problem build failed: " + lib.fsi_problem_last_error().decode())
         self.h = h
         self.spec = spec
         self.nlevels = lib.fsi_problem_nlevels(h)
@@ -163,6 +167,18 @@ class MG:
         d["status"] = st
         d["history"] = hist[: d["iters"] + 1].copy()
         return x, d
+
+    def refactor(self):
+        """Re-run extraction, block inversion and coarse inversion on the device."""
+        L.check(L.lib().fsi_mg_refactor(self.h, _stream()), "refactor")
+
+    def profile_start(self):
+        L.check(L.lib().fsi_mg_profile(self.h, 1, None))
+
+    def profile_stop(self):
+        out = (C.c_double * 2)()
+        L.check(L.lib().fsi_mg_profile(self.h, 0, out))
+        return out[0], int(out[1])
 
     def export_patches(self, level, blocks=False):
         info = self.level_info(level)

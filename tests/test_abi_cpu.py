@@ -1,0 +1,164 @@
+"""CPU checks of the native library: exports, host-side validation, and the
+native problem builder against the checker's independent assembly."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import fem
+from oracle import problem as oprob
+from synth import ProblemSpec, config, fourier_coefficients
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in ("fsi_mg.h", "fsi_problem.h"):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"\b(fsi_[a-z0-9_]+)\s*\(", txt):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1709_05660_amd import _lib
+    L = _lib.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 20
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert set(_lib.EXPORTS) == declared
+    assert L.fsi_abi_version() == 1
+    assert L.fsi_status_string(-3) == b"singular block"
+
+
+def _csr(p, level, which="J"):
+    rp, ci, v, sh = p.csr(level, which)
+    return sp.csr_matrix((v, ci, rp), shape=sh)
+
+
+@pytest.mark.parametrize("name,kw", [("c0_2d_16x4", {}),
+                                     ("c3_3d_32x8x8", dict(nx=16, ny=4, nz=4, levels=2, patch=2)),
+                                     ("c1_2d_128x32", dict(nx=32, ny=8, levels=3, mu_s=3.0e4, seed=7))])
+def test_builder_matches_checker(name, kw):
+    """The native builder and the checker assemble the same hierarchy: P, R and
+    the patch lists bit for bit, J and b to rounding (sums in another order)."""
+    from paper_1709_05660_amd import Problem
+    s = config(name).with_(**kw)
+    a = fourier_coefficients(s.dim, s.seed)
+    p = Problem(s, a)
+    h = oprob.build(s, a, factor=False)
+    assert p.n == h.b.size
+    assert np.max(np.abs(p.y - h.y)) <= 1e-15 * np.max(np.abs(h.y))
+    assert np.max(np.abs(p.b - h.b)) <= 1e-13 * np.max(np.abs(h.b))
+    for l in range(p.nlevels):
+        A, B = _csr(p, l), h.levels[l].J
+        rowscale = np.maximum(np.abs(B).max(axis=1).toarray().ravel(), 1e-300)
+        diff = np.abs(A - B).max(axis=1).toarray().ravel()
+        assert np.all(diff <= 1e-12 * rowscale), (l, (diff / rowscale).max())
+        if l == p.nlevels - 1:
+            assert np.array_equal(A.indptr, B.indptr) and np.array_equal(A.indices, B.indices)
+        if l > 0:
+            for w in "PR":
+                X, Y = _csr(p, l, w), getattr(h.levels[l], w)
+                assert np.array_equal(X.indptr, Y.indptr)
+                assert np.array_equal(X.indices, Y.indices)
+                assert np.array_equal(X.data, Y.data)
+            ptr, dof, owned, kind = p.patches(l)
+            lv = h.levels[l]
+            assert np.array_equal(ptr, lv.ptr) and np.array_equal(dof, lv.dof)
+            assert np.array_equal(owned, lv.owned) and np.array_equal(kind, lv.kind)
+        assert np.array_equal(p.dirichlet(l), h.flags[l])
+
+
+def test_builder_residual_matches_checker_off_state():
+    """Residual at a state with random displacement, velocity and pressure."""
+    from paper_1709_05660_amd import Problem
+    s = config("c0_2d_16x4")
+    a = fourier_coefficients(2, s.seed)
+    p = Problem(s, a)
+    mesh = fem.Mesh(s, (16, 4, 1))
+    rng = np.random.default_rng(11)
+    y = p.y + 1e-2 * rng.standard_normal(p.n)
+    r_nat = p.residual(y)
+    r_orc, _ = fem.assemble(mesh, s, y, jacobian=False)
+    assert np.max(np.abs(r_nat - r_orc)) <= 1e-12 * np.max(np.abs(r_orc))
+
+
+def test_builder_rejects_bad_spec():
+    from paper_1709_05660_amd import FsiError, Problem
+    s = config("c0_2d_16x4").with_(nx=18)          # not divisible by 2 * patch
+    with pytest.raises(FsiError):
+        Problem(s, fourier_coefficients(2, 1))
+    s = config("c0_2d_16x4").with_(solid_lo=(1.1, 0.0, 0.0))   # solid not element-aligned
+    with pytest.raises(FsiError):
+        Problem(s, fourier_coefficients(2, 1))
+
+
+def _setup_status(levels, nlevels, **opts):
+    from paper_1709_05660_amd import _lib, mg_opts
+    o = mg_opts(**opts)
+    h = C.c_void_p()
+    st = _lib.lib().fsi_mg_setup(levels, nlevels, C.byref(o), None, C.byref(h))
+    return st, _lib.lib().fsi_last_error().decode()
+
+
+def test_setup_validation_errors_are_reported_on_the_host():
+    """Malformed inputs are rejected before any device call (FSI_E_INVALID)."""
+    from paper_1709_05660_amd import Problem
+    s = config("c0_2d_16x4")
+    p = Problem(s, fourier_coefficients(2, s.seed))
+    L = p.nlevels
+    # 1. columns not increasing in a row of J
+    J = p.levels[L - 1].J
+    ci = np.ctypeslib.as_array(J.colind, shape=(J.nnz,))
+    rp = np.ctypeslib.as_array(J.rowptr, shape=(J.nrows + 1,))
+    r = int(np.argmax(np.diff(rp) >= 3))
+    a = int(rp[r])
+    ci[a], ci[a + 1] = ci[a + 1], ci[a]
+    st, msg = _setup_status(p.levels, L)
+    ci[a], ci[a + 1] = ci[a + 1], ci[a]
+    assert st == -1 and "strictly increasing" in msg
+    # 2. a dof owned twice
+    P = p.levels[L - 1].patches
+    owned = np.ctypeslib.as_array(P.owned, shape=(int(np.ctypeslib.as_array(P.ptr, shape=(P.npatch + 1,))[-1]),))
+    idx = int(np.nonzero(owned == 0)[0][0])
+    owned[idx] = 1
+    st, msg = _setup_status(p.levels, L)
+    owned[idx] = 0
+    assert st == -1 and "owned" in msg
+    # 3. level dimension mismatch (P of the wrong shape)
+    saved = p.levels[L - 1].P.ncols
+    p.levels[L - 1].P.ncols = saved + 1
+    st, msg = _setup_status(p.levels, L)
+    p.levels[L - 1].P.ncols = saved
+    assert st == -1 and "dimension" in msg
+    # 4. bad options
+    st, msg = _setup_status(p.levels, L, omega=-1.0)
+    assert st == -1
+
+
+def test_server_rejects_oversized_request():
+    from paper_1709_05660_amd import Problem, _lib, mg_opts
+    s = config("c0_2d_16x4")
+    p = Problem(s, fourier_coefficients(2, s.seed))
+    lib = _lib.lib()
+    so = _lib.ServerOpts(1 << 20, 4, 0)                 # 1 MiB budget
+    h = C.c_void_p()
+    assert lib.fsi_server_create(C.byref(so), C.byref(h)) == 0
+    ko = _lib.KrylovOpts(30, 1e-10, 100, 0, None)
+    mo = mg_opts()
+    t = C.c_uint64()
+    st = lib.fsi_serve_submit(h, p.levels, p.nlevels, p.b.ctypes.data_as(C.c_void_p), C.byref(mo),
+                              C.byref(ko), C.byref(t))
+    assert st == -6
+    assert lib.fsi_serve_poll(h, 12345, None, None) == -7
+    stats = (C.c_int64 * 8)()
+    assert lib.fsi_server_stats(h, stats) == 0 and stats[0] == 0
+    assert lib.fsi_server_destroy(h) == 0
