@@ -121,6 +121,79 @@ def gpu_leg(args):
     return out
 
 
+def serve_leg(args):
+    """Served solves/s and latency percentiles for the stream of independent 2D
+    systems (mesh, solid stiffness and inflow drawn per request), mixed
+    precision, admission by device-memory budget, continuous batching."""
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_1709_05660_amd import Problem, Server
+    from synth import config, fourier_coefficients, serving_stream
+
+    reqs = serving_stream(args.serve_n)
+    base = config("c2_2d_128x32_mixed")
+
+    def make(r):
+        s = base.with_(nx=r.nx, ny=r.ny, levels=r.levels, mu_s=r.mu_s, u_peak=r.u_peak, seed=r.seed)
+        return Problem(s, fourier_coefficients(2, r.seed))
+
+    t = time.time()
+    with ThreadPoolExecutor(4) as ex:
+        probs = list(ex.map(make, reqs))
+    build_s = time.time() - t
+    budget, slots = args.serve_budget_gb << 30, args.serve_slots
+
+    def run(arrivals):
+        srv = Server(hbm_budget_bytes=budget, max_slots=slots)
+        done_at = {}
+        sub_at = {}
+        tickets = [None] * len(probs)
+        t0 = time.perf_counter()
+
+        def producer():
+            for i, p in enumerate(probs):
+                delay = t0 + arrivals[i] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                sub_at[i] = time.perf_counter()
+                tickets[i] = srv.submit(p, precision=args.mixed, rtol=1e-8)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        bad = 0
+        iters = []
+        while len(done_at) < len(probs):
+            for i, tk in enumerate(tickets):
+                if tk is None or i in done_at:
+                    continue
+                st, x, info = srv.poll(tk)
+                if st != 2:
+                    done_at[i] = time.perf_counter()
+                    bad += st != 0
+                    if info and "iters" in info:
+                        iters.append(info["iters"])
+            time.sleep(0.0002)
+        th.join()
+        stats = srv.stats()
+        srv.close()
+        lat = np.array([done_at[i] - sub_at[i] for i in range(len(probs))]) * 1e3
+        span = max(done_at.values()) - min(sub_at.values())
+        return {"solves_per_s": round(len(probs) / span, 2), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2), "failed": int(bad),
+                "mean_iters": round(float(np.mean(iters)), 2) if iters else None,
+                "max_coresident": stats["max_coresident"], "peak_bytes": stats["peak_bytes"]}
+
+    closed = run([0.0] * len(probs))
+    rate = 0.7 * closed["solves_per_s"]
+    stream_rate = len(reqs) / reqs[-1].arrival_s
+    arrivals = [r.arrival_s * stream_rate / rate for r in reqs]
+    opened = run(arrivals)
+    return {"systems": len(probs), "precision": args.mixed, "rtol": 1e-8,
+            "budget_bytes": budget, "max_slots": slots, "host_build_s": round(build_s, 1),
+            "closed_loop": closed, "poisson_0.7x_saturation": dict(opened, rate_per_s=round(rate, 2))}
+
+
 def cpu_leg(args):
     """The checker as it stands, on a bounded sample: the same step (block and
     coarse factorisation + FGMRES solve) of the same system."""
@@ -154,6 +227,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-n", type=int, default=256)
+    ap.add_argument("--serve-budget-gb", type=int, default=4)
+    ap.add_argument("--serve-slots", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
@@ -176,7 +253,9 @@ def main():
         "dof_per_s": round(value * g["n"], 1),
     }
     if "mixed" in g:
-        line["mixed"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in g["mixed"].items()}
+        line["mixed"] = {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in g["mixed"].items()}
+    if not args.no_serve:
+        line["served"] = serve_leg(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_leg(args)
     print(json.dumps(line), flush=True)

@@ -112,6 +112,7 @@ fsi_status fgmres(MG &mg, const double *b, double *x, int x0_nonzero, const fsi_
 RasView ras_view(const Level &L);
 void ensure_krylov(MG &mg, int m);
 void refactor(MG &mg, hipStream_t st);
+void release_setup_scratch(MG &mg);
 
 struct FgmresRun {
   enum Phase { kFirst, kIter, kCheck, kDone };

@@ -245,6 +245,7 @@ static void enqueue_coarse(MG &mg, Level &L, hipStream_t st) {
 // inversion runs on a second stream while all smoothing levels' blocks are
 // extracted and inverted in one launch on the main stream
 void refactor(MG &mg, hipStream_t st) {
+  if (!mg.dense_scratch) throw Error(FSI_E_INVALID, "setup scratch released; refactor unavailable");
   auto t0 = std::chrono::steady_clock::now();
   if (mg.mixed)
     for (int l = 1; l < mg.nlevels; ++l) launch_cast_d2f(mg.lv[l].J.val, mg.lv[l].J.val32, mg.lv[l].J.nnz, st);
@@ -507,6 +508,24 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
   }
   mg->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return mg;
+}
+
+// frees the setup scratch (dense blocks, coarse dense matrix); a later
+// refactor is then refused.  Used by the server once a system is set up.
+void release_setup_scratch(MG &mg) {
+  auto drop = [&](void *p) {
+    if (!p) return;
+    for (size_t i = 0; i < mg.owned.size(); ++i)
+      if (mg.owned[i] == p) {
+        (void)hipFree(p);
+        mg.owned.erase(mg.owned.begin() + i);
+        return;
+      }
+  };
+  drop(mg.blk_scratch);
+  drop(mg.dense_scratch);
+  mg.blk_scratch = nullptr;
+  mg.dense_scratch = nullptr;
 }
 
 void destroy_mg(MG *mg) {
@@ -906,6 +925,7 @@ fsi_status fsi_mg_export_patches(struct fsi_mg *h, int32_t level, int64_t *ptr, 
                 "D2H dof");
     if (owned) std::copy(L.h_owned.begin(), L.h_owned.end(), owned);
     if (blocks) {
+      if (!mg->blk_scratch) throw Error(FSI_E_INVALID, "setup scratch released");
       double *B = mg->blk_scratch + L.blk_base;
       launch_fill_f64(B, L.boff_total, 0.0, st);
       launch_extract(L.J.v64(), L.npatch, L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff, B, L.sum_m,

@@ -32,7 +32,7 @@ struct Request {
   std::vector<double> b;
   fsi_mg_opts mo{};
   fsi_krylov_opts ko{};
-  int64_t footprint = 0;
+  int64_t footprint = 0, transient = 0;
   Clock::time_point t_submit;
 };
 
@@ -70,7 +70,7 @@ struct Server {
 // device bytes of one system: operators, block inverses, coarse inverse,
 // vectors and the Krylov basis; plus the transient dense blocks of the setup
 static int64_t footprint(const fsi_level *lv, int nl, const fsi_mg_opts &mo,
-                         const fsi_krylov_opts &ko) {
+                         const fsi_krylov_opts &ko, int64_t *transient_out) {
   const bool mixed = mo.precision != FSI_PREC_FP64;
   const int wbytes = mo.precision == FSI_PREC_FP64 ? 8 : (mo.precision == FSI_PREC_MIXED_FP32 ? 4 : 2);
   int64_t res = 0, transient = 0;
@@ -94,10 +94,11 @@ static int64_t footprint(const fsi_level *lv, int nl, const fsi_mg_opts &mo,
       m2 += m * m;
     }
     res += om * wbytes + P.ptr[P.npatch] * 40;
-    transient = std::max<int64_t>(transient, m2 * 8);
+    transient += m2 * 8;                 // all levels' dense blocks share one setup scratch
   }
   const int64_t nf = lv[nl - 1].J.nrows;
   res += nf * 8 * (2 * (int64_t)ko.restart + 4) + 2 * nf * 8;
+  if (transient_out) *transient_out = transient;
   return res + transient;
 }
 
@@ -204,7 +205,10 @@ static void worker_loop(Server *S) {
         hip_check(hipMemcpyAsync(a->d_b, a->req->b.data(), sizeof(double) * n, hipMemcpyHostToDevice, a->st), "H2D");
         a->run.start(*a->mg, a->d_b, a->d_x, 0, a->req->ko, a->st);
         a->t_ready = Clock::now();
+        release_setup_scratch(*a->mg);      // the setup scratch is only needed during setup
         std::lock_guard<std::mutex> lk(S->mu);
+        S->used -= a->req->transient;
+        a->req->footprint -= a->req->transient;
         S->active.push_back(std::move(a));
         S->max_coresident = std::max<int64_t>(S->max_coresident, (int64_t)S->active.size());
         S->n_active = (int64_t)S->active.size();
@@ -288,10 +292,13 @@ fsi_status fsi_serve_submit(struct fsi_server *h, const fsi_level *levels, int32
     Server *S = reinterpret_cast<Server *>(h);
     if (!S || !levels || nlevels < 1 || !b_host || !mo || !ko || !ticket)
       throw Error(FSI_E_INVALID, "null argument");
-    const int64_t fp = footprint(levels, nlevels, *mo, *ko);
+    validate_levels(levels, nlevels, mo);
+    int64_t transient = 0;
+    const int64_t fp = footprint(levels, nlevels, *mo, *ko, &transient);
     if (fp > S->o.hbm_budget_bytes) throw Error(FSI_E_CAPACITY, "request larger than the memory budget");
     std::unique_ptr<Request> r = copy_request(levels, nlevels, b_host, *mo, *ko);
     r->footprint = fp;
+    r->transient = transient;
     r->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(S->mu);
     r->ticket = S->next_ticket++;

@@ -201,3 +201,62 @@ class MG:
             self.close()
         except Exception:
             pass
+
+
+class Server:
+    """Continuous-batching solve server (fsi_server_* of the C ABI).
+
+    Requests are copied at submit; the server keeps admitted hierarchies on
+    the device, admits in arrival order while the memory budget and a slot
+    allow, and advances all active systems one FGMRES step per tick.
+    """
+
+    def __init__(self, hbm_budget_bytes=4 << 30, max_slots=16, device=0):
+        so = L.ServerOpts(int(hbm_budget_bytes), int(max_slots), int(device))
+        h = C.c_void_p()
+        L.check(L.lib().fsi_server_create(C.byref(so), C.byref(h)), "server create")
+        self.h = h
+        self.sizes = {}
+
+    def submit(self, problem, b=None, precision="bf16", rtol=1e-8, restart=30, maxit=1000, **mg):
+        b = problem.b if b is None else np.ascontiguousarray(b, dtype=np.float64)
+        mo = mg_opts(precision=precision, **mg)
+        ko = L.KrylovOpts(restart, rtol, maxit, 0, None)
+        t = C.c_uint64()
+        L.check(L.lib().fsi_serve_submit(self.h, problem.levels, problem.nlevels,
+                                         b.ctypes.data_as(C.c_void_p), C.byref(mo), C.byref(ko),
+                                         C.byref(t)), "submit")
+        self.sizes[t.value] = problem.n
+        return t.value
+
+    def poll(self, ticket):
+        """(status, x, info); status 2 (pending) gives x = info = None."""
+        n = self.sizes.get(ticket, 0)
+        x = np.empty(max(n, 1))
+        info = L.SolveInfo()
+        st = L.lib().fsi_serve_poll(self.h, C.c_uint64(ticket), x.ctypes.data_as(C.c_void_p),
+                                    C.byref(info))
+        if st == L.FSI_PENDING:
+            return st, None, None
+        self.sizes.pop(ticket, None)
+        if st < 0:
+            return st, None, {"error": L.lib().fsi_last_error().decode()}
+        return st, x[:n], info.as_dict()
+
+    def stats(self):
+        out = (C.c_int64 * 8)()
+        L.check(L.lib().fsi_server_stats(self.h, out))
+        keys = ["submitted", "finished", "active", "queued", "bytes_in_use", "peak_bytes", "ticks",
+                "max_coresident"]
+        return dict(zip(keys, list(out)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.lib().fsi_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -229,3 +229,51 @@ def test_mixed_precision_c1(c1, prec):
          "err vs fp64", np.linalg.norm(x - x64) / np.linalg.norm(x64))
     assert info["converged"] == 1 and info["true_relres"] <= 1e-8
     mg.close()
+
+
+@pytest.fixture(scope="module")
+def c3():
+    from paper_1709_05660_amd import MG
+    _say("setup c3_3d_32x8x8 fp64")
+    p = product_problem("c3_3d_32x8x8")
+    mg = MG(p, precision="fp64")
+    yield p, mg
+    mg.close()
+
+
+def test_vcycle_parity_3d(c3):
+    p, mg = c3
+    oh = oracle_on_product("c3_3d_32x8x8")
+    s = oh.spec
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal(p.n)
+    z = host(mg.vcycle(dev(r)))
+    ref = osolver.vcycle(oh.levels, len(oh.levels) - 1, r, s.nu_pre, s.nu_post, s.omega)
+    _say("3d vcycle rel diff", np.linalg.norm(z - ref) / np.linalg.norm(ref))
+    assert np.linalg.norm(z - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_fgmres_parity_3d(c3):
+    """3D FP64: same iterates as the checker's algorithm on the same matrices."""
+    p, mg = c3
+    oh = oracle_on_product("c3_3d_32x8x8")
+    s = oh.spec
+    x_o, info_o = oprob.solve(oh)
+    xg, ig = mg.fgmres(dev(p.b), restart=s.restart, rtol=s.rtol)
+    xg = host(xg)
+    rel = np.linalg.norm(xg - x_o) / np.linalg.norm(x_o)
+    _say("3d iters gpu", ig["iters"], "checker", info_o.iters, "rel diff", rel, "true", ig["true_relres"])
+    assert ig["converged"] == 1 and ig["true_relres"] <= s.rtol
+    assert abs(ig["iters"] - info_o.iters) <= 1
+    assert rel <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_mixed_precision_3d(c3, prec):
+    from paper_1709_05660_amd import MG
+    p, _ = c3
+    mg = MG(p, precision=prec)
+    x, info = mg.fgmres(dev(p.b), restart=30, rtol=1e-8)
+    _say("3d", prec, "iters", info["iters"], "true", info["true_relres"])
+    assert info["converged"] == 1 and info["true_relres"] <= 1e-8
+    mg.close()

@@ -1,0 +1,135 @@
+"""GPU tests of the continuous-batching server (through the C ABI)."""
+
+import sys
+import time
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from synth import config, fourier_coefficients
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _problems():
+    from paper_1709_05660_amd import Problem
+    base = config("c1_2d_128x32")
+    specs = [base.with_(nx=32, ny=8, levels=2, mu_s=2.0e4, u_peak=0.1, seed=1001),
+             base.with_(nx=64, ny=16, levels=3, mu_s=3.0e5, u_peak=0.25, seed=1002),
+             base.with_(nx=32, ny=8, levels=2, mu_s=8.0e5, u_peak=0.05, seed=1003),
+             base.with_(nx=64, ny=16, levels=3, mu_s=1.0e4, u_peak=0.3, seed=1004)]
+    return [Problem(s, fourier_coefficients(2, s.seed)) for s in specs]
+
+
+def _wait(server, ticket, timeout=60.0):
+    t0 = time.time()
+    while True:
+        st, x, info = server.poll(ticket)
+        if st != 2:
+            return st, x, info
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"ticket {ticket} not finished")
+        time.sleep(0.001)
+
+
+def _true_relres(p, x):
+    rp, ci, v, sh = p.csr(p.nlevels - 1)
+    J = sp.csr_matrix((v, ci, rp), shape=sh)
+    return np.linalg.norm(p.b - J @ x) / np.linalg.norm(p.b)
+
+
+def test_alone_equals_mixed():
+    """Each system's result is the same solved alone and in a mix of
+    co-resident systems (per-system arithmetic does not depend on the batch)."""
+    from paper_1709_05660_amd import MG, Server
+    probs = _problems()
+    alone = []
+    srv = Server(hbm_budget_bytes=8 << 30, max_slots=1)
+    for p in probs:
+        _say("alone", p.n)
+        st, x, info = _wait(srv, srv.submit(p, precision="bf16", rtol=1e-8))
+        assert st == 0, info
+        alone.append(x)
+    srv.close()
+    srv = Server(hbm_budget_bytes=8 << 30, max_slots=8)
+    tickets = [srv.submit(p, precision="bf16", rtol=1e-8) for p in probs]
+    mixed = [_wait(srv, t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    _say("mixed stats", stats)
+    assert stats["max_coresident"] >= 2
+    for p, xa, (st, xm, info) in zip(probs, alone, mixed):
+        assert st == 0
+        assert np.array_equal(xa, xm) or np.linalg.norm(xa - xm) <= 1e-12 * np.linalg.norm(xa)
+        assert _true_relres(p, xm) <= 1e-8 * 1.001
+    # the same system through the synchronous path gives the same answer
+    import torch
+    mg = MG(probs[1], precision="bf16")
+    xd, _ = mg.fgmres(torch.as_tensor(probs[1].b).to("cuda"), rtol=1e-8)
+    xd = xd.cpu().numpy()
+    assert np.linalg.norm(xd - mixed[1][1]) <= 1e-12 * np.linalg.norm(xd)
+    mg.close()
+
+
+def test_admission_binds_and_is_fifo():
+    """A budget that fits one system at a time: systems run one by one, in
+    submission order."""
+    from paper_1709_05660_amd import Server
+    probs = [_problems()[1], _problems()[3], _problems()[1]]     # three 64x16 systems
+    probe = Server(hbm_budget_bytes=8 << 30, max_slots=1)
+    st, _, _ = _wait(probe, probe.submit(probs[0], precision="bf16", rtol=1e-8))
+    one = probe.stats()["peak_bytes"]                              # footprint of one system
+    probe.close()
+    # one system's full footprint (resident + setup scratch) plus 2 %: after a
+    # system's setup its scratch is released, but the next one's footprint no
+    # longer fits until the first finishes
+    budget = int(1.02 * one)
+    srv = Server(hbm_budget_bytes=budget, max_slots=8)
+    tickets = [srv.submit(p, precision="bf16", rtol=1e-8) for p in probs]
+    order = []
+    pending = set(tickets)
+    t0 = time.time()
+    while pending and time.time() - t0 < 60:
+        for t in list(pending):
+            st, x, info = srv.poll(t)
+            if st != 2:
+                assert st == 0, info
+                order.append(t)
+                pending.discard(t)
+        time.sleep(0.0005)
+    stats = srv.stats()
+    srv.close()
+    _say("budget stats", stats, "order", order)
+    assert not pending
+    assert stats["max_coresident"] == 1
+    assert order == tickets
+    assert stats["peak_bytes"] <= budget
+
+
+def test_failed_request_is_isolated():
+    """A request whose block is singular fails alone; the others finish."""
+    from paper_1709_05660_amd import Server
+    probs = _problems()[:3]
+    bad = probs[1]
+    J = bad.levels[bad.nlevels - 1].J
+    ptr, dof, owned, kind = bad.patches(bad.nlevels - 1)
+    row = int(dof[ptr[2] + 3])
+    vals = np.ctypeslib.as_array(J.val, shape=(J.nnz,))
+    rp = np.ctypeslib.as_array(J.rowptr, shape=(J.nrows + 1,))
+    saved = vals[rp[row]:rp[row + 1]].copy()
+    vals[rp[row]:rp[row + 1]] = 0.0
+    srv = Server(hbm_budget_bytes=8 << 30, max_slots=4)
+    try:
+        tickets = [srv.submit(p, precision="bf16", rtol=1e-8) for p in probs]
+    finally:
+        vals[rp[row]:rp[row + 1]] = saved       # the request holds its own copy
+    res = [_wait(srv, t) for t in tickets]
+    srv.close()
+    assert res[0][0] == 0 and res[2][0] == 0
+    assert res[1][0] == -3
