@@ -80,6 +80,10 @@ def gpu_leg(args):
         t = time.time()
         mg = MG(p, precision="fp64", use_graph=True)
         setup_upload_ms = (time.time() - t) * 1e3
+        tune_db = os.environ.get("FSI_TUNING_DB", os.path.join("/tmp", "fsi_tuning.db"))
+        t = time.time()
+        out["autotune_new_measurements"] = mg.autotune(tune_db)
+        out["autotune_s"] = round(time.time() - t, 3)
         _, warm = timed_steps(mg, args.warmup, spec.rtol)
         total_ms, infos = timed_steps(mg, args.steps, spec.rtol)
         out["ms_per_step"] = total_ms / args.steps
@@ -107,10 +111,19 @@ def gpu_leg(args):
                            "frac": round(achieved / 8000.0, 4), "traffic": None,
                            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": cnt,
                            "bytes_per_launch": int(bytes_per_launch)}
+        if args.traffic_probe:
+            # plain copy of known size (512 MiB read + 512 MiB written), to
+            # calibrate the FETCH_SIZE / WRITE_SIZE counters of a profiler run
+            src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
         mg.close()
         # ---- mixed precision form (FP32 V-cycle, BF16 block inverses, FP64 Krylov)
         if not args.no_mixed:
             mgm = MG(p, precision=args.mixed, use_graph=True)
+            mgm.autotune(tune_db)
             timed_steps(mgm, args.warmup, 1e-8)
             tm, im = timed_steps(mgm, args.steps, 1e-8)
             out["mixed"] = {"precision": args.mixed, "rtol": 1e-8, "ms_per_step": tm / args.steps,
@@ -228,6 +241,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true")
     ap.add_argument("--serve-n", type=int, default=256)
     ap.add_argument("--serve-budget-gb", type=int, default=4)
     ap.add_argument("--serve-slots", type=int, default=16)
@@ -251,6 +265,8 @@ def main():
         "vcycle_ms_fp64": round(g["vcycle_ms_fp64"], 4),
         "refactor_ms_fp64": round(g["refactor_ms_fp64"], 3), "solve_ms_fp64": round(g["solve_ms_fp64"], 3),
         "dof_per_s": round(value * g["n"], 1),
+        "autotune": {"new_measurements": g["autotune_new_measurements"], "seconds": g["autotune_s"]},
+        "setup_with_upload_ms": round(g["setup_with_upload_ms"], 1),
     }
     if "mixed" in g:
         line["mixed"] = {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in g["mixed"].items()}

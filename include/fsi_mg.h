@@ -157,6 +157,15 @@ fsi_status fsi_mg_jvalues(struct fsi_mg *mg, int32_t level, double **val_dev);
  * writes out[0] = total kernel milliseconds, out[1] = number of launches. */
 fsi_status fsi_mg_profile(struct fsi_mg *mg, int32_t enable, double out[2]);
 
+/* Autotuner: times the lanes-per-row of every level's SpMV (J, P, R, in the
+ * V-cycle's precision) and the panel width of the batched block inversion
+ * with events on the stream, keeps the fastest, and persists the choices in
+ * the text database db_path (may be NULL; entries found there are applied
+ * without measuring).  *measured (may be NULL) = number of new measurements.
+ * Captured graphs are rebuilt afterwards. */
+fsi_status fsi_mg_autotune(struct fsi_mg *mg, const char *db_path, void *hip_stream,
+                           int32_t *measured);
+
 /* Sizes of level `level`: n, nnz(J), npatch, sum m_k, sum m_k^2, sum owned_k * m_k. */
 fsi_status fsi_mg_level_info(struct fsi_mg *mg, int32_t level, int64_t out[6]);
 

@@ -80,7 +80,7 @@ class ServerOpts(C.Structure):
 EXPORTS = [
     "fsi_abi_version", "fsi_status_string", "fsi_last_error", "fsi_mg_setup", "fsi_mg_vcycle",
     "fsi_fgmres_solve", "fsi_mg_apply", "fsi_mg_export_patches", "fsi_mg_level_info",
-    "fsi_mg_refactor", "fsi_mg_jvalues", "fsi_mg_profile",
+    "fsi_mg_refactor", "fsi_mg_jvalues", "fsi_mg_profile", "fsi_mg_autotune",
     "fsi_mg_destroy", "fsi_server_create", "fsi_serve_submit", "fsi_serve_poll",
     "fsi_server_stats", "fsi_server_destroy",
     "fsi_problem_build", "fsi_problem_nlevels", "fsi_problem_levels", "fsi_problem_vectors",
@@ -114,6 +114,7 @@ def lib():
         "fsi_mg_level_info": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_int64)]),
         "fsi_mg_destroy": (C.c_int32, [P]),
         "fsi_mg_refactor": (C.c_int32, [P, P]),
+        "fsi_mg_autotune": (C.c_int32, [P, C.c_char_p, P, C.POINTER(C.c_int32)]),
         "fsi_mg_jvalues": (C.c_int32, [P, C.c_int32, C.POINTER(C.POINTER(C.c_double))]),
         "fsi_mg_profile": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_double)]),
         "fsi_server_create": (C.c_int32, [C.POINTER(ServerOpts), C.POINTER(P)]),

@@ -91,6 +91,7 @@ struct MG {
   int64_t *all_boff = nullptr;
   int *all_pm = nullptr;
   int npatch_all = 0, mmax_all = 1;
+  int gj_nb = 0;          // panel width of the batched Gauss-Jordan (0 = by size)
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // event timing of the finest-level Schwarz kernel

@@ -31,8 +31,9 @@ void launch_extract(const CsrView<double> &J, int npatch, const int *pm, const i
                     const int *row_patch, const int *row_local, hipStream_t st);
 // in-place inverse of every block, one workgroup per block; status[k] = 0 ok, else 1 + failing step
 int gj_panel_width(int mmax);
+// nb_req: panel width chosen by the autotuner (8 or 16), 0 = by size
 void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, int npatch, int mmax,
-                       int *status, hipStream_t st);
+                       int *status, hipStream_t st, int nb_req = 0);
 // in-place inverse of one large matrix (row-major n x n), many workgroups per step
 void gj_large(double *A, int n, int *status_dev, double *work, hipStream_t st);
 // W_k[c * o_k + r] = Binv_k[own_row_r][c] (column-major owned rows), optional FP32/16-bit copies

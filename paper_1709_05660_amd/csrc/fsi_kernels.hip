@@ -412,9 +412,10 @@ static void launch_gj_nb(double *blocks, const int64_t *boff, const int *pm, int
 }
 
 void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, int npatch, int mmax,
-                       int *status, hipStream_t st) {
+                       int *status, hipStream_t st, int nb_req) {
   if (npatch == 0) return;
-  const int nb = gj_panel_width(mmax);
+  int nb = gj_panel_width(mmax);
+  if (nb_req == 8 || (nb_req == 16 && (int64_t)mmax * 17 * 8 <= 150 * 1024)) nb = nb_req;
   if (nb == 16)
     launch_gj_nb<16>(blocks, boff, pm, npatch, mmax, status, st);
   else

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -260,7 +261,8 @@ void refactor(MG &mg, hipStream_t st) {
       launch_extract(L.J.v64(), L.npatch, L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff,
                      mg.blk_scratch + L.blk_base, L.sum_m, L.d_row_patch, L.d_row_local, st);
     }
-    launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.npatch_all, mg.mmax_all, mg.status, st);
+    launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.npatch_all, mg.mmax_all, mg.status, st,
+                      mg.gj_nb);
     hip_check(hipGetLastError(), "gj launch");
     for (int l = 1; l < mg.nlevels; ++l) pack_level(mg, mg.lv[l], st);
   }
@@ -734,6 +736,123 @@ fsi_status fgmres(MG &mg, const double *b, double *x, int x0_nonzero, const fsi_
   return run.converged ? FSI_OK : FSI_NOT_CONVERGED;
 }
 
+// ------------------------------------------------------------------ autotuner
+// Lanes per row of every SpMV (J, P, R per level) and the panel width of the
+// batched Gauss-Jordan, timed with events on the stream; results persist in a
+// text database keyed by operator shape and precision.
+static float time_events(hipStream_t st, const std::function<void()> &fn, int reps) {
+  hipEvent_t a, b;
+  hip_check(hipEventCreate(&a), "event");
+  hip_check(hipEventCreate(&b), "event");
+  fn();
+  hip_check(hipEventRecord(a, st), "record");
+  for (int i = 0; i < reps; ++i) fn();
+  hip_check(hipEventRecord(b, st), "record");
+  hip_check(hipEventSynchronize(b), "event sync");
+  float ms = 0.f;
+  hip_check(hipEventElapsedTime(&ms, a, b), "elapsed");
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
+}
+
+int autotune(MG &mg, const char *db_path, hipStream_t st) {
+  std::map<std::string, int> db;
+  if (db_path) {
+    if (FILE *f = fopen(db_path, "r")) {
+      char key[256];
+      int v;
+      while (fscanf(f, "%255s %d", key, &v) == 2) db[key] = v;
+      fclose(f);
+    }
+  }
+  int measured = 0;
+  const char *prec = mg.mixed ? "f32" : "f64";
+  auto tune_csr = [&](DevCsr &A, const char *what, double *x64, double *y64, float *x32, float *y32,
+                      bool use32) {
+    char key[256];
+    snprintf(key, sizeof key, "spmv:%s:%s:%d:%d:%d", what, use32 ? "f32" : "f64", A.n, A.m, A.nnz);
+    auto it = db.find(key);
+    if (it != db.end()) {
+      A.lpr = it->second;
+      return;
+    }
+    int best = A.lpr;
+    float best_ms = 1e30f;
+    for (int lpr : {2, 4, 8, 16, 32, 64}) {
+      float ms;
+      if (use32)
+        ms = time_events(st, [&] { launch_spmv(A.v32(), x32, (const float *)nullptr, y32, kSpmvSet, lpr, st); }, 10);
+      else
+        ms = time_events(st, [&] { launch_spmv(A.v64(), x64, (const double *)nullptr, y64, kSpmvSet, lpr, st); }, 10);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = lpr;
+      }
+    }
+    A.lpr = best;
+    db[key] = best;
+    ++measured;
+  };
+  for (int l = 0; l < mg.nlevels; ++l) {
+    Level &L = mg.lv[l];
+    const bool use32 = mg.mixed && l > 0;
+    launch_fill_f64(L.r, L.n, 1.0, st);
+    if (use32) launch_fill_f32(L.r32, L.n, 1.0f, st);
+    tune_csr(L.J, "J", L.r, L.s, L.r32, L.s32, use32);
+    if (l > 0) {
+      Level &C = mg.lv[l - 1];
+      launch_fill_f64(C.r, C.n, 1.0, st);
+      if (use32) launch_fill_f32(C.r32, C.n, 1.0f, st);
+      tune_csr(L.P, "P", C.r, L.s, C.r32, L.s32, use32);
+      tune_csr(L.R, "R", L.r, C.s, L.r32, C.s32, use32);
+    }
+  }
+  if (mg.npatch_all && mg.blk_scratch) {
+    char key[256];
+    snprintf(key, sizeof key, "gj:%d:%d:%lld", mg.mmax_all, mg.npatch_all, (long long)mg.blk_total);
+    auto it = db.find(key);
+    if (it != db.end()) {
+      mg.gj_nb = it->second;
+    } else {
+      int best = 16;
+      float best_ms = 1e30f;
+      for (int nb : {8, 16}) {
+        if (nb == 16 && (int64_t)mg.mmax_all * 17 * 8 > 150 * 1024) continue;
+        const float ms = time_events(st, [&] {
+          for (int l = 1; l < mg.nlevels; ++l) {
+            Level &L = mg.lv[l];
+            launch_fill_f64(mg.blk_scratch + L.blk_base, L.boff_total, 0.0, st);
+            launch_extract(L.J.v64(), L.npatch, L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff,
+                           mg.blk_scratch + L.blk_base, L.sum_m, L.d_row_patch, L.d_row_local, st);
+          }
+          launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.npatch_all, mg.mmax_all,
+                            mg.status, st, nb);
+        }, 1);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = nb;
+        }
+      }
+      mg.gj_nb = best;
+      db[key] = best;
+      ++measured;
+      refactor(mg, st);   // the blocks were overwritten by the timing runs
+    }
+  }
+  hip_check(hipGetLastError(), "autotune");
+  for (auto &kv : mg.graphs) (void)hipGraphExecDestroy(kv.second);
+  mg.graphs.clear();
+  if (db_path && measured) {
+    if (FILE *f = fopen(db_path, "w")) {
+      for (auto &kv : db) fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+      fclose(f);
+    }
+  }
+  (void)prec;
+  return measured;
+}
+
 }  // namespace fsi
 
 // ==================================================================== C ABI
@@ -858,6 +977,18 @@ fsi_status fsi_mg_refactor(struct fsi_mg *h, void *hip_stream) {
     if (!mg) throw Error(FSI_E_INVALID, "null handle");
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
     refactor(*mg, st);
+    return FSI_OK;
+  })
+}
+
+fsi_status fsi_mg_autotune(struct fsi_mg *h, const char *db_path, void *hip_stream,
+                           int32_t *measured) {
+  FSI_GUARD({
+    MG *mg = reinterpret_cast<MG *>(h);
+    if (!mg) throw Error(FSI_E_INVALID, "null handle");
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
+    const int m = autotune(*mg, db_path, st);
+    if (measured) *measured = m;
     return FSI_OK;
   })
 }

@@ -21,6 +21,7 @@
 namespace fsi {
 
 using Clock = std::chrono::steady_clock;
+constexpr int kSetupThreads = 3;   // concurrent setups (each on its system's stream)
 
 struct Request {
   uint64_t ticket = 0;
@@ -60,11 +61,12 @@ struct Server {
   std::map<uint64_t, Done> done;
   std::set<uint64_t> live;
   std::vector<std::unique_ptr<Active>> active;
-  std::thread worker;
+  int setting_up = 0;
+  std::vector<std::thread> setup_threads;
+  std::thread tick_thread;
   std::atomic<bool> stop{false};
   uint64_t next_ticket = 1;
   int64_t used = 0, peak = 0, submitted = 0, finished = 0, ticks = 0, max_coresident = 0;
-  std::atomic<int64_t> n_active{0};
 };
 
 // device bytes of one system: operators, block inverses, coarse inverse,
@@ -179,57 +181,77 @@ static void finish(Server &S, Active &a, fsi_status st, const std::string &msg, 
   S.cv.notify_all();
 }
 
-static void worker_loop(Server *S) {
+// Admission + setup threads: requests leave the queue in arrival order while
+// a slot is free and the footprint fits the budget; each system is set up on
+// its own stream, so setups overlap with each other and with the other
+// systems' iterations run by the tick thread.
+static void setup_loop(Server *S) {
+  (void)hipSetDevice(S->o.device);
+  while (true) {
+    std::unique_ptr<Request> req;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait_for(lk, std::chrono::milliseconds(5), [&] {
+        return S->stop.load() ||
+               (!S->queue.empty() && (int)S->active.size() + S->setting_up < S->o.max_slots &&
+                S->used + S->queue.front()->footprint <= S->o.hbm_budget_bytes);
+      });
+      if (S->stop.load()) return;
+      if (S->queue.empty() || (int)S->active.size() + S->setting_up >= S->o.max_slots ||
+          S->used + S->queue.front()->footprint > S->o.hbm_budget_bytes)
+        continue;
+      req = std::move(S->queue.front());
+      S->queue.pop_front();
+      S->used += req->footprint;
+      S->peak = std::max(S->peak, S->used);
+      S->setting_up++;
+    }
+    std::unique_ptr<Active> a(new Active());
+    a->req = std::move(req);
+    const int n = (int)a->req->b.size();
+    try {
+      hip_check(hipStreamCreate(&a->st), "stream");
+      a->mg = mg_setup(a->req->levels.data(), (int)a->req->levels.size(), &a->req->mo, a->st, a->st);
+      hip_check(hipMalloc(&a->d_b, sizeof(double) * n), "hipMalloc");
+      hip_check(hipMalloc(&a->d_x, sizeof(double) * n), "hipMalloc");
+      hip_check(hipMemcpyAsync(a->d_b, a->req->b.data(), sizeof(double) * n, hipMemcpyHostToDevice, a->st), "H2D");
+      a->run.start(*a->mg, a->d_b, a->d_x, 0, a->req->ko, a->st);
+      a->t_ready = Clock::now();
+      release_setup_scratch(*a->mg);      // the setup scratch is only needed during setup
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->used -= a->req->transient;
+      a->req->footprint -= a->req->transient;
+      S->active.push_back(std::move(a));
+      S->setting_up--;
+      S->max_coresident = std::max<int64_t>(S->max_coresident, (int64_t)S->active.size());
+      S->cv.notify_all();
+    } catch (const Error &e) {
+      a->t_ready = Clock::now();
+      finish(*S, *a, e.code, e.msg, false);
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->setting_up--;
+      S->cv.notify_all();
+    }
+  }
+}
+
+// Tick thread: every active system advances by one unit of FGMRES work per
+// tick; the other systems' work stays in flight on their streams while one
+// stream is being synchronised.
+static void tick_loop(Server *S) {
   (void)hipSetDevice(S->o.device);
   while (!S->stop.load()) {
-    // admission (FIFO): slot free and footprint within the budget
-    while (true) {
-      std::unique_ptr<Request> req;
-      {
-        std::lock_guard<std::mutex> lk(S->mu);
-        if (S->queue.empty() || (int)S->active.size() >= S->o.max_slots) break;
-        if (S->used + S->queue.front()->footprint > S->o.hbm_budget_bytes) break;
-        req = std::move(S->queue.front());
-        S->queue.pop_front();
-        S->used += req->footprint;
-        S->peak = std::max(S->peak, S->used);
-      }
-      std::unique_ptr<Active> a(new Active());
-      a->req = std::move(req);
-      const int n = (int)a->req->b.size();
-      try {
-        hip_check(hipStreamCreate(&a->st), "stream");
-        a->mg = mg_setup(a->req->levels.data(), (int)a->req->levels.size(), &a->req->mo, a->st, a->st);
-        hip_check(hipMalloc(&a->d_b, sizeof(double) * n), "hipMalloc");
-        hip_check(hipMalloc(&a->d_x, sizeof(double) * n), "hipMalloc");
-        hip_check(hipMemcpyAsync(a->d_b, a->req->b.data(), sizeof(double) * n, hipMemcpyHostToDevice, a->st), "H2D");
-        a->run.start(*a->mg, a->d_b, a->d_x, 0, a->req->ko, a->st);
-        a->t_ready = Clock::now();
-        release_setup_scratch(*a->mg);      // the setup scratch is only needed during setup
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->used -= a->req->transient;
-        a->req->footprint -= a->req->transient;
-        S->active.push_back(std::move(a));
-        S->max_coresident = std::max<int64_t>(S->max_coresident, (int64_t)S->active.size());
-        S->n_active = (int64_t)S->active.size();
-      } catch (const Error &e) {
-        a->t_ready = Clock::now();
-        finish(*S, *a, e.code, e.msg, false);
-      }
-    }
     std::vector<Active *> cur;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       if (S->active.empty()) {
         S->cv.wait_for(lk, std::chrono::milliseconds(2),
-                       [&] { return S->stop.load() || !S->queue.empty(); });
+                       [&] { return S->stop.load() || !S->active.empty(); });
         continue;
       }
       for (auto &p : S->active) cur.push_back(p.get());
       S->ticks++;
     }
-    // one tick: every active system advances by one unit of work; the others'
-    // work stays in flight on their streams while one is being synchronised
     std::vector<Active *> retired;
     for (Active *a : cur) {
       try {
@@ -253,10 +275,12 @@ static void worker_loop(Server *S) {
             S->active.erase(S->active.begin() + i);
             break;
           }
-      S->n_active = (int64_t)S->active.size();
+      S->cv.notify_all();
     }
   }
-  // drain on shutdown
+}
+
+static void drain(Server *S) {
   for (auto &a : S->active) {
     (void)hipStreamSynchronize(a->st);
     finish(*S, *a, FSI_E_DEVICE, "server destroyed", false);
@@ -276,7 +300,8 @@ fsi_status fsi_server_create(const fsi_server_opts *o, struct fsi_server **out) 
       throw Error(FSI_E_INVALID, "invalid server options");
     Server *S = new Server();
     S->o = *o;
-    S->worker = std::thread(worker_loop, S);
+    for (int i = 0; i < kSetupThreads; ++i) S->setup_threads.emplace_back(setup_loop, S);
+    S->tick_thread = std::thread(tick_loop, S);
     *out = reinterpret_cast<fsi_server *>(S);
     return FSI_OK;
   } catch (const Error &e) {
@@ -348,9 +373,15 @@ fsi_status fsi_server_stats(struct fsi_server *h, int64_t out[8]) {
 fsi_status fsi_server_destroy(struct fsi_server *h) {
   Server *S = reinterpret_cast<Server *>(h);
   if (!S) return FSI_OK;
-  S->stop = true;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
   S->cv.notify_all();
-  if (S->worker.joinable()) S->worker.join();
+  for (auto &t : S->setup_threads)
+    if (t.joinable()) t.join();
+  if (S->tick_thread.joinable()) S->tick_thread.join();
+  drain(S);
   delete S;
   return FSI_OK;
 }

@@ -172,6 +172,14 @@ class MG:
         """Re-run extraction, block inversion and coarse inversion on the device."""
         L.check(L.lib().fsi_mg_refactor(self.h, _stream()), "refactor")
 
+    def autotune(self, db_path=None):
+        """Pick SpMV lanes-per-row and the block-inversion panel width by timing;
+        returns the number of new measurements (0 when db_path had them all)."""
+        m = C.c_int32()
+        L.check(L.lib().fsi_mg_autotune(self.h, db_path.encode() if db_path else None, _stream(),
+                                        C.byref(m)), "autotune")
+        return m.value
+
     def profile_start(self):
         L.check(L.lib().fsi_mg_profile(self.h, 1, None))
 

@@ -277,3 +277,24 @@ def test_mixed_precision_3d(c3, prec):
     _say("3d", prec, "iters", info["iters"], "true", info["true_relres"])
     assert info["converged"] == 1 and info["true_relres"] <= 1e-8
     mg.close()
+
+
+def test_autotune_persists_and_keeps_results(c1, tmp_path):
+    """The autotuner picks kernel shapes by timing, persists them, and the
+    solve is unchanged up to rounding (only reduction orders change)."""
+    from paper_1709_05660_amd import MG
+    p, mg64 = c1
+    db = str(tmp_path / "tune.db")
+    mg = MG(p, precision="fp64", use_graph=True)
+    assert mg.autotune(db) > 0
+    x, info = mg.fgmres(dev(p.b), restart=30, rtol=1e-10)
+    x0, info0 = mg64.fgmres(dev(p.b), restart=30, rtol=1e-10)
+    x, x0 = host(x), host(x0)
+    assert info["converged"] == 1 and abs(info["iters"] - info0["iters"]) <= 1
+    assert np.linalg.norm(x - x0) <= 1e-10 * np.linalg.norm(x0)
+    mg2 = MG(p, precision="fp64")
+    assert mg2.autotune(db) == 0            # every choice found in the database
+    lines = open(db).read().split("\n")
+    _say("tuning db", [l for l in lines if l])
+    mg.close()
+    mg2.close()
