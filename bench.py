@@ -105,7 +105,7 @@ def gpu_leg(args):
         kms, cnt = mg.profile_stop()
         avg_ms = kms / max(cnt, 1)
         bytes_per_launch = ras_bytes(fine, 8, 8)
-        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if cnt else 0.0
         out["roofline"] = {"bound": "hbm", "kernel": "k_ras<double> (finest level)",
                            "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                            "frac": round(achieved / 8000.0, 4), "traffic": None,

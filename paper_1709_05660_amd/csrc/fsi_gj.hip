@@ -1,0 +1,560 @@
+// gfx950 Gauss-Jordan inversions of the setup: the explicit inverses of the
+// Schwarz blocks B_k of every smoothing level (one workgroup per block, all
+// levels in one launch) and of the coarsest operator (one workgroup factors
+// each pivot panel, a grid of workgroups applies it to the other columns).
+//
+// Both are the same blocked right-looking Gauss-Jordan elimination with
+// partial pivoting (largest magnitude among the rows not yet used as pivots,
+// lowest row on ties).  A panel of NB pivot columns is factored with its
+// rows held in registers: thread t holds rows t, t + NT, ...  A pivot step
+// costs one workgroup barrier: each wave publishes its best candidate row in
+// LDS (double-buffered by step parity) and every thread then takes the best
+// of the waves' candidates and eliminates it from its own rows.
+//
+// Rows are never exchanged.  The pivot row of step s is recorded as
+// perm[s], the step at which row i served as pivot as used[i], and the
+// stored result S is the inverse up to these two permutations,
+//     inv(A)[k][c] = S[perm[k]][used[c]],
+// which the consumers (the owned-row packing, the coarse transpose) apply
+// as they read S.  A factored panel PC (rows of S in the panel's columns)
+// acts on every other column j by
+//     A[i][j] <- [i is not a pivot row of the panel] A[i][j]
+//                + sum_t PC[i][t] X[t][j],
+// where X[t][j] is the panel's t-th pivot row before the update.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "fsi_kernels.h"
+
+namespace fsi {
+
+static inline int cdivg(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+constexpr int kNoRow = 0x7fffffff;
+
+struct Argmax {
+  double v;
+  int i;
+};
+__device__ inline bool beats(const Argmax &b, const Argmax &a) {
+  return (b.v > a.v) | ((b.v == a.v) & (b.i < a.i));   // branch-free
+}
+// DPP move of a double within rows of 16 lanes (full EXEC)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// DPP controls: quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_ror 4, row_ror 8
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppRor4 = 0x124, kDppRor8 = 0x128;
+
+// wave-wide argmax (largest value, then lowest index) in every lane: the
+// maximum by a DPP reduction inside each row of 16 lanes and a combination
+// of the four rows, then the lowest index among the lanes holding it.
+// Requires all 64 lanes active.
+__device__ __forceinline__ Argmax wave_argmax(Argmax a) {
+  double v = a.v;
+  v = fmax(v, dpp_f64<kDppXor1>(v));
+  v = fmax(v, dpp_f64<kDppXor2>(v));
+  v = fmax(v, dpp_f64<kDppRor4>(v));
+  v = fmax(v, dpp_f64<kDppRor8>(v));
+  const double wmax = fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
+                           fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+  int i = a.v == wmax ? a.i : kNoRow;
+  i = min(i, dpp_i32<kDppXor1>(i));
+  i = min(i, dpp_i32<kDppXor2>(i));
+  i = min(i, dpp_i32<kDppRor4>(i));
+  i = min(i, dpp_i32<kDppRor8>(i));
+  const int wi = min(min(__builtin_amdgcn_readlane(i, 0), __builtin_amdgcn_readlane(i, 16)),
+                     min(__builtin_amdgcn_readlane(i, 32), __builtin_amdgcn_readlane(i, 48)));
+  return Argmax{wmax, wi};
+}
+
+// LDS of the pivot steps: one candidate row per wave and step parity, and
+// the panel's pivot rows in step order.
+template <int NB, int NW>
+struct PivotLds {
+  double row[2][NW][NB];
+  double val[2][NW];
+  int idx[2][NW];
+  int piv[NB];
+};
+
+// One pivot step on column t of the panel held in v (see reg_panel).
+// Returns 0 or 1 + the failing step, uniformly.
+template <int NB, int R, int NT>
+__device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int m, int p0, int t,
+                                          int col, PivotLds<NB, NT / 64> &sh) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int buf = t & 1;
+  Argmax best{-1.0, kNoRow};
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = tid + q * NT;
+    if (i < m && stp[q] < 0) {
+      const double a = fabs(v[q][col]);
+      const Argmax c{a != a ? INFINITY : a, i};
+      if (beats(c, best)) best = c;
+    }
+  }
+  best = wave_argmax(best);
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+    if (tid + q * NT == best.i) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) sh.row[buf][wave][c] = v[q][c];
+    }
+  if (lane == 0) {
+    sh.val[buf][wave] = best.v;
+    sh.idx[buf][wave] = best.i;
+  }
+  __syncthreads();
+  Argmax g{sh.val[buf][0], sh.idx[buf][0]};
+  int gw = 0;
+#pragma unroll
+  for (int k = 1; k < NW; ++k) {
+    const Argmax c{sh.val[buf][k], sh.idx[buf][k]};
+    if (beats(c, g)) {
+      g = c;
+      gw = k;
+    }
+  }
+  if (!(g.v > 0.0) || isinf(g.v)) return p0 + t + 1;
+  if (tid == 0) sh.piv[t] = g.i;
+  const double *prow = sh.row[buf][gw];
+  const double d = 1.0 / prow[col];
+  double pr[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) pr[c] = prow[c] * d;
+  // every row is eliminated, then the one lane holding the pivot row
+  // overwrites it (a branch of one lane instead of a select on every row)
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const double f = v[q][col];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) v[q][c] = c == col ? -f * d : v[q][c] - f * pr[c];
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+    if (tid + q * NT == g.i) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) v[q][c] = c == col ? d : pr[c];
+      stp[q] = p0 + t;
+    }
+  return 0;
+}
+
+// Factors the panel of columns [p0, p0 + w) of an m-row matrix whose rows
+// tid + q * NT sit in v[q][0..NB) (columns beyond w are zero; rows beyond m
+// are never candidates); stp[q] is the step at which that row became a
+// pivot (< 0: not yet; rows beyond m carry kNoRow).  UNR: the NB steps are
+// unrolled and step t works on the static column t.  Otherwise the step loop
+// is rolled: the current pivot column is always v[q][0] and each step
+// rotates the row left by one column (every register index stays static),
+// the columns being back in order after NB rotations.  Called by all NT
+// threads.  Returns 0, or 1 + the step whose pivot is zero or not finite
+// (the same value in every thread).
+template <int NB, int R, int NT, bool UNR>
+__device__ __forceinline__ int reg_panel(double (&v)[R][NB], int (&stp)[R], int m, int p0, int w,
+                                         PivotLds<NB, NT / 64> &sh) {
+  if constexpr (UNR) {
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+      if (t < w) {
+        const int f = pivot_step<NB, R, NT>(v, stp, m, p0, t, t, sh);
+        if (f) return f;
+      }
+  } else {
+    for (int t = 0; t < NB; ++t) {
+      if (t < w) {
+        const int f = pivot_step<NB, R, NT>(v, stp, m, p0, t, 0, sh);
+        if (f) return f;
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const double h = v[q][0];
+#pragma unroll
+        for (int c = 0; c + 1 < NB; ++c) v[q][c] = v[q][c + 1];
+        v[q][NB - 1] = h;
+      }
+    }
+  }
+  return 0;
+}
+
+// ------------------------------------------------------------------ batched blocks
+typedef double dx4 __attribute__((ext_vector_type(4)));
+constexpr int kPrefetch = 4;   // row tiles in flight per wave in the updates
+
+// One workgroup of NT threads per block at a time (m <= NT R), looping
+// over blocks k = blockIdx.x, + gridDim.x, ...  Per panel: factor in
+// registers, store the panel to the block and to LDS (stride NB + 1), then
+// apply it to the other columns on the matrix cores: each wave owns whole
+// 16-column tiles, reads its tiles' X (the pivot rows' old values) first and
+// then updates every 16-row tile, pivot rows included, with
+// v_mfma_f64_16x16x4f64 (A: PC rows, B: X; operand layouts: A[i][k] in lane
+// i + 16 k, B[k][j] in lane j + 16 k, D[i][j] in lane j + 16 (i % 4),
+// register i / 4), the tiles' loads issued kPrefetch tiles ahead.  The block array is padded by NB doubles at its end:
+// a panel slice is loaded whole from its row base.
+template <int NB, int R, int NT, bool UNR>
+__global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
+                                                    const int64_t *__restrict__ boff,
+                                                    const int *__restrict__ pm,
+                                                    const int64_t *__restrict__ poff,
+                                                    int *__restrict__ perm_all,
+                                                    int *__restrict__ used_all,
+                                                    int *__restrict__ status, int npatch) {
+  constexpr int PS = NB + 1, KC = NB / 4;
+  extern __shared__ double PC[];
+  __shared__ PivotLds<NB, NT / 64> sh;
+  __shared__ int s_used[R * NT];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int jl = lane & 15, kq = lane >> 4;
+  for (int k = blockIdx.x; k < npatch; k += gridDim.x) {
+    const int m = pm[k];
+    double *A = blocks + boff[k];
+    int *perm = perm_all + poff[k];
+    for (int i = tid; i < m; i += NT) s_used[i] = -1;
+    __syncthreads();
+    int fail = 0;
+    for (int p0 = 0; p0 < m; p0 += NB) {
+      const int w = min(NB, m - p0);
+      double v[R][NB];
+      int stp[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int i = tid + q * NT;
+        stp[q] = i < m ? s_used[i] : kNoRow;
+        const double *row = A + min(i, m - 1) * m + p0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) v[q][c] = row[c];
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          if (c >= w) v[q][c] = 0.0;
+      fail = reg_panel<NB, R, NT, UNR>(v, stp, m, p0, w, sh);
+      if (fail) break;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int i = tid + q * NT;
+        if (i < m) {
+#pragma unroll
+          for (int c = 0; c < NB; ++c) {
+            if (c < w) A[i * m + p0 + c] = v[q][c];
+            PC[i * PS + c] = v[q][c];
+          }
+          if (stp[q] >= p0) s_used[i] = stp[q];
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+      if (tid < w) perm[p0 + tid] = sh.piv[tid];
+      const int mp = m - w;
+      const int nct = (mp + 15) >> 4, nrt = (m + 15) >> 4;
+      for (int ct = wave; ct < nct; ct += NT / 64) {
+        const int q = ct * 16 + jl;
+        const bool colok = q < mp;
+        const int j = colok ? (q < p0 ? q : q + w) : 0;
+        double bx[KC];
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+          const int t = kk * 4 + kq;
+          bx[kk] = (colok && t < w) ? A[sh.piv[t] * m + j] : 0.0;
+        }
+        // clamped addresses: loads never wait on anything; the pivot rows
+        // and the rows past m are zeroed where the tile is used
+        auto load_tile = [&](int rt) {
+          dx4 c;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) c[r] = A[min(rt * 16 + r * 4 + kq, m - 1) * m + j];
+          return c;
+        };
+        dx4 ring[kPrefetch];
+#pragma unroll
+        for (int u = 0; u < kPrefetch; ++u) ring[u] = load_tile(u);
+        for (int rt0 = 0; rt0 < nrt; rt0 += kPrefetch) {
+#pragma unroll
+          for (int u = 0; u < kPrefetch; ++u) {
+            const int rt = rt0 + u;
+            if (rt < nrt) {
+              dx4 c = ring[u];
+              if (rt + kPrefetch < nrt) ring[u] = load_tile(rt + kPrefetch);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int i = rt * 16 + r * 4 + kq;
+                const int si = i < m ? s_used[i] : p0;
+                if (!(colok && i < m && (si < p0 || si >= p0 + w))) c[r] = 0.0;
+              }
+              const int ia = rt * 16 + jl;
+#pragma unroll
+              for (int kk = 0; kk < KC; ++kk) {
+                const double a = ia < m ? PC[ia * PS + kk * 4 + kq] : 0.0;
+                c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bx[kk], c, 0, 0, 0);
+              }
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int i = rt * 16 + r * 4 + kq;
+                if (colok && i < m) A[i * m + j] = c[r];
+              }
+            }
+          }
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
+    // a failed block publishes the identity permutation, so that the packing
+    // (which runs before the host reads the status) stays inside the block
+    __syncthreads();
+    for (int i = tid; i < m; i += NT) {
+      used_all[poff[k] + i] = fail ? i : s_used[i];
+      if (fail) perm[i] = i;
+    }
+    if (tid == 0) status[k] = fail;
+    __syncthreads();
+  }
+}
+
+static size_t gj_batched_lds(int mmax, int nb) { return (size_t)mmax * (nb + 1) * sizeof(double); }
+
+// largest panel width whose LDS panel fits next to the static LDS
+int gj_panel_width(int mmax) {
+  return gj_batched_lds(mmax, 32) <= 140 * 1024 ? 32 : 16;
+}
+
+template <int NB, int R, int NT, bool UNR>
+static void launch_gj_nbr(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
+                          int *perm, int *used, int npatch, int mmax, int *status, hipStream_t st) {
+  const size_t shm = gj_batched_lds(mmax, NB);
+  (void)hipFuncSetAttribute((const void *)k_gj_batched<NB, R, NT, UNR>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  // as many workgroups as the fewest rounds over the compute units need:
+  // the rest of the device stays free for the coarsest inversion
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  ncu = std::max(ncu, 1);
+  const int rounds = (npatch + ncu - 1) / ncu;
+  const int grid = (npatch + rounds - 1) / rounds;
+  k_gj_batched<NB, R, NT, UNR><<<grid, NT, shm, st>>>(blocks, boff, pm, poff, perm, used, status,
+                                                       npatch);
+}
+
+void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
+                       int *perm, int *used, int npatch, int mmax, int *status, hipStream_t st,
+                       int nb_req) {
+  if (npatch == 0) return;
+  int nb = gj_panel_width(mmax);
+  if (nb_req == 16 || (nb_req == 32 && nb == 32)) nb = nb_req;
+  // NB 16: 256 threads (one wave per SIMD, the per-step work common to a
+  // wave shared by more rows); NB 32: 512 threads, one row each (no spills)
+  if (mmax <= 512) {
+    if (nb == 32)
+      launch_gj_nbr<32, 1, 512, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
+    else
+      launch_gj_nbr<16, 2, 256, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
+  } else {
+    launch_gj_nbr<16, 4, 256, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
+  }
+}
+
+// ------------------------------------------------------------------ coarsest operator
+// A: n x n row-major with leading dimension ld (a multiple of 16 doubles).
+__global__ void k_fill_i32(int *x, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+template <int NB, int R, int NT>
+__global__ __launch_bounds__(NT) void k_cgj_panel(double *__restrict__ A, int n, int64_t ld,
+                                                  int p0, int w, int *__restrict__ perm,
+                                                  int *__restrict__ used,
+                                                  int *__restrict__ status) {
+  __shared__ PivotLds<NB, NT / 64> sh;
+  if (status[0]) return;
+  const int tid = threadIdx.x;
+  double v[R][NB];
+  int stp[R];
+  // p0 + NB <= ld (ld is a multiple of 16 and NB divides 16): a row's panel
+  // slice is loaded whole from one base address; rows beyond n repeat row
+  // n - 1 and are never candidates
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = tid + q * NT;
+    stp[q] = i < n ? used[i] : kNoRow;
+    const double *row = A + (int64_t)min(i, n - 1) * ld + p0;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) v[q][c] = row[c];
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c >= w) v[q][c] = 0.0;
+  const int f = reg_panel<NB, R, NT, true>(v, stp, n, p0, w, sh);
+  if (f) {
+    if (tid == 0) status[0] = f;
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = tid + q * NT;
+    if (i < n) {
+      double *row = A + (int64_t)i * ld + p0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < w) row[c] = v[q][c];
+      if (stp[q] >= p0) used[i] = stp[q];
+    }
+  }
+  __syncthreads();
+  if (tid < w) perm[p0 + tid] = sh.piv[tid];
+}
+
+// One workgroup per tile of 16 of the columns outside the panel (taken in
+// order, skipping the panel).  Its four waves read the tile's X (pivot
+// rows' old values) into registers, meet at a barrier, then update the
+// tile's 16-row tiles round-robin on the matrix cores (same operand layouts
+// as the batched kernel); no other workgroup touches the tile.
+template <int NB>
+__global__ __launch_bounds__(256) void k_cgj_update(double *__restrict__ A, int n, int64_t ld,
+                                                    int p0, int w, const int *__restrict__ perm,
+                                                    const int *__restrict__ used,
+                                                    const int *__restrict__ status) {
+  constexpr int KC = (NB + 3) / 4;
+  if (status[0]) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int jl = lane & 15, kq = lane >> 4;
+  const int mp = n - w;
+  const int q = blockIdx.x * 16 + jl;
+  const bool colok = q < mp;
+  const int j = colok ? (q < p0 ? q : q + w) : 0;
+  double bx[KC];
+#pragma unroll
+  for (int kk = 0; kk < KC; ++kk) {
+    const int t = kk * 4 + kq;
+    bx[kk] = (colok && t < w) ? A[perm[p0 + t] * ld + j] : 0.0;
+  }
+  __syncthreads();
+  const int nrt = (n + 15) >> 4;
+  // clamped addresses: no load waits on another; the pivot rows, the rows
+  // past n and the columns past the panel are zeroed where the tile is used
+  struct Tile {
+    dx4 c;
+    int u[4];
+    double a[KC];
+  };
+  auto load_tile = [&](int rt) {
+    Tile T;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = min(rt * 16 + r * 4 + kq, n - 1);
+      T.c[r] = A[i * ld + j];
+      T.u[r] = used[i];
+    }
+    const int ia = min(rt * 16 + jl, n - 1);
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) T.a[kk] = A[ia * ld + p0 + min(kk * 4 + kq, NB - 1)];
+    return T;
+  };
+  Tile ring[kPrefetch];
+#pragma unroll
+  for (int u = 0; u < kPrefetch; ++u) ring[u] = load_tile(wave + 4 * u);
+  for (int rt0 = wave; rt0 < nrt; rt0 += 4 * kPrefetch) {
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+      const int rt = rt0 + 4 * u;
+      if (rt < nrt) {
+        Tile T = ring[u];
+        if (rt + 4 * kPrefetch < nrt) ring[u] = load_tile(rt + 4 * kPrefetch);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = rt * 16 + r * 4 + kq;
+          if (!(colok && i < n && (T.u[r] < p0 || T.u[r] >= p0 + w))) T.c[r] = 0.0;
+        }
+        const bool arow = rt * 16 + jl < n;
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+          const double a = (arow && kk * 4 + kq < NB) ? T.a[kk] : 0.0;
+          T.c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bx[kk], T.c, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = rt * 16 + r * 4 + kq;
+          if (colok && i < n) A[i * ld + j] = T.c[r];
+        }
+      }
+    }
+  }
+}
+
+// C0[c * n + k] = inv(A)[k][c] = S[perm[k]][used[c]] (column-major, dense GEMV layout)
+__global__ void k_cgj_finish(const double *__restrict__ S, int n, int64_t ld,
+                             const int *__restrict__ perm, const int *__restrict__ used,
+                             const int *__restrict__ status, double *__restrict__ C0) {
+  if (status[0]) return;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (k >= n) return;
+  C0[(int64_t)c * n + k] = S[perm[k] * ld + used[c]];
+}
+
+template <int NB, int R, int NT>
+static void gj_coarse_nb(double *A, int n, int64_t ld, int *perm, int *used, int *status,
+                         hipStream_t st) {
+  for (int p0 = 0; p0 < n; p0 += NB) {
+    const int w = std::min(NB, n - p0);
+    k_cgj_panel<NB, R, NT><<<1, NT, 0, st>>>(A, n, ld, p0, w, perm, used, status);
+    if (n > w) k_cgj_update<NB><<<cdivg(n - w, 16), 256, 0, st>>>(A, n, ld, p0, w, perm, used, status);
+  }
+}
+
+void gj_coarse(double *A, int n, int64_t ld, double *C0, int *status, int *iwork,
+               hipStream_t st) {
+  int *perm = iwork, *used = iwork + n;
+  k_fill_i32<<<cdivg(n, 256), 256, 0, st>>>(used, n, -1);
+  // (panel width, rows per thread, threads): 256 threads, one wave per
+  // SIMD, with the panel rows in registers without spilling
+  if (n <= 512)
+    gj_coarse_nb<16, 2, 256>(A, n, ld, perm, used, status, st);
+  else if (n <= 1024)
+    gj_coarse_nb<16, 4, 256>(A, n, ld, perm, used, status, st);
+  else if (n <= 1536)
+    gj_coarse_nb<16, 6, 256>(A, n, ld, perm, used, status, st);
+  else if (n <= 3072)
+    gj_coarse_nb<8, 12, 256>(A, n, ld, perm, used, status, st);
+  else
+    gj_coarse_nb<4, 24, 256>(A, n, ld, perm, used, status, st);
+  k_cgj_finish<<<dim3(cdivg(n, 256), n), 256, 0, st>>>(A, n, ld, perm, used, status, C0);
+}
+
+__global__ void k_csr_to_dense(int n, int64_t ld, const int *rowptr, const int *col,
+                               const double *val, double *A) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int p = rowptr[r]; p < rowptr[r + 1]; ++p) A[r * ld + col[p]] = val[p];
+}
+void launch_csr_to_dense(const CsrView<double> &A, double *dense, int64_t ld, hipStream_t st) {
+  if (A.nrows > 0)
+    k_csr_to_dense<<<cdivg(A.nrows, 256), 256, 0, st>>>(A.nrows, ld, A.rowptr, A.col, A.val,
+                                                         dense);
+}
+
+}  // namespace fsi

@@ -40,6 +40,7 @@ struct Level {
   int64_t sum_m = 0, sum_m2 = 0, sum_om = 0, total_owned = 0, boff_total = 0, woff_total = 0;
   std::vector<int64_t> h_ptr, h_boff;
   int64_t blk_base = 0;   // offset of this level's blocks in the shared scratch
+  int64_t pm_base = 0;    // offset of this level's pivot arrays (sum of m over earlier levels)
   std::vector<int32_t> h_dof;
   std::vector<uint8_t> h_owned, h_kind;
   int *d_pm = nullptr, *d_po = nullptr, *d_dof = nullptr, *d_out_off = nullptr,
@@ -88,8 +89,10 @@ struct MG {
   double *blk_scratch = nullptr, *dense_scratch = nullptr, *gj_work = nullptr;
   int *status = nullptr, *status0 = nullptr;
   int64_t blk_total = 0;
-  int64_t *all_boff = nullptr;
+  int64_t *all_boff = nullptr, *all_poff = nullptr;
   int *all_pm = nullptr;
+  int *gj_perm = nullptr, *gj_used = nullptr;   // pivot permutations of the block inverses
+  int64_t dense_ld = 0;                         // leading dimension of the coarse dense matrix
   int npatch_all = 0, mmax_all = 1;
   int gj_nb = 0;          // panel width of the batched Gauss-Jordan (0 = by size)
   hipStream_t side_stream = nullptr;

@@ -29,25 +29,31 @@ void launch_fill_f64(double *x, int64_t n, double v, hipStream_t st);
 void launch_extract(const CsrView<double> &J, int npatch, const int *pm, const int64_t *pdof_off,
                     const int *dof, const int64_t *boff, double *blocks, int64_t total_rows,
                     const int *row_patch, const int *row_local, hipStream_t st);
-// in-place inverse of every block, one workgroup per block; status[k] = 0 ok, else 1 + failing step
+// Gauss-Jordan inverse of every block, one workgroup per block (m <= 1024),
+// rows never exchanged: Binv[i][c] = S[perm[i]][used[c]] with S left in the
+// block and perm/used at poff[k]; status[k] = 0 ok, else 1 + failing step
 int gj_panel_width(int mmax);
-// nb_req: panel width chosen by the autotuner (8 or 16), 0 = by size
-void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, int npatch, int mmax,
-                       int *status, hipStream_t st, int nb_req = 0);
-// in-place inverse of one large matrix (row-major n x n), many workgroups per step
-void gj_large(double *A, int n, int *status_dev, double *work, hipStream_t st);
+// nb_req: panel width chosen by the autotuner (16 or 32), 0 = by size
+void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
+                       int *perm, int *used, int npatch, int mmax, int *status, hipStream_t st,
+                       int nb_req = 0);
+// inverse of the coarsest operator (row-major n x n, leading dimension ld,
+// n <= kMaxCoarse), written column-major to C0; iwork: 2 n ints; status[0]
+// = 0 ok, else 1 + failing step
+constexpr int kMaxCoarse = 6144;
+void gj_coarse(double *A, int n, int64_t ld, double *C0, int *status, int *iwork, hipStream_t st);
 // W_k[c * o_k + r] = Binv_k[own_row_r][c] (column-major owned rows), optional FP32/16-bit copies
 void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm, const int *po,
                        const int64_t *woff, const int *own_off, const int *own_local, int npatch,
                        int64_t total_owned, const int *orow_patch, const int *orow_r, double *W64,
                        float *W32, uint16_t *W16, int w16_kind, float *wscale,
-                       const int64_t *pdof_off, const float *cscale, hipStream_t st);
+                       const int64_t *pdof_off, const float *cscale, const int *perm,
+                       const int *used, hipStream_t st);
 // 16-bit storage: per-column scales of the owned rows of every block inverse
 void launch_colscale(const double *blocks, const int64_t *boff, const int *pm, const int *po,
                      const int *own_off, const int *own_local, const int64_t *pdof_off,
                      int64_t total_cols, const int *col_patch, const int *col_local, float *cscale,
-                     hipStream_t st);
-void launch_transpose_colmajor(const double *A, int n, double *W, hipStream_t st);
+                     const int *perm, const int *used, hipStream_t st);
 
 // ---- smoother (a5): e[out] += omega * W_k s[I_k] for every owned row
 //      (16-bit: W_k = diag(rs) W16 diag(cs), two-sided scaling)
@@ -103,6 +109,6 @@ void launch_start_cycle(int n, const double *r, const double *nrm2, double *v, d
 }  // namespace fsi
 
 namespace fsi {
-// dense row-major n x n from CSR (A zero-filled beforehand)
-void launch_csr_to_dense(const CsrView<double> &A, double *dense, hipStream_t st);
+// dense row-major n x n (leading dimension ld) from CSR (zero-filled beforehand)
+void launch_csr_to_dense(const CsrView<double> &A, double *dense, int64_t ld, hipStream_t st);
 }  // namespace fsi

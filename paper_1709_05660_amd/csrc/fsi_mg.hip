@@ -222,23 +222,25 @@ static void pack_level(MG &mg, Level &L, hipStream_t st) {
     }
     L.w16_kind = prec == FSI_PREC_MIXED_BF16 ? 1 : 2;
     launch_colscale(B, L.d_boff, L.d_pm, L.d_po, L.d_out_off, L.d_own_local, L.d_pdof_off,
-                    L.sum_m, L.d_row_patch, L.d_row_local, L.Cscale, st);
+                    L.sum_m, L.d_row_patch, L.d_row_local, L.Cscale, mg.gj_perm + L.pm_base,
+                    mg.gj_used + L.pm_base, st);
   }
   launch_pack_owned(B, L.d_boff, L.d_pm, L.d_po, L.d_woff, L.d_out_off, L.d_own_local, L.npatch,
                     L.total_owned, L.d_orow_patch, L.d_orow_r, L.W64, L.W32, L.W16, L.w16_kind,
-                    L.Wscale, L.d_pdof_off, L.Cscale, st);
+                    L.Wscale, L.d_pdof_off, L.Cscale, mg.gj_perm + L.pm_base, mg.gj_used + L.pm_base,
+                    st);
   hip_check(hipGetLastError(), "pack launch");
 }
 
-// coarsest operator: dense copy, Gauss-Jordan inverse, column-major for the GEMV (no sync)
+// coarsest operator: dense copy, Gauss-Jordan inverse written column-major
+// for the GEMV (no sync)
 static void enqueue_coarse(MG &mg, Level &L, hipStream_t st) {
   const int n = L.n;
   double *A = mg.dense_scratch;
-  launch_fill_f64(A, (int64_t)n * n, 0.0, st);
-  launch_csr_to_dense(L.J.v64(), A, st);
+  launch_fill_f64(A, (int64_t)n * mg.dense_ld, 0.0, st);
+  launch_csr_to_dense(L.J.v64(), A, mg.dense_ld, st);
   hip_check(hipMemsetAsync(mg.status0, 0, sizeof(int), st), "memset");
-  gj_large(A, n, mg.status0, mg.gj_work, st);
-  launch_transpose_colmajor(A, n, L.C0, st);
+  gj_coarse(A, n, mg.dense_ld, L.C0, mg.status0, reinterpret_cast<int *>(mg.gj_work), st);
   hip_check(hipGetLastError(), "coarse launch");
 }
 
@@ -261,8 +263,8 @@ void refactor(MG &mg, hipStream_t st) {
       launch_extract(L.J.v64(), L.npatch, L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff,
                      mg.blk_scratch + L.blk_base, L.sum_m, L.d_row_patch, L.d_row_local, st);
     }
-    launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.npatch_all, mg.mmax_all, mg.status, st,
-                      mg.gj_nb);
+    launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.all_poff, mg.gj_perm, mg.gj_used,
+                      mg.npatch_all, mg.mmax_all, mg.status, st, mg.gj_nb);
     hip_check(hipGetLastError(), "gj launch");
     for (int l = 1; l < mg.nlevels; ++l) pack_level(mg, mg.lv[l], st);
   }
@@ -436,6 +438,12 @@ void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *op
     throw Error(FSI_E_INVALID, "invalid multigrid options");
   std::vector<int64_t> n(nlevels);
   for (int l = 0; l < nlevels; ++l) n[l] = levels[l].J.nrows;
+  if (n[0] > kMaxCoarse) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "coarsest level has %lld unknowns; the dense direct solve takes at most %d",
+             (long long)n[0], kMaxCoarse);
+    throw Error(FSI_E_INVALID, buf);
+  }
   for (int l = 0; l < nlevels; ++l) {
     if (n[l] < 1) throw Error(FSI_E_INVALID, "empty level");
     validate_csr(levels[l].J, n[l], n[l], "J", l);
@@ -473,30 +481,38 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
       alloc_level_vectors(*mg, L);
     }
     // all levels' blocks in one scratch; one offset/size table for the batched inversion
-    std::vector<int64_t> all_boff;
+    std::vector<int64_t> all_boff, all_poff;
     std::vector<int> all_pm;
-    int64_t base = 0;
+    int64_t base = 0, pbase = 0;
     mg->mmax_all = 1;
     for (int l = 1; l < nlevels; ++l) {
       Level &L = mg->lv[l];
       L.blk_base = base;
+      L.pm_base = pbase;
       for (int k = 0; k < L.npatch; ++k) {
         all_boff.push_back(base + L.h_boff[k]);
+        all_poff.push_back(pbase + L.h_ptr[k]);
         all_pm.push_back((int)(L.h_ptr[k + 1] - L.h_ptr[k]));
       }
       base += L.boff_total;
+      pbase += L.sum_m;
       mg->mmax_all = std::max(mg->mmax_all, L.mmax);
     }
     mg->blk_total = base;
     mg->npatch_all = (int)all_pm.size();
     const int64_t n0 = mg->lv[0].n;
-    mg->blk_scratch = dalloc<double>(std::max<int64_t>(base, 1), mg->owned);
+    // + 64: the batched inversion loads each panel slice whole from its row base
+    mg->blk_scratch = dalloc<double>(base + 64, mg->owned);
     mg->all_boff = dupload(all_boff.data(), (int64_t)all_boff.size(), mg->owned, st);
     mg->all_pm = dupload(all_pm.data(), (int64_t)all_pm.size(), mg->owned, st);
+    mg->all_poff = dupload(all_poff.data(), (int64_t)all_poff.size(), mg->owned, st);
+    mg->gj_perm = dalloc<int>(std::max<int64_t>(pbase, 1), mg->owned);
+    mg->gj_used = dalloc<int>(std::max<int64_t>(pbase, 1), mg->owned);
     mg->status = dalloc<int>(std::max(mg->npatch_all, 1), mg->owned);
     mg->status0 = dalloc<int>(1, mg->owned);
-    mg->dense_scratch = dalloc<double>(n0 * n0, mg->owned);
-    mg->gj_work = dalloc<double>((2 + 16) * n0 + 64, mg->owned);
+    mg->dense_ld = (n0 + 15) / 16 * 16;
+    mg->dense_scratch = dalloc<double>(n0 * mg->dense_ld, mg->owned);
+    mg->gj_work = dalloc<double>(n0 + 64, mg->owned);
     mg->lv[0].C0 = dalloc<double>(n0 * n0, mg->owned);
     mg->lv[0].gemv_partial = dalloc<double>(8 * n0, mg->owned);
     hip_check(hipStreamCreateWithFlags(&mg->side_stream, hipStreamNonBlocking), "side stream");
@@ -810,15 +826,15 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
   }
   if (mg.npatch_all && mg.blk_scratch) {
     char key[256];
-    snprintf(key, sizeof key, "gj:%d:%d:%lld", mg.mmax_all, mg.npatch_all, (long long)mg.blk_total);
+    snprintf(key, sizeof key, "gj2:%d:%d:%lld", mg.mmax_all, mg.npatch_all, (long long)mg.blk_total);
     auto it = db.find(key);
     if (it != db.end()) {
       mg.gj_nb = it->second;
     } else {
       int best = 16;
       float best_ms = 1e30f;
-      for (int nb : {8, 16}) {
-        if (nb == 16 && (int64_t)mg.mmax_all * 17 * 8 > 150 * 1024) continue;
+      for (int nb : {16, 32}) {
+        if (nb == 32 && gj_panel_width(mg.mmax_all) != 32) continue;
         const float ms = time_events(st, [&] {
           for (int l = 1; l < mg.nlevels; ++l) {
             Level &L = mg.lv[l];
@@ -826,8 +842,8 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
             launch_extract(L.J.v64(), L.npatch, L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff,
                            mg.blk_scratch + L.blk_base, L.sum_m, L.d_row_patch, L.d_row_local, st);
           }
-          launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.npatch_all, mg.mmax_all,
-                            mg.status, st, nb);
+          launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.all_poff, mg.gj_perm,
+                            mg.gj_used, mg.npatch_all, mg.mmax_all, mg.status, st, nb);
         }, 1);
         if (ms < best_ms) {
           best_ms = ms;

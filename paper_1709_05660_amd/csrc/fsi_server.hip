@@ -82,7 +82,7 @@ static int64_t footprint(const fsi_level *lv, int nl, const fsi_mg_opts &mo,
     res += csr(lv[l].J) + 6 * n * 8;
     if (l == 0) {
       res += n * n * 8 + 8 * n * 8;
-      transient = std::max<int64_t>(transient, n * n * 8 + 18 * n * 8);
+      transient = std::max<int64_t>(transient, n * ((n + 15) / 16 * 16) * 8 + 2 * n * 8);
       continue;
     }
     res += csr(lv[l].P) + csr(lv[l].R);
@@ -95,7 +95,7 @@ static int64_t footprint(const fsi_level *lv, int nl, const fsi_mg_opts &mo,
       om += o * m;
       m2 += m * m;
     }
-    res += om * wbytes + P.ptr[P.npatch] * 40;
+    res += om * wbytes + P.ptr[P.npatch] * 48;
     transient += m2 * 8;                 // all levels' dense blocks share one setup scratch
   }
   const int64_t nf = lv[nl - 1].J.nrows;
