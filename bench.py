@@ -12,8 +12,10 @@ the timed region starts.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -31,6 +33,33 @@ def ras_bytes(info, wbytes, vbytes):
     every block inverse once, the gathered residual entries (index + value),
     and the owned corrections (index, read, write)."""
     return wbytes * info["sum_om"] + (4 + vbytes) * info["sum_m"] + (4 + 2 * vbytes) * info["n_owned"]
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ras_finest_c1_2d_128x32_fp64_traffic.md")
+
+
+def ras_kernel_digest():
+    """Digest of the device code of the Schwarz kernel (helpers and kernel
+    body, not the host launchers): counter readings apply only to this code."""
+    src = open(os.path.join(ROOT, "paper_1709_05660_amd", "csrc", "fsi_kernels.hip")).read()
+    a = src.index("__device__ inline float w16val")
+    b = src.index("// ev0/ev1 (optional, finest level)")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per finest-level Schwarz launch from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None
+    when the summary was taken on other kernel code."""
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    b = re.search(r"traffic_bytes_per_launch:\s*(\d+)", txt)
+    d = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", txt)
+    if not b or not d or d.group(1) != ras_kernel_digest():
+        return None
+    return int(b.group(1))
 
 
 def gpu_leg(args):
@@ -108,7 +137,7 @@ def gpu_leg(args):
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if cnt else 0.0
         out["roofline"] = {"bound": "hbm", "kernel": "k_ras<double> (finest level)",
                            "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-                           "frac": round(achieved / 8000.0, 4), "traffic": None,
+                           "frac": round(achieved / 8000.0, 4), "traffic": measured_traffic(),
                            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": cnt,
                            "bytes_per_launch": int(bytes_per_launch)}
         if args.traffic_probe:

@@ -64,7 +64,8 @@ constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppRor4 = 0x124, kDppRor8 = 0x1
 
 // wave-wide argmax (largest value, then lowest index) in every lane: the
 // maximum by a DPP reduction inside each row of 16 lanes and a combination
-// of the four rows, then the lowest index among the lanes holding it.
+// of the four rows; the lane holding it from a ballot when it is unique,
+// else the lowest index among the tied lanes by a second reduction.
 // Requires all 64 lanes active.
 __device__ __forceinline__ Argmax wave_argmax(Argmax a) {
   double v = a.v;
@@ -74,6 +75,8 @@ __device__ __forceinline__ Argmax wave_argmax(Argmax a) {
   v = fmax(v, dpp_f64<kDppRor8>(v));
   const double wmax = fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
                            fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+  const unsigned long long tie = __ballot(a.v == wmax);
+  if (__popcll(tie) == 1) return Argmax{wmax, __builtin_amdgcn_readlane(a.i, __ffsll((long long)tie) - 1)};
   int i = a.v == wmax ? a.i : kNoRow;
   i = min(i, dpp_i32<kDppXor1>(i));
   i = min(i, dpp_i32<kDppXor2>(i));
@@ -84,12 +87,14 @@ __device__ __forceinline__ Argmax wave_argmax(Argmax a) {
   return Argmax{wmax, wi};
 }
 
-// LDS of the pivot steps: one candidate row per wave and step parity, and
-// the panel's pivot rows in step order.
+// LDS of the pivot steps: one candidate row (with the reciprocal of its
+// pivot-column entry) per wave and step parity, and the panel's pivot rows
+// in step order.
 template <int NB, int NW>
 struct PivotLds {
   double row[2][NW][NB];
   double val[2][NW];
+  double dinv[2][NW];
   int idx[2][NW];
   int piv[NB];
 };
@@ -103,57 +108,71 @@ __device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int buf = t & 1;
   Argmax best{-1.0, kNoRow};
+  double sv = 1.0;   // signed pivot-column entry of this lane's candidate
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int i = tid + q * NT;
     if (i < m && stp[q] < 0) {
       const double a = fabs(v[q][col]);
       const Argmax c{a != a ? INFINITY : a, i};
-      if (beats(c, best)) best = c;
+      if (beats(c, best)) {
+        best = c;
+        sv = v[q][col];
+      }
     }
   }
+  // every lane inverts its own candidate while the wave reduction runs;
+  // the winner publishes its reciprocal
+  const double dl = 1.0 / sv;
   best = wave_argmax(best);
 #pragma unroll
   for (int q = 0; q < R; ++q)
     if (tid + q * NT == best.i) {
 #pragma unroll
       for (int c = 0; c < NB; ++c) sh.row[buf][wave][c] = v[q][c];
+      sh.dinv[buf][wave] = dl;
     }
   if (lane == 0) {
     sh.val[buf][wave] = best.v;
     sh.idx[buf][wave] = best.i;
   }
   __syncthreads();
-  Argmax g{sh.val[buf][0], sh.idx[buf][0]};
-  int gw = 0;
+  // the waves' candidates combined by a tree (same result as in order)
+  Argmax cand[NW];
+  int cw[NW];
 #pragma unroll
-  for (int k = 1; k < NW; ++k) {
-    const Argmax c{sh.val[buf][k], sh.idx[buf][k]};
-    if (beats(c, g)) {
-      g = c;
-      gw = k;
-    }
+  for (int k = 0; k < NW; ++k) {
+    cand[k] = Argmax{sh.val[buf][k], sh.idx[buf][k]};
+    cw[k] = k;
   }
+#pragma unroll
+  for (int s2 = 1; s2 < NW; s2 <<= 1)
+#pragma unroll
+    for (int k = 0; k + s2 < NW; k += 2 * s2)
+      if (beats(cand[k + s2], cand[k])) {
+        cand[k] = cand[k + s2];
+        cw[k] = cw[k + s2];
+      }
+  const Argmax g = cand[0];
+  const int gw = cw[0];
   if (!(g.v > 0.0) || isinf(g.v)) return p0 + t + 1;
   if (tid == 0) sh.piv[t] = g.i;
   const double *prow = sh.row[buf][gw];
-  const double d = 1.0 / prow[col];
-  double pr[NB];
-#pragma unroll
-  for (int c = 0; c < NB; ++c) pr[c] = prow[c] * d;
-  // every row is eliminated, then the one lane holding the pivot row
-  // overwrites it (a branch of one lane instead of a select on every row)
+  const double d = sh.dinv[buf][gw];
+  // every row is eliminated with one FMA per column, v - (f d) prow, then
+  // the one lane holding the pivot row overwrites it with prow d (a branch
+  // of one lane instead of a select on every row)
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const double f = v[q][col];
+    const double fd = v[q][col] * d;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) v[q][c] = c == col ? -f * d : v[q][c] - f * pr[c];
+    for (int c = 0; c < NB; ++c) v[q][c] = c == col ? -fd : v[q][c] - fd * prow[c];
   }
 #pragma unroll
   for (int q = 0; q < R; ++q)
     if (tid + q * NT == g.i) {
 #pragma unroll
-      for (int c = 0; c < NB; ++c) v[q][c] = c == col ? d : pr[c];
+      for (int c = 0; c < NB; ++c) v[q][c] = c == col ? d : prow[c] * d;
       stp[q] = p0 + t;
     }
   return 0;
@@ -381,20 +400,22 @@ __global__ void k_fill_i32(int *x, int n, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;
 }
+void launch_fill_i32(int *x, int n, int v, hipStream_t st) {
+  if (n > 0) k_fill_i32<<<cdivg(n, 256), 256, 0, st>>>(x, n, v);
+}
 
+// Factors the panel of columns [p0, p0 + w) of the coarse matrix (all NT
+// threads of the workgroup; rows tid + q NT in registers).  p0 + NB <= ld
+// (ld is a multiple of 16 and NB divides 16): a row's panel slice is loaded
+// whole from one base address; rows beyond n repeat row n - 1 and are never
+// candidates.  On failure status[0] = 1 + the failing step.
 template <int NB, int R, int NT>
-__global__ __launch_bounds__(NT) void k_cgj_panel(double *__restrict__ A, int n, int64_t ld,
-                                                  int p0, int w, int *__restrict__ perm,
-                                                  int *__restrict__ used,
-                                                  int *__restrict__ status) {
-  __shared__ PivotLds<NB, NT / 64> sh;
-  if (status[0]) return;
+__device__ __forceinline__ void cgj_factor(double *__restrict__ A, int n, int64_t ld, int p0,
+                                           int w, int *__restrict__ perm, int *__restrict__ used,
+                                           int *__restrict__ status, PivotLds<NB, NT / 64> &sh) {
   const int tid = threadIdx.x;
   double v[R][NB];
   int stp[R];
-  // p0 + NB <= ld (ld is a multiple of 16 and NB divides 16): a row's panel
-  // slice is loaded whole from one base address; rows beyond n repeat row
-  // n - 1 and are never candidates
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int i = tid + q * NT;
@@ -428,22 +449,31 @@ __global__ __launch_bounds__(NT) void k_cgj_panel(double *__restrict__ A, int n,
   if (tid < w) perm[p0 + tid] = sh.piv[tid];
 }
 
-// One workgroup per tile of 16 of the columns outside the panel (taken in
-// order, skipping the panel).  Its four waves read the tile's X (pivot
-// rows' old values) into registers, meet at a barrier, then update the
-// tile's 16-row tiles round-robin on the matrix cores (same operand layouts
-// as the batched kernel); no other workgroup touches the tile.
-template <int NB>
-__global__ __launch_bounds__(256) void k_cgj_update(double *__restrict__ A, int n, int64_t ld,
-                                                    int p0, int w, const int *__restrict__ perm,
-                                                    const int *__restrict__ used,
-                                                    const int *__restrict__ status) {
-  constexpr int KC = (NB + 3) / 4;
+template <int NB, int R, int NT>
+__global__ __launch_bounds__(NT) void k_cgj_panel(double *__restrict__ A, int n, int64_t ld,
+                                                  int p0, int w, int *__restrict__ perm,
+                                                  int *__restrict__ used,
+                                                  int *__restrict__ status) {
+  __shared__ PivotLds<NB, NT / 64> sh;
   if (status[0]) return;
+  cgj_factor<NB, R, NT>(A, n, ld, p0, w, perm, used, status, sh);
+}
+
+// Applies the factored panel [p0, p0 + w) to one tile of 16 of the columns
+// outside it (taken in order, skipping the panel).  The workgroup's waves
+// read the tile's X (pivot rows' old values) into registers, meet at a
+// barrier, then update the tile's 16-row tiles round-robin on the matrix
+// cores (operand layouts as in the batched kernel); no other workgroup
+// touches the tile.
+template <int NB, int NT>
+__device__ __forceinline__ void cgj_update_tile(double *__restrict__ A, int n, int64_t ld, int p0,
+                                                int w, int ct, const int *__restrict__ perm,
+                                                const int *__restrict__ used) {
+  constexpr int KC = (NB + 3) / 4, NWV = NT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int jl = lane & 15, kq = lane >> 4;
   const int mp = n - w;
-  const int q = blockIdx.x * 16 + jl;
+  const int q = ct * 16 + jl;
   const bool colok = q < mp;
   const int j = colok ? (q < p0 ? q : q + w) : 0;
   double bx[KC];
@@ -476,14 +506,14 @@ __global__ __launch_bounds__(256) void k_cgj_update(double *__restrict__ A, int 
   };
   Tile ring[kPrefetch];
 #pragma unroll
-  for (int u = 0; u < kPrefetch; ++u) ring[u] = load_tile(wave + 4 * u);
-  for (int rt0 = wave; rt0 < nrt; rt0 += 4 * kPrefetch) {
+  for (int u = 0; u < kPrefetch; ++u) ring[u] = load_tile(wave + NWV * u);
+  for (int rt0 = wave; rt0 < nrt; rt0 += NWV * kPrefetch) {
 #pragma unroll
     for (int u = 0; u < kPrefetch; ++u) {
-      const int rt = rt0 + 4 * u;
+      const int rt = rt0 + NWV * u;
       if (rt < nrt) {
         Tile T = ring[u];
-        if (rt + 4 * kPrefetch < nrt) ring[u] = load_tile(rt + 4 * kPrefetch);
+        if (rt + NWV * kPrefetch < nrt) ring[u] = load_tile(rt + NWV * kPrefetch);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = rt * 16 + r * 4 + kq;
@@ -505,6 +535,28 @@ __global__ __launch_bounds__(256) void k_cgj_update(double *__restrict__ A, int 
   }
 }
 
+// One launch per panel [p0, p0 + w): every workgroup updates one column
+// tile; the workgroup whose tile holds the next panel's columns (compressed
+// tile p0 / 16, since NB divides 16) then factors that panel.  Concurrent
+// readers of used[] only test membership in [p0, p0 + w), which the
+// factorization never changes (it sets entries that were -1 to steps
+// >= p0 + w); it writes only its own tile and perm[p0 + w ...].
+template <int NB, int R, int NT>
+__global__ __launch_bounds__(NT) void k_cgj_step(double *__restrict__ A, int n, int64_t ld,
+                                                 int p0, int w, int *__restrict__ perm,
+                                                 int *__restrict__ used,
+                                                 int *__restrict__ status) {
+  __shared__ PivotLds<NB, NT / 64> sh;
+  if (status[0]) return;
+  cgj_update_tile<NB, NT>(A, n, ld, p0, w, blockIdx.x, perm, used);
+  const int pn = p0 + w;
+  if (pn < n && (int)blockIdx.x == p0 / 16) {
+    __threadfence_block();
+    __syncthreads();
+    cgj_factor<NB, R, NT>(A, n, ld, pn, min(NB, n - pn), perm, used, status, sh);
+  }
+}
+
 // C0[c * n + k] = inv(A)[k][c] = S[perm[k]][used[c]] (column-major, dense GEMV layout)
 __global__ void k_cgj_finish(const double *__restrict__ S, int n, int64_t ld,
                              const int *__restrict__ perm, const int *__restrict__ used,
@@ -519,10 +571,10 @@ __global__ void k_cgj_finish(const double *__restrict__ S, int n, int64_t ld,
 template <int NB, int R, int NT>
 static void gj_coarse_nb(double *A, int n, int64_t ld, int *perm, int *used, int *status,
                          hipStream_t st) {
+  k_cgj_panel<NB, R, NT><<<1, NT, 0, st>>>(A, n, ld, 0, std::min(NB, n), perm, used, status);
   for (int p0 = 0; p0 < n; p0 += NB) {
     const int w = std::min(NB, n - p0);
-    k_cgj_panel<NB, R, NT><<<1, NT, 0, st>>>(A, n, ld, p0, w, perm, used, status);
-    if (n > w) k_cgj_update<NB><<<cdivg(n - w, 16), 256, 0, st>>>(A, n, ld, p0, w, perm, used, status);
+    if (n > w) k_cgj_step<NB, R, NT><<<cdivg(n - w, 16), NT, 0, st>>>(A, n, ld, p0, w, perm, used, status);
   }
 }
 
@@ -530,18 +582,18 @@ void gj_coarse(double *A, int n, int64_t ld, double *C0, int *status, int *iwork
                hipStream_t st) {
   int *perm = iwork, *used = iwork + n;
   k_fill_i32<<<cdivg(n, 256), 256, 0, st>>>(used, n, -1);
-  // (panel width, rows per thread, threads): 256 threads, one wave per
-  // SIMD, with the panel rows in registers without spilling
+  // (panel width, rows per thread, threads): 512 threads, the panel rows in
+  // registers without spilling
   if (n <= 512)
-    gj_coarse_nb<16, 2, 256>(A, n, ld, perm, used, status, st);
+    gj_coarse_nb<16, 1, 512>(A, n, ld, perm, used, status, st);
   else if (n <= 1024)
-    gj_coarse_nb<16, 4, 256>(A, n, ld, perm, used, status, st);
+    gj_coarse_nb<16, 2, 512>(A, n, ld, perm, used, status, st);
   else if (n <= 1536)
-    gj_coarse_nb<16, 6, 256>(A, n, ld, perm, used, status, st);
+    gj_coarse_nb<16, 3, 512>(A, n, ld, perm, used, status, st);
   else if (n <= 3072)
-    gj_coarse_nb<8, 12, 256>(A, n, ld, perm, used, status, st);
+    gj_coarse_nb<8, 6, 512>(A, n, ld, perm, used, status, st);
   else
-    gj_coarse_nb<4, 24, 256>(A, n, ld, perm, used, status, st);
+    gj_coarse_nb<4, 12, 512>(A, n, ld, perm, used, status, st);
   k_cgj_finish<<<dim3(cdivg(n, 256), n), 256, 0, st>>>(A, n, ld, perm, used, status, C0);
 }
 

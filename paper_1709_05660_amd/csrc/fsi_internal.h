@@ -97,6 +97,7 @@ struct MG {
   int gj_nb = 0;          // panel width of the batched Gauss-Jordan (0 = by size)
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipGraphExec_t coarse_graph = nullptr;   // the coarsest inversion's launch chain, replayed per refactor
   // event timing of the finest-level Schwarz kernel
   bool prof_on = false;
   size_t prof_used = 0;

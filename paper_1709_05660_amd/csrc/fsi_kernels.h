@@ -41,6 +41,7 @@ void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const
 // n <= kMaxCoarse), written column-major to C0; iwork: 2 n ints; status[0]
 // = 0 ok, else 1 + failing step
 constexpr int kMaxCoarse = 6144;
+void launch_fill_i32(int *x, int n, int v, hipStream_t st);
 void gj_coarse(double *A, int n, int64_t ld, double *C0, int *status, int *iwork, hipStream_t st);
 // W_k[c * o_k + r] = Binv_k[own_row_r][c] (column-major owned rows), optional FP32/16-bit copies
 void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm, const int *po,
@@ -65,12 +66,14 @@ struct RasView {
   const int *dof, *out_off, *out_idx;
   const float *cscale;   // 16-bit storage: column scales (per patch dof), else null
 };
+// ev0/ev1: optional events recorded at the finest-level kernel's start and end
 void launch_ras_f64(const RasView &v, const double *W, const double *s, double *e, double omega,
-                    bool finest, hipStream_t st);
+                    bool finest, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_ras_f32(const RasView &v, const float *W, const float *s, float *e, float omega,
-                    bool finest, hipStream_t st);
+                    bool finest, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_ras_16(const RasView &v, const uint16_t *W, int w16_kind, const float *wscale,
-                   const float *s, float *e, float omega, bool finest, hipStream_t st);
+                   const float *s, float *e, float omega, bool finest, hipStream_t st,
+                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // ---- coarsest solve (a7): y = W x, W column-major n x n FP64
 void launch_dense_gemv(const double *W, int n, const double *x, double *y, double *partial,

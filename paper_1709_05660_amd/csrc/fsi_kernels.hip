@@ -7,6 +7,7 @@
 #include "fsi_kernels.h"
 
 #include <hip/hip_bf16.h>
+#include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
@@ -343,27 +344,33 @@ __global__ __launch_bounds__(256) void k_ras(RasView v, const WT *__restrict__ W
   }
 }
 
+// ev0/ev1 (optional, finest level): timing events recorded at the kernel's
+// own start and end (hipExtLaunchKernelGGL), not around its launch
 void launch_ras_f64(const RasView &v, const double *W, const double *s, double *e, double omega,
-                    bool finest, hipStream_t st) {
+                    bool finest, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (v.ntask == 0) return;
   if (finest)
-    k_ras<double, double, double, false, 1><<<v.ntask, 256, 0, st>>>(v, W, 0, nullptr, s, e, omega);
+    hipExtLaunchKernelGGL(k_ras<double, double, double, false, 1>, dim3(v.ntask), dim3(256), 0, st,
+                          ev0, ev1, 0, v, W, 0, (const float *)nullptr, s, e, omega);
   else
     k_ras<double, double, double, false, 0><<<v.ntask, 256, 0, st>>>(v, W, 0, nullptr, s, e, omega);
 }
 void launch_ras_f32(const RasView &v, const float *W, const float *s, float *e, float omega,
-                    bool finest, hipStream_t st) {
+                    bool finest, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (v.ntask == 0) return;
   if (finest)
-    k_ras<float, float, float, false, 1><<<v.ntask, 256, 0, st>>>(v, W, 0, nullptr, s, e, omega);
+    hipExtLaunchKernelGGL(k_ras<float, float, float, false, 1>, dim3(v.ntask), dim3(256), 0, st, ev0,
+                          ev1, 0, v, W, 0, (const float *)nullptr, s, e, omega);
   else
     k_ras<float, float, float, false, 0><<<v.ntask, 256, 0, st>>>(v, W, 0, nullptr, s, e, omega);
 }
 void launch_ras_16(const RasView &v, const uint16_t *W, int w16_kind, const float *wscale,
-                   const float *s, float *e, float omega, bool finest, hipStream_t st) {
+                   const float *s, float *e, float omega, bool finest, hipStream_t st,
+                   hipEvent_t ev0, hipEvent_t ev1) {
   if (v.ntask == 0) return;
   if (finest)
-    k_ras<uint16_t, float, float, true, 1><<<v.ntask, 256, 0, st>>>(v, W, w16_kind, wscale, s, e, omega);
+    hipExtLaunchKernelGGL(k_ras<uint16_t, float, float, true, 1>, dim3(v.ntask), dim3(256), 0, st,
+                          ev0, ev1, 0, v, W, w16_kind, wscale, s, e, omega);
   else
     k_ras<uint16_t, float, float, true, 0><<<v.ntask, 256, 0, st>>>(v, W, w16_kind, wscale, s, e, omega);
 }

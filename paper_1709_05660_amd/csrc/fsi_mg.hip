@@ -239,23 +239,23 @@ static void enqueue_coarse(MG &mg, Level &L, hipStream_t st) {
   double *A = mg.dense_scratch;
   launch_fill_f64(A, (int64_t)n * mg.dense_ld, 0.0, st);
   launch_csr_to_dense(L.J.v64(), A, mg.dense_ld, st);
-  hip_check(hipMemsetAsync(mg.status0, 0, sizeof(int), st), "memset");
+  launch_fill_i32(mg.status0, 1, 0, st);   // a kernel, not a memset: this chain is graph-captured
   gj_coarse(A, n, mg.dense_ld, L.C0, mg.status0, reinterpret_cast<int *>(mg.gj_work), st);
   hip_check(hipGetLastError(), "coarse launch");
 }
 
-// setup of a1-a3 from the device-resident operator values: the coarsest
-// inversion runs on a second stream while all smoothing levels' blocks are
-// extracted and inverted in one launch on the main stream
+// setup of a1-a3 from the device-resident operator values.  The blocks of
+// all smoothing levels are extracted and inverted in one launch on the main
+// stream, enqueued first; the coarsest inversion (a chain of ~n/16 small
+// launches, replayed from a graph captured at the first refactor) runs
+// beside it on a second stream, on the compute units the batched launch
+// leaves free.
 void refactor(MG &mg, hipStream_t st) {
   if (!mg.dense_scratch) throw Error(FSI_E_INVALID, "setup scratch released; refactor unavailable");
   auto t0 = std::chrono::steady_clock::now();
   if (mg.mixed)
     for (int l = 1; l < mg.nlevels; ++l) launch_cast_d2f(mg.lv[l].J.val, mg.lv[l].J.val32, mg.lv[l].J.nnz, st);
   hip_check(hipEventRecord(mg.ev_fork, st), "fork");
-  hip_check(hipStreamWaitEvent(mg.side_stream, mg.ev_fork, 0), "fork wait");
-  enqueue_coarse(mg, mg.lv[0], mg.side_stream);
-  hip_check(hipEventRecord(mg.ev_join, mg.side_stream), "join");
   if (mg.nlevels > 1) {
     launch_fill_f64(mg.blk_scratch, mg.blk_total, 0.0, st);
     for (int l = 1; l < mg.nlevels; ++l) {
@@ -268,6 +268,21 @@ void refactor(MG &mg, hipStream_t st) {
     hip_check(hipGetLastError(), "gj launch");
     for (int l = 1; l < mg.nlevels; ++l) pack_level(mg, mg.lv[l], st);
   }
+  hip_check(hipStreamWaitEvent(mg.side_stream, mg.ev_fork, 0), "fork wait");
+  if (mg.opts.use_graph) {
+    if (!mg.coarse_graph) {
+      hipGraph_t g;
+      hip_check(hipStreamBeginCapture(mg.side_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+      enqueue_coarse(mg, mg.lv[0], mg.side_stream);
+      hip_check(hipStreamEndCapture(mg.side_stream, &g), "end capture");
+      hip_check(hipGraphInstantiate(&mg.coarse_graph, g, nullptr, nullptr, 0), "instantiate");
+      (void)hipGraphDestroy(g);
+    }
+    hip_check(hipGraphLaunch(mg.coarse_graph, mg.side_stream), "graph launch");
+  } else {
+    enqueue_coarse(mg, mg.lv[0], mg.side_stream);
+  }
+  hip_check(hipEventRecord(mg.ev_join, mg.side_stream), "join");
   hip_check(hipStreamWaitEvent(st, mg.ev_join, 0), "join wait");
   std::vector<int> hs(mg.npatch_all + 1, 0);
   if (mg.npatch_all)
@@ -293,7 +308,7 @@ void refactor(MG &mg, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ V-cycle
-// event pair around the finest-level Schwarz kernel while profiling
+// event pair recorded at the finest-level Schwarz kernel's start and end while profiling
 static hipEvent_t *prof_pair(MG &mg, Level &L) {
   if (!mg.prof_on || &L != &mg.lv.back()) return nullptr;
   if (mg.prof_used == mg.prof_ev.size()) {
@@ -306,19 +321,17 @@ static hipEvent_t *prof_pair(MG &mg, Level &L) {
 }
 static void ras64(MG &mg, Level &L, const double *s, double *e, hipStream_t st) {
   hipEvent_t *ev = prof_pair(mg, L);
-  if (ev) hip_check(hipEventRecord(ev[0], st), "record");
-  launch_ras_f64(ras_view(L), L.W64, s, e, mg.opts.omega, &L == &mg.lv.back(), st);
-  if (ev) hip_check(hipEventRecord(ev[1], st), "record");
+  launch_ras_f64(ras_view(L), L.W64, s, e, mg.opts.omega, &L == &mg.lv.back(), st,
+                 ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
 }
 static void ras32(MG &mg, Level &L, const float *s, float *e, hipStream_t st) {
   hipEvent_t *ev = prof_pair(mg, L);
-  if (ev) hip_check(hipEventRecord(ev[0], st), "record");
   if (L.W32)
-    launch_ras_f32(ras_view(L), L.W32, s, e, (float)mg.opts.omega, &L == &mg.lv.back(), st);
+    launch_ras_f32(ras_view(L), L.W32, s, e, (float)mg.opts.omega, &L == &mg.lv.back(), st,
+                   ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
   else
     launch_ras_16(ras_view(L), L.W16, L.w16_kind, L.Wscale, s, e, (float)mg.opts.omega,
-                  &L == &mg.lv.back(), st);
-  if (ev) hip_check(hipEventRecord(ev[1], st), "record");
+                  &L == &mg.lv.back(), st, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
 }
 
 // FP64 V-cycle on level l: input L.r, output L.e
@@ -552,6 +565,7 @@ void destroy_mg(MG *mg) {
     (void)hipStreamSynchronize(mg->side_stream);
     (void)hipStreamDestroy(mg->side_stream);
   }
+  if (mg->coarse_graph) (void)hipGraphExecDestroy(mg->coarse_graph);
   if (mg->ev_fork) (void)hipEventDestroy(mg->ev_fork);
   if (mg->ev_join) (void)hipEventDestroy(mg->ev_join);
   for (auto &p : mg->prof_ev) {
