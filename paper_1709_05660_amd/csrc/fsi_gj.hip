@@ -535,12 +535,55 @@ __device__ __forceinline__ void cgj_update_tile(double *__restrict__ A, int n, i
   }
 }
 
-// One launch per panel [p0, p0 + w): every workgroup updates one column
-// tile; the workgroup whose tile holds the next panel's columns (compressed
-// tile p0 / 16, since NB divides 16) then factors that panel.  Concurrent
-// readers of used[] only test membership in [p0, p0 + w), which the
-// factorization never changes (it sets entries that were -1 to steps
-// >= p0 + w); it writes only its own tile and perm[p0 + w ...].
+// Update of the compressed column tile p0 / 16, which holds the next
+// panel, by the factored panel [p0, p0 + w), for every row that is not one
+// of the panel's pivot rows (those are read here as X and finished by the
+// factoring workgroup of k_cgj_step); 64 rows per workgroup, 4 threads per
+// row, 4 columns each.  The critical path between two panels is then this
+// short launch and the factorization, not a whole-tile update.
+template <int NB>
+__global__ __launch_bounds__(256) void k_cgj_next(double *__restrict__ A, int n, int64_t ld, int p0,
+                                                  int w, const int *__restrict__ perm,
+                                                  const int *__restrict__ used,
+                                                  const int *__restrict__ status) {
+  __shared__ double X[NB][16];   // the pivot rows' values in the tile, staged once
+  if (status[0]) return;
+  const int tid = threadIdx.x, mp = n - w, q00 = (p0 / 16) * 16;
+  if (tid < 16 * NB) {
+    const int t = tid >> 4, q = q00 + (tid & 15);
+    X[t][tid & 15] = (t < w && q < mp) ? A[perm[p0 + t] * ld + (q < p0 ? q : q + w)] : 0.0;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 64 + (tid >> 2);
+  if (i >= n) return;
+  const int s = used[i];
+  if (s >= p0 && s < p0 + w) return;
+  const int e0 = (tid & 3) * 4;
+  double *Ai = A + i * ld;
+  double pc[NB];
+#pragma unroll
+  for (int t = 0; t < NB; ++t) pc[t] = t < w ? Ai[p0 + t] : 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int q = q00 + e0 + e;
+    if (q < mp) {
+      const int j = q < p0 ? q : q + w;
+      double acc = Ai[j];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) acc += pc[t] * X[t][e0 + e];
+      Ai[j] = acc;
+    }
+  }
+}
+
+// One launch per panel [p0, p0 + w).  Every workgroup but one updates one
+// compressed column tile with the panel.  The workgroup of tile p0 / 16
+// (which holds the next panel; k_cgj_next has updated its other rows)
+// computes the panel's pivot rows in that tile, then factors the next
+// panel.  Concurrent readers of used[] only test membership in
+// [p0, p0 + w), which the factorization never changes (it sets entries that
+// were -1 to steps >= p0 + w); it writes only its own tile and
+// perm[p0 + w ...].
 template <int NB, int R, int NT>
 __global__ __launch_bounds__(NT) void k_cgj_step(double *__restrict__ A, int n, int64_t ld,
                                                  int p0, int w, int *__restrict__ perm,
@@ -548,13 +591,32 @@ __global__ __launch_bounds__(NT) void k_cgj_step(double *__restrict__ A, int n, 
                                                  int *__restrict__ status) {
   __shared__ PivotLds<NB, NT / 64> sh;
   if (status[0]) return;
-  cgj_update_tile<NB, NT>(A, n, ld, p0, w, blockIdx.x, perm, used);
   const int pn = p0 + w;
-  if (pn < n && (int)blockIdx.x == p0 / 16) {
-    __threadfence_block();
-    __syncthreads();
-    cgj_factor<NB, R, NT>(A, n, ld, pn, min(NB, n - pn), perm, used, status, sh);
+  if (pn >= n || (int)blockIdx.x != p0 / 16) {
+    cgj_update_tile<NB, NT>(A, n, ld, p0, w, blockIdx.x, perm, used);
+    return;
   }
+  // the panel's pivot rows in this tile: new A[r_s][j] = sum_t PC[r_s][t] X[t][j]
+  // with X the pivot rows' old values (all read before any is written)
+  const int tid = threadIdx.x, mp = n - w, ct = p0 / 16;
+  double val = 0.0;
+  int64_t dst = -1;
+  if (tid < 16 * w) {
+    const int sidx = tid >> 4, q = ct * 16 + (tid & 15);
+    if (q < mp) {
+      const int j = q < p0 ? q : q + w;
+      const double *pr = A + perm[p0 + sidx] * ld + p0;
+#pragma unroll
+      for (int t = 0; t < NB; ++t)
+        if (t < w) val += pr[t] * A[perm[p0 + t] * ld + j];
+      dst = perm[p0 + sidx] * ld + j;
+    }
+  }
+  __syncthreads();
+  if (dst >= 0) A[dst] = val;
+  __threadfence_block();
+  __syncthreads();
+  cgj_factor<NB, R, NT>(A, n, ld, pn, min(NB, n - pn), perm, used, status, sh);
 }
 
 // C0[c * n + k] = inv(A)[k][c] = S[perm[k]][used[c]] (column-major, dense GEMV layout)
@@ -574,7 +636,9 @@ static void gj_coarse_nb(double *A, int n, int64_t ld, int *perm, int *used, int
   k_cgj_panel<NB, R, NT><<<1, NT, 0, st>>>(A, n, ld, 0, std::min(NB, n), perm, used, status);
   for (int p0 = 0; p0 < n; p0 += NB) {
     const int w = std::min(NB, n - p0);
-    if (n > w) k_cgj_step<NB, R, NT><<<cdivg(n - w, 16), NT, 0, st>>>(A, n, ld, p0, w, perm, used, status);
+    if (n <= w) break;
+    if (p0 + w < n) k_cgj_next<NB><<<cdivg(n, 64), 256, 0, st>>>(A, n, ld, p0, w, perm, used, status);
+    k_cgj_step<NB, R, NT><<<cdivg(n - w, 16), NT, 0, st>>>(A, n, ld, p0, w, perm, used, status);
   }
 }
 

@@ -45,8 +45,7 @@ struct Level {
   std::vector<uint8_t> h_owned, h_kind;
   int *d_pm = nullptr, *d_po = nullptr, *d_dof = nullptr, *d_out_off = nullptr,
       *d_own_local = nullptr, *d_out_idx = nullptr, *d_task_patch = nullptr,
-      *d_task_row0 = nullptr, *d_row_patch = nullptr, *d_row_local = nullptr,
-      *d_orow_patch = nullptr, *d_orow_r = nullptr;
+      *d_task_row0 = nullptr, *d_row_patch = nullptr, *d_row_local = nullptr;
   int64_t *d_pdof_off = nullptr, *d_woff = nullptr, *d_boff = nullptr;
   double *W64 = nullptr;
   float *W32 = nullptr;

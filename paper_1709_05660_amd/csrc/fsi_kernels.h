@@ -43,18 +43,19 @@ void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const
 constexpr int kMaxCoarse = 6144;
 void launch_fill_i32(int *x, int n, int v, hipStream_t st);
 void gj_coarse(double *A, int n, int64_t ld, double *C0, int *status, int *iwork, hipStream_t st);
-// W_k[c * o_k + r] = Binv_k[own_row_r][c] (column-major owned rows), optional FP32/16-bit copies
+// W_k[c * o_k + r] = Binv_k[own_row_r][c] (column-major owned rows), optional
+// FP32/16-bit copies; one workgroup per (patch, 64 owned rows) task
 void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm, const int *po,
-                       const int64_t *woff, const int *own_off, const int *own_local, int npatch,
-                       int64_t total_owned, const int *orow_patch, const int *orow_r, double *W64,
+                       const int64_t *woff, const int *own_off, const int *own_local,
+                       const int *task_patch, const int *task_row0, int ntask, double *W64,
                        float *W32, uint16_t *W16, int w16_kind, float *wscale,
                        const int64_t *pdof_off, const float *cscale, const int *perm,
                        const int *used, hipStream_t st);
 // 16-bit storage: per-column scales of the owned rows of every block inverse
 void launch_colscale(const double *blocks, const int64_t *boff, const int *pm, const int *po,
                      const int *own_off, const int *own_local, const int64_t *pdof_off,
-                     int64_t total_cols, const int *col_patch, const int *col_local, float *cscale,
-                     const int *perm, const int *used, hipStream_t st);
+                     const int *task_patch, const int *task_row0, int ntask, int64_t total_cols,
+                     float *cscale, const int *perm, hipStream_t st);
 
 // ---- smoother (a5): e[out] += omega * W_k s[I_k] for every owned row
 //      (16-bit: W_k = diag(rs) W16 diag(cs), two-sided scaling)

@@ -185,10 +185,62 @@ __device__ inline float from_fp16(uint16_t u) {
   return __half2float(h);
 }
 
-// one wave per owned row: W[c * o + r] = Binv[own_local[r]][c]; 16-bit rows scaled by max |.|.
-// The Gauss-Jordan result S holds Binv up to its pivot permutations:
-// Binv[i][c] = S[perm[i]][used[c]] (per-patch arrays at pdof_off[k]).
+// The Gauss-Jordan result S holds every block inverse up to its pivot
+// permutations: Binv[i][c] = S[perm[i]][used[c]], equivalently physical
+// column p of S is logical column perm[p] (per-patch arrays at pdof_off[k]).
 
+// Column scales of the owned rows of every block inverse (16-bit storage):
+// cs[c] = max over owned rows r of |Binv[r][c]| (cscale zeroed beforehand).
+// One workgroup per (patch, 64 owned rows): the rows are read contiguously,
+// the maxima meet in LDS (float bit patterns order like the non-negative
+// values) and then in cscale.
+__global__ __launch_bounds__(256) void k_colscale(const double *__restrict__ blocks,
+                                                  const int64_t *__restrict__ boff,
+                                                  const int *__restrict__ pm,
+                                                  const int *__restrict__ po,
+                                                  const int *__restrict__ own_off,
+                                                  const int *__restrict__ own_local,
+                                                  const int64_t *__restrict__ pdof_off,
+                                                  const int *__restrict__ task_patch,
+                                                  const int *__restrict__ task_row0, float *cscale,
+                                                  const int *__restrict__ perm) {
+  __shared__ unsigned cmax[kMaxPatch];
+  const int k = task_patch[blockIdx.x], r0 = task_row0[blockIdx.x];
+  const int m = pm[k], nr = min(64, po[k] - r0);
+  const int *pk = perm + pdof_off[k];
+  const double *B = blocks + boff[k];
+  for (int c = threadIdx.x; c < m; c += blockDim.x) cmax[c] = 0u;
+  __syncthreads();
+  for (int r = 0; r < nr; ++r) {
+    const double *row = B + (int64_t)pk[own_local[own_off[k] + r0 + r]] * m;
+    for (int p = threadIdx.x; p < m; p += blockDim.x)
+      atomicMax(&cmax[pk[p]], __float_as_uint((float)fabs(row[p])));
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < m; c += blockDim.x)
+    atomicMax(reinterpret_cast<unsigned *>(cscale + pdof_off[k]) + c, cmax[c]);
+}
+// columns with no nonzero owned entry get scale 1
+__global__ void k_scale_fix(float *cs, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n && !(cs[i] > 0.0f)) cs[i] = 1.0f;
+}
+void launch_colscale(const double *blocks, const int64_t *boff, const int *pm, const int *po,
+                     const int *own_off, const int *own_local, const int64_t *pdof_off,
+                     const int *task_patch, const int *task_row0, int ntask, int64_t total_cols,
+                     float *cscale, const int *perm, hipStream_t st) {
+  if (ntask == 0) return;
+  launch_fill_f32(cscale, total_cols, 0.0f, st);
+  k_colscale<<<ntask, 256, 0, st>>>(blocks, boff, pm, po, own_off, own_local, pdof_off, task_patch,
+                                    task_row0, cscale, perm);
+  k_scale_fix<<<cdiv(total_cols, 256), 256, 0, st>>>(cscale, total_cols);
+}
+
+// W_k[c * o + r] = Binv_k[own_r][c], column-major owned rows.  One workgroup
+// per (patch, 64 owned rows): 64 columns at a time are gathered through the
+// permutations into an LDS tile and written with consecutive owned rows in
+// consecutive lanes (coalesced stores).  16-bit storage: row r is stored
+// divided by cs[c] and by its row scale, the largest |Binv[r][c]| / cs[c].
 __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ blocks,
                                                     const int64_t *__restrict__ boff,
                                                     const int *__restrict__ pm,
@@ -196,84 +248,71 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
                                                     const int64_t *__restrict__ woff,
                                                     const int *__restrict__ own_off,
                                                     const int *__restrict__ own_local,
-                                                    int64_t total_owned,
-                                                    const int *__restrict__ orow_patch,
-                                                    const int *__restrict__ orow_r, double *W64,
+                                                    const int *__restrict__ task_patch,
+                                                    const int *__restrict__ task_row0, double *W64,
                                                     float *W32, uint16_t *W16, int w16_kind,
                                                     float *wscale, const int64_t *__restrict__ pdof_off,
                                                     const float *__restrict__ cscale,
                                                     const int *__restrict__ perm,
                                                     const int *__restrict__ used) {
-  const int64_t t = blockIdx.x * 4 + threadIdx.x / 64;
-  const int lane = threadIdx.x % 64;
-  if (t >= total_owned) return;
-  const int k = orow_patch[t];
-  const int r = orow_r[t];
-  const int m = pm[k], o = po[k];
+  __shared__ double tile[64][65];
+  __shared__ int64_t rowoff[64];
+  __shared__ double rsc[64];
+  const int k = task_patch[blockIdx.x], r0 = task_row0[blockIdx.x];
+  const int m = pm[k], o = po[k], nr = min(64, o - r0);
   const int *pk = perm + pdof_off[k], *uk = used + pdof_off[k];
-  const double *row = blocks + boff[k] + (int64_t)pk[own_local[own_off[k] + r]] * m;
-  const float *cs = W16 ? cscale + pdof_off[k] : nullptr;
-  double mx = 0.0;
-  if (W16) {
-    for (int c = lane; c < m; c += 64) mx = fmax(mx, fabs(row[uk[c]]) / (double)cs[c]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-    if (mx == 0.0) mx = 1.0;
-    if (lane == 0) wscale[own_off[k] + r] = (float)mx;
-  }
-  for (int c = lane; c < m; c += 64) {
-    const int64_t dst = woff[k] + (int64_t)c * o + r;
-    const double v = row[uk[c]];
-    if (W64) W64[dst] = v;
-    if (W32) W32[dst] = (float)v;
-    if (W16) {
-      const float q = (float)(v / ((double)cs[c] * mx));
-      W16[dst] = w16_kind == 1 ? to_bf16(q) : to_fp16(q);
-    }
-  }
-}
-
-// column scales of the owned rows of every block inverse: cs = max_r |Binv[own_r][c]|
-__global__ void k_colscale(const double *__restrict__ blocks, const int64_t *__restrict__ boff,
-                           const int *__restrict__ pm, const int *__restrict__ po,
-                           const int *__restrict__ own_off, const int *__restrict__ own_local,
-                           const int64_t *__restrict__ pdof_off, int64_t total_cols,
-                           const int *__restrict__ col_patch, const int *__restrict__ col_local,
-                           float *cscale, const int *__restrict__ perm,
-                           const int *__restrict__ used) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= total_cols) return;
-  const int k = col_patch[t], c = col_local[t];
-  const int m = pm[k], o = po[k];
   const double *B = blocks + boff[k];
-  double mx = 0.0;
-  const int *pk = perm + pdof_off[k];
-  const int uc = used[pdof_off[k] + c];
-  for (int r = 0; r < o; ++r) mx = fmax(mx, fabs(B[(int64_t)pk[own_local[own_off[k] + r]] * m + uc]));
-  cscale[pdof_off[k] + c] = mx > 0.0 ? (float)mx : 1.0f;
+  const float *cs = W16 ? cscale + pdof_off[k] : nullptr;
+  const int tid = threadIdx.x;
+  if (tid < 64) rowoff[tid] = tid < nr ? (int64_t)pk[own_local[own_off[k] + r0 + tid]] * m : 0;
+  __syncthreads();
+  if (W16) {
+    const int r = tid >> 2, sub = tid & 3;   // 4 threads per row
+    double mx = 0.0;
+    if (r < nr)
+      for (int c = sub; c < m; c += 4) mx = fmax(mx, fabs(B[rowoff[r] + uk[c]]) / (double)cs[c]);
+    mx = fmax(mx, __shfl_xor(mx, 1, 4));
+    mx = fmax(mx, __shfl_xor(mx, 2, 4));
+    if (mx == 0.0) mx = 1.0;
+    if (sub == 0 && r < nr) {
+      rsc[r] = mx;
+      wscale[own_off[k] + r0 + r] = (float)mx;
+    }
+    __syncthreads();
+  }
+  const int64_t wk = woff[k];
+  for (int c0 = 0; c0 < m; c0 += 64) {
+    for (int idx = tid; idx < 64 * 64; idx += 256) {
+      const int r = idx >> 6, c = idx & 63;
+      if (r < nr && c0 + c < m) tile[r][c] = B[rowoff[r] + uk[c0 + c]];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 64 * 64; idx += 256) {
+      const int c = idx >> 6, r = idx & 63;
+      if (r < nr && c0 + c < m) {
+        const double v = tile[r][c];
+        const int64_t dst = wk + (int64_t)(c0 + c) * o + r0 + r;
+        if (W64) W64[dst] = v;
+        if (W32) W32[dst] = (float)v;
+        if (W16) {
+          const float q = (float)(v / ((double)cs[c0 + c] * rsc[r]));
+          W16[dst] = w16_kind == 1 ? to_bf16(q) : to_fp16(q);
+        }
+      }
+    }
+    __syncthreads();
+  }
 }
-void launch_colscale(const double *blocks, const int64_t *boff, const int *pm, const int *po,
-                     const int *own_off, const int *own_local, const int64_t *pdof_off,
-                     int64_t total_cols, const int *col_patch, const int *col_local, float *cscale,
-                     const int *perm, const int *used, hipStream_t st) {
-  if (total_cols == 0) return;
-  k_colscale<<<cdiv(total_cols, 256), 256, 0, st>>>(blocks, boff, pm, po, own_off, own_local,
-                                                     pdof_off, total_cols, col_patch, col_local,
-                                                     cscale, perm, used);
-}
-
 void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm, const int *po,
-                       const int64_t *woff, const int *own_off, const int *own_local, int npatch,
-                       int64_t total_owned, const int *orow_patch, const int *orow_r, double *W64,
+                       const int64_t *woff, const int *own_off, const int *own_local,
+                       const int *task_patch, const int *task_row0, int ntask, double *W64,
                        float *W32, uint16_t *W16, int w16_kind, float *wscale,
                        const int64_t *pdof_off, const float *cscale, const int *perm,
                        const int *used, hipStream_t st) {
-  (void)npatch;
-  if (total_owned == 0) return;
-  k_pack_owned<<<cdiv(total_owned, 4), 256, 0, st>>>(blocks, boff, pm, po, woff, own_off,
-                                                      own_local, total_owned, orow_patch, orow_r,
-                                                      W64, W32, W16, w16_kind, wscale, pdof_off,
-                                                      cscale, perm, used);
+  if (ntask == 0) return;
+  k_pack_owned<<<ntask, 256, 0, st>>>(blocks, boff, pm, po, woff, own_off, own_local, task_patch,
+                                      task_row0, W64, W32, W16, w16_kind, wscale, pdof_off, cscale,
+                                      perm, used);
 }
 
 // ------------------------------------------------------------------ restricted Schwarz

@@ -127,7 +127,7 @@ static void build_patch_layout(Level &L, const fsi_patches &P, MG &mg, hipStream
   if (P.kind) L.h_kind.assign(P.kind, P.kind + np);
   std::vector<int> pm(np), po(np), out_off(np + 1, 0), own_local, out_idx, task_patch, task_row0;
   std::vector<int64_t> pdof_off(np), woff(np + 1, 0), boff(np + 1, 0);
-  std::vector<int> row_patch, row_local, orow_patch, orow_r;
+  std::vector<int> row_patch, row_local;
   L.mmax = 0;
   L.sum_m = L.sum_m2 = L.sum_om = 0;
   for (int k = 0; k < np; ++k) {
@@ -139,8 +139,6 @@ static void build_patch_layout(Level &L, const fsi_patches &P, MG &mg, hipStream
       if (P.owned[p]) {
         own_local.push_back((int)(p - a));
         out_idx.push_back(P.dof[p]);
-        orow_patch.push_back(k);
-        orow_r.push_back(o);
         ++o;
       }
     po[k] = o;
@@ -176,8 +174,6 @@ static void build_patch_layout(Level &L, const fsi_patches &P, MG &mg, hipStream
   L.d_task_row0 = dupload(task_row0.data(), (int64_t)task_row0.size(), own, st);
   L.d_row_patch = dupload(row_patch.data(), (int64_t)row_patch.size(), own, st);
   L.d_row_local = dupload(row_local.data(), (int64_t)row_local.size(), own, st);
-  L.d_orow_patch = dupload(orow_patch.data(), (int64_t)orow_patch.size(), own, st);
-  L.d_orow_r = dupload(orow_r.data(), (int64_t)orow_r.size(), own, st);
   L.boff_total = boff[np];
   L.woff_total = woff[np];
   L.h_boff = boff;
@@ -222,11 +218,11 @@ static void pack_level(MG &mg, Level &L, hipStream_t st) {
     }
     L.w16_kind = prec == FSI_PREC_MIXED_BF16 ? 1 : 2;
     launch_colscale(B, L.d_boff, L.d_pm, L.d_po, L.d_out_off, L.d_own_local, L.d_pdof_off,
-                    L.sum_m, L.d_row_patch, L.d_row_local, L.Cscale, mg.gj_perm + L.pm_base,
-                    mg.gj_used + L.pm_base, st);
+                    L.d_task_patch, L.d_task_row0, L.ntask, L.sum_m, L.Cscale, mg.gj_perm + L.pm_base,
+                    st);
   }
-  launch_pack_owned(B, L.d_boff, L.d_pm, L.d_po, L.d_woff, L.d_out_off, L.d_own_local, L.npatch,
-                    L.total_owned, L.d_orow_patch, L.d_orow_r, L.W64, L.W32, L.W16, L.w16_kind,
+  launch_pack_owned(B, L.d_boff, L.d_pm, L.d_po, L.d_woff, L.d_out_off, L.d_own_local,
+                    L.d_task_patch, L.d_task_row0, L.ntask, L.W64, L.W32, L.W16, L.w16_kind,
                     L.Wscale, L.d_pdof_off, L.Cscale, mg.gj_perm + L.pm_base, mg.gj_used + L.pm_base,
                     st);
   hip_check(hipGetLastError(), "pack launch");
