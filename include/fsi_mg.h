@@ -51,10 +51,10 @@ enum {
 
 /* Precision of the V-cycle (the Krylov method, the true residual and the
  * coarsest solve are always FP64).  MIXED_*: V-cycle vectors, operators and
- * transfers in FP32; the owned rows of every block inverse stored in the
- * named 16-bit type (per-row FP32 scale) and applied with FP32
- * accumulation, followed by `refine_sweeps` FP32 refinement sweeps of the
- * local solve; MIXED_FP32: block inverses stored in FP32. */
+ * transfers in FP32; the block inverses are computed in FP64 and their owned
+ * rows stored in the named 16-bit type with two-sided FP32 scaling
+ * (B^{-1} = diag(rs) W diag(cs)) and applied with FP32 accumulation;
+ * MIXED_FP32: owned rows stored in FP32. */
 enum { FSI_PREC_FP64 = 0, FSI_PREC_MIXED_BF16 = 1, FSI_PREC_MIXED_FP16 = 2, FSI_PREC_MIXED_FP32 = 3 };
 
 typedef struct {
@@ -86,8 +86,11 @@ typedef struct {
   int32_t nu_pre, nu_post; /* Richardson sweeps before / after the coarse correction */
   double omega;            /* Richardson damping (the paper uses 0.7) */
   int32_t precision;       /* FSI_PREC_* */
-  int32_t solid_precision; /* precision of solid patches; -1 = same as `precision` */
-  int32_t refine_sweeps;   /* mixed only: FP32 refinement sweeps of each local solve */
+  int32_t solid_precision; /* reserved: -1 or equal to `precision` (one precision per
+                              hierarchy); other values are rejected (FSI_E_INVALID) */
+  int32_t refine_sweeps;   /* reserved: must be 0 (no per-block refinement; the outer
+                              Richardson and FGMRES iterations correct the rounding of
+                              the stored inverse rows); other values are rejected */
   int32_t use_graph;       /* capture the V-cycle in a hipGraph */
 } fsi_mg_opts;
 

@@ -445,6 +445,10 @@ void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *op
   if (opts->nu_pre < 0 || opts->nu_post < 0 || !(opts->omega > 0.0) ||
       opts->precision < FSI_PREC_FP64 || opts->precision > FSI_PREC_MIXED_FP32)
     throw Error(FSI_E_INVALID, "invalid multigrid options");
+  if (opts->solid_precision != -1 && opts->solid_precision != opts->precision)
+    throw Error(FSI_E_INVALID, "solid_precision must be -1 or equal to precision");
+  if (opts->refine_sweeps != 0)
+    throw Error(FSI_E_INVALID, "refine_sweeps must be 0 (no per-block refinement)");
   std::vector<int64_t> n(nlevels);
   for (int l = 0; l < nlevels; ++l) n[l] = levels[l].J.nrows;
   if (n[0] > kMaxCoarse) {

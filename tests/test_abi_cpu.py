@@ -142,6 +142,11 @@ def test_setup_validation_errors_are_reported_on_the_host():
     # 4. bad options
     st, msg = _setup_status(p.levels, L, omega=-1.0)
     assert st == -1
+    # 5. reserved options
+    st, msg = _setup_status(p.levels, L, precision="bf16", refine_sweeps=1)
+    assert st == -1 and "refine_sweeps" in msg
+    st, msg = _setup_status(p.levels, L, precision="bf16", solid_precision="fp32")
+    assert st == -1 and "solid_precision" in msg
 
 
 def test_server_rejects_oversized_request():
