@@ -8,6 +8,7 @@ namespace fsi {
 constexpr int kWave = 64;
 constexpr int kMaxPatch = 800;      // largest Schwarz block handled by one wave's LDS slice
 constexpr int kMdotBlocks = 256;    // fixed number of partial sums in the Krylov reductions
+constexpr int kGemvSplit = 32;      // column chunks of the coarsest GEMV (partial buffer: kGemvSplit n)
 
 // CSR on the device: int32 offsets and columns (sizes checked at upload).
 template <typename T>
@@ -50,7 +51,7 @@ void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm,
                        const int *task_patch, const int *task_row0, int ntask, double *W64,
                        float *W32, uint16_t *W16, int w16_kind, float *wscale,
                        const int64_t *pdof_off, const float *cscale, const int *perm,
-                       const int *used, hipStream_t st);
+                       hipStream_t st);
 // 16-bit storage: per-column scales of the owned rows of every block inverse
 void launch_colscale(const double *blocks, const int64_t *boff, const int *pm, const int *po,
                      const int *own_off, const int *own_local, const int64_t *pdof_off,

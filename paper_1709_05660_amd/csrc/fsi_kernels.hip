@@ -11,6 +11,7 @@
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 namespace fsi {
@@ -18,6 +19,35 @@ namespace fsi {
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // ------------------------------------------------------------------ SpMV
+// Sum over a group of LPR consecutive lanes, the total in every lane of the
+// group: DPP within rows of 16 lanes (quad swaps, then the half-row and row
+// mirrors), cross-lane shuffles only for groups of 32 and 64.
+template <typename T, int LPR>
+__device__ __forceinline__ T group_sum(T v) {
+  auto dpp = [](T x, auto ctrl) {
+    if constexpr (sizeof(T) == 8) {
+      const long long b = __double_as_longlong(x);
+      const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, decltype(ctrl)::value, 0xF, 0xF, false);
+      const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), decltype(ctrl)::value, 0xF, 0xF, false);
+      return (T)__longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    } else {
+      return (T)__int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),
+                                                            decltype(ctrl)::value, 0xF, 0xF, false));
+    }
+  };
+  if constexpr (LPR >= 2) v += dpp(v, std::integral_constant<int, 0xB1>{});   // quad_perm [1,0,3,2]
+  if constexpr (LPR >= 4) v += dpp(v, std::integral_constant<int, 0x4E>{});   // quad_perm [2,3,0,1]
+  if constexpr (LPR >= 8) v += dpp(v, std::integral_constant<int, 0x141>{});  // row_half_mirror
+  if constexpr (LPR >= 16) v += dpp(v, std::integral_constant<int, 0x140>{}); // row_mirror
+  if constexpr (LPR >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (LPR >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// LPR lanes per row; each lane takes the row's entries lane, lane + LPR, ...
+// four at a time (their column and value loads issued together), summing
+// in the same order as a one-at-a-time loop.  Whole rows leave together, so
+// every group reduces with all its lanes active.
 template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_spmv(int nrows, const int *__restrict__ rowptr,
                                               const int *__restrict__ col,
@@ -27,13 +57,23 @@ __global__ __launch_bounds__(256) void k_spmv(int nrows, const int *__restrict__
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int row = gid / LPR;
   const int lane = gid % LPR;
-  if (row >= nrows) return;  // whole lane group leaves together
-  const int beg = rowptr[row], end = rowptr[row + 1];
+  const bool live = row < nrows;
   T acc = 0;
-  for (int p = beg + lane; p < end; p += LPR) acc += val[p] * x[col[p]];
-#pragma unroll
-  for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
-  if (lane == 0) {
+  if (live) {
+    const int beg = rowptr[row], end = rowptr[row + 1];
+    int p = beg + lane;
+    for (; p + 3 * LPR < end; p += 4 * LPR) {
+      const int c0 = col[p], c1 = col[p + LPR], c2 = col[p + 2 * LPR], c3 = col[p + 3 * LPR];
+      const T v0 = val[p], v1 = val[p + LPR], v2 = val[p + 2 * LPR], v3 = val[p + 3 * LPR];
+      acc += v0 * x[c0];
+      acc += v1 * x[c1];
+      acc += v2 * x[c2];
+      acc += v3 * x[c3];
+    }
+    for (; p < end; p += LPR) acc += val[p] * x[col[p]];
+  }
+  acc = group_sum<T, LPR>(acc);
+  if (live && lane == 0) {
     if (mode == kSpmvSet)
       y[row] = acc;
     else if (mode == kSpmvResid)
@@ -237,10 +277,12 @@ void launch_colscale(const double *blocks, const int64_t *boff, const int *pm, c
 }
 
 // W_k[c * o + r] = Binv_k[own_r][c], column-major owned rows.  One workgroup
-// per (patch, 64 owned rows): 64 columns at a time are gathered through the
-// permutations into an LDS tile and written with consecutive owned rows in
-// consecutive lanes (coalesced stores).  16-bit storage: row r is stored
-// divided by cs[c] and by its row scale, the largest |Binv[r][c]| / cs[c].
+// per (patch, 64 owned rows), 64 physical columns p of S at a time: the
+// rows' segments are read in order into an LDS tile, and column p is written
+// to logical column c = perm[p] with consecutive owned rows in consecutive
+// lanes, so both the reads and the stores are contiguous.  16-bit storage:
+// row r is stored divided by cs[c] and by its row scale, the largest
+// |Binv[r][c]| / cs[c] of the row.
 __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ blocks,
                                                     const int64_t *__restrict__ boff,
                                                     const int *__restrict__ pm,
@@ -253,14 +295,13 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
                                                     float *W32, uint16_t *W16, int w16_kind,
                                                     float *wscale, const int64_t *__restrict__ pdof_off,
                                                     const float *__restrict__ cscale,
-                                                    const int *__restrict__ perm,
-                                                    const int *__restrict__ used) {
+                                                    const int *__restrict__ perm) {
   __shared__ double tile[64][65];
   __shared__ int64_t rowoff[64];
   __shared__ double rsc[64];
   const int k = task_patch[blockIdx.x], r0 = task_row0[blockIdx.x];
   const int m = pm[k], o = po[k], nr = min(64, o - r0);
-  const int *pk = perm + pdof_off[k], *uk = used + pdof_off[k];
+  const int *pk = perm + pdof_off[k];
   const double *B = blocks + boff[k];
   const float *cs = W16 ? cscale + pdof_off[k] : nullptr;
   const int tid = threadIdx.x;
@@ -270,7 +311,7 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
     const int r = tid >> 2, sub = tid & 3;   // 4 threads per row
     double mx = 0.0;
     if (r < nr)
-      for (int c = sub; c < m; c += 4) mx = fmax(mx, fabs(B[rowoff[r] + uk[c]]) / (double)cs[c]);
+      for (int p = sub; p < m; p += 4) mx = fmax(mx, fabs(B[rowoff[r] + p]) / (double)cs[pk[p]]);
     mx = fmax(mx, __shfl_xor(mx, 1, 4));
     mx = fmax(mx, __shfl_xor(mx, 2, 4));
     if (mx == 0.0) mx = 1.0;
@@ -281,21 +322,22 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
     __syncthreads();
   }
   const int64_t wk = woff[k];
-  for (int c0 = 0; c0 < m; c0 += 64) {
+  for (int q0 = 0; q0 < m; q0 += 64) {
     for (int idx = tid; idx < 64 * 64; idx += 256) {
-      const int r = idx >> 6, c = idx & 63;
-      if (r < nr && c0 + c < m) tile[r][c] = B[rowoff[r] + uk[c0 + c]];
+      const int r = idx >> 6, p = idx & 63;
+      if (r < nr && q0 + p < m) tile[r][p] = B[rowoff[r] + q0 + p];
     }
     __syncthreads();
     for (int idx = tid; idx < 64 * 64; idx += 256) {
-      const int c = idx >> 6, r = idx & 63;
-      if (r < nr && c0 + c < m) {
-        const double v = tile[r][c];
-        const int64_t dst = wk + (int64_t)(c0 + c) * o + r0 + r;
+      const int p = idx >> 6, r = idx & 63;
+      if (r < nr && q0 + p < m) {
+        const int c = pk[q0 + p];
+        const double v = tile[r][p];
+        const int64_t dst = wk + (int64_t)c * o + r0 + r;
         if (W64) W64[dst] = v;
         if (W32) W32[dst] = (float)v;
         if (W16) {
-          const float q = (float)(v / ((double)cs[c0 + c] * rsc[r]));
+          const float q = (float)(v / ((double)cs[c] * rsc[r]));
           W16[dst] = w16_kind == 1 ? to_bf16(q) : to_fp16(q);
         }
       }
@@ -308,11 +350,11 @@ void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm,
                        const int *task_patch, const int *task_row0, int ntask, double *W64,
                        float *W32, uint16_t *W16, int w16_kind, float *wscale,
                        const int64_t *pdof_off, const float *cscale, const int *perm,
-                       const int *used, hipStream_t st) {
+                       hipStream_t st) {
   if (ntask == 0) return;
   k_pack_owned<<<ntask, 256, 0, st>>>(blocks, boff, pm, po, woff, own_off, own_local, task_patch,
                                       task_row0, W64, W32, W16, w16_kind, wscale, pdof_off, cscale,
-                                      perm, used);
+                                      perm);
 }
 
 // ------------------------------------------------------------------ restricted Schwarz
@@ -415,7 +457,6 @@ void launch_ras_16(const RasView &v, const uint16_t *W, int w16_kind, const floa
 }
 
 // ------------------------------------------------------------------ coarsest solve GEMV
-constexpr int kGemvSplit = 8;
 __global__ __launch_bounds__(256) void k_gemv_partial(const double *__restrict__ W, int n,
                                                       const double *__restrict__ x,
                                                       double *__restrict__ partial) {

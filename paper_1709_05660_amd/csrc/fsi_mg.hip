@@ -223,8 +223,7 @@ static void pack_level(MG &mg, Level &L, hipStream_t st) {
   }
   launch_pack_owned(B, L.d_boff, L.d_pm, L.d_po, L.d_woff, L.d_out_off, L.d_own_local,
                     L.d_task_patch, L.d_task_row0, L.ntask, L.W64, L.W32, L.W16, L.w16_kind,
-                    L.Wscale, L.d_pdof_off, L.Cscale, mg.gj_perm + L.pm_base, mg.gj_used + L.pm_base,
-                    st);
+                    L.Wscale, L.d_pdof_off, L.Cscale, mg.gj_perm + L.pm_base, st);
   hip_check(hipGetLastError(), "pack launch");
 }
 
@@ -527,7 +526,7 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
     mg->dense_scratch = dalloc<double>(n0 * mg->dense_ld, mg->owned);
     mg->gj_work = dalloc<double>(n0 + 64, mg->owned);
     mg->lv[0].C0 = dalloc<double>(n0 * n0, mg->owned);
-    mg->lv[0].gemv_partial = dalloc<double>(8 * n0, mg->owned);
+    mg->lv[0].gemv_partial = dalloc<double>((int64_t)kGemvSplit * n0, mg->owned);
     hip_check(hipStreamCreateWithFlags(&mg->side_stream, hipStreamNonBlocking), "side stream");
     hip_check(hipEventCreateWithFlags(&mg->ev_fork, hipEventDisableTiming), "event");
     hip_check(hipEventCreateWithFlags(&mg->ev_join, hipEventDisableTiming), "event");
