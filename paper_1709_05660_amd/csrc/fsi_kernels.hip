@@ -310,8 +310,10 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
   if (W16) {
     const int r = tid >> 2, sub = tid & 3;   // 4 threads per row
     double mx = 0.0;
-    if (r < nr)
+    if (r < nr) {
+#pragma unroll 8
       for (int p = sub; p < m; p += 4) mx = fmax(mx, fabs(B[rowoff[r] + p]) / (double)cs[pk[p]]);
+    }
     mx = fmax(mx, __shfl_xor(mx, 1, 4));
     mx = fmax(mx, __shfl_xor(mx, 2, 4));
     if (mx == 0.0) mx = 1.0;
@@ -323,9 +325,18 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
   }
   const int64_t wk = woff[k];
   for (int q0 = 0; q0 < m; q0 += 64) {
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
-      const int r = idx >> 6, p = idx & 63;
-      if (r < nr && q0 + p < m) tile[r][p] = B[rowoff[r] + q0 + p];
+    // all 16 loads of a thread in flight together; clamped addresses (the
+    // entries past the block are never stored)
+    double vals[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = tid + 256 * u;
+      vals[u] = B[rowoff[min(idx >> 6, nr - 1)] + min(q0 + (idx & 63), m - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = tid + 256 * u;
+      tile[idx >> 6][idx & 63] = vals[u];
     }
     __syncthreads();
     for (int idx = tid; idx < 64 * 64; idx += 256) {
@@ -515,16 +526,24 @@ void launch_mdot(int n, const double *V, int64_t ldv, int k, const double *w, do
                  int ldp, hipStream_t st) {
   k_mdot<<<kMdotBlocks, 256, 0, st>>>(n, V, ldv, k, w, partial, ldp);
 }
-__global__ void k_mdot_finish(const double *partial, int ldp, int k, double *out, int acc) {
-  const int i = threadIdx.x;
-  if (i >= k) return;
-  double s = 0.0;
-  for (int b = 0; b < kMdotBlocks; ++b) s += partial[(int64_t)b * ldp + i];
-  out[i] = acc ? out[i] + s : s;
+// out[i] (=, or += with acc) sum over the kMdotBlocks partials of column i:
+// wave w takes columns w, w + 4, ...; lane l adds partials l, l + 64, ...
+// in order, then a fixed butterfly over the wave (a deterministic order)
+__global__ __launch_bounds__(256) void k_mdot_finish(const double *partial, int ldp, int k,
+                                                     double *out, int acc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < k; i += 4) {
+    double s = 0.0;
+#pragma unroll
+    for (int b = lane; b < kMdotBlocks; b += 64) s += partial[(int64_t)b * ldp + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) out[i] = acc ? out[i] + s : s;
+  }
 }
 void launch_mdot_finish(const double *partial, int ldp, int k, double *out, int accumulate,
                         hipStream_t st) {
-  k_mdot_finish<<<1, 64, 0, st>>>(partial, ldp, k, out, accumulate);
+  k_mdot_finish<<<1, 256, 0, st>>>(partial, ldp, k, out, accumulate);
 }
 
 __global__ __launch_bounds__(256) void k_mupdate(int n, const double *__restrict__ V, int64_t ldv,
