@@ -103,7 +103,7 @@ struct PivotLds {
 // Returns 0 or 1 + the failing step, uniformly.
 template <int NB, int R, int NT>
 __device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int m, int p0, int t,
-                                          int col, PivotLds<NB, NT / 64> &sh) {
+                                          int col, PivotLds<NB, NT / 64> &sh, int &mypiv) {
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int buf = t & 1;
@@ -157,6 +157,7 @@ __device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int
   const int gw = cw[0];
   if (!(g.v > 0.0) || isinf(g.v)) return p0 + t + 1;
   if (tid == 0) sh.piv[t] = g.i;
+  if (tid == t) mypiv = g.i;
   const double *prow = sh.row[buf][gw];
   const double d = sh.dinv[buf][gw];
   // every row is eliminated with one FMA per column, v - (f d) prow, then
@@ -181,7 +182,8 @@ __device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int
 // Factors the panel of columns [p0, p0 + w) of an m-row matrix whose rows
 // tid + q * NT sit in v[q][0..NB) (columns beyond w are zero; rows beyond m
 // are never candidates); stp[q] is the step at which that row became a
-// pivot (< 0: not yet; rows beyond m carry kNoRow).  UNR: the NB steps are
+// pivot (< 0: not yet; rows beyond m carry kNoRow).  Thread t receives the
+// pivot row of step t in mypiv.  UNR: the NB steps are
 // unrolled and step t works on the static column t.  Otherwise the step loop
 // is rolled: the current pivot column is always v[q][0] and each step
 // rotates the row left by one column (every register index stays static),
@@ -190,18 +192,18 @@ __device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int
 // (the same value in every thread).
 template <int NB, int R, int NT, bool UNR>
 __device__ __forceinline__ int reg_panel(double (&v)[R][NB], int (&stp)[R], int m, int p0, int w,
-                                         PivotLds<NB, NT / 64> &sh) {
+                                         PivotLds<NB, NT / 64> &sh, int &mypiv) {
   if constexpr (UNR) {
 #pragma unroll
     for (int t = 0; t < NB; ++t)
       if (t < w) {
-        const int f = pivot_step<NB, R, NT>(v, stp, m, p0, t, t, sh);
+        const int f = pivot_step<NB, R, NT>(v, stp, m, p0, t, t, sh, mypiv);
         if (f) return f;
       }
   } else {
     for (int t = 0; t < NB; ++t) {
       if (t < w) {
-        const int f = pivot_step<NB, R, NT>(v, stp, m, p0, t, 0, sh);
+        const int f = pivot_step<NB, R, NT>(v, stp, m, p0, t, 0, sh, mypiv);
         if (f) return f;
       }
 #pragma unroll
@@ -268,7 +270,8 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
 #pragma unroll
         for (int c = 0; c < NB; ++c)
           if (c >= w) v[q][c] = 0.0;
-      fail = reg_panel<NB, R, NT, UNR>(v, stp, m, p0, w, sh);
+      int mypiv = 0;   // unused here: the update reads the pivots from LDS
+      fail = reg_panel<NB, R, NT, UNR>(v, stp, m, p0, w, sh, mypiv);
       if (fail) break;
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -404,32 +407,46 @@ void launch_fill_i32(int *x, int n, int v, hipStream_t st) {
   if (n > 0) k_fill_i32<<<cdivg(n, 256), 256, 0, st>>>(x, n, v);
 }
 
-// Factors the panel of columns [p0, p0 + w) of the coarse matrix (all NT
-// threads of the workgroup; rows tid + q NT in registers).  p0 + NB <= ld
-// (ld is a multiple of 16 and NB divides 16): a row's panel slice is loaded
-// whole from one base address; rows beyond n repeat row n - 1 and are never
-// candidates.  On failure status[0] = 1 + the failing step.
+// The coarse matrix's panel [p0, p0 + w) into registers: rows tid + q NT,
+// loaded whole from their base (p0 + NB <= ld: ld is a multiple of 16 and
+// NB divides 16; 16-byte accesses since ld and p0 are multiples of 2); rows
+// beyond n repeat row n - 1 and are never candidates.
 template <int NB, int R, int NT>
-__device__ __forceinline__ void cgj_factor(double *__restrict__ A, int n, int64_t ld, int p0,
-                                           int w, int *__restrict__ perm, int *__restrict__ used,
-                                           int *__restrict__ status, PivotLds<NB, NT / 64> &sh) {
+__device__ __forceinline__ void cgj_load(const double *__restrict__ A, int n, int64_t ld, int p0,
+                                         int w, const int *__restrict__ used, double (&v)[R][NB],
+                                         int (&stp)[R]) {
   const int tid = threadIdx.x;
-  double v[R][NB];
-  int stp[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int i = tid + q * NT;
     stp[q] = i < n ? used[i] : kNoRow;
-    const double *row = A + (int64_t)min(i, n - 1) * ld + p0;
+    const double2 *row = reinterpret_cast<const double2 *>(A + (int64_t)min(i, n - 1) * ld + p0);
 #pragma unroll
-    for (int c = 0; c < NB; ++c) v[q][c] = row[c];
+    for (int c = 0; c < NB / 2; ++c) {
+      const double2 x = row[c];
+      v[q][2 * c] = x.x;
+      v[q][2 * c + 1] = x.y;
+    }
   }
 #pragma unroll
   for (int q = 0; q < R; ++q)
 #pragma unroll
     for (int c = 0; c < NB; ++c)
       if (c >= w) v[q][c] = 0.0;
-  const int f = reg_panel<NB, R, NT, true>(v, stp, n, p0, w, sh);
+}
+
+// Factors the loaded panel (all NT threads of the workgroup), stores it,
+// marks its pivot rows in used[] and writes perm[p0 ...] from the threads
+// that hold them (no barrier after the stores).  On failure status[0] =
+// 1 + the failing step.
+template <int NB, int R, int NT>
+__device__ __forceinline__ void cgj_factor(double *__restrict__ A, int n, int64_t ld, int p0,
+                                           int w, int *__restrict__ perm, int *__restrict__ used,
+                                           int *__restrict__ status, PivotLds<NB, NT / 64> &sh,
+                                           double (&v)[R][NB], int (&stp)[R]) {
+  const int tid = threadIdx.x;
+  int mypiv = 0;
+  const int f = reg_panel<NB, R, NT, true>(v, stp, n, p0, w, sh, mypiv);
   if (f) {
     if (tid == 0) status[0] = f;
     return;
@@ -439,14 +456,19 @@ __device__ __forceinline__ void cgj_factor(double *__restrict__ A, int n, int64_
     const int i = tid + q * NT;
     if (i < n) {
       double *row = A + (int64_t)i * ld + p0;
+      if (w == NB) {
+        double2 *row2 = reinterpret_cast<double2 *>(row);
 #pragma unroll
-      for (int c = 0; c < NB; ++c)
-        if (c < w) row[c] = v[q][c];
+        for (int c = 0; c < NB / 2; ++c) row2[c] = make_double2(v[q][2 * c], v[q][2 * c + 1]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          if (c < w) row[c] = v[q][c];
+      }
       if (stp[q] >= p0) used[i] = stp[q];
     }
   }
-  __syncthreads();
-  if (tid < w) perm[p0 + tid] = sh.piv[tid];
+  if (tid < w) perm[p0 + tid] = mypiv;
 }
 
 template <int NB, int R, int NT>
@@ -456,7 +478,10 @@ __global__ __launch_bounds__(NT) void k_cgj_panel(double *__restrict__ A, int n,
                                                   int *__restrict__ status) {
   __shared__ PivotLds<NB, NT / 64> sh;
   if (status[0]) return;
-  cgj_factor<NB, R, NT>(A, n, ld, p0, w, perm, used, status, sh);
+  double v[R][NB];
+  int stp[R];
+  cgj_load<NB, R, NT>(A, n, ld, p0, w, used, v, stp);
+  cgj_factor<NB, R, NT>(A, n, ld, p0, w, perm, used, status, sh, v, stp);
 }
 
 // Applies the factored panel [p0, p0 + w) to one tile of 16 of the columns
@@ -596,9 +621,15 @@ __global__ __launch_bounds__(NT) void k_cgj_step(double *__restrict__ A, int n, 
     cgj_update_tile<NB, NT>(A, n, ld, p0, w, blockIdx.x, perm, used);
     return;
   }
-  // the panel's pivot rows in this tile: new A[r_s][j] = sum_t PC[r_s][t] X[t][j]
-  // with X the pivot rows' old values (all read before any is written)
-  const int tid = threadIdx.x, mp = n - w, ct = p0 / 16;
+  // the next panel's loads go out first; meanwhile the panel's pivot rows in
+  // this tile are computed, new A[r_s][j] = sum_t PC[r_s][t] X[t][j] with X
+  // the pivot rows' old values (all read before any is written), stored to
+  // the block and patched into the loaded rows through LDS
+  __shared__ double fix[NB][16];
+  const int tid = threadIdx.x, mp = n - w, ct = p0 / 16, wn = min(NB, n - pn);
+  double v[R][NB];
+  int stp[R];
+  cgj_load<NB, R, NT>(A, n, ld, pn, wn, used, v, stp);
   double val = 0.0;
   int64_t dst = -1;
   if (tid < 16 * w) {
@@ -611,12 +642,19 @@ __global__ __launch_bounds__(NT) void k_cgj_step(double *__restrict__ A, int n, 
         if (t < w) val += pr[t] * A[perm[p0 + t] * ld + j];
       dst = perm[p0 + sidx] * ld + j;
     }
+    fix[sidx][tid & 15] = val;
   }
   __syncthreads();
   if (dst >= 0) A[dst] = val;
-  __threadfence_block();
-  __syncthreads();
-  cgj_factor<NB, R, NT>(A, n, ld, pn, min(NB, n - pn), perm, used, status, sh);
+  const int e0 = p0 - ct * 16;   // the next panel's first column within the tile
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+    if (stp[q] >= p0 && stp[q] < p0 + w) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < wn) v[q][c] = fix[stp[q] - p0][e0 + c];
+    }
+  cgj_factor<NB, R, NT>(A, n, ld, pn, wn, perm, used, status, sh, v, stp);
 }
 
 // C0[c * n + k] = inv(A)[k][c] = S[perm[k]][used[c]] (column-major, dense GEMV layout)
