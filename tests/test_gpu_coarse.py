@@ -1,0 +1,84 @@
+"""GPU tests of the coarsest-level direct solve at every size class of its
+Gauss-Jordan kernels (through the C ABI, a one-level hierarchy).
+
+The matrices are seeded saddle-point systems [[K, B^T], [B, 0]]: the zero
+block forces row pivoting.  The reference is numpy's dense FP64 solve."""
+
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def saddle(n, seed):
+    """n x n saddle-point matrix: K (SPD, 4/5 of the rows) and a full-rank B."""
+    rng = np.random.default_rng(seed)
+    nk = n - n // 5
+    nb = n - nk
+    K = sp.random(nk, nk, density=min(1.0, 12.0 / nk), random_state=rng, format="csr")
+    K = K + K.T + sp.diags(np.full(nk, 30.0))
+    B = sp.random(nb, nk, density=min(1.0, 8.0 / nk), random_state=rng, format="csr")
+    B = B + sp.hstack([sp.identity(nb), sp.csr_matrix((nb, nk - nb))])   # full row rank
+    A = sp.bmat([[K, B.T], [B, None]], format="csr")
+    A.sort_indices()
+    return A
+
+
+class OneLevel:
+    """A hierarchy made of the coarsest level only (for fsi_mg_setup)."""
+
+    def __init__(self, A):
+        from paper_1709_05660_amd import _lib as L
+        A = sp.csr_matrix(A)
+        A.sort_indices()
+        self.rowptr = np.ascontiguousarray(A.indptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(A.indices, dtype=np.int32)
+        self.val = np.ascontiguousarray(A.data, dtype=np.float64)
+        self.levels = (L.LevelC * 1)()
+        J = self.levels[0].J
+        J.nrows = J.ncols = A.shape[0]
+        J.nnz = A.nnz
+        J.rowptr = self.rowptr.ctypes.data_as(C.POINTER(C.c_int64))
+        J.colind = self.col.ctypes.data_as(C.POINTER(C.c_int32))
+        J.val = self.val.ctypes.data_as(C.POINTER(C.c_double))
+        self.nlevels = 1
+        self.n = A.shape[0]
+
+
+# sizes covering (panel width, rows per thread): 16/1, 16/2, 16/3, 8/6, 4/12; none a multiple of 16
+@pytest.mark.parametrize("n", [37, 301, 703, 1381, 2003, 3501])
+def test_coarsest_solve_matches_dense(n):
+    import torch
+
+    from paper_1709_05660_amd import MG
+    A = saddle(n, 100 + n)
+    _say("coarse n", n, "nnz", A.nnz)
+    mg = MG(OneLevel(A), precision="fp64")
+    rng = np.random.default_rng(n)
+    b = rng.standard_normal(n)
+    y = mg.apply(0, 5, torch.as_tensor(b, device="cuda")).cpu().numpy()
+    mg.close()
+    ref = np.linalg.solve(A.toarray(), b)
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    _say("  rel err", err)
+    assert err <= 1e-11
+
+
+def test_coarsest_singular_is_reported():
+    from paper_1709_05660_amd import MG, FsiError
+    A = saddle(301, 7).tolil()
+    A[150, :] = 0.0
+    A = A.tocsr()
+    A.eliminate_zeros()
+    with pytest.raises(FsiError) as e:
+        MG(OneLevel(A), precision="fp64")
+    assert "coarsest" in str(e.value)
