@@ -401,6 +401,21 @@ __global__ __launch_bounds__(256) void k_ras(RasView v, const WT *__restrict__ W
   const int r0 = v.task_row0[task];
   const int m = v.pm[k], o = v.po[k];
   const int *d = v.dof + v.pdof_off[k];
+  const int row = r0 + lane;
+  const bool live = row < o;
+  const int quarter = (m + 3) >> 2;
+  const int c0 = wave * quarter, c1 = min(m, c0 + quarter);
+  // this wave's columns stream 8 at a time, one chunk ahead of the one being
+  // summed; the first chunk is issued before the residual gather so that no
+  // workgroup starts with an idle memory pipe (clamped addresses; columns
+  // past c1 are never summed)
+  const WT *w = W + v.woff[k] + (live ? row : o - 1);
+  auto load8 = [&](int c, AT(&wv)[8]) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) wv[u] = wload<WT, AT, IS16>(w, (int64_t)min(c + u, m - 1) * o, w16_kind);
+  };
+  AT cur[8];
+  load8(c0, cur);
   if constexpr (IS16) {
     const float *cs = v.cscale + v.pdof_off[k];
     for (int c = threadIdx.x; c < m; c += 256) xs[c] = (AT)s[d[c]] * (AT)cs[c];
@@ -408,27 +423,22 @@ __global__ __launch_bounds__(256) void k_ras(RasView v, const WT *__restrict__ W
     for (int c = threadIdx.x; c < m; c += 256) xs[c] = (AT)s[d[c]];
   }
   __syncthreads();
-  const int row = r0 + lane;
-  const int quarter = (m + 3) >> 2;
-  const int c0 = wave * quarter, c1 = min(m, c0 + quarter);
-  AT acc = 0;
-  if (row < o) {
-    const WT *w = W + v.woff[k] + row;
-    AT a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int c = c0;
-    for (; c + 8 <= c1; c += 8) {
-      AT wv[8];
+  AT a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int c = c0;
+  for (; c + 8 <= c1; c += 8) {
+    AT nxt[8];
+    load8(c + 8, nxt);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) wv[u] = wload<WT, AT, IS16>(w, (int64_t)(c + u) * o, w16_kind);
+    for (int u = 0; u < 8; ++u) a[u] += cur[u] * xs[c + u];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] += wv[u] * xs[c + u];
-    }
-    for (; c < c1; ++c) a[0] += wload<WT, AT, IS16>(w, (int64_t)c * o, w16_kind) * xs[c];
-    acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
   }
+  // the last partial chunk (already loaded in cur), in column order
+  for (int u = 0; c + u < c1; ++u) a[0] += cur[u] * xs[c + u];
+  AT acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   if (wave > 0) red[wave - 1][lane] = acc;
   __syncthreads();
-  if (wave == 0 && row < o) {
+  if (wave == 0 && live) {
     acc = ((acc + red[0][lane]) + red[1][lane]) + red[2][lane];
     if constexpr (IS16) acc *= (AT)wscale[v.out_off[k] + row];
     const int g = v.out_idx[v.out_off[k] + row];
