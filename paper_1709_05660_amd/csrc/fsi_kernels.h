@@ -44,8 +44,9 @@ void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const
 constexpr int kMaxCoarse = 6144;
 void launch_fill_i32(int *x, int n, int v, hipStream_t st);
 void gj_coarse(double *A, int n, int64_t ld, double *C0, int *status, int *iwork, hipStream_t st);
-// W_k[c * o_k + r] = Binv_k[own_row_r][c] (column-major owned rows), optional
-// FP32/16-bit copies; one workgroup per (patch, 64 owned rows) task
+// Owned rows of Binv_k, column-major per (patch, 64 owned rows) task: task
+// (k, r0) with nr = min(64, o_k - r0) rows holds entry (c, r) at
+// W[woff_k + r0 m_k + c nr + r - r0]; optional FP32/16-bit copies
 void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm, const int *po,
                        const int64_t *woff, const int *own_off, const int *own_local,
                        const int *task_patch, const int *task_row0, int ntask, double *W64,

@@ -276,8 +276,11 @@ void launch_colscale(const double *blocks, const int64_t *boff, const int *pm, c
   k_scale_fix<<<cdiv(total_cols, 256), 256, 0, st>>>(cscale, total_cols);
 }
 
-// W_k[c * o + r] = Binv_k[own_r][c], column-major owned rows.  One workgroup
-// per (patch, 64 owned rows), 64 physical columns p of S at a time: the
+// Owned rows of Binv_k in task-contiguous column-major order: the rows of
+// task (k, r0) (nr = min(64, o - r0) rows) occupy W_k[r0 m ...], entry (c, r)
+// at W_k[r0 m + c nr + r - r0], so one Schwarz workgroup streams one
+// contiguous region.  One workgroup per (patch, 64 owned rows), 64 physical
+// columns p of S at a time: the
 // rows' segments are read in order into an LDS tile, and column p is written
 // to logical column c = perm[p] with consecutive owned rows in consecutive
 // lanes, so both the reads and the stores are contiguous.  16-bit storage:
@@ -323,7 +326,7 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
     }
     __syncthreads();
   }
-  const int64_t wk = woff[k];
+  const int64_t wk = woff[k] + (int64_t)r0 * m;
   for (int q0 = 0; q0 < m; q0 += 64) {
     // all 16 loads of a thread in flight together; clamped addresses (the
     // entries past the block are never stored)
@@ -344,7 +347,7 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
       if (r < nr && q0 + p < m) {
         const int c = pk[q0 + p];
         const double v = tile[r][p];
-        const int64_t dst = wk + (int64_t)c * o + r0 + r;
+        const int64_t dst = wk + (int64_t)c * nr + r;
         if (W64) W64[dst] = v;
         if (W32) W32[dst] = (float)v;
         if (W16) {
@@ -371,9 +374,10 @@ void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm,
 // ------------------------------------------------------------------ restricted Schwarz
 // One workgroup per (patch, 64 owned rows).  The patch's residual entries
 // are gathered once into LDS; each of the four waves accumulates its quarter
-// of the columns of the owned rows of B_k^{-1} (stored column-major, so one
-// step over a column is one coalesced 64-row load, eight loads in flight per
-// lane), the partial sums meet in LDS and lane r of the first wave adds
+// of the columns of the task's owned rows of B_k^{-1} (stored column-major
+// per task, so the workgroup's rows are one contiguous region and one step
+// over a column is one coalesced load of the task's rows, eight loads in
+// flight per lane), the partial sums meet in LDS and lane r of the first wave adds
 // omega times row r to its owned dof.  TAG only names the finest-level launch.
 __device__ inline float w16val(uint16_t v, int kind) {
   return kind == 1 ? from_bf16(v) : from_fp16(v);
@@ -409,10 +413,11 @@ __global__ __launch_bounds__(256) void k_ras(RasView v, const WT *__restrict__ W
   // summed; the first chunk is issued before the residual gather so that no
   // workgroup starts with an idle memory pipe (clamped addresses; columns
   // past c1 are never summed)
-  const WT *w = W + v.woff[k] + (live ? row : o - 1);
+  const int nr = min(64, o - r0);
+  const WT *w = W + v.woff[k] + (int64_t)r0 * m + (live ? lane : nr - 1);
   auto load8 = [&](int c, AT(&wv)[8]) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) wv[u] = wload<WT, AT, IS16>(w, (int64_t)min(c + u, m - 1) * o, w16_kind);
+    for (int u = 0; u < 8; ++u) wv[u] = wload<WT, AT, IS16>(w, (int64_t)min(c + u, m - 1) * nr, w16_kind);
   };
   AT cur[8];
   load8(c0, cur);
