@@ -5,11 +5,13 @@
 //
 // Both are the same blocked right-looking Gauss-Jordan elimination with
 // partial pivoting (largest magnitude among the rows not yet used as pivots,
-// lowest row on ties).  A panel of NB pivot columns is factored with its
-// rows held in registers: thread t holds rows t, t + NT, ...  A pivot step
-// costs one workgroup barrier: each wave publishes its best candidate row in
-// LDS (double-buffered by step parity) and every thread then takes the best
-// of the waves' candidates and eliminates it from its own rows.
+// compared to 39 significant bits, lowest row on ties).  A panel of NB pivot
+// columns is factored with its rows held in registers: thread t holds rows
+// t, t + NT, ...  A pivot step costs one workgroup barrier: each wave reduces
+// its candidates' keys (magnitude and row in one double) with DPP, publishes
+// its best candidate row in LDS (double-buffered by step parity), and every
+// thread then takes the best of the waves' keys and eliminates that row from
+// its own rows.
 //
 // Rows are never exchanged.  The pivot row of step s is recorded as
 // perm[s], the step at which row i served as pivot as used[i], and the
@@ -25,6 +27,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 
 #include "fsi_kernels.h"
@@ -35,13 +38,6 @@ static inline int cdivg(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 constexpr int kNoRow = 0x7fffffff;
 
-struct Argmax {
-  double v;
-  int i;
-};
-__device__ inline bool beats(const Argmax &b, const Argmax &a) {
-  return (b.v > a.v) | ((b.v == a.v) & (b.i < a.i));   // branch-free
-}
 // DPP move of a double within rows of 16 lanes (full EXEC)
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double x) {
@@ -49,10 +45,6 @@ __device__ __forceinline__ double dpp_f64(double x) {
   const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xF, 0xF, false);
   const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-template <int CTRL>
-__device__ __forceinline__ int dpp_i32(int x) {
-  return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
 }
 __device__ __forceinline__ double readlane_f64(double x, int l) {
   const long long b = __double_as_longlong(x);
@@ -62,40 +54,44 @@ __device__ __forceinline__ double readlane_f64(double x, int l) {
 // DPP controls: quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_ror 4, row_ror 8
 constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppRor4 = 0x124, kDppRor8 = 0x128;
 
-// wave-wide argmax (largest value, then lowest index) in every lane: the
-// maximum by a DPP reduction inside each row of 16 lanes and a combination
-// of the four rows; the lane holding it from a ballot when it is unique,
-// else the lowest index among the tied lanes by a second reduction.
-// Requires all 64 lanes active.
-__device__ __forceinline__ Argmax wave_argmax(Argmax a) {
-  double v = a.v;
+// Pivot keys.  A candidate row i with entry a in the pivot column is keyed
+// by |a| with its lowest 13 mantissa bits replaced by 8191 - i (rows are
+// below 8192): keys order by |a| to 39 significant bits, then by the lowest
+// row, and a plain fmax reduces them (positive doubles order as their bit
+// patterns).  A non-finite |a| keys as the largest finite double, which
+// fails the step; rows that are not candidates carry -1.
+constexpr long long kKeyMask = (1LL << 13) - 1;
+__device__ __forceinline__ double pivot_key(double a, int i) {
+  double x = fabs(a);
+  if (!(x <= DBL_MAX)) x = DBL_MAX;   // NaN or infinite
+  return __longlong_as_double((__double_as_longlong(x) & ~kKeyMask) | (kKeyMask - i));
+}
+__device__ __forceinline__ int key_row(double k) {
+  return (int)(kKeyMask - (__double_as_longlong(k) & kKeyMask));
+}
+__device__ __forceinline__ double key_value(double k) {
+  return __longlong_as_double(__double_as_longlong(k) & ~kKeyMask);
+}
+
+// wave-wide maximum of a double in every lane: DPP inside each row of 16
+// lanes, then the four rows combined.  Requires all 64 lanes active.
+__device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_f64<kDppXor1>(v));
   v = fmax(v, dpp_f64<kDppXor2>(v));
   v = fmax(v, dpp_f64<kDppRor4>(v));
   v = fmax(v, dpp_f64<kDppRor8>(v));
-  const double wmax = fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
-                           fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
-  const unsigned long long tie = __ballot(a.v == wmax);
-  if (__popcll(tie) == 1) return Argmax{wmax, __builtin_amdgcn_readlane(a.i, __ffsll((long long)tie) - 1)};
-  int i = a.v == wmax ? a.i : kNoRow;
-  i = min(i, dpp_i32<kDppXor1>(i));
-  i = min(i, dpp_i32<kDppXor2>(i));
-  i = min(i, dpp_i32<kDppRor4>(i));
-  i = min(i, dpp_i32<kDppRor8>(i));
-  const int wi = min(min(__builtin_amdgcn_readlane(i, 0), __builtin_amdgcn_readlane(i, 16)),
-                     min(__builtin_amdgcn_readlane(i, 32), __builtin_amdgcn_readlane(i, 48)));
-  return Argmax{wmax, wi};
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
+              fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
 // LDS of the pivot steps: one candidate row (with the reciprocal of its
-// pivot-column entry) per wave and step parity, and the panel's pivot rows
-// in step order.
+// pivot-column entry and its key) per wave and step parity, and the panel's
+// pivot rows in step order.
 template <int NB, int NW>
 struct PivotLds {
   double row[2][NW][NB];
-  double val[2][NW];
+  double key[2][NW];
   double dinv[2][NW];
-  int idx[2][NW];
   int piv[NB];
 };
 
@@ -107,57 +103,49 @@ __device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int buf = t & 1;
-  Argmax best{-1.0, kNoRow};
-  double sv = 1.0;   // signed pivot-column entry of this lane's candidate
+  double key = -1.0, sv = 1.0;   // this lane's best key and its signed pivot-column entry
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int i = tid + q * NT;
     if (i < m && stp[q] < 0) {
-      const double a = fabs(v[q][col]);
-      const Argmax c{a != a ? INFINITY : a, i};
-      if (beats(c, best)) {
-        best = c;
+      const double kq = pivot_key(v[q][col], i);
+      if (kq > key) {
+        key = kq;
         sv = v[q][col];
       }
     }
   }
   // every lane inverts its own candidate while the wave reduction runs;
-  // the winner publishes its reciprocal
+  // the winner publishes its row and reciprocal
   const double dl = 1.0 / sv;
-  best = wave_argmax(best);
+  const double wkey = wave_max(key);
+  if (wkey >= 0.0 && key == wkey) {
+    const int i = key_row(key);
 #pragma unroll
-  for (int q = 0; q < R; ++q)
-    if (tid + q * NT == best.i) {
+    for (int q = 0; q < R; ++q)
+      if (tid + q * NT == i) {
 #pragma unroll
-      for (int c = 0; c < NB; ++c) sh.row[buf][wave][c] = v[q][c];
-      sh.dinv[buf][wave] = dl;
-    }
-  if (lane == 0) {
-    sh.val[buf][wave] = best.v;
-    sh.idx[buf][wave] = best.i;
+        for (int c = 0; c < NB; ++c) sh.row[buf][wave][c] = v[q][c];
+      }
+    sh.dinv[buf][wave] = dl;
   }
+  if (lane == 0) sh.key[buf][wave] = wkey;
   __syncthreads();
-  // the waves' candidates combined by a tree (same result as in order)
-  Argmax cand[NW];
-  int cw[NW];
+  // the waves' keys combined by a tree
+  double kk[NW];
 #pragma unroll
-  for (int k = 0; k < NW; ++k) {
-    cand[k] = Argmax{sh.val[buf][k], sh.idx[buf][k]};
-    cw[k] = k;
-  }
+  for (int k = 0; k < NW; ++k) kk[k] = sh.key[buf][k];
 #pragma unroll
   for (int s2 = 1; s2 < NW; s2 <<= 1)
 #pragma unroll
-    for (int k = 0; k + s2 < NW; k += 2 * s2)
-      if (beats(cand[k + s2], cand[k])) {
-        cand[k] = cand[k + s2];
-        cw[k] = cw[k + s2];
-      }
-  const Argmax g = cand[0];
-  const int gw = cw[0];
-  if (!(g.v > 0.0) || isinf(g.v)) return p0 + t + 1;
-  if (tid == 0) sh.piv[t] = g.i;
-  if (tid == t) mypiv = g.i;
+    for (int k = 0; k + s2 < NW; k += 2 * s2) kk[k] = fmax(kk[k], kk[k + s2]);
+  const double gkey = kk[0];
+  const double gv = key_value(gkey);
+  if (!(gkey >= 0.0) || !(gv > 0.0) || gv >= key_value(pivot_key(DBL_MAX, 0))) return p0 + t + 1;
+  const int gi = key_row(gkey);
+  const int gw = (gi % NT) >> 6;
+  if (tid == 0) sh.piv[t] = gi;
+  if (tid == t) mypiv = gi;
   const double *prow = sh.row[buf][gw];
   const double d = sh.dinv[buf][gw];
   // every row is eliminated with one FMA per column, v - (f d) prow, then
@@ -171,7 +159,7 @@ __device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int
   }
 #pragma unroll
   for (int q = 0; q < R; ++q)
-    if (tid + q * NT == g.i) {
+    if (tid + q * NT == gi) {
 #pragma unroll
       for (int c = 0; c < NB; ++c) v[q][c] = c == col ? d : prow[c] * d;
       stp[q] = p0 + t;
