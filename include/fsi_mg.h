@@ -91,7 +91,7 @@ typedef struct {
   int32_t refine_sweeps;   /* reserved: must be 0 (no per-block refinement; the outer
                               Richardson and FGMRES iterations correct the rounding of
                               the stored inverse rows); other values are rejected */
-  int32_t use_graph;       /* capture the V-cycle in a hipGraph */
+  int32_t use_graph;       /* replay the V-cycle and each Arnoldi step from hipGraphs */
 } fsi_mg_opts;
 
 typedef struct {

@@ -62,9 +62,12 @@ struct Level {
 struct Krylov {
   int m = 0;
   double *V = nullptr, *Z = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
-         *y = nullptr, *h1 = nullptr, *h2 = nullptr, *partial = nullptr, *npart = nullptr,
+         *y = nullptr, *h1 = nullptr, *partial = nullptr, *npart = nullptr,
          *nrm = nullptr, *flags = nullptr, *scal = nullptr, *w = nullptr;
-  double *pinned = nullptr;
+  double *pinned = nullptr;       // 8 doubles of host-coherent pinned memory (a pool slot)
+  double *pinned_dev = nullptr;   // its device address
+  hipEvent_t ev_done = nullptr;   // recorded after a phase's D2H copy, polled by the host
+  std::vector<hipGraphExec_t> step_graphs;   // Arnoldi step j as one graph (use_graph)
   std::vector<void *> owned;
 };
 
@@ -115,6 +118,9 @@ fsi_status fgmres(MG &mg, const double *b, double *x, int x0_nonzero, const fsi_
                   fsi_solve_info *info, hipStream_t st);
 RasView ras_view(const Level &L);
 void ensure_krylov(MG &mg, int m);
+void clear_graphs(MG &mg);
+double *pinned_slot_acquire();
+void pinned_slot_release(double *s);
 void refactor(MG &mg, hipStream_t st);
 void release_setup_scratch(MG &mg);
 
@@ -138,6 +144,7 @@ struct FgmresRun {
   void fill_info(fsi_solve_info *info) const;
  private:
   void enqueue_residual();
+  void enqueue_step();
   void finish_cycle();
   void add_hist(double v);
 };

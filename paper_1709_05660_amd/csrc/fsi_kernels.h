@@ -3,11 +3,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace fsi {
 
 constexpr int kWave = 64;
 constexpr int kMaxPatch = 800;      // largest Schwarz block handled by one wave's LDS slice
-constexpr int kMdotBlocks = 256;    // fixed number of partial sums in the Krylov reductions
 constexpr int kGemvSplit = 32;      // column chunks of the coarsest GEMV (partial buffer: kGemvSplit n)
 
 // CSR on the device: int32 offsets and columns (sizes checked at upload).
@@ -90,20 +91,30 @@ void launch_axpy_f64(int n, double a, const double *x, double *y, hipStream_t st
 void launch_copy_f64(int n, const double *x, double *y, hipStream_t st);
 
 // ---- Krylov (a8, a9)
-// partial[b * ldp + i] = sum over rows of block b of V[i * ldv + row] * w[row], i < k
-void launch_mdot(int n, const double *V, int64_t ldv, int k, const double *w, double *partial,
-                 int ldp, hipStream_t st);
-// out[i] (= or +=) sum_b partial[b * ldp + i]
-void launch_mdot_finish(const double *partial, int ldp, int k, double *out, int accumulate,
-                        hipStream_t st);
-// w -= V h (k columns); if norm_partial != NULL also partial sums of w^2 (after update)
-void launch_mupdate(int n, const double *V, int64_t ldv, int k, const double *h, double *w,
-                    double *norm_partial, hipStream_t st);
-// Arnoldi column j: H[:, j] = h, hn = sqrt(nrm2), rotations, g; flags[0] = |g_{j+1}|,
-// flags[1] = breakdown, scal[0] = hn (v_{j+1} = w / hn)
-void launch_givens(double *H, int ldh, int j, const double *h, const double *nrm2, double *cs,
-                   double *sn, double *g, double *flags, double *scal, hipStream_t st);
-void launch_scale_to(int n, const double *w, const double *scal, double *v, hipStream_t st);
+// Reductions over n rows use krylov_blocks(n) row chunks of at most
+// kKrylovChunk rows; chunk sums are stored as partial[i * nblk + chunk].
+constexpr int kKrylovThreads = 512;
+constexpr int kKrylovWaves = kKrylovThreads / 64;
+constexpr int kKrylovChunk = 2048;
+constexpr int kMaxKrylovCols = 64;
+inline int krylov_blocks(int n) { return std::max(256, (n + kKrylovChunk - 1) / kKrylovChunk); }
+// h[i] = V[:, i]^T w, i < k <= kMaxKrylovCols (V column-major, leading dimension
+// ldv); partial holds krylov_blocks(n) * k doubles
+void launch_kdot(int n, const double *V, int64_t ldv, int k, const double *w, double *partial,
+                 double *h, hipStream_t st);
+// Orthogonalisation of Arnoldi step j (k = j + 1 basis vectors V) by classical
+// Gram-Schmidt applied twice, and its Givens column, in four launches:
+// h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; h1 += h2;
+// H[:, j] = h1, H[j + 1, j] = |w|, previous rotations then a new one on H[:, j]
+// and g; flags[0] = |g[j + 1]|, flags[1] = breakdown, scal[0] = |w|;
+// v_next = w / |w| (untouched when |w| == 0).  partial holds
+// 2 * krylov_blocks(n) * kMaxKrylovCols doubles, npart krylov_blocks(n).
+// host_out (device address of host-coherent pinned memory, or NULL): flags[0],
+// flags[1] are written to host_out[0..1], then host_out[2] = 1 (ready).
+void launch_arnoldi_orth(int n, const double *V, int64_t ldv, int k, double *w, double *partial,
+                         double *h1, double *npart, double *v_next, double *H, int ldh, int j,
+                         double *cs, double *sn, double *g, double *flags, double *scal,
+                         double *host_out, hipStream_t st);
 // y = H^{-1} g (upper triangular k x k), then x += Z y
 void launch_backsolve(const double *H, int ldh, const double *g, int k, double *y, hipStream_t st);
 void launch_zupdate(int n, const double *Z, int64_t ldz, int k, const double *y, double *x,

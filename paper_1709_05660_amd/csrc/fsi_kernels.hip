@@ -513,86 +513,10 @@ void launch_dense_gemv(const double *W, int n, const double *x, double *y, doubl
   k_gemv_finish<<<cdiv(n, 256), 256, 0, st>>>(partial, n, y);
 }
 
-// ------------------------------------------------------------------ Krylov reductions
-__device__ inline double block_sum_256(double v, double *sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
-}
-
-__global__ __launch_bounds__(256) void k_mdot(int n, const double *__restrict__ V, int64_t ldv,
-                                              int k, const double *__restrict__ w,
-                                              double *__restrict__ partial, int ldp) {
-  __shared__ double sh[4];
-  const int chunk = (n + kMdotBlocks - 1) / kMdotBlocks;
-  const int r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
-  for (int i = 0; i < k; ++i) {
-    const double *Vi = V + (int64_t)i * ldv;
-    double acc = 0.0;
-    for (int r = r0 + threadIdx.x; r < r1; r += 256) acc += Vi[r] * w[r];
-    const double s = block_sum_256(acc, sh);
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * ldp + i] = s;
-  }
-}
-void launch_mdot(int n, const double *V, int64_t ldv, int k, const double *w, double *partial,
-                 int ldp, hipStream_t st) {
-  k_mdot<<<kMdotBlocks, 256, 0, st>>>(n, V, ldv, k, w, partial, ldp);
-}
-// out[i] (=, or += with acc) sum over the kMdotBlocks partials of column i:
-// wave w takes columns w, w + 4, ...; lane l adds partials l, l + 64, ...
-// in order, then a fixed butterfly over the wave (a deterministic order)
-__global__ __launch_bounds__(256) void k_mdot_finish(const double *partial, int ldp, int k,
-                                                     double *out, int acc) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = wave; i < k; i += 4) {
-    double s = 0.0;
-#pragma unroll
-    for (int b = lane; b < kMdotBlocks; b += 64) s += partial[(int64_t)b * ldp + i];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) out[i] = acc ? out[i] + s : s;
-  }
-}
-void launch_mdot_finish(const double *partial, int ldp, int k, double *out, int accumulate,
-                        hipStream_t st) {
-  k_mdot_finish<<<1, 256, 0, st>>>(partial, ldp, k, out, accumulate);
-}
-
-__global__ __launch_bounds__(256) void k_mupdate(int n, const double *__restrict__ V, int64_t ldv,
-                                                 int k, const double *__restrict__ h,
-                                                 double *__restrict__ w,
-                                                 double *__restrict__ norm_partial) {
-  __shared__ double sh[4];
-  __shared__ double hs[64];
-  if (threadIdx.x < k) hs[threadIdx.x] = h[threadIdx.x];
-  __syncthreads();
-  const int chunk = (n + kMdotBlocks - 1) / kMdotBlocks;
-  const int r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
-  double nacc = 0.0;
-  for (int r = r0 + threadIdx.x; r < r1; r += 256) {
-    double s = 0.0;
-    for (int i = 0; i < k; ++i) s += V[(int64_t)i * ldv + r] * hs[i];
-    const double nv = w[r] - s;
-    w[r] = nv;
-    nacc += nv * nv;
-  }
-  if (norm_partial) {
-    const double t = block_sum_256(nacc, sh);
-    if (threadIdx.x == 0) norm_partial[blockIdx.x] = t;
-  }
-}
-void launch_mupdate(int n, const double *V, int64_t ldv, int k, const double *h, double *w,
-                    double *norm_partial, hipStream_t st) {
-  k_mupdate<<<kMdotBlocks, 256, 0, st>>>(n, V, ldv, k, h, w, norm_partial);
-}
-
-// single thread: Arnoldi column bookkeeping and Givens rotations
-__global__ void k_givens(double *H, int ldh, int j, const double *h, const double *nrm2,
-                         double *cs, double *sn, double *g, double *flags, double *scal) {
-  if (threadIdx.x != 0) return;
+// Arnoldi column j (one thread): H[:, j] = h, |w| and breakdown test, the
+// previous rotations, a new one, and g
+__device__ void givens_column(double *H, int ldh, int j, const double *h, const double *nrm2,
+                              double *cs, double *sn, double *g, double *flags, double *scal) {
   const double hn = sqrt(nrm2[0]);
   double hh = 0.0;
   for (int i = 0; i <= j; ++i) {
@@ -618,18 +542,188 @@ __global__ void k_givens(double *H, int ldh, int j, const double *h, const doubl
   flags[1] = breakdown ? 1.0 : 0.0;
   scal[0] = hn;
 }
-void launch_givens(double *H, int ldh, int j, const double *h, const double *nrm2, double *cs,
-                   double *sn, double *g, double *flags, double *scal, hipStream_t st) {
-  k_givens<<<1, 64, 0, st>>>(H, ldh, j, h, nrm2, cs, sn, g, flags, scal);
+// ------------------------------------------------------------------ Krylov reductions
+// Every reduction over the n rows runs on krylov_blocks(n) fixed row chunks:
+// a chunk's sum, formed in a fixed order, goes to partial[i * nblk + chunk].
+// The kernel that needs the totals adds the chunk sums in a fixed order, in
+// every workgroup (a few KB read from L2 each), so no separate reduction
+// launch and no cross-workgroup signalling is needed, and every sum has one
+// order for a given n: runs are reproducible.
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
-__global__ void k_scale_to(int n, const double *w, const double *scal, double *v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const double hn = scal[0];
-  if (i < n && hn > 0.0) v[i] = w[i] / hn;
+
+// out[i] = sum over the nblk chunk sums of column i, i < k <= kMaxKrylovCols.
+// Wave w takes columns w, w + kKrylovWaves, ...; lane l adds chunks l, l + 64,
+// ... in order, then a fixed butterfly.  All loads are issued before the adds.
+__device__ __forceinline__ void finish_cols(const double *__restrict__ partial, int nblk, int k,
+                                            double *out) {
+  constexpr int C = (kMaxKrylovCols + kKrylovWaves - 1) / kKrylovWaves;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave >= k) return;
+  double s[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) s[c] = 0.0;
+#pragma unroll 4
+  for (int b0 = 0; b0 < nblk; b0 += 64) {
+    const bool ok = b0 + lane < nblk;
+    const int b = ok ? b0 + lane : nblk - 1;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int i = min(wave + kKrylovWaves * c, k - 1);
+      const double v = partial[(int64_t)i * nblk + b];
+      s[c] += ok ? v : 0.0;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const double t = wave_sum(s[c]);
+    if (lane == 0 && wave + kKrylovWaves * c < k) out[wave + kKrylovWaves * c] = t;
+  }
 }
-void launch_scale_to(int n, const double *w, const double *scal, double *v, hipStream_t st) {
-  k_scale_to<<<cdiv(n, 256), 256, 0, st>>>(n, w, scal, v);
+
+__device__ __forceinline__ void chunk_range(int n, int &r0, int &r1) {
+  const int chunk = (n + gridDim.x - 1) / gridDim.x;
+  r0 = min(n, (int)blockIdx.x * chunk);
+  r1 = min(n, r0 + chunk);
 }
+
+// chunk sums of V[:, i]^T w for i < k, one wave per column (w from global, or
+// from LDS indexed from the chunk's first row)
+template <bool WLDS>
+__device__ __forceinline__ void chunk_dots(const double *__restrict__ V, int64_t ldv, int k,
+                                           const double *w, int r0, int r1,
+                                           double *__restrict__ partial) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nblk = gridDim.x;
+  for (int i = wave; i < k; i += kKrylovWaves) {
+    const double *Vi = V + (int64_t)i * ldv;
+    double acc = 0.0;
+    for (int r = r0 + lane; r < r1; r += 64) acc += Vi[r] * (WLDS ? w[r - r0] : w[r]);
+    acc = wave_sum(acc);
+    if (lane == 0) partial[(int64_t)i * nblk + blockIdx.x] = acc;
+  }
+}
+
+// w -= V h on the chunk's rows (h in LDS; sum over the columns in order), the
+// new rows also kept in LDS (ws, when given); returns this thread's sum of squares
+__device__ __forceinline__ double chunk_update(const double *__restrict__ V, int64_t ldv, int k,
+                                               const double *hs, double *__restrict__ w, int r0,
+                                               int r1, double *ws) {
+  double nacc = 0.0;
+  for (int r = r0 + threadIdx.x; r < r1; r += kKrylovThreads) {
+    double s = 0.0;
+    for (int i = 0; i < k; ++i) s += V[(int64_t)i * ldv + r] * hs[i];
+    const double nv = w[r] - s;
+    w[r] = nv;
+    if (ws) ws[r - r0] = nv;
+    nacc += nv * nv;
+  }
+  return nacc;
+}
+
+// partial <- chunk sums of V[:, 0..k)^T w
+__global__ __launch_bounds__(kKrylovThreads) void k_kdot(int n, const double *__restrict__ V,
+                                                         int64_t ldv, int k,
+                                                         const double *__restrict__ w,
+                                                         double *__restrict__ partial) {
+  int r0, r1;
+  chunk_range(n, r0, r1);
+  chunk_dots<false>(V, ldv, k, w, r0, r1, partial);
+}
+__global__ __launch_bounds__(kKrylovThreads) void k_kfinish(const double *__restrict__ partial,
+                                                            int nblk, int k,
+                                                            double *__restrict__ h) {
+  finish_cols(partial, nblk, k, h);
+}
+void launch_kdot(int n, const double *V, int64_t ldv, int k, const double *w, double *partial,
+                 double *h, hipStream_t st) {
+  const int nb = krylov_blocks(n);
+  k_kdot<<<nb, kKrylovThreads, 0, st>>>(n, V, ldv, k, w, partial);
+  k_kfinish<<<1, kKrylovThreads, 0, st>>>(partial, nb, k, h);
+}
+
+// h1 = sum of pin's chunk sums (block 0 stores it); w -= V h1; pout <- chunk
+// sums of V^T w
+__global__ __launch_bounds__(kKrylovThreads) void k_kupdate_dot(
+    int n, const double *__restrict__ V, int64_t ldv, int k, const double *__restrict__ pin,
+    double *__restrict__ h1, double *__restrict__ w, double *__restrict__ pout) {
+  __shared__ double hs[kMaxKrylovCols];
+  __shared__ double ws[kKrylovChunk];
+  int r0, r1;
+  chunk_range(n, r0, r1);
+  finish_cols(pin, gridDim.x, k, hs);
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x < k) h1[threadIdx.x] = hs[threadIdx.x];
+  (void)chunk_update(V, ldv, k, hs, w, r0, r1, ws);
+  __syncthreads();
+  chunk_dots<true>(V, ldv, k, ws, r0, r1, pout);
+}
+
+// h2 = sum of pin's chunk sums (block 0: h1 += h2); w -= V h2; npart <- chunk
+// sums of w^2
+__global__ __launch_bounds__(kKrylovThreads) void k_kupdate_norm(
+    int n, const double *__restrict__ V, int64_t ldv, int k, const double *__restrict__ pin,
+    double *__restrict__ h1, double *__restrict__ w, double *__restrict__ npart) {
+  __shared__ double hs[kMaxKrylovCols];
+  __shared__ double red[kKrylovWaves];
+  int r0, r1;
+  chunk_range(n, r0, r1);
+  finish_cols(pin, gridDim.x, k, hs);
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x < k) h1[threadIdx.x] += hs[threadIdx.x];
+  const double nacc = wave_sum(chunk_update(V, ldv, k, hs, w, r0, r1, nullptr));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nacc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kKrylovWaves; ++q) t += red[q];
+    npart[blockIdx.x] = t;
+  }
+}
+
+// |w|^2 from npart; block 0 forms Arnoldi column j and its rotations; every
+// block writes its chunk of v_{j+1} = w / |w| (unless |w| == 0)
+__global__ __launch_bounds__(kKrylovThreads) void k_kgivens_scale(
+    int n, const double *__restrict__ npart, const double *__restrict__ w, double *__restrict__ v,
+    double *H, int ldh, int j, const double *h1, double *cs, double *sn, double *g,
+    double *flags, double *scal, double *host_out) {
+  __shared__ double nrm2[1];
+  int r0, r1;
+  chunk_range(n, r0, r1);
+  finish_cols(npart, gridDim.x, 1, nrm2);
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    givens_column(H, ldh, j, h1, nrm2, cs, sn, g, flags, scal);
+    if (host_out) {
+      host_out[0] = flags[0];
+      host_out[1] = flags[1];
+      __threadfence_system();
+      host_out[2] = 1.0;   // ready: the host polls this after clearing it
+    }
+  }
+  const double hn = sqrt(nrm2[0]);
+  if (hn > 0.0)
+    for (int r = r0 + threadIdx.x; r < r1; r += kKrylovThreads) v[r] = w[r] / hn;
+}
+
+void launch_arnoldi_orth(int n, const double *V, int64_t ldv, int k, double *w, double *partial,
+                         double *h1, double *npart, double *v_next, double *H, int ldh, int j,
+                         double *cs, double *sn, double *g, double *flags, double *scal,
+                         double *host_out, hipStream_t st) {
+  const int nb = krylov_blocks(n);
+  double *p1 = partial, *p2 = partial + (int64_t)nb * kMaxKrylovCols;
+  k_kdot<<<nb, kKrylovThreads, 0, st>>>(n, V, ldv, k, w, p1);
+  k_kupdate_dot<<<nb, kKrylovThreads, 0, st>>>(n, V, ldv, k, p1, h1, w, p2);
+  k_kupdate_norm<<<nb, kKrylovThreads, 0, st>>>(n, V, ldv, k, p2, h1, w, npart);
+  k_kgivens_scale<<<nb, kKrylovThreads, 0, st>>>(n, npart, w, v_next, H, ldh, j, h1, cs, sn, g,
+                                                 flags, scal, host_out);
+}
+
 __global__ void k_backsolve(const double *H, int ldh, const double *g, int k, double *y) {
   if (threadIdx.x != 0) return;
   for (int i = k - 1; i >= 0; --i) {

@@ -3,11 +3,13 @@
 #include "fsi_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -90,6 +92,31 @@ T *dalloc(int64_t n, std::vector<void *> &owned) {
   owned.push_back(p);
   return static_cast<T *>(p);
 }
+// 64-byte slots of host-coherent pinned memory that kernels write small
+// results into and the host polls.  Chunks are allocated once and kept for the
+// life of the process; slots are recycled.
+static std::mutex g_slot_mu;
+static std::vector<double *> g_free_slots;
+double *pinned_slot_acquire() {
+  std::lock_guard<std::mutex> lk(g_slot_mu);
+  if (g_free_slots.empty()) {
+    constexpr int kSlots = 256;
+    double *p = nullptr;
+    hip_check(hipHostMalloc((void **)&p, kSlots * 8 * sizeof(double),
+                            hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable),
+              "pinned");
+    for (int i = kSlots - 1; i >= 0; --i) g_free_slots.push_back(p + 8 * i);
+  }
+  double *s = g_free_slots.back();
+  g_free_slots.pop_back();
+  for (int i = 0; i < 8; ++i) s[i] = 0.0;
+  return s;
+}
+void pinned_slot_release(double *s) {
+  std::lock_guard<std::mutex> lk(g_slot_mu);
+  g_free_slots.push_back(s);
+}
+
 template <typename T>
 T *dupload(const T *h, int64_t n, std::vector<void *> &owned, hipStream_t st) {
   T *d = dalloc<T>(n, owned);
@@ -571,19 +598,30 @@ void destroy_mg(MG *mg) {
     (void)hipEventDestroy(p.first);
     (void)hipEventDestroy(p.second);
   }
-  for (auto &kv : mg->graphs) (void)hipGraphExecDestroy(kv.second);
-  mg->graphs.clear();
+  clear_graphs(*mg);
   free_list(mg->owned);
   free_list(mg->kry.owned);
-  if (mg->kry.pinned) (void)hipHostFree(mg->kry.pinned);
+  if (mg->kry.pinned) pinned_slot_release(mg->kry.pinned);
+  if (mg->kry.ev_done) (void)hipEventDestroy(mg->kry.ev_done);
   delete mg;
 }
 
 // ------------------------------------------------------------------ FGMRES
+void clear_graphs(MG &mg) {
+  for (auto &kv : mg.graphs) (void)hipGraphExecDestroy(kv.second);
+  mg.graphs.clear();
+  for (auto &g : mg.kry.step_graphs)
+    if (g) (void)hipGraphExecDestroy(g);
+  mg.kry.step_graphs.clear();
+}
+
 void ensure_krylov(MG &mg, int m) {
   Krylov &K = mg.kry;
   const int n = mg.lv.back().n;
   if (K.m == m && K.V) return;
+  for (auto &g : K.step_graphs)
+    if (g) (void)hipGraphExecDestroy(g);
+  K.step_graphs.assign(m, nullptr);
   free_list(K.owned);
   K.m = m;
   K.V = dalloc<double>((int64_t)n * (m + 1), K.owned);
@@ -594,14 +632,18 @@ void ensure_krylov(MG &mg, int m) {
   K.g = dalloc<double>(m + 2, K.owned);
   K.y = dalloc<double>(m + 1, K.owned);
   K.h1 = dalloc<double>(m + 2, K.owned);
-  K.h2 = dalloc<double>(m + 2, K.owned);
-  K.partial = dalloc<double>((int64_t)kMdotBlocks * (m + 2), K.owned);
-  K.npart = dalloc<double>(kMdotBlocks, K.owned);
+  K.partial = dalloc<double>((int64_t)2 * krylov_blocks(n) * kMaxKrylovCols, K.owned);
+  K.npart = dalloc<double>(krylov_blocks(n), K.owned);
   K.nrm = dalloc<double>(4, K.owned);
   K.flags = dalloc<double>(4, K.owned);
   K.scal = dalloc<double>(4, K.owned);
   K.w = dalloc<double>(n, K.owned);
-  if (!K.pinned) hip_check(hipHostMalloc((void **)&K.pinned, 8 * sizeof(double), 0), "pinned");
+  if (!K.ev_done)
+    hip_check(hipEventCreateWithFlags(&K.ev_done, hipEventDisableTiming), "event");
+  if (!K.pinned) {
+    K.pinned = pinned_slot_acquire();
+    hip_check(hipHostGetDevicePointer((void **)&K.pinned_dev, K.pinned, 0), "pinned address");
+  }
 }
 
 // ---- FGMRES as a host state machine: enqueue() puts the next unit of work on
@@ -631,8 +673,7 @@ void FgmresRun::start(MG &mg_, const double *b_, double *x_, int x0_nonzero,
   est = NAN;
   if (!x0_nonzero) launch_fill_f64(x, n, 0.0, st);
   // |b|^2 and |b - J x|^2
-  launch_mdot(n, b, n, 1, b, K.partial, 1, st);
-  launch_mdot_finish(K.partial, 1, 1, K.nrm + 1, 0, st);
+  launch_kdot(n, b, n, 1, b, K.partial, K.nrm + 1, st);
   enqueue_residual();
   hip_check(hipMemcpyAsync(K.pinned, K.nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "D2H");
   phase = kFirst;
@@ -643,35 +684,43 @@ void FgmresRun::enqueue_residual() {
   Level &F = mg->lv.back();
   const int n = F.n;
   launch_spmv(F.J.v64(), x, b, K.w, kSpmvResid, F.J.lpr, st);
-  launch_mdot(n, K.w, n, 1, K.w, K.partial, 1, st);
-  launch_mdot_finish(K.partial, 1, 1, K.nrm, 0, st);
+  launch_kdot(n, K.w, n, 1, K.w, K.partial, K.nrm, st);
+}
+
+// Arnoldi step j: v_j -> z_j = M^{-1} v_j -> w = J z_j -> orthogonalisation,
+// Givens column, v_{j+1}; |g_{j+1}| and the breakdown flag land in pinned memory
+void FgmresRun::enqueue_step() {
+  Krylov &K = mg->kry;
+  Level &F = mg->lv.back();
+  const int n = F.n, m = ko.restart;
+  if (j == 0) launch_start_cycle(n, K.w, K.nrm, K.V, K.g, m, st);
+  double *vj = K.V + (int64_t)j * n;
+  double *zj = K.Z + (int64_t)j * n;
+  apply_vcycle(*mg, vj, zj, st);
+  launch_spmv(F.J.v64(), zj, (const double *)nullptr, K.w, kSpmvSet, F.J.lpr, st);
+  launch_arnoldi_orth(n, K.V, n, j + 1, K.w, K.partial, K.h1, K.npart, K.V + (int64_t)(j + 1) * n,
+                      K.H, m + 1, j, K.cs, K.sn, K.g, K.flags, K.scal, K.pinned_dev, st);
 }
 
 void FgmresRun::enqueue() {
   if (phase != kIter) return;
   Krylov &K = mg->kry;
-  Level &F = mg->lv.back();
-  const int n = F.n, m = ko.restart;
-  const auto J = F.J.v64();
-  if (j == 0) launch_start_cycle(n, K.w, K.nrm, K.V, K.g, m, st);
-  double *vj = K.V + (int64_t)j * n;
-  double *zj = K.Z + (int64_t)j * n;
-  run_vcycle(*mg, vj, zj, st);
-  launch_spmv(J, zj, (const double *)nullptr, K.w, kSpmvSet, F.J.lpr, st);
-  // classical Gram-Schmidt, twice
-  launch_mdot(n, K.V, n, j + 1, K.w, K.partial, m + 2, st);
-  launch_mdot_finish(K.partial, m + 2, j + 1, K.h1, 0, st);
-  launch_mupdate(n, K.V, n, j + 1, K.h1, K.w, nullptr, st);
-  launch_mdot(n, K.V, n, j + 1, K.w, K.partial, m + 2, st);
-  launch_mdot_finish(K.partial, m + 2, j + 1, K.h2, 0, st);
-  launch_mupdate(n, K.V, n, j + 1, K.h2, K.w, K.npart, st);
-  launch_mdot_finish(K.partial, m + 2, j + 1, K.h1, 1, st);  // h1 += h2
-  launch_mdot_finish(K.npart, 1, 1, K.nrm + 2, 0, st);
-  launch_givens(K.H, m + 1, j, K.h1, K.nrm + 2, K.cs, K.sn, K.g, K.flags, K.scal, st);
-  launch_scale_to(n, K.w, K.scal, K.V + (int64_t)(j + 1) * n, st);
+  reinterpret_cast<volatile double *>(K.pinned)[2] = 0.0;   // set again by the step's last kernel
+  if (mg->opts.use_graph && !mg->prof_on) {
+    hipGraphExec_t &ex = K.step_graphs[j];
+    if (!ex) {
+      hipGraph_t g;
+      hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+      enqueue_step();
+      hip_check(hipStreamEndCapture(st, &g), "end capture");
+      hip_check(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "instantiate");
+      (void)hipGraphDestroy(g);
+    }
+    hip_check(hipGraphLaunch(ex, st), "graph launch");
+  } else {
+    enqueue_step();
+  }
   hip_check(hipGetLastError(), "arnoldi launch");
-  hip_check(hipMemcpyAsync(K.pinned, K.flags, 2 * sizeof(double), hipMemcpyDeviceToHost, st),
-            "D2H flags");
 }
 
 void FgmresRun::finish_cycle() {
@@ -756,10 +805,39 @@ fsi_status fgmres(MG &mg, const double *b, double *x, int x0_nonzero, const fsi_
                   fsi_solve_info *info, hipStream_t st) {
   FgmresRun run;
   run.start(mg, b, x, x0_nonzero, ko, st);
-  hip_check(hipStreamSynchronize(st), "fgmres start");
+  // A phase's outcome is a few bytes in pinned memory.  The start and restart
+  // phases copy it and are waited for by polling an event behind the copy; an
+  // Arnoldi step's last kernel writes it itself with a ready mark, which the
+  // host polls (the stream is queried now and then so that a failed launch
+  // cannot leave the host waiting).
+  auto wait_copy = [&](const char *what) {
+    hip_check(hipEventRecord(mg.kry.ev_done, st), what);
+    hipError_t e;
+    while ((e = hipEventQuery(mg.kry.ev_done)) == hipErrorNotReady) {
+    }
+    hip_check(e, what);
+  };
+  auto wait_step = [&]() {
+    volatile double *ready = mg.kry.pinned + 2;
+    for (unsigned spin = 1; *ready == 0.0; ++spin) {
+      if (spin % 4096 == 0) {
+        const hipError_t e = hipStreamQuery(st);
+        if (e == hipSuccess) {
+          if (*ready != 0.0) break;
+          throw Error(FSI_E_DEVICE, "Arnoldi step finished without its result");
+        }
+        if (e != hipErrorNotReady) hip_check(e, "fgmres step");
+      }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+  };
+  wait_copy("fgmres start");
   while (!run.complete()) {
     run.enqueue();
-    hip_check(hipStreamSynchronize(st), "fgmres step");
+    if (run.phase == FgmresRun::kIter)
+      wait_step();
+    else
+      wait_copy("fgmres restart");
   }
   run.fill_info(info);
   return run.converged ? FSI_OK : FSI_NOT_CONVERGED;
@@ -870,8 +948,7 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
     }
   }
   hip_check(hipGetLastError(), "autotune");
-  for (auto &kv : mg.graphs) (void)hipGraphExecDestroy(kv.second);
-  mg.graphs.clear();
+  clear_graphs(mg);
   if (db_path && measured) {
     if (FILE *f = fopen(db_path, "w")) {
       for (auto &kv : db) fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
