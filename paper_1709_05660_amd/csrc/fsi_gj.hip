@@ -282,13 +282,15 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
         const int q = ct * 16 + jl;
         const bool colok = q < mp;
         const int j = colok ? (q < p0 ? q : q + w) : 0;
+        // X: clamped loads issued together, zeroed outside the panel
         double bx[KC];
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-          const int t = kk * 4 + kq;
-          bx[kk] = (colok && t < w) ? A[sh.piv[t] * m + j] : 0.0;
-        }
-        // clamped addresses: loads never wait on anything; the pivot rows
+        for (int kk = 0; kk < KC; ++kk) bx[kk] = A[sh.piv[min(kk * 4 + kq, w - 1)] * m + j];
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk)
+          if (!(colok && kk * 4 + kq < w)) bx[kk] = 0.0;
+        // every load unconditional at a clamped address (prefetches past the
+        // last tile repeat it), so no load waits on a branch; the pivot rows
         // and the rows past m are zeroed where the tile is used
         auto load_tile = [&](int rt) {
           dx4 c;
@@ -298,26 +300,29 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
         };
         dx4 ring[kPrefetch];
 #pragma unroll
-        for (int u = 0; u < kPrefetch; ++u) ring[u] = load_tile(u);
+        for (int u = 0; u < kPrefetch; ++u) ring[u] = load_tile(min(u, nrt - 1));
         for (int rt0 = 0; rt0 < nrt; rt0 += kPrefetch) {
 #pragma unroll
           for (int u = 0; u < kPrefetch; ++u) {
             const int rt = rt0 + u;
+            dx4 c = ring[u];
+            ring[u] = load_tile(min(rt + kPrefetch, nrt - 1));
             if (rt < nrt) {
-              dx4 c = ring[u];
-              if (rt + kPrefetch < nrt) ring[u] = load_tile(rt + kPrefetch);
+              int su[4];
+              double a[KC];
+              const int ia = rt * 16 + jl;
+#pragma unroll
+              for (int r = 0; r < 4; ++r) su[r] = s_used[min(rt * 16 + r * 4 + kq, m - 1)];
+#pragma unroll
+              for (int kk = 0; kk < KC; ++kk) a[kk] = PC[min(ia, m - 1) * PS + kk * 4 + kq];
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const int i = rt * 16 + r * 4 + kq;
-                const int si = i < m ? s_used[i] : p0;
-                if (!(colok && i < m && (si < p0 || si >= p0 + w))) c[r] = 0.0;
+                if (!(colok && i < m && (su[r] < p0 || su[r] >= p0 + w))) c[r] = 0.0;
               }
-              const int ia = rt * 16 + jl;
 #pragma unroll
-              for (int kk = 0; kk < KC; ++kk) {
-                const double a = ia < m ? PC[ia * PS + kk * 4 + kq] : 0.0;
-                c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bx[kk], c, 0, 0, 0);
-              }
+              for (int kk = 0; kk < KC; ++kk)
+                c = __builtin_amdgcn_mfma_f64_16x16x4f64(ia < m ? a[kk] : 0.0, bx[kk], c, 0, 0, 0);
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const int i = rt * 16 + r * 4 + kq;
@@ -489,12 +494,16 @@ __device__ __forceinline__ void cgj_update_tile(double *__restrict__ A, int n, i
   const int q = ct * 16 + jl;
   const bool colok = q < mp;
   const int j = colok ? (q < p0 ? q : q + w) : 0;
+  // X: pivot rows' old values, clamped loads issued together (perm, then A)
+  int pr[KC];
+#pragma unroll
+  for (int kk = 0; kk < KC; ++kk) pr[kk] = perm[p0 + min(kk * 4 + kq, w - 1)];
   double bx[KC];
 #pragma unroll
-  for (int kk = 0; kk < KC; ++kk) {
-    const int t = kk * 4 + kq;
-    bx[kk] = (colok && t < w) ? A[perm[p0 + t] * ld + j] : 0.0;
-  }
+  for (int kk = 0; kk < KC; ++kk) bx[kk] = A[pr[kk] * ld + j];
+#pragma unroll
+  for (int kk = 0; kk < KC; ++kk)
+    if (!(colok && kk * 4 + kq < w)) bx[kk] = 0.0;
   __syncthreads();
   const int nrt = (n + 15) >> 4;
   // clamped addresses: no load waits on another; the pivot rows, the rows
@@ -517,16 +526,18 @@ __device__ __forceinline__ void cgj_update_tile(double *__restrict__ A, int n, i
     for (int kk = 0; kk < KC; ++kk) T.a[kk] = A[ia * ld + p0 + min(kk * 4 + kq, NB - 1)];
     return T;
   };
+  // prefetches are unconditional (past the last tile they repeat it), so no
+  // load waits on a branch
   Tile ring[kPrefetch];
 #pragma unroll
-  for (int u = 0; u < kPrefetch; ++u) ring[u] = load_tile(wave + NWV * u);
+  for (int u = 0; u < kPrefetch; ++u) ring[u] = load_tile(min(wave + NWV * u, nrt - 1));
   for (int rt0 = wave; rt0 < nrt; rt0 += NWV * kPrefetch) {
 #pragma unroll
     for (int u = 0; u < kPrefetch; ++u) {
       const int rt = rt0 + NWV * u;
+      Tile T = ring[u];
+      ring[u] = load_tile(min(rt + NWV * kPrefetch, nrt - 1));
       if (rt < nrt) {
-        Tile T = ring[u];
-        if (rt + NWV * kPrefetch < nrt) ring[u] = load_tile(rt + NWV * kPrefetch);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = rt * 16 + r * 4 + kq;
@@ -562,30 +573,47 @@ __global__ __launch_bounds__(256) void k_cgj_next(double *__restrict__ A, int n,
   __shared__ double X[NB][16];   // the pivot rows' values in the tile, staged once
   if (status[0]) return;
   const int tid = threadIdx.x, mp = n - w, q00 = (p0 / 16) * 16;
-  if (tid < 16 * NB) {
-    const int t = tid >> 4, q = q00 + (tid & 15);
-    X[t][tid & 15] = (t < w && q < mp) ? A[perm[p0 + t] * ld + (q < p0 ? q : q + w)] : 0.0;
-  }
-  __syncthreads();
+  // this thread's row: panel values (whole 16-byte pairs: p0 + NB <= ld) and
+  // its 4 tile entries, all loads issued before the X staging (clamped
+  // addresses; what lies outside is never stored)
   const int i = blockIdx.x * 64 + (tid >> 2);
-  if (i >= n) return;
-  const int s = used[i];
-  if (s >= p0 && s < p0 + w) return;
+  const int ic = min(i, n - 1);
+  const int s = used[ic];
   const int e0 = (tid & 3) * 4;
-  double *Ai = A + i * ld;
+  double *Ai = A + ic * ld;
   double pc[NB];
+  const double2 *pc2 = reinterpret_cast<const double2 *>(Ai + p0);
 #pragma unroll
-  for (int t = 0; t < NB; ++t) pc[t] = t < w ? Ai[p0 + t] : 0.0;
+  for (int c = 0; c < NB / 2; ++c) {
+    const double2 x = pc2[c];
+    pc[2 * c] = x.x;
+    pc[2 * c + 1] = x.y;
+  }
+  int jj[4];
+  double a[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const int q = q00 + e0 + e;
-    if (q < mp) {
-      const int j = q < p0 ? q : q + w;
-      double acc = Ai[j];
+    const int q = min(q00 + e0 + e, mp - 1);
+    jj[e] = q < p0 ? q : q + w;
+    a[e] = Ai[jj[e]];
+  }
+  if (tid < 16 * NB) {
+    const int t = tid >> 4, q = q00 + (tid & 15);
+    const int qc = min(q, mp - 1);
+    const double x = A[perm[p0 + min(t, w - 1)] * ld + (qc < p0 ? qc : qc + w)];
+    X[t][tid & 15] = (t < w && q < mp) ? x : 0.0;
+  }
+  __syncthreads();
+  if (i >= n || (s >= p0 && s < p0 + w)) return;
 #pragma unroll
-      for (int t = 0; t < NB; ++t) acc += pc[t] * X[t][e0 + e];
-      Ai[j] = acc;
-    }
+  for (int t = 0; t < NB; ++t)
+    if (t >= w) pc[t] = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    double acc = a[e];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) acc += pc[t] * X[t][e0 + e];
+    if (q00 + e0 + e < mp) Ai[jj[e]] = acc;
   }
 }
 
@@ -621,15 +649,29 @@ __global__ __launch_bounds__(NT) void k_cgj_step(double *__restrict__ A, int n, 
   double val = 0.0;
   int64_t dst = -1;
   if (tid < 16 * w) {
+    // clamped loads issued together: the panel's pivot rows, then this
+    // thread's pivot-row panel values and the pivot rows' tile column
     const int sidx = tid >> 4, q = ct * 16 + (tid & 15);
-    if (q < mp) {
-      const int j = q < p0 ? q : q + w;
-      const double *pr = A + perm[p0 + sidx] * ld + p0;
+    const int qc = min(q, mp - 1);
+    const int j = qc < p0 ? qc : qc + w;
+    int pv[NB];
 #pragma unroll
-      for (int t = 0; t < NB; ++t)
-        if (t < w) val += pr[t] * A[perm[p0 + t] * ld + j];
-      dst = perm[p0 + sidx] * ld + j;
+    for (int t = 0; t < NB; ++t) pv[t] = perm[p0 + min(t, w - 1)];
+    const double2 *pr2 = reinterpret_cast<const double2 *>(A + pv[sidx] * ld + p0);
+    double prv[NB], xa[NB];
+#pragma unroll
+    for (int c = 0; c < NB / 2; ++c) {
+      const double2 x = pr2[c];
+      prv[2 * c] = x.x;
+      prv[2 * c + 1] = x.y;
     }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) xa[t] = A[pv[t] * ld + j];
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+      if (t < w) val += prv[t] * xa[t];
+    if (q < mp) dst = pv[sidx] * ld + j;
+    else val = 0.0;
     fix[sidx][tid & 15] = val;
   }
   __syncthreads();
@@ -645,15 +687,15 @@ __global__ __launch_bounds__(NT) void k_cgj_step(double *__restrict__ A, int n, 
   cgj_factor<NB, R, NT>(A, n, ld, pn, wn, perm, used, status, sh, v, stp);
 }
 
-// C0[c * n + k] = inv(A)[k][c] = S[perm[k]][used[c]] (column-major, dense GEMV layout)
+// C0[k * n + c] = inv(A)[k][c] = S[perm[k]][used[c]] (row-major, the dense GEMV layout)
 __global__ void k_cgj_finish(const double *__restrict__ S, int n, int64_t ld,
                              const int *__restrict__ perm, const int *__restrict__ used,
                              const int *__restrict__ status, double *__restrict__ C0) {
   if (status[0]) return;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
-  if (k >= n) return;
-  C0[(int64_t)c * n + k] = S[perm[k] * ld + used[c]];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (c >= n) return;
+  C0[(int64_t)k * n + c] = S[perm[k] * ld + used[c]];
 }
 
 template <int NB, int R, int NT>

@@ -52,8 +52,9 @@ struct Level {
   uint16_t *W16 = nullptr;
   float *Wscale = nullptr, *Cscale = nullptr;
   int w16_kind = 0;
-  // coarsest level: column-major inverse
-  double *C0 = nullptr, *gemv_partial = nullptr;
+  bool all_owned = false;   // every dof owned by a patch (a smoothing step can store, not add)
+  // coarsest level: row-major inverse
+  double *C0 = nullptr;
   // work vectors
   double *r = nullptr, *e = nullptr, *s = nullptr;
   float *r32 = nullptr, *e32 = nullptr, *s32 = nullptr;

@@ -9,7 +9,6 @@ namespace fsi {
 
 constexpr int kWave = 64;
 constexpr int kMaxPatch = 800;      // largest Schwarz block handled by one wave's LDS slice
-constexpr int kGemvSplit = 32;      // column chunks of the coarsest GEMV (partial buffer: kGemvSplit n)
 
 // CSR on the device: int32 offsets and columns (sizes checked at upload).
 template <typename T>
@@ -40,7 +39,7 @@ void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const
                        int *perm, int *used, int npatch, int mmax, int *status, hipStream_t st,
                        int nb_req = 0);
 // inverse of the coarsest operator (row-major n x n, leading dimension ld,
-// n <= kMaxCoarse), written column-major to C0; iwork: 2 n ints; status[0]
+// n <= kMaxCoarse), written row-major to C0; iwork: 2 n ints; status[0]
 // = 0 ok, else 1 + failing step
 constexpr int kMaxCoarse = 6144;
 void launch_fill_i32(int *x, int n, int v, hipStream_t st);
@@ -70,18 +69,21 @@ struct RasView {
   const int *dof, *out_off, *out_idx;
   const float *cscale;   // 16-bit storage: column scales (per patch dof), else null
 };
-// ev0/ev1: optional events recorded at the finest-level kernel's start and end
+// e[owned dofs] (+= when add, else =) omega * (owned rows of B_k^{-1}) s_k; with
+// add false the dofs no patch owns are left untouched.  ev0/ev1: optional
+// events recorded at the finest-level kernel's start and end
 void launch_ras_f64(const RasView &v, const double *W, const double *s, double *e, double omega,
-                    bool finest, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                    bool finest, bool add, hipStream_t st, hipEvent_t ev0 = nullptr,
+                    hipEvent_t ev1 = nullptr);
 void launch_ras_f32(const RasView &v, const float *W, const float *s, float *e, float omega,
-                    bool finest, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                    bool finest, bool add, hipStream_t st, hipEvent_t ev0 = nullptr,
+                    hipEvent_t ev1 = nullptr);
 void launch_ras_16(const RasView &v, const uint16_t *W, int w16_kind, const float *wscale,
-                   const float *s, float *e, float omega, bool finest, hipStream_t st,
+                   const float *s, float *e, float omega, bool finest, bool add, hipStream_t st,
                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
-// ---- coarsest solve (a7): y = W x, W column-major n x n FP64
-void launch_dense_gemv(const double *W, int n, const double *x, double *y, double *partial,
-                       hipStream_t st);
+// ---- coarsest solve (a7): y = W x, W row-major n x n FP64
+void launch_dense_gemv(const double *W, int n, const double *x, double *y, hipStream_t st);
 
 // ---- vectors
 void launch_cast_d2f(const double *x, float *y, int n, hipStream_t st);

@@ -378,7 +378,8 @@ void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm,
 // per task, so the workgroup's rows are one contiguous region and one step
 // over a column is one coalesced load of the task's rows, eight loads in
 // flight per lane), the partial sums meet in LDS and lane r of the first wave adds
-// omega times row r to its owned dof.  TAG only names the finest-level launch.
+// omega times row r to its owned dof (or stores it, when add is 0: a zero
+// initial correction).  TAG only names the finest-level launch.
 __device__ inline float w16val(uint16_t v, int kind) {
   return kind == 1 ? from_bf16(v) : from_fp16(v);
 }
@@ -395,7 +396,7 @@ template <typename WT, typename VT, typename AT, bool IS16, int TAG>
 __global__ __launch_bounds__(256) void k_ras(RasView v, const WT *__restrict__ W, int w16_kind,
                                              const float *__restrict__ wscale,
                                              const VT *__restrict__ s, VT *__restrict__ e,
-                                             AT omega) {
+                                             AT omega, int add) {
   __shared__ AT xs[kMaxPatch];
   __shared__ AT red[3][64];
   const int wave = threadIdx.x >> 6;
@@ -447,70 +448,71 @@ __global__ __launch_bounds__(256) void k_ras(RasView v, const WT *__restrict__ W
     acc = ((acc + red[0][lane]) + red[1][lane]) + red[2][lane];
     if constexpr (IS16) acc *= (AT)wscale[v.out_off[k] + row];
     const int g = v.out_idx[v.out_off[k] + row];
-    e[g] = e[g] + (VT)(omega * acc);
+    const VT upd = (VT)(omega * acc);
+    e[g] = add ? e[g] + upd : upd;
   }
 }
 
 // ev0/ev1 (optional, finest level): timing events recorded at the kernel's
 // own start and end (hipExtLaunchKernelGGL), not around its launch
 void launch_ras_f64(const RasView &v, const double *W, const double *s, double *e, double omega,
-                    bool finest, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                    bool finest, bool add, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (v.ntask == 0) return;
   if (finest)
     hipExtLaunchKernelGGL(k_ras<double, double, double, false, 1>, dim3(v.ntask), dim3(256), 0, st,
-                          ev0, ev1, 0, v, W, 0, (const float *)nullptr, s, e, omega);
+                          ev0, ev1, 0, v, W, 0, (const float *)nullptr, s, e, omega, (int)add);
   else
-    k_ras<double, double, double, false, 0><<<v.ntask, 256, 0, st>>>(v, W, 0, nullptr, s, e, omega);
+    k_ras<double, double, double, false, 0><<<v.ntask, 256, 0, st>>>(v, W, 0, nullptr, s, e, omega,
+                                                                      (int)add);
 }
 void launch_ras_f32(const RasView &v, const float *W, const float *s, float *e, float omega,
-                    bool finest, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                    bool finest, bool add, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (v.ntask == 0) return;
   if (finest)
     hipExtLaunchKernelGGL(k_ras<float, float, float, false, 1>, dim3(v.ntask), dim3(256), 0, st, ev0,
-                          ev1, 0, v, W, 0, (const float *)nullptr, s, e, omega);
+                          ev1, 0, v, W, 0, (const float *)nullptr, s, e, omega, (int)add);
   else
-    k_ras<float, float, float, false, 0><<<v.ntask, 256, 0, st>>>(v, W, 0, nullptr, s, e, omega);
+    k_ras<float, float, float, false, 0><<<v.ntask, 256, 0, st>>>(v, W, 0, nullptr, s, e, omega,
+                                                                   (int)add);
 }
 void launch_ras_16(const RasView &v, const uint16_t *W, int w16_kind, const float *wscale,
-                   const float *s, float *e, float omega, bool finest, hipStream_t st,
+                   const float *s, float *e, float omega, bool finest, bool add, hipStream_t st,
                    hipEvent_t ev0, hipEvent_t ev1) {
   if (v.ntask == 0) return;
   if (finest)
     hipExtLaunchKernelGGL(k_ras<uint16_t, float, float, true, 1>, dim3(v.ntask), dim3(256), 0, st,
-                          ev0, ev1, 0, v, W, w16_kind, wscale, s, e, omega);
+                          ev0, ev1, 0, v, W, w16_kind, wscale, s, e, omega, (int)add);
   else
-    k_ras<uint16_t, float, float, true, 0><<<v.ntask, 256, 0, st>>>(v, W, w16_kind, wscale, s, e, omega);
+    k_ras<uint16_t, float, float, true, 0><<<v.ntask, 256, 0, st>>>(v, W, w16_kind, wscale, s, e,
+                                                                    omega, (int)add);
 }
 
 // ------------------------------------------------------------------ coarsest solve GEMV
-__global__ __launch_bounds__(256) void k_gemv_partial(const double *__restrict__ W, int n,
-                                                      const double *__restrict__ x,
-                                                      double *__restrict__ partial) {
-  __shared__ double red[4][64];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 64 + lane;
-  const int chunk = (n + kGemvSplit - 1) / kGemvSplit;
-  const int c0 = blockIdx.y * chunk, c1 = min(n, c0 + chunk);
-  double acc = 0.0;
-  if (row < n)
-    for (int c = c0 + wave; c < c1; c += 4) acc += W[(int64_t)c * n + row] * x[c];
-  red[wave][lane] = acc;
-  __syncthreads();
-  if (wave == 0 && row < n)
-    partial[(int64_t)blockIdx.y * n + row] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+// y = W x with W row-major: one wave per row streams the row (64 consecutive
+// doubles per load, four loads in flight), then a fixed butterfly
+__global__ __launch_bounds__(256) void k_gemv_rows(const double *__restrict__ W, int n,
+                                                   const double *__restrict__ x,
+                                                   double *__restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const double *w = W + (int64_t)row * n;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int c = lane;
+  for (; c + 192 < n; c += 256) {
+    a0 += w[c] * x[c];
+    a1 += w[c + 64] * x[c + 64];
+    a2 += w[c + 128] * x[c + 128];
+    a3 += w[c + 192] * x[c + 192];
+  }
+  for (; c < n; c += 64) a0 += w[c] * x[c];
+  double acc = (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) y[row] = acc;
 }
-__global__ void k_gemv_finish(const double *partial, int n, double *y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int q = 0; q < kGemvSplit; ++q) s += partial[(int64_t)q * n + i];
-  y[i] = s;
-}
-void launch_dense_gemv(const double *W, int n, const double *x, double *y, double *partial,
-                       hipStream_t st) {
-  dim3 grid(cdiv(n, 64), kGemvSplit);
-  k_gemv_partial<<<grid, 256, 0, st>>>(W, n, x, partial);
-  k_gemv_finish<<<cdiv(n, 256), 256, 0, st>>>(partial, n, y);
+void launch_dense_gemv(const double *W, int n, const double *x, double *y, hipStream_t st) {
+  if (n > 0) k_gemv_rows<<<cdiv(n, 4), 256, 0, st>>>(W, n, x, y);
 }
 
 // Arnoldi column j (one thread): H[:, j] = h, |w| and breakdown test, the

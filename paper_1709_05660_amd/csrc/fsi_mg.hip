@@ -186,6 +186,7 @@ static void build_patch_layout(Level &L, const fsi_patches &P, MG &mg, hipStream
     L.sum_om += (int64_t)o * pm[k];
   }
   L.total_owned = out_off[np];
+  L.all_owned = L.total_owned == L.n;
   L.ntask = (int)task_patch.size();
   auto &own = mg.owned;
   L.d_pm = dupload(pm.data(), np, own, st);
@@ -341,93 +342,116 @@ static hipEvent_t *prof_pair(MG &mg, Level &L) {
   }
   return &mg.prof_ev[mg.prof_used++].first;
 }
-static void ras64(MG &mg, Level &L, const double *s, double *e, hipStream_t st) {
+static void ras64(MG &mg, Level &L, const double *s, double *e, bool add, hipStream_t st) {
   hipEvent_t *ev = prof_pair(mg, L);
-  launch_ras_f64(ras_view(L), L.W64, s, e, mg.opts.omega, &L == &mg.lv.back(), st,
+  launch_ras_f64(ras_view(L), L.W64, s, e, mg.opts.omega, &L == &mg.lv.back(), add, st,
                  ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
 }
-static void ras32(MG &mg, Level &L, const float *s, float *e, hipStream_t st) {
+static void ras32(MG &mg, Level &L, const float *s, float *e, bool add, hipStream_t st) {
   hipEvent_t *ev = prof_pair(mg, L);
   if (L.W32)
-    launch_ras_f32(ras_view(L), L.W32, s, e, (float)mg.opts.omega, &L == &mg.lv.back(), st,
+    launch_ras_f32(ras_view(L), L.W32, s, e, (float)mg.opts.omega, &L == &mg.lv.back(), add, st,
                    ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
   else
     launch_ras_16(ras_view(L), L.W16, L.w16_kind, L.Wscale, s, e, (float)mg.opts.omega,
-                  &L == &mg.lv.back(), st, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
+                  &L == &mg.lv.back(), add, st, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
 }
 
-// FP64 V-cycle on level l: input L.r, output L.e
-static void vcycle64(MG &mg, int l, hipStream_t st) {
-  Level &L = mg.lv[l];
-  if (l == 0) {
-    launch_dense_gemv(L.C0, L.n, L.r, L.e, L.gemv_partial, st);
-    return;
+// One V-cycle on level l for e = M_l^{-1} r (r and e distinct; the finest
+// level works on the caller's vectors directly).  The first smoothing step
+// starts from e = 0: it stores its correction instead of adding it when
+// every dof is owned by a patch (no zero fill), and without pre-smoothing
+// the coarse correction is stored into e.
+template <typename T>
+struct VOps;
+template <>
+struct VOps<double> {
+  static CsrView<double> J(Level &L) { return L.J.v64(); }
+  static CsrView<double> R(Level &L) { return L.R.v64(); }
+  static CsrView<double> P(Level &L) { return L.P.v64(); }
+  static double *r(Level &L) { return L.r; }
+  static double *e(Level &L) { return L.e; }
+  static double *s(Level &L) { return L.s; }
+  static void fill(double *x, int n, hipStream_t st) { launch_fill_f64(x, n, 0.0, st); }
+  static void ras(MG &mg, Level &L, const double *s, double *e, bool add, hipStream_t st) {
+    ras64(mg, L, s, e, add, st);
   }
-  Level &C = mg.lv[l - 1];
-  const auto J = L.J.v64();
-  launch_fill_f64(L.e, L.n, 0.0, st);
-  for (int it = 0; it < mg.opts.nu_pre; ++it) {
-    if (it == 0) {
-      ras64(mg, L, L.r, L.e, st);
-    } else {
-      launch_spmv(J, L.e, L.r, L.s, kSpmvResid, L.J.lpr, st);
-      ras64(mg, L, L.s, L.e, st);
-    }
+};
+template <>
+struct VOps<float> {
+  static CsrView<float> J(Level &L) { return L.J.v32(); }
+  static CsrView<float> R(Level &L) { return L.R.v32(); }
+  static CsrView<float> P(Level &L) { return L.P.v32(); }
+  static float *r(Level &L) { return L.r32; }
+  static float *e(Level &L) { return L.e32; }
+  static float *s(Level &L) { return L.s32; }
+  static void fill(float *x, int n, hipStream_t st) { launch_fill_f32(x, n, 0.0f, st); }
+  static void ras(MG &mg, Level &L, const float *s, float *e, bool add, hipStream_t st) {
+    ras32(mg, L, s, e, add, st);
   }
-  if (mg.opts.nu_pre == 0)
-    launch_copy_f64(L.n, L.r, L.s, st);
-  else
-    launch_spmv(J, L.e, L.r, L.s, kSpmvResid, L.J.lpr, st);
-  launch_spmv(L.R.v64(), L.s, (const double *)nullptr, C.r, kSpmvSet, L.R.lpr, st);
-  vcycle64(mg, l - 1, st);
-  launch_spmv(L.P.v64(), C.e, (const double *)nullptr, L.e, kSpmvAdd, L.P.lpr, st);
-  for (int it = 0; it < mg.opts.nu_post; ++it) {
-    launch_spmv(J, L.e, L.r, L.s, kSpmvResid, L.J.lpr, st);
-    ras64(mg, L, L.s, L.e, st);
-  }
+};
+
+// the coarsest solve: FP64 dense inverse (the mixed cycle converts around it)
+static void coarse_solve(MG &mg, const double *r, double *e, hipStream_t st) {
+  Level &L = mg.lv[0];
+  launch_dense_gemv(L.C0, L.n, r, e, st);
+}
+static void coarse_solve(MG &mg, const float *r, float *e, hipStream_t st) {
+  Level &L = mg.lv[0];
+  launch_cast_f2d(r, L.r, L.n, st);
+  launch_dense_gemv(L.C0, L.n, L.r, L.e, st);
+  launch_cast_d2f(L.e, e, L.n, st);
 }
 
-// mixed V-cycle: FP32 on levels >= 1, FP64 coarsest solve
-static void vcycle32(MG &mg, int l, hipStream_t st) {
-  Level &L = mg.lv[l];
+template <typename T>
+static void vcycle(MG &mg, int l, const T *r, T *e, hipStream_t st) {
+  using O = VOps<T>;
   if (l == 0) {
-    launch_cast_f2d(L.r32, L.r, L.n, st);
-    launch_dense_gemv(L.C0, L.n, L.r, L.e, L.gemv_partial, st);
-    launch_cast_d2f(L.e, L.e32, L.n, st);
+    coarse_solve(mg, r, e, st);
     return;
   }
+  Level &L = mg.lv[l];
   Level &C = mg.lv[l - 1];
-  const auto J = L.J.v32();
-  launch_fill_f32(L.e32, L.n, 0.0f, st);
-  for (int it = 0; it < mg.opts.nu_pre; ++it) {
+  const auto J = O::J(L);
+  T *s = O::s(L);
+  const int nu_pre = mg.opts.nu_pre;
+  for (int it = 0; it < nu_pre; ++it) {
     if (it == 0) {
-      ras32(mg, L, L.r32, L.e32, st);
+      if (!L.all_owned) O::fill(e, L.n, st);
+      O::ras(mg, L, r, e, !L.all_owned, st);
     } else {
-      launch_spmv(J, L.e32, L.r32, L.s32, kSpmvResid, L.J.lpr, st);
-      ras32(mg, L, L.s32, L.e32, st);
+      launch_spmv(J, e, r, s, kSpmvResid, L.J.lpr, st);
+      O::ras(mg, L, s, e, true, st);
     }
   }
-  launch_spmv(J, L.e32, L.r32, L.s32, kSpmvResid, L.J.lpr, st);
-  launch_spmv(L.R.v32(), L.s32, (const float *)nullptr, C.r32, kSpmvSet, L.R.lpr, st);
-  vcycle32(mg, l - 1, st);
-  launch_spmv(L.P.v32(), C.e32, (const float *)nullptr, L.e32, kSpmvAdd, L.P.lpr, st);
+  if (nu_pre == 0) {
+    launch_spmv(O::R(L), r, (const T *)nullptr, O::r(C), kSpmvSet, L.R.lpr, st);
+  } else {
+    launch_spmv(J, e, r, s, kSpmvResid, L.J.lpr, st);
+    launch_spmv(O::R(L), s, (const T *)nullptr, O::r(C), kSpmvSet, L.R.lpr, st);
+  }
+  vcycle<T>(mg, l - 1, O::r(C), O::e(C), st);
+  launch_spmv(O::P(L), O::e(C), (const T *)nullptr, e, nu_pre == 0 ? kSpmvSet : kSpmvAdd,
+              L.P.lpr, st);
   for (int it = 0; it < mg.opts.nu_post; ++it) {
-    launch_spmv(J, L.e32, L.r32, L.s32, kSpmvResid, L.J.lpr, st);
-    ras32(mg, L, L.s32, L.e32, st);
+    launch_spmv(J, e, r, s, kSpmvResid, L.J.lpr, st);
+    O::ras(mg, L, s, e, true, st);
   }
 }
 
 // z = M^{-1} r (device FP64 vectors of the finest size)
 void apply_vcycle(MG &mg, const double *r, double *z, hipStream_t st) {
   Level &F = mg.lv.back();
-  if (mg.mixed) {
+  if (r == z) {
+    launch_copy_f64(F.n, r, F.r, st);
+    r = F.r;
+  }
+  if (mg.mixed && mg.nlevels > 1) {
     launch_cast_d2f(r, F.r32, F.n, st);
-    vcycle32(mg, mg.nlevels - 1, st);
+    vcycle<float>(mg, mg.nlevels - 1, F.r32, F.e32, st);
     launch_cast_f2d(F.e32, z, F.n, st);
   } else {
-    launch_copy_f64(F.n, r, F.r, st);
-    vcycle64(mg, mg.nlevels - 1, st);
-    launch_copy_f64(F.n, F.e, z, st);
+    vcycle<double>(mg, mg.nlevels - 1, r, z, st);
   }
 }
 
@@ -553,7 +577,6 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
     mg->dense_scratch = dalloc<double>(n0 * mg->dense_ld, mg->owned);
     mg->gj_work = dalloc<double>(n0 + 64, mg->owned);
     mg->lv[0].C0 = dalloc<double>(n0 * n0, mg->owned);
-    mg->lv[0].gemv_partial = dalloc<double>((int64_t)kGemvSplit * n0, mg->owned);
     hip_check(hipStreamCreateWithFlags(&mg->side_stream, hipStreamNonBlocking), "side stream");
     hip_check(hipEventCreateWithFlags(&mg->ev_fork, hipEventDisableTiming), "event");
     hip_check(hipEventCreateWithFlags(&mg->ev_join, hipEventDisableTiming), "event");
@@ -1064,11 +1087,12 @@ fsi_status fsi_mg_apply(struct fsi_mg *h, int32_t level, int32_t op, const doubl
         if (level == 0) throw Error(FSI_E_INVALID, "no patches on level 0");
         if (!L.W64) throw Error(FSI_E_INVALID, "op 4 needs the FP64 precision");
         launch_fill_f64(y_dev, L.n, 0.0, st);
-        launch_ras_f64(ras_view(L), L.W64, x_dev, y_dev, 1.0, level == mg->nlevels - 1, st);
+        launch_ras_f64(ras_view(L), L.W64, x_dev, y_dev, 1.0, level == mg->nlevels - 1, true,
+                       st);
         break;
       case 5:
         if (level != 0) throw Error(FSI_E_INVALID, "direct solve only on level 0");
-        launch_dense_gemv(L.C0, L.n, x_dev, y_dev, L.gemv_partial, st);
+        launch_dense_gemv(L.C0, L.n, x_dev, y_dev, st);
         break;
       default: throw Error(FSI_E_INVALID, "unknown op");
     }

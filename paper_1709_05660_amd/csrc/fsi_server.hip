@@ -81,7 +81,7 @@ static int64_t footprint(const fsi_level *lv, int nl, const fsi_mg_opts &mo,
     auto csr = [&](const fsi_csr &A) { return (A.nrows + 1) * 4 + A.nnz * (4 + 8 + (mixed ? 4 : 0)); };
     res += csr(lv[l].J) + 6 * n * 8;
     if (l == 0) {
-      res += n * n * 8 + (int64_t)kGemvSplit * n * 8;
+      res += n * n * 8;
       transient = std::max<int64_t>(transient, n * ((n + 15) / 16 * 16) * 8 + 2 * n * 8);
       continue;
     }
