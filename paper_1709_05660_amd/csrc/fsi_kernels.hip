@@ -373,13 +373,15 @@ void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm,
 
 // ------------------------------------------------------------------ restricted Schwarz
 // One workgroup per (patch, 64 owned rows).  The patch's residual entries
-// are gathered once into LDS; each of the four waves accumulates its quarter
+// are gathered once into LDS; each of the NWV waves accumulates its share
 // of the columns of the task's owned rows of B_k^{-1} (stored column-major
 // per task, so the workgroup's rows are one contiguous region and one step
 // over a column is one coalesced load of the task's rows, eight loads in
-// flight per lane), the partial sums meet in LDS and lane r of the first wave adds
-// omega times row r to its owned dof (or stores it, when add is 0: a zero
-// initial correction).  TAG only names the finest-level launch.
+// flight per lane), the partial sums meet in LDS and lane r of the first
+// wave adds omega times row r to its owned dof (or stores it, when add is 0:
+// a zero initial correction).  Levels with few tasks use more waves per
+// workgroup (a shorter chain of loads per wave).  TAG only names the
+// finest-level launch.
 __device__ inline float w16val(uint16_t v, int kind) {
   return kind == 1 ? from_bf16(v) : from_fp16(v);
 }
@@ -392,13 +394,13 @@ __device__ inline AT wload(const WT *w, int64_t idx, int kind) {
     return (AT)w[idx];
 }
 
-template <typename WT, typename VT, typename AT, bool IS16, int TAG>
-__global__ __launch_bounds__(256) void k_ras(RasView v, const WT *__restrict__ W, int w16_kind,
-                                             const float *__restrict__ wscale,
-                                             const VT *__restrict__ s, VT *__restrict__ e,
-                                             AT omega, int add) {
+template <typename WT, typename VT, typename AT, bool IS16, int TAG, int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_ras(RasView v, const WT *__restrict__ W,
+                                                  int w16_kind, const float *__restrict__ wscale,
+                                                  const VT *__restrict__ s,
+                                                  VT *__restrict__ e, AT omega, int add) {
   __shared__ AT xs[kMaxPatch];
-  __shared__ AT red[3][64];
+  __shared__ AT red[NWV - 1][64];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int task = blockIdx.x;
@@ -408,8 +410,8 @@ __global__ __launch_bounds__(256) void k_ras(RasView v, const WT *__restrict__ W
   const int *d = v.dof + v.pdof_off[k];
   const int row = r0 + lane;
   const bool live = row < o;
-  const int quarter = (m + 3) >> 2;
-  const int c0 = wave * quarter, c1 = min(m, c0 + quarter);
+  const int share = (m + NWV - 1) / NWV;
+  const int c0 = wave * share, c1 = min(m, c0 + share);
   // this wave's columns stream 8 at a time, one chunk ahead of the one being
   // summed; the first chunk is issued before the residual gather so that no
   // workgroup starts with an idle memory pipe (clamped addresses; columns
@@ -421,12 +423,12 @@ __global__ __launch_bounds__(256) void k_ras(RasView v, const WT *__restrict__ W
     for (int u = 0; u < 8; ++u) wv[u] = wload<WT, AT, IS16>(w, (int64_t)min(c + u, m - 1) * nr, w16_kind);
   };
   AT cur[8];
-  load8(c0, cur);
+  load8(min(c0, m - 1), cur);
   if constexpr (IS16) {
     const float *cs = v.cscale + v.pdof_off[k];
-    for (int c = threadIdx.x; c < m; c += 256) xs[c] = (AT)s[d[c]] * (AT)cs[c];
+    for (int c = threadIdx.x; c < m; c += 64 * NWV) xs[c] = (AT)s[d[c]] * (AT)cs[c];
   } else {
-    for (int c = threadIdx.x; c < m; c += 256) xs[c] = (AT)s[d[c]];
+    for (int c = threadIdx.x; c < m; c += 64 * NWV) xs[c] = (AT)s[d[c]];
   }
   __syncthreads();
   AT a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -445,7 +447,8 @@ __global__ __launch_bounds__(256) void k_ras(RasView v, const WT *__restrict__ W
   if (wave > 0) red[wave - 1][lane] = acc;
   __syncthreads();
   if (wave == 0 && live) {
-    acc = ((acc + red[0][lane]) + red[1][lane]) + red[2][lane];
+#pragma unroll
+    for (int q = 0; q < NWV - 1; ++q) acc += red[q][lane];
     if constexpr (IS16) acc *= (AT)wscale[v.out_off[k] + row];
     const int g = v.out_idx[v.out_off[k] + row];
     const VT upd = (VT)(omega * acc);
@@ -455,36 +458,51 @@ __global__ __launch_bounds__(256) void k_ras(RasView v, const WT *__restrict__ W
 
 // ev0/ev1 (optional, finest level): timing events recorded at the kernel's
 // own start and end (hipExtLaunchKernelGGL), not around its launch
+static int ras_waves(int ntask) { return ntask >= 1024 ? 4 : (ntask >= 256 ? 8 : 16); }
+
+template <typename WT, typename VT, typename AT, bool IS16, int NWV>
+static void launch_ras_nw(const RasView &v, const WT *W, int w16_kind, const float *wscale,
+                          const VT *s, VT *e, AT omega, bool finest, bool add, hipStream_t st,
+                          hipEvent_t ev0, hipEvent_t ev1) {
+  if (finest)
+    hipExtLaunchKernelGGL(k_ras<WT, VT, AT, IS16, 1, NWV>, dim3(v.ntask), dim3(64 * NWV), 0, st,
+                          ev0, ev1, 0, v, W, w16_kind, wscale, s, e, omega, (int)add);
+  else
+    k_ras<WT, VT, AT, IS16, 0, NWV><<<v.ntask, 64 * NWV, 0, st>>>(v, W, w16_kind, wscale, s, e,
+                                                                 omega, (int)add);
+}
+template <typename WT, typename VT, typename AT, bool IS16>
+static void launch_ras_any(const RasView &v, const WT *W, int w16_kind, const float *wscale,
+                           const VT *s, VT *e, AT omega, bool finest, bool add, hipStream_t st,
+                           hipEvent_t ev0, hipEvent_t ev1) {
+  if (v.ntask == 0) return;
+  switch (ras_waves(v.ntask)) {
+    case 4:
+      launch_ras_nw<WT, VT, AT, IS16, 4>(v, W, w16_kind, wscale, s, e, omega, finest, add, st, ev0, ev1);
+      break;
+    case 8:
+      launch_ras_nw<WT, VT, AT, IS16, 8>(v, W, w16_kind, wscale, s, e, omega, finest, add, st, ev0, ev1);
+      break;
+    default:
+      launch_ras_nw<WT, VT, AT, IS16, 16>(v, W, w16_kind, wscale, s, e, omega, finest, add, st, ev0,
+                                          ev1);
+  }
+}
 void launch_ras_f64(const RasView &v, const double *W, const double *s, double *e, double omega,
                     bool finest, bool add, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  if (v.ntask == 0) return;
-  if (finest)
-    hipExtLaunchKernelGGL(k_ras<double, double, double, false, 1>, dim3(v.ntask), dim3(256), 0, st,
-                          ev0, ev1, 0, v, W, 0, (const float *)nullptr, s, e, omega, (int)add);
-  else
-    k_ras<double, double, double, false, 0><<<v.ntask, 256, 0, st>>>(v, W, 0, nullptr, s, e, omega,
-                                                                      (int)add);
+  launch_ras_any<double, double, double, false>(v, W, 0, nullptr, s, e, omega, finest, add, st,
+                                                ev0, ev1);
 }
 void launch_ras_f32(const RasView &v, const float *W, const float *s, float *e, float omega,
                     bool finest, bool add, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  if (v.ntask == 0) return;
-  if (finest)
-    hipExtLaunchKernelGGL(k_ras<float, float, float, false, 1>, dim3(v.ntask), dim3(256), 0, st, ev0,
-                          ev1, 0, v, W, 0, (const float *)nullptr, s, e, omega, (int)add);
-  else
-    k_ras<float, float, float, false, 0><<<v.ntask, 256, 0, st>>>(v, W, 0, nullptr, s, e, omega,
-                                                                   (int)add);
+  launch_ras_any<float, float, float, false>(v, W, 0, nullptr, s, e, omega, finest, add, st, ev0,
+                                             ev1);
 }
 void launch_ras_16(const RasView &v, const uint16_t *W, int w16_kind, const float *wscale,
                    const float *s, float *e, float omega, bool finest, bool add, hipStream_t st,
                    hipEvent_t ev0, hipEvent_t ev1) {
-  if (v.ntask == 0) return;
-  if (finest)
-    hipExtLaunchKernelGGL(k_ras<uint16_t, float, float, true, 1>, dim3(v.ntask), dim3(256), 0, st,
-                          ev0, ev1, 0, v, W, w16_kind, wscale, s, e, omega, (int)add);
-  else
-    k_ras<uint16_t, float, float, true, 0><<<v.ntask, 256, 0, st>>>(v, W, w16_kind, wscale, s, e,
-                                                                    omega, (int)add);
+  launch_ras_any<uint16_t, float, float, true>(v, W, w16_kind, wscale, s, e, omega, finest, add,
+                                               st, ev0, ev1);
 }
 
 // ------------------------------------------------------------------ coarsest solve GEMV
