@@ -65,7 +65,7 @@ def measured_traffic():
 def gpu_leg(args):
     import torch
 
-    from paper_1709_05660_amd import MG, Problem
+    from paper_1709_05660_amd import MG, Problem, stream_read_gbps
     from synth import config, fourier_coefficients
 
     spec = config(WORKLOAD)
@@ -140,6 +140,13 @@ def gpu_leg(args):
                            "frac": round(achieved / 8000.0, 4), "traffic": measured_traffic(),
                            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": cnt,
                            "bytes_per_launch": int(bytes_per_launch)}
+        # what a plain streaming read of the same byte count achieves on this
+        # device (a library reduction over a float64 tensor), for context
+        ceil = stream_read_gbps(int(bytes_per_launch))
+        out["roofline"]["read_ceiling"] = {
+            "kernel": "fsi_stream_read: plain 16-byte streaming read of the same byte count",
+            "achieved": round(ceil, 1), "unit": "GB/s",
+            "frac_of_ceiling": round(achieved / ceil, 4) if ceil else None}
         if args.traffic_probe:
             # plain copy of known size (512 MiB read + 512 MiB written), to
             # calibrate the FETCH_SIZE / WRITE_SIZE counters of a profiler run

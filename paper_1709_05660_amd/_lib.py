@@ -82,7 +82,7 @@ EXPORTS = [
     "fsi_fgmres_solve", "fsi_mg_apply", "fsi_mg_export_patches", "fsi_mg_level_info",
     "fsi_mg_refactor", "fsi_mg_jvalues", "fsi_mg_profile", "fsi_mg_autotune",
     "fsi_mg_destroy", "fsi_server_create", "fsi_serve_submit", "fsi_serve_poll",
-    "fsi_server_stats", "fsi_server_destroy",
+    "fsi_server_stats", "fsi_server_destroy", "fsi_stream_read", "fsi_stream_read_blocks",
     "fsi_problem_build", "fsi_problem_nlevels", "fsi_problem_levels", "fsi_problem_vectors",
     "fsi_problem_dirichlet", "fsi_problem_residual", "fsi_problem_destroy", "fsi_problem_last_error",
 ]
@@ -117,6 +117,8 @@ def lib():
         "fsi_mg_autotune": (C.c_int32, [P, C.c_char_p, P, C.POINTER(C.c_int32)]),
         "fsi_mg_jvalues": (C.c_int32, [P, C.c_int32, C.POINTER(C.POINTER(C.c_double))]),
         "fsi_mg_profile": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_double)]),
+        "fsi_stream_read": (C.c_int32, [P, C.c_int64, P, P]),
+        "fsi_stream_read_blocks": (C.c_int32, []),
         "fsi_server_create": (C.c_int32, [C.POINTER(ServerOpts), C.POINTER(P)]),
         "fsi_serve_submit": (C.c_int32, [P, C.POINTER(LevelC), C.c_int32, P, C.POINTER(MgOpts),
                                          C.POINTER(KrylovOpts), C.POINTER(C.c_uint64)]),

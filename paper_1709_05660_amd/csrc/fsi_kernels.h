@@ -85,6 +85,11 @@ void launch_ras_16(const RasView &v, const uint16_t *W, int w16_kind, const floa
 // ---- coarsest solve (a7): y = W x, W row-major n x n FP64
 void launch_dense_gemv(const double *W, int n, const double *x, double *y, hipStream_t st);
 
+// ---- measurement: plain streaming read of n doubles (x 16-byte aligned, n
+// even); out receives kStreamReadBlocks partial sums
+constexpr int kStreamReadBlocks = 4096;
+void launch_stream_read(const double *x, int64_t n, double *out, hipStream_t st);
+
 // ---- vectors
 void launch_cast_d2f(const double *x, float *y, int n, hipStream_t st);
 void launch_cast_f2d(const float *x, double *y, int n, hipStream_t st);

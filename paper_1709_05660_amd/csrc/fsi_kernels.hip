@@ -783,4 +783,34 @@ void launch_start_cycle(int n, const double *r, const double *nrm2, double *v, d
   k_start_cycle<<<cdiv(std::max(n, m + 1), 256), 256, 0, st>>>(n, r, nrm2, v, g, m);
 }
 
+// ------------------------------------------------------------------ measurement
+// Streaming read of n doubles with 16-byte loads, eight in flight per lane
+// over a grid-stride loop; block b writes its partial sum to out[b].  It is
+// the device's plain read rate that the HBM-bound kernels are compared with.
+__global__ __launch_bounds__(256) void k_stream_read(const double2 *__restrict__ x, int64_t n2,
+                                                     double *__restrict__ out) {
+  __shared__ double red[4];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  for (; i + 7 * stride < n2; i += 8 * stride) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = x[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u].x + v[u].y;
+  }
+  for (; i < n2; i += stride) s += x[i].x + x[i].y;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+void launch_stream_read(const double *x, int64_t n, double *out, hipStream_t st) {
+  if (n >= 2)
+    k_stream_read<<<kStreamReadBlocks, 256, 0, st>>>(reinterpret_cast<const double2 *>(x), n / 2,
+                                                     out);
+}
+
 }  // namespace fsi

@@ -1158,6 +1158,18 @@ fsi_status fsi_mg_profile(struct fsi_mg *h, int32_t enable, double out[2]) {
   })
 }
 
+fsi_status fsi_stream_read(const double *x_dev, int64_t n, double *out_dev, void *hip_stream) {
+  FSI_GUARD({
+    if (!x_dev || !out_dev || n < 2 || (n & 1) || (reinterpret_cast<uintptr_t>(x_dev) & 15))
+      throw Error(FSI_E_INVALID, "stream read needs an even n >= 2 and a 16-byte aligned x");
+    launch_stream_read(x_dev, n, out_dev, (hipStream_t)hip_stream);
+    hip_check(hipGetLastError(), "stream read launch");
+    return FSI_OK;
+  })
+}
+
+int32_t fsi_stream_read_blocks(void) { return kStreamReadBlocks; }
+
 fsi_status fsi_mg_level_info(struct fsi_mg *h, int32_t level, int64_t out[6]) {
   FSI_GUARD({
     MG *mg = reinterpret_cast<MG *>(h);

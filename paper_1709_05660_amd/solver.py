@@ -22,6 +22,32 @@ def _dptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def stream_read_gbps(nbytes, reps=20):
+    """Best rate (GB/s) of the library's plain streaming-read kernel over
+    nbytes of device memory, timed with events on the current stream: the
+    read rate the HBM-bound kernels are compared with."""
+    import torch
+    n = (nbytes // 16) * 2
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    out = torch.empty(L.lib().fsi_stream_read_blocks(), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    best = None
+    for r in range(reps + 3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        L.check(L.lib().fsi_stream_read(_dptr(x), n, _dptr(out), C.c_void_p(st.cuda_stream)),
+                "stream read")
+        e1.record(st)
+        e1.synchronize()
+        if r >= 3:
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+    if abs(float(out.sum()) - n) > 1e-6 * n:
+        raise RuntimeError("stream read returned a wrong sum")
+    return n * 8 / (best * 1e-3) / 1e9
+
+
 class Problem:
     """A generated multigrid hierarchy (host arrays owned by the native builder)."""
 

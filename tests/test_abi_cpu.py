@@ -167,3 +167,16 @@ def test_server_rejects_oversized_request():
     stats = (C.c_int64 * 8)()
     assert lib.fsi_server_stats(h, stats) == 0 and stats[0] == 0
     assert lib.fsi_server_destroy(h) == 0
+
+
+def test_stream_read_rejects_bad_sizes():
+    """The measurement helper validates its arguments on the host."""
+    import ctypes as C
+
+    from paper_1709_05660_amd import _lib
+    L = _lib.lib()
+    assert L.fsi_stream_read_blocks() > 0
+    buf = C.c_void_p(4096)   # never dereferenced: the size check fails first
+    assert L.fsi_stream_read(buf, 3, buf, None) == -1
+    assert L.fsi_stream_read(None, 4, buf, None) == -1
+    assert L.fsi_stream_read(C.c_void_p(4104), 4, buf, None) == -1   # not 16-byte aligned
