@@ -45,14 +45,15 @@ struct Level {
   std::vector<uint8_t> h_owned, h_kind;
   int *d_pm = nullptr, *d_po = nullptr, *d_dof = nullptr, *d_out_off = nullptr,
       *d_own_local = nullptr, *d_out_idx = nullptr, *d_task_patch = nullptr,
-      *d_task_row0 = nullptr, *d_row_patch = nullptr, *d_row_local = nullptr;
+      *d_task_row0 = nullptr, *d_row_patch = nullptr, *d_row_local = nullptr,
+      *d_unowned = nullptr;
+  int n_unowned = 0;
   int64_t *d_pdof_off = nullptr, *d_woff = nullptr, *d_boff = nullptr;
   double *W64 = nullptr;
   float *W32 = nullptr;
   uint16_t *W16 = nullptr;
   float *Wscale = nullptr, *Cscale = nullptr;
   int w16_kind = 0;
-  bool all_owned = false;   // every dof owned by a patch (a smoothing step can store, not add)
   // coarsest level: row-major inverse
   double *C0 = nullptr;
   // work vectors

@@ -68,10 +68,13 @@ struct RasView {
   const int64_t *pdof_off, *woff;
   const int *dof, *out_off, *out_idx;
   const float *cscale;   // 16-bit storage: column scales (per patch dof), else null
+  const int *unowned;    // the dofs no patch owns (nunowned of them)
+  int nunowned;
 };
 // e[owned dofs] (+= when add, else =) omega * (owned rows of B_k^{-1}) s_k; with
-// add false the dofs no patch owns are left untouched.  ev0/ev1: optional
-// events recorded at the finest-level kernel's start and end
+// add false (a zero initial correction) the dofs no patch owns are set to 0,
+// so e needs no clearing.  ev0/ev1: optional events recorded at the
+// finest-level kernel's start and end
 void launch_ras_f64(const RasView &v, const double *W, const double *s, double *e, double omega,
                     bool finest, bool add, hipStream_t st, hipEvent_t ev0 = nullptr,
                     hipEvent_t ev1 = nullptr);

@@ -379,7 +379,8 @@ void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm,
 // over a column is one coalesced load of the task's rows, eight loads in
 // flight per lane), the partial sums meet in LDS and lane r of the first
 // wave adds omega times row r to its owned dof (or stores it, when add is 0:
-// a zero initial correction).  Levels with few tasks use more waves per
+// a zero initial correction; the workgroups then also clear the dofs no patch
+// owns, a slice each).  Levels with few tasks use more waves per
 // workgroup (a shorter chain of loads per wave).  TAG only names the
 // finest-level launch.
 __device__ inline float w16val(uint16_t v, int kind) {
@@ -430,6 +431,9 @@ __global__ __launch_bounds__(64 * NWV) void k_ras(RasView v, const WT *__restric
   } else {
     for (int c = threadIdx.x; c < m; c += 64 * NWV) xs[c] = (AT)s[d[c]];
   }
+  if (!add)
+    for (int i = blockIdx.x * 64 * NWV + threadIdx.x; i < v.nunowned; i += gridDim.x * 64 * NWV)
+      e[v.unowned[i]] = (VT)0;
   __syncthreads();
   AT a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int c = c0;

@@ -186,7 +186,12 @@ static void build_patch_layout(Level &L, const fsi_patches &P, MG &mg, hipStream
     L.sum_om += (int64_t)o * pm[k];
   }
   L.total_owned = out_off[np];
-  L.all_owned = L.total_owned == L.n;
+  std::vector<char> is_owned(L.n, 0);
+  for (int d : out_idx) is_owned[d] = 1;
+  std::vector<int> unowned;
+  for (int d = 0; d < L.n; ++d)
+    if (!is_owned[d]) unowned.push_back(d);
+  L.n_unowned = (int)unowned.size();
   L.ntask = (int)task_patch.size();
   auto &own = mg.owned;
   L.d_pm = dupload(pm.data(), np, own, st);
@@ -202,6 +207,7 @@ static void build_patch_layout(Level &L, const fsi_patches &P, MG &mg, hipStream
   L.d_task_row0 = dupload(task_row0.data(), (int64_t)task_row0.size(), own, st);
   L.d_row_patch = dupload(row_patch.data(), (int64_t)row_patch.size(), own, st);
   L.d_row_local = dupload(row_local.data(), (int64_t)row_local.size(), own, st);
+  L.d_unowned = dupload(unowned.data(), (int64_t)unowned.size(), own, st);
   L.boff_total = boff[np];
   L.woff_total = woff[np];
   L.h_boff = boff;
@@ -221,6 +227,8 @@ RasView ras_view(const Level &L) {
   v.out_off = L.d_out_off;
   v.out_idx = L.d_out_idx;
   v.cscale = L.Cscale;
+  v.unowned = L.d_unowned;
+  v.nunowned = L.n_unowned;
   return v;
 }
 
@@ -359,9 +367,9 @@ static void ras32(MG &mg, Level &L, const float *s, float *e, bool add, hipStrea
 
 // One V-cycle on level l for e = M_l^{-1} r (r and e distinct; the finest
 // level works on the caller's vectors directly).  The first smoothing step
-// starts from e = 0: it stores its correction instead of adding it when
-// every dof is owned by a patch (no zero fill), and without pre-smoothing
-// the coarse correction is stored into e.
+// starts from e = 0: it stores its correction and clears the dofs no patch
+// owns (no zero fill), and without pre-smoothing the coarse correction is
+// stored into e.
 template <typename T>
 struct VOps;
 template <>
@@ -372,7 +380,6 @@ struct VOps<double> {
   static double *r(Level &L) { return L.r; }
   static double *e(Level &L) { return L.e; }
   static double *s(Level &L) { return L.s; }
-  static void fill(double *x, int n, hipStream_t st) { launch_fill_f64(x, n, 0.0, st); }
   static void ras(MG &mg, Level &L, const double *s, double *e, bool add, hipStream_t st) {
     ras64(mg, L, s, e, add, st);
   }
@@ -385,7 +392,6 @@ struct VOps<float> {
   static float *r(Level &L) { return L.r32; }
   static float *e(Level &L) { return L.e32; }
   static float *s(Level &L) { return L.s32; }
-  static void fill(float *x, int n, hipStream_t st) { launch_fill_f32(x, n, 0.0f, st); }
   static void ras(MG &mg, Level &L, const float *s, float *e, bool add, hipStream_t st) {
     ras32(mg, L, s, e, add, st);
   }
@@ -417,8 +423,7 @@ static void vcycle(MG &mg, int l, const T *r, T *e, hipStream_t st) {
   const int nu_pre = mg.opts.nu_pre;
   for (int it = 0; it < nu_pre; ++it) {
     if (it == 0) {
-      if (!L.all_owned) O::fill(e, L.n, st);
-      O::ras(mg, L, r, e, !L.all_owned, st);
+      O::ras(mg, L, r, e, false, st);
     } else {
       launch_spmv(J, e, r, s, kSpmvResid, L.J.lpr, st);
       O::ras(mg, L, s, e, true, st);
