@@ -4,6 +4,7 @@
 
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -61,6 +62,25 @@ struct Level {
   float *r32 = nullptr, *e32 = nullptr, *s32 = nullptr;
 };
 
+// Caching device allocator for the server: freed blocks are kept (by size)
+// and handed out again, so serving never calls hipFree (which synchronises
+// the device); everything is released when the pool is destroyed.
+struct DevicePool {
+  std::mutex mu;
+  std::multimap<size_t, void *> free_blocks;
+  std::vector<void *> all;
+  void *get(size_t bytes, size_t *got);
+  void put(void *p, size_t bytes);
+  ~DevicePool();
+};
+
+// Device allocations owned by one object: from the pool when there is one,
+// else hipMalloc/hipFree.
+struct DevList {
+  DevicePool *pool = nullptr;
+  std::vector<std::pair<void *, size_t>> v;
+};
+
 struct Krylov {
   int m = 0;
   double *V = nullptr, *Z = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
@@ -70,7 +90,7 @@ struct Krylov {
   double *pinned_dev = nullptr;   // its device address
   hipEvent_t ev_done = nullptr;   // recorded after a phase's D2H copy, polled by the host
   std::vector<hipGraphExec_t> step_graphs;   // Arnoldi step j as one graph (use_graph)
-  std::vector<void *> owned;
+  DevList owned;
 };
 
 struct GraphKey {
@@ -84,8 +104,9 @@ struct MG {
   bool mixed = false;
   fsi_mg_opts opts{};
   std::vector<Level> lv;
-  std::vector<void *> owned;
+  DevList owned;
   hipStream_t own_stream = nullptr;
+  bool own_side = true;   // side_stream created by the handle (else borrowed)
   Krylov kry;
   std::map<GraphKey, hipGraphExec_t> graphs;
   double setup_ms = 0.0;
@@ -110,8 +131,10 @@ struct MG {
 
 extern thread_local std::string g_last_error;
 
+// pool (may be NULL): device memory from the caching allocator; side_st (may
+// be NULL): a borrowed second stream for the coarsest inversion
 MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipStream_t user_st,
-             hipStream_t own_st);
+             hipStream_t own_st, DevicePool *pool = nullptr, hipStream_t side_st = nullptr);
 void destroy_mg(MG *mg);
 void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts);
 void apply_vcycle(MG &mg, const double *r, double *z, hipStream_t st);

@@ -84,13 +84,53 @@ static void validate_patches(const fsi_patches &P, int64_t n, int lev) {
 }
 
 // ------------------------------------------------------------------ device helpers
-template <typename T>
-T *dalloc(int64_t n, std::vector<void *> &owned) {
-  if (n <= 0) return nullptr;
+void *DevicePool::get(size_t bytes, size_t *got) {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    // best fit among the cached blocks, wasting at most a quarter
+    auto it = free_blocks.lower_bound(bytes);
+    if (it != free_blocks.end() && it->first <= bytes + bytes / 4 + 4096) {
+      void *p = it->second;
+      *got = it->first;
+      free_blocks.erase(it);
+      return p;
+    }
+  }
   void *p = nullptr;
-  hip_check(hipMalloc(&p, sizeof(T) * (size_t)n), "hipMalloc");
-  owned.push_back(p);
+  hip_check(hipMalloc(&p, bytes), "hipMalloc");
+  std::lock_guard<std::mutex> lk(mu);
+  all.push_back(p);
+  *got = bytes;
+  return p;
+}
+void DevicePool::put(void *p, size_t bytes) {
+  std::lock_guard<std::mutex> lk(mu);
+  free_blocks.emplace(bytes, p);
+}
+DevicePool::~DevicePool() {
+  for (void *p : all) (void)hipFree(p);
+}
+
+template <typename T>
+T *dalloc(int64_t n, DevList &owned) {
+  if (n <= 0) return nullptr;
+  const size_t bytes = (sizeof(T) * (size_t)n + 255) / 256 * 256;
+  void *p = nullptr;
+  size_t got = bytes;
+  if (owned.pool)
+    p = owned.pool->get(bytes, &got);
+  else
+    hip_check(hipMalloc(&p, bytes), "hipMalloc");
+  owned.v.push_back({p, got});
   return static_cast<T *>(p);
+}
+static void free_one(DevList &owned, size_t i) {
+  auto &e = owned.v[i];
+  if (owned.pool)
+    owned.pool->put(e.first, e.second);
+  else
+    (void)hipFree(e.first);
+  owned.v.erase(owned.v.begin() + i);
 }
 // 64-byte slots of host-coherent pinned memory that kernels write small
 // results into and the host polls.  Chunks are allocated once and kept for the
@@ -117,15 +157,51 @@ void pinned_slot_release(double *s) {
   g_free_slots.push_back(s);
 }
 
+// Host-to-device uploads go through a pinned staging buffer of the calling
+// thread: the copies are asynchronous (no per-copy staging by the runtime)
+// and the host source may be released at once.  The buffer is reused after
+// the stream has drained; a setup ends with such a drain.
+struct Staging {
+  char *buf = nullptr;
+  size_t cap = 0, off = 0;
+  hipStream_t st = nullptr;
+  ~Staging() {
+    if (buf) (void)hipHostFree(buf);
+  }
+};
+static thread_local Staging g_stage;
+static void stage_drain() {
+  if (g_stage.st) hip_check(hipStreamSynchronize(g_stage.st), "upload");
+  g_stage.off = 0;
+  g_stage.st = nullptr;
+}
+static void stage_copy(void *dst, const void *src, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return;
+  Staging &S = g_stage;
+  if (S.st && S.st != st) stage_drain();
+  if (S.off + bytes > S.cap) {
+    stage_drain();
+    if (bytes > S.cap) {
+      if (S.buf) (void)hipHostFree(S.buf);
+      S.buf = nullptr;
+      S.cap = std::max<size_t>(bytes, 64u << 20);
+      hip_check(hipHostMalloc((void **)&S.buf, S.cap, 0), "pinned staging");
+    }
+  }
+  std::memcpy(S.buf + S.off, src, bytes);
+  hip_check(hipMemcpyAsync(dst, S.buf + S.off, bytes, hipMemcpyHostToDevice, st), "H2D");
+  S.off += (bytes + 255) / 256 * 256;
+  S.st = st;
+}
+
 template <typename T>
-T *dupload(const T *h, int64_t n, std::vector<void *> &owned, hipStream_t st) {
+T *dupload(const T *h, int64_t n, DevList &owned, hipStream_t st) {
   T *d = dalloc<T>(n, owned);
-  if (n > 0) hip_check(hipMemcpyAsync(d, h, sizeof(T) * (size_t)n, hipMemcpyHostToDevice, st), "H2D");
+  if (n > 0) stage_copy(d, h, sizeof(T) * (size_t)n, st);
   return d;
 }
 
-static void upload_csr(const fsi_csr &A, DevCsr &D, bool want32, std::vector<void *> &own,
-                       hipStream_t st) {
+static void upload_csr(const fsi_csr &A, DevCsr &D, bool want32, DevList &own, hipStream_t st) {
   D.n = A.nrows;
   D.m = A.ncols;
   D.nnz = (int)A.nnz;
@@ -140,7 +216,6 @@ static void upload_csr(const fsi_csr &A, DevCsr &D, bool want32, std::vector<voi
     D.val32 = dupload(v32.data(), A.nnz, own, st);
   }
   D.lpr = pick_lpr(A.nnz, A.nrows);
-  hip_check(hipStreamSynchronize(st), "upload");
 }
 
 // ------------------------------------------------------------------ patch layout
@@ -211,7 +286,6 @@ static void build_patch_layout(Level &L, const fsi_patches &P, MG &mg, hipStream
   L.boff_total = boff[np];
   L.woff_total = woff[np];
   L.h_boff = boff;
-  hip_check(hipStreamSynchronize(st), "patch layout");
 }
 
 RasView ras_view(const Level &L) {
@@ -232,9 +306,8 @@ RasView ras_view(const Level &L) {
   return v;
 }
 
-static void free_list(std::vector<void *> &v) {
-  for (void *p : v) (void)hipFree(p);
-  v.clear();
+static void free_list(DevList &owned) {
+  while (!owned.v.empty()) free_one(owned, owned.v.size() - 1);
 }
 
 // owned rows of every block inverse in the storage precision of the level
@@ -524,7 +597,7 @@ void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *op
 }
 
 MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipStream_t user_st,
-             hipStream_t own_st) {
+             hipStream_t own_st, DevicePool *pool, hipStream_t side_st) {
   auto t0 = std::chrono::steady_clock::now();
   validate_levels(levels, nlevels, opts);
   std::vector<int64_t> n(nlevels);
@@ -534,6 +607,8 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
   mg->nlevels = nlevels;
   mg->mixed = opts->precision != FSI_PREC_FP64;
   mg->own_stream = own_st;
+  mg->owned.pool = pool;
+  mg->kry.owned.pool = pool;
   hipStream_t st = user_st ? user_st : own_st;
   try {
     mg->lv.resize(nlevels);
@@ -582,12 +657,22 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
     mg->dense_scratch = dalloc<double>(n0 * mg->dense_ld, mg->owned);
     mg->gj_work = dalloc<double>(n0 + 64, mg->owned);
     mg->lv[0].C0 = dalloc<double>(n0 * n0, mg->owned);
-    hip_check(hipStreamCreateWithFlags(&mg->side_stream, hipStreamNonBlocking), "side stream");
+    if (side_st) {
+      mg->side_stream = side_st;
+      mg->own_side = false;
+    } else {
+      hip_check(hipStreamCreateWithFlags(&mg->side_stream, hipStreamNonBlocking), "side stream");
+    }
     hip_check(hipEventCreateWithFlags(&mg->ev_fork, hipEventDisableTiming), "event");
     hip_check(hipEventCreateWithFlags(&mg->ev_join, hipEventDisableTiming), "event");
+    stage_drain();   // the uploads are complete and the staging buffer is free again
     hip_check(hipStreamSynchronize(st), "upload");
     refactor(*mg, st);
   } catch (...) {
+    try {
+      stage_drain();   // no copy may still write into memory about to be released
+    } catch (...) {
+    }
     destroy_mg(mg);
     throw;
   }
@@ -600,10 +685,9 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
 void release_setup_scratch(MG &mg) {
   auto drop = [&](void *p) {
     if (!p) return;
-    for (size_t i = 0; i < mg.owned.size(); ++i)
-      if (mg.owned[i] == p) {
-        (void)hipFree(p);
-        mg.owned.erase(mg.owned.begin() + i);
+    for (size_t i = 0; i < mg.owned.v.size(); ++i)
+      if (mg.owned.v[i].first == p) {
+        free_one(mg.owned, i);
         return;
       }
   };
@@ -617,7 +701,7 @@ void destroy_mg(MG *mg) {
   if (!mg) return;
   if (mg->side_stream) {
     (void)hipStreamSynchronize(mg->side_stream);
-    (void)hipStreamDestroy(mg->side_stream);
+    if (mg->own_side) (void)hipStreamDestroy(mg->side_stream);
   }
   if (mg->coarse_graph) (void)hipGraphExecDestroy(mg->coarse_graph);
   if (mg->ev_fork) (void)hipEventDestroy(mg->ev_fork);

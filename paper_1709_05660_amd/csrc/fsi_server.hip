@@ -5,7 +5,10 @@
 // admitted hierarchy resident, and advances every active system by one unit
 // of FGMRES work per tick, each system on its own stream so that their
 // kernels overlap on the device.  A system that finishes is retired (result
-// copied to host, device memory released) and the next request admitted.
+// copied to host, device memory returned to the server's caching pool) and
+// the next request admitted.  Device memory and streams are recycled: while
+// serving no hipFree (a device-wide synchronisation) and no stream creation
+// happens once the pool has warmed up.
 #include <atomic>
 #include <condition_variable>
 #include <cstring>
@@ -40,6 +43,8 @@ struct Request {
 struct Active {
   std::unique_ptr<Request> req;
   MG *mg = nullptr;
+  hipStream_t side = nullptr;
+  size_t b_bytes = 0, x_bytes = 0;
   hipStream_t st = nullptr;
   double *d_b = nullptr, *d_x = nullptr;
   FgmresRun run;
@@ -55,7 +60,9 @@ struct Done {
 
 struct Server {
   fsi_server_opts o{};
+  DevicePool pool;   // destroyed after every system (declared first)
   std::mutex mu;
+  std::vector<std::pair<hipStream_t, hipStream_t>> free_streams;   // (main, side) pairs
   std::condition_variable cv;
   std::deque<std::unique_ptr<Request>> queue;
   std::map<uint64_t, Done> done;
@@ -170,11 +177,12 @@ static void finish(Server &S, Active &a, fsi_status st, const std::string &msg, 
   const auto now = Clock::now();
   d.info.setup_ms = std::chrono::duration<double, std::milli>(a.t_ready - a.req->t_submit).count();
   d.info.solve_ms = std::chrono::duration<double, std::milli>(now - a.t_ready).count();
+  if (a.st) (void)hipStreamSynchronize(a.st);
   if (a.mg) destroy_mg(a.mg);
-  if (a.d_b) (void)hipFree(a.d_b);
-  if (a.d_x) (void)hipFree(a.d_x);
-  if (a.st) (void)hipStreamDestroy(a.st);
+  if (a.d_b) S.pool.put(a.d_b, a.b_bytes);
+  if (a.d_x) S.pool.put(a.d_x, a.x_bytes);
   std::lock_guard<std::mutex> lk(S.mu);
+  if (a.st) S.free_streams.push_back({a.st, a.side});
   S.used -= a.req->footprint;
   S.done[a.req->ticket] = std::move(d);
   S.finished++;
@@ -210,10 +218,22 @@ static void setup_loop(Server *S) {
     a->req = std::move(req);
     const int n = (int)a->req->b.size();
     try {
-      hip_check(hipStreamCreate(&a->st), "stream");
-      a->mg = mg_setup(a->req->levels.data(), (int)a->req->levels.size(), &a->req->mo, a->st, a->st);
-      hip_check(hipMalloc(&a->d_b, sizeof(double) * n), "hipMalloc");
-      hip_check(hipMalloc(&a->d_x, sizeof(double) * n), "hipMalloc");
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (!S->free_streams.empty()) {
+          a->st = S->free_streams.back().first;
+          a->side = S->free_streams.back().second;
+          S->free_streams.pop_back();
+        }
+      }
+      if (!a->st) {
+        hip_check(hipStreamCreate(&a->st), "stream");
+        hip_check(hipStreamCreateWithFlags(&a->side, hipStreamNonBlocking), "stream");
+      }
+      a->mg = mg_setup(a->req->levels.data(), (int)a->req->levels.size(), &a->req->mo, a->st, a->st,
+                       &S->pool, a->side);
+      a->d_b = static_cast<double *>(S->pool.get(sizeof(double) * n, &a->b_bytes));
+      a->d_x = static_cast<double *>(S->pool.get(sizeof(double) * n, &a->x_bytes));
       hip_check(hipMemcpyAsync(a->d_b, a->req->b.data(), sizeof(double) * n, hipMemcpyHostToDevice, a->st), "H2D");
       a->run.start(*a->mg, a->d_b, a->d_x, 0, a->req->ko, a->st);
       a->t_ready = Clock::now();
@@ -300,6 +320,18 @@ fsi_status fsi_server_create(const fsi_server_opts *o, struct fsi_server **out) 
       throw Error(FSI_E_INVALID, "invalid server options");
     Server *S = new Server();
     S->o = *o;
+    // the slots' streams are created up front (a stream's first creation is
+    // slow), then recycled
+    (void)hipSetDevice(o->device);
+    for (int i = 0; i < o->max_slots; ++i) {
+      hipStream_t a = nullptr, b = nullptr;
+      if (hipStreamCreate(&a) != hipSuccess) break;
+      if (hipStreamCreateWithFlags(&b, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(a);
+        break;
+      }
+      S->free_streams.push_back({a, b});
+    }
     for (int i = 0; i < kSetupThreads; ++i) S->setup_threads.emplace_back(setup_loop, S);
     S->tick_thread = std::thread(tick_loop, S);
     *out = reinterpret_cast<fsi_server *>(S);
@@ -382,6 +414,10 @@ fsi_status fsi_server_destroy(struct fsi_server *h) {
     if (t.joinable()) t.join();
   if (S->tick_thread.joinable()) S->tick_thread.join();
   drain(S);
+  for (auto &p : S->free_streams) {
+    (void)hipStreamDestroy(p.first);
+    (void)hipStreamDestroy(p.second);
+  }
   delete S;
   return FSI_OK;
 }
