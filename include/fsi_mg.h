@@ -188,9 +188,11 @@ int32_t fsi_stream_read_blocks(void);
  * A server keeps the hierarchies of admitted systems resident on the device,
  * admits queued requests in arrival order while their estimated device
  * footprint fits the budget and a slot is free, and advances every active
- * system by one FGMRES iteration per scheduling tick, the systems' kernels
- * overlapping on the device; a converged system is retired (result copied to
- * host, memory freed) and the next request admitted. */
+ * system by one FGMRES iteration as soon as its previous one has finished,
+ * the systems' kernels overlapping on the device; a converged system is
+ * retired (result copied to host, device memory returned to the server's
+ * cache, released when the server is destroyed) and the next request
+ * admitted. */
 typedef struct {
   int64_t hbm_budget_bytes; /* admission budget of device memory */
   int32_t max_slots;        /* maximum co-resident systems */

@@ -1,10 +1,10 @@
 // Solve server: continuous batching of independent systems on one GPU.
 //
-// A scheduler thread admits queued requests in arrival order while a slot is
-// free and the estimated device footprint fits the budget, keeps each
-// admitted hierarchy resident, and advances every active system by one unit
-// of FGMRES work per tick, each system on its own stream so that their
-// kernels overlap on the device.  A system that finishes is retired (result
+// Setup threads admit queued requests in arrival order while a slot is free
+// and the estimated device footprint fits the budget and set them up; each
+// admitted hierarchy stays resident, and tick threads advance every active
+// system by one unit of FGMRES work as soon as its previous unit finished,
+// each system on its own stream so that their kernels overlap on the device.  A system that finishes is retired (result
 // copied to host, device memory returned to the server's caching pool) and
 // the next request admitted.  Device memory and streams are recycled: while
 // serving no hipFree (a device-wide synchronisation) and no stream creation
@@ -24,7 +24,8 @@
 namespace fsi {
 
 using Clock = std::chrono::steady_clock;
-constexpr int kSetupThreads = 3;   // concurrent setups (each on its system's stream)
+constexpr int kSetupThreads = 6;   // concurrent setups (each on its system's stream)
+constexpr int kTickThreads = 2;    // threads that advance the active systems (each owns a share)
 
 struct Request {
   uint64_t ticket = 0;
@@ -45,6 +46,7 @@ struct Active {
   MG *mg = nullptr;
   hipStream_t side = nullptr;
   size_t b_bytes = 0, x_bytes = 0;
+  int owner = 0;   // the tick thread that advances this system
   hipStream_t st = nullptr;
   double *d_b = nullptr, *d_x = nullptr;
   FgmresRun run;
@@ -70,7 +72,8 @@ struct Server {
   std::vector<std::unique_ptr<Active>> active;
   int setting_up = 0;
   std::vector<std::thread> setup_threads;
-  std::thread tick_thread;
+  std::vector<std::thread> tick_threads;
+  int next_owner = 0;
   std::atomic<bool> stop{false};
   uint64_t next_ticket = 1;
   int64_t used = 0, peak = 0, submitted = 0, finished = 0, ticks = 0, max_coresident = 0;
@@ -241,6 +244,7 @@ static void setup_loop(Server *S) {
       std::lock_guard<std::mutex> lk(S->mu);
       S->used -= a->req->transient;
       a->req->footprint -= a->req->transient;
+      a->owner = S->next_owner++ % kTickThreads;
       S->active.push_back(std::move(a));
       S->setting_up--;
       S->max_coresident = std::max<int64_t>(S->max_coresident, (int64_t)S->active.size());
@@ -255,27 +259,36 @@ static void setup_loop(Server *S) {
   }
 }
 
-// Tick thread: every active system advances by one unit of FGMRES work per
-// tick; the other systems' work stays in flight on their streams while one
-// stream is being synchronised.
-static void tick_loop(Server *S) {
+// Tick threads: each owns a share of the active systems and polls their
+// streams; a system whose previous unit of FGMRES work has finished is
+// advanced by one unit at once, so no system waits for another.
+static void tick_loop(Server *S, int me) {
   (void)hipSetDevice(S->o.device);
   while (!S->stop.load()) {
     std::vector<Active *> cur;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      if (S->active.empty()) {
-        S->cv.wait_for(lk, std::chrono::milliseconds(2),
-                       [&] { return S->stop.load() || !S->active.empty(); });
+      for (auto &p : S->active)
+        if (p->owner == me) cur.push_back(p.get());
+      if (cur.empty()) {
+        S->cv.wait_for(lk, std::chrono::milliseconds(2), [&] {
+          if (S->stop.load()) return true;
+          for (auto &p : S->active)
+            if (p->owner == me) return true;
+          return false;
+        });
         continue;
       }
-      for (auto &p : S->active) cur.push_back(p.get());
       S->ticks++;
     }
     std::vector<Active *> retired;
+    bool progressed = false;
     for (Active *a : cur) {
       try {
-        hip_check(hipStreamSynchronize(a->st), "tick");
+        const hipError_t q = hipStreamQuery(a->st);
+        if (q == hipErrorNotReady) continue;
+        hip_check(q, "tick");
+        progressed = true;
         if (a->run.complete()) {
           finish(*S, *a, a->run.converged ? FSI_OK : FSI_NOT_CONVERGED, "", true);
           retired.push_back(a);
@@ -297,6 +310,7 @@ static void tick_loop(Server *S) {
           }
       S->cv.notify_all();
     }
+    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
 }
 
@@ -333,7 +347,7 @@ fsi_status fsi_server_create(const fsi_server_opts *o, struct fsi_server **out) 
       S->free_streams.push_back({a, b});
     }
     for (int i = 0; i < kSetupThreads; ++i) S->setup_threads.emplace_back(setup_loop, S);
-    S->tick_thread = std::thread(tick_loop, S);
+    for (int i = 0; i < kTickThreads; ++i) S->tick_threads.emplace_back(tick_loop, S, i);
     *out = reinterpret_cast<fsi_server *>(S);
     return FSI_OK;
   } catch (const Error &e) {
@@ -412,7 +426,8 @@ fsi_status fsi_server_destroy(struct fsi_server *h) {
   S->cv.notify_all();
   for (auto &t : S->setup_threads)
     if (t.joinable()) t.join();
-  if (S->tick_thread.joinable()) S->tick_thread.join();
+  for (auto &t : S->tick_threads)
+    if (t.joinable()) t.join();
   drain(S);
   for (auto &p : S->free_streams) {
     (void)hipStreamDestroy(p.first);

@@ -133,3 +133,21 @@ def test_failed_request_is_isolated():
     srv.close()
     assert res[0][0] == 0 and res[2][0] == 0
     assert res[1][0] == -3
+
+
+def test_recycled_memory_gives_identical_results():
+    """The server recycles device blocks and streams: a system solved again
+    (into blocks that still hold an earlier system's data) gives bit-identical
+    results, so no kernel depends on the prior contents of its memory."""
+    from paper_1709_05660_amd import Server
+    probs = _problems()
+    srv = Server(hbm_budget_bytes=8 << 30, max_slots=1)
+    runs = []
+    for p in (probs[1], probs[0], probs[1], probs[3], probs[1]):
+        _say("recycle", p.n)
+        st, x, info = _wait(srv, srv.submit(p, precision="bf16", rtol=1e-8))
+        assert st == 0, info
+        runs.append(x)
+    srv.close()
+    assert np.array_equal(runs[0], runs[2])
+    assert np.array_equal(runs[0], runs[4])
