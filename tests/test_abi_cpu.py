@@ -180,3 +180,22 @@ def test_stream_read_rejects_bad_sizes():
     assert L.fsi_stream_read(buf, 3, buf, None) == -1
     assert L.fsi_stream_read(None, 4, buf, None) == -1
     assert L.fsi_stream_read(C.c_void_p(4104), 4, buf, None) == -1   # not 16-byte aligned
+
+
+def test_coarsest_size_limit_is_reported_on_the_host():
+    """A coarsest level above the dense solve's limit (6144 unknowns) is
+    rejected before any device call."""
+    from paper_1709_05660_amd import _lib
+    n = 6145
+    rp = np.arange(n + 1, dtype=np.int64)
+    ci = np.arange(n, dtype=np.int32)
+    v = np.ones(n)
+    lv = (_lib.LevelC * 1)()
+    J = lv[0].J
+    J.nrows = J.ncols = n
+    J.nnz = n
+    J.rowptr = rp.ctypes.data_as(C.POINTER(C.c_int64))
+    J.colind = ci.ctypes.data_as(C.POINTER(C.c_int32))
+    J.val = v.ctypes.data_as(C.POINTER(C.c_double))
+    st, msg = _setup_status(lv, 1)
+    assert st == -1 and "coarsest" in msg and "6144" in msg

@@ -54,8 +54,9 @@ class OneLevel:
         self.n = A.shape[0]
 
 
-# sizes covering (panel width, rows per thread): 16/1, 16/2, 16/3, 8/6, 4/12; none a multiple of 16
-@pytest.mark.parametrize("n", [37, 301, 703, 1381, 2003, 3501])
+# sizes covering (panel width, rows per thread): 16/1, 16/2, 16/3, 8/6, 4/12, and the largest
+# coarsest size accepted (6144); none but the last a multiple of 16
+@pytest.mark.parametrize("n", [37, 301, 703, 1381, 2003, 3501, 6144])
 def test_coarsest_solve_matches_dense(n):
     import torch
 
@@ -82,3 +83,24 @@ def test_coarsest_singular_is_reported():
     with pytest.raises(FsiError) as e:
         MG(OneLevel(A), precision="fp64")
     assert "coarsest" in str(e.value)
+
+
+# FGMRES on a one-level hierarchy (the preconditioner is the exact inverse):
+# n = 37 leaves most of the 256 row chunks of the Krylov reductions empty
+@pytest.mark.parametrize("n,graph", [(37, False), (37, True), (301, True)])
+def test_fgmres_one_level_small(n, graph):
+    import torch
+
+    from paper_1709_05660_amd import MG
+    A = saddle(n, 500 + n)
+    mg = MG(OneLevel(A), precision="fp64", use_graph=graph)
+    rng = np.random.default_rng(n + 1)
+    b = rng.standard_normal(n)
+    x, info = mg.fgmres(torch.as_tensor(b, device="cuda"), rtol=1e-12)
+    x = x.cpu().numpy()
+    mg.close()
+    ref = np.linalg.solve(A.toarray(), b)
+    _say("one level", n, graph, info["iters"], info["true_relres"])
+    assert info["status"] == 0 and info["converged"] == 1
+    assert info["iters"] <= 2
+    assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
