@@ -38,12 +38,20 @@ static inline int cdivg(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 constexpr int kNoRow = 0x7fffffff;
 
-// DPP move of a double within rows of 16 lanes (full EXEC)
+// DPP move of a double to a fresh register (full EXEC, every row written)
 template <int CTRL>
+__device__ __forceinline__ double mov_dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// DPP move of a double (full EXEC); rows outside ROWS keep their own value
+template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ double dpp_f64(double x) {
   const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, ROWS, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 __device__ __forceinline__ double readlane_f64(double x, int l) {
@@ -51,8 +59,11 @@ __device__ __forceinline__ double readlane_f64(double x, int l) {
   const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
-// DPP controls: quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_ror 4, row_ror 8
+// DPP controls: quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_ror 4, row_ror 8,
+// row_bcast 15 (lane 15 of each row into the next row), row_bcast 31 (lane 31
+// into rows 2 and 3)
 constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppRor4 = 0x124, kDppRor8 = 0x128;
+constexpr int kDppBcast15 = 0x142, kDppBcast31 = 0x143;
 
 // Pivot keys.  A candidate row i with entry a in the pivot column is keyed
 // by |a| with its lowest 13 mantissa bits replaced by 8191 - i (rows are
@@ -73,15 +84,43 @@ __device__ __forceinline__ double key_value(double k) {
   return __longlong_as_double(__double_as_longlong(k) & ~kKeyMask);
 }
 
-// wave-wide maximum of a double in every lane: DPP inside each row of 16
-// lanes, then the four rows combined.  Requires all 64 lanes active.
+// max of two pivot keys.  Keys are never NaN, so with RAW the plain
+// instruction is used (fmax first quiets possible signalling NaNs of both
+// operands); the asm statement limits the scheduler, so kernels whose panel
+// already fills most registers keep fmax.
+template <bool RAW>
+__device__ __forceinline__ double key_max(double a, double b) {
+  if constexpr (RAW) {
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+  } else {
+    return fmax(a, b);
+  }
+}
+
+// wave-wide maximum of a key, the same value in every lane: DPP inside each
+// row of 16 lanes, then row broadcasts carry the running maximum into the
+// last row, whose lane 63 is read.  Requires all 64 lanes active.
+template <bool RAW>
 __device__ __forceinline__ double wave_max(double v) {
-  v = fmax(v, dpp_f64<kDppXor1>(v));
-  v = fmax(v, dpp_f64<kDppXor2>(v));
-  v = fmax(v, dpp_f64<kDppRor4>(v));
-  v = fmax(v, dpp_f64<kDppRor8>(v));
-  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
-              fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+  v = key_max<RAW>(v, mov_dpp_f64<kDppXor1>(v));
+  v = key_max<RAW>(v, mov_dpp_f64<kDppXor2>(v));
+  v = key_max<RAW>(v, mov_dpp_f64<kDppRor4>(v));
+  v = key_max<RAW>(v, mov_dpp_f64<kDppRor8>(v));
+  v = key_max<RAW>(v, dpp_f64<kDppBcast15, 0xA>(v));   // rows 1, 3: max with rows 0, 2
+  v = key_max<RAW>(v, dpp_f64<kDppBcast31, 0xC>(v));   // rows 2, 3: max with row 1
+  return readlane_f64(v, 63);
+}
+
+// 1 / a from the hardware reciprocal refined by two Newton steps: within an
+// ulp of the rounded quotient for 2^-1021 <= |a| <= 2^1021 (outside that range
+// the result may be 0 or NaN; such a pivot leaves the block unusable anyway)
+__device__ __forceinline__ double recip(double a) {
+  double x = __builtin_amdgcn_rcp(a);
+  x = fma(x, fma(-a, x, 1.0), x);
+  x = fma(x, fma(-a, x, 1.0), x);
+  return x;
 }
 
 // LDS of the pivot steps: one candidate row (with the reciprocal of its
@@ -96,8 +135,8 @@ struct PivotLds {
 };
 
 // One pivot step on column t of the panel held in v (see reg_panel).
-// Returns 0 or 1 + the failing step, uniformly.
-template <int NB, int R, int NT>
+// Returns 0 or 1 + the failing step, uniformly.  RAW: see key_max.
+template <int NB, int R, int NT, bool RAW>
 __device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int m, int p0, int t,
                                           int col, PivotLds<NB, NT / 64> &sh, int &mypiv) {
   constexpr int NW = NT / 64;
@@ -117,8 +156,8 @@ __device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int
   }
   // every lane inverts its own candidate while the wave reduction runs;
   // the winner publishes its row and reciprocal
-  const double dl = 1.0 / sv;
-  const double wkey = wave_max(key);
+  const double dl = recip(sv);
+  const double wkey = wave_max<RAW>(key);
   if (wkey >= 0.0 && key == wkey) {
     const int i = key_row(key);
 #pragma unroll
@@ -138,7 +177,7 @@ __device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int
 #pragma unroll
   for (int s2 = 1; s2 < NW; s2 <<= 1)
 #pragma unroll
-    for (int k = 0; k + s2 < NW; k += 2 * s2) kk[k] = fmax(kk[k], kk[k + s2]);
+    for (int k = 0; k + s2 < NW; k += 2 * s2) kk[k] = key_max<RAW>(kk[k], kk[k + s2]);
   const double gkey = kk[0];
   const double gv = key_value(gkey);
   if (!(gkey >= 0.0) || !(gv > 0.0) || gv >= key_value(pivot_key(DBL_MAX, 0))) return p0 + t + 1;
@@ -171,27 +210,27 @@ __device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int
 // tid + q * NT sit in v[q][0..NB) (columns beyond w are zero; rows beyond m
 // are never candidates); stp[q] is the step at which that row became a
 // pivot (< 0: not yet; rows beyond m carry kNoRow).  Thread t receives the
-// pivot row of step t in mypiv.  UNR: the NB steps are
+// pivot row of step t in mypiv.  RAW: see key_max.  UNR: the NB steps are
 // unrolled and step t works on the static column t.  Otherwise the step loop
 // is rolled: the current pivot column is always v[q][0] and each step
 // rotates the row left by one column (every register index stays static),
 // the columns being back in order after NB rotations.  Called by all NT
 // threads.  Returns 0, or 1 + the step whose pivot is zero or not finite
 // (the same value in every thread).
-template <int NB, int R, int NT, bool UNR>
+template <int NB, int R, int NT, bool UNR, bool RAW>
 __device__ __forceinline__ int reg_panel(double (&v)[R][NB], int (&stp)[R], int m, int p0, int w,
                                          PivotLds<NB, NT / 64> &sh, int &mypiv) {
   if constexpr (UNR) {
 #pragma unroll
     for (int t = 0; t < NB; ++t)
       if (t < w) {
-        const int f = pivot_step<NB, R, NT>(v, stp, m, p0, t, t, sh, mypiv);
+        const int f = pivot_step<NB, R, NT, RAW>(v, stp, m, p0, t, t, sh, mypiv);
         if (f) return f;
       }
   } else {
     for (int t = 0; t < NB; ++t) {
       if (t < w) {
-        const int f = pivot_step<NB, R, NT>(v, stp, m, p0, t, 0, sh, mypiv);
+        const int f = pivot_step<NB, R, NT, RAW>(v, stp, m, p0, t, 0, sh, mypiv);
         if (f) return f;
       }
 #pragma unroll
@@ -259,7 +298,7 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
         for (int c = 0; c < NB; ++c)
           if (c >= w) v[q][c] = 0.0;
       int mypiv = 0;   // unused here: the update reads the pivots from LDS
-      fail = reg_panel<NB, R, NT, UNR>(v, stp, m, p0, w, sh, mypiv);
+      fail = reg_panel<NB, R, NT, UNR, false>(v, stp, m, p0, w, sh, mypiv);
       if (fail) break;
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -439,7 +478,7 @@ __device__ __forceinline__ void cgj_factor(double *__restrict__ A, int n, int64_
                                            double (&v)[R][NB], int (&stp)[R]) {
   const int tid = threadIdx.x;
   int mypiv = 0;
-  const int f = reg_panel<NB, R, NT, true>(v, stp, n, p0, w, sh, mypiv);
+  const int f = reg_panel<NB, R, NT, true, true>(v, stp, n, p0, w, sh, mypiv);
   if (f) {
     if (tid == 0) status[0] = f;
     return;
