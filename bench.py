@@ -62,6 +62,95 @@ def measured_traffic():
     return int(b.group(1))
 
 
+def vcycle_times(mg, n, stream, reps=50):
+    """Mean V-cycle time over reps back-to-back applications (warm: the
+    operators may stay in the 256 MB last-level cache between cycles)."""
+    import torch
+    r = torch.randn(n, dtype=torch.float64, device="cuda")
+    z = torch.empty_like(r)
+    for _ in range(3):
+        mg.vcycle(r, z)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(reps):
+        mg.vcycle(r, z)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps
+
+
+def vcycle_cold_ms(mg, n, stream, reps=20):
+    """Median V-cycle time with the caches flushed first: a 512 MiB fill (twice
+    the last-level cache) runs before each timed cycle, outside its events."""
+    import torch
+    r = torch.randn(n, dtype=torch.float64, device="cuda")
+    z = torch.empty_like(r)
+    flush = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
+    mg.vcycle(r, z)
+    ts = []
+    for i in range(reps):
+        flush.fill_(float(i))
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        mg.vcycle(r, z)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(ev0.elapsed_time(ev1))
+    del flush
+    return float(np.median(ts))
+
+
+def three_d_leg(args):
+    """The 3D 32x8x8 three-level system (120,902 unknowns, 2x2x2-element
+    Schwarz blocks of 416-782 dofs) in FP64 and in the mixed form, both to the
+    workload's rtol 1e-8: steps/s, V-cycle (warm and cold), refactor split."""
+    import torch
+
+    from paper_1709_05660_amd import MG, Problem
+    from synth import config, fourier_coefficients
+
+    spec = config("c3_3d_32x8x8")
+    p = Problem(spec, fourier_coefficients(spec.dim, spec.seed))
+    stream = torch.cuda.Stream()
+    res = {"unknowns": p.n, "rtol": spec.rtol}
+    tune_db = os.environ.get("FSI_TUNING_DB", os.path.join("/tmp", "fsi_tuning.db"))
+    with torch.cuda.stream(stream):
+        b = torch.as_tensor(p.b).to("cuda")
+        x = torch.zeros_like(b)
+        for prec in ("fp64", args.mixed):
+            mg = MG(p, precision=prec, use_graph=True)
+            mg.autotune(tune_db)
+            if prec == "fp64":
+                gf = 0.0
+                for l in range(1, p.nlevels):
+                    m = np.diff(mg.export_patches(l)[0]).astype(np.float64)
+                    gf += 2.0 * float((m ** 3).sum()) / 1e9
+                res["block_inversion_gflop"] = round(gf, 2)
+            infos = []
+            torch.cuda.synchronize()
+            for k in range(args.warmup + args.steps_3d):
+                if k == args.warmup:
+                    torch.cuda.synchronize()
+                    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    ev0.record(stream)
+                mg.refactor()
+                _, info = mg.fgmres(b, x, restart=spec.restart, rtol=spec.rtol, maxit=spec.maxit)
+                infos.append(info)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / args.steps_3d
+            res[prec] = {"ms_per_step": round(ms, 3), "solves_per_s": round(1e3 / ms, 2),
+                         "iters": infos[-1]["iters"], "true_relres": float(f"{infos[-1]['true_relres']:.4g}"),
+                         "converged": all(i["converged"] == 1 for i in infos),
+                         "refactor_ms": round(infos[-1]["setup_ms"], 3),
+                         "solve_ms": round(infos[-1]["solve_ms"], 3),
+                         "vcycle_ms": round(vcycle_times(mg, p.n, stream, 20), 4),
+                         "vcycle_ms_cold": round(vcycle_cold_ms(mg, p.n, stream, 10), 4)}
+            mg.close()
+    return res
+
+
 def gpu_leg(args):
     import torch
 
@@ -92,18 +181,7 @@ def gpu_leg(args):
             return ev0.elapsed_time(ev1), infos
 
         def vcycle_ms(mg, reps=50):
-            r = torch.randn(p.n, dtype=torch.float64, device="cuda")
-            z = torch.empty_like(r)
-            for _ in range(3):
-                mg.vcycle(r, z)
-            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            ev0.record(stream)
-            for _ in range(reps):
-                mg.vcycle(r, z)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            return ev0.elapsed_time(ev1) / reps
+            return vcycle_times(mg, p.n, stream, reps)
 
         # ---- FP64 (the workload's precision): value
         t = time.time()
@@ -120,6 +198,7 @@ def gpu_leg(args):
         out["true_relres"] = infos[-1]["true_relres"]
         out["converged"] = all(i["converged"] == 1 for i in infos)
         out["vcycle_ms_fp64"] = vcycle_ms(mg)
+        out["vcycle_ms_fp64_cold"] = vcycle_cold_ms(mg, p.n, stream)
         out["refactor_ms_fp64"] = infos[-1]["setup_ms"]
         out["solve_ms_fp64"] = infos[-1]["solve_ms"]
         out["setup_with_upload_ms"] = setup_upload_ms
@@ -277,6 +356,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--steps-3d", type=int, default=5)
+    ap.add_argument("--only-3d", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true")
     ap.add_argument("--serve-n", type=int, default=256)
     ap.add_argument("--serve-budget-gb", type=int, default=4)
@@ -286,6 +368,10 @@ def main():
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
               file=sys.stderr)
         sys.exit(2)
+    if args.only_3d:
+        # profiling aid: the 3D leg alone, its own JSON line
+        print(json.dumps({"three_d": three_d_leg(args)}), flush=True)
+        return
     g = gpu_leg(args)
     value = args.steps / (g["ms_per_step"] * args.steps * 1e-3)
     line = {
@@ -299,6 +385,7 @@ def main():
         "roofline": g["roofline"],
         "fgmres_iters": g["iters"], "true_relres": g["true_relres"], "converged": g["converged"],
         "vcycle_ms_fp64": round(g["vcycle_ms_fp64"], 4),
+        "vcycle_ms_fp64_cold": round(g["vcycle_ms_fp64_cold"], 4),
         "refactor_ms_fp64": round(g["refactor_ms_fp64"], 3), "solve_ms_fp64": round(g["solve_ms_fp64"], 3),
         "dof_per_s": round(value * g["n"], 1),
         "autotune": {"new_measurements": g["autotune_new_measurements"], "seconds": g["autotune_s"]},
@@ -306,6 +393,8 @@ def main():
     }
     if "mixed" in g:
         line["mixed"] = {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in g["mixed"].items()}
+    if not args.no_3d:
+        line["three_d"] = three_d_leg(args)
     if not args.no_serve:
         line["served"] = serve_leg(args)
     if not args.no_cpu_baseline:

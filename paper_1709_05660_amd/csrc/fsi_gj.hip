@@ -388,9 +388,16 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
 
 static size_t gj_batched_lds(int mmax, int nb) { return (size_t)mmax * (nb + 1) * sizeof(double); }
 
-// largest panel width whose LDS panel fits next to the static LDS
-int gj_panel_width(int mmax) {
-  return gj_batched_lds(mmax, 32) <= 140 * 1024 ? 32 : 16;
+bool gj_variant_ok(int variant, int mmax) {
+  switch (variant) {
+    case kGj16x256:
+    case kGj16x512:
+      return mmax <= 1024;
+    case kGj32x512:   // one row per thread, and the LDS panel next to the static LDS
+      return mmax <= 512 && gj_batched_lds(mmax, 32) <= 140 * 1024;
+    default:
+      return false;
+  }
 }
 
 template <int NB, int R, int NT, bool UNR>
@@ -413,20 +420,24 @@ static void launch_gj_nbr(double *blocks, const int64_t *boff, const int *pm, co
 
 void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
                        int *perm, int *used, int npatch, int mmax, int *status, hipStream_t st,
-                       int nb_req) {
+                       int variant) {
   if (npatch == 0) return;
-  int nb = gj_panel_width(mmax);
-  if (nb_req == 16 || (nb_req == 32 && nb == 32)) nb = nb_req;
-  // NB 16: 256 threads (one wave per SIMD, the per-step work common to a
-  // wave shared by more rows); NB 32: 512 threads, one row each (no spills)
-  if (mmax <= 512) {
-    if (nb == 32)
-      launch_gj_nbr<32, 1, 512, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
-    else
-      launch_gj_nbr<16, 2, 256, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
-  } else {
+  if (!gj_variant_ok(variant, mmax))
+    variant = gj_variant_ok(kGj32x512, mmax) ? kGj32x512 : kGj16x256;
+  const bool small = mmax <= 512;
+  // NB 16 on 256 threads: one wave per SIMD, the per-step work common to a
+  // wave shared by more rows; on 512 threads: twice the waves, so twice the
+  // update loads in flight per compute unit.  NB 32: one row per thread.
+  if (variant == kGj32x512)
+    launch_gj_nbr<32, 1, 512, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
+  else if (variant == kGj16x512 && small)
+    launch_gj_nbr<16, 1, 512, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
+  else if (variant == kGj16x512)
+    launch_gj_nbr<16, 2, 512, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
+  else if (small)
+    launch_gj_nbr<16, 2, 256, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
+  else
     launch_gj_nbr<16, 4, 256, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
-  }
 }
 
 // ------------------------------------------------------------------ coarsest operator

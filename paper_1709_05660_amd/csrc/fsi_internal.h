@@ -119,7 +119,7 @@ struct MG {
   int *gj_perm = nullptr, *gj_used = nullptr;   // pivot permutations of the block inverses
   int64_t dense_ld = 0;                         // leading dimension of the coarse dense matrix
   int npatch_all = 0, mmax_all = 1;
-  int gj_nb = 0;          // panel width of the batched Gauss-Jordan (0 = by size)
+  int gj_variant = 0;     // batched Gauss-Jordan kernel variant (GjVariant, 0 = by size)
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraphExec_t coarse_graph = nullptr;   // the coarsest inversion's launch chain, replayed per refactor

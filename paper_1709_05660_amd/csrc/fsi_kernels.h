@@ -33,11 +33,14 @@ void launch_extract(const CsrView<double> &J, int npatch, const int *pm, const i
 // Gauss-Jordan inverse of every block, one workgroup per block (m <= 1024),
 // rows never exchanged: Binv[i][c] = S[perm[i]][used[c]] with S left in the
 // block and perm/used at poff[k]; status[k] = 0 ok, else 1 + failing step
-int gj_panel_width(int mmax);
-// nb_req: panel width chosen by the autotuner (16 or 32), 0 = by size
+// kernel variants (panel width x threads), chosen by the autotuner; an
+// unsupported or zero variant falls back to NB 32 where it fits, else NB 16
+// on 256 threads
+enum GjVariant { kGjAuto = 0, kGj16x256 = 1, kGj16x512 = 2, kGj32x512 = 3 };
+bool gj_variant_ok(int variant, int mmax);
 void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
                        int *perm, int *used, int npatch, int mmax, int *status, hipStream_t st,
-                       int nb_req = 0);
+                       int variant = kGjAuto);
 // inverse of the coarsest operator (row-major n x n, leading dimension ld,
 // n <= kMaxCoarse), written row-major to C0; iwork: 2 n ints; status[0]
 // = 0 ok, else 1 + failing step

@@ -368,7 +368,7 @@ void refactor(MG &mg, hipStream_t st) {
                      mg.blk_scratch + L.blk_base, L.sum_m, L.d_row_patch, L.d_row_local, st);
     }
     launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.all_poff, mg.gj_perm, mg.gj_used,
-                      mg.npatch_all, mg.mmax_all, mg.status, st, mg.gj_nb);
+                      mg.npatch_all, mg.mmax_all, mg.status, st, mg.gj_variant);
     hip_check(hipGetLastError(), "gj launch");
     for (int l = 1; l < mg.nlevels; ++l) pack_level(mg, mg.lv[l], st);
   }
@@ -1029,15 +1029,15 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
   }
   if (mg.npatch_all && mg.blk_scratch) {
     char key[256];
-    snprintf(key, sizeof key, "gj2:%d:%d:%lld", mg.mmax_all, mg.npatch_all, (long long)mg.blk_total);
+    snprintf(key, sizeof key, "gj3:%d:%d:%lld", mg.mmax_all, mg.npatch_all, (long long)mg.blk_total);
     auto it = db.find(key);
     if (it != db.end()) {
-      mg.gj_nb = it->second;
+      mg.gj_variant = it->second;
     } else {
-      int best = 16;
+      int best = kGjAuto;
       float best_ms = 1e30f;
-      for (int nb : {16, 32}) {
-        if (nb == 32 && gj_panel_width(mg.mmax_all) != 32) continue;
+      for (int var : {kGj16x256, kGj16x512, kGj32x512}) {
+        if (!gj_variant_ok(var, mg.mmax_all)) continue;
         const float ms = time_events(st, [&] {
           for (int l = 1; l < mg.nlevels; ++l) {
             Level &L = mg.lv[l];
@@ -1046,14 +1046,14 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
                            mg.blk_scratch + L.blk_base, L.sum_m, L.d_row_patch, L.d_row_local, st);
           }
           launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.all_poff, mg.gj_perm,
-                            mg.gj_used, mg.npatch_all, mg.mmax_all, mg.status, st, nb);
+                            mg.gj_used, mg.npatch_all, mg.mmax_all, mg.status, st, var);
         }, 1);
         if (ms < best_ms) {
           best_ms = ms;
-          best = nb;
+          best = var;
         }
       }
-      mg.gj_nb = best;
+      mg.gj_variant = best;
       db[key] = best;
       ++measured;
       refactor(mg, st);   // the blocks were overwritten by the timing runs

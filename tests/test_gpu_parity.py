@@ -298,3 +298,50 @@ def test_autotune_persists_and_keeps_results(c1, tmp_path):
     _say("tuning db", [l for l in lines if l])
     mg.close()
     mg2.close()
+
+
+def _forced_variant_vcycle(p, db, variant, r):
+    """V-cycle output of a hierarchy whose batched block inversion runs the
+    given kernel variant (forced through the tuning database)."""
+    from paper_1709_05660_amd import MG
+    lines = [l for l in open(db).read().split("\n") if l]
+    forced = str(db) + f".v{variant}"
+    with open(forced, "w") as f:
+        for l in lines:
+            k, v = l.split()
+            f.write(f"{k} {variant if k.startswith('gj3:') else v}\n")
+    mg = MG(p, precision="fp64")
+    assert mg.autotune(forced) == 0
+    mg.refactor()                    # the setup inverted the blocks with the default variant
+    z = host(mg.vcycle(dev(r)))
+    mg.close()
+    return z
+
+
+@pytest.mark.parametrize("name", ["c1_2d_128x32", "c3_3d_32x8x8"])
+def test_every_block_inversion_variant(name, tmp_path):
+    """Each batched Gauss-Jordan variant the autotuner may pick (panel width x
+    threads per block) gives the checker's V-cycle; the two 16-column variants
+    do the same arithmetic in the same order, so they agree bit for bit."""
+    from paper_1709_05660_amd import MG
+    p = product_problem(name)
+    oh = oracle_on_product(name)
+    s = oh.spec
+    db = str(tmp_path / "tune.db")
+    mg = MG(p, precision="fp64")
+    mg.autotune(db)
+    mg.close()
+    assert any(l.startswith("gj3:") for l in open(db).read().split("\n"))
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal(p.n)
+    ref = osolver.vcycle(oh.levels, len(oh.levels) - 1, r, s.nu_pre, s.nu_post, s.omega)
+    mmax = max(int(np.diff(p.patches(l)[0]).max()) for l in range(1, p.nlevels))
+    variants = [1, 2] + ([3] if mmax <= 512 else [])
+    zs = {}
+    for v in variants:
+        _say(name, "variant", v, "mmax", mmax)
+        zs[v] = _forced_variant_vcycle(p, db, v, r)
+        rel = np.linalg.norm(zs[v] - ref) / np.linalg.norm(ref)
+        _say(name, "variant", v, "vcycle rel diff", rel)
+        assert rel <= 1e-10
+    assert np.array_equal(zs[1], zs[2])
