@@ -29,6 +29,9 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <functional>
+#include <queue>
+#include <vector>
 
 #include "fsi_kernels.h"
 
@@ -250,7 +253,8 @@ typedef double dx4 __attribute__((ext_vector_type(4)));
 constexpr int kPrefetch = 4;   // row tiles in flight per wave in the updates
 
 // One workgroup of NT threads per block at a time (m <= NT R), looping
-// over blocks k = blockIdx.x, + gridDim.x, ...  Per panel: factor in
+// over the blocks the schedule gives it: sched[0..grid] are offsets into
+// the block list sched[grid + 1 ..] (see gj_schedule).  Per panel: factor in
 // registers, store the panel to the block and to LDS (stride NB + 1), then
 // apply it to the other columns on the matrix cores: each wave owns whole
 // 16-column tiles, reads its tiles' X (the pivot rows' old values) first and
@@ -266,14 +270,17 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
                                                     const int64_t *__restrict__ poff,
                                                     int *__restrict__ perm_all,
                                                     int *__restrict__ used_all,
-                                                    int *__restrict__ status, int npatch) {
+                                                    int *__restrict__ status,
+                                                    const int *__restrict__ sched) {
   constexpr int PS = NB + 1, KC = NB / 4;
   extern __shared__ double PC[];
   __shared__ PivotLds<NB, NT / 64> sh;
   __shared__ int s_used[R * NT];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int jl = lane & 15, kq = lane >> 4;
-  for (int k = blockIdx.x; k < npatch; k += gridDim.x) {
+  const int *list = sched + gridDim.x + 1;
+  for (int t = sched[blockIdx.x]; t < sched[blockIdx.x + 1]; ++t) {
+    const int k = list[t];
     const int m = pm[k];
     double *A = blocks + boff[k];
     int *perm = perm_all + poff[k];
@@ -400,27 +407,58 @@ bool gj_variant_ok(int variant, int mmax) {
   }
 }
 
-template <int NB, int R, int NT, bool UNR>
-static void launch_gj_nbr(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
-                          int *perm, int *used, int npatch, int mmax, int *status, hipStream_t st) {
-  const size_t shm = gj_batched_lds(mmax, NB);
-  (void)hipFuncSetAttribute((const void *)k_gj_batched<NB, R, NT, UNR>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+int gj_batched_grid(int npatch) {
   // as many workgroups as the fewest rounds over the compute units need:
   // the rest of the device stays free for the coarsest inversion
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   ncu = std::max(ncu, 1);
+  npatch = std::max(npatch, 1);
   const int rounds = (npatch + ncu - 1) / ncu;
-  const int grid = (npatch + rounds - 1) / rounds;
+  return (npatch + rounds - 1) / rounds;
+}
+
+std::vector<int> gj_schedule(const int *pm, int npatch, int grid) {
+  // longest processing time first: blocks by decreasing m^3 (the update
+  // work), each to the workgroup with the least work so far (ties: lowest
+  // index), so mixed block sizes do not leave one workgroup two large ones
+  std::vector<int> order(npatch);
+  for (int k = 0; k < npatch; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pm[a] > pm[b]; });
+  typedef std::pair<double, int> Load;
+  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+  for (int g = 0; g < grid; ++g) heap.push(Load(0.0, g));
+  std::vector<std::vector<int>> per(grid);
+  for (int k : order) {
+    Load l = heap.top();
+    heap.pop();
+    per[l.second].push_back(k);
+    const double m = pm[k];
+    heap.push(Load(l.first + m * m * m, l.second));
+  }
+  std::vector<int> out(grid + 1 + npatch);
+  out[0] = 0;
+  for (int g = 0; g < grid; ++g) out[g + 1] = out[g] + (int)per[g].size();
+  for (int g = 0; g < grid; ++g)
+    std::copy(per[g].begin(), per[g].end(), out.begin() + grid + 1 + out[g]);
+  return out;
+}
+
+template <int NB, int R, int NT, bool UNR>
+static void launch_gj_nbr(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
+                          int *perm, int *used, int grid, const int *sched, int mmax, int *status,
+                          hipStream_t st) {
+  const size_t shm = gj_batched_lds(mmax, NB);
+  (void)hipFuncSetAttribute((const void *)k_gj_batched<NB, R, NT, UNR>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   k_gj_batched<NB, R, NT, UNR><<<grid, NT, shm, st>>>(blocks, boff, pm, poff, perm, used, status,
-                                                       npatch);
+                                                       sched);
 }
 
 void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
-                       int *perm, int *used, int npatch, int mmax, int *status, hipStream_t st,
-                       int variant) {
+                       int *perm, int *used, int npatch, int mmax, int *status, int grid,
+                       const int *sched, hipStream_t st, int variant) {
   if (npatch == 0) return;
   if (!gj_variant_ok(variant, mmax))
     variant = gj_variant_ok(kGj32x512, mmax) ? kGj32x512 : kGj16x256;
@@ -429,15 +467,15 @@ void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const
   // wave shared by more rows; on 512 threads: twice the waves, so twice the
   // update loads in flight per compute unit.  NB 32: one row per thread.
   if (variant == kGj32x512)
-    launch_gj_nbr<32, 1, 512, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
+    launch_gj_nbr<32, 1, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st);
   else if (variant == kGj16x512 && small)
-    launch_gj_nbr<16, 1, 512, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
+    launch_gj_nbr<16, 1, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st);
   else if (variant == kGj16x512)
-    launch_gj_nbr<16, 2, 512, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
+    launch_gj_nbr<16, 2, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st);
   else if (small)
-    launch_gj_nbr<16, 2, 256, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
+    launch_gj_nbr<16, 2, 256, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st);
   else
-    launch_gj_nbr<16, 4, 256, true>(blocks, boff, pm, poff, perm, used, npatch, mmax, status, st);
+    launch_gj_nbr<16, 4, 256, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st);
 }
 
 // ------------------------------------------------------------------ coarsest operator

@@ -120,6 +120,8 @@ struct MG {
   int64_t dense_ld = 0;                         // leading dimension of the coarse dense matrix
   int npatch_all = 0, mmax_all = 1;
   int gj_variant = 0;     // batched Gauss-Jordan kernel variant (GjVariant, 0 = by size)
+  int gj_grid = 0;        // its workgroups, and their block lists (gj_schedule)
+  int *gj_sched = nullptr;
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraphExec_t coarse_graph = nullptr;   // the coarsest inversion's launch chain, replayed per refactor

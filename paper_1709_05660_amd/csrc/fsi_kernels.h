@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <vector>
 
 namespace fsi {
 
@@ -38,9 +39,14 @@ void launch_extract(const CsrView<double> &J, int npatch, const int *pm, const i
 // on 256 threads
 enum GjVariant { kGjAuto = 0, kGj16x256 = 1, kGj16x512 = 2, kGj32x512 = 3 };
 bool gj_variant_ok(int variant, int mmax);
+// workgroups of the batched inversion for npatch blocks (the fewest rounds
+// over the compute units), and the host-built schedule: grid + 1 offsets
+// into the block list that follows them (grid + 1 + npatch ints)
+int gj_batched_grid(int npatch);
+std::vector<int> gj_schedule(const int *pm, int npatch, int grid);
 void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
-                       int *perm, int *used, int npatch, int mmax, int *status, hipStream_t st,
-                       int variant = kGjAuto);
+                       int *perm, int *used, int npatch, int mmax, int *status, int grid,
+                       const int *sched, hipStream_t st, int variant = kGjAuto);
 // inverse of the coarsest operator (row-major n x n, leading dimension ld,
 // n <= kMaxCoarse), written row-major to C0; iwork: 2 n ints; status[0]
 // = 0 ok, else 1 + failing step

@@ -368,7 +368,8 @@ void refactor(MG &mg, hipStream_t st) {
                      mg.blk_scratch + L.blk_base, L.sum_m, L.d_row_patch, L.d_row_local, st);
     }
     launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.all_poff, mg.gj_perm, mg.gj_used,
-                      mg.npatch_all, mg.mmax_all, mg.status, st, mg.gj_variant);
+                      mg.npatch_all, mg.mmax_all, mg.status, mg.gj_grid, mg.gj_sched, st,
+                      mg.gj_variant);
     hip_check(hipGetLastError(), "gj launch");
     for (int l = 1; l < mg.nlevels; ++l) pack_level(mg, mg.lv[l], st);
   }
@@ -649,6 +650,11 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
     mg->all_boff = dupload(all_boff.data(), (int64_t)all_boff.size(), mg->owned, st);
     mg->all_pm = dupload(all_pm.data(), (int64_t)all_pm.size(), mg->owned, st);
     mg->all_poff = dupload(all_poff.data(), (int64_t)all_poff.size(), mg->owned, st);
+    if (mg->npatch_all) {
+      mg->gj_grid = gj_batched_grid(mg->npatch_all);
+      const std::vector<int> sched = gj_schedule(all_pm.data(), mg->npatch_all, mg->gj_grid);
+      mg->gj_sched = dupload(sched.data(), (int64_t)sched.size(), mg->owned, st);
+    }
     mg->gj_perm = dalloc<int>(std::max<int64_t>(pbase, 1), mg->owned);
     mg->gj_used = dalloc<int>(std::max<int64_t>(pbase, 1), mg->owned);
     mg->status = dalloc<int>(std::max(mg->npatch_all, 1), mg->owned);
@@ -1046,7 +1052,8 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
                            mg.blk_scratch + L.blk_base, L.sum_m, L.d_row_patch, L.d_row_local, st);
           }
           launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.all_poff, mg.gj_perm,
-                            mg.gj_used, mg.npatch_all, mg.mmax_all, mg.status, st, var);
+                            mg.gj_used, mg.npatch_all, mg.mmax_all, mg.status, mg.gj_grid,
+                            mg.gj_sched, st, var);
         }, 1);
         if (ms < best_ms) {
           best_ms = ms;
