@@ -62,22 +62,24 @@ def measured_traffic():
     return int(b.group(1))
 
 
-def vcycle_times(mg, n, stream, reps=50):
-    """Mean V-cycle time over reps back-to-back applications (warm: the
-    operators may stay in the 256 MB last-level cache between cycles)."""
+def vcycle_times(mg, n, stream, reps=50, warm=5):
+    """Median V-cycle time over reps applications after warm ones, each cycle
+    between its own events (warm: the operators may stay in the 256 MB
+    last-level cache between cycles)."""
     import torch
     r = torch.randn(n, dtype=torch.float64, device="cuda")
     z = torch.empty_like(r)
-    for _ in range(3):
+    for _ in range(warm):
         mg.vcycle(r, z)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
     torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(reps):
+    for e0, e1 in evs:
+        e0.record(stream)
         mg.vcycle(r, z)
-    ev1.record(stream)
+        e1.record(stream)
     torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1) / reps
+    return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
 
 
 def vcycle_cold_ms(mg, n, stream, reps=20):
@@ -151,6 +153,40 @@ def three_d_leg(args):
     return res
 
 
+def small_leg(args):
+    """The 16x4 two-level system (1,380 unknowns): V-cycle and solve in FP64,
+    where launch latency, not bandwidth, sets the time."""
+    import torch
+
+    from paper_1709_05660_amd import MG, Problem
+    from synth import config, fourier_coefficients
+
+    spec = config("c0_2d_16x4")
+    p = Problem(spec, fourier_coefficients(spec.dim, spec.seed))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = torch.as_tensor(p.b).to("cuda")
+        x = torch.zeros_like(b)
+        mg = MG(p, precision="fp64", use_graph=True)
+        for _ in range(args.warmup):
+            mg.refactor()
+            mg.fgmres(b, x, restart=spec.restart, rtol=spec.rtol, maxit=spec.maxit)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            mg.refactor()
+            _, info = mg.fgmres(b, x, restart=spec.restart, rtol=spec.rtol, maxit=spec.maxit)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        res = {"unknowns": p.n, "vcycle_us": round(1e3 * vcycle_times(mg, p.n, stream), 2),
+               "ms_per_step": round(ms, 3), "solves_per_s": round(1e3 / ms, 1),
+               "iters": info["iters"], "true_relres": float(f"{info['true_relres']:.4g}")}
+        mg.close()
+    return res
+
+
 def gpu_leg(args):
     import torch
 
@@ -197,6 +233,7 @@ def gpu_leg(args):
         out["iters"] = infos[-1]["iters"]
         out["true_relres"] = infos[-1]["true_relres"]
         out["converged"] = all(i["converged"] == 1 for i in infos)
+        x64 = x.clone()
         out["vcycle_ms_fp64"] = vcycle_ms(mg)
         out["vcycle_ms_fp64_cold"] = vcycle_cold_ms(mg, p.n, stream)
         out["refactor_ms_fp64"] = infos[-1]["setup_ms"]
@@ -235,16 +272,21 @@ def gpu_leg(args):
                 dst.copy_(src)
             torch.cuda.synchronize()
         mg.close()
-        # ---- mixed precision form (FP32 V-cycle, BF16 block inverses, FP64 Krylov)
+        # ---- mixed precision forms (FP32 V-cycle, 16-bit block inverses, FP64 Krylov)
         if not args.no_mixed:
-            mgm = MG(p, precision=args.mixed, use_graph=True)
-            mgm.autotune(tune_db)
-            timed_steps(mgm, args.warmup, 1e-8)
-            tm, im = timed_steps(mgm, args.steps, 1e-8)
-            out["mixed"] = {"precision": args.mixed, "rtol": 1e-8, "ms_per_step": tm / args.steps,
-                            "solves_per_s": args.steps / (tm * 1e-3), "iters": im[-1]["iters"],
-                            "true_relres": im[-1]["true_relres"], "vcycle_ms": vcycle_ms(mgm)}
-            mgm.close()
+            precs = [args.mixed] + [q for q in ("bf16", "fp16") if q != args.mixed]
+            for q in precs:
+                mgm = MG(p, precision=q, use_graph=True)
+                mgm.autotune(tune_db)
+                timed_steps(mgm, args.warmup, 1e-8)
+                tm, im = timed_steps(mgm, args.steps, 1e-8)
+                err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+                out["mixed" if q == args.mixed else "mixed_" + q] = {
+                    "precision": q, "rtol": 1e-8, "ms_per_step": tm / args.steps,
+                    "solves_per_s": args.steps / (tm * 1e-3), "iters": im[-1]["iters"],
+                    "true_relres": im[-1]["true_relres"], "err_vs_fp64": err,
+                    "vcycle_ms": vcycle_ms(mgm)}
+                mgm.close()
     out["n"] = p.n
     return out
 
@@ -341,8 +383,17 @@ def cpu_leg(args):
         steps += 1
     dt = time.time() - t
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    host = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                host = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(steps / dt, 4), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{steps} full steps (block LU + coarse LU + FGMRES to 1e-10) of {WORKLOAD}, {dt:.1f} s"}
+            "sample": f"{steps} full steps (block LU + coarse LU + FGMRES to 1e-10) of {WORKLOAD}, {dt:.1f} s",
+            "host_cpu": host, "host_logical_cpus": os.cpu_count()}
 
 
 def main():
@@ -393,6 +444,9 @@ def main():
     }
     if "mixed" in g:
         line["mixed"] = {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in g["mixed"].items()}
+    for key in sorted(k for k in g if k.startswith("mixed_")):
+        line[key] = {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in g[key].items()}
+    line["small_c0"] = small_leg(args)
     if not args.no_3d:
         line["three_d"] = three_d_leg(args)
     if not args.no_serve:
