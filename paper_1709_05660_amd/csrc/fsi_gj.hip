@@ -817,16 +817,18 @@ void gj_coarse(double *A, int n, int64_t ld, double *C0, int *status, int *iwork
   k_cgj_finish<<<dim3(cdivg(n, 256), n), 256, 0, st>>>(A, n, ld, perm, used, status, C0);
 }
 
-__global__ void k_csr_to_dense(int n, int64_t ld, const int *rowptr, const int *col,
-                               const double *val, double *A) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// one wave per row, its lanes over the row's entries
+__global__ __launch_bounds__(256) void k_csr_to_dense(int n, int64_t ld, const int *rowptr,
+                                                      const int *col, const double *val,
+                                                      double *A) {
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= n) return;
-  for (int p = rowptr[r]; p < rowptr[r + 1]; ++p) A[r * ld + col[p]] = val[p];
+  const int lane = threadIdx.x & 63;
+  for (int p = rowptr[r] + lane; p < rowptr[r + 1]; p += 64) A[r * ld + col[p]] = val[p];
 }
 void launch_csr_to_dense(const CsrView<double> &A, double *dense, int64_t ld, hipStream_t st) {
   if (A.nrows > 0)
-    k_csr_to_dense<<<cdivg(A.nrows, 256), 256, 0, st>>>(A.nrows, ld, A.rowptr, A.col, A.val,
-                                                         dense);
+    k_csr_to_dense<<<cdivg(A.nrows, 4), 256, 0, st>>>(A.nrows, ld, A.rowptr, A.col, A.val, dense);
 }
 
 }  // namespace fsi

@@ -350,16 +350,19 @@ static void enqueue_coarse(MG &mg, Level &L, hipStream_t st) {
 
 // setup of a1-a3 from the device-resident operator values.  The blocks of
 // all smoothing levels are extracted and inverted in one launch on the main
-// stream, enqueued first; the coarsest inversion (a chain of ~n/16 small
-// launches, replayed from a graph captured at the first refactor) runs
-// beside it on a second stream, on the compute units the batched launch
-// leaves free.
+// stream; the coarsest inversion (a chain of ~n/16 small launches, replayed
+// from a graph captured at the first refactor) runs beside it on a second
+// stream, on the compute units the batched launch leaves free.
 void refactor(MG &mg, hipStream_t st) {
   if (!mg.dense_scratch) throw Error(FSI_E_INVALID, "setup scratch released; refactor unavailable");
   auto t0 = std::chrono::steady_clock::now();
+  // the coarsest inversion needs only the coarsest operator.  Its chain goes
+  // on the side stream after the main stream's (short) extraction launches
+  // and before the batched inversion, so that it starts early while the
+  // host's graph launch overlaps the extraction
+  hip_check(hipEventRecord(mg.ev_fork, st), "fork");
   if (mg.mixed)
     for (int l = 1; l < mg.nlevels; ++l) launch_cast_d2f(mg.lv[l].J.val, mg.lv[l].J.val32, mg.lv[l].J.nnz, st);
-  hip_check(hipEventRecord(mg.ev_fork, st), "fork");
   if (mg.nlevels > 1) {
     launch_fill_f64(mg.blk_scratch, mg.blk_total, 0.0, st);
     for (int l = 1; l < mg.nlevels; ++l) {
@@ -367,11 +370,6 @@ void refactor(MG &mg, hipStream_t st) {
       launch_extract(L.J.v64(), L.npatch, L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff,
                      mg.blk_scratch + L.blk_base, L.sum_m, L.d_row_patch, L.d_row_local, st);
     }
-    launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.all_poff, mg.gj_perm, mg.gj_used,
-                      mg.npatch_all, mg.mmax_all, mg.status, mg.gj_grid, mg.gj_sched, st,
-                      mg.gj_variant);
-    hip_check(hipGetLastError(), "gj launch");
-    for (int l = 1; l < mg.nlevels; ++l) pack_level(mg, mg.lv[l], st);
   }
   hip_check(hipStreamWaitEvent(mg.side_stream, mg.ev_fork, 0), "fork wait");
   if (mg.opts.use_graph) {
@@ -388,12 +386,16 @@ void refactor(MG &mg, hipStream_t st) {
     enqueue_coarse(mg, mg.lv[0], mg.side_stream);
   }
   hip_check(hipEventRecord(mg.ev_join, mg.side_stream), "join");
+  if (mg.nlevels > 1) {
+    launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.all_poff, mg.gj_perm, mg.gj_used,
+                      mg.npatch_all, mg.mmax_all, mg.status, mg.gj_grid, mg.gj_sched, st,
+                      mg.gj_variant);
+    hip_check(hipGetLastError(), "gj launch");
+    for (int l = 1; l < mg.nlevels; ++l) pack_level(mg, mg.lv[l], st);
+  }
   hip_check(hipStreamWaitEvent(st, mg.ev_join, 0), "join wait");
   std::vector<int> hs(mg.npatch_all + 1, 0);
-  if (mg.npatch_all)
-    hip_check(hipMemcpyAsync(hs.data(), mg.status, sizeof(int) * mg.npatch_all, hipMemcpyDeviceToHost, st),
-              "D2H status");
-  hip_check(hipMemcpyAsync(hs.data() + mg.npatch_all, mg.status0, sizeof(int), hipMemcpyDeviceToHost, st),
+  hip_check(hipMemcpyAsync(hs.data(), mg.status, sizeof(int) * (mg.npatch_all + 1), hipMemcpyDeviceToHost, st),
             "D2H status");
   hip_check(hipStreamSynchronize(st), "refactor");
   if (hs[mg.npatch_all]) {
@@ -657,8 +659,9 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
     }
     mg->gj_perm = dalloc<int>(std::max<int64_t>(pbase, 1), mg->owned);
     mg->gj_used = dalloc<int>(std::max<int64_t>(pbase, 1), mg->owned);
-    mg->status = dalloc<int>(std::max(mg->npatch_all, 1), mg->owned);
-    mg->status0 = dalloc<int>(1, mg->owned);
+    // the blocks' statuses, then the coarsest operator's (one read-back)
+    mg->status = dalloc<int>(mg->npatch_all + 1, mg->owned);
+    mg->status0 = mg->status + mg->npatch_all;
     mg->dense_ld = (n0 + 15) / 16 * 16;
     mg->dense_scratch = dalloc<double>(n0 * mg->dense_ld, mg->owned);
     mg->gj_work = dalloc<double>(n0 + 64, mg->owned);
