@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <climits>
 #include <cmath>
 #include <functional>
 #include <queue>
@@ -775,15 +776,47 @@ __global__ __launch_bounds__(NT) void k_cgj_step(double *__restrict__ A, int n, 
   cgj_factor<NB, R, NT>(A, n, ld, pn, wn, perm, used, status, sh, v, stp);
 }
 
-// C0[k * n + c] = inv(A)[k][c] = S[perm[k]][used[c]] (row-major, the dense GEMV layout)
+// C0[k * n + c] = inv(A)[k][c] (row-major, the dense GEMV layout): on F x F
+// S[perm[fk]][used[fc]], on the diagonal of D 1 / a_kk (the row's single
+// entry), zero elsewhere
 __global__ void k_cgj_finish(const double *__restrict__ S, int n, int64_t ld,
                              const int *__restrict__ perm, const int *__restrict__ used,
-                             const int *__restrict__ status, double *__restrict__ C0) {
+                             const int *__restrict__ fpos, const int *__restrict__ rowptr,
+                             const double *__restrict__ val, const int *__restrict__ status,
+                             double *__restrict__ C0) {
   if (status[0]) return;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = blockIdx.y;
   if (c >= n) return;
-  C0[(int64_t)k * n + c] = S[perm[k] * ld + used[c]];
+  const int fk = fpos[k], fc = fpos[c];
+  double x = 0.0;
+  if (fk >= 0 && fc >= 0)
+    x = S[perm[fk] * ld + used[fc]];
+  else if (k == c)
+    x = 1.0 / val[rowptr[k]];
+  C0[(int64_t)k * n + c] = x;
+}
+
+// the diagonal entries of D: a zero or non-finite one is reported as step
+// nf + (its index in dlist) when the free block itself inverted (one
+// workgroup; the smallest failing index wins)
+__global__ __launch_bounds__(256) void k_cgj_dcheck(const int *__restrict__ dlist, int nd, int nf,
+                                                    const int *__restrict__ rowptr,
+                                                    const double *__restrict__ val,
+                                                    int *__restrict__ status) {
+  __shared__ int smin[256];
+  int mine = INT_MAX;
+  for (int t = threadIdx.x; t < nd; t += 256) {
+    const double a = val[rowptr[dlist[t]]];
+    if (!(a != 0.0 && fabs(a) <= DBL_MAX)) mine = min(mine, t);
+  }
+  smin[threadIdx.x] = mine;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) smin[threadIdx.x] = min(smin[threadIdx.x], smin[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && status[0] == 0 && smin[0] != INT_MAX) status[0] = 1 + nf + smin[0];
 }
 
 template <int NB, int R, int NT>
@@ -798,37 +831,49 @@ static void gj_coarse_nb(double *A, int n, int64_t ld, int *perm, int *used, int
   }
 }
 
-void gj_coarse(double *A, int n, int64_t ld, double *C0, int *status, int *iwork,
-               hipStream_t st) {
-  int *perm = iwork, *used = iwork + n;
-  k_fill_i32<<<cdivg(n, 256), 256, 0, st>>>(used, n, -1);
-  // (panel width, rows per thread, threads): 512 threads, the panel rows in
-  // registers without spilling
-  if (n <= 512)
-    gj_coarse_nb<16, 1, 512>(A, n, ld, perm, used, status, st);
-  else if (n <= 1024)
-    gj_coarse_nb<16, 2, 512>(A, n, ld, perm, used, status, st);
-  else if (n <= 1536)
-    gj_coarse_nb<16, 3, 512>(A, n, ld, perm, used, status, st);
-  else if (n <= 3072)
-    gj_coarse_nb<8, 6, 512>(A, n, ld, perm, used, status, st);
-  else
-    gj_coarse_nb<4, 12, 512>(A, n, ld, perm, used, status, st);
-  k_cgj_finish<<<dim3(cdivg(n, 256), n), 256, 0, st>>>(A, n, ld, perm, used, status, C0);
+void gj_coarse(double *A, int nf, int64_t ld, const CoarseSplit &cs, double *C0, int *status,
+               int *iwork, hipStream_t st) {
+  int *perm = iwork, *used = iwork + nf;
+  if (nf > 0) {
+    k_fill_i32<<<cdivg(nf, 256), 256, 0, st>>>(used, nf, -1);
+    // (panel width, rows per thread, threads): 512 threads, the panel rows in
+    // registers without spilling
+    if (nf <= 512)
+      gj_coarse_nb<16, 1, 512>(A, nf, ld, perm, used, status, st);
+    else if (nf <= 1024)
+      gj_coarse_nb<16, 2, 512>(A, nf, ld, perm, used, status, st);
+    else if (nf <= 1536)
+      gj_coarse_nb<16, 3, 512>(A, nf, ld, perm, used, status, st);
+    else if (nf <= 3072)
+      gj_coarse_nb<8, 6, 512>(A, nf, ld, perm, used, status, st);
+    else
+      gj_coarse_nb<4, 12, 512>(A, nf, ld, perm, used, status, st);
+  }
+  if (cs.nd > 0)
+    k_cgj_dcheck<<<1, 256, 0, st>>>(cs.dlist, cs.nd, nf, cs.rowptr, cs.val, status);
+  k_cgj_finish<<<dim3(cdivg(cs.n, 256), cs.n), 256, 0, st>>>(A, cs.n, ld, perm, used, cs.fpos,
+                                                             cs.rowptr, cs.val, status, C0);
 }
 
-// one wave per row, its lanes over the row's entries
+// one wave per row of F, its lanes over the row's entries
 __global__ __launch_bounds__(256) void k_csr_to_dense(int n, int64_t ld, const int *rowptr,
                                                       const int *col, const double *val,
-                                                      double *A) {
+                                                      const int *fpos, double *A) {
   const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= n) return;
+  const int fr = fpos[r];
+  if (fr < 0) return;
   const int lane = threadIdx.x & 63;
-  for (int p = rowptr[r] + lane; p < rowptr[r + 1]; p += 64) A[r * ld + col[p]] = val[p];
+  for (int p = rowptr[r] + lane; p < rowptr[r + 1]; p += 64) {
+    const int fc = fpos[col[p]];
+    if (fc >= 0) A[fr * ld + fc] = val[p];
+  }
 }
-void launch_csr_to_dense(const CsrView<double> &A, double *dense, int64_t ld, hipStream_t st) {
+void launch_csr_to_dense(const CsrView<double> &A, const int *fpos, double *dense, int64_t ld,
+                         hipStream_t st) {
   if (A.nrows > 0)
-    k_csr_to_dense<<<cdivg(A.nrows, 4), 256, 0, st>>>(A.nrows, ld, A.rowptr, A.col, A.val, dense);
+    k_csr_to_dense<<<cdivg(A.nrows, 4), 256, 0, st>>>(A.nrows, ld, A.rowptr, A.col, A.val, fpos,
+                                                      dense);
 }
 
 }  // namespace fsi

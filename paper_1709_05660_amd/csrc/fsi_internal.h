@@ -118,6 +118,10 @@ struct MG {
   int *all_pm = nullptr;
   int *gj_perm = nullptr, *gj_used = nullptr;   // pivot permutations of the block inverses
   int64_t dense_ld = 0;                         // leading dimension of the coarse dense matrix
+  // coarsest operator split (CoarseSplit): nf free dofs inverted densely, nd
+  // diagonal-only dofs by a reciprocal
+  int coarse_nf = 0, coarse_nd = 0;
+  int *coarse_fpos = nullptr, *coarse_dlist = nullptr;
   int npatch_all = 0, mmax_all = 1;
   int gj_variant = 0;     // batched Gauss-Jordan kernel variant (GjVariant, 0 = by size)
   int gj_grid = 0;        // its workgroups, and their block lists (gj_schedule)

@@ -47,12 +47,25 @@ std::vector<int> gj_schedule(const int *pm, int npatch, int grid);
 void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
                        int *perm, int *used, int npatch, int mmax, int *status, int grid,
                        const int *sched, hipStream_t st, int variant = kGjAuto);
-// inverse of the coarsest operator (row-major n x n, leading dimension ld,
-// n <= kMaxCoarse), written row-major to C0; iwork: 2 n ints; status[0]
-// = 0 ok, else 1 + failing step
+// The coarsest operator's dofs split into D, whose row and column hold only
+// the diagonal entry (Dirichlet rows of a symmetrically eliminated
+// operator), and the free rest F: the operator is diag(a_D) + A_FF up to
+// ordering, and so is its inverse.  fpos[i]: position of dof i in F, -1 in
+// D; dlist: the nd dofs of D; rowptr/val: the operator's CSR on the device
+// (a_dd is the single entry of row d).
+struct CoarseSplit {
+  int n = 0, nd = 0;
+  const int *fpos = nullptr, *dlist = nullptr, *rowptr = nullptr;
+  const double *val = nullptr;
+};
+// inverse of the coarsest operator written row-major (n x n) to C0: the
+// dense F x F block A (leading dimension ld, nf <= kMaxCoarse, overwritten)
+// by Gauss-Jordan, 1 / a_dd on D; iwork: 2 nf ints; status[0] = 0 ok, else
+// 1 + failing step (the steps of D follow the nf of F)
 constexpr int kMaxCoarse = 6144;
 void launch_fill_i32(int *x, int n, int v, hipStream_t st);
-void gj_coarse(double *A, int n, int64_t ld, double *C0, int *status, int *iwork, hipStream_t st);
+void gj_coarse(double *A, int nf, int64_t ld, const CoarseSplit &cs, double *C0, int *status,
+               int *iwork, hipStream_t st);
 // Owned rows of Binv_k, column-major per (patch, 64 owned rows) task: task
 // (k, r0) with nr = min(64, o_k - r0) rows holds entry (c, r) at
 // W[woff_k + r0 m_k + c nr + r - r0]; optional FP32/16-bit copies
@@ -145,6 +158,8 @@ void launch_start_cycle(int n, const double *r, const double *nrm2, double *v, d
 }  // namespace fsi
 
 namespace fsi {
-// dense row-major n x n (leading dimension ld) from CSR (zero-filled beforehand)
-void launch_csr_to_dense(const CsrView<double> &A, double *dense, int64_t ld, hipStream_t st);
+// the F x F block (see CoarseSplit), dense row-major with leading dimension
+// ld, from CSR (zero-filled beforehand)
+void launch_csr_to_dense(const CsrView<double> &A, const int *fpos, double *dense, int64_t ld,
+                         hipStream_t st);
 }  // namespace fsi

@@ -339,12 +339,22 @@ static void pack_level(MG &mg, Level &L, hipStream_t st) {
 // coarsest operator: dense copy, Gauss-Jordan inverse written column-major
 // for the GEMV (no sync)
 static void enqueue_coarse(MG &mg, Level &L, hipStream_t st) {
-  const int n = L.n;
+  const int nf = mg.coarse_nf;
   double *A = mg.dense_scratch;
-  launch_fill_f64(A, (int64_t)n * mg.dense_ld, 0.0, st);
-  launch_csr_to_dense(L.J.v64(), A, mg.dense_ld, st);
+  const CsrView<double> J = L.J.v64();
+  if (nf > 0) {
+    launch_fill_f64(A, (int64_t)nf * mg.dense_ld, 0.0, st);
+    launch_csr_to_dense(J, mg.coarse_fpos, A, mg.dense_ld, st);
+  }
   launch_fill_i32(mg.status0, 1, 0, st);   // a kernel, not a memset: this chain is graph-captured
-  gj_coarse(A, n, mg.dense_ld, L.C0, mg.status0, reinterpret_cast<int *>(mg.gj_work), st);
+  CoarseSplit cs;
+  cs.n = L.n;
+  cs.nd = mg.coarse_nd;
+  cs.fpos = mg.coarse_fpos;
+  cs.dlist = mg.coarse_dlist;
+  cs.rowptr = J.rowptr;
+  cs.val = J.val;
+  gj_coarse(A, nf, mg.dense_ld, cs, L.C0, mg.status0, reinterpret_cast<int *>(mg.gj_work), st);
   hip_check(hipGetLastError(), "coarse launch");
 }
 
@@ -662,8 +672,28 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
     // the blocks' statuses, then the coarsest operator's (one read-back)
     mg->status = dalloc<int>(mg->npatch_all + 1, mg->owned);
     mg->status0 = mg->status + mg->npatch_all;
-    mg->dense_ld = (n0 + 15) / 16 * 16;
-    mg->dense_scratch = dalloc<double>(n0 * mg->dense_ld, mg->owned);
+    // coarsest operator: the dofs whose row and column hold only the
+    // diagonal (D) are inverted by a reciprocal, the rest (F) densely
+    {
+      const fsi_csr &J0 = levels[0].J;
+      std::vector<int> colcnt(n0, 0), fpos(n0, -1), dlist;
+      for (int64_t p = 0; p < J0.nnz; ++p) ++colcnt[J0.colind[p]];
+      int nf = 0;
+      for (int64_t i = 0; i < n0; ++i) {
+        const bool diag_only = J0.rowptr[i + 1] - J0.rowptr[i] == 1 && J0.colind[J0.rowptr[i]] == i &&
+                               colcnt[i] == 1;
+        if (diag_only)
+          dlist.push_back((int)i);
+        else
+          fpos[i] = nf++;
+      }
+      mg->coarse_nf = nf;
+      mg->coarse_nd = (int)dlist.size();
+      mg->coarse_fpos = dupload(fpos.data(), n0, mg->owned, st);
+      mg->coarse_dlist = dupload(dlist.data(), (int64_t)dlist.size(), mg->owned, st);
+    }
+    mg->dense_ld = (std::max(mg->coarse_nf, 1) + 15) / 16 * 16;
+    mg->dense_scratch = dalloc<double>(std::max(mg->coarse_nf, 1) * mg->dense_ld, mg->owned);
     mg->gj_work = dalloc<double>(n0 + 64, mg->owned);
     mg->lv[0].C0 = dalloc<double>(n0 * n0, mg->owned);
     if (side_st) {

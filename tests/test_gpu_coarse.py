@@ -104,3 +104,63 @@ def test_fgmres_one_level_small(n, graph):
     assert info["status"] == 0 and info["converged"] == 1
     assert info["iters"] <= 2
     assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def with_diagonal_dofs(nf, nd, ndecoy, seed):
+    """A saddle-point block on nf dofs, plus nd dofs whose row and column hold
+    only a (nonzero, random) diagonal, plus ndecoy rows with a single
+    diagonal entry whose column another row also uses (these belong to the
+    dense part), all interleaved by a random permutation."""
+    rng = np.random.default_rng(seed)
+    parts = [saddle(nf, seed)] if nf else []
+    if ndecoy:
+        # decoy rows: [[a I, 0], [C, A_F]] stays nonsingular
+        A_F = parts[0]
+        Cc = sp.random(nf, ndecoy, density=min(1.0, 4.0 / nf), random_state=rng, format="csr")
+        Cc = Cc + sp.csr_matrix((np.ones(ndecoy), (np.arange(ndecoy) % nf, np.arange(ndecoy))),
+                                shape=(nf, ndecoy))
+        top = sp.hstack([sp.diags(rng.uniform(1.0, 3.0, ndecoy)), sp.csr_matrix((ndecoy, nf))])
+        parts = [sp.vstack([top, sp.hstack([Cc, A_F])]).tocsr()]
+    dvals = rng.uniform(0.5, 2.0, nd) * rng.choice([-1.0, 1.0], nd)
+    if nd:
+        parts.append(sp.diags(dvals).tocsr())
+    A = sp.block_diag(parts, format="csr")
+    perm = rng.permutation(A.shape[0])
+    A = A[perm][:, perm].tocsr()
+    A.sort_indices()
+    return A
+
+
+@pytest.mark.parametrize("nf,nd,ndecoy", [(300, 100, 0), (700, 990, 37), (1100, 306, 0), (0, 64, 0)])
+def test_coarsest_with_diagonal_only_dofs(nf, nd, ndecoy):
+    """Dofs whose row and column hold only the diagonal are inverted by a
+    reciprocal and the rest densely; decoy single-entry rows whose column
+    is used elsewhere stay in the dense part."""
+    import torch
+
+    from paper_1709_05660_amd import MG
+    A = with_diagonal_dofs(nf, nd, ndecoy, 900 + nf + nd)
+    n = A.shape[0]
+    _say("coarse with diagonal dofs", nf, nd, ndecoy, "n", n)
+    mg = MG(OneLevel(A), precision="fp64")
+    rng = np.random.default_rng(n)
+    b = rng.standard_normal(n)
+    y = mg.apply(0, 5, torch.as_tensor(b, device="cuda")).cpu().numpy()
+    mg.close()
+    ref = np.linalg.solve(A.toarray(), b)
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    _say("  rel err", err)
+    assert err <= 1e-11
+
+
+def test_coarsest_zero_diagonal_only_dof_is_reported():
+    from paper_1709_05660_amd import MG, FsiError
+    A = with_diagonal_dofs(200, 40, 0, 77)
+    colcnt = np.bincount(A.indices, minlength=A.shape[0])
+    rows = [i for i in range(A.shape[0]) if A.indptr[i + 1] - A.indptr[i] == 1
+            and A.indices[A.indptr[i]] == i and colcnt[i] == 1]
+    assert len(rows) == 40
+    A.data[A.indptr[rows[5]]] = 0.0     # a stored zero: still a diagonal-only dof
+    with pytest.raises(FsiError) as e:
+        MG(OneLevel(A), precision="fp64")
+    assert "coarsest" in str(e.value)
