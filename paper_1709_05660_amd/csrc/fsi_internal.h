@@ -126,6 +126,7 @@ struct MG {
   int gj_variant = 0;     // batched Gauss-Jordan kernel variant (GjVariant, 0 = by size)
   int gj_grid = 0;        // its workgroups, and their block lists (gj_schedule)
   int *gj_sched = nullptr;
+  std::vector<int> h_all_pm;   // block sizes of all levels, in the batched order
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraphExec_t coarse_graph = nullptr;   // the coarsest inversion's launch chain, replayed per refactor

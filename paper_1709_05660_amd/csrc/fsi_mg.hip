@@ -663,9 +663,12 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
     mg->all_pm = dupload(all_pm.data(), (int64_t)all_pm.size(), mg->owned, st);
     mg->all_poff = dupload(all_poff.data(), (int64_t)all_poff.size(), mg->owned, st);
     if (mg->npatch_all) {
+      // room for the schedule of any grid up to one workgroup per block
+      mg->h_all_pm = all_pm;
       mg->gj_grid = gj_batched_grid(mg->npatch_all);
       const std::vector<int> sched = gj_schedule(all_pm.data(), mg->npatch_all, mg->gj_grid);
-      mg->gj_sched = dupload(sched.data(), (int64_t)sched.size(), mg->owned, st);
+      mg->gj_sched = dalloc<int>(2 * (int64_t)mg->npatch_all + 1, mg->owned);
+      stage_copy(mg->gj_sched, sched.data(), sizeof(int) * sched.size(), st);
     }
     mg->gj_perm = dalloc<int>(std::max<int64_t>(pbase, 1), mg->owned);
     mg->gj_used = dalloc<int>(std::max<int64_t>(pbase, 1), mg->owned);
@@ -1014,6 +1017,16 @@ static float time_events(hipStream_t st, const std::function<void()> &fn, int re
   return ms / reps;
 }
 
+// the batched inversion's workgroup count and its longest-first schedule
+static void set_gj_grid(MG &mg, int grid, hipStream_t st) {
+  grid = std::max(1, std::min(grid, mg.npatch_all));
+  const std::vector<int> sched = gj_schedule(mg.h_all_pm.data(), mg.npatch_all, grid);
+  hip_check(hipMemcpyAsync(mg.gj_sched, sched.data(), sizeof(int) * sched.size(), hipMemcpyHostToDevice, st),
+            "schedule upload");
+  hip_check(hipStreamSynchronize(st), "schedule upload");
+  mg.gj_grid = grid;
+}
+
 int autotune(MG &mg, const char *db_path, hipStream_t st) {
   std::map<std::string, int> db;
   if (db_path) {
@@ -1097,6 +1110,46 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
       db[key] = best;
       ++measured;
       refactor(mg, st);   // the blocks were overwritten by the timing runs
+    }
+    // the batched inversion's grid: the fewest rounds over the compute units
+    // leave the most room to the coarsest inversion beside it, more
+    // workgroups shorten the batched launch itself; timed on whole refactors
+    // (the schedule changes which workgroup inverts a block, not the result)
+    snprintf(key, sizeof key, "gjg:%d:%d:%lld:%d", mg.mmax_all, mg.npatch_all, (long long)mg.blk_total,
+             mg.gj_variant);
+    it = db.find(key);
+    if (it != db.end()) {
+      set_gj_grid(mg, it->second, st);
+    } else {
+      int dev = 0, ncu = 256;
+      if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+      std::vector<int> cands;
+      for (int g : {gj_batched_grid(mg.npatch_all), ncu - 64, ncu - 40}) {
+        g = std::max(1, std::min(g, mg.npatch_all));
+        if (std::find(cands.begin(), cands.end(), g) == cands.end()) cands.push_back(g);
+      }
+      int best = cands[0];
+      if (cands.size() > 1) {
+        double best_ms = 1e300;
+        for (int g : cands) {
+          set_gj_grid(mg, g, st);
+          refactor(mg, st);
+          for (int rep = 0; rep < 2; ++rep) {
+            const auto a = std::chrono::steady_clock::now();
+            refactor(mg, st);
+            const double ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
+            if (ms < best_ms) {
+              best_ms = ms;
+              best = g;
+            }
+          }
+        }
+        ++measured;
+      }
+      set_gj_grid(mg, best, st);
+      db[key] = best;
     }
   }
   hip_check(hipGetLastError(), "autotune");

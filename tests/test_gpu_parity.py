@@ -309,7 +309,11 @@ def _forced_variant_vcycle(p, db, variant, r):
     with open(forced, "w") as f:
         for l in lines:
             k, v = l.split()
-            f.write(f"{k} {variant if k.startswith('gj3:') else v}\n")
+            if k.startswith("gj3:"):
+                v = variant
+            elif k.startswith("gjg:"):              # the grid entry is kept per variant
+                k = k.rsplit(":", 1)[0] + f":{variant}"
+            f.write(f"{k} {v}\n")
     mg = MG(p, precision="fp64")
     assert mg.autotune(forced) == 0
     mg.refactor()                    # the setup inverted the blocks with the default variant
