@@ -408,6 +408,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--steps-3d", type=int, default=5)
     ap.add_argument("--only-3d", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true")
@@ -446,7 +447,8 @@ def main():
         line["mixed"] = {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in g["mixed"].items()}
     for key in sorted(k for k in g if k.startswith("mixed_")):
         line[key] = {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in g[key].items()}
-    line["small_c0"] = small_leg(args)
+    if not args.no_small:
+        line["small_c0"] = small_leg(args)
     if not args.no_3d:
         line["three_d"] = three_d_leg(args)
     if not args.no_serve:
