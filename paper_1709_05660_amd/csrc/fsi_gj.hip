@@ -263,8 +263,10 @@ constexpr int kPrefetch = 4;   // row tiles in flight per wave in the updates
 // v_mfma_f64_16x16x4f64 (A: PC rows, B: X; operand layouts: A[i][k] in lane
 // i + 16 k, B[k][j] in lane j + 16 k, D[i][j] in lane j + 16 (i % 4),
 // register i / 4), the tiles' loads issued kPrefetch tiles ahead.  The block array is padded by NB doubles at its end:
-// a panel slice is loaded whole from its row base.
-template <int NB, int R, int NT, bool UNR>
+// a panel slice is loaded whole from its row base.  GPC: the update reads
+// the panel from the block's own panel columns (just written, in L2)
+// instead of an LDS copy, so NB = 32 needs no LDS of m (NB + 1) doubles.
+template <int NB, int R, int NT, bool UNR, bool GPC>
 __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
                                                     const int64_t *__restrict__ boff,
                                                     const int *__restrict__ pm,
@@ -315,7 +317,7 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
 #pragma unroll
           for (int c = 0; c < NB; ++c) {
             if (c < w) A[i * m + p0 + c] = v[q][c];
-            PC[i * PS + c] = v[q][c];
+            if constexpr (!GPC) PC[i * PS + c] = v[q][c];
           }
           if (stp[q] >= p0) s_used[i] = stp[q];
         }
@@ -361,7 +363,15 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
 #pragma unroll
               for (int r = 0; r < 4; ++r) su[r] = s_used[min(rt * 16 + r * 4 + kq, m - 1)];
 #pragma unroll
-              for (int kk = 0; kk < KC; ++kk) a[kk] = PC[min(ia, m - 1) * PS + kk * 4 + kq];
+              for (int kk = 0; kk < KC; ++kk) {
+                if constexpr (GPC) {
+                  // clamped to the panel's last column, zeroed beyond it
+                  const double x = A[min(ia, m - 1) * m + p0 + min(kk * 4 + kq, w - 1)];
+                  a[kk] = kk * 4 + kq < w ? x : 0.0;
+                } else {
+                  a[kk] = PC[min(ia, m - 1) * PS + kk * 4 + kq];
+                }
+              }
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const int i = rt * 16 + r * 4 + kq;
@@ -403,6 +413,8 @@ bool gj_variant_ok(int variant, int mmax) {
       return mmax <= 1024;
     case kGj32x512:   // one row per thread, and the LDS panel next to the static LDS
       return mmax <= 512 && gj_batched_lds(mmax, 32) <= 140 * 1024;
+    case kGjWideG:    // panel read from the block itself: no LDS of m
+      return mmax <= 1024;
     default:
       return false;
   }
@@ -446,15 +458,16 @@ std::vector<int> gj_schedule(const int *pm, int npatch, int grid) {
   return out;
 }
 
-template <int NB, int R, int NT, bool UNR>
+template <int NB, int R, int NT, bool UNR, bool GPC = false>
 static void launch_gj_nbr(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
                           int *perm, int *used, int grid, const int *sched, int mmax, int *status,
                           hipStream_t st) {
-  const size_t shm = gj_batched_lds(mmax, NB);
-  (void)hipFuncSetAttribute((const void *)k_gj_batched<NB, R, NT, UNR>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  k_gj_batched<NB, R, NT, UNR><<<grid, NT, shm, st>>>(blocks, boff, pm, poff, perm, used, status,
-                                                       sched);
+  const size_t shm = GPC ? 0 : gj_batched_lds(mmax, NB);
+  if (shm)
+    (void)hipFuncSetAttribute((const void *)k_gj_batched<NB, R, NT, UNR, GPC>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  k_gj_batched<NB, R, NT, UNR, GPC><<<grid, NT, shm, st>>>(blocks, boff, pm, poff, perm, used,
+                                                            status, sched);
 }
 
 void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
@@ -466,9 +479,17 @@ void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const
   const bool small = mmax <= 512;
   // NB 16 on 256 threads: one wave per SIMD, the per-step work common to a
   // wave shared by more rows; on 512 threads: twice the waves, so twice the
-  // update loads in flight per compute unit.  NB 32: one row per thread.
+  // update loads in flight per compute unit.  NB 32 (24 for two rows per
+  // thread, the most that stays in registers): 1/2 (2/3) of the update
+  // traffic of NB 16, the panel in LDS or read from the block.
   if (variant == kGj32x512)
     launch_gj_nbr<32, 1, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st);
+  else if (variant == kGjWideG && small)
+    launch_gj_nbr<32, 1, 512, true, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax,
+                                          status, st);
+  else if (variant == kGjWideG)
+    launch_gj_nbr<24, 2, 512, true, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax,
+                                          status, st);
   else if (variant == kGj16x512 && small)
     launch_gj_nbr<16, 1, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st);
   else if (variant == kGj16x512)

@@ -34,10 +34,12 @@ void launch_extract(const CsrView<double> &J, int npatch, const int *pm, const i
 // Gauss-Jordan inverse of every block, one workgroup per block (m <= 1024),
 // rows never exchanged: Binv[i][c] = S[perm[i]][used[c]] with S left in the
 // block and perm/used at poff[k]; status[k] = 0 ok, else 1 + failing step
-// kernel variants (panel width x threads), chosen by the autotuner; an
-// unsupported or zero variant falls back to NB 32 where it fits, else NB 16
-// on 256 threads
-enum GjVariant { kGjAuto = 0, kGj16x256 = 1, kGj16x512 = 2, kGj32x512 = 3 };
+// kernel variants (panel width x threads), chosen by the autotuner: NB 16
+// on 256 or 512 threads, NB 32 on 512 with the panel in LDS (m <= 512), and
+// a wide panel read back from the block itself (NB 32 for m <= 512, 24 for
+// m <= 1024, 512 threads).  An unsupported or zero variant falls back to
+// NB 32 where it fits, else NB 16 on 256 threads
+enum GjVariant { kGjAuto = 0, kGj16x256 = 1, kGj16x512 = 2, kGj32x512 = 3, kGjWideG = 4 };
 bool gj_variant_ok(int variant, int mmax);
 // workgroups of the batched inversion for npatch blocks (the fewest rounds
 // over the compute units), and the host-built schedule: grid + 1 offsets

@@ -325,8 +325,9 @@ def _forced_variant_vcycle(p, db, variant, r):
 @pytest.mark.parametrize("name", ["c1_2d_128x32", "c3_3d_32x8x8"])
 def test_every_block_inversion_variant(name, tmp_path):
     """Each batched Gauss-Jordan variant the autotuner may pick (panel width x
-    threads per block) gives the checker's V-cycle; the two 16-column variants
-    do the same arithmetic in the same order, so they agree bit for bit."""
+    threads per block, panel in LDS or read from the block) gives the
+    checker's V-cycle; variants doing the same arithmetic in the same order
+    (the two 16-column ones; the two 32-column ones) agree bit for bit."""
     from paper_1709_05660_amd import MG
     p = product_problem(name)
     oh = oracle_on_product(name)
@@ -340,7 +341,7 @@ def test_every_block_inversion_variant(name, tmp_path):
     r = rng.standard_normal(p.n)
     ref = osolver.vcycle(oh.levels, len(oh.levels) - 1, r, s.nu_pre, s.nu_post, s.omega)
     mmax = max(int(np.diff(p.patches(l)[0]).max()) for l in range(1, p.nlevels))
-    variants = [1, 2] + ([3] if mmax <= 512 else [])
+    variants = [1, 2, 4] + ([3] if mmax <= 512 else [])
     zs = {}
     for v in variants:
         _say(name, "variant", v, "mmax", mmax)
@@ -349,3 +350,5 @@ def test_every_block_inversion_variant(name, tmp_path):
         _say(name, "variant", v, "vcycle rel diff", rel)
         assert rel <= 1e-10
     assert np.array_equal(zs[1], zs[2])
+    if 3 in zs:                  # NB 32 with the panel in LDS or read from the block
+        assert np.array_equal(zs[3], zs[4])
