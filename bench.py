@@ -377,6 +377,8 @@ def cpu_leg(args):
     from oracle import solver as osolver
     from synth import config, fourier_coefficients
 
+    from threadpoolctl import threadpool_limits
+
     spec = config(WORKLOAD)
     h = oprob.build(spec, fourier_coefficients(spec.dim, spec.seed), factor=False)
     t = time.time()
@@ -387,6 +389,23 @@ def cpu_leg(args):
         steps += 1
     dt = time.time() - t
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    # the same step on one thread
+    with threadpool_limits(limits=1):
+        t = time.time()
+        osolver.setup_factors(h.levels)
+        oprob.solve(h)
+        dt1 = time.time() - t
+    # host memory bandwidth: a STREAM-like triad a = b + 3 c over 128 MB
+    # arrays, in two numpy passes (c read, a written; a and b read, a written)
+    b_, c_ = np.ones(16 << 20), np.full(16 << 20, 2.0)
+    a_ = np.empty_like(b_)
+    best = 1e30
+    for _ in range(5):
+        t = time.perf_counter()
+        np.multiply(c_, 3.0, out=a_)
+        np.add(a_, b_, out=a_)
+        best = min(best, time.perf_counter() - t)
+    triad_gbs = 5 * a_.nbytes / best / 1e9
     host = "unknown"
     try:
         for ln in open("/proc/cpuinfo"):
@@ -397,7 +416,8 @@ def cpu_leg(args):
         pass
     return {"value": round(steps / dt, 4), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{steps} full steps (block LU + coarse LU + FGMRES to 1e-10) of {WORKLOAD}, {dt:.1f} s",
-            "host_cpu": host, "host_logical_cpus": os.cpu_count()}
+            "host_cpu": host, "host_logical_cpus": os.cpu_count(),
+            "one_thread_value": round(1.0 / dt1, 4), "host_triad_gb_s": round(triad_gbs, 1)}
 
 
 def main():
