@@ -50,6 +50,10 @@ struct Level {
       *d_unowned = nullptr;
   int n_unowned = 0;
   int64_t *d_pdof_off = nullptr, *d_woff = nullptr, *d_boff = nullptr;
+  // block extraction map (launch_extract_map): nslots (entry, position) pairs
+  int64_t ext_nslots = 0;
+  int *d_ext_src = nullptr, *d_ext_dst = nullptr;
+  int64_t *d_ext_slot_off = nullptr;
   double *W64 = nullptr;
   float *W32 = nullptr;
   uint16_t *W16 = nullptr;

@@ -27,10 +27,17 @@ void launch_spmv(const CsrView<T> &A, const T *x, const T *r, T *y, int mode, in
 
 // ---- setup (a1, a2, a3)
 void launch_fill_f64(double *x, int64_t n, double v, hipStream_t st);
-// B_k = J[I_k, I_k] (row-major, zero-filled beforehand)
-void launch_extract(const CsrView<double> &J, int npatch, const int *pm, const int64_t *pdof_off,
-                    const int *dof, const int64_t *boff, double *blocks, int64_t total_rows,
-                    const int *row_patch, const int *row_local, hipStream_t st);
+// extraction map of a level (built once): for every slot, one CSR entry of a
+// block row (slots of row t start at slot_off[t]), the entry's index src and
+// its position dst in the level's blocks (row-major B_k at boff[k]), -1 when
+// its column lies outside the block; dst < 2^31 (checked on the host)
+void launch_extract_map(const CsrView<double> &J, const int *pm, const int64_t *pdof_off,
+                        const int *dof, const int64_t *boff, int64_t total_rows,
+                        const int *row_patch, const int *row_local, const int64_t *slot_off,
+                        int *src, int *dst, hipStream_t st);
+// B_k = J[I_k, I_k] through the map (blocks zero-filled beforehand)
+void launch_extract(const double *val, int64_t nslots, const int *src, const int *dst,
+                    double *blocks, hipStream_t st);
 // Gauss-Jordan inverse of every block, one workgroup per block (m <= 1024),
 // rows never exchanged: Binv[i][c] = S[perm[i]][used[c]] with S left in the
 // block and perm/used at poff[k]; status[k] = 0 ok, else 1 + failing step

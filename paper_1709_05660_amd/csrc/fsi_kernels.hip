@@ -159,18 +159,20 @@ void launch_copy_f64(int n, const double *x, double *y, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ block extraction
-// One wave per (patch, local row): every nonzero of the CSR row whose column
-// belongs to the patch lands at its position (binary search in the sorted dof list).
-__global__ __launch_bounds__(256) void k_extract(int nrows_total, const int *__restrict__ row_patch,
-                                                 const int *__restrict__ row_local,
-                                                 const int *__restrict__ pm,
-                                                 const int64_t *__restrict__ pdof_off,
-                                                 const int *__restrict__ dof,
-                                                 const int64_t *__restrict__ boff,
-                                                 const int *__restrict__ rowptr,
-                                                 const int *__restrict__ col,
-                                                 const double *__restrict__ val,
-                                                 double *__restrict__ blocks) {
+// Extraction map, built once at setup: one wave per (patch, local row); each
+// slot (one CSR entry of the row, slots of row t from slot_off[t]) records the
+// entry's index and its position in the level's blocks, found by a binary
+// search of its column in the sorted dof list, or -1 outside the patch.
+__global__ __launch_bounds__(256) void k_extract_map(int nrows_total, const int *__restrict__ row_patch,
+                                                     const int *__restrict__ row_local,
+                                                     const int *__restrict__ pm,
+                                                     const int64_t *__restrict__ pdof_off,
+                                                     const int *__restrict__ dof,
+                                                     const int64_t *__restrict__ boff,
+                                                     const int *__restrict__ rowptr,
+                                                     const int *__restrict__ col,
+                                                     const int64_t *__restrict__ slot_off,
+                                                     int *__restrict__ src, int *__restrict__ dst) {
   const int t = blockIdx.x * 4 + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (t >= nrows_total) return;
@@ -179,15 +181,16 @@ __global__ __launch_bounds__(256) void k_extract(int nrows_total, const int *__r
   const int m = pm[k];
   const int *d = dof + pdof_off[k];
   const int g = d[i];
-  double *B = blocks + boff[k] + (int64_t)i * m;
+  const int64_t base = boff[k] + (int64_t)i * m;
+  const int64_t s0 = slot_off[t];
   for (int p = rowptr[g] + lane; p < rowptr[g + 1]; p += 64) {
     const int c = col[p];
-    int lo = 0, hi = m - 1;
+    int lo = 0, hi = m - 1, at = -1;
     while (lo <= hi) {
       const int mid = (lo + hi) >> 1;
       const int v = d[mid];
       if (v == c) {
-        B[mid] = val[p];
+        at = mid;
         break;
       }
       if (v < c)
@@ -195,17 +198,36 @@ __global__ __launch_bounds__(256) void k_extract(int nrows_total, const int *__r
       else
         hi = mid - 1;
     }
+    src[s0 + (p - rowptr[g])] = p;
+    dst[s0 + (p - rowptr[g])] = at < 0 ? -1 : (int)(base + at);
   }
 }
 
-void launch_extract(const CsrView<double> &J, int npatch, const int *pm, const int64_t *pdof_off,
-                    const int *dof, const int64_t *boff, double *blocks, int64_t total_rows,
-                    const int *row_patch, const int *row_local, hipStream_t st) {
-  (void)npatch;
+void launch_extract_map(const CsrView<double> &J, const int *pm, const int64_t *pdof_off,
+                        const int *dof, const int64_t *boff, int64_t total_rows,
+                        const int *row_patch, const int *row_local, const int64_t *slot_off,
+                        int *src, int *dst, hipStream_t st) {
   if (total_rows == 0) return;
-  k_extract<<<cdiv(total_rows, 4), 256, 0, st>>>((int)total_rows, row_patch, row_local, pm,
-                                                  pdof_off, dof, boff, J.rowptr, J.col, J.val,
-                                                  blocks);
+  k_extract_map<<<cdiv(total_rows, 4), 256, 0, st>>>((int)total_rows, row_patch, row_local, pm,
+                                                      pdof_off, dof, boff, J.rowptr, J.col,
+                                                      slot_off, src, dst);
+}
+
+// B_k = J[I_k, I_k]: one thread per slot of the map
+__global__ __launch_bounds__(256) void k_extract(int64_t nslots, const int *__restrict__ src,
+                                                 const int *__restrict__ dst,
+                                                 const double *__restrict__ val,
+                                                 double *__restrict__ blocks) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nslots) return;
+  const int q = dst[e];
+  if (q >= 0) blocks[q] = val[src[e]];
+}
+
+void launch_extract(const double *val, int64_t nslots, const int *src, const int *dst,
+                    double *blocks, hipStream_t st) {
+  if (nslots == 0) return;
+  k_extract<<<(unsigned)((nslots + 255) / 256), 256, 0, st>>>(nslots, src, dst, val, blocks);
 }
 
 // ------------------------------------------------------------------ packing of owned rows

@@ -219,7 +219,8 @@ static void upload_csr(const fsi_csr &A, DevCsr &D, bool want32, DevList &own, h
 }
 
 // ------------------------------------------------------------------ patch layout
-static void build_patch_layout(Level &L, const fsi_patches &P, MG &mg, hipStream_t st) {
+static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J, MG &mg,
+                               hipStream_t st) {
   L.npatch = P.npatch;
   const int np = P.npatch;
   L.h_ptr.assign(P.ptr, P.ptr + np + 1);
@@ -286,6 +287,21 @@ static void build_patch_layout(Level &L, const fsi_patches &P, MG &mg, hipStream
   L.boff_total = boff[np];
   L.woff_total = woff[np];
   L.h_boff = boff;
+  // extraction map: one slot per CSR entry of every block row
+  if (L.boff_total >= ((int64_t)1 << 31))
+    throw Error(FSI_E_INVALID, "the blocks of one level exceed 2^31 entries");
+  std::vector<int64_t> slot_off(row_patch.size() + 1, 0);
+  for (size_t t = 0; t < row_patch.size(); ++t) {
+    const int g = P.dof[pdof_off[row_patch[t]] + row_local[t]];
+    slot_off[t + 1] = slot_off[t] + (J.rowptr[g + 1] - J.rowptr[g]);
+  }
+  L.ext_nslots = slot_off.back();
+  L.d_ext_slot_off = dupload(slot_off.data(), (int64_t)slot_off.size(), own, st);
+  L.d_ext_src = dalloc<int>(L.ext_nslots, own);
+  L.d_ext_dst = dalloc<int>(L.ext_nslots, own);
+  launch_extract_map(L.J.v64(), L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff, (int64_t)row_patch.size(),
+                     L.d_row_patch, L.d_row_local, L.d_ext_slot_off, L.d_ext_src, L.d_ext_dst, st);
+  hip_check(hipGetLastError(), "extraction map");
 }
 
 RasView ras_view(const Level &L) {
@@ -377,8 +393,7 @@ void refactor(MG &mg, hipStream_t st) {
     launch_fill_f64(mg.blk_scratch, mg.blk_total, 0.0, st);
     for (int l = 1; l < mg.nlevels; ++l) {
       Level &L = mg.lv[l];
-      launch_extract(L.J.v64(), L.npatch, L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff,
-                     mg.blk_scratch + L.blk_base, L.sum_m, L.d_row_patch, L.d_row_local, st);
+      launch_extract(L.J.val, L.ext_nslots, L.d_ext_src, L.d_ext_dst, mg.blk_scratch + L.blk_base, st);
     }
   }
   hip_check(hipStreamWaitEvent(mg.side_stream, mg.ev_fork, 0), "fork wait");
@@ -632,7 +647,7 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
       if (l > 0) {
         upload_csr(levels[l].P, L.P, mg->mixed, mg->owned, st);
         upload_csr(levels[l].R, L.R, mg->mixed, mg->owned, st);
-        build_patch_layout(L, levels[l].patches, *mg, st);
+        build_patch_layout(L, levels[l].patches, levels[l].J, *mg, st);
       }
       alloc_level_vectors(*mg, L);
     }
@@ -737,6 +752,13 @@ void release_setup_scratch(MG &mg) {
   drop(mg.dense_scratch);
   mg.blk_scratch = nullptr;
   mg.dense_scratch = nullptr;
+  for (Level &L : mg.lv) {
+    drop(L.d_ext_src);
+    drop(L.d_ext_dst);
+    drop(L.d_ext_slot_off);
+    L.d_ext_src = L.d_ext_dst = nullptr;
+    L.d_ext_slot_off = nullptr;
+  }
 }
 
 void destroy_mg(MG *mg) {
@@ -1094,8 +1116,8 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
           for (int l = 1; l < mg.nlevels; ++l) {
             Level &L = mg.lv[l];
             launch_fill_f64(mg.blk_scratch + L.blk_base, L.boff_total, 0.0, st);
-            launch_extract(L.J.v64(), L.npatch, L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff,
-                           mg.blk_scratch + L.blk_base, L.sum_m, L.d_row_patch, L.d_row_local, st);
+            launch_extract(L.J.val, L.ext_nslots, L.d_ext_src, L.d_ext_dst,
+                           mg.blk_scratch + L.blk_base, st);
           }
           launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.all_poff, mg.gj_perm,
                             mg.gj_used, mg.npatch_all, mg.mmax_all, mg.status, mg.gj_grid,
@@ -1383,8 +1405,7 @@ fsi_status fsi_mg_export_patches(struct fsi_mg *h, int32_t level, int64_t *ptr, 
       if (!mg->blk_scratch) throw Error(FSI_E_INVALID, "setup scratch released");
       double *B = mg->blk_scratch + L.blk_base;
       launch_fill_f64(B, L.boff_total, 0.0, st);
-      launch_extract(L.J.v64(), L.npatch, L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff, B, L.sum_m,
-                     L.d_row_patch, L.d_row_local, st);
+      launch_extract(L.J.val, L.ext_nslots, L.d_ext_src, L.d_ext_dst, B, st);
       hip_check(hipMemcpyAsync(blocks, B, sizeof(double) * L.boff_total, hipMemcpyDeviceToHost, st),
                 "D2H blocks");
       hip_check(hipStreamSynchronize(st), "export");

@@ -97,16 +97,21 @@ static int64_t footprint(const fsi_level *lv, int nl, const fsi_mg_opts &mo,
     }
     res += csr(lv[l].P) + csr(lv[l].R);
     const fsi_patches &P = lv[l].patches;
-    int64_t om = 0, m2 = 0;
+    int64_t om = 0, m2 = 0, slots = 0;
     for (int k = 0; k < P.npatch; ++k) {
       const int64_t m = P.ptr[k + 1] - P.ptr[k];
       int64_t o = 0;
-      for (int64_t p = P.ptr[k]; p < P.ptr[k + 1]; ++p) o += P.owned[p] ? 1 : 0;
+      for (int64_t p = P.ptr[k]; p < P.ptr[k + 1]; ++p) {
+        o += P.owned[p] ? 1 : 0;
+        slots += lv[l].J.rowptr[P.dof[p] + 1] - lv[l].J.rowptr[P.dof[p]];
+      }
       om += o * m;
       m2 += m * m;
     }
     res += om * wbytes + P.ptr[P.npatch] * 48;
-    transient += m2 * 8;                 // all levels' dense blocks share one setup scratch
+    // all levels' dense blocks share one setup scratch; the extraction map
+    // (two ints per slot, an offset per block row) is setup scratch too
+    transient += m2 * 8 + slots * 8 + P.ptr[P.npatch] * 8;
   }
   const int64_t nf = lv[nl - 1].J.nrows;
   res += nf * 8 * (2 * (int64_t)ko.restart + 4) + 2 * nf * 8;
