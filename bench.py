@@ -62,6 +62,23 @@ def measured_traffic():
     return int(b.group(1))
 
 
+def tuning_choices(db):
+    """The batched inversion's variant and grid as the autotuner left them in
+    its database (keys gj3:... and gjg:...)."""
+    names = {1: "NB16 x 256", 2: "NB16 x 512", 3: "NB32 x 512 (LDS panel)", 4: "wide panel from the block"}
+    out = {}
+    try:
+        for line in open(db):
+            k, v = line.split()
+            if k.startswith("gj3:"):
+                out.setdefault("gj_variant", {})[k] = names.get(int(v), v)
+            elif k.startswith("gjg:"):
+                out.setdefault("gj_grid", {})[k] = int(v)
+    except OSError:
+        pass
+    return out
+
+
 def vcycle_times(mg, n, stream, reps=50, warm=5):
     """Median V-cycle time over reps applications after warm ones, each cycle
     between its own events (warm: the operators may stay in the 256 MB
@@ -227,6 +244,7 @@ def gpu_leg(args):
         t = time.time()
         out["autotune_new_measurements"] = mg.autotune(tune_db)
         out["autotune_s"] = round(time.time() - t, 3)
+        out["autotune_choices"] = tuning_choices(tune_db)
         _, warm = timed_steps(mg, args.warmup, spec.rtol)
         total_ms, infos = timed_steps(mg, args.steps, spec.rtol)
         out["ms_per_step"] = total_ms / args.steps
@@ -371,30 +389,28 @@ def serve_leg(args):
 def cpu_leg(args):
     """The checker as it stands, on a bounded sample: the same step (block and
     coarse factorisation + FGMRES solve) of the same system."""
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import problem as oprob
     from oracle import solver as osolver
     from synth import config, fourier_coefficients
 
-    from threadpoolctl import threadpool_limits
-
     spec = config(WORKLOAD)
     h = oprob.build(spec, fourier_coefficients(spec.dim, spec.seed), factor=False)
-    t = time.time()
-    steps = 0
-    while steps < args.cpu_steps:
-        osolver.setup_factors(h.levels)
-        oprob.solve(h)
-        steps += 1
-    dt = time.time() - t
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    # the same step on one thread
-    with threadpool_limits(limits=1):
+
+    def timed(steps):
         t = time.time()
-        osolver.setup_factors(h.levels)
-        oprob.solve(h)
-        dt1 = time.time() - t
+        for _ in range(steps):
+            osolver.setup_factors(h.levels)
+            oprob.solve(h)
+        return time.time() - t
+
+    timed(1)                                   # untimed warm-up (first-touch, library set-up)
+    steps = args.cpu_steps
+    dt_all = timed(steps)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    with threadpool_limits(limits=1):          # the same steps on one thread
+        dt1 = timed(steps)
     # host memory bandwidth: a STREAM-like triad a = b + 3 c over 128 MB
     # arrays, in two numpy passes (c read, a written; a and b read, a written)
     b_, c_ = np.ones(16 << 20), np.full(16 << 20, 2.0)
@@ -414,10 +430,14 @@ def cpu_leg(args):
                 break
     except OSError:
         pass
-    return {"value": round(steps / dt, 4), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{steps} full steps (block LU + coarse LU + FGMRES to 1e-10) of {WORKLOAD}, {dt:.1f} s",
-            "host_cpu": host, "host_logical_cpus": os.cpu_count(),
-            "one_thread_value": round(1.0 / dt1, 4), "host_triad_gb_s": round(triad_gbs, 1)}
+    # the faster of the two runs is the baseline; both are reported
+    best_dt, best_cores = (dt_all, int(threads)) if dt_all <= dt1 else (dt1, 1)
+    return {"value": round(steps / best_dt, 4), "unit": "solves/s", "cores": best_cores, "kind": "oracle",
+            "sample": f"{steps} full steps (block LU + coarse LU + FGMRES to 1e-10) of {WORKLOAD} after one "
+                      f"untimed step, {best_dt:.1f} s",
+            "all_threads_value": round(steps / dt_all, 4), "all_threads": int(threads),
+            "one_thread_value": round(steps / dt1, 4),
+            "host_cpu": host, "host_logical_cpus": os.cpu_count(), "host_triad_gb_s": round(triad_gbs, 1)}
 
 
 def main():
@@ -464,7 +484,8 @@ def main():
         "vcycle_ms_fp64_cold": round(g["vcycle_ms_fp64_cold"], 4),
         "refactor_ms_fp64": round(g["refactor_ms_fp64"], 3), "solve_ms_fp64": round(g["solve_ms_fp64"], 3),
         "dof_per_s": round(value * g["n"], 1),
-        "autotune": {"new_measurements": g["autotune_new_measurements"], "seconds": g["autotune_s"]},
+        "autotune": {"new_measurements": g["autotune_new_measurements"], "seconds": g["autotune_s"],
+                     "choices": g["autotune_choices"]},
         "setup_with_upload_ms": round(g["setup_with_upload_ms"], 1),
     }
     if "mixed" in g:
