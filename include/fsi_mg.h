@@ -116,7 +116,10 @@ const char *fsi_last_error(void);
 
 /* Uploads the hierarchy, extracts B_k = J_l[I_k, I_k] for every patch, inverts
  * it (Gauss-Jordan, partial pivoting; the paper's local direct solve) keeping
- * the rows selected by R^0_k, and inverts the coarsest operator.  Errors:
+ * the rows selected by R^0_k, and inverts the coarsest operator (its dofs
+ * whose row and column hold only the diagonal, the eliminated Dirichlet dofs,
+ * by a reciprocal, the others by Gauss-Jordan; the sparsity pattern decides,
+ * so a refactor keeps the split).  Errors:
  * FSI_E_INVALID (malformed CSR/patch lists, dimension mismatch, owned sets
  * not a partition of the covered dofs), FSI_E_SINGULAR (message names level
  * and patch), FSI_E_OOM, FSI_E_DEVICE. */
