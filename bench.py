@@ -62,6 +62,25 @@ def measured_traffic():
     return int(b.group(1))
 
 
+_TUNING_DB = None
+
+
+def tuning_db():
+    """The autotuner's database: FSI_TUNING_DB when set (to reuse the choices
+    of an earlier run, e.g. one made without a profiler), else a fresh file
+    for this run, so that no earlier run's timings decide."""
+    global _TUNING_DB
+    if os.environ.get("FSI_TUNING_DB"):
+        return os.environ["FSI_TUNING_DB"]
+    if _TUNING_DB is None:
+        import atexit
+        import tempfile
+        fd, _TUNING_DB = tempfile.mkstemp(prefix="fsi_tuning_", suffix=".db")
+        os.close(fd)
+        atexit.register(lambda: os.path.exists(_TUNING_DB) and os.remove(_TUNING_DB))
+    return _TUNING_DB
+
+
 def tuning_choices(db):
     """The batched inversion's variant and grid as the autotuner left them in
     its database (keys gj3:... and gjg:...)."""
@@ -133,7 +152,7 @@ def three_d_leg(args):
     p = Problem(spec, fourier_coefficients(spec.dim, spec.seed))
     stream = torch.cuda.Stream()
     res = {"unknowns": p.n, "rtol": spec.rtol}
-    tune_db = os.environ.get("FSI_TUNING_DB", os.path.join("/tmp", "fsi_tuning.db"))
+    tune_db = tuning_db()
     with torch.cuda.stream(stream):
         b = torch.as_tensor(p.b).to("cuda")
         x = torch.zeros_like(b)
@@ -240,7 +259,7 @@ def gpu_leg(args):
         t = time.time()
         mg = MG(p, precision="fp64", use_graph=True)
         setup_upload_ms = (time.time() - t) * 1e3
-        tune_db = os.environ.get("FSI_TUNING_DB", os.path.join("/tmp", "fsi_tuning.db"))
+        tune_db = tuning_db()
         t = time.time()
         out["autotune_new_measurements"] = mg.autotune(tune_db)
         out["autotune_s"] = round(time.time() - t, 3)
