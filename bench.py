@@ -84,7 +84,8 @@ def tuning_db():
 def tuning_choices(db):
     """The batched inversion's variant and grid as the autotuner left them in
     its database (keys gj3:... and gjg:...)."""
-    names = {1: "NB16 x 256", 2: "NB16 x 512", 3: "NB32 x 512 (LDS panel)", 4: "wide panel from the block"}
+    names = {1: "NB16 x 256", 2: "NB16 x 512", 3: "NB32 x 512 (LDS panel)", 4: "wide panel from the block",
+             5: "NB24 x 512 (LDS panel)"}
     out = {}
     try:
         for line in open(db):

@@ -278,7 +278,7 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
   constexpr int PS = NB + 1, KC = NB / 4;
   extern __shared__ double PC[];
   __shared__ PivotLds<NB, NT / 64> sh;
-  __shared__ int s_used[R * NT];
+  __shared__ short s_used[R * NT];   // step numbers < 1024, or -1
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int jl = lane & 15, kq = lane >> 4;
   const int *list = sched + gridDim.x + 1;
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
             if (c < w) A[i * m + p0 + c] = v[q][c];
             if constexpr (!GPC) PC[i * PS + c] = v[q][c];
           }
-          if (stp[q] >= p0) s_used[i] = stp[q];
+          if (stp[q] >= p0) s_used[i] = (short)stp[q];
         }
       }
       __threadfence_block();
@@ -415,6 +415,13 @@ bool gj_variant_ok(int variant, int mmax) {
       return mmax <= 512 && gj_batched_lds(mmax, 32) <= 140 * 1024;
     case kGjWideG:    // panel read from the block itself: no LDS of m
       return mmax <= 1024;
+    case kGj24x512: {  // two rows per thread, the LDS panel next to the static LDS
+      hipFuncAttributes a;
+      if (mmax > 1024 ||
+          hipFuncGetAttributes(&a, (const void *)k_gj_batched<24, 2, 512, true, false>) != hipSuccess)
+        return false;
+      return a.sharedSizeBytes + gj_batched_lds(mmax, 24) <= 160 * 1024;
+    }
     default:
       return false;
   }
@@ -490,6 +497,9 @@ void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const
   else if (variant == kGjWideG)
     launch_gj_nbr<24, 2, 512, true, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax,
                                           status, st);
+  else if (variant == kGj24x512)
+    launch_gj_nbr<24, 2, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status,
+                                    st);
   else if (variant == kGj16x512 && small)
     launch_gj_nbr<16, 1, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st);
   else if (variant == kGj16x512)

@@ -44,9 +44,11 @@ void launch_extract(const double *val, int64_t nslots, const int *src, const int
 // kernel variants (panel width x threads), chosen by the autotuner: NB 16
 // on 256 or 512 threads, NB 32 on 512 with the panel in LDS (m <= 512), and
 // a wide panel read back from the block itself (NB 32 for m <= 512, 24 for
-// m <= 1024, 512 threads).  An unsupported or zero variant falls back to
-// NB 32 where it fits, else NB 16 on 256 threads
-enum GjVariant { kGjAuto = 0, kGj16x256 = 1, kGj16x512 = 2, kGj32x512 = 3, kGjWideG = 4 };
+// m <= 1024, 512 threads), and NB 24 on 512 threads with the panel in LDS
+// (where m 25 doubles fit beside the static LDS, m <= ~790).  An
+// unsupported or zero variant falls back to NB 32 where it fits, else NB 16
+// on 256 threads
+enum GjVariant { kGjAuto = 0, kGj16x256 = 1, kGj16x512 = 2, kGj32x512 = 3, kGjWideG = 4, kGj24x512 = 5 };
 bool gj_variant_ok(int variant, int mmax);
 // workgroups of the batched inversion for npatch blocks (the fewest rounds
 // over the compute units), and the host-built schedule: grid + 1 offsets

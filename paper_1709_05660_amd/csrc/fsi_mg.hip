@@ -1110,7 +1110,7 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
     } else {
       int best = kGjAuto;
       float best_ms = 1e30f;
-      for (int var : {kGj16x256, kGj16x512, kGj32x512, kGjWideG}) {
+      for (int var : {kGj16x256, kGj16x512, kGj32x512, kGjWideG, kGj24x512}) {
         if (!gj_variant_ok(var, mg.mmax_all)) continue;
         const float ms = time_events(st, [&] {
           for (int l = 1; l < mg.nlevels; ++l) {

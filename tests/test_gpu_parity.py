@@ -341,7 +341,7 @@ def test_every_block_inversion_variant(name, tmp_path):
     r = rng.standard_normal(p.n)
     ref = osolver.vcycle(oh.levels, len(oh.levels) - 1, r, s.nu_pre, s.nu_post, s.omega)
     mmax = max(int(np.diff(p.patches(l)[0]).max()) for l in range(1, p.nlevels))
-    variants = [1, 2, 4] + ([3] if mmax <= 512 else [])
+    variants = [1, 2, 4, 5] + ([3] if mmax <= 512 else [])
     zs = {}
     for v in variants:
         _say(name, "variant", v, "mmax", mmax)
@@ -352,3 +352,5 @@ def test_every_block_inversion_variant(name, tmp_path):
     assert np.array_equal(zs[1], zs[2])
     if 3 in zs:                  # NB 32 with the panel in LDS or read from the block
         assert np.array_equal(zs[3], zs[4])
+    else:                        # NB 24 likewise (blocks above 512 dofs)
+        assert np.array_equal(zs[4], zs[5])
