@@ -482,7 +482,9 @@ void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const
                        const int *sched, hipStream_t st, int variant) {
   if (npatch == 0) return;
   if (!gj_variant_ok(variant, mmax))
-    variant = gj_variant_ok(kGj32x512, mmax) ? kGj32x512 : kGj16x256;
+    variant = gj_variant_ok(kGj32x512, mmax)   ? kGj32x512
+              : gj_variant_ok(kGj24x512, mmax) ? kGj24x512
+                                               : kGj16x256;
   const bool small = mmax <= 512;
   // NB 16 on 256 threads: one wave per SIMD, the per-step work common to a
   // wave shared by more rows; on 512 threads: twice the waves, so twice the

@@ -46,8 +46,8 @@ void launch_extract(const double *val, int64_t nslots, const int *src, const int
 // a wide panel read back from the block itself (NB 32 for m <= 512, 24 for
 // m <= 1024, 512 threads), and NB 24 on 512 threads with the panel in LDS
 // (where m 25 doubles fit beside the static LDS, m <= ~790).  An
-// unsupported or zero variant falls back to NB 32 where it fits, else NB 16
-// on 256 threads
+// unsupported or zero variant falls back to the first that fits of NB 32,
+// NB 24 (both with the LDS panel) and NB 16 on 256 threads
 enum GjVariant { kGjAuto = 0, kGj16x256 = 1, kGj16x512 = 2, kGj32x512 = 3, kGjWideG = 4, kGj24x512 = 5 };
 bool gj_variant_ok(int variant, int mmax);
 // workgroups of the batched inversion for npatch blocks (the fewest rounds
