@@ -180,7 +180,8 @@ fsi_status fsi_mg_destroy(struct fsi_mg *mg);
 /* Measurement helper, not part of the method: a plain streaming read of the
  * n doubles at x_dev (device memory, 16-byte aligned, n even and >= 2) on the
  * given stream, 16-byte loads, fsi_stream_read_blocks() workgroups of 256
- * threads; out_dev (device, fsi_stream_read_blocks() doubles, owned by the
+ * threads each reading one contiguous chunk (the fastest read pattern
+ * measured on this device); out_dev (device, fsi_stream_read_blocks() doubles, owned by the
  * caller) receives one partial sum per workgroup.  Timing it gives the read
  * rate the HBM-bound kernels are compared with.  FSI_E_INVALID on a bad size
  * or alignment; launch errors as FSI_E_DEVICE. */

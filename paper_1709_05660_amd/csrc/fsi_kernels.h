@@ -123,7 +123,7 @@ void launch_dense_gemv(const double *W, int n, const double *x, double *y, hipSt
 
 // ---- measurement: plain streaming read of n doubles (x 16-byte aligned, n
 // even); out receives kStreamReadBlocks partial sums
-constexpr int kStreamReadBlocks = 4096;
+constexpr int kStreamReadBlocks = 1024;
 void launch_stream_read(const double *x, int64_t n, double *out, hipStream_t st);
 
 // ---- vectors

@@ -813,20 +813,24 @@ void launch_start_cycle(int n, const double *r, const double *nrm2, double *v, d
 // Streaming read of n doubles with 16-byte loads, eight in flight per lane
 // over a grid-stride loop; block b writes its partial sum to out[b].  It is
 // the device's plain read rate that the HBM-bound kernels are compared with.
+// each workgroup streams its own contiguous chunk (a grid-stride pattern over
+// the whole buffer reads about 10 % slower on this device)
 __global__ __launch_bounds__(256) void k_stream_read(const double2 *__restrict__ x, int64_t n2,
                                                      double *__restrict__ out) {
   __shared__ double red[4];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t chunk = (n2 + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * chunk;
+  const int64_t b1 = b0 + chunk < n2 ? b0 + chunk : n2;
+  int64_t i = b0 + threadIdx.x;
   double s = 0.0;
-  for (; i + 7 * stride < n2; i += 8 * stride) {
+  for (; i + 7 * 256 < b1; i += 8 * 256) {
     double2 v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = x[i + u * stride];
+    for (int u = 0; u < 8; ++u) v[u] = x[i + u * 256];
 #pragma unroll
     for (int u = 0; u < 8; ++u) s += v[u].x + v[u].y;
   }
-  for (; i < n2; i += stride) s += x[i].x + x[i].y;
+  for (; i < b1; i += 256) s += x[i].x + x[i].y;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
