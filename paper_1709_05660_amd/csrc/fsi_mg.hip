@@ -1147,7 +1147,7 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
       if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
       std::vector<int> cands;
-      for (int g : {gj_batched_grid(mg.npatch_all), ncu - 64, ncu - 40}) {
+      for (int g : {gj_batched_grid(mg.npatch_all), ncu - 64, ncu - 48, ncu - 40}) {
         g = std::max(1, std::min(g, mg.npatch_all));
         if (std::find(cands.begin(), cands.end(), g) == cands.end()) cands.push_back(g);
       }
