@@ -416,11 +416,15 @@ bool gj_variant_ok(int variant, int mmax) {
     case kGjWideG:    // panel read from the block itself: no LDS of m
       return mmax <= 1024;
     case kGj24x512: {  // two rows per thread, the LDS panel next to the static LDS
-      hipFuncAttributes a;
-      if (mmax > 1024 ||
-          hipFuncGetAttributes(&a, (const void *)k_gj_batched<24, 2, 512, true, false>) != hipSuccess)
-        return false;
-      return a.sharedSizeBytes + gj_batched_lds(mmax, 24) <= 160 * 1024;
+      // the kernel's static LDS, queried once (-1: the query failed)
+      static const int64_t static_lds = [] {
+        hipFuncAttributes a;
+        return hipFuncGetAttributes(&a, (const void *)k_gj_batched<24, 2, 512, true, false>) == hipSuccess
+                   ? (int64_t)a.sharedSizeBytes
+                   : (int64_t)-1;
+      }();
+      return mmax <= 1024 && static_lds >= 0 &&
+             static_lds + (int64_t)gj_batched_lds(mmax, 24) <= 160 * 1024;
     }
     default:
       return false;
