@@ -5,8 +5,9 @@ CPU-baseline leg of the benchmark may import it; the GPU solver path never
 calls it and shares no code with it.
 
 Contents (each function cites the passage of the paper it follows):
-  fem      -- structured Q2/Q1 mesh, dof numbering, steady monolithic ALE
-              residual and its exact Jacobian (complex-step differentiation)
+  fem      -- structured Q2-P1disc mesh (Q1 pressure as an option), dof
+              numbering, steady monolithic ALE residual and its exact
+              Jacobian (complex-step differentiation)
   transfer -- natural-injection prolongation, equation-aware restriction,
               Galerkin coarse operators
   patches  -- Schwarz patches split along the fluid/solid interface

@@ -1,4 +1,4 @@
-"""Checker: structured Q2/Q1 monolithic ALE discretisation (FP64, CPU).
+"""Checker: structured Q2-P1disc monolithic ALE discretisation (FP64, CPU).
 
 Test infrastructure only (see the package docstring).
 
@@ -6,10 +6,13 @@ Follows the paper's monolithic weak form (section "Weak FSI problem":
 equations weakmom, cntsld, cntfld, kinsld, kinfld) in the steady case, on a
 structured box mesh, with the readings used throughout this repository:
 
-* velocity/displacement in Q2 (section "Discretization of the operator
-  formulation"); pressure in Q1, continuous inside each material and
-  duplicated at interface vertices (the paper's P1disc pressure is also
-  discontinuous across the interface; the workload asks for Q2/Q1);
+* velocity/displacement in Q2 and pressure in P1disc, the paper's pair
+  (section "Discretization of the operator formulation"): dim+1 pressure
+  dofs per element (its value at the element centre and its slopes), so the
+  pressure is discontinuous between elements and across the interface.  A
+  continuous Q1 pressure per material (duplicated at interface vertices) is
+  kept as an option (spec.pressure = "q1"); the box-patch Richardson-Schwarz
+  smoother diverges with it (a slow CPU test shows this);
 * rows in the shuffled layout (equation jac_blocks_shuf): the displacement
   slot of a node carries the mesh-motion equation (fluid-only nodes), the
   solid momentum (solid-only nodes) or the interface momentum (interface
