@@ -22,6 +22,25 @@ def _dptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _vec(t, n, name):
+    """Device pointer of an FP64 vector of n entries, after checking that the
+    tensor is what the library will read or write through it (the library
+    sees only the pointer: a short, strided, host or FP32 tensor would be
+    accessed out of bounds on the device)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name}: dtype must be float64, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a device (cuda) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name}: expected {n} entries, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
 def stream_read_gbps(nbytes, reps=20):
     """Best rate (GB/s) of the library's plain streaming-read kernel over
     nbytes of device memory, timed with events on the current stream: the
@@ -163,31 +182,40 @@ class MG:
     def vcycle(self, r, z=None):
         import torch
         if z is None:
-            z = torch.empty_like(r)
-        L.check(L.lib().fsi_mg_vcycle(self.h, _dptr(r), _dptr(z), _stream()), "vcycle")
+            z = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        L.check(L.lib().fsi_mg_vcycle(self.h, _vec(r, self.n, "r"), _vec(z, self.n, "z"), _stream()),
+                "vcycle")
         return z
 
     def apply(self, level, op, x, r=None, y=None):
+        """One operator of a level (fsi_mg_apply): op 0 J x, 1 r - J x, 2 P x,
+        3 R x, 4 one Schwarz application, 5 the coarsest direct solve."""
         import torch
+        if not 0 <= level < self.nlevels:
+            raise ValueError(f"level {level} out of range")
         n = self.level_info(level)["n"]
+        nc = self.level_info(level - 1)["n"] if level > 0 else 0
+        nin, nout = {2: (nc, n), 3: (n, nc)}.get(op, (n, n))
         if y is None:
-            y = torch.empty(n if op != 3 else self.level_info(level - 1)["n"], dtype=torch.float64,
-                            device=x.device)
-        L.check(L.lib().fsi_mg_apply(self.h, level, op, _dptr(x), _dptr(r) if r is not None else None,
-                                     _dptr(y), _stream()), "apply")
+            y = torch.empty(nout, dtype=torch.float64, device="cuda")
+        rp = _vec(r, n, "r") if r is not None else None
+        L.check(L.lib().fsi_mg_apply(self.h, level, op, _vec(x, nin, "x"), rp, _vec(y, nout, "y"),
+                                     _stream()), "apply")
         return y
 
     def fgmres(self, b, x=None, restart=30, rtol=1e-10, maxit=1000, fixed_iters=0, x0=False):
         import torch
         if x is None:
-            x = torch.zeros_like(b)
+            if x0:
+                raise ValueError("x0=True needs the starting vector x")
+            x = torch.zeros(self.n, dtype=torch.float64, device="cuda")
         hist = np.zeros(maxit + 2)
         ko = L.KrylovOpts()
         ko.restart, ko.rtol, ko.maxit, ko.fixed_iters = restart, rtol, maxit, fixed_iters
         ko.history = L._ptr(hist, C.c_double)
         info = L.SolveInfo()
-        st = L.lib().fsi_fgmres_solve(self.h, _dptr(b), _dptr(x), 1 if x0 else 0, C.byref(ko),
-                                      C.byref(info), _stream())
+        st = L.lib().fsi_fgmres_solve(self.h, _vec(b, self.n, "b"), _vec(x, self.n, "x"), 1 if x0 else 0,
+                                      C.byref(ko), C.byref(info), _stream())
         L.check(st, "fgmres")
         d = info.as_dict()
         d["status"] = st
@@ -252,10 +280,13 @@ class Server:
         self.h = h
         self.sizes = {}
 
-    def submit(self, problem, b=None, precision="bf16", rtol=1e-8, restart=30, maxit=1000, **mg):
+    def submit(self, problem, b=None, precision="bf16", rtol=1e-8, restart=30, maxit=1000, fixed_iters=0,
+               **mg):
         b = problem.b if b is None else np.ascontiguousarray(b, dtype=np.float64)
+        if b.shape != (problem.n,):
+            raise ValueError(f"b: expected {problem.n} entries, got {b.shape}")
         mo = mg_opts(precision=precision, **mg)
-        ko = L.KrylovOpts(restart, rtol, maxit, 0, None)
+        ko = L.KrylovOpts(restart, rtol, maxit, fixed_iters, None)
         t = C.c_uint64()
         L.check(L.lib().fsi_serve_submit(self.h, problem.levels, problem.nlevels,
                                          b.ctypes.data_as(C.c_void_p), C.byref(mo), C.byref(ko),

@@ -45,7 +45,10 @@ def _csr(p, level, which="J"):
 
 @pytest.mark.parametrize("name,kw", [("c0_2d_16x4", {}),
                                      ("c3_3d_32x8x8", dict(nx=16, ny=4, nz=4, levels=2, patch=2)),
-                                     ("c1_2d_128x32", dict(nx=32, ny=8, levels=3, mu_s=3.0e4, seed=7))])
+                                     ("c1_2d_128x32", dict(nx=32, ny=8, levels=3, mu_s=3.0e4, seed=7)),
+                                     # the full-size workloads (the 3D checker assembly takes ~2 min)
+                                     pytest.param("c1_2d_128x32", {}, marks=pytest.mark.slow),
+                                     pytest.param("c3_3d_32x8x8", {}, marks=pytest.mark.slow)])
 def test_builder_matches_checker(name, kw):
     """The native builder and the checker assemble the same hierarchy: P, R and
     the patch lists bit for bit, J and b to rounding (sums in another order)."""
@@ -199,3 +202,21 @@ def test_coarsest_size_limit_is_reported_on_the_host():
     J.val = v.ctypes.data_as(C.POINTER(C.c_double))
     st, msg = _setup_status(lv, 1)
     assert st == -1 and "coarsest" in msg and "6144" in msg
+
+
+def test_binding_rejects_vectors_the_library_would_overrun():
+    """The binding checks dtype, device, contiguity and length before passing
+    a tensor's pointer to the library (which sees only the pointer)."""
+    import torch
+
+    from paper_1709_05660_amd.solver import _vec
+    for t, why in [(torch.zeros(10, dtype=torch.float32), "dtype"),
+                   (torch.zeros(10, dtype=torch.float64), "device"),
+                   (np.zeros(10), "Tensor")]:
+        with pytest.raises((ValueError, TypeError), match=why):
+            _vec(t, 10, "x")
+    if torch.cuda.is_available():       # the remaining checks need a device tensor
+        with pytest.raises(ValueError, match="contiguous"):
+            _vec(torch.zeros(20, dtype=torch.float64, device="cuda")[::2], 10, "x")
+        with pytest.raises(ValueError, match="entries"):
+            _vec(torch.zeros(9, dtype=torch.float64, device="cuda"), 10, "x")
