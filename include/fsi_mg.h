@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define FSI_ABI_VERSION 1
+#define FSI_ABI_VERSION 2
 
 typedef int32_t fsi_status;
 enum {
@@ -56,6 +56,19 @@ enum {
  * (B^{-1} = diag(rs) W diag(cs)) and applied with FP32 accumulation;
  * MIXED_FP32: owned rows stored in FP32. */
 enum { FSI_PREC_FP64 = 0, FSI_PREC_MIXED_BF16 = 1, FSI_PREC_MIXED_FP16 = 2, FSI_PREC_MIXED_FP32 = 3 };
+
+/* Orthogonalisation of the Krylov basis: classical Gram-Schmidt applied
+ * twice (the default) or once (the paper's PETSc setting, section "Details
+ * on the iterative solver"). */
+enum { FSI_ORTH_CGS2 = 0, FSI_ORTH_CGS = 1 };
+
+/* Side of the preconditioner.  RIGHT: flexible GMRES (Saad) on J M^{-1},
+ * the basis of preconditioned vectors z_j = M^{-1} v_j kept, stop when the
+ * true residual |b - J x| <= rtol |b|.  LEFT: GMRES on M^{-1} J with the
+ * paper's stopping rule |M^{-1}(b - J x_j)| < rtol |M^{-1}(b - J x_0)| on the
+ * left-preconditioned residual (section "Details on the iterative solver";
+ * the paper runs restart 10, FSI_ORTH_CGS, rtol 1e-4). */
+enum { FSI_SIDE_RIGHT = 0, FSI_SIDE_LEFT = 1 };
 
 typedef struct {
   int32_t nrows, ncols;
@@ -80,6 +93,10 @@ typedef struct {
   fsi_csr P;               /* n_l x n_{l-1} prolongation; ignored on level 0 */
   fsi_csr R;               /* n_{l-1} x n_l restriction; ignored on level 0 */
   fsi_patches patches;     /* ignored on level 0 (direct solve) */
+  const uint8_t *dirichlet; /* optional (NULL: unchecked): n_l flags, 1 at a Dirichlet dof.
+                              Checked at setup: a flagged row of J is the identity row
+                              (its only entry is the diagonal, 1.0) and no patch holds
+                              a flagged dof (the Newton correction is zero there) */
 } fsi_level;
 
 typedef struct {
@@ -92,20 +109,33 @@ typedef struct {
                               Richardson and FGMRES iterations correct the rounding of
                               the stored inverse rows); other values are rejected */
   int32_t use_graph;       /* replay the V-cycle and each Arnoldi step from hipGraphs */
+  const char *tuning_db;   /* NULL, or a text database path: setup then runs the
+                              autotuner (fsi_mg_autotune) with it */
 } fsi_mg_opts;
 
 typedef struct {
-  int32_t restart;         /* FGMRES(m) restart length */
-  double rtol;             /* stop when |b - J x| <= rtol |b| */
+  int32_t restart;         /* GMRES(m) restart length, 1..60 */
+  double rtol;             /* relative tolerance (see FSI_SIDE_*) */
   int32_t maxit;           /* total preconditioner applications */
+  int32_t orth;            /* FSI_ORTH_* */
+  int32_t x0_nonzero;      /* 1: x_dev holds the initial guess; 0: x0 = 0 */
+  double *history;         /* optional host buffer of maxit+1 residual norms: the initial
+                              one, then each step's estimate (RIGHT: of |b - J x|,
+                              LEFT: of |M^{-1}(b - J x)|) */
   int32_t fixed_iters;     /* > 0: run exactly this many iterations, ignore rtol */
-  double *history;         /* optional host buffer of maxit+1 residual estimates */
+  int32_t side;            /* FSI_SIDE_* */
 } fsi_krylov_opts;
 
 typedef struct {
   int32_t iters, restarts, converged;
-  double true_relres, est_relres;
+  double true_relres;      /* |b - J x| / |b| of the returned x */
+  double est_relres;       /* last monitored norm over the stopping rule's reference
+                              (RIGHT: |b|, LEFT: |M^{-1}(b - J x_0)|) */
   double setup_ms, solve_ms;
+  double rho;              /* average convergence rate (r_N / r_0)^(1/N) of the monitored
+                              residual over the N iterations (defined with the tables of
+                              section "Condition number estimates": the geometric mean
+                              of the ratios of consecutive residuals); 0 when N = 0 */
 } fsi_solve_info;
 
 struct fsi_mg;
@@ -114,25 +144,44 @@ int32_t fsi_abi_version(void);
 const char *fsi_status_string(fsi_status s);
 const char *fsi_last_error(void);
 
-/* Uploads the hierarchy, extracts B_k = J_l[I_k, I_k] for every patch, inverts
+/* Sections "Geometric Multigrid preconditioner" (levels, Galerkin coarse
+ * operators, transfers) and "Richardson-Schwarz smoother" (blocks B_k =
+ * R^delta_k J R^delta_k^T solved exactly, restricted write-back R^0_k).
+ * Uploads the hierarchy, extracts B_k = J_l[I_k, I_k] for every patch, inverts
  * it (Gauss-Jordan, partial pivoting; the paper's local direct solve) keeping
  * the rows selected by R^0_k, and inverts the coarsest operator (its dofs
  * whose row and column hold only the diagonal, the eliminated Dirichlet dofs,
  * by a reciprocal, the others by Gauss-Jordan; the sparsity pattern decides,
- * so a refactor keeps the split).  Errors:
- * FSI_E_INVALID (malformed CSR/patch lists, dimension mismatch, owned sets
- * not a partition of the covered dofs), FSI_E_SINGULAR (message names level
- * and patch), FSI_E_OOM, FSI_E_DEVICE. */
+ * so a refactor keeps the split).  levels: host array of nlevels views,
+ * coarsest first, borrowed for the call; *out receives the handle (NULL on
+ * error).  Errors: FSI_E_INVALID (malformed CSR/patch lists, dimension
+ * mismatch, owned sets not a partition of the covered dofs, a Dirichlet flag
+ * on a non-identity row or inside a patch), FSI_E_SINGULAR (message names
+ * level and patch), FSI_E_OOM, FSI_E_DEVICE. */
 fsi_status fsi_mg_setup(const fsi_level *levels, int32_t nlevels, const fsi_mg_opts *opts,
                         void *hip_stream, struct fsi_mg **out);
 
-/* z = M^{-1} r: one V-cycle from the finest level, FP64 in and out (n_finest doubles each). */
+/* Section "Geometric Multigrid preconditioner" (V-cycle, direct solve on the
+ * coarsest level) with the smoother of section "Richardson-Schwarz
+ * smoother": nu_pre sweeps e <- e + omega B^{-1}(r - J e) from e = 0, the
+ * coarse correction e <- e + P V(R (r - J e)), nu_post sweeps.
+ * z = M^{-1} r: r_dev, z_dev distinct or equal device arrays of n_finest
+ * doubles, stream-ordered on hip_stream.  Errors: FSI_E_INVALID (null
+ * argument), FSI_E_DEVICE (launch failure). */
 fsi_status fsi_mg_vcycle(struct fsi_mg *mg, const double *r_dev, double *z_dev, void *hip_stream);
 
-/* FGMRES(restart) with CGS2 on J_finest x = b; x_dev holds x0 on entry when
- * x0_nonzero, else it is overwritten.  Returns FSI_OK, FSI_NOT_CONVERGED or
- * an error; info (may be NULL) is filled in every case it can be. */
-fsi_status fsi_fgmres_solve(struct fsi_mg *mg, const double *b_dev, double *x_dev, int32_t x0_nonzero,
+/* Section "Details on the iterative solver" (GMRES preconditioned by one
+ * V-cycle per step) for J_finest x = b, the linear system of a Newton step
+ * (section "Structure of the Jacobian").  kopts->side picks flexible GMRES
+ * with right preconditioning (default) or the paper's left-preconditioned
+ * GMRES; kopts->orth the Gram-Schmidt variant.  b_dev, x_dev: device arrays
+ * of n_finest doubles; x_dev holds x0 on entry when kopts->x0_nonzero, else
+ * it is overwritten.  The call returns when the solve is over (the host
+ * waits for each step's few result bytes).  Returns FSI_OK,
+ * FSI_NOT_CONVERGED (maxit reached; x holds the last iterate) or an error:
+ * FSI_E_INVALID (options), FSI_E_NONFINITE (NaN/Inf in b or a residual),
+ * FSI_E_DEVICE.  info (may be NULL) is filled whenever the solve ran. */
+fsi_status fsi_fgmres_solve(struct fsi_mg *mg, const double *b_dev, double *x_dev,
                             const fsi_krylov_opts *kopts, fsi_solve_info *info, void *hip_stream);
 
 /* Debug/parity: applies one operator of level `level` to x_dev (device, FP64):
@@ -149,9 +198,11 @@ fsi_status fsi_mg_apply(struct fsi_mg *mg, int32_t level, int32_t op, const doub
 fsi_status fsi_mg_export_patches(struct fsi_mg *mg, int32_t level, int64_t *ptr, int32_t *dof,
                                  uint8_t *owned, double *blocks);
 
-/* Recomputes the block inverses and the coarsest inverse from the operator
- * values resident on the device (a new Newton Jacobian with the same
- * sparsity, written through fsi_mg_jvalues).  Same errors as setup. */
+/* Section "Monolithic Newton-Krylov solver with Multigrid-Richardson-Schwarz
+ * preconditioner": every Newton step brings a new Jacobian with the same
+ * sparsity.  Recomputes the block inverses and the coarsest inverse from the
+ * operator values resident on the device (written through fsi_mg_jvalues),
+ * on hip_stream; returns when done.  Same errors as setup. */
 fsi_status fsi_mg_refactor(struct fsi_mg *mg, void *hip_stream);
 
 /* Device pointer to the FP64 values of J on `level` (the input CSR order),
@@ -206,7 +257,12 @@ typedef struct {
 struct fsi_server;
 
 fsi_status fsi_server_create(const fsi_server_opts *o, struct fsi_server **out);
-/* Copies the request (levels, b) and queues it; returns a ticket. */
+/* Section "Details on the iterative solver" applied to independent systems
+ * (the paper solves one system at a time; serving them together is this
+ * library's).  Copies the request (levels, b; mo->tuning_db is ignored) and
+ * queues it; returns a ticket.  Errors at submit: FSI_E_INVALID (malformed
+ * hierarchy or options; ko->x0_nonzero must be 0), FSI_E_CAPACITY (the
+ * request's estimated footprint exceeds the budget). */
 fsi_status fsi_serve_submit(struct fsi_server *s, const fsi_level *levels, int32_t nlevels,
                             const double *b_host, const fsi_mg_opts *mo, const fsi_krylov_opts *ko,
                             uint64_t *ticket);
@@ -215,8 +271,12 @@ fsi_status fsi_serve_submit(struct fsi_server *s, const fsi_level *levels, int32
  * solve; returns the solve's status.  A finished ticket is released. */
 fsi_status fsi_serve_poll(struct fsi_server *s, uint64_t ticket, double *x_host, fsi_solve_info *info);
 /* Server counters: [0] submitted, [1] finished, [2] active, [3] queued,
- * [4] bytes in use, [5] peak bytes, [6] ticks, [7] max co-resident. */
-fsi_status fsi_server_stats(struct fsi_server *s, int64_t out[8]);
+ * [4] admitted footprint bytes, [5] peak admitted footprint bytes, [6] ticks,
+ * [7] max co-resident, [8] device bytes the server's pool allocated (kept
+ * until fsi_server_destroy), [9] peak device bytes handed out by the pool.
+ * The admitted footprint is an estimate that includes the pool's rounding
+ * slack; [9] is what the systems actually held. */
+fsi_status fsi_server_stats(struct fsi_server *s, int64_t out[10]);
 fsi_status fsi_server_destroy(struct fsi_server *s);
 
 #ifdef __cplusplus

@@ -73,3 +73,14 @@ def solve(h, **kw):
     kw.setdefault("rtol", s.rtol)
     kw.setdefault("maxit", s.maxit)
     return solver.fgmres(h.levels[-1].J, h.b, preconditioner(h), **kw)
+
+
+def solve_paper(h, **kw):
+    """The paper's Krylov setting (section "Details on the iterative solver"):
+    left-preconditioned GMRES(10), one classical Gram-Schmidt pass, rtol 1e-4
+    on the left-preconditioned residual; the V-cycle sweeps are the spec's."""
+    kw.setdefault("restart", 10)
+    kw.setdefault("rtol", 1e-4)
+    kw.setdefault("maxit", h.spec.maxit)
+    kw.setdefault("orth", "cgs")
+    return solver.gmres_left(h.levels[-1].J, h.b, preconditioner(h), **kw)

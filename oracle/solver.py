@@ -12,8 +12,14 @@ Test infrastructure only.
   restriction of the residual, recursive coarse correction, prolongation,
   post-smoothing; a direct solve on the coarsest level.
 * Krylov: right-preconditioned flexible GMRES(m) (Saad) with classical
-  Gram-Schmidt applied twice; the paper's PETSc GMRES is left-preconditioned
-  with a single classical Gram-Schmidt pass.
+  Gram-Schmidt applied twice (or once), and the paper's setting (section
+  "Details on the iterative solver"): GMRES on M^{-1} J (left
+  preconditioning) with one classical Gram-Schmidt pass, restart 10, stopped
+  when the left-preconditioned residual |M^{-1}(b - J x_j)| falls below rtol
+  times its initial value.
+* The average convergence rate rho = (r_N / r_0)^(1/N) of the monitored
+  residual over the N iterations (defined with the tables of section
+  "Condition number estimates").
 """
 
 from __future__ import annotations
@@ -94,9 +100,110 @@ class SolveInfo:
     true_relres: float
     est_relres: float
     history: list
+    rho: float = 0.0          # (r_N / r_0)^(1/N) of the monitored residual
 
 
-def fgmres(A, b, M, restart=30, rtol=1e-10, maxit=1000, x0=None, fixed_iters=None):
+def convergence_rate(r0, rN, iters):
+    """rho = (r_N / r_0)^(1/N): the geometric mean of the ratios of consecutive residuals."""
+    return (rN / r0) ** (1.0 / iters) if iters > 0 and r0 > 0 else 0.0
+
+
+def _orthogonalize(V, w, j, passes):
+    """Classical Gram-Schmidt of w against V[:, :j+1], applied `passes` times;
+    returns (h, w)."""
+    h = np.zeros(j + 1)
+    for _ in range(passes):
+        hp = V[:, : j + 1].T @ w
+        w = w - V[:, : j + 1] @ hp
+        h = h + hp
+    return h, w
+
+
+def _givens_step(H, cs, sn, g, j):
+    """Applies the stored rotations to column j of H, then a new rotation that
+    annihilates H[j+1, j]; updates g."""
+    for i in range(j):
+        t1 = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+        t2 = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+        H[i, j], H[i + 1, j] = t1, t2
+    den = math.hypot(H[j, j], H[j + 1, j])
+    cs[j] = H[j, j] / den
+    sn[j] = H[j + 1, j] / den
+    H[j, j] = den
+    H[j + 1, j] = 0.0
+    g[j + 1] = -sn[j] * g[j]
+    g[j] = cs[j] * g[j]
+
+
+def _back_solve(H, g, k):
+    y = np.zeros(k)
+    for i in range(k - 1, -1, -1):
+        y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]
+    return y
+
+
+def gmres_left(A, b, M, restart=10, rtol=1e-4, maxit=1000, x0=None, fixed_iters=None, orth="cgs"):
+    """GMRES(restart) on M^{-1} A x = M^{-1} b (left preconditioning).
+
+    Per step j: w = M(A v_j); w is orthogonalised against V by classical
+    Gram-Schmidt (one pass for "cgs", two for "cgs2"); h_{j+1,j} = |w|;
+    v_{j+1} = w / h_{j+1,j}; Givens rotations as in `fgmres`.  |g_{j+1}| is
+    the preconditioned residual norm |M^{-1}(b - A x_j)|.  The solve stops
+    when it is <= rtol times the initial |M^{-1}(b - A x_0)| (or at a happy
+    breakdown, at the restart length, at maxit); then x += V y and the
+    preconditioned residual of the new x decides exit or restart.
+    true_relres is |b - A x| / |b| of the returned x; est_relres the last
+    preconditioned residual over the initial one.
+    """
+    passes = {"cgs": 1, "cgs2": 2}[orth]
+    n = b.size
+    x = np.zeros(n) if x0 is None else x0.astype(float).copy()
+    bnorm = float(np.linalg.norm(b))
+    limit = maxit if fixed_iters is None else fixed_iters
+    iters = restarts = 0
+    hist = []
+    r = M(b - A @ x)
+    beta = beta0 = float(np.linalg.norm(r))
+    hist.append(beta)
+    tol = rtol * beta0
+
+    def done(conv):
+        tr = float(np.linalg.norm(b - A @ x)) / bnorm if bnorm > 0 else 0.0
+        return x, SolveInfo(iters, restarts, conv, tr, beta / beta0 if beta0 > 0 else 0.0, hist,
+                            convergence_rate(beta0, beta, iters))
+
+    while True:
+        if (fixed_iters is None and beta <= tol) or iters >= limit or beta == 0.0:
+            return done(beta <= tol)
+        m = restart
+        V = np.zeros((n, m + 1))
+        H = np.zeros((m + 1, m))
+        cs, sn, g = np.zeros(m), np.zeros(m), np.zeros(m + 1)
+        g[0] = beta
+        V[:, 0] = r / beta
+        k = 0
+        for j in range(m):
+            w = M(A @ V[:, j])
+            iters += 1
+            h, w = _orthogonalize(V, w, j, passes)
+            hn = float(np.linalg.norm(w))
+            H[: j + 1, j] = h
+            H[j + 1, j] = hn
+            breakdown = hn <= 1e-14 * float(np.linalg.norm(h))
+            if not breakdown:
+                V[:, j + 1] = w / hn
+            _givens_step(H, cs, sn, g, j)
+            hist.append(abs(g[j + 1]))
+            k = j + 1
+            if (fixed_iters is None and abs(g[j + 1]) <= tol) or breakdown or iters >= limit:
+                break
+        x = x + V[:, :k] @ _back_solve(H, g, k)
+        restarts += 1
+        r = M(b - A @ x)
+        beta = float(np.linalg.norm(r))
+
+
+def fgmres(A, b, M, restart=30, rtol=1e-10, maxit=1000, x0=None, fixed_iters=None, orth="cgs2"):
     """Right-preconditioned FGMRES(restart) with CGS2.
 
     Per step j: z_j = M(v_j); w = A z_j; h = V^T w, w -= V h; h' = V^T w,
@@ -108,8 +215,10 @@ def fgmres(A, b, M, restart=30, rtol=1e-10, maxit=1000, x0=None, fixed_iters=Non
     restart length is reached or at the iteration limit; then y = H^{-1} g,
     x += Z y and the true residual b - A x decides exit or restart.
     `fixed_iters` runs exactly that many preconditioner applications
-    (ignoring the tolerance) for fixed-iteration comparisons.
+    (ignoring the tolerance) for fixed-iteration comparisons.  orth="cgs"
+    orthogonalises with one classical Gram-Schmidt pass instead of two.
     """
+    passes = {"cgs": 1, "cgs2": 2}[orth]
     n = b.size
     x = np.zeros(n) if x0 is None else x0.astype(float).copy()
     bnorm = float(np.linalg.norm(b))
@@ -125,9 +234,11 @@ def fgmres(A, b, M, restart=30, rtol=1e-10, maxit=1000, x0=None, fixed_iters=Non
         if not hist:
             hist.append(beta)
         if fixed_iters is None and beta <= tol:
-            return x, SolveInfo(iters, restarts, True, beta / bnorm, beta / bnorm, hist)
+            return x, SolveInfo(iters, restarts, True, beta / bnorm, beta / bnorm, hist,
+                                convergence_rate(hist[0], beta, iters))
         if iters >= limit or beta == 0.0:
-            return x, SolveInfo(iters, restarts, beta <= tol, beta / bnorm, est, hist)
+            return x, SolveInfo(iters, restarts, beta <= tol, beta / bnorm, est, hist,
+                                convergence_rate(hist[0], beta, iters))
         m = restart
         V = np.zeros((n, m + 1))
         Z = np.zeros((n, m))
@@ -142,35 +253,18 @@ def fgmres(A, b, M, restart=30, rtol=1e-10, maxit=1000, x0=None, fixed_iters=Non
             Z[:, j] = M(V[:, j])
             iters += 1
             w = A @ Z[:, j]
-            h = V[:, : j + 1].T @ w
-            w = w - V[:, : j + 1] @ h
-            h2 = V[:, : j + 1].T @ w
-            w = w - V[:, : j + 1] @ h2
-            h = h + h2
+            h, w = _orthogonalize(V, w, j, passes)
             hn = float(np.linalg.norm(w))
             H[: j + 1, j] = h
             H[j + 1, j] = hn
             breakdown = hn <= 1e-14 * float(np.linalg.norm(h))
             if not breakdown:
                 V[:, j + 1] = w / hn
-            for i in range(j):
-                t1 = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
-                t2 = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
-                H[i, j], H[i + 1, j] = t1, t2
-            den = math.hypot(H[j, j], H[j + 1, j])
-            cs[j] = H[j, j] / den
-            sn[j] = H[j + 1, j] / den
-            H[j, j] = den
-            H[j + 1, j] = 0.0
-            g[j + 1] = -sn[j] * g[j]
-            g[j] = cs[j] * g[j]
+            _givens_step(H, cs, sn, g, j)
             est = abs(g[j + 1]) / bnorm
             hist.append(abs(g[j + 1]))
             k = j + 1
             if (fixed_iters is None and abs(g[j + 1]) <= tol) or breakdown or iters >= limit:
                 break
-        y = np.zeros(k)
-        for i in range(k - 1, -1, -1):
-            y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]
-        x = x + Z[:, :k] @ y
+        x = x + Z[:, :k] @ _back_solve(H, g, k)
         restarts += 1

@@ -8,4 +8,4 @@ generates the linear systems.
 """
 
 from ._lib import FsiError, lib  # noqa: F401
-from .solver import MG, Problem, Server, mg_opts, stream_read_gbps  # noqa: F401
+from .solver import MG, Problem, Server, krylov_opts, mg_opts, stream_read_gbps  # noqa: F401

@@ -19,6 +19,8 @@ FSI_OK, FSI_NOT_CONVERGED, FSI_PENDING = 0, 1, 2
 FSI_E_INVALID, FSI_E_OOM, FSI_E_SINGULAR, FSI_E_DEVICE = -1, -2, -3, -4
 FSI_E_NONFINITE, FSI_E_CAPACITY, FSI_E_UNKNOWN_TICKET = -5, -6, -7
 PREC = {"fp64": 0, "bf16": 1, "fp16": 2, "fp32": 3}
+ORTH = {"cgs2": 0, "cgs": 1}
+SIDE = {"right": 0, "left": 1}
 
 
 class FsiError(RuntimeError):
@@ -39,24 +41,26 @@ class Patches(C.Structure):
 
 
 class LevelC(C.Structure):
-    _fields_ = [("J", Csr), ("P", Csr), ("R", Csr), ("patches", Patches)]
+    _fields_ = [("J", Csr), ("P", Csr), ("R", Csr), ("patches", Patches),
+                ("dirichlet", C.POINTER(C.c_uint8))]
 
 
 class MgOpts(C.Structure):
     _fields_ = [("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("omega", C.c_double),
                 ("precision", C.c_int32), ("solid_precision", C.c_int32),
-                ("refine_sweeps", C.c_int32), ("use_graph", C.c_int32)]
+                ("refine_sweeps", C.c_int32), ("use_graph", C.c_int32), ("tuning_db", C.c_char_p)]
 
 
 class KrylovOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("rtol", C.c_double), ("maxit", C.c_int32),
-                ("fixed_iters", C.c_int32), ("history", C.POINTER(C.c_double))]
+                ("orth", C.c_int32), ("x0_nonzero", C.c_int32), ("history", C.POINTER(C.c_double)),
+                ("fixed_iters", C.c_int32), ("side", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("true_relres", C.c_double), ("est_relres", C.c_double),
-                ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("rho", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -108,7 +112,7 @@ def lib():
         "fsi_last_error": (C.c_char_p, []),
         "fsi_mg_setup": (C.c_int32, [C.POINTER(LevelC), C.c_int32, C.POINTER(MgOpts), P, C.POINTER(P)]),
         "fsi_mg_vcycle": (C.c_int32, [P, P, P, P]),
-        "fsi_fgmres_solve": (C.c_int32, [P, P, P, C.c_int32, C.POINTER(KrylovOpts), C.POINTER(SolveInfo), P]),
+        "fsi_fgmres_solve": (C.c_int32, [P, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo), P]),
         "fsi_mg_apply": (C.c_int32, [P, C.c_int32, C.c_int32, P, P, P, P]),
         "fsi_mg_export_patches": (C.c_int32, [P, C.c_int32, P, P, P, P]),
         "fsi_mg_level_info": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_int64)]),

@@ -870,6 +870,7 @@ fsi_status fsi_problem_levels(const struct fsi_problem *hp, fsi_level *levels) {
     fsi_level &L = levels[l];
     std::memset(&L, 0, sizeof L);
     L.J = view(p->J[l]);
+    L.dirichlet = p->meshes[l].dir.data();
     if (l > 0) {
       L.P = view(p->P[l]);
       L.R = view(p->R[l]);

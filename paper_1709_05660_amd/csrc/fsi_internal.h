@@ -73,6 +73,7 @@ struct DevicePool {
   std::mutex mu;
   std::multimap<size_t, void *> free_blocks;
   std::vector<void *> all;
+  int64_t allocated = 0, in_use = 0, peak_in_use = 0;   // bytes: hipMalloc'd, handed out, most handed out
   void *get(size_t bytes, size_t *got);
   void put(void *p, size_t bytes);
   ~DevicePool();
@@ -94,6 +95,7 @@ struct Krylov {
   double *pinned_dev = nullptr;   // its device address
   hipEvent_t ev_done = nullptr;   // recorded after a phase's D2H copy, polled by the host
   std::vector<hipGraphExec_t> step_graphs;   // Arnoldi step j as one graph (use_graph)
+  int graph_side = -1, graph_orth = -1;      // the solve variant the step graphs hold
   DevList owned;
 };
 
@@ -150,8 +152,8 @@ void destroy_mg(MG *mg);
 void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts);
 void apply_vcycle(MG &mg, const double *r, double *z, hipStream_t st);
 void run_vcycle(MG &mg, const double *r, double *z, hipStream_t st);
-fsi_status fgmres(MG &mg, const double *b, double *x, int x0_nonzero, const fsi_krylov_opts &ko,
-                  fsi_solve_info *info, hipStream_t st);
+fsi_status fgmres(MG &mg, const double *b, double *x, const fsi_krylov_opts &ko, fsi_solve_info *info,
+                  hipStream_t st);
 RasView ras_view(const Level &L);
 void ensure_krylov(MG &mg, int m);
 void clear_graphs(MG &mg);
@@ -160,29 +162,37 @@ void pinned_slot_release(double *s);
 void refactor(MG &mg, hipStream_t st);
 void release_setup_scratch(MG &mg);
 
+// GMRES(m) as a host state machine over the device work (section "Details on
+// the iterative solver").  RIGHT: flexible GMRES, z_j = M^{-1} v_j kept, the
+// monitored residual is |b - J x|.  LEFT: GMRES on M^{-1} J, the monitored
+// residual is |M^{-1}(b - J x)| and the reference of the stopping rule is its
+// initial value; a final phase computes the true residual |b - J x|.
 struct FgmresRun {
-  enum Phase { kFirst, kIter, kCheck, kDone };
+  enum Phase { kFirst, kIter, kCheck, kFinal, kDone };
   MG *mg = nullptr;
   const double *b = nullptr;
   double *x = nullptr;
   fsi_krylov_opts ko{};
   hipStream_t st = nullptr;
   Phase phase = kDone;
-  double bnorm = 0.0, beta = 0.0, est = 0.0;
+  bool left = false, twice = true;
+  double bnorm = 0.0, ref = 0.0, beta = 0.0, beta0 = 0.0, est = 0.0, true_res = 0.0;
   int iters = 0, restarts = 0, j = 0, k = 0, limit = 0;
   bool fixed = false, converged = false;
   std::vector<double> hist;
   std::chrono::steady_clock::time_point t0;
-  void start(MG &mg, const double *b, double *x, int x0_nonzero, const fsi_krylov_opts &ko,
-             hipStream_t st);
+  void start(MG &mg, const double *b, double *x, const fsi_krylov_opts &ko, hipStream_t st);
   void enqueue();
   bool complete();
   void fill_info(fsi_solve_info *info) const;
  private:
   void enqueue_residual();
+  void enqueue_true_residual();
   void enqueue_step();
   void finish_cycle();
+  bool finish();
   void add_hist(double v);
 };
+void validate_krylov(const fsi_krylov_opts &ko);
 
 }  // namespace fsi

@@ -146,8 +146,9 @@ inline int krylov_blocks(int n) { return std::max(256, (n + kKrylovChunk - 1) / 
 void launch_kdot(int n, const double *V, int64_t ldv, int k, const double *w, double *partial,
                  double *h, hipStream_t st);
 // Orthogonalisation of Arnoldi step j (k = j + 1 basis vectors V) by classical
-// Gram-Schmidt applied twice, and its Givens column, in four launches:
-// h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; h1 += h2;
+// Gram-Schmidt applied twice (twice) or once, and its Givens column, in four
+// launches (three for one pass): h1 = V^T w; w -= V h1; [h2 = V^T w; w -= V h2;
+// h1 += h2;]
 // H[:, j] = h1, H[j + 1, j] = |w|, previous rotations then a new one on H[:, j]
 // and g; flags[0] = |g[j + 1]|, flags[1] = breakdown, scal[0] = |w|;
 // v_next = w / |w| (untouched when |w| == 0).  partial holds
@@ -157,7 +158,7 @@ void launch_kdot(int n, const double *V, int64_t ldv, int k, const double *w, do
 void launch_arnoldi_orth(int n, const double *V, int64_t ldv, int k, double *w, double *partial,
                          double *h1, double *npart, double *v_next, double *H, int ldh, int j,
                          double *cs, double *sn, double *g, double *flags, double *scal,
-                         double *host_out, hipStream_t st);
+                         double *host_out, hipStream_t st, bool twice = true);
 // y = H^{-1} g (upper triangular k x k), then x += Z y
 void launch_backsolve(const double *H, int ldh, const double *g, int k, double *y, hipStream_t st);
 void launch_zupdate(int n, const double *Z, int64_t ldz, int k, const double *y, double *x,

@@ -709,8 +709,9 @@ __global__ __launch_bounds__(kKrylovThreads) void k_kupdate_dot(
   chunk_dots<true>(V, ldv, k, ws, r0, r1, pout);
 }
 
-// h2 = sum of pin's chunk sums (block 0: h1 += h2); w -= V h2; npart <- chunk
-// sums of w^2
+// h2 = sum of pin's chunk sums (block 0: h1 += h2, or h1 = h2 when the pass
+// is the only one, SET); w -= V h2; npart <- chunk sums of w^2
+template <bool SET>
 __global__ __launch_bounds__(kKrylovThreads) void k_kupdate_norm(
     int n, const double *__restrict__ V, int64_t ldv, int k, const double *__restrict__ pin,
     double *__restrict__ h1, double *__restrict__ w, double *__restrict__ npart) {
@@ -720,7 +721,7 @@ __global__ __launch_bounds__(kKrylovThreads) void k_kupdate_norm(
   chunk_range(n, r0, r1);
   finish_cols(pin, gridDim.x, k, hs);
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x < k) h1[threadIdx.x] += hs[threadIdx.x];
+  if (blockIdx.x == 0 && threadIdx.x < k) h1[threadIdx.x] = SET ? hs[threadIdx.x] : h1[threadIdx.x] + hs[threadIdx.x];
   const double nacc = wave_sum(chunk_update(V, ldv, k, hs, w, r0, r1, nullptr));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nacc;
   __syncthreads();
@@ -760,12 +761,16 @@ __global__ __launch_bounds__(kKrylovThreads) void k_kgivens_scale(
 void launch_arnoldi_orth(int n, const double *V, int64_t ldv, int k, double *w, double *partial,
                          double *h1, double *npart, double *v_next, double *H, int ldh, int j,
                          double *cs, double *sn, double *g, double *flags, double *scal,
-                         double *host_out, hipStream_t st) {
+                         double *host_out, hipStream_t st, bool twice) {
   const int nb = krylov_blocks(n);
   double *p1 = partial, *p2 = partial + (int64_t)nb * kMaxKrylovCols;
   k_kdot<<<nb, kKrylovThreads, 0, st>>>(n, V, ldv, k, w, p1);
-  k_kupdate_dot<<<nb, kKrylovThreads, 0, st>>>(n, V, ldv, k, p1, h1, w, p2);
-  k_kupdate_norm<<<nb, kKrylovThreads, 0, st>>>(n, V, ldv, k, p2, h1, w, npart);
+  if (twice) {
+    k_kupdate_dot<<<nb, kKrylovThreads, 0, st>>>(n, V, ldv, k, p1, h1, w, p2);
+    k_kupdate_norm<false><<<nb, kKrylovThreads, 0, st>>>(n, V, ldv, k, p2, h1, w, npart);
+  } else {
+    k_kupdate_norm<true><<<nb, kKrylovThreads, 0, st>>>(n, V, ldv, k, p1, h1, w, npart);
+  }
   k_kgivens_scale<<<nb, kKrylovThreads, 0, st>>>(n, npart, w, v_next, H, ldh, j, h1, cs, sn, g,
                                                  flags, scal, host_out);
 }

@@ -83,6 +83,30 @@ static void validate_patches(const fsi_patches &P, int64_t n, int lev) {
   }
 }
 
+// Dirichlet flags (optional): a flagged dof's row is the identity row (the
+// Newton correction is zero there) and no patch holds it (section
+// "Richardson-Schwarz smoother": the blocks are built on the unknowns)
+static void validate_dirichlet(const fsi_level &L, int64_t n, int lev) {
+  char buf[256];
+  const fsi_csr &J = L.J;
+  for (int64_t d = 0; d < n; ++d) {
+    if (!L.dirichlet[d]) continue;
+    const int64_t a = J.rowptr[d], b = J.rowptr[d + 1];
+    if (b - a != 1 || J.colind[a] != d || J.val[a] != 1.0) {
+      snprintf(buf, sizeof buf, "level %d: Dirichlet dof %lld does not hold an identity row", lev, (long long)d);
+      throw Error(FSI_E_INVALID, buf);
+    }
+  }
+  if (lev == 0) return;
+  const fsi_patches &P = L.patches;
+  for (int k = 0; k < P.npatch; ++k)
+    for (int64_t p = P.ptr[k]; p < P.ptr[k + 1]; ++p)
+      if (L.dirichlet[P.dof[p]]) {
+        snprintf(buf, sizeof buf, "level %d patch %d: holds Dirichlet dof %d", lev, k, P.dof[p]);
+        throw Error(FSI_E_INVALID, buf);
+      }
+}
+
 // ------------------------------------------------------------------ device helpers
 void *DevicePool::get(size_t bytes, size_t *got) {
   {
@@ -93,6 +117,8 @@ void *DevicePool::get(size_t bytes, size_t *got) {
       void *p = it->second;
       *got = it->first;
       free_blocks.erase(it);
+      in_use += (int64_t)*got;
+      peak_in_use = std::max(peak_in_use, in_use);
       return p;
     }
   }
@@ -101,11 +127,15 @@ void *DevicePool::get(size_t bytes, size_t *got) {
   std::lock_guard<std::mutex> lk(mu);
   all.push_back(p);
   *got = bytes;
+  allocated += (int64_t)bytes;
+  in_use += (int64_t)bytes;
+  peak_in_use = std::max(peak_in_use, in_use);
   return p;
 }
 void DevicePool::put(void *p, size_t bytes) {
   std::lock_guard<std::mutex> lk(mu);
   free_blocks.emplace(bytes, p);
+  in_use -= (int64_t)bytes;
 }
 DevicePool::~DevicePool() {
   for (void *p : all) (void)hipFree(p);
@@ -621,8 +651,11 @@ void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *op
       validate_csr(levels[l].R, n[l - 1], n[l], "R", l);
       validate_patches(levels[l].patches, n[l], l);
     }
+    if (levels[l].dirichlet) validate_dirichlet(levels[l], n[l], l);
   }
 }
+
+int autotune(MG &mg, const char *db_path, hipStream_t st);
 
 MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipStream_t user_st,
              hipStream_t own_st, DevicePool *pool, hipStream_t side_st) {
@@ -725,6 +758,8 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
     stage_drain();   // the uploads are complete and the staging buffer is free again
     hip_check(hipStreamSynchronize(st), "upload");
     refactor(*mg, st);
+    if (opts->tuning_db) autotune(*mg, opts->tuning_db, st);
+    mg->opts.tuning_db = nullptr;   // borrowed for the call only
   } catch (...) {
     try {
       stage_drain();   // no copy may still write into memory about to be released
@@ -786,9 +821,11 @@ void destroy_mg(MG *mg) {
 void clear_graphs(MG &mg) {
   for (auto &kv : mg.graphs) (void)hipGraphExecDestroy(kv.second);
   mg.graphs.clear();
-  for (auto &g : mg.kry.step_graphs)
+  // the per-step slots stay (a later solve with the same restart indexes them)
+  for (auto &g : mg.kry.step_graphs) {
     if (g) (void)hipGraphExecDestroy(g);
-  mg.kry.step_graphs.clear();
+    g = nullptr;
+  }
 }
 
 void ensure_krylov(MG &mg, int m) {
@@ -822,23 +859,40 @@ void ensure_krylov(MG &mg, int m) {
   }
 }
 
-// ---- FGMRES as a host state machine: enqueue() puts the next unit of work on
+// ---- GMRES as a host state machine: enqueue() puts the next unit of work on
 // the stream (ending with a small D2H copy into pinned memory), complete()
 // runs after the stream has drained and decides what comes next.  The
 // synchronous solve alternates the two; the server interleaves many systems.
-void FgmresRun::start(MG &mg_, const double *b_, double *x_, int x0_nonzero,
-                      const fsi_krylov_opts &ko_, hipStream_t st_) {
+void validate_krylov(const fsi_krylov_opts &ko) {
+  if (ko.restart < 1 || ko.restart > 60) throw Error(FSI_E_INVALID, "restart must be in [1, 60]");
+  if (!(ko.rtol >= 0.0) || ko.maxit < 1 || ko.fixed_iters < 0)
+    throw Error(FSI_E_INVALID, "invalid Krylov options (rtol, maxit, fixed_iters)");
+  if (ko.orth != FSI_ORTH_CGS2 && ko.orth != FSI_ORTH_CGS) throw Error(FSI_E_INVALID, "unknown orth");
+  if (ko.side != FSI_SIDE_RIGHT && ko.side != FSI_SIDE_LEFT) throw Error(FSI_E_INVALID, "unknown side");
+  if (ko.x0_nonzero != 0 && ko.x0_nonzero != 1) throw Error(FSI_E_INVALID, "x0_nonzero must be 0 or 1");
+}
+
+void FgmresRun::start(MG &mg_, const double *b_, double *x_, const fsi_krylov_opts &ko_,
+                      hipStream_t st_) {
   mg = &mg_;
   b = b_;
   x = x_;
   ko = ko_;
   st = st_;
-  const int m = ko.restart;
-  if (m < 1 || m > 60) throw Error(FSI_E_INVALID, "restart must be in [1, 60]");
-  if (!(ko.rtol >= 0.0) || ko.maxit < 1) throw Error(FSI_E_INVALID, "invalid Krylov options");
+  validate_krylov(ko);
+  left = ko.side == FSI_SIDE_LEFT;
+  twice = ko.orth == FSI_ORTH_CGS2;
   t0 = std::chrono::steady_clock::now();
-  ensure_krylov(*mg, m);
+  ensure_krylov(*mg, ko.restart);
   Krylov &K = mg->kry;
+  if (K.graph_side != ko.side || K.graph_orth != ko.orth ||   // the step graphs hold one variant
+      (int)K.step_graphs.size() != ko.restart) {
+    for (auto &g : K.step_graphs)
+      if (g) (void)hipGraphExecDestroy(g);
+    K.step_graphs.assign(ko.restart, nullptr);
+    K.graph_side = ko.side;
+    K.graph_orth = ko.orth;
+  }
   Level &F = mg->lv.back();
   const int n = F.n;
   fixed = ko.fixed_iters > 0;
@@ -847,35 +901,59 @@ void FgmresRun::start(MG &mg_, const double *b_, double *x_, int x0_nonzero,
   converged = false;
   hist.clear();
   est = NAN;
-  if (!x0_nonzero) launch_fill_f64(x, n, 0.0, st);
-  // |b|^2 and |b - J x|^2
+  true_res = 0.0;
+  if (!ko.x0_nonzero) launch_fill_f64(x, n, 0.0, st);
+  // |b|^2 and the monitored initial residual
   launch_kdot(n, b, n, 1, b, K.partial, K.nrm + 1, st);
   enqueue_residual();
   hip_check(hipMemcpyAsync(K.pinned, K.nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "D2H");
   phase = kFirst;
 }
 
+// the monitored residual into K.w and its square norm into nrm[0]: b - J x
+// (RIGHT) or M^{-1}(b - J x) (LEFT, through the first column of Z, which the
+// left form does not otherwise use)
 void FgmresRun::enqueue_residual() {
   Krylov &K = mg->kry;
   Level &F = mg->lv.back();
   const int n = F.n;
-  launch_spmv(F.J.v64(), x, b, K.w, kSpmvResid, F.J.lpr, st);
+  if (left) {
+    launch_spmv(F.J.v64(), x, b, K.Z, kSpmvResid, F.J.lpr, st);
+    apply_vcycle(*mg, K.Z, K.w, st);
+  } else {
+    launch_spmv(F.J.v64(), x, b, K.w, kSpmvResid, F.J.lpr, st);
+  }
   launch_kdot(n, K.w, n, 1, K.w, K.partial, K.nrm, st);
 }
 
-// Arnoldi step j: v_j -> z_j = M^{-1} v_j -> w = J z_j -> orthogonalisation,
-// Givens column, v_{j+1}; |g_{j+1}| and the breakdown flag land in pinned memory
+// |b - J x|^2 into nrm[2] and the pinned slot (LEFT form, once at the end)
+void FgmresRun::enqueue_true_residual() {
+  Krylov &K = mg->kry;
+  Level &F = mg->lv.back();
+  launch_spmv(F.J.v64(), x, b, K.Z, kSpmvResid, F.J.lpr, st);
+  launch_kdot(F.n, K.Z, F.n, 1, K.Z, K.partial, K.nrm + 2, st);
+  hip_check(hipMemcpyAsync(K.pinned, K.nrm + 2, sizeof(double), hipMemcpyDeviceToHost, st), "D2H");
+}
+
+// Arnoldi step j: RIGHT v_j -> z_j = M^{-1} v_j -> w = J z_j; LEFT v_j -> J v_j
+// -> w = M^{-1} J v_j; then the orthogonalisation, the Givens column and
+// v_{j+1}; |g_{j+1}| and the breakdown flag land in pinned memory
 void FgmresRun::enqueue_step() {
   Krylov &K = mg->kry;
   Level &F = mg->lv.back();
   const int n = F.n, m = ko.restart;
   if (j == 0) launch_start_cycle(n, K.w, K.nrm, K.V, K.g, m, st);
   double *vj = K.V + (int64_t)j * n;
-  double *zj = K.Z + (int64_t)j * n;
-  apply_vcycle(*mg, vj, zj, st);
-  launch_spmv(F.J.v64(), zj, (const double *)nullptr, K.w, kSpmvSet, F.J.lpr, st);
+  if (left) {
+    launch_spmv(F.J.v64(), vj, (const double *)nullptr, K.Z, kSpmvSet, F.J.lpr, st);
+    apply_vcycle(*mg, K.Z, K.w, st);
+  } else {
+    double *zj = K.Z + (int64_t)j * n;
+    apply_vcycle(*mg, vj, zj, st);
+    launch_spmv(F.J.v64(), zj, (const double *)nullptr, K.w, kSpmvSet, F.J.lpr, st);
+  }
   launch_arnoldi_orth(n, K.V, n, j + 1, K.w, K.partial, K.h1, K.npart, K.V + (int64_t)(j + 1) * n,
-                      K.H, m + 1, j, K.cs, K.sn, K.g, K.flags, K.scal, K.pinned_dev, st);
+                      K.H, m + 1, j, K.cs, K.sn, K.g, K.flags, K.scal, K.pinned_dev, st, twice);
 }
 
 void FgmresRun::enqueue() {
@@ -899,15 +977,30 @@ void FgmresRun::enqueue() {
   hip_check(hipGetLastError(), "arnoldi launch");
 }
 
+// end of a cycle: y = H^{-1} g, x += Z y (RIGHT) or V y (LEFT), then the
+// monitored residual of the new x decides exit or restart
 void FgmresRun::finish_cycle() {
   Krylov &K = mg->kry;
   Level &F = mg->lv.back();
   launch_backsolve(K.H, ko.restart + 1, K.g, k, K.y, st);
-  launch_zupdate(F.n, K.Z, F.n, k, K.y, x, st);
+  launch_zupdate(F.n, left ? K.V : K.Z, F.n, k, K.y, x, st);
   ++restarts;
   enqueue_residual();
   hip_check(hipMemcpyAsync(K.pinned, K.nrm, sizeof(double), hipMemcpyDeviceToHost, st), "D2H");
   phase = kCheck;
+}
+
+// the solve is over: the right form already holds |b - J x|; the left form
+// computes it in one more phase
+bool FgmresRun::finish() {
+  if (left) {
+    enqueue_true_residual();
+    phase = kFinal;
+    return false;
+  }
+  true_res = beta;
+  phase = kDone;
+  return true;
 }
 
 void FgmresRun::add_hist(double v) {
@@ -918,19 +1011,21 @@ void FgmresRun::add_hist(double v) {
 // decide after the stream drained; returns true when the solve is over
 bool FgmresRun::complete() {
   Krylov &K = mg->kry;
-  const double tol = ko.rtol * bnorm;
+  const double tol = ko.rtol * ref;
   if (phase == kFirst) {
     const double bn2 = K.pinned[1];
     if (!std::isfinite(bn2)) throw Error(FSI_E_NONFINITE, "right-hand side has NaN/Inf");
     bnorm = std::sqrt(bn2);
     beta = std::sqrt(K.pinned[0]);
+    if (!std::isfinite(beta)) throw Error(FSI_E_NONFINITE, "non-finite initial residual");
+    beta0 = beta;
+    ref = left ? beta : bnorm;
     add_hist(beta);
-    const double tol0 = ko.rtol * bnorm;
+    const double tol0 = ko.rtol * ref;
     if ((!fixed && beta <= tol0) || iters >= limit || beta == 0.0) {
       converged = beta <= tol0;
-      est = bnorm > 0 ? beta / bnorm : 0.0;
-      phase = kDone;
-      return true;
+      est = ref > 0 ? beta / ref : 0.0;
+      return finish();
     }
     j = 0;
     phase = kIter;
@@ -941,7 +1036,7 @@ bool FgmresRun::complete() {
     const bool breakdown = K.pinned[1] != 0.0;
     if (!std::isfinite(gj)) throw Error(FSI_E_NONFINITE, "non-finite Krylov residual estimate");
     ++iters;
-    est = gj / bnorm;
+    est = gj / ref;
     add_hist(gj);
     k = j + 1;
     if ((!fixed && gj <= tol) || breakdown || iters >= limit || k == ko.restart) {
@@ -953,14 +1048,19 @@ bool FgmresRun::complete() {
   }
   if (phase == kCheck) {
     beta = std::sqrt(K.pinned[0]);
+    if (!std::isfinite(beta)) throw Error(FSI_E_NONFINITE, "non-finite residual");
     if ((!fixed && beta <= tol) || iters >= limit || beta == 0.0) {
       converged = beta <= tol;
-      phase = kDone;
-      return true;
+      return finish();
     }
     j = 0;
     phase = kIter;
     return false;
+  }
+  if (phase == kFinal) {
+    true_res = std::sqrt(K.pinned[0]);
+    phase = kDone;
+    return true;
   }
   return phase == kDone;
 }
@@ -970,17 +1070,19 @@ void FgmresRun::fill_info(fsi_solve_info *info) const {
   info->iters = iters;
   info->restarts = restarts;
   info->converged = converged ? 1 : 0;
-  info->true_relres = bnorm > 0 ? beta / bnorm : 0.0;
+  info->true_relres = bnorm > 0 ? true_res / bnorm : 0.0;
   info->est_relres = est;
   info->setup_ms = mg->setup_ms;
   info->solve_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  // the monitored residual at exit over the initial one, per iteration
+  info->rho = iters > 0 && beta0 > 0 ? std::pow(beta / beta0, 1.0 / iters) : 0.0;
 }
 
-fsi_status fgmres(MG &mg, const double *b, double *x, int x0_nonzero, const fsi_krylov_opts &ko,
-                  fsi_solve_info *info, hipStream_t st) {
+fsi_status fgmres(MG &mg, const double *b, double *x, const fsi_krylov_opts &ko, fsi_solve_info *info,
+                  hipStream_t st) {
   FgmresRun run;
-  run.start(mg, b, x, x0_nonzero, ko, st);
+  run.start(mg, b, x, ko, st);
   // A phase's outcome is a few bytes in pinned memory.  The start and restart
   // phases copy it and are waited for by polling an event behind the copy; an
   // Arnoldi step's last kernel writes it itself with a ready mark, which the
@@ -1255,13 +1357,12 @@ fsi_status fsi_mg_vcycle(struct fsi_mg *h, const double *r_dev, double *z_dev, v
 }
 
 fsi_status fsi_fgmres_solve(struct fsi_mg *h, const double *b_dev, double *x_dev,
-                            int32_t x0_nonzero, const fsi_krylov_opts *kopts, fsi_solve_info *info,
-                            void *hip_stream) {
+                            const fsi_krylov_opts *kopts, fsi_solve_info *info, void *hip_stream) {
   FSI_GUARD({
     MG *mg = reinterpret_cast<MG *>(h);
     if (!mg || !b_dev || !x_dev || !kopts) throw Error(FSI_E_INVALID, "null argument");
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
-    return fgmres(*mg, b_dev, x_dev, x0_nonzero, *kopts, info, st);
+    return fgmres(*mg, b_dev, x_dev, *kopts, info, st);
   })
 }
 

@@ -113,10 +113,17 @@ static int64_t footprint(const fsi_level *lv, int nl, const fsi_mg_opts &mo,
     // (two ints per slot, an offset per block row) is setup scratch too
     transient += m2 * 8 + slots * 8 + P.ptr[P.npatch] * 8;
   }
-  const int64_t nf = lv[nl - 1].J.nrows;
-  res += nf * 8 * (2 * (int64_t)ko.restart + 4) + 2 * nf * 8;
+  // Krylov: V (m+1 columns), Z (m), w, b and x; H and the rotations; the
+  // reductions' chunk sums (two sets of kMaxKrylovCols columns) and norms
+  const int64_t nf = lv[nl - 1].J.nrows, m = ko.restart;
+  const int64_t kb = krylov_blocks((int)nf);
+  res += nf * 8 * (2 * m + 4) + ((m + 1) * m + 6 * (m + 2)) * 8;
+  res += (2 * kb * kMaxKrylovCols + kb + 12) * 8;
+  // the caching pool may hand out a block up to a quarter (+ 4 KiB) larger
+  // than asked for: admission counts that slack too
+  const int64_t slack = (res + transient) / 4 + 96 * 4096;
   if (transient_out) *transient_out = transient;
-  return res + transient;
+  return res + transient + slack;
 }
 
 static std::unique_ptr<Request> copy_request(const fsi_level *lv, int nl, const double *b,
@@ -137,7 +144,7 @@ static std::unique_ptr<Request> copy_request(const fsi_level *lv, int nl, const 
   r->i64.reserve(4 * nl);
   r->i32.reserve(4 * nl);
   r->f64.reserve(4 * nl);
-  r->u8.reserve(2 * nl);
+  r->u8.reserve(2 * nl);   // owned and kind per level (the Dirichlet flags were checked at submit)
   for (int l = 0; l < nl; ++l) {
     fsi_level &L = r->levels[l];
     std::memset(&L, 0, sizeof L);
@@ -163,6 +170,7 @@ static std::unique_ptr<Request> copy_request(const fsi_level *lv, int nl, const 
   }
   r->b.assign(b, b + lv[nl - 1].J.nrows);
   r->mo = mo;
+  r->mo.tuning_db = nullptr;   // served systems are not autotuned per request
   r->ko = ko;
   r->ko.history = nullptr;
   return r;
@@ -243,7 +251,7 @@ static void setup_loop(Server *S) {
       a->d_b = static_cast<double *>(S->pool.get(sizeof(double) * n, &a->b_bytes));
       a->d_x = static_cast<double *>(S->pool.get(sizeof(double) * n, &a->x_bytes));
       hip_check(hipMemcpyAsync(a->d_b, a->req->b.data(), sizeof(double) * n, hipMemcpyHostToDevice, a->st), "H2D");
-      a->run.start(*a->mg, a->d_b, a->d_x, 0, a->req->ko, a->st);
+      a->run.start(*a->mg, a->d_b, a->d_x, a->req->ko, a->st);
       a->t_ready = Clock::now();
       release_setup_scratch(*a->mg);      // the setup scratch is only needed during setup
       std::lock_guard<std::mutex> lk(S->mu);
@@ -369,6 +377,8 @@ fsi_status fsi_serve_submit(struct fsi_server *h, const fsi_level *levels, int32
     if (!S || !levels || nlevels < 1 || !b_host || !mo || !ko || !ticket)
       throw Error(FSI_E_INVALID, "null argument");
     validate_levels(levels, nlevels, mo);
+    validate_krylov(*ko);
+    if (ko->x0_nonzero) throw Error(FSI_E_INVALID, "a served request starts from x0 = 0");
     int64_t transient = 0;
     const int64_t fp = footprint(levels, nlevels, *mo, *ko, &transient);
     if (fp > S->o.hbm_budget_bytes) throw Error(FSI_E_CAPACITY, "request larger than the memory budget");
@@ -406,7 +416,7 @@ fsi_status fsi_serve_poll(struct fsi_server *h, uint64_t ticket, double *x_host,
   return st;
 }
 
-fsi_status fsi_server_stats(struct fsi_server *h, int64_t out[8]) {
+fsi_status fsi_server_stats(struct fsi_server *h, int64_t out[10]) {
   Server *S = reinterpret_cast<Server *>(h);
   if (!S || !out) return FSI_E_INVALID;
   std::lock_guard<std::mutex> lk(S->mu);
@@ -418,6 +428,9 @@ fsi_status fsi_server_stats(struct fsi_server *h, int64_t out[8]) {
   out[5] = S->peak;
   out[6] = S->ticks;
   out[7] = S->max_coresident;
+  std::lock_guard<std::mutex> lp(S->pool.mu);
+  out[8] = S->pool.allocated;
+  out[9] = S->pool.peak_in_use;
   return FSI_OK;
 }
 

@@ -149,14 +149,27 @@ class Problem:
 
 
 def mg_opts(nu_pre=2, nu_post=2, omega=0.7, precision="fp64", solid_precision=None,
-            refine_sweeps=0, use_graph=False):
+            refine_sweeps=0, use_graph=False, tuning_db=None):
     o = L.MgOpts()
     o.nu_pre, o.nu_post, o.omega = nu_pre, nu_post, omega
     o.precision = L.PREC[precision]
     o.solid_precision = -1 if solid_precision is None else L.PREC[solid_precision]
     o.refine_sweeps = refine_sweeps
     o.use_graph = 1 if use_graph else 0
+    o.tuning_db = tuning_db.encode() if tuning_db else None
     return o
+
+
+def krylov_opts(restart=30, rtol=1e-10, maxit=1000, orth="cgs2", x0=False, history=None, fixed_iters=0,
+                side="right"):
+    ko = L.KrylovOpts()
+    ko.restart, ko.rtol, ko.maxit = restart, rtol, maxit
+    ko.orth = L.ORTH[orth]
+    ko.x0_nonzero = 1 if x0 else 0
+    ko.history = L._ptr(history, C.c_double) if history is not None else None
+    ko.fixed_iters = fixed_iters
+    ko.side = L.SIDE[side]
+    return ko
 
 
 class MG:
@@ -203,19 +216,22 @@ class MG:
                                      _stream()), "apply")
         return y
 
-    def fgmres(self, b, x=None, restart=30, rtol=1e-10, maxit=1000, fixed_iters=0, x0=False):
+    def fgmres(self, b, x=None, restart=30, rtol=1e-10, maxit=1000, fixed_iters=0, x0=False,
+               orth="cgs2", side="right"):
+        """GMRES preconditioned by the V-cycle (fsi_fgmres_solve): side "right"
+        is flexible GMRES stopping on |b - J x| <= rtol |b|; side "left" is the
+        paper's left-preconditioned GMRES stopping on the preconditioned
+        residual relative to its initial value.  Returns (x, info dict)."""
         import torch
         if x is None:
             if x0:
                 raise ValueError("x0=True needs the starting vector x")
             x = torch.zeros(self.n, dtype=torch.float64, device="cuda")
         hist = np.zeros(maxit + 2)
-        ko = L.KrylovOpts()
-        ko.restart, ko.rtol, ko.maxit, ko.fixed_iters = restart, rtol, maxit, fixed_iters
-        ko.history = L._ptr(hist, C.c_double)
+        ko = krylov_opts(restart, rtol, maxit, orth, x0, hist, fixed_iters, side)
         info = L.SolveInfo()
-        st = L.lib().fsi_fgmres_solve(self.h, _vec(b, self.n, "b"), _vec(x, self.n, "x"), 1 if x0 else 0,
-                                      C.byref(ko), C.byref(info), _stream())
+        st = L.lib().fsi_fgmres_solve(self.h, _vec(b, self.n, "b"), _vec(x, self.n, "x"), C.byref(ko),
+                                      C.byref(info), _stream())
         L.check(st, "fgmres")
         d = info.as_dict()
         d["status"] = st
@@ -286,7 +302,7 @@ class Server:
         if b.shape != (problem.n,):
             raise ValueError(f"b: expected {problem.n} entries, got {b.shape}")
         mo = mg_opts(precision=precision, **mg)
-        ko = L.KrylovOpts(restart, rtol, maxit, fixed_iters, None)
+        ko = krylov_opts(restart, rtol, maxit, fixed_iters=fixed_iters)
         t = C.c_uint64()
         L.check(L.lib().fsi_serve_submit(self.h, problem.levels, problem.nlevels,
                                          b.ctypes.data_as(C.c_void_p), C.byref(mo), C.byref(ko),
@@ -309,10 +325,10 @@ class Server:
         return st, x[:n], info.as_dict()
 
     def stats(self):
-        out = (C.c_int64 * 8)()
+        out = (C.c_int64 * 10)()
         L.check(L.lib().fsi_server_stats(self.h, out))
         keys = ["submitted", "finished", "active", "queued", "bytes_in_use", "peak_bytes", "ticks",
-                "max_coresident"]
+                "max_coresident", "pool_allocated_bytes", "pool_peak_in_use_bytes"]
         return dict(zip(keys, list(out)))
 
     def close(self):

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
     for name in sorted(declared):
         assert hasattr(L, name), name
     assert set(_lib.EXPORTS) == declared
-    assert L.fsi_abi_version() == 1
+    assert L.fsi_abi_version() == 2
     assert L.fsi_status_string(-3) == b"singular block"
 
 
@@ -153,21 +153,32 @@ def test_setup_validation_errors_are_reported_on_the_host():
 
 
 def test_server_rejects_oversized_request():
-    from paper_1709_05660_amd import Problem, _lib, mg_opts
+    from paper_1709_05660_amd import Problem, _lib, krylov_opts, mg_opts
     s = config("c0_2d_16x4")
     p = Problem(s, fourier_coefficients(2, s.seed))
     lib = _lib.lib()
     so = _lib.ServerOpts(1 << 20, 4, 0)                 # 1 MiB budget
     h = C.c_void_p()
     assert lib.fsi_server_create(C.byref(so), C.byref(h)) == 0
-    ko = _lib.KrylovOpts(30, 1e-10, 100, 0, None)
+    ko = krylov_opts(30, 1e-10, 100)
     mo = mg_opts()
     t = C.c_uint64()
     st = lib.fsi_serve_submit(h, p.levels, p.nlevels, p.b.ctypes.data_as(C.c_void_p), C.byref(mo),
                               C.byref(ko), C.byref(t))
     assert st == -6
+    # Krylov options are checked at submit: a warm start, a restart of 0, an
+    # unknown side or orthogonalisation
+    bads = [(krylov_opts(x0=True), b"x0"), (krylov_opts(restart=0), b"restart")]
+    for field, word in (("side", b"side"), ("orth", b"orth")):
+        ko2 = krylov_opts()
+        setattr(ko2, field, 7)
+        bads.append((ko2, word))
+    for bad, word in bads:
+        st = lib.fsi_serve_submit(h, p.levels, p.nlevels, p.b.ctypes.data_as(C.c_void_p), C.byref(mo),
+                                  C.byref(bad), C.byref(t))
+        assert st == -1 and word in lib.fsi_last_error(), lib.fsi_last_error()
     assert lib.fsi_serve_poll(h, 12345, None, None) == -7
-    stats = (C.c_int64 * 8)()
+    stats = (C.c_int64 * 10)()
     assert lib.fsi_server_stats(h, stats) == 0 and stats[0] == 0
     assert lib.fsi_server_destroy(h) == 0
 
@@ -220,3 +231,49 @@ def test_binding_rejects_vectors_the_library_would_overrun():
             _vec(torch.zeros(20, dtype=torch.float64, device="cuda")[::2], 10, "x")
         with pytest.raises(ValueError, match="entries"):
             _vec(torch.zeros(9, dtype=torch.float64, device="cuda"), 10, "x")
+
+
+def test_dirichlet_flags_are_validated_on_the_host():
+    """The builder's Dirichlet flags pass (the setup then reaches the device:
+    status -4 here without a GPU); a flagged row that is not the identity row
+    and a flagged dof inside a patch are rejected (FSI_E_INVALID)."""
+    from paper_1709_05660_amd import Problem
+    s = config("c0_2d_16x4")
+    p = Problem(s, fourier_coefficients(2, s.seed))
+    L = p.nlevels
+    assert all(bool(p.levels[l].dirichlet) for l in range(L))
+    st, msg = _setup_status(p.levels, L)
+    assert st != -1, msg
+    flags = np.ctypeslib.as_array(p.levels[L - 1].dirichlet, shape=(p.n,))
+    ptr, dof, owned, kind = p.patches(L - 1)
+    d = int(dof[ptr[1] + 5])            # a free dof inside patch 1
+    assert flags[d] == 0
+    flags[d] = 1
+    st, msg = _setup_status(p.levels, L)
+    flags[d] = 0
+    assert st == -1 and "identity row" in msg
+    # an identity row that a patch holds: make row d the identity, flag it
+    J = p.levels[L - 1].J
+    rp = np.ctypeslib.as_array(J.rowptr, shape=(J.nrows + 1,))
+    nz = np.nonzero(np.diff(rp) == 1)[0]
+    fd = np.nonzero(flags)[0]
+    assert np.array_equal(nz[np.isin(nz, fd)], fd)       # every flagged row holds one entry
+    saved = (J.nrows, J.rowptr, J.colind, J.val, J.nnz)
+    rp2 = np.ctypeslib.as_array(J.rowptr, shape=(J.nrows + 1,)).copy()
+    ci2 = np.ctypeslib.as_array(J.colind, shape=(J.nnz,)).copy()
+    v2 = np.ctypeslib.as_array(J.val, shape=(J.nnz,)).copy()
+    a, b = rp2[d], rp2[d + 1]
+    ci2 = np.concatenate([ci2[:a], [d], ci2[b:]]).astype(np.int32)
+    v2 = np.concatenate([v2[:a], [1.0], v2[b:]])
+    rp2[d + 1:] -= (b - a) - 1
+    J.rowptr = rp2.ctypes.data_as(C.POINTER(C.c_int64))
+    J.colind = ci2.ctypes.data_as(C.POINTER(C.c_int32))
+    J.val = v2.ctypes.data_as(C.POINTER(C.c_double))
+    J.nnz = int(rp2[-1])
+    flags[d] = 1
+    try:
+        st, msg = _setup_status(p.levels, L)
+    finally:
+        flags[d] = 0
+        J.nrows, J.rowptr, J.colind, J.val, J.nnz = saved
+    assert st == -1 and "holds Dirichlet dof" in msg

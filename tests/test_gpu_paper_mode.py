@@ -1,0 +1,112 @@
+"""GPU parity of the paper's Krylov setting (section "Details on the iterative
+solver": left-preconditioned GMRES(10), one classical Gram-Schmidt pass,
+rtol 1e-4 on the left-preconditioned residual) and of the one-pass
+orthogonalisation in flexible GMRES, against the FP64 checker."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import dev, host, oracle_hierarchy, product_problem
+from oracle import problem as oprob
+from oracle import solver as osolver
+from synth import config, fourier_coefficients
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("name,graph", [("c0_2d_16x4", False), ("c0_2d_16x4", True),
+                                        ("c1_2d_128x32", True)])
+def test_paper_mode_parity(name, graph):
+    """Left GMRES(10) with one CGS pass to 1e-4: the GPU iterate after the
+    checker's iteration count equals the checker's to 1e-10, the converged
+    counts are equal within one, and the convergence rates agree."""
+    from paper_1709_05660_amd import MG
+    p = product_problem(name)
+    oh = oracle_hierarchy(name)
+    x_o, io = oprob.solve_paper(oh)
+    k = io.iters
+    x_fix, i_fix = oprob.solve_paper(oh, fixed_iters=k)
+    mg = MG(p, precision="fp64", use_graph=graph)
+    b = dev(p.b)
+    xg, ig = mg.fgmres(b, restart=10, rtol=1e-4, fixed_iters=k, side="left", orth="cgs")
+    rel = _rel(host(xg), x_fix)
+    _say(f"{name} paper mode: checker iters {k} rho {io.rho:.4f}; gpu fixed rel diff {rel:.2e} "
+         f"rho {ig['rho']:.4f} hist0 {ig['history'][0]:.6e} vs {io.history[0]:.6e}")
+    assert ig["history"][0] == pytest.approx(io.history[0], rel=1e-10)
+    assert rel <= 1e-10
+    assert ig["rho"] == pytest.approx(i_fix.rho, rel=1e-8)
+    x2, i2 = mg.fgmres(b, restart=10, rtol=1e-4, side="left", orth="cgs")
+    assert i2["converged"] == 1 and abs(i2["iters"] - k) <= 1
+    assert i2["est_relres"] <= 1e-4
+    if i2["iters"] == k:
+        assert i2["true_relres"] == pytest.approx(io.true_relres, rel=1e-6)
+        assert _rel(host(x2), x_o) <= 1e-10
+    mg.close()
+
+
+def test_left_graph_equals_eager():
+    from paper_1709_05660_amd import MG
+    p = product_problem("c0_2d_16x4")
+    b = dev(p.b)
+    res = []
+    for graph in (False, True):
+        mg = MG(p, precision="fp64", use_graph=graph)
+        for _ in range(2):                   # the second solve replays the captured steps
+            x, info = mg.fgmres(b, restart=10, rtol=1e-8, side="left", orth="cgs2")
+        res.append((host(x), info["iters"]))
+        mg.close()
+    assert res[0][1] == res[1][1]
+    assert np.array_equal(res[0][0], res[1][0])
+
+
+def test_one_pass_cgs_fgmres_parity_c0():
+    """Right-preconditioned FGMRES with one CGS pass: fixed-iteration parity."""
+    from paper_1709_05660_amd import MG
+    p = product_problem("c0_2d_16x4")
+    oh = oracle_hierarchy("c0_2d_16x4")
+    s = oh.spec
+    x_o, io = oprob.solve(oh, orth="cgs")
+    x_fix, _ = oprob.solve(oh, orth="cgs", fixed_iters=io.iters)
+    mg = MG(p, precision="fp64", use_graph=True)
+    xg, ig = mg.fgmres(dev(p.b), restart=s.restart, rtol=s.rtol, fixed_iters=io.iters, orth="cgs")
+    rel = _rel(host(xg), x_fix)
+    _say("c0 fgmres one CGS pass: iters", io.iters, "rel diff", rel)
+    assert rel <= 1e-10
+    # the same handle then runs the two-pass form again (its graphs rebuilt)
+    x2, i2 = mg.fgmres(dev(p.b), restart=s.restart, rtol=s.rtol)
+    x_o2, io2 = oprob.solve(oh)
+    assert abs(i2["iters"] - io2.iters) <= 1 and _rel(host(x2), x_o2) <= 1e-10
+    mg.close()
+
+
+def test_paper_mode_rates_on_the_gpu():
+    """Table FSI_results_pre_post's trend on the GPU, 64x16 on three levels:
+    (4, 4) sweeps give a lower average rate than (2, 2), each equal to the
+    checker's rate for the same iterations."""
+    from paper_1709_05660_amd import MG, Problem
+    rates = {}
+    for sw in ((2, 2), (4, 4)):
+        s = config("c1_2d_128x32").with_(nx=64, ny=16, levels=3, nu_pre=sw[0], nu_post=sw[1])
+        a = fourier_coefficients(2, s.seed)
+        oh = oprob.build(s, a)
+        _, io = oprob.solve_paper(oh)
+        p = Problem(s, a)
+        mg = MG(p, precision="fp64", nu_pre=sw[0], nu_post=sw[1])
+        _, ig = mg.fgmres(dev(p.b), restart=10, rtol=1e-4, side="left", orth="cgs",
+                          fixed_iters=io.iters)
+        _say(f"64x16 sweeps {sw}: iters {io.iters} rho gpu {ig['rho']:.4f} checker {io.rho:.4f}")
+        assert ig["rho"] == pytest.approx(io.rho, rel=1e-6)
+        rates[sw] = ig["rho"]
+        mg.close()
+    assert rates[(4, 4)] < rates[(2, 2)]

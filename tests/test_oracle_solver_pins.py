@@ -180,3 +180,97 @@ def test_q1_pressure_box_smoother_fails_where_p1disc_converges():
         res[pres] = info
     assert not res["q1"].converged and res["q1"].true_relres > 0.5
     assert res["p1disc"].converged and res["p1disc"].iters <= 20
+
+
+# ------------------------------------------------------------ paper mode: left GMRES
+def _left_system(n=30, seed=12, pert=0.4):
+    """A dense system and a dense preconditioner M^{-1} = (A + E)^{-1}."""
+    rng = np.random.default_rng(seed)
+    A = np.eye(n) * 3 + rng.standard_normal((n, n)) * 0.5
+    E = rng.standard_normal((n, n)) * pert
+    Minv = np.linalg.inv(A + E)
+    b = rng.standard_normal(n)
+    return A, Minv, b
+
+
+def test_left_gmres_residuals_are_krylov_minima():
+    """GMRES minimises |M^{-1}(b - A x)| over x0 + K_j(M^{-1} A, r0): each
+    estimate equals the least-squares minimum over an orthonormal basis of
+    the power basis [r0, B r0, ..., B^{j-1} r0], B = M^{-1} A, computed densely."""
+    A, Minv, b = _left_system()
+    B = Minv @ A
+    r0 = Minv @ b
+    for orth in ("cgs", "cgs2"):
+        x, info = solver.gmres_left(sp.csr_matrix(A), b, lambda v: Minv @ v, restart=30, rtol=1e-12,
+                                    fixed_iters=8, orth=orth)
+        K = np.empty((b.size, 8))
+        v = r0.copy()
+        for j in range(8):
+            K[:, j] = v
+            v = B @ v
+        for j in range(1, 9):
+            Q, _ = np.linalg.qr(K[:, :j])
+            y, *_ = np.linalg.lstsq(B @ Q, r0, rcond=None)
+            rmin = np.linalg.norm(r0 - B @ Q @ y)
+            assert info.history[j] == pytest.approx(rmin, rel=1e-8, abs=1e-13 * np.linalg.norm(r0))
+        # the returned iterate attains the last minimum
+        assert np.linalg.norm(Minv @ (b - A @ x)) == pytest.approx(info.history[8], rel=1e-8)
+
+
+def test_left_gmres_stopping_rule_and_rate():
+    """Exit when |M^{-1}(b - A x)| <= rtol |M^{-1} b| (x0 = 0), not one
+    iteration earlier; rho = (r_N / r_0)^(1/N) of those norms; an exact
+    preconditioner needs one iteration."""
+    A, Minv, b = _left_system(seed=3)
+    rtol = 1e-6
+    x, info = solver.gmres_left(sp.csr_matrix(A), b, lambda v: Minv @ v, restart=10, rtol=rtol)
+    r0 = np.linalg.norm(Minv @ b)
+    rN = np.linalg.norm(Minv @ (b - A @ x))
+    assert info.converged and rN <= rtol * r0 * 1.0001
+    x1, i1 = solver.gmres_left(sp.csr_matrix(A), b, lambda v: Minv @ v, restart=10, rtol=rtol,
+                               fixed_iters=info.iters - 1)
+    assert np.linalg.norm(Minv @ (b - A @ x1)) > rtol * r0
+    assert info.rho == pytest.approx((rN / r0) ** (1.0 / info.iters), rel=1e-6)
+    assert info.true_relres == pytest.approx(np.linalg.norm(b - A @ x) / np.linalg.norm(b), rel=1e-10)
+    Ainv = np.linalg.inv(A)
+    _, ie = solver.gmres_left(sp.csr_matrix(A), b, lambda v: Ainv @ v, restart=10, rtol=1e-10)
+    assert ie.iters == 1 and ie.converged
+
+
+def test_left_gmres_restarts_reach_the_solution():
+    A, Minv, b = _left_system(n=40, seed=8, pert=0.05)
+    x, info = solver.gmres_left(sp.csr_matrix(A), b, lambda v: Minv @ v, restart=3, rtol=1e-12, maxit=400)
+    xd = np.linalg.solve(A, b)
+    assert info.converged and info.restarts >= 2
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("passes", ["cgs", "cgs2"])
+def test_fgmres_one_and_two_gram_schmidt_passes_agree(passes):
+    """In exact arithmetic one and two classical Gram-Schmidt passes give the
+    same basis: on a well-conditioned system the histories agree."""
+    A, b = _dense_system(seed=7)
+    _, i1 = solver.fgmres(sp.csr_matrix(A), b, lambda v: v.copy(), restart=40, rtol=1e-12, orth=passes)
+    _, i2 = solver.fgmres(sp.csr_matrix(A), b, lambda v: v.copy(), restart=40, rtol=1e-12, orth="cgs2")
+    h1, h2 = np.array(i1.history), np.array(i2.history)
+    assert h1.size == h2.size
+    assert np.all(np.abs(h1 - h2) <= 1e-9 * h2[0])
+
+
+def test_paper_mode_rate_trends():
+    """Trends of Tables FSI_results_mg and FSI_results_pre_post in the paper's
+    Krylov setting (left GMRES(10), one CGS pass, rtol 1e-4): the average
+    convergence rate does not grow when the mesh is refined by one level
+    (32x8 on two levels, 64x16 on three), and (4, 4) sweeps converge faster
+    than (2, 2)."""
+    rho = {}
+    for (nx, ny, L) in ((32, 8, 2), (64, 16, 3)):
+        for sw in ((2, 2), (4, 4)):
+            h = _hier("c1_2d_128x32", nx=nx, ny=ny, levels=L, nu_pre=sw[0], nu_post=sw[1])
+            x, info = problem.solve_paper(h)
+            assert info.converged and info.est_relres <= 1e-4
+            rho[(nx, sw)] = info.rho
+    for sw in ((2, 2), (4, 4)):
+        assert rho[(64, sw)] <= 1.1 * rho[(32, sw)]
+    for nx in (32, 64):
+        assert rho[(nx, (4, 4))] < rho[(nx, (2, 2))]
