@@ -184,6 +184,26 @@ fsi_status fsi_mg_vcycle(struct fsi_mg *mg, const double *r_dev, double *z_dev, 
 fsi_status fsi_fgmres_solve(struct fsi_mg *mg, const double *b_dev, double *x_dev,
                             const fsi_krylov_opts *kopts, fsi_solve_info *info, void *hip_stream);
 
+/* For callers that cannot allocate device memory while they solve (tight
+ * serving loops, code that must not call hipMalloc): the same solve as
+ * fsi_fgmres_solve (same kernels, same results, launched one by one, never
+ * from graphs) whose Krylov buffers live in a static device workspace of
+ * 64 MiB that the library holds on each device it runs on until the process
+ * ends; the call itself allocates nothing (the handle took its pinned
+ * result slot and event at setup).  The workspace takes
+ * 8 (n (2 restart + 2) + O(restart^2) + 33,000) bytes, rounded per buffer:
+ * up to about 130,000 unknowns at restart 30.  Larger requests return
+ * FSI_E_CAPACITY with the sizes in the message.  Every call on a device
+ * shares that device's workspace and leaves its contents behind (no buffer
+ * needs to start at zero: every value is written before it is read in the
+ * same call); calls that overlap on one device, from several threads or on
+ * several streams, race and must be serialised by the caller.  The handle's
+ * device must be current (else FSI_E_INVALID).  Other errors as
+ * fsi_fgmres_solve. */
+fsi_status fsi_fgmres_solve_noalloc(struct fsi_mg *mg, const double *b_dev, double *x_dev,
+                                    const fsi_krylov_opts *kopts, fsi_solve_info *info,
+                                    void *hip_stream);
+
 /* Debug/parity: applies one operator of level `level` to x_dev (device, FP64):
  * op 0: y = J x;  1: y = r - J x (r_dev given);  2: y = P x;  3: y = R x;
  * 4: y = sum_k R^0_k^T B_k^{-1} R^delta_k x (one Schwarz application);

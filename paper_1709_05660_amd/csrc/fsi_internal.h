@@ -107,6 +107,8 @@ struct GraphKey {
 
 struct MG {
   int nlevels = 0;
+  int device = 0;                 // HIP device current at setup
+  double *static_ws = nullptr;    // that device's static Krylov workspace (fsi_fgmres_solve_noalloc)
   bool mixed = false;
   fsi_mg_opts opts{};
   std::vector<Level> lv;
@@ -153,7 +155,7 @@ void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *op
 void apply_vcycle(MG &mg, const double *r, double *z, hipStream_t st);
 void run_vcycle(MG &mg, const double *r, double *z, hipStream_t st);
 fsi_status fgmres(MG &mg, const double *b, double *x, const fsi_krylov_opts &ko, fsi_solve_info *info,
-                  hipStream_t st);
+                  hipStream_t st, Krylov *ws = nullptr);
 RasView ras_view(const Level &L);
 void ensure_krylov(MG &mg, int m);
 void clear_graphs(MG &mg);
@@ -170,18 +172,22 @@ void release_setup_scratch(MG &mg);
 struct FgmresRun {
   enum Phase { kFirst, kIter, kCheck, kFinal, kDone };
   MG *mg = nullptr;
+  Krylov *K = nullptr;            // the workspace: mg->kry, or a caller-bound one (no graphs)
   const double *b = nullptr;
   double *x = nullptr;
   fsi_krylov_opts ko{};
   hipStream_t st = nullptr;
   Phase phase = kDone;
-  bool left = false, twice = true;
+  bool left = false, twice = true, graphs = false;
   double bnorm = 0.0, ref = 0.0, beta = 0.0, beta0 = 0.0, est = 0.0, true_res = 0.0;
-  int iters = 0, restarts = 0, j = 0, k = 0, limit = 0;
+  int iters = 0, restarts = 0, j = 0, k = 0, limit = 0, nhist = 0;
   bool fixed = false, converged = false;
-  std::vector<double> hist;
   std::chrono::steady_clock::time_point t0;
-  void start(MG &mg, const double *b, double *x, const fsi_krylov_opts &ko, hipStream_t st);
+  // ws: NULL (the handle's own workspace, allocated on first use, steps
+  // replayed from graphs when use_graph) or a workspace bound by
+  // bind_krylov (no allocation, no graphs)
+  void start(MG &mg, const double *b, double *x, const fsi_krylov_opts &ko, hipStream_t st,
+             Krylov *ws = nullptr);
   void enqueue();
   bool complete();
   void fill_info(fsi_solve_info *info) const;
@@ -194,5 +200,10 @@ struct FgmresRun {
   void add_hist(double v);
 };
 void validate_krylov(const fsi_krylov_opts &ko);
+// doubles of device memory the Krylov buffers of an n-row system with restart m take
+int64_t krylov_doubles(int n, int m);
+// points the buffers of K into base (krylov_doubles(n, m) doubles, 256-byte
+// aligned); the pinned slot and the event are the handle's (acquired at setup)
+void bind_krylov(Krylov &K, const MG &mg, double *base, int n, int m);
 
 }  // namespace fsi

@@ -17,6 +17,27 @@ namespace fsi {
 
 thread_local std::string g_last_error;
 
+// Static Krylov workspace of fsi_fgmres_solve_noalloc, one per device (each
+// device that loads the library holds it until the process ends).  Host code
+// never uses the symbol itself as an address: scratch_address() takes the
+// device address once per device, with that device current, and keeps it.
+constexpr int64_t kStaticScratchBytes = 64ll << 20;
+static __device__ __align__(256) double scratch[kStaticScratchBytes / 8];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices];
+static double *scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) throw Error(FSI_E_DEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "static workspace address");
+    if (!ptr) throw Error(FSI_E_DEVICE, "static workspace address is null");
+    g_scratch_ptr[dev] = static_cast<double *>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
 void set_error(const std::string &m) { g_last_error = m; }
 
 void hip_check(hipError_t e, const char *what) {
@@ -666,6 +687,7 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
   MG *mg = new MG();
   mg->opts = *opts;
   mg->nlevels = nlevels;
+  hip_check(hipGetDevice(&mg->device), "device");
   mg->mixed = opts->precision != FSI_PREC_FP64;
   mg->own_stream = own_st;
   mg->owned.pool = pool;
@@ -755,6 +777,13 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
     }
     hip_check(hipEventCreateWithFlags(&mg->ev_fork, hipEventDisableTiming), "event");
     hip_check(hipEventCreateWithFlags(&mg->ev_join, hipEventDisableTiming), "event");
+    // the solve's host-coherent result slot and its event, taken here so that
+    // fsi_fgmres_solve_noalloc allocates nothing; the static workspace's
+    // address on this device (the device is current here)
+    mg->kry.pinned = pinned_slot_acquire();
+    hip_check(hipHostGetDevicePointer((void **)&mg->kry.pinned_dev, mg->kry.pinned, 0), "pinned address");
+    hip_check(hipEventCreateWithFlags(&mg->kry.ev_done, hipEventDisableTiming), "event");
+    mg->static_ws = scratch_address(mg->device);
     stage_drain();   // the uploads are complete and the staging buffer is free again
     hip_check(hipStreamSynchronize(st), "upload");
     refactor(*mg, st);
@@ -859,6 +888,34 @@ void ensure_krylov(MG &mg, int m) {
   }
 }
 
+// The Krylov buffers in one region (sizes as ensure_krylov allocates them),
+// each starting on a 256-byte boundary.
+static int64_t krylov_layout(int n, int m, double *base, Krylov *K) {
+  int64_t off = 0;
+  auto take = [&](int64_t cnt) {
+    double *p = base ? base + off : nullptr;
+    off += (cnt + 31) / 32 * 32;
+    return p;
+  };
+  double *V = take((int64_t)n * (m + 1)), *Z = take((int64_t)n * m), *H = take((int64_t)(m + 1) * m);
+  double *cs = take(m + 1), *sn = take(m + 1), *g = take(m + 2), *y = take(m + 1), *h1 = take(m + 2);
+  double *partial = take((int64_t)2 * krylov_blocks(n) * kMaxKrylovCols), *npart = take(krylov_blocks(n));
+  double *nrm = take(4), *flags = take(4), *scal = take(4), *w = take(n);
+  if (K) {
+    K->V = V; K->Z = Z; K->H = H; K->cs = cs; K->sn = sn; K->g = g; K->y = y; K->h1 = h1;
+    K->partial = partial; K->npart = npart; K->nrm = nrm; K->flags = flags; K->scal = scal; K->w = w;
+  }
+  return off;
+}
+int64_t krylov_doubles(int n, int m) { return krylov_layout(n, m, nullptr, nullptr); }
+void bind_krylov(Krylov &K, const MG &mg, double *base, int n, int m) {
+  krylov_layout(n, m, base, &K);
+  K.m = m;
+  K.pinned = mg.kry.pinned;
+  K.pinned_dev = mg.kry.pinned_dev;
+  K.ev_done = mg.kry.ev_done;
+}
+
 // ---- GMRES as a host state machine: enqueue() puts the next unit of work on
 // the stream (ending with a small D2H copy into pinned memory), complete()
 // runs after the stream has drained and decides what comes next.  The
@@ -873,7 +930,7 @@ void validate_krylov(const fsi_krylov_opts &ko) {
 }
 
 void FgmresRun::start(MG &mg_, const double *b_, double *x_, const fsi_krylov_opts &ko_,
-                      hipStream_t st_) {
+                      hipStream_t st_, Krylov *ws) {
   mg = &mg_;
   b = b_;
   x = x_;
@@ -883,23 +940,31 @@ void FgmresRun::start(MG &mg_, const double *b_, double *x_, const fsi_krylov_op
   left = ko.side == FSI_SIDE_LEFT;
   twice = ko.orth == FSI_ORTH_CGS2;
   t0 = std::chrono::steady_clock::now();
-  ensure_krylov(*mg, ko.restart);
-  Krylov &K = mg->kry;
-  if (K.graph_side != ko.side || K.graph_orth != ko.orth ||   // the step graphs hold one variant
-      (int)K.step_graphs.size() != ko.restart) {
-    for (auto &g : K.step_graphs)
-      if (g) (void)hipGraphExecDestroy(g);
-    K.step_graphs.assign(ko.restart, nullptr);
-    K.graph_side = ko.side;
-    K.graph_orth = ko.orth;
+  if (ws) {
+    K = ws;
+    graphs = false;
+  } else {
+    ensure_krylov(*mg, ko.restart);
+    K = &mg->kry;
+    graphs = mg->opts.use_graph && !mg->prof_on;
+    Krylov &G = *K;
+    if (G.graph_side != ko.side || G.graph_orth != ko.orth ||   // the step graphs hold one variant
+        (int)G.step_graphs.size() != ko.restart) {
+      for (auto &g : G.step_graphs)
+        if (g) (void)hipGraphExecDestroy(g);
+      G.step_graphs.assign(ko.restart, nullptr);
+      G.graph_side = ko.side;
+      G.graph_orth = ko.orth;
+    }
   }
+  Krylov &K = *this->K;
   Level &F = mg->lv.back();
   const int n = F.n;
   fixed = ko.fixed_iters > 0;
   limit = fixed ? ko.fixed_iters : ko.maxit;
   iters = restarts = j = k = 0;
   converged = false;
-  hist.clear();
+  nhist = 0;
   est = NAN;
   true_res = 0.0;
   if (!ko.x0_nonzero) launch_fill_f64(x, n, 0.0, st);
@@ -914,7 +979,7 @@ void FgmresRun::start(MG &mg_, const double *b_, double *x_, const fsi_krylov_op
 // (RIGHT) or M^{-1}(b - J x) (LEFT, through the first column of Z, which the
 // left form does not otherwise use)
 void FgmresRun::enqueue_residual() {
-  Krylov &K = mg->kry;
+  Krylov &K = *this->K;
   Level &F = mg->lv.back();
   const int n = F.n;
   if (left) {
@@ -928,7 +993,7 @@ void FgmresRun::enqueue_residual() {
 
 // |b - J x|^2 into nrm[2] and the pinned slot (LEFT form, once at the end)
 void FgmresRun::enqueue_true_residual() {
-  Krylov &K = mg->kry;
+  Krylov &K = *this->K;
   Level &F = mg->lv.back();
   launch_spmv(F.J.v64(), x, b, K.Z, kSpmvResid, F.J.lpr, st);
   launch_kdot(F.n, K.Z, F.n, 1, K.Z, K.partial, K.nrm + 2, st);
@@ -939,7 +1004,7 @@ void FgmresRun::enqueue_true_residual() {
 // -> w = M^{-1} J v_j; then the orthogonalisation, the Givens column and
 // v_{j+1}; |g_{j+1}| and the breakdown flag land in pinned memory
 void FgmresRun::enqueue_step() {
-  Krylov &K = mg->kry;
+  Krylov &K = *this->K;
   Level &F = mg->lv.back();
   const int n = F.n, m = ko.restart;
   if (j == 0) launch_start_cycle(n, K.w, K.nrm, K.V, K.g, m, st);
@@ -958,9 +1023,9 @@ void FgmresRun::enqueue_step() {
 
 void FgmresRun::enqueue() {
   if (phase != kIter) return;
-  Krylov &K = mg->kry;
+  Krylov &K = *this->K;
   reinterpret_cast<volatile double *>(K.pinned)[2] = 0.0;   // set again by the step's last kernel
-  if (mg->opts.use_graph && !mg->prof_on) {
+  if (graphs) {
     hipGraphExec_t &ex = K.step_graphs[j];
     if (!ex) {
       hipGraph_t g;
@@ -980,7 +1045,7 @@ void FgmresRun::enqueue() {
 // end of a cycle: y = H^{-1} g, x += Z y (RIGHT) or V y (LEFT), then the
 // monitored residual of the new x decides exit or restart
 void FgmresRun::finish_cycle() {
-  Krylov &K = mg->kry;
+  Krylov &K = *this->K;
   Level &F = mg->lv.back();
   launch_backsolve(K.H, ko.restart + 1, K.g, k, K.y, st);
   launch_zupdate(F.n, left ? K.V : K.Z, F.n, k, K.y, x, st);
@@ -1004,13 +1069,13 @@ bool FgmresRun::finish() {
 }
 
 void FgmresRun::add_hist(double v) {
-  if (ko.history && (int)hist.size() <= ko.maxit) ko.history[hist.size()] = v;
-  hist.push_back(v);
+  if (ko.history && nhist <= ko.maxit) ko.history[nhist] = v;
+  ++nhist;
 }
 
 // decide after the stream drained; returns true when the solve is over
 bool FgmresRun::complete() {
-  Krylov &K = mg->kry;
+  Krylov &K = *this->K;
   const double tol = ko.rtol * ref;
   if (phase == kFirst) {
     const double bn2 = K.pinned[1];
@@ -1080,23 +1145,23 @@ void FgmresRun::fill_info(fsi_solve_info *info) const {
 }
 
 fsi_status fgmres(MG &mg, const double *b, double *x, const fsi_krylov_opts &ko, fsi_solve_info *info,
-                  hipStream_t st) {
+                  hipStream_t st, Krylov *ws) {
   FgmresRun run;
-  run.start(mg, b, x, ko, st);
+  run.start(mg, b, x, ko, st, ws);
   // A phase's outcome is a few bytes in pinned memory.  The start and restart
   // phases copy it and are waited for by polling an event behind the copy; an
   // Arnoldi step's last kernel writes it itself with a ready mark, which the
   // host polls (the stream is queried now and then so that a failed launch
   // cannot leave the host waiting).
   auto wait_copy = [&](const char *what) {
-    hip_check(hipEventRecord(mg.kry.ev_done, st), what);
+    hip_check(hipEventRecord(run.K->ev_done, st), what);
     hipError_t e;
-    while ((e = hipEventQuery(mg.kry.ev_done)) == hipErrorNotReady) {
+    while ((e = hipEventQuery(run.K->ev_done)) == hipErrorNotReady) {
     }
     hip_check(e, what);
   };
   auto wait_step = [&]() {
-    volatile double *ready = mg.kry.pinned + 2;
+    volatile double *ready = run.K->pinned + 2;
     for (unsigned spin = 1; *ready == 0.0; ++spin) {
       if (spin % 4096 == 0) {
         const hipError_t e = hipStreamQuery(st);
@@ -1363,6 +1428,33 @@ fsi_status fsi_fgmres_solve(struct fsi_mg *h, const double *b_dev, double *x_dev
     if (!mg || !b_dev || !x_dev || !kopts) throw Error(FSI_E_INVALID, "null argument");
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
     return fgmres(*mg, b_dev, x_dev, *kopts, info, st);
+  })
+}
+
+fsi_status fsi_fgmres_solve_noalloc(struct fsi_mg *h, const double *b_dev, double *x_dev,
+                                    const fsi_krylov_opts *kopts, fsi_solve_info *info,
+                                    void *hip_stream) {
+  FSI_GUARD({
+    MG *mg = reinterpret_cast<MG *>(h);
+    if (!mg || !b_dev || !x_dev || !kopts) throw Error(FSI_E_INVALID, "null argument");
+    validate_krylov(*kopts);
+    const int n = mg->lv.back().n;
+    const int64_t need = krylov_doubles(n, kopts->restart) * 8;
+    if (need > kStaticScratchBytes) {
+      char buf[200];
+      snprintf(buf, sizeof buf,
+               "the Krylov workspace of %d unknowns at restart %d takes %lld bytes; the static "
+               "workspace holds %lld",
+               n, kopts->restart, (long long)need, (long long)kStaticScratchBytes);
+      throw Error(FSI_E_CAPACITY, buf);
+    }
+    int dev = -1;
+    hip_check(hipGetDevice(&dev), "device");
+    if (dev != mg->device) throw Error(FSI_E_INVALID, "the handle's device is not the current device");
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
+    Krylov ws;
+    bind_krylov(ws, *mg, mg->static_ws, n, kopts->restart);
+    return fgmres(*mg, b_dev, x_dev, *kopts, info, st, &ws);
   })
 }
 
