@@ -285,7 +285,7 @@ def gpu_leg(args):
         mg.profile_start()
         for _ in range(args.prof_steps):
             mg.fgmres(b, x, restart=spec.restart, rtol=spec.rtol, maxit=spec.maxit)
-        kms, cnt = mg.profile_stop()
+        kms, cnt, _, _ = mg.profile_stop()
         avg_ms = kms / max(cnt, 1)
         bytes_per_launch = ras_bytes(fine, 8, 8)
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if cnt else 0.0

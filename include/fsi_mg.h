@@ -50,11 +50,12 @@ enum {
 };
 
 /* Precision of the V-cycle (the Krylov method, the true residual and the
- * coarsest solve are always FP64).  MIXED_*: V-cycle vectors, operators and
- * transfers in FP32; the block inverses are computed in FP64 and their owned
- * rows stored in the named 16-bit type with two-sided FP32 scaling
- * (B^{-1} = diag(rs) W diag(cs)) and applied with FP32 accumulation;
- * MIXED_FP32: owned rows stored in FP32. */
+ * coarsest solve are always FP64).  FP64: blocks inverted and applied in
+ * FP64.  MIXED_*: V-cycle vectors, operators and transfers in FP32; the
+ * blocks are inverted in FP32 (Gauss-Jordan on the FP32 matrix cores) and
+ * the owned rows of each inverse stored in the named 16-bit type with
+ * two-sided FP32 scaling (B^{-1} = diag(rs) W diag(cs)) and applied with FP32
+ * accumulation; MIXED_FP32: owned rows stored in FP32. */
 enum { FSI_PREC_FP64 = 0, FSI_PREC_MIXED_BF16 = 1, FSI_PREC_MIXED_FP16 = 2, FSI_PREC_MIXED_FP32 = 3 };
 
 /* Orthogonalisation of the Krylov basis: classical Gram-Schmidt applied
@@ -103,11 +104,15 @@ typedef struct {
   int32_t nu_pre, nu_post; /* Richardson sweeps before / after the coarse correction */
   double omega;            /* Richardson damping (the paper uses 0.7) */
   int32_t precision;       /* FSI_PREC_* */
-  int32_t solid_precision; /* reserved: -1 or equal to `precision` (one precision per
-                              hierarchy); other values are rejected (FSI_E_INVALID) */
-  int32_t refine_sweeps;   /* reserved: must be 0 (no per-block refinement; the outer
-                              Richardson and FGMRES iterations correct the rounding of
-                              the stored inverse rows); other values are rejected */
+  int32_t solid_precision; /* storage of the solid blocks' inverses (patch kind 1): -1 or
+                              `precision` (every block alike), or FSI_PREC_MIXED_FP32 in a
+                              mixed hierarchy (solid blocks in FP32, fluid blocks in
+                              `precision`).  The paper requires exact local solves on the
+                              solid blocks (section "Richardson-Schwarz smoother") */
+  int32_t refine_sweeps;   /* 0..4, mixed hierarchies only: refinement sweeps of each solid
+                              block's local solve, y <- y + B~^{-1}(g - B_k y) with the
+                              FP32 inverse B~^{-1} (all its rows kept) and the block B_k
+                              taken from J in FP32; fluid blocks are solved once */
   int32_t use_graph;       /* replay the V-cycle and each Arnoldi step from hipGraphs */
   const char *tuning_db;   /* NULL, or a text database path: setup then runs the
                               autotuner (fsi_mg_autotune) with it */
@@ -206,8 +211,11 @@ fsi_status fsi_fgmres_solve_noalloc(struct fsi_mg *mg, const double *b_dev, doub
 
 /* Debug/parity: applies one operator of level `level` to x_dev (device, FP64):
  * op 0: y = J x;  1: y = r - J x (r_dev given);  2: y = P x;  3: y = R x;
- * 4: y = sum_k R^0_k^T B_k^{-1} R^delta_k x (one Schwarz application);
- * 5: y = coarsest direct solve of x (level 0). */
+ * 4: y = sum_k R^0_k^T B_k^{-1} R^delta_k x (one Schwarz application, FP64
+ *    hierarchies); 5: y = coarsest direct solve of x (level 0);
+ * 6: the Schwarz application as the V-cycle performs it in the hierarchy's
+ *    precision (mixed: x rounded to FP32, the stored inverses, refined solid
+ *    blocks, the result widened to FP64). */
 fsi_status fsi_mg_apply(struct fsi_mg *mg, int32_t level, int32_t op, const double *x_dev,
                         const double *r_dev, double *y_dev, void *hip_stream);
 
@@ -229,10 +237,13 @@ fsi_status fsi_mg_refactor(struct fsi_mg *mg, void *hip_stream);
  * owned by the handle; callers may overwrite them before fsi_mg_refactor. */
 fsi_status fsi_mg_jvalues(struct fsi_mg *mg, int32_t level, double **val_dev);
 
-/* Profiling of the finest-level Schwarz kernel with HIP events on its stream:
- * enable = 1 starts (V-cycles then run without graphs), enable = 0 stops and
- * writes out[0] = total kernel milliseconds, out[1] = number of launches. */
-fsi_status fsi_mg_profile(struct fsi_mg *mg, int32_t enable, double out[2]);
+/* Measurement hook: HIP events recorded at the own start and end of the
+ * finest-level Schwarz kernel and of the batched block inversion, on the
+ * streams they run on.  enable = 1 starts (V-cycles and Arnoldi steps then
+ * run without graphs), enable = 0 stops and writes out[0] = total Schwarz
+ * kernel milliseconds, out[1] = its launches, out[2] = total batched
+ * inversion milliseconds, out[3] = its launches (out may be NULL). */
+fsi_status fsi_mg_profile(struct fsi_mg *mg, int32_t enable, double out[4]);
 
 /* Autotuner: times the lanes-per-row of every level's SpMV (J, P, R, in the
  * V-cycle's precision) and the panel width of the batched block inversion

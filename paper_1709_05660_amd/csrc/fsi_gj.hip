@@ -23,6 +23,7 @@
 //     A[i][j] <- [i is not a pivot row of the panel] A[i][j]
 //                + sum_t PC[i][t] X[t][j],
 // where X[t][j] is the panel's t-th pivot row before the update.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -130,28 +131,38 @@ __device__ __forceinline__ double recip(double a) {
 // LDS of the pivot steps: one candidate row (with the reciprocal of its
 // pivot-column entry and its key) per wave and step parity, and the panel's
 // pivot rows in step order.
-template <int NB, int NW>
+template <int NB, int NW, typename T = double>
 struct PivotLds {
-  double row[2][NW][NB];
+  T row[2][NW][NB];
   double key[2][NW];
-  double dinv[2][NW];
+  T dinv[2][NW];
   int piv[NB];
 };
 
+// 1 / a in single precision: the hardware reciprocal and one Newton step
+__device__ __forceinline__ float recip(float a) {
+  float x = __builtin_amdgcn_rcpf(a);
+  return fmaf(x, fmaf(-a, x, 1.0f), x);
+}
+
 // One pivot step on column t of the panel held in v (see reg_panel).
 // Returns 0 or 1 + the failing step, uniformly.  RAW: see key_max.
-template <int NB, int R, int NT, bool RAW>
-__device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int m, int p0, int t,
-                                          int col, PivotLds<NB, NT / 64> &sh, int &mypiv) {
+// T: the element type of the rows (double, or float for the mixed forms'
+// working matrices); the keys are doubles in both cases (a float magnitude
+// converts exactly and leaves the low mantissa bits to the row number).
+template <int NB, int R, int NT, bool RAW, typename T>
+__device__ __forceinline__ int pivot_step(T (&v)[R][NB], int (&stp)[R], int m, int p0, int t,
+                                          int col, PivotLds<NB, NT / 64, T> &sh, int &mypiv) {
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int buf = t & 1;
-  double key = -1.0, sv = 1.0;   // this lane's best key and its signed pivot-column entry
+  double key = -1.0;   // this lane's best key and its signed pivot-column entry
+  T sv = 1;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int i = tid + q * NT;
     if (i < m && stp[q] < 0) {
-      const double kq = pivot_key(v[q][col], i);
+      const double kq = pivot_key((double)v[q][col], i);
       if (kq > key) {
         key = kq;
         sv = v[q][col];
@@ -160,7 +171,7 @@ __device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int
   }
   // every lane inverts its own candidate while the wave reduction runs;
   // the winner publishes its row and reciprocal
-  const double dl = recip(sv);
+  const T dl = recip(sv);
   const double wkey = wave_max<RAW>(key);
   if (wkey >= 0.0 && key == wkey) {
     const int i = key_row(key);
@@ -189,14 +200,14 @@ __device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int
   const int gw = (gi % NT) >> 6;
   if (tid == 0) sh.piv[t] = gi;
   if (tid == t) mypiv = gi;
-  const double *prow = sh.row[buf][gw];
-  const double d = sh.dinv[buf][gw];
+  const T *prow = sh.row[buf][gw];
+  const T d = sh.dinv[buf][gw];
   // every row is eliminated with one FMA per column, v - (f d) prow, then
   // the one lane holding the pivot row overwrites it with prow d (a branch
   // of one lane instead of a select on every row)
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const double fd = v[q][col] * d;
+    const T fd = v[q][col] * d;
 #pragma unroll
     for (int c = 0; c < NB; ++c) v[q][c] = c == col ? -fd : v[q][c] - fd * prow[c];
   }
@@ -221,25 +232,25 @@ __device__ __forceinline__ int pivot_step(double (&v)[R][NB], int (&stp)[R], int
 // the columns being back in order after NB rotations.  Called by all NT
 // threads.  Returns 0, or 1 + the step whose pivot is zero or not finite
 // (the same value in every thread).
-template <int NB, int R, int NT, bool UNR, bool RAW>
-__device__ __forceinline__ int reg_panel(double (&v)[R][NB], int (&stp)[R], int m, int p0, int w,
-                                         PivotLds<NB, NT / 64> &sh, int &mypiv) {
+template <int NB, int R, int NT, bool UNR, bool RAW, typename T>
+__device__ __forceinline__ int reg_panel(T (&v)[R][NB], int (&stp)[R], int m, int p0, int w,
+                                         PivotLds<NB, NT / 64, T> &sh, int &mypiv) {
   if constexpr (UNR) {
 #pragma unroll
     for (int t = 0; t < NB; ++t)
       if (t < w) {
-        const int f = pivot_step<NB, R, NT, RAW>(v, stp, m, p0, t, t, sh, mypiv);
+        const int f = pivot_step<NB, R, NT, RAW, T>(v, stp, m, p0, t, t, sh, mypiv);
         if (f) return f;
       }
   } else {
     for (int t = 0; t < NB; ++t) {
       if (t < w) {
-        const int f = pivot_step<NB, R, NT, RAW>(v, stp, m, p0, t, 0, sh, mypiv);
+        const int f = pivot_step<NB, R, NT, RAW, T>(v, stp, m, p0, t, 0, sh, mypiv);
         if (f) return f;
       }
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        const double h = v[q][0];
+        const T h = v[q][0];
 #pragma unroll
         for (int c = 0; c + 1 < NB; ++c) v[q][c] = v[q][c + 1];
         v[q][NB - 1] = h;
@@ -251,8 +262,34 @@ __device__ __forceinline__ int reg_panel(double (&v)[R][NB], int (&stp)[R], int 
 
 // ------------------------------------------------------------------ batched blocks
 typedef double dx4 __attribute__((ext_vector_type(4)));
+typedef float fx4 __attribute__((ext_vector_type(4)));
 constexpr int kPrefetch = 4;   // row tiles in flight per wave in the updates
 
+// The 16x16x4 matrix-core product of each element type.  Operand layouts are
+// the same (A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k); the output
+// tile differs: the FP64 instruction holds D[i][j] in lane j + 16 (i % 4),
+// register i / 4, the FP32 one in lane j + 16 (i / 4), register i % 4.
+template <typename T>
+struct Mfma16;
+template <>
+struct Mfma16<double> {
+  typedef dx4 acc;
+  static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int kq) { return r * 4 + kq; }
+};
+template <>
+struct Mfma16<float> {
+  typedef fx4 acc;
+  static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int kq) { return kq * 4 + r; }
+};
+
+// T: FP64 (the plain form) or FP32 (the mixed forms: the working matrix and
+// the matrix-core products in single precision, the pivot keys in double).
 // One workgroup of NT threads per block at a time (m <= NT R), looping
 // over the blocks the schedule gives it: sched[0..grid] are offsets into
 // the block list sched[grid + 1 ..] (see gj_schedule).  Per panel: factor in
@@ -266,8 +303,8 @@ constexpr int kPrefetch = 4;   // row tiles in flight per wave in the updates
 // a panel slice is loaded whole from its row base.  GPC: the update reads
 // the panel from the block's own panel columns (just written, in L2)
 // instead of an LDS copy, so NB = 32 needs no LDS of m (NB + 1) doubles.
-template <int NB, int R, int NT, bool UNR, bool GPC>
-__global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
+template <typename T, int NB, int R, int NT, bool UNR, bool GPC>
+__global__ __launch_bounds__(NT) void k_gj_batched(T *__restrict__ blocks,
                                                     const int64_t *__restrict__ boff,
                                                     const int *__restrict__ pm,
                                                     const int64_t *__restrict__ poff,
@@ -275,9 +312,12 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
                                                     int *__restrict__ used_all,
                                                     int *__restrict__ status,
                                                     const int *__restrict__ sched) {
+  typedef Mfma16<T> MM;
+  typedef typename MM::acc acc;
   constexpr int PS = NB + 1, KC = NB / 4;
-  extern __shared__ double PC[];
-  __shared__ PivotLds<NB, NT / 64> sh;
+  extern __shared__ __align__(16) unsigned char gj_dyn_lds[];
+  T *PC = reinterpret_cast<T *>(gj_dyn_lds);
+  __shared__ PivotLds<NB, NT / 64, T> sh;
   __shared__ short s_used[R * NT];   // step numbers < 1024, or -1
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int jl = lane & 15, kq = lane >> 4;
@@ -285,20 +325,20 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
   for (int t = sched[blockIdx.x]; t < sched[blockIdx.x + 1]; ++t) {
     const int k = list[t];
     const int m = pm[k];
-    double *A = blocks + boff[k];
+    T *A = blocks + boff[k];
     int *perm = perm_all + poff[k];
     for (int i = tid; i < m; i += NT) s_used[i] = -1;
     __syncthreads();
     int fail = 0;
     for (int p0 = 0; p0 < m; p0 += NB) {
       const int w = min(NB, m - p0);
-      double v[R][NB];
+      T v[R][NB];
       int stp[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const int i = tid + q * NT;
         stp[q] = i < m ? s_used[i] : kNoRow;
-        const double *row = A + min(i, m - 1) * m + p0;
+        const T *row = A + min(i, m - 1) * m + p0;
 #pragma unroll
         for (int c = 0; c < NB; ++c) v[q][c] = row[c];
       }
@@ -306,7 +346,7 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
       for (int q = 0; q < R; ++q)
 #pragma unroll
         for (int c = 0; c < NB; ++c)
-          if (c >= w) v[q][c] = 0.0;
+          if (c >= w) v[q][c] = 0;
       int mypiv = 0;   // unused here: the update reads the pivots from LDS
       fail = reg_panel<NB, R, NT, UNR, false>(v, stp, m, p0, w, sh, mypiv);
       if (fail) break;
@@ -332,57 +372,56 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
         const bool colok = q < mp;
         const int j = colok ? (q < p0 ? q : q + w) : 0;
         // X: clamped loads issued together, zeroed outside the panel
-        double bx[KC];
+        T bx[KC];
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) bx[kk] = A[sh.piv[min(kk * 4 + kq, w - 1)] * m + j];
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk)
-          if (!(colok && kk * 4 + kq < w)) bx[kk] = 0.0;
+          if (!(colok && kk * 4 + kq < w)) bx[kk] = 0;
         // every load unconditional at a clamped address (prefetches past the
         // last tile repeat it), so no load waits on a branch; the pivot rows
         // and the rows past m are zeroed where the tile is used
         auto load_tile = [&](int rt) {
-          dx4 c;
+          acc c;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) c[r] = A[min(rt * 16 + r * 4 + kq, m - 1) * m + j];
+          for (int r = 0; r < 4; ++r) c[r] = A[min(rt * 16 + MM::row(r, kq), m - 1) * m + j];
           return c;
         };
-        dx4 ring[kPrefetch];
+        acc ring[kPrefetch];
 #pragma unroll
         for (int u = 0; u < kPrefetch; ++u) ring[u] = load_tile(min(u, nrt - 1));
         for (int rt0 = 0; rt0 < nrt; rt0 += kPrefetch) {
 #pragma unroll
           for (int u = 0; u < kPrefetch; ++u) {
             const int rt = rt0 + u;
-            dx4 c = ring[u];
+            acc c = ring[u];
             ring[u] = load_tile(min(rt + kPrefetch, nrt - 1));
             if (rt < nrt) {
               int su[4];
-              double a[KC];
+              T a[KC];
               const int ia = rt * 16 + jl;
 #pragma unroll
-              for (int r = 0; r < 4; ++r) su[r] = s_used[min(rt * 16 + r * 4 + kq, m - 1)];
+              for (int r = 0; r < 4; ++r) su[r] = s_used[min(rt * 16 + MM::row(r, kq), m - 1)];
 #pragma unroll
               for (int kk = 0; kk < KC; ++kk) {
                 if constexpr (GPC) {
                   // clamped to the panel's last column, zeroed beyond it
-                  const double x = A[min(ia, m - 1) * m + p0 + min(kk * 4 + kq, w - 1)];
-                  a[kk] = kk * 4 + kq < w ? x : 0.0;
+                  const T x = A[min(ia, m - 1) * m + p0 + min(kk * 4 + kq, w - 1)];
+                  a[kk] = kk * 4 + kq < w ? x : (T)0;
                 } else {
                   a[kk] = PC[min(ia, m - 1) * PS + kk * 4 + kq];
                 }
               }
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                const int i = rt * 16 + r * 4 + kq;
-                if (!(colok && i < m && (su[r] < p0 || su[r] >= p0 + w))) c[r] = 0.0;
+                const int i = rt * 16 + MM::row(r, kq);
+                if (!(colok && i < m && (su[r] < p0 || su[r] >= p0 + w))) c[r] = 0;
               }
 #pragma unroll
-              for (int kk = 0; kk < KC; ++kk)
-                c = __builtin_amdgcn_mfma_f64_16x16x4f64(ia < m ? a[kk] : 0.0, bx[kk], c, 0, 0, 0);
+              for (int kk = 0; kk < KC; ++kk) c = MM::mma(ia < m ? a[kk] : (T)0, bx[kk], c);
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                const int i = rt * 16 + r * 4 + kq;
+                const int i = rt * 16 + MM::row(r, kq);
                 if (colok && i < m) A[i * m + j] = c[r];
               }
             }
@@ -404,7 +443,27 @@ __global__ __launch_bounds__(NT) void k_gj_batched(double *__restrict__ blocks,
   }
 }
 
-static size_t gj_batched_lds(int mmax, int nb) { return (size_t)mmax * (nb + 1) * sizeof(double); }
+static size_t gj_batched_lds(int mmax, int nb, size_t elem = sizeof(double)) {
+  return (size_t)mmax * (nb + 1) * elem;
+}
+
+// static LDS of a kernel instance, queried once per instance (-1: the query failed)
+template <typename T, int NB, int R, int NT, bool UNR = true>
+static int64_t gj_static_lds() {
+  static const int64_t v = [] {
+    hipFuncAttributes a;
+    return hipFuncGetAttributes(&a, (const void *)k_gj_batched<T, NB, R, NT, UNR, false>) == hipSuccess
+               ? (int64_t)a.sharedSizeBytes
+               : (int64_t)-1;
+  }();
+  return v;
+}
+// the LDS panel (m rows of NB + 1 elements) fits beside the static LDS
+template <typename T, int NB, int R, int NT, bool UNR = true>
+static bool gj_lds_fits(int mmax) {
+  const int64_t st = gj_static_lds<T, NB, R, NT, UNR>();
+  return mmax <= R * NT && st >= 0 && st + (int64_t)gj_batched_lds(mmax, NB, sizeof(T)) <= 160 * 1024;
+}
 
 bool gj_variant_ok(int variant, int mmax) {
   switch (variant) {
@@ -415,21 +474,24 @@ bool gj_variant_ok(int variant, int mmax) {
       return mmax <= 512 && gj_batched_lds(mmax, 32) <= 140 * 1024;
     case kGjWideG:    // panel read from the block itself: no LDS of m
       return mmax <= 1024;
-    case kGj24x512: {  // two rows per thread, the LDS panel next to the static LDS
-      // the kernel's static LDS, queried once (-1: the query failed)
-      static const int64_t static_lds = [] {
-        hipFuncAttributes a;
-        return hipFuncGetAttributes(&a, (const void *)k_gj_batched<24, 2, 512, true, false>) == hipSuccess
-                   ? (int64_t)a.sharedSizeBytes
-                   : (int64_t)-1;
-      }();
-      return mmax <= 1024 && static_lds >= 0 &&
-             static_lds + (int64_t)gj_batched_lds(mmax, 24) <= 160 * 1024;
-    }
+    case kGj24x512:   // two rows per thread, the LDS panel next to the static LDS
+      return gj_lds_fits<double, 24, 2, 512>(mmax);
+    case kGjF64x512:
+      return gj_lds_fits<float, 64, 1, 512, false>(mmax);
+    case kGjF32x512:
+      return gj_lds_fits<float, 32, 1, 512>(mmax);
+    case kGjF32x256:
+      return gj_lds_fits<float, 32, 2, 256>(mmax);
+    case kGjF32x512r2:
+      return gj_lds_fits<float, 32, 2, 512>(mmax);
+    case kGjF48x512r2:
+      return gj_lds_fits<float, 48, 2, 512, false>(mmax);
     default:
       return false;
   }
 }
+
+bool gj_variant_f32(int variant) { return variant >= kGjF64x512; }
 
 int gj_batched_grid(int npatch) {
   // as many workgroups as the fewest rounds over the compute units need:
@@ -469,21 +531,22 @@ std::vector<int> gj_schedule(const int *pm, int npatch, int grid) {
   return out;
 }
 
-template <int NB, int R, int NT, bool UNR, bool GPC = false>
-static void launch_gj_nbr(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
+template <int NB, int R, int NT, bool UNR, bool GPC = false, typename T>
+static void launch_gj_nbr(T *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
                           int *perm, int *used, int grid, const int *sched, int mmax, int *status,
-                          hipStream_t st) {
-  const size_t shm = GPC ? 0 : gj_batched_lds(mmax, NB);
+                          hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+  const size_t shm = GPC ? 0 : gj_batched_lds(mmax, NB, sizeof(T));
   if (shm)
-    (void)hipFuncSetAttribute((const void *)k_gj_batched<NB, R, NT, UNR, GPC>,
+    (void)hipFuncSetAttribute((const void *)k_gj_batched<T, NB, R, NT, UNR, GPC>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  k_gj_batched<NB, R, NT, UNR, GPC><<<grid, NT, shm, st>>>(blocks, boff, pm, poff, perm, used,
-                                                            status, sched);
+  // with events: recorded at the kernel's own start and end
+  hipExtLaunchKernelGGL(k_gj_batched<T, NB, R, NT, UNR, GPC>, dim3(grid), dim3(NT), shm, st, ev0, ev1, 0,
+                        blocks, boff, pm, poff, perm, used, status, sched);
 }
 
 void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
                        int *perm, int *used, int npatch, int mmax, int *status, int grid,
-                       const int *sched, hipStream_t st, int variant) {
+                       const int *sched, hipStream_t st, int variant, hipEvent_t ev0, hipEvent_t ev1) {
   if (npatch == 0) return;
   if (!gj_variant_ok(variant, mmax))
     variant = gj_variant_ok(kGj32x512, mmax)   ? kGj32x512
@@ -496,24 +559,61 @@ void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const
   // thread, the most that stays in registers): 1/2 (2/3) of the update
   // traffic of NB 16, the panel in LDS or read from the block.
   if (variant == kGj32x512)
-    launch_gj_nbr<32, 1, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st);
+    launch_gj_nbr<32, 1, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
   else if (variant == kGjWideG && small)
     launch_gj_nbr<32, 1, 512, true, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax,
-                                          status, st);
+                                          status, st, ev0, ev1);
   else if (variant == kGjWideG)
     launch_gj_nbr<24, 2, 512, true, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax,
-                                          status, st);
+                                          status, st, ev0, ev1);
   else if (variant == kGj24x512)
     launch_gj_nbr<24, 2, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status,
-                                    st);
+                                    st, ev0, ev1);
   else if (variant == kGj16x512 && small)
-    launch_gj_nbr<16, 1, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st);
+    launch_gj_nbr<16, 1, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
   else if (variant == kGj16x512)
-    launch_gj_nbr<16, 2, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st);
+    launch_gj_nbr<16, 2, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
   else if (small)
-    launch_gj_nbr<16, 2, 256, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st);
+    launch_gj_nbr<16, 2, 256, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
   else
-    launch_gj_nbr<16, 4, 256, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st);
+    launch_gj_nbr<16, 4, 256, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
+}
+
+// FP32 working matrices (the mixed forms): NB 64 on 512 threads (one row per
+// thread), NB 32 on 512 or on 256 threads (two rows per thread: two
+// workgroups fit a compute unit), NB 32 or 48 on 512 threads with two rows
+// per thread (blocks up to 1024 dofs); every variant keeps the panel in LDS.
+// An unsupported variant falls back to the first that fits of these.
+void launch_gj_batched_f32(float *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
+                           int *perm, int *used, int npatch, int mmax, int *status, int grid,
+                           const int *sched, hipStream_t st, int variant, hipEvent_t ev0,
+                           hipEvent_t ev1) {
+  if (npatch == 0) return;
+  if (!gj_variant_f32(variant) || !gj_variant_ok(variant, mmax)) {
+    variant = kGjF32x512r2;
+    for (int v : {kGjF64x512, kGjF32x512, kGjF48x512r2, kGjF32x512r2})
+      if (gj_variant_ok(v, mmax)) {
+        variant = v;
+        break;
+      }
+  }
+  switch (variant) {
+    case kGjF64x512:
+      launch_gj_nbr<64, 1, 512, false>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
+      break;
+    case kGjF32x512:
+      launch_gj_nbr<32, 1, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
+      break;
+    case kGjF32x256:
+      launch_gj_nbr<32, 2, 256, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
+      break;
+    case kGjF48x512r2:
+      launch_gj_nbr<48, 2, 512, false>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
+      break;
+    default:
+      launch_gj_nbr<32, 2, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
+      break;
+  }
 }
 
 // ------------------------------------------------------------------ coarsest operator

@@ -54,6 +54,19 @@ struct Level {
   int64_t ext_nslots = 0;
   int *d_ext_src = nullptr, *d_ext_dst = nullptr;
   int64_t *d_ext_slot_off = nullptr;
+  // solid blocks apart (solid_precision / refine_sweeps): owned rows in FP32
+  // (ntask_s tasks, offsets woff into Ws), or full FP32 inverses (nftask
+  // packing tasks over all rows, offsets woff_full into Wfull) applied with
+  // refinement sweeps; nref refined blocks with local CSR rows of B_k
+  int ntask_s = 0, nref = 0, nftask = 0;
+  int64_t woff_solid = 0, wfull_total = 0, full_rows = 0;
+  int *d_task_patch_s = nullptr, *d_task_row0_s = nullptr, *d_po_full = nullptr,
+      *d_full_off = nullptr, *d_full_local = nullptr, *d_ftask_patch = nullptr, *d_ftask_row0 = nullptr,
+      *d_ref_patch = nullptr, *d_ref_rptr_off = nullptr, *d_ref_rptr = nullptr, *d_ref_col = nullptr,
+      *d_ref_src = nullptr;
+  int64_t *d_woff_full = nullptr;
+  float *Ws = nullptr, *Wfull32 = nullptr, *Wscale_full = nullptr;
+  uint16_t *Wfull16 = nullptr;
   double *W64 = nullptr;
   float *W32 = nullptr;
   uint16_t *W16 = nullptr;
@@ -140,8 +153,8 @@ struct MG {
   hipGraphExec_t coarse_graph = nullptr;   // the coarsest inversion's launch chain, replayed per refactor
   // event timing of the finest-level Schwarz kernel
   bool prof_on = false;
-  size_t prof_used = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+  size_t prof_used = 0, prof_gj_used = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev, prof_gj_ev;   // Schwarz (finest), batched inversion
 };
 
 extern thread_local std::string g_last_error;

@@ -35,9 +35,12 @@ void launch_extract_map(const CsrView<double> &J, const int *pm, const int64_t *
                         const int *dof, const int64_t *boff, int64_t total_rows,
                         const int *row_patch, const int *row_local, const int64_t *slot_off,
                         int *src, int *dst, hipStream_t st);
-// B_k = J[I_k, I_k] through the map (blocks zero-filled beforehand)
+// B_k = J[I_k, I_k] through the map (blocks zero-filled beforehand), in
+// FP64 or rounded to FP32
 void launch_extract(const double *val, int64_t nslots, const int *src, const int *dst,
                     double *blocks, hipStream_t st);
+void launch_extract(const double *val, int64_t nslots, const int *src, const int *dst,
+                    float *blocks, hipStream_t st);
 // Gauss-Jordan inverse of every block, one workgroup per block (m <= 1024),
 // rows never exchanged: Binv[i][c] = S[perm[i]][used[c]] with S left in the
 // block and perm/used at poff[k]; status[k] = 0 ok, else 1 + failing step
@@ -48,16 +51,27 @@ void launch_extract(const double *val, int64_t nslots, const int *src, const int
 // (where m 25 doubles fit beside the static LDS, m <= ~790).  An
 // unsupported or zero variant falls back to the first that fits of NB 32,
 // NB 24 (both with the LDS panel) and NB 16 on 256 threads
-enum GjVariant { kGjAuto = 0, kGj16x256 = 1, kGj16x512 = 2, kGj32x512 = 3, kGjWideG = 4, kGj24x512 = 5 };
+enum GjVariant { kGjAuto = 0, kGj16x256 = 1, kGj16x512 = 2, kGj32x512 = 3, kGjWideG = 4, kGj24x512 = 5,
+                 // FP32 working matrices (mixed forms): panel width x threads (x rows per thread)
+                 kGjF64x512 = 11, kGjF32x512 = 12, kGjF32x256 = 13, kGjF32x512r2 = 14, kGjF48x512r2 = 15 };
 bool gj_variant_ok(int variant, int mmax);
+bool gj_variant_f32(int variant);
 // workgroups of the batched inversion for npatch blocks (the fewest rounds
 // over the compute units), and the host-built schedule: grid + 1 offsets
 // into the block list that follows them (grid + 1 + npatch ints)
 int gj_batched_grid(int npatch);
 std::vector<int> gj_schedule(const int *pm, int npatch, int grid);
+// ev0/ev1 (optional): events recorded at the kernel's own start and end
 void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
                        int *perm, int *used, int npatch, int mmax, int *status, int grid,
-                       const int *sched, hipStream_t st, int variant = kGjAuto);
+                       const int *sched, hipStream_t st, int variant = kGjAuto,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// the same elimination on FP32 blocks (the working matrices of the mixed
+// forms), on the FP32 matrix cores
+void launch_gj_batched_f32(float *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
+                           int *perm, int *used, int npatch, int mmax, int *status, int grid,
+                           const int *sched, hipStream_t st, int variant = kGjAuto,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // The coarsest operator's dofs split into D, whose row and column hold only
 // the diagonal entry (Dirichlet rows of a symmetrically eliminated
 // operator), and the free rest F: the operator is diag(a_D) + A_FF up to
@@ -79,18 +93,22 @@ void gj_coarse(double *A, int nf, int64_t ld, const CoarseSplit &cs, double *C0,
                int *iwork, hipStream_t st);
 // Owned rows of Binv_k, column-major per (patch, 64 owned rows) task: task
 // (k, r0) with nr = min(64, o_k - r0) rows holds entry (c, r) at
-// W[woff_k + r0 m_k + c nr + r - r0]; optional FP32/16-bit copies
-void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm, const int *po,
+// W[woff_k + r0 m_k + c nr + r - r0]; optional FP32/16-bit copies; the
+// inverted blocks in FP64 or FP32 (TB)
+template <typename TB>
+void launch_pack_owned(const TB *blocks, const int64_t *boff, const int *pm, const int *po,
                        const int64_t *woff, const int *own_off, const int *own_local,
                        const int *task_patch, const int *task_row0, int ntask, double *W64,
                        float *W32, uint16_t *W16, int w16_kind, float *wscale,
                        const int64_t *pdof_off, const float *cscale, const int *perm,
                        hipStream_t st);
 // 16-bit storage: per-column scales of the owned rows of every block inverse
-void launch_colscale(const double *blocks, const int64_t *boff, const int *pm, const int *po,
+template <typename TB>
+void launch_colscale(const TB *blocks, const int64_t *boff, const int *pm, const int *po,
                      const int *own_off, const int *own_local, const int64_t *pdof_off,
                      const int *task_patch, const int *task_row0, int ntask, int64_t total_cols,
-                     float *cscale, const int *perm, hipStream_t st);
+                     float *cscale, const int *perm, hipStream_t st, bool first = true,
+                     bool last = true);
 
 // ---- smoother (a5): e[out] += omega * W_k s[I_k] for every owned row
 //      (16-bit: W_k = diag(rs) W16 diag(cs), two-sided scaling)
@@ -117,6 +135,26 @@ void launch_ras_f32(const RasView &v, const float *W, const float *s, float *e, 
 void launch_ras_16(const RasView &v, const uint16_t *W, int w16_kind, const float *wscale,
                    const float *s, float *e, float omega, bool finest, bool add, hipStream_t st,
                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// ---- refined local solves of the solid blocks (mixed forms): per block k
+// (one workgroup), g = s[I_k], y = W~ g, then `sweeps` times
+// y += W~ (g - B_k y) with B_k = J[I_k, I_k] in FP32 (local CSR rows, values
+// read from jval at the J entry index src), and e[owned] (+)= omega y.
+// W~: every row of the inverse (FP32, or 16-bit with row scales rscale at
+// full_off[k] and column scales cscale at pdof_off[k]), in the packing's task
+// layout (rows in chunks of 64, column-major inside a chunk) at woff_full[k].
+// With add false the dofs no patch owns are also cleared.
+struct RefineView {
+  int nref, w16_kind;
+  const int *ref_patch, *pm, *po, *dof, *out_off, *own_local, *out_idx, *full_off;
+  const int64_t *pdof_off, *woff_full;
+  const int *rptr_off, *rptr, *col, *src;
+  const float *jval, *rscale, *cscale;
+  const int *unowned;
+  int nunowned;
+};
+void launch_ras_refine(const RefineView &v, const float *W32, const uint16_t *W16, const float *s, float *e,
+                       float omega, bool add, int sweeps, hipStream_t st);
 
 // ---- coarsest solve (a7): y = W x, W row-major n x n FP64
 void launch_dense_gemv(const double *W, int n, const double *x, double *y, hipStream_t st);

@@ -213,19 +213,26 @@ void launch_extract_map(const CsrView<double> &J, const int *pm, const int64_t *
                                                       slot_off, src, dst);
 }
 
-// B_k = J[I_k, I_k]: one thread per slot of the map
+// B_k = J[I_k, I_k]: one thread per slot of the map (FP32 blocks: the values
+// rounded to single precision, the working matrices of the mixed forms)
+template <typename TB>
 __global__ __launch_bounds__(256) void k_extract(int64_t nslots, const int *__restrict__ src,
                                                  const int *__restrict__ dst,
                                                  const double *__restrict__ val,
-                                                 double *__restrict__ blocks) {
+                                                 TB *__restrict__ blocks) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= nslots) return;
   const int q = dst[e];
-  if (q >= 0) blocks[q] = val[src[e]];
+  if (q >= 0) blocks[q] = (TB)val[src[e]];
 }
 
 void launch_extract(const double *val, int64_t nslots, const int *src, const int *dst,
                     double *blocks, hipStream_t st) {
+  if (nslots == 0) return;
+  k_extract<<<(unsigned)((nslots + 255) / 256), 256, 0, st>>>(nslots, src, dst, val, blocks);
+}
+void launch_extract(const double *val, int64_t nslots, const int *src, const int *dst,
+                    float *blocks, hipStream_t st) {
   if (nslots == 0) return;
   k_extract<<<(unsigned)((nslots + 255) / 256), 256, 0, st>>>(nslots, src, dst, val, blocks);
 }
@@ -256,7 +263,8 @@ __device__ inline float from_fp16(uint16_t u) {
 // One workgroup per (patch, 64 owned rows): the rows are read contiguously,
 // the maxima meet in LDS (float bit patterns order like the non-negative
 // values) and then in cscale.
-__global__ __launch_bounds__(256) void k_colscale(const double *__restrict__ blocks,
+template <typename TB>
+__global__ __launch_bounds__(256) void k_colscale(const TB *__restrict__ blocks,
                                                   const int64_t *__restrict__ boff,
                                                   const int *__restrict__ pm,
                                                   const int *__restrict__ po,
@@ -270,13 +278,13 @@ __global__ __launch_bounds__(256) void k_colscale(const double *__restrict__ blo
   const int k = task_patch[blockIdx.x], r0 = task_row0[blockIdx.x];
   const int m = pm[k], nr = min(64, po[k] - r0);
   const int *pk = perm + pdof_off[k];
-  const double *B = blocks + boff[k];
+  const TB *B = blocks + boff[k];
   for (int c = threadIdx.x; c < m; c += blockDim.x) cmax[c] = 0u;
   __syncthreads();
   for (int r = 0; r < nr; ++r) {
-    const double *row = B + (int64_t)pk[own_local[own_off[k] + r0 + r]] * m;
+    const TB *row = B + (int64_t)pk[own_local[own_off[k] + r0 + r]] * m;
     for (int p = threadIdx.x; p < m; p += blockDim.x)
-      atomicMax(&cmax[pk[p]], __float_as_uint((float)fabs(row[p])));
+      atomicMax(&cmax[pk[p]], __float_as_uint((float)fabs((double)row[p])));
   }
   __syncthreads();
   for (int c = threadIdx.x; c < m; c += blockDim.x)
@@ -287,15 +295,16 @@ __global__ void k_scale_fix(float *cs, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n && !(cs[i] > 0.0f)) cs[i] = 1.0f;
 }
-void launch_colscale(const double *blocks, const int64_t *boff, const int *pm, const int *po,
+template <typename TB>
+void launch_colscale(const TB *blocks, const int64_t *boff, const int *pm, const int *po,
                      const int *own_off, const int *own_local, const int64_t *pdof_off,
                      const int *task_patch, const int *task_row0, int ntask, int64_t total_cols,
-                     float *cscale, const int *perm, hipStream_t st) {
-  if (ntask == 0) return;
-  launch_fill_f32(cscale, total_cols, 0.0f, st);
-  k_colscale<<<ntask, 256, 0, st>>>(blocks, boff, pm, po, own_off, own_local, pdof_off, task_patch,
-                                    task_row0, cscale, perm);
-  k_scale_fix<<<cdiv(total_cols, 256), 256, 0, st>>>(cscale, total_cols);
+                     float *cscale, const int *perm, hipStream_t st, bool first, bool last) {
+  if (first) launch_fill_f32(cscale, total_cols, 0.0f, st);
+  if (ntask)
+    k_colscale<<<ntask, 256, 0, st>>>(blocks, boff, pm, po, own_off, own_local, pdof_off, task_patch,
+                                      task_row0, cscale, perm);
+  if (last) k_scale_fix<<<cdiv(total_cols, 256), 256, 0, st>>>(cscale, total_cols);
 }
 
 // Owned rows of Binv_k in task-contiguous column-major order: the rows of
@@ -308,7 +317,8 @@ void launch_colscale(const double *blocks, const int64_t *boff, const int *pm, c
 // lanes, so both the reads and the stores are contiguous.  16-bit storage:
 // row r is stored divided by cs[c] and by its row scale, the largest
 // |Binv[r][c]| / cs[c] of the row.
-__global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ blocks,
+template <typename TB>
+__global__ __launch_bounds__(256) void k_pack_owned(const TB *__restrict__ blocks,
                                                     const int64_t *__restrict__ boff,
                                                     const int *__restrict__ pm,
                                                     const int *__restrict__ po,
@@ -327,7 +337,7 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
   const int k = task_patch[blockIdx.x], r0 = task_row0[blockIdx.x];
   const int m = pm[k], o = po[k], nr = min(64, o - r0);
   const int *pk = perm + pdof_off[k];
-  const double *B = blocks + boff[k];
+  const TB *B = blocks + boff[k];
   const float *cs = W16 ? cscale + pdof_off[k] : nullptr;
   const int tid = threadIdx.x;
   if (tid < 64) rowoff[tid] = tid < nr ? (int64_t)pk[own_local[own_off[k] + r0 + tid]] * m : 0;
@@ -337,7 +347,7 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
     double mx = 0.0;
     if (r < nr) {
 #pragma unroll 8
-      for (int p = sub; p < m; p += 4) mx = fmax(mx, fabs(B[rowoff[r] + p]) / (double)cs[pk[p]]);
+      for (int p = sub; p < m; p += 4) mx = fmax(mx, fabs((double)B[rowoff[r] + p]) / (double)cs[pk[p]]);
     }
     mx = fmax(mx, __shfl_xor(mx, 1, 4));
     mx = fmax(mx, __shfl_xor(mx, 2, 4));
@@ -356,7 +366,7 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int idx = tid + 256 * u;
-      vals[u] = B[rowoff[min(idx >> 6, nr - 1)] + min(q0 + (idx & 63), m - 1)];
+      vals[u] = (double)B[rowoff[min(idx >> 6, nr - 1)] + min(q0 + (idx & 63), m - 1)];
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -381,7 +391,8 @@ __global__ __launch_bounds__(256) void k_pack_owned(const double *__restrict__ b
     __syncthreads();
   }
 }
-void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm, const int *po,
+template <typename TB>
+void launch_pack_owned(const TB *blocks, const int64_t *boff, const int *pm, const int *po,
                        const int64_t *woff, const int *own_off, const int *own_local,
                        const int *task_patch, const int *task_row0, int ntask, double *W64,
                        float *W32, uint16_t *W16, int w16_kind, float *wscale,
@@ -392,6 +403,17 @@ void launch_pack_owned(const double *blocks, const int64_t *boff, const int *pm,
                                       task_row0, W64, W32, W16, w16_kind, wscale, pdof_off, cscale,
                                       perm);
 }
+#define FSI_PACK_INST(TB)                                                                            \
+  template void launch_colscale<TB>(const TB *, const int64_t *, const int *, const int *, const int *, \
+                                    const int *, const int64_t *, const int *, const int *, int,       \
+                                    int64_t, float *, const int *, hipStream_t, bool, bool);           \
+  template void launch_pack_owned<TB>(const TB *, const int64_t *, const int *, const int *,           \
+                                      const int64_t *, const int *, const int *, const int *,          \
+                                      const int *, int, double *, float *, uint16_t *, int, float *,   \
+                                      const int64_t *, const float *, const int *, hipStream_t);
+FSI_PACK_INST(double)
+FSI_PACK_INST(float)
+#undef FSI_PACK_INST
 
 // ------------------------------------------------------------------ restricted Schwarz
 // One workgroup per (patch, 64 owned rows).  The patch's residual entries
@@ -480,6 +502,83 @@ __global__ __launch_bounds__(64 * NWV) void k_ras(RasView v, const WT *__restric
     const VT upd = (VT)(omega * acc);
     e[g] = add ? e[g] + upd : upd;
   }
+}
+
+// Refined local solve of one solid block per workgroup (see RefineView).
+// Thread t handles rows t, t + 512; within a 64-row chunk consecutive lanes
+// read consecutive rows of a column, so every column step is a coalesced
+// load.  16-bit storage: W~[r][c] = rs[r] w[r][c] cs[c]; the vector is
+// multiplied by cs as it enters LDS and each row's sum by rs[r].
+template <typename WT, bool IS16>
+__device__ __forceinline__ float full_row_dot(const WT *__restrict__ W, int m, int r, const float *xs,
+                                              int kind) {
+  const int r0 = r & ~63, nr = min(64, m - r0);
+  const WT *w = W + (int64_t)r0 * m + (r - r0);
+  float a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int c = 0;
+  for (; c + 8 <= m; c += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += wload<WT, float, IS16>(w, (int64_t)(c + u) * nr, kind) * xs[c + u];
+  }
+  for (int u = 0; c + u < m; ++u) a[0] += wload<WT, float, IS16>(w, (int64_t)(c + u) * nr, kind) * xs[c + u];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+template <typename WT, bool IS16>
+__global__ __launch_bounds__(512) void k_ras_refine(RefineView v, const WT *__restrict__ Wfull,
+                                                    const float *__restrict__ s, float *__restrict__ e,
+                                                    float omega, int add, int sweeps) {
+  __shared__ float g[kMaxPatch], x[kMaxPatch], y[kMaxPatch];
+  const int k = v.ref_patch[blockIdx.x];
+  const int m = v.pm[k];
+  const int *d = v.dof + v.pdof_off[k];
+  const WT *W = Wfull + v.woff_full[k];
+  const int *rp = v.rptr + v.rptr_off[k];
+  const float *cs = IS16 ? v.cscale + v.pdof_off[k] : nullptr;
+  const float *rs = IS16 ? v.rscale + v.full_off[k] : nullptr;
+  for (int c = threadIdx.x; c < m; c += 512) {
+    g[c] = s[d[c]];
+    x[c] = IS16 ? g[c] * cs[c] : g[c];
+  }
+  if (!add)
+    for (int i = blockIdx.x * 512 + threadIdx.x; i < v.nunowned; i += gridDim.x * 512) e[v.unowned[i]] = 0.0f;
+  __syncthreads();
+  for (int r = threadIdx.x; r < m; r += 512) {
+    const float t = full_row_dot<WT, IS16>(W, m, r, x, v.w16_kind);
+    y[r] = IS16 ? t * rs[r] : t;
+  }
+  __syncthreads();
+  for (int sw = 0; sw < sweeps; ++sw) {
+    // the block residual g - B_k y in FP32, scaled like g for the product
+    for (int i = threadIdx.x; i < m; i += 512) {
+      float acc = g[i];
+      for (int q = rp[i]; q < rp[i + 1]; ++q) acc -= v.jval[v.src[q]] * y[v.col[q]];
+      x[i] = IS16 ? acc * cs[i] : acc;
+    }
+    __syncthreads();
+    float upd[2] = {0.0f, 0.0f};
+    for (int r = threadIdx.x, u = 0; r < m; r += 512, ++u) {
+      const float t = full_row_dot<WT, IS16>(W, m, r, x, v.w16_kind);
+      upd[u] = IS16 ? t * rs[r] : t;
+    }
+    __syncthreads();   // every row's update was computed from the same y
+    for (int r = threadIdx.x, u = 0; r < m; r += 512, ++u) y[r] += upd[u];
+    __syncthreads();
+  }
+  const int o = v.po[k];
+  for (int q = threadIdx.x; q < o; q += 512) {
+    const int i = v.own_local[v.out_off[k] + q];
+    const int gd = v.out_idx[v.out_off[k] + q];
+    const float u = omega * y[i];
+    e[gd] = add ? e[gd] + u : u;
+  }
+}
+void launch_ras_refine(const RefineView &v, const float *W32, const uint16_t *W16, const float *s, float *e,
+                       float omega, bool add, int sweeps, hipStream_t st) {
+  if (v.nref == 0) return;
+  if (W16)
+    k_ras_refine<uint16_t, true><<<v.nref, 512, 0, st>>>(v, W16, s, e, omega, (int)add, sweeps);
+  else
+    k_ras_refine<float, false><<<v.nref, 512, 0, st>>>(v, W32, s, e, omega, (int)add, sweeps);
 }
 
 // ev0/ev1 (optional, finest level): timing events recorded at the kernel's

@@ -11,6 +11,7 @@
 #include <functional>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 namespace fsi {
@@ -270,6 +271,12 @@ static void upload_csr(const fsi_csr &A, DevCsr &D, bool want32, DevList &own, h
 }
 
 // ------------------------------------------------------------------ patch layout
+// the solid blocks get their own storage (FP32 owned rows, or full FP32
+// inverses with refinement sweeps) in a mixed hierarchy whose options ask for it
+static bool solid_split(const fsi_mg_opts &o) {
+  return o.precision != FSI_PREC_FP64 &&
+         ((o.solid_precision != -1 && o.solid_precision != o.precision) || o.refine_sweeps > 0);
+}
 static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J, MG &mg,
                                hipStream_t st) {
   L.npatch = P.npatch;
@@ -282,10 +289,21 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
   std::vector<int> pm(np), po(np), out_off(np + 1, 0), own_local, out_idx, task_patch, task_row0;
   std::vector<int64_t> pdof_off(np), woff(np + 1, 0), boff(np + 1, 0);
   std::vector<int> row_patch, row_local;
+  // solid blocks (kind 1) apart when the options give them their own
+  // storage: their owned rows in FP32 (task list _s, offsets into Ws), or,
+  // with refinement sweeps, their whole FP32 inverses (task list over all
+  // rows, offsets into Wfull) and their sparse block B_k
+  const bool split = solid_split(mg.opts);
+  const bool refine = split && mg.opts.refine_sweeps > 0;
+  std::vector<int> task_patch_s, task_row0_s, po_full(np, 0), full_off(np + 1, 0), full_local, ftask_patch,
+      ftask_row0, ref_patch;
+  std::vector<int64_t> woff_full(np, 0);
+  int64_t wmain = 0, wsolid = 0, wfull = 0;
   L.mmax = 0;
   L.sum_m = L.sum_m2 = L.sum_om = 0;
   for (int k = 0; k < np; ++k) {
     const int64_t a = P.ptr[k], b = P.ptr[k + 1];
+    const bool solid = split && L.h_kind[k] == 1;
     pm[k] = (int)(b - a);
     pdof_off[k] = a;
     int o = 0;
@@ -297,21 +315,39 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
       }
     po[k] = o;
     out_off[k + 1] = out_off[k] + o;
-    woff[k + 1] = woff[k] + (int64_t)o * pm[k];
+    // woff[k]: offset of the patch's owned rows in its class's storage
+    int64_t &wcls = solid ? wsolid : wmain;
+    woff[k] = wcls;
+    wcls += (int64_t)o * pm[k];
     boff[k + 1] = boff[k] + (int64_t)pm[k] * pm[k];
     for (int i = 0; i < pm[k]; ++i) {
       row_patch.push_back(k);
       row_local.push_back(i);
     }
-    for (int r0 = 0; r0 < o; r0 += 64) {
-      task_patch.push_back(k);
-      task_row0.push_back(r0);
+    if (refine && solid) {
+      ref_patch.push_back(k);
+      po_full[k] = pm[k];
+      woff_full[k] = wfull;
+      wfull += (int64_t)pm[k] * pm[k];
+      for (int i = 0; i < pm[k]; ++i) full_local.push_back(i);
+      full_off[k + 1] = full_off[k] + pm[k];
+      for (int r0 = 0; r0 < pm[k]; r0 += 64) {
+        ftask_patch.push_back(k);
+        ftask_row0.push_back(r0);
+      }
+    } else {
+      full_off[k + 1] = full_off[k];
+      for (int r0 = 0; r0 < o; r0 += 64) {
+        (solid ? task_patch_s : task_patch).push_back(k);
+        (solid ? task_row0_s : task_row0).push_back(r0);
+      }
     }
     L.mmax = std::max(L.mmax, pm[k]);
     L.sum_m += pm[k];
     L.sum_m2 += (int64_t)pm[k] * pm[k];
     L.sum_om += (int64_t)o * pm[k];
   }
+  woff[np] = wmain;
   L.total_owned = out_off[np];
   std::vector<char> is_owned(L.n, 0);
   for (int d : out_idx) is_owned[d] = 1;
@@ -336,8 +372,51 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
   L.d_row_local = dupload(row_local.data(), (int64_t)row_local.size(), own, st);
   L.d_unowned = dupload(unowned.data(), (int64_t)unowned.size(), own, st);
   L.boff_total = boff[np];
-  L.woff_total = woff[np];
+  L.woff_total = wmain;
+  L.woff_solid = wsolid;
   L.h_boff = boff;
+  L.ntask_s = (int)task_patch_s.size();
+  L.d_task_patch_s = dupload(task_patch_s.data(), (int64_t)task_patch_s.size(), own, st);
+  L.d_task_row0_s = dupload(task_row0_s.data(), (int64_t)task_row0_s.size(), own, st);
+  if (refine && !ref_patch.empty()) {
+    // full inverses (all rows, the packing's task layout) and each refined
+    // block's rows of B_k = J[I_k, I_k] as local CSR with the J entry index of
+    // every value (the values follow the operator through refactors)
+    L.nref = (int)ref_patch.size();
+    L.wfull_total = wfull;
+    L.full_rows = full_off[np];
+    L.nftask = (int)ftask_patch.size();
+    L.d_po_full = dupload(po_full.data(), np, own, st);
+    L.d_woff_full = dupload(woff_full.data(), np, own, st);
+    L.d_full_off = dupload(full_off.data(), np + 1, own, st);
+    L.d_full_local = dupload(full_local.data(), (int64_t)full_local.size(), own, st);
+    L.d_ftask_patch = dupload(ftask_patch.data(), (int64_t)ftask_patch.size(), own, st);
+    L.d_ftask_row0 = dupload(ftask_row0.data(), (int64_t)ftask_row0.size(), own, st);
+    L.d_ref_patch = dupload(ref_patch.data(), (int64_t)ref_patch.size(), own, st);
+    std::vector<int> rptr_off(np, 0), rptr, rcol, rsrc;
+    for (int k : ref_patch) {
+      rptr_off[k] = (int)rptr.size();
+      const int32_t *I = P.dof + P.ptr[k];
+      const int m = pm[k];
+      rptr.push_back((int)rcol.size());
+      for (int i = 0; i < m; ++i) {
+        const int g = I[i];
+        for (int64_t q = J.rowptr[g]; q < J.rowptr[g + 1]; ++q) {
+          const int32_t c = J.colind[q];
+          const int32_t *f = std::lower_bound(I, I + m, c);
+          if (f != I + m && *f == c) {
+            rcol.push_back((int)(f - I));
+            rsrc.push_back((int)q);
+          }
+        }
+        rptr.push_back((int)rcol.size());
+      }
+    }
+    L.d_ref_rptr_off = dupload(rptr_off.data(), np, own, st);
+    L.d_ref_rptr = dupload(rptr.data(), (int64_t)rptr.size(), own, st);
+    L.d_ref_col = dupload(rcol.data(), (int64_t)rcol.size(), own, st);
+    L.d_ref_src = dupload(rsrc.data(), (int64_t)rsrc.size(), own, st);
+  }
   // extraction map: one slot per CSR entry of every block row
   if (L.boff_total >= ((int64_t)1 << 31))
     throw Error(FSI_E_INVALID, "the blocks of one level exceed 2^31 entries");
@@ -353,6 +432,41 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
   launch_extract_map(L.J.v64(), L.d_pm, L.d_pdof_off, L.d_dof, L.d_boff, (int64_t)row_patch.size(),
                      L.d_row_patch, L.d_row_local, L.d_ext_slot_off, L.d_ext_src, L.d_ext_dst, st);
   hip_check(hipGetLastError(), "extraction map");
+}
+
+// the solid blocks' FP32 owned-row launch (the main view's arrays, the solid task list)
+static RasView ras_view_solid(const Level &L) {
+  RasView v = ras_view(L);
+  v.ntask = L.ntask_s;
+  v.task_patch = L.d_task_patch_s;
+  v.task_row0 = L.d_task_row0_s;
+  v.cscale = nullptr;
+  return v;
+}
+static RefineView refine_view(const Level &L) {
+  RefineView v;
+  v.nref = L.nref;
+  v.ref_patch = L.d_ref_patch;
+  v.pm = L.d_pm;
+  v.po = L.d_po;
+  v.pdof_off = L.d_pdof_off;
+  v.dof = L.d_dof;
+  v.woff_full = L.d_woff_full;
+  v.out_off = L.d_out_off;
+  v.own_local = L.d_own_local;
+  v.out_idx = L.d_out_idx;
+  v.rptr_off = L.d_ref_rptr_off;
+  v.rptr = L.d_ref_rptr;
+  v.col = L.d_ref_col;
+  v.src = L.d_ref_src;
+  v.jval = L.J.val32;
+  v.unowned = L.d_unowned;
+  v.nunowned = L.n_unowned;
+  v.w16_kind = L.w16_kind;
+  v.full_off = L.d_full_off;
+  v.rscale = L.Wscale_full;
+  v.cscale = L.Cscale;
+  return v;
 }
 
 RasView ras_view(const Level &L) {
@@ -379,8 +493,8 @@ static void free_list(DevList &owned) {
 
 // owned rows of every block inverse in the storage precision of the level
 // (the inverted blocks of level L sit at mg.blk_scratch + L.blk_base)
-static void pack_level(MG &mg, Level &L, hipStream_t st) {
-  const double *B = mg.blk_scratch + L.blk_base;
+template <typename TB>
+static void pack_level_t(MG &mg, Level &L, const TB *B, hipStream_t st) {
   const int prec = mg.opts.precision;
   if (prec == FSI_PREC_FP64) {
     if (!L.W64) L.W64 = dalloc<double>(L.woff_total, mg.owned);
@@ -393,16 +507,51 @@ static void pack_level(MG &mg, Level &L, hipStream_t st) {
       L.Cscale = dalloc<float>(L.sum_m, mg.owned);
     }
     L.w16_kind = prec == FSI_PREC_MIXED_BF16 ? 1 : 2;
+    // column scales of the owned rows, and of every row of the refined
+    // blocks when they are kept in 16 bits (one scale array, disjoint columns)
+    const bool full16 = L.nftask && mg.opts.solid_precision != FSI_PREC_MIXED_FP32;
     launch_colscale(B, L.d_boff, L.d_pm, L.d_po, L.d_out_off, L.d_own_local, L.d_pdof_off,
                     L.d_task_patch, L.d_task_row0, L.ntask, L.sum_m, L.Cscale, mg.gj_perm + L.pm_base,
-                    st);
+                    st, true, !full16);
+    if (full16)
+      launch_colscale(B, L.d_boff, L.d_pm, L.d_po_full, L.d_full_off, L.d_full_local, L.d_pdof_off,
+                      L.d_ftask_patch, L.d_ftask_row0, L.nftask, L.sum_m, L.Cscale,
+                      mg.gj_perm + L.pm_base, st, false, true);
   }
   launch_pack_owned(B, L.d_boff, L.d_pm, L.d_po, L.d_woff, L.d_out_off, L.d_own_local,
                     L.d_task_patch, L.d_task_row0, L.ntask, L.W64, L.W32, L.W16, L.w16_kind,
                     L.Wscale, L.d_pdof_off, L.Cscale, mg.gj_perm + L.pm_base, st);
+  if (L.ntask_s) {   // solid blocks' owned rows in FP32
+    if (!L.Ws) L.Ws = dalloc<float>(L.woff_solid, mg.owned);
+    launch_pack_owned(B, L.d_boff, L.d_pm, L.d_po, L.d_woff, L.d_out_off, L.d_own_local,
+                      L.d_task_patch_s, L.d_task_row0_s, L.ntask_s, (double *)nullptr, L.Ws,
+                      (uint16_t *)nullptr, 0, (float *)nullptr, L.d_pdof_off, (const float *)nullptr,
+                      mg.gj_perm + L.pm_base, st);
+  }
+  if (L.nftask) {    // refined solid blocks: every row of the inverse, FP32 or 16-bit
+    const bool full16 = prec != FSI_PREC_MIXED_FP32 && mg.opts.solid_precision != FSI_PREC_MIXED_FP32;
+    if (full16) {
+      if (!L.Wfull16) {
+        L.Wfull16 = dalloc<uint16_t>(L.wfull_total, mg.owned);
+        L.Wscale_full = dalloc<float>(L.full_rows, mg.owned);
+      }
+    } else if (!L.Wfull32) {
+      L.Wfull32 = dalloc<float>(L.wfull_total, mg.owned);
+    }
+    launch_pack_owned(B, L.d_boff, L.d_pm, L.d_po_full, L.d_woff_full, L.d_full_off, L.d_full_local,
+                      L.d_ftask_patch, L.d_ftask_row0, L.nftask, (double *)nullptr, full16 ? nullptr : L.Wfull32,
+                      full16 ? L.Wfull16 : nullptr, L.w16_kind, L.Wscale_full, L.d_pdof_off,
+                      full16 ? L.Cscale : nullptr, mg.gj_perm + L.pm_base, st);
+  }
   hip_check(hipGetLastError(), "pack launch");
 }
 
+static void pack_level(MG &mg, Level &L, hipStream_t st) {
+  if (mg.mixed)
+    pack_level_t(mg, L, reinterpret_cast<const float *>(mg.blk_scratch) + L.blk_base, st);
+  else
+    pack_level_t(mg, L, mg.blk_scratch + L.blk_base, st);
+}
 // coarsest operator: dense copy, Gauss-Jordan inverse written column-major
 // for the GEMV (no sync)
 static void enqueue_coarse(MG &mg, Level &L, hipStream_t st) {
@@ -425,6 +574,49 @@ static void enqueue_coarse(MG &mg, Level &L, hipStream_t st) {
   hip_check(hipGetLastError(), "coarse launch");
 }
 
+// B_k = J_l[I_k, I_k] of every smoothing level into the setup scratch: FP64
+// blocks, or FP32 working matrices for the mixed forms (the same element
+// offsets, the buffer read as floats)
+static void extract_blocks(MG &mg, hipStream_t st) {
+  if (mg.mixed) {
+    float *B = reinterpret_cast<float *>(mg.blk_scratch);
+    launch_fill_f32(B, mg.blk_total, 0.0f, st);
+    for (int l = 1; l < mg.nlevels; ++l) {
+      Level &L = mg.lv[l];
+      launch_extract(L.J.val, L.ext_nslots, L.d_ext_src, L.d_ext_dst, B + L.blk_base, st);
+    }
+  } else {
+    launch_fill_f64(mg.blk_scratch, mg.blk_total, 0.0, st);
+    for (int l = 1; l < mg.nlevels; ++l) {
+      Level &L = mg.lv[l];
+      launch_extract(L.J.val, L.ext_nslots, L.d_ext_src, L.d_ext_dst, mg.blk_scratch + L.blk_base, st);
+    }
+  }
+}
+
+// the batched Gauss-Jordan inversion of every block (FP64, or FP32 for the mixed forms)
+static void invert_blocks(MG &mg, int variant, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (mg.mixed)
+    launch_gj_batched_f32(reinterpret_cast<float *>(mg.blk_scratch), mg.all_boff, mg.all_pm, mg.all_poff,
+                          mg.gj_perm, mg.gj_used, mg.npatch_all, mg.mmax_all, mg.status, mg.gj_grid,
+                          mg.gj_sched, st, variant, ev0, ev1);
+  else
+    launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.all_poff, mg.gj_perm, mg.gj_used,
+                      mg.npatch_all, mg.mmax_all, mg.status, mg.gj_grid, mg.gj_sched, st, variant, ev0,
+                      ev1);
+}
+
+// next event pair of a profiling list (created on first use)
+static hipEvent_t *prof_event_pair(std::vector<std::pair<hipEvent_t, hipEvent_t>> &evs, size_t &used) {
+  if (used == evs.size()) {
+    hipEvent_t a, b;
+    hip_check(hipEventCreate(&a), "event");
+    hip_check(hipEventCreate(&b), "event");
+    evs.push_back({a, b});
+  }
+  return &evs[used++].first;
+}
+
 // setup of a1-a3 from the device-resident operator values.  The blocks of
 // all smoothing levels are extracted and inverted in one launch on the main
 // stream; the coarsest inversion (a chain of ~n/16 small launches, replayed
@@ -440,13 +632,7 @@ void refactor(MG &mg, hipStream_t st) {
   hip_check(hipEventRecord(mg.ev_fork, st), "fork");
   if (mg.mixed)
     for (int l = 1; l < mg.nlevels; ++l) launch_cast_d2f(mg.lv[l].J.val, mg.lv[l].J.val32, mg.lv[l].J.nnz, st);
-  if (mg.nlevels > 1) {
-    launch_fill_f64(mg.blk_scratch, mg.blk_total, 0.0, st);
-    for (int l = 1; l < mg.nlevels; ++l) {
-      Level &L = mg.lv[l];
-      launch_extract(L.J.val, L.ext_nslots, L.d_ext_src, L.d_ext_dst, mg.blk_scratch + L.blk_base, st);
-    }
-  }
+  if (mg.nlevels > 1) extract_blocks(mg, st);
   hip_check(hipStreamWaitEvent(mg.side_stream, mg.ev_fork, 0), "fork wait");
   if (mg.opts.use_graph) {
     if (!mg.coarse_graph) {
@@ -463,9 +649,8 @@ void refactor(MG &mg, hipStream_t st) {
   }
   hip_check(hipEventRecord(mg.ev_join, mg.side_stream), "join");
   if (mg.nlevels > 1) {
-    launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.all_poff, mg.gj_perm, mg.gj_used,
-                      mg.npatch_all, mg.mmax_all, mg.status, mg.gj_grid, mg.gj_sched, st,
-                      mg.gj_variant);
+    hipEvent_t *ev = mg.prof_on ? prof_event_pair(mg.prof_gj_ev, mg.prof_gj_used) : nullptr;
+    invert_blocks(mg, mg.gj_variant, st, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
     hip_check(hipGetLastError(), "gj launch");
     for (int l = 1; l < mg.nlevels; ++l) pack_level(mg, mg.lv[l], st);
   }
@@ -507,14 +692,20 @@ static void ras64(MG &mg, Level &L, const double *s, double *e, bool add, hipStr
   launch_ras_f64(ras_view(L), L.W64, s, e, mg.opts.omega, &L == &mg.lv.back(), add, st,
                  ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
 }
-static void ras32(MG &mg, Level &L, const float *s, float *e, bool add, hipStream_t st) {
+static void ras32(MG &mg, Level &L, const float *s, float *e, bool add, hipStream_t st,
+                  double omega_d = -1.0) {
   hipEvent_t *ev = prof_pair(mg, L);
+  const float omega = (float)(omega_d > 0.0 ? omega_d : mg.opts.omega);
   if (L.W32)
-    launch_ras_f32(ras_view(L), L.W32, s, e, (float)mg.opts.omega, &L == &mg.lv.back(), add, st,
+    launch_ras_f32(ras_view(L), L.W32, s, e, omega, &L == &mg.lv.back(), add, st,
                    ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
   else
-    launch_ras_16(ras_view(L), L.W16, L.w16_kind, L.Wscale, s, e, (float)mg.opts.omega,
+    launch_ras_16(ras_view(L), L.W16, L.w16_kind, L.Wscale, s, e, omega,
                   &L == &mg.lv.back(), add, st, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
+  // the solid blocks apart: FP32 owned rows, or refined local solves
+  if (L.ntask_s) launch_ras_f32(ras_view_solid(L), L.Ws, s, e, omega, false, add, st);
+  if (L.nref)
+    launch_ras_refine(refine_view(L), L.Wfull32, L.Wfull16, s, e, omega, add, mg.opts.refine_sweeps, st);
 }
 
 // One V-cycle on level l for e = M_l^{-1} r (r and e distinct; the finest
@@ -652,10 +843,13 @@ void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *op
   if (opts->nu_pre < 0 || opts->nu_post < 0 || !(opts->omega > 0.0) ||
       opts->precision < FSI_PREC_FP64 || opts->precision > FSI_PREC_MIXED_FP32)
     throw Error(FSI_E_INVALID, "invalid multigrid options");
-  if (opts->solid_precision != -1 && opts->solid_precision != opts->precision)
-    throw Error(FSI_E_INVALID, "solid_precision must be -1 or equal to precision");
-  if (opts->refine_sweeps != 0)
-    throw Error(FSI_E_INVALID, "refine_sweeps must be 0 (no per-block refinement)");
+  const bool mixed = opts->precision != FSI_PREC_FP64;
+  if (opts->solid_precision != -1 && opts->solid_precision != opts->precision &&
+      !(mixed && opts->solid_precision == FSI_PREC_MIXED_FP32))
+    throw Error(FSI_E_INVALID,
+                "solid_precision must be -1, equal to precision, or FSI_PREC_MIXED_FP32 in a mixed hierarchy");
+  if (opts->refine_sweeps < 0 || opts->refine_sweeps > 4 || (opts->refine_sweeps > 0 && !mixed))
+    throw Error(FSI_E_INVALID, "refine_sweeps must be 0..4, and 0 for an FP64 hierarchy");
   std::vector<int64_t> n(nlevels);
   for (int l = 0; l < nlevels; ++l) n[l] = levels[l].J.nrows;
   if (n[0] > kMaxCoarse) {
@@ -834,10 +1028,11 @@ void destroy_mg(MG *mg) {
   if (mg->coarse_graph) (void)hipGraphExecDestroy(mg->coarse_graph);
   if (mg->ev_fork) (void)hipEventDestroy(mg->ev_fork);
   if (mg->ev_join) (void)hipEventDestroy(mg->ev_join);
-  for (auto &p : mg->prof_ev) {
-    (void)hipEventDestroy(p.first);
-    (void)hipEventDestroy(p.second);
-  }
+  for (auto *list : {&mg->prof_ev, &mg->prof_gj_ev})
+    for (auto &p : *list) {
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
   clear_graphs(*mg);
   free_list(mg->owned);
   free_list(mg->kry.owned);
@@ -1269,76 +1464,83 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
     }
   }
   if (mg.npatch_all && mg.blk_scratch) {
-    char key[256];
-    snprintf(key, sizeof key, "gj3:%d:%d:%lld", mg.mmax_all, mg.npatch_all, (long long)mg.blk_total);
+    // The batched inversion's kernel variant and grid, chosen together: a
+    // variant on 256 threads fits two workgroups on a compute unit and wants
+    // one workgroup per block, a 512-thread one the fewest rounds (which also
+    // leaves the most room to the coarsest inversion beside it).  Every
+    // (variant, grid) pair is timed on the extraction and inversion launches;
+    // the best three are then timed on whole refactors (the coarse chain
+    // overlaps the batched launch there).  The schedule changes which
+    // workgroup inverts a block, not the result.
+    char key[256], gkey[256];
+    snprintf(key, sizeof key, "gj3:%s%d:%d:%lld", mg.mixed ? "f32:" : "", mg.mmax_all, mg.npatch_all,
+             (long long)mg.blk_total);
+    auto gj_key = [&](int var) {
+      snprintf(gkey, sizeof gkey, "gjg:%s%d:%d:%lld:%d", mg.mixed ? "f32:" : "", mg.mmax_all,
+               mg.npatch_all, (long long)mg.blk_total, var);
+      return std::string(gkey);
+    };
     auto it = db.find(key);
-    if (it != db.end()) {
+    if (it != db.end() && db.count(gj_key(it->second))) {
       mg.gj_variant = it->second;
-    } else {
-      int best = kGjAuto;
-      float best_ms = 1e30f;
-      for (int var : {kGj16x256, kGj16x512, kGj32x512, kGjWideG, kGj24x512}) {
-        if (!gj_variant_ok(var, mg.mmax_all)) continue;
-        const float ms = time_events(st, [&] {
-          for (int l = 1; l < mg.nlevels; ++l) {
-            Level &L = mg.lv[l];
-            launch_fill_f64(mg.blk_scratch + L.blk_base, L.boff_total, 0.0, st);
-            launch_extract(L.J.val, L.ext_nslots, L.d_ext_src, L.d_ext_dst,
-                           mg.blk_scratch + L.blk_base, st);
-          }
-          launch_gj_batched(mg.blk_scratch, mg.all_boff, mg.all_pm, mg.all_poff, mg.gj_perm,
-                            mg.gj_used, mg.npatch_all, mg.mmax_all, mg.status, mg.gj_grid,
-                            mg.gj_sched, st, var);
-        }, 1);
-        if (ms < best_ms) {
-          best_ms = ms;
-          best = var;
-        }
-      }
-      mg.gj_variant = best;
-      db[key] = best;
-      ++measured;
-      refactor(mg, st);   // the blocks were overwritten by the timing runs
-    }
-    // the batched inversion's grid: the fewest rounds over the compute units
-    // leave the most room to the coarsest inversion beside it, more
-    // workgroups shorten the batched launch itself; timed on whole refactors
-    // (the schedule changes which workgroup inverts a block, not the result)
-    snprintf(key, sizeof key, "gjg:%d:%d:%lld:%d", mg.mmax_all, mg.npatch_all, (long long)mg.blk_total,
-             mg.gj_variant);
-    it = db.find(key);
-    if (it != db.end()) {
-      set_gj_grid(mg, it->second, st);
+      set_gj_grid(mg, db[gj_key(it->second)], st);
     } else {
       int dev = 0, ncu = 256;
       if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-      std::vector<int> cands;
-      for (int g : {gj_batched_grid(mg.npatch_all), ncu - 64, ncu - 48, ncu - 40}) {
+      std::vector<int> grids;
+      for (int g : {gj_batched_grid(mg.npatch_all), ncu - 64, ncu - 48, ncu - 40, 2 * ncu}) {
         g = std::max(1, std::min(g, mg.npatch_all));
-        if (std::find(cands.begin(), cands.end(), g) == cands.end()) cands.push_back(g);
+        if (std::find(grids.begin(), grids.end(), g) == grids.end()) grids.push_back(g);
       }
-      int best = cands[0];
-      if (cands.size() > 1) {
-        double best_ms = 1e300;
-        for (int g : cands) {
+      const std::vector<int> vars =
+          mg.mixed ? std::vector<int>{kGjF64x512, kGjF32x512, kGjF32x256, kGjF32x512r2, kGjF48x512r2}
+                   : std::vector<int>{kGj16x256, kGj16x512, kGj32x512, kGjWideG, kGj24x512};
+      std::vector<std::tuple<float, int, int>> timed;   // (ms, variant, grid)
+      for (int var : vars) {
+        if (!gj_variant_ok(var, mg.mmax_all)) continue;
+        for (int g : grids) {
           set_gj_grid(mg, g, st);
+          const float ms = time_events(st, [&] {
+            extract_blocks(mg, st);
+            invert_blocks(mg, var, st, nullptr, nullptr);
+          }, 1);
+          timed.emplace_back(ms, var, g);
+        }
+      }
+      std::sort(timed.begin(), timed.end());
+      int best_var = std::get<1>(timed[0]), best_grid = std::get<2>(timed[0]);
+      // whole refactors decide among every grid of the two fastest variants
+      // (a grid that speeds the batched launch up may starve the coarse chain)
+      std::vector<std::pair<int, int>> finals;
+      std::vector<int> top_vars;
+      for (auto &t : timed)
+        if (std::find(top_vars.begin(), top_vars.end(), std::get<1>(t)) == top_vars.end() && top_vars.size() < 2)
+          top_vars.push_back(std::get<1>(t));
+      for (int v : top_vars)
+        for (int g : grids) finals.push_back({v, g});
+      double best_ms = 1e300;
+      for (auto &fg : finals) {
+        mg.gj_variant = fg.first;
+        set_gj_grid(mg, fg.second, st);
+        refactor(mg, st);
+        for (int rep = 0; rep < 2; ++rep) {
+          const auto a = std::chrono::steady_clock::now();
           refactor(mg, st);
-          for (int rep = 0; rep < 2; ++rep) {
-            const auto a = std::chrono::steady_clock::now();
-            refactor(mg, st);
-            const double ms =
-                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
-            if (ms < best_ms) {
-              best_ms = ms;
-              best = g;
-            }
+          const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
+          if (ms < best_ms) {
+            best_ms = ms;
+            best_var = mg.gj_variant;
+            best_grid = mg.gj_grid;
           }
         }
-        ++measured;
       }
-      set_gj_grid(mg, best, st);
-      db[key] = best;
+      mg.gj_variant = best_var;
+      set_gj_grid(mg, best_grid, st);
+      db[key] = best_var;
+      db[gj_key(best_var)] = best_grid;
+      ++measured;
+      refactor(mg, st);   // the blocks were overwritten by the timing runs
     }
   }
   hip_check(hipGetLastError(), "autotune");
@@ -1491,6 +1693,17 @@ fsi_status fsi_mg_apply(struct fsi_mg *h, int32_t level, int32_t op, const doubl
         if (level != 0) throw Error(FSI_E_INVALID, "direct solve only on level 0");
         launch_dense_gemv(L.C0, L.n, x_dev, y_dev, st);
         break;
+      case 6:   // one Schwarz application as the V-cycle performs it (mixed: FP32 inside)
+        if (level == 0) throw Error(FSI_E_INVALID, "no patches on level 0");
+        if (!mg->mixed) {
+          launch_fill_f64(y_dev, L.n, 0.0, st);
+          launch_ras_f64(ras_view(L), L.W64, x_dev, y_dev, 1.0, false, true, st);
+        } else {
+          launch_cast_d2f(x_dev, L.s32, L.n, st);
+          ras32(*mg, L, L.s32, L.e32, false, st, 1.0);
+          launch_cast_f2d(L.e32, y_dev, L.n, st);
+        }
+        break;
       default: throw Error(FSI_E_INVALID, "unknown op");
     }
     hip_check(hipGetLastError(), "apply launch");
@@ -1529,28 +1742,35 @@ fsi_status fsi_mg_jvalues(struct fsi_mg *h, int32_t level, double **val_dev) {
   })
 }
 
-fsi_status fsi_mg_profile(struct fsi_mg *h, int32_t enable, double out[2]) {
+fsi_status fsi_mg_profile(struct fsi_mg *h, int32_t enable, double out[4]) {
   FSI_GUARD({
     MG *mg = reinterpret_cast<MG *>(h);
     if (!mg) throw Error(FSI_E_INVALID, "null handle");
     if (enable) {
       mg->prof_on = true;
-      mg->prof_used = 0;
+      mg->prof_used = mg->prof_gj_used = 0;
       return FSI_OK;
     }
-    double tot = 0.0;
-    for (size_t i = 0; i < mg->prof_used; ++i) {
-      hip_check(hipEventSynchronize(mg->prof_ev[i].second), "event sync");
-      float ms = 0.f;
-      hip_check(hipEventElapsedTime(&ms, mg->prof_ev[i].first, mg->prof_ev[i].second), "elapsed");
-      tot += ms;
-    }
+    auto total = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>> &evs, size_t used) {
+      double tot = 0.0;
+      for (size_t i = 0; i < used; ++i) {
+        hip_check(hipEventSynchronize(evs[i].second), "event sync");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, evs[i].first, evs[i].second), "elapsed");
+        tot += ms;
+      }
+      return tot;
+    };
+    const double ras_ms = total(mg->prof_ev, mg->prof_used);
+    const double gj_ms = total(mg->prof_gj_ev, mg->prof_gj_used);
     if (out) {
-      out[0] = tot;
+      out[0] = ras_ms;
       out[1] = (double)mg->prof_used;
+      out[2] = gj_ms;
+      out[3] = (double)mg->prof_gj_used;
     }
     mg->prof_on = false;
-    mg->prof_used = 0;
+    mg->prof_used = mg->prof_gj_used = 0;
     return FSI_OK;
   })
 }

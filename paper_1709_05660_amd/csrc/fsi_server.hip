@@ -97,18 +97,26 @@ static int64_t footprint(const fsi_level *lv, int nl, const fsi_mg_opts &mo,
     }
     res += csr(lv[l].P) + csr(lv[l].R);
     const fsi_patches &P = lv[l].patches;
-    int64_t om = 0, m2 = 0, slots = 0;
+    // solid blocks apart (solid_precision / refine_sweeps): FP32 owned rows,
+    // or full FP32 inverses plus their local block rows
+    const bool split = mixed && ((mo.solid_precision != -1 && mo.solid_precision != mo.precision) ||
+                                 mo.refine_sweeps > 0);
+    int64_t om = 0, m2 = 0, slots = 0, solid_bytes = 0;
     for (int k = 0; k < P.npatch; ++k) {
       const int64_t m = P.ptr[k + 1] - P.ptr[k];
-      int64_t o = 0;
+      int64_t o = 0, ks = 0;
       for (int64_t p = P.ptr[k]; p < P.ptr[k + 1]; ++p) {
         o += P.owned[p] ? 1 : 0;
-        slots += lv[l].J.rowptr[P.dof[p] + 1] - lv[l].J.rowptr[P.dof[p]];
+        ks += lv[l].J.rowptr[P.dof[p] + 1] - lv[l].J.rowptr[P.dof[p]];
       }
-      om += o * m;
+      slots += ks;
+      if (split && P.kind && P.kind[k] == 1)
+        solid_bytes += mo.refine_sweeps > 0 ? m * m * 4 + ks * 8 + (m + 1) * 4 : o * m * 4;
+      else
+        om += o * m;
       m2 += m * m;
     }
-    res += om * wbytes + P.ptr[P.npatch] * 48;
+    res += om * wbytes + solid_bytes + P.ptr[P.npatch] * 48;
     // all levels' dense blocks share one setup scratch; the extraction map
     // (two ints per slot, an offset per block row) is setup scratch too
     transient += m2 * 8 + slots * 8 + P.ptr[P.npatch] * 8;

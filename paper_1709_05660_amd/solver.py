@@ -254,9 +254,10 @@ class MG:
         L.check(L.lib().fsi_mg_profile(self.h, 1, None))
 
     def profile_stop(self):
-        out = (C.c_double * 2)()
+        """(Schwarz ms, Schwarz launches, inversion ms, inversion launches) since profile_start."""
+        out = (C.c_double * 4)()
         L.check(L.lib().fsi_mg_profile(self.h, 0, out))
-        return out[0], int(out[1])
+        return out[0], int(out[1]), out[2], int(out[3])
 
     def export_patches(self, level, blocks=False):
         info = self.level_info(level)

@@ -145,11 +145,21 @@ def test_setup_validation_errors_are_reported_on_the_host():
     # 4. bad options
     st, msg = _setup_status(p.levels, L, omega=-1.0)
     assert st == -1
-    # 5. reserved options
-    st, msg = _setup_status(p.levels, L, precision="bf16", refine_sweeps=1)
-    assert st == -1 and "refine_sweeps" in msg
-    st, msg = _setup_status(p.levels, L, precision="bf16", solid_precision="fp32")
-    assert st == -1 and "solid_precision" in msg
+    # 5. per-kind options: refinement only in a mixed hierarchy and at most 4
+    #    sweeps; FP32 solid blocks only in a mixed hierarchy
+    for kw, word in ((dict(precision="fp64", refine_sweeps=1), "refine_sweeps"),
+                     (dict(precision="bf16", refine_sweeps=5), "refine_sweeps"),
+                     (dict(precision="bf16", refine_sweeps=-1), "refine_sweeps"),
+                     (dict(precision="fp64", solid_precision="fp32"), "solid_precision"),
+                     (dict(precision="fp16", solid_precision="bf16"), "solid_precision")):
+        st, msg = _setup_status(p.levels, L, **kw)
+        assert st == -1 and word in msg, (kw, msg)
+    # accepted combinations pass the host checks (then need the device: -4 here)
+    for kw in (dict(precision="bf16", refine_sweeps=1), dict(precision="fp16", solid_precision="fp32"),
+               dict(precision="bf16", solid_precision="fp32", refine_sweeps=2),
+               dict(precision="fp32", refine_sweeps=1)):
+        st, msg = _setup_status(p.levels, L, **kw)
+        assert st != -1, (kw, msg)
 
 
 def test_server_rejects_oversized_request():
