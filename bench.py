@@ -36,30 +36,49 @@ def ras_bytes(info, wbytes, vbytes):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ras_finest_c1_2d_128x32_fp64_traffic.md")
+GJ_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gj_batched_c1_2d_128x32_fp64_traffic.md")
+CSRC = os.path.join(ROOT, "paper_1709_05660_amd", "csrc")
 
 
 def ras_kernel_digest():
     """Digest of the device code of the Schwarz kernel (helpers and kernel
     body, not the host launchers): counter readings apply only to this code."""
-    src = open(os.path.join(ROOT, "paper_1709_05660_amd", "csrc", "fsi_kernels.hip")).read()
+    src = open(os.path.join(CSRC, "fsi_kernels.hip")).read()
     a = src.index("__device__ inline float w16val")
-    b = src.index("// ev0/ev1 (optional, finest level)")
+    b = src.index("// Refined local solve of one solid block per workgroup")
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per finest-level Schwarz launch from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None
-    when the summary was taken on other kernel code."""
+def gj_kernel_digest():
+    """Digest of the device code of the batched Gauss-Jordan inversion (the
+    pivot step, the register panel and the batched kernel)."""
+    src = open(os.path.join(CSRC, "fsi_gj.hip")).read()
+    b = src.index("static size_t gj_batched_lds")
+    return hashlib.sha256(src[:b].encode()).hexdigest()[:16]
+
+
+def measured_traffic(path=TRAFFIC_PROFILE, digest=ras_kernel_digest):
+    """HBM bytes per launch of a kernel from a committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None when the
+    summary was taken on other kernel code."""
     try:
-        txt = open(TRAFFIC_PROFILE).read()
+        txt = open(path).read()
     except OSError:
         return None
     b = re.search(r"traffic_bytes_per_launch:\s*(\d+)", txt)
     d = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", txt)
-    if not b or not d or d.group(1) != ras_kernel_digest():
+    if not b or not d or d.group(1) != digest():
         return None
     return int(b.group(1))
+
+
+# panel width of each batched-inversion variant (the streamed update moves
+# the trailing block once per panel: 2 sizeof(T) m^3 / NB bytes per block)
+GJ_VARIANTS = {1: ("NB16 x 256, FP64", 16, 8), 2: ("NB16 x 512, FP64", 16, 8),
+               3: ("NB32 x 512, LDS panel, FP64", 32, 8), 4: ("wide panel from the block, FP64", 32, 8),
+               5: ("NB24 x 512, LDS panel, FP64", 24, 8), 11: ("NB64 x 512, FP32", 64, 4),
+               12: ("NB32 x 512, FP32", 32, 4), 13: ("NB32 x 256 (2 rows/thread), FP32", 32, 4),
+               14: ("NB32 x 512 (2 rows/thread), FP32", 32, 4), 15: ("NB48 x 512 (2 rows/thread), FP32", 48, 4)}
 
 
 _TUNING_DB = None
@@ -84,14 +103,12 @@ def tuning_db():
 def tuning_choices(db):
     """The batched inversion's variant and grid as the autotuner left them in
     its database (keys gj3:... and gjg:...)."""
-    names = {1: "NB16 x 256", 2: "NB16 x 512", 3: "NB32 x 512 (LDS panel)", 4: "wide panel from the block",
-             5: "NB24 x 512 (LDS panel)"}
     out = {}
     try:
         for line in open(db):
             k, v = line.split()
             if k.startswith("gj3:"):
-                out.setdefault("gj_variant", {})[k] = names.get(int(v), v)
+                out.setdefault("gj_variant", {})[k] = GJ_VARIANTS.get(int(v), (v,))[0]
             elif k.startswith("gjg:"):
                 out.setdefault("gj_grid", {})[k] = int(v)
     except OSError:
@@ -278,29 +295,67 @@ def gpu_leg(args):
         out["solve_ms_fp64"] = infos[-1]["solve_ms"]
         out["setup_with_upload_ms"] = setup_upload_ms
         out["build_s"] = build_s
-        # ---- dominant kernel: finest-level Schwarz GEMV, event-timed on its stream
+        # ---- event timing of the two kernels that bound the step: the batched
+        # block inversion (the refactor's dominant kernel and the step's) and the
+        # finest-level Schwarz GEMV (the solve's), each on its own stream
         fine = mg.level_info(p.nlevels - 1)
         ptr, dof, owned, _ = mg.export_patches(p.nlevels - 1)
         fine["n_owned"] = int(owned.sum())
+        m3 = 0.0
+        for l in range(1, p.nlevels):
+            m = np.diff(mg.export_patches(l)[0]).astype(np.float64)
+            m3 += float((m ** 3).sum())
         mg.profile_start()
         for _ in range(args.prof_steps):
+            mg.refactor()
             mg.fgmres(b, x, restart=spec.restart, rtol=spec.rtol, maxit=spec.maxit)
-        kms, cnt, _, _ = mg.profile_stop()
+        kms, cnt, gms, gcnt = mg.profile_stop()
+        gj_avg_ms = gms / max(gcnt, 1)
+        lu_flops, gj_flops = 2.0 / 3.0 * m3, 2.0 * m3
+        gj_key = "gj3:%d:%d:" % (max(int(np.diff(mg.export_patches(l)[0]).max()) for l in range(1, p.nlevels)),
+                                  sum(mg.level_info(l)["npatch"] for l in range(1, p.nlevels)))
+        variant = next((v for k, v in out["autotune_choices"].get("gj_variant", {}).items()
+                        if k.startswith(gj_key)), None)
+        vid = next((k for k, v in GJ_VARIANTS.items() if v[0] == variant), 3)
+        nb, wsize = GJ_VARIANTS[vid][1], GJ_VARIANTS[vid][2]
+        gj_tflops = lu_flops / (gj_avg_ms * 1e-3) / 1e12 if gcnt else 0.0
+        out["roofline"] = {
+            "bound": "mfma", "kernel": "k_gj_batched<double> (Gauss-Jordan inverse of all 336 Schwarz blocks, "
+                                       "FP64 matrix cores)",
+            "achieved": round(gj_tflops, 3), "peak": 78.6, "unit": "TFLOP/s",
+            "frac": round(gj_tflops / 78.6, 4), "traffic": measured_traffic(GJ_TRAFFIC_PROFILE, gj_kernel_digest),
+            "flops_per_launch": lu_flops, "flop_count": "2/3 sum m_k^3 (LU-equivalent work of the local solves)",
+            "gauss_jordan_flops_per_launch": gj_flops,
+            "frac_on_gauss_jordan_flops": round(gj_flops / (gj_avg_ms * 1e-3) / 1e12 / 78.6, 4) if gcnt else None,
+            "traffic_model_bytes": int(2 * wsize * m3 / nb), "variant": variant,
+            "avg_launch_us": round(gj_avg_ms * 1e3, 2), "launches": gcnt,
+            "share_of_step": round(gj_avg_ms / out["ms_per_step"], 3)}
         avg_ms = kms / max(cnt, 1)
         bytes_per_launch = ras_bytes(fine, 8, 8)
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if cnt else 0.0
-        out["roofline"] = {"bound": "hbm", "kernel": "k_ras<double> (finest level)",
-                           "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-                           "frac": round(achieved / 8000.0, 4), "traffic": measured_traffic(),
-                           "avg_launch_us": round(avg_ms * 1e3, 2), "launches": cnt,
-                           "bytes_per_launch": int(bytes_per_launch)}
+        out["roofline_solve_kernel"] = {
+            "bound": "hbm", "kernel": "k_ras<double> (finest level)",
+            "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(achieved / 8000.0, 4), "traffic": measured_traffic(),
+            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": cnt,
+            "bytes_per_launch": int(bytes_per_launch),
+            "launches_per_step": round(cnt / max(args.prof_steps, 1), 1)}
         # what a plain streaming read of the same byte count achieves on this
         # device (a library reduction over a float64 tensor), for context
         ceil = stream_read_gbps(int(bytes_per_launch))
-        out["roofline"]["read_ceiling"] = {
+        out["roofline_solve_kernel"]["read_ceiling"] = {
             "kernel": "fsi_stream_read: plain 16-byte streaming read of the same byte count",
             "achieved": round(ceil, 1), "unit": "GB/s",
             "frac_of_ceiling": round(achieved / ceil, 4) if ceil else None}
+        # ---- the same FP64 step to the mixed forms' tolerance (1e-8), so that
+        # the forms are compared at equal accuracy
+        t8, i8 = timed_steps(mg, args.steps, 1e-8)
+        out["fp64_rtol_1e-8"] = {"ms_per_step": round(t8 / args.steps, 3),
+                                 "solves_per_s": round(args.steps / (t8 * 1e-3), 2),
+                                 "iters": i8[-1]["iters"], "true_relres": float(f"{i8[-1]['true_relres']:.4g}")}
+        timed_steps(mg, 1, spec.rtol)
+        x64 = x.clone()
+        out["solutions"] = {"fp64": x64.cpu().numpy()}
         if args.traffic_probe:
             # plain copy of known size (512 MiB read + 512 MiB written), to
             # calibrate the FETCH_SIZE / WRITE_SIZE counters of a profiler run
@@ -310,20 +365,33 @@ def gpu_leg(args):
                 dst.copy_(src)
             torch.cuda.synchronize()
         mg.close()
-        # ---- mixed precision forms (FP32 V-cycle, 16-bit block inverses, FP64 Krylov)
+        # ---- mixed precision forms: FP32 V-cycle, blocks inverted in FP32 on
+        # the matrix cores and stored in 16 bits (or FP32), FP64 Krylov, true
+        # residual and coarsest solve; the solid-block policies beside them
         if not args.no_mixed:
-            precs = [args.mixed] + [q for q in ("bf16", "fp16") if q != args.mixed]
-            for q in precs:
-                mgm = MG(p, precision=q, use_graph=True)
+            forms = [("mixed", args.mixed, {})]
+            forms += [("mixed_" + q, q, {}) for q in ("bf16", "fp16") if q != args.mixed]
+            forms += [("mixed_bf16_refine1", "bf16", {"refine_sweeps": 1}),
+                      ("mixed_bf16_solid_fp32", "bf16", {"solid_precision": "fp32"})]
+            for key, q, kw in forms:
+                mgm = MG(p, precision=q, use_graph=True, **kw)
                 mgm.autotune(tune_db)
                 timed_steps(mgm, args.warmup, 1e-8)
                 tm, im = timed_steps(mgm, args.steps, 1e-8)
                 err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
-                out["mixed" if q == args.mixed else "mixed_" + q] = {
-                    "precision": q, "rtol": 1e-8, "ms_per_step": tm / args.steps,
+                mgm.profile_start()
+                mgm.refactor()
+                _, _, gm, gc = mgm.profile_stop()
+                out["solutions"][key] = x.cpu().numpy()
+                out[key] = {
+                    "precision": q, "policy": kw or "every block alike",
+                    "blocks": "inverted in FP32 on the FP32 matrix cores, owned rows stored in "
+                              + ("FP32" if q == "fp32" else q + " with two-sided FP32 scaling"),
+                    "rtol": 1e-8, "ms_per_step": tm / args.steps,
                     "solves_per_s": args.steps / (tm * 1e-3), "iters": im[-1]["iters"],
                     "true_relres": im[-1]["true_relres"], "err_vs_fp64": err,
-                    "vcycle_ms": vcycle_ms(mgm)}
+                    "refactor_ms": im[-1]["setup_ms"], "block_inversion_ms": gm / max(gc, 1),
+                    "solve_ms": im[-1]["solve_ms"], "vcycle_ms": vcycle_ms(mgm)}
                 mgm.close()
     out["n"] = p.n
     return out
@@ -352,26 +420,28 @@ def serve_leg(args):
     build_s = time.time() - t
     budget, slots = args.serve_budget_gb << 30, args.serve_slots
 
-    def run(arrivals):
+    def run(arrivals, plist=None, precision=None):
+        plist = probs if plist is None else plist
+        precision = precision or args.mixed
         srv = Server(hbm_budget_bytes=budget, max_slots=slots)
         done_at = {}
         sub_at = {}
-        tickets = [None] * len(probs)
+        tickets = [None] * len(plist)
         t0 = time.perf_counter()
 
         def producer():
-            for i, p in enumerate(probs):
+            for i, p in enumerate(plist):
                 delay = t0 + arrivals[i] - time.perf_counter()
                 if delay > 0:
                     time.sleep(delay)
                 sub_at[i] = time.perf_counter()
-                tickets[i] = srv.submit(p, precision=args.mixed, rtol=1e-8)
+                tickets[i] = srv.submit(p, precision=precision, rtol=1e-8)
 
         th = threading.Thread(target=producer)
         th.start()
         bad = 0
         iters = []
-        while len(done_at) < len(probs):
+        while len(done_at) < len(plist):
             for i, tk in enumerate(tickets):
                 if tk is None or i in done_at:
                     continue
@@ -385,17 +455,42 @@ def serve_leg(args):
         th.join()
         stats = srv.stats()
         srv.close()
-        lat = np.array([done_at[i] - sub_at[i] for i in range(len(probs))]) * 1e3
+        lat = np.array([done_at[i] - sub_at[i] for i in range(len(plist))]) * 1e3
         span = max(done_at.values()) - min(sub_at.values())
-        return {"solves_per_s": round(len(probs) / span, 2), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+        return {"solves_per_s": round(len(plist) / span, 2),
+                "dof_per_s": round(sum(p.n for p in plist) / span, 1),
+                "p50_ms": round(float(np.percentile(lat, 50)), 2),
                 "p99_ms": round(float(np.percentile(lat, 99)), 2), "failed": int(bad),
                 "mean_iters": round(float(np.mean(iters)), 2) if iters else None,
-                "max_coresident": stats["max_coresident"], "peak_bytes": stats["peak_bytes"]}
+                "max_coresident": stats["max_coresident"], "peak_bytes": stats["peak_bytes"],
+                "pool_peak_in_use_bytes": stats["pool_peak_in_use_bytes"]}
+
+    def sequential(plist, precision):
+        """The same requests solved one at a time through the synchronous path,
+        each with its upload, setup, solve and copy back (as a served request)."""
+        import torch
+
+        from paper_1709_05660_amd import MG
+        t = time.perf_counter()
+        for p in plist:
+            mg = MG(p, precision=precision)
+            x, _ = mg.fgmres(torch.as_tensor(p.b).to("cuda"), restart=30, rtol=1e-8)
+            x.cpu()
+            mg.close()
+        span = time.perf_counter() - t
+        return {"solves_per_s": round(len(plist) / span, 2), "dof_per_s": round(sum(p.n for p in plist) / span, 1)}
 
     closed = run([0.0] * len(probs))
     out = {"systems": len(probs), "precision": args.mixed, "rtol": 1e-8,
            "budget_bytes": budget, "max_slots": slots, "host_build_s": round(build_s, 1),
-           "closed_loop": closed}
+           "each_request": "upload, setup (block and coarse inversion), solve, copy back",
+           "closed_loop": closed,
+           # like for like: the same stream served in FP64, and the 128x32
+           # systems alone, served and one at a time, setup included on both sides
+           "closed_loop_fp64": run([0.0] * len(probs), precision="fp64")}
+    big = [p for p in probs if p.spec.nx == 128][:32]
+    out["only_128x32"] = {"systems": len(big), "served_closed_loop": run([0.0] * len(big), big),
+                          "one_at_a_time": sequential(big, args.mixed)}
     # the same Poisson stream scaled to 0.7 (the headline), 0.5 and 1.0 of
     # the measured closed-loop rate
     stream_rate = len(reqs) / reqs[-1].arrival_s
@@ -406,9 +501,45 @@ def serve_leg(args):
     return out
 
 
-def cpu_leg(args):
+def paper_leg(args):
+    """The paper's Krylov setting (left-preconditioned GMRES(10), one classical
+    Gram-Schmidt pass, rtol 1e-4 on the left-preconditioned residual) on the
+    2D meshes of the serving stream, with (2, 2) and (4, 4) sweeps: iterations
+    and the average convergence rate rho beside the paper's own (Tables
+    FSI_results_mg and FSI_results_pre_post, other geometry and hardware)."""
+    import torch
+
+    from paper_1709_05660_amd import MG, Problem
+    from synth import config, fourier_coefficients
+
+    out = {"krylov": "left GMRES(10), one CGS pass, rtol 1e-4 (preconditioned residual), FP64",
+           "paper_context": {"FSI1-S-2D rho, levels 2-5 (4,4)": [0.15, 0.10, 0.09, 0.08],
+                             "FSI3-T-2D rho, (2,2) vs (4,4)": [0.61, 0.32]}}
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for (nx, ny, lv) in ((32, 8, 2), (64, 16, 3), (128, 32, 4)):
+            for sw in ((2, 2), (4, 4)):
+                spec = config(WORKLOAD).with_(nx=nx, ny=ny, levels=lv, nu_pre=sw[0], nu_post=sw[1])
+                p = Problem(spec, fourier_coefficients(2, spec.seed))
+                mg = MG(p, precision="fp64", use_graph=True, nu_pre=sw[0], nu_post=sw[1])
+                b = torch.as_tensor(p.b).to("cuda")
+                mg.fgmres(b, restart=10, rtol=1e-4, side="left", orth="cgs")
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                x, info = mg.fgmres(b, restart=10, rtol=1e-4, side="left", orth="cgs")
+                ms = (time.perf_counter() - t) * 1e3
+                out[f"{nx}x{ny} L{lv} sweeps {sw[0]},{sw[1]}"] = {
+                    "unknowns": p.n, "iters": info["iters"], "rho": round(info["rho"], 4),
+                    "true_relres": float(f"{info['true_relres']:.3g}"), "solve_ms": round(ms, 3)}
+                mg.close()
+    return out
+
+
+def cpu_leg(args, solutions=None):
     """The checker as it stands, on a bounded sample: the same step (block and
-    coarse factorisation + FGMRES solve) of the same system."""
+    coarse factorisation + FGMRES solve) of the same system.  Also the
+    relative error of each GPU solution (FP64 and mixed forms, kept by the GPU
+    leg) against the checker's FP64 solution of its own assembly."""
     from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import problem as oprob
@@ -418,11 +549,13 @@ def cpu_leg(args):
     spec = config(WORKLOAD)
     h = oprob.build(spec, fourier_coefficients(spec.dim, spec.seed), factor=False)
 
+    last = {}
+
     def timed(steps):
         t = time.time()
         for _ in range(steps):
             osolver.setup_factors(h.levels)
-            oprob.solve(h)
+            last["x"], _ = oprob.solve(h)
         return time.time() - t
 
     timed(1)                                   # untimed warm-up (first-touch, library set-up)
@@ -452,7 +585,10 @@ def cpu_leg(args):
         pass
     # the faster of the two runs is the baseline; both are reported
     best_dt, best_cores = (dt_all, int(threads)) if dt_all <= dt1 else (dt1, 1)
+    errs = {k: float(f"{np.linalg.norm(v - last['x']) / np.linalg.norm(last['x']):.4g}")
+            for k, v in (solutions or {}).items()}
     return {"value": round(steps / best_dt, 4), "unit": "solves/s", "cores": best_cores, "kind": "oracle",
+            "err_vs_oracle": errs,
             "sample": f"{steps} full steps (block LU + coarse LU + FGMRES to 1e-10) of {WORKLOAD} after one "
                       f"untimed step, {best_dt:.1f} s",
             "all_threads_value": round(steps / dt_all, 4), "all_threads": int(threads),
@@ -473,6 +609,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--steps-3d", type=int, default=5)
     ap.add_argument("--only-3d", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true")
@@ -498,7 +635,8 @@ def main():
         "config": {"workload": "2D steady FSI 128x32 Q2-P1disc, 4 MG levels, 4x4 Schwarz blocks, "
                                "FGMRES(30) rtol 1e-10, FP64 (one Newton step: block inversion + solve)",
                    "unknowns": g["n"]},
-        "roofline": g["roofline"],
+        "roofline": g["roofline"], "roofline_solve_kernel": g["roofline_solve_kernel"],
+        "fp64_rtol_1e-8": g["fp64_rtol_1e-8"],
         "fgmres_iters": g["iters"], "true_relres": g["true_relres"], "converged": g["converged"],
         "vcycle_ms_fp64": round(g["vcycle_ms_fp64"], 4),
         "vcycle_ms_fp64_cold": round(g["vcycle_ms_fp64_cold"], 4),
@@ -516,10 +654,12 @@ def main():
         line["small_c0"] = small_leg(args)
     if not args.no_3d:
         line["three_d"] = three_d_leg(args)
+    if not args.no_paper:
+        line["paper_mode"] = paper_leg(args)
     if not args.no_serve:
         line["served"] = serve_leg(args)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_leg(args)
+        line["cpu_baseline"] = cpu_leg(args, g.get("solutions"))
     print(json.dumps(line), flush=True)
 
 

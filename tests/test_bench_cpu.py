@@ -45,6 +45,14 @@ def test_tuning_database(tmp_path, monkeypatch):
     monkeypatch.setenv("FSI_TUNING_DB", str(db))
     assert bench.tuning_db() == str(db)
     ch = bench.tuning_choices(str(db))
-    assert ch["gj_variant"] == {"gj3:372:336:1": "NB32 x 512 (LDS panel)"}
+    assert ch["gj_variant"] == {"gj3:372:336:1": "NB32 x 512, LDS panel, FP64"}
     assert ch["gj_grid"] == {"gjg:372:336:1:3": 168}
     assert bench.tuning_choices(str(tmp_path / "missing.db")) == {}
+
+
+def test_inversion_traffic_record_matches_the_kernel_source():
+    """The batched inversion's counter traffic is reported only for the code
+    it was measured on; against the streamed-update model 16 sum m^3 / 32 of
+    the 2D system (sum m^3 = 15,524,440,128) it is a little above 1."""
+    t = bench.measured_traffic(bench.GJ_TRAFFIC_PROFILE, bench.gj_kernel_digest)
+    assert t is not None and 1.0 < t / (16 * 15524440128 / 32) < 1.3
