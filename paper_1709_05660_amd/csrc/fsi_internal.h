@@ -62,9 +62,12 @@ struct Level {
   int64_t woff_solid = 0, wfull_total = 0, full_rows = 0;
   int *d_task_patch_s = nullptr, *d_task_row0_s = nullptr, *d_po_full = nullptr,
       *d_full_off = nullptr, *d_full_local = nullptr, *d_ftask_patch = nullptr, *d_ftask_row0 = nullptr,
-      *d_ref_patch = nullptr, *d_ref_rptr_off = nullptr, *d_ref_rptr = nullptr, *d_ref_col = nullptr,
-      *d_ref_src = nullptr;
+      *d_ref_patch = nullptr, *d_ref_src = nullptr, *d_own_dof = nullptr;
   int64_t *d_woff_full = nullptr;
+  float *yref0 = nullptr, *yref1 = nullptr, *gref = nullptr, *rhoref = nullptr;   // refined rows' vectors
+  int *d_ref_growptr = nullptr, *d_ref_gcol = nullptr;   // the refined blocks as one CSR (rows, columns)
+  float *bref = nullptr;                                  // its values (FP32, gathered at refactor)
+  int ref_nnz = 0, ref_lpr = 8;
   float *Ws = nullptr, *Wfull32 = nullptr, *Wscale_full = nullptr;
   uint16_t *Wfull16 = nullptr;
   double *W64 = nullptr;

@@ -136,25 +136,33 @@ void launch_ras_16(const RasView &v, const uint16_t *W, int w16_kind, const floa
                    const float *s, float *e, float omega, bool finest, bool add, hipStream_t st,
                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
-// ---- refined local solves of the solid blocks (mixed forms): per block k
-// (one workgroup), g = s[I_k], y = W~ g, then `sweeps` times
-// y += W~ (g - B_k y) with B_k = J[I_k, I_k] in FP32 (local CSR rows, values
-// read from jval at the J entry index src), and e[owned] (+)= omega y.
-// W~: every row of the inverse (FP32, or 16-bit with row scales rscale at
-// full_off[k] and column scales cscale at pdof_off[k]), in the packing's task
-// layout (rows in chunks of 64, column-major inside a chunk) at woff_full[k].
-// With add false the dofs no patch owns are also cleared.
+// ---- refined local solves of the solid blocks (mixed forms): per block k,
+// g = s[I_k], y = W~ g, then `sweeps` times y += W~ (g - B_k y) with
+// B_k = J[I_k, I_k] in FP32, and e[owned] (+)= omega y.  B: all refined
+// blocks as one FP32 CSR matrix over their rows (row full_off[k] + i of block
+// k, columns in the same numbering), applied by the SpMV with lpr lanes per
+// row; gfull, rho: vectors of the refined rows.  W~: every row of the inverse
+// (FP32, or 16-bit with row scales rscale at full_off[k] and column scales
+// cscale at pdof_off[k]) in the packing's task layout (rows in chunks of 64,
+// column-major inside a chunk) at woff_full[k]; the ntask (block, 64 rows)
+// tasks of all refined blocks; own_dof[full_off[k] + i]: the global dof that
+// row i writes, -1 when block k does not own it.  y0, y1: two scratch vectors
+// of the refined rows (full_off totals).  With add false the dofs no patch
+// owns are also cleared.  1 + sweeps launches.
 struct RefineView {
-  int nref, w16_kind;
-  const int *ref_patch, *pm, *po, *dof, *out_off, *own_local, *out_idx, *full_off;
+  int ntask, w16_kind, lpr;
+  const int *task_patch, *task_row0, *pm, *dof, *full_off, *own_dof;
   const int64_t *pdof_off, *woff_full;
-  const int *rptr_off, *rptr, *col, *src;
-  const float *jval, *rscale, *cscale;
+  CsrView<float> B;
+  float *gfull, *rho;
+  const float *rscale, *cscale;
   const int *unowned;
   int nunowned;
 };
+// out[q] = val[src[q]] (the refined blocks' values, refreshed at each refactor)
+void launch_gather_f32(const float *val, const int *src, int n, float *out, hipStream_t st);
 void launch_ras_refine(const RefineView &v, const float *W32, const uint16_t *W16, const float *s, float *e,
-                       float omega, bool add, int sweeps, hipStream_t st);
+                       float omega, bool add, int sweeps, float *y0, float *y1, hipStream_t st);
 
 // ---- coarsest solve (a7): y = W x, W row-major n x n FP64
 void launch_dense_gemv(const double *W, int n, const double *x, double *y, hipStream_t st);

@@ -504,81 +504,124 @@ __global__ __launch_bounds__(64 * NWV) void k_ras(RasView v, const WT *__restric
   }
 }
 
-// Refined local solve of one solid block per workgroup (see RefineView).
-// Thread t handles rows t, t + 512; within a 64-row chunk consecutive lanes
-// read consecutive rows of a column, so every column step is a coalesced
-// load.  16-bit storage: W~[r][c] = rs[r] w[r][c] cs[c]; the vector is
-// multiplied by cs as it enters LDS and each row's sum by rs[r].
-template <typename WT, bool IS16>
-__device__ __forceinline__ float full_row_dot(const WT *__restrict__ W, int m, int r, const float *xs,
-                                              int kind) {
-  const int r0 = r & ~63, nr = min(64, m - r0);
-  const WT *w = W + (int64_t)r0 * m + (r - r0);
-  float a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int c = 0;
-  for (; c + 8 <= m; c += 8) {
+static int ras_waves(int ntask);
+
+// out[q] = val[src[q]]: the refined blocks' entries of the FP32 operator
+__global__ void k_gather_f32(const float *__restrict__ val, const int *__restrict__ src, int n,
+                             float *__restrict__ out) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q < n) out[q] = val[src[q]];
+}
+void launch_gather_f32(const float *val, const int *src, int n, float *out, hipStream_t st) {
+  if (n > 0) k_gather_f32<<<cdiv(n, 256), 256, 0, st>>>(val, src, n, out);
+}
+// Refined local solves of the solid blocks (see RefineView), with the work
+// layout of k_ras: one workgroup per (block, 64 rows) task of every row of
+// the stored inverse, NWV waves splitting its columns.  MODE 0: y_out = W~ g
+// with g = s[I_k] (the first task of each block also keeps g).  MODE 1, a
+// refinement sweep after the block SpMV rho = g - B y_in:
+// y_out = y_in + W~ rho for its rows; the last sweep writes
+// omega y_out to the owned dofs of e instead (stores when add is 0, and then
+// also clears the dofs no patch owns).  16-bit storage: the gathered vector is
+// multiplied by the column scales, each row's sum by its row scale.
+template <typename WT, bool IS16, int NWV, int MODE>
+__global__ __launch_bounds__(64 * NWV) void k_refine(RefineView v, const WT *__restrict__ W,
+                                                     const float *__restrict__ s,
+                                                     const float *__restrict__ y_in,
+                                                     float *__restrict__ y_out, float *__restrict__ e,
+                                                     float omega, int add, int last) {
+  __shared__ float xs[kMaxPatch];
+  __shared__ float red[NWV - 1][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int k = v.task_patch[blockIdx.x], r0 = v.task_row0[blockIdx.x];
+  const int m = v.pm[k], fo = v.full_off[k];
+  const int *d = v.dof + v.pdof_off[k];
+  const int row = r0 + lane;
+  const bool live = row < m;
+  const int nr = min(64, m - r0);
+  const int share = (m + NWV - 1) / NWV;
+  const int c0 = wave * share, c1 = min(m, c0 + share);
+  const WT *w = W + v.woff_full[k] + (int64_t)r0 * m + (live ? lane : nr - 1);
+  auto load8 = [&](int c, float(&wv)[8]) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] += wload<WT, float, IS16>(w, (int64_t)(c + u) * nr, kind) * xs[c + u];
+    for (int u = 0; u < 8; ++u) wv[u] = wload<WT, float, IS16>(w, (int64_t)min(c + u, m - 1) * nr, v.w16_kind);
+  };
+  float cur[8];
+  load8(min(c0, m - 1), cur);
+  const float *cs = IS16 ? v.cscale + v.pdof_off[k] : nullptr;
+  for (int c = threadIdx.x; c < m; c += 64 * NWV) {
+    float g;
+    if constexpr (MODE == 0) {
+      g = s[d[c]];
+      if (r0 == 0) v.gfull[fo + c] = g;   // the block's right-hand side, for the residual
+    } else {
+      g = v.rho[fo + c];                   // g - B_k y_in, from the block SpMV
+    }
+    xs[c] = IS16 ? g * cs[c] : g;
   }
-  for (int u = 0; c + u < m; ++u) a[0] += wload<WT, float, IS16>(w, (int64_t)(c + u) * nr, kind) * xs[c + u];
-  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  if (MODE == 1 && last && !add)
+    for (int i = blockIdx.x * 64 * NWV + threadIdx.x; i < v.nunowned; i += gridDim.x * 64 * NWV)
+      e[v.unowned[i]] = 0.0f;
+  __syncthreads();
+  float a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int c = c0;
+  for (; c + 8 <= c1; c += 8) {
+    float nxt[8];
+    load8(c + 8, nxt);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += cur[u] * xs[c + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
+  }
+  for (int u = 0; c + u < c1; ++u) a[0] += cur[u] * xs[c + u];
+  float acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  if (wave > 0) red[wave - 1][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && live) {
+#pragma unroll
+    for (int q = 0; q < NWV - 1; ++q) acc += red[q][lane];
+    if constexpr (IS16) acc *= v.rscale[fo + row];
+    if constexpr (MODE == 0) {
+      y_out[fo + row] = acc;
+    } else {
+      const float yn = y_in[fo + row] + acc;
+      if (!last) {
+        y_out[fo + row] = yn;
+      } else {
+        const int gd = v.own_dof[fo + row];
+        if (gd >= 0) e[gd] = add ? e[gd] + omega * yn : omega * yn;
+      }
+    }
+  }
+}
+
+template <typename WT, bool IS16, int NWV>
+static void refine_nw(const RefineView &v, const WT *W, const float *s, float *e, float omega, bool add,
+                      int sweeps, float *y0, float *y1, hipStream_t st) {
+  k_refine<WT, IS16, NWV, 0><<<v.ntask, 64 * NWV, 0, st>>>(v, W, s, nullptr, y0, e, omega, (int)add, 0);
+  for (int sw = 0; sw < sweeps; ++sw) {
+    launch_spmv(v.B, y0, v.gfull, v.rho, kSpmvResid, v.lpr, st);
+    k_refine<WT, IS16, NWV, 1><<<v.ntask, 64 * NWV, 0, st>>>(v, W, s, y0, y1, e, omega, (int)add,
+                                                            sw + 1 == sweeps);
+    std::swap(y0, y1);
+  }
 }
 template <typename WT, bool IS16>
-__global__ __launch_bounds__(512) void k_ras_refine(RefineView v, const WT *__restrict__ Wfull,
-                                                    const float *__restrict__ s, float *__restrict__ e,
-                                                    float omega, int add, int sweeps) {
-  __shared__ float g[kMaxPatch], x[kMaxPatch], y[kMaxPatch];
-  const int k = v.ref_patch[blockIdx.x];
-  const int m = v.pm[k];
-  const int *d = v.dof + v.pdof_off[k];
-  const WT *W = Wfull + v.woff_full[k];
-  const int *rp = v.rptr + v.rptr_off[k];
-  const float *cs = IS16 ? v.cscale + v.pdof_off[k] : nullptr;
-  const float *rs = IS16 ? v.rscale + v.full_off[k] : nullptr;
-  for (int c = threadIdx.x; c < m; c += 512) {
-    g[c] = s[d[c]];
-    x[c] = IS16 ? g[c] * cs[c] : g[c];
-  }
-  if (!add)
-    for (int i = blockIdx.x * 512 + threadIdx.x; i < v.nunowned; i += gridDim.x * 512) e[v.unowned[i]] = 0.0f;
-  __syncthreads();
-  for (int r = threadIdx.x; r < m; r += 512) {
-    const float t = full_row_dot<WT, IS16>(W, m, r, x, v.w16_kind);
-    y[r] = IS16 ? t * rs[r] : t;
-  }
-  __syncthreads();
-  for (int sw = 0; sw < sweeps; ++sw) {
-    // the block residual g - B_k y in FP32, scaled like g for the product
-    for (int i = threadIdx.x; i < m; i += 512) {
-      float acc = g[i];
-      for (int q = rp[i]; q < rp[i + 1]; ++q) acc -= v.jval[v.src[q]] * y[v.col[q]];
-      x[i] = IS16 ? acc * cs[i] : acc;
-    }
-    __syncthreads();
-    float upd[2] = {0.0f, 0.0f};
-    for (int r = threadIdx.x, u = 0; r < m; r += 512, ++u) {
-      const float t = full_row_dot<WT, IS16>(W, m, r, x, v.w16_kind);
-      upd[u] = IS16 ? t * rs[r] : t;
-    }
-    __syncthreads();   // every row's update was computed from the same y
-    for (int r = threadIdx.x, u = 0; r < m; r += 512, ++u) y[r] += upd[u];
-    __syncthreads();
-  }
-  const int o = v.po[k];
-  for (int q = threadIdx.x; q < o; q += 512) {
-    const int i = v.own_local[v.out_off[k] + q];
-    const int gd = v.out_idx[v.out_off[k] + q];
-    const float u = omega * y[i];
-    e[gd] = add ? e[gd] + u : u;
+static void refine_any(const RefineView &v, const WT *W, const float *s, float *e, float omega, bool add,
+                       int sweeps, float *y0, float *y1, hipStream_t st) {
+  switch (ras_waves(v.ntask)) {
+    case 4: refine_nw<WT, IS16, 4>(v, W, s, e, omega, add, sweeps, y0, y1, st); break;
+    case 8: refine_nw<WT, IS16, 8>(v, W, s, e, omega, add, sweeps, y0, y1, st); break;
+    default: refine_nw<WT, IS16, 16>(v, W, s, e, omega, add, sweeps, y0, y1, st);
   }
 }
 void launch_ras_refine(const RefineView &v, const float *W32, const uint16_t *W16, const float *s, float *e,
-                       float omega, bool add, int sweeps, hipStream_t st) {
-  if (v.nref == 0) return;
+                       float omega, bool add, int sweeps, float *y0, float *y1, hipStream_t st) {
+  if (v.ntask == 0 || sweeps < 1) return;
   if (W16)
-    k_ras_refine<uint16_t, true><<<v.nref, 512, 0, st>>>(v, W16, s, e, omega, (int)add, sweeps);
+    refine_any<uint16_t, true>(v, W16, s, e, omega, add, sweeps, y0, y1, st);
   else
-    k_ras_refine<float, false><<<v.nref, 512, 0, st>>>(v, W32, s, e, omega, (int)add, sweeps);
+    refine_any<float, false>(v, W32, s, e, omega, add, sweeps, y0, y1, st);
 }
 
 // ev0/ev1 (optional, finest level): timing events recorded at the kernel's

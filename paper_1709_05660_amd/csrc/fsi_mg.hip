@@ -412,10 +412,34 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
         rptr.push_back((int)rcol.size());
       }
     }
-    L.d_ref_rptr_off = dupload(rptr_off.data(), np, own, st);
-    L.d_ref_rptr = dupload(rptr.data(), (int64_t)rptr.size(), own, st);
-    L.d_ref_col = dupload(rcol.data(), (int64_t)rcol.size(), own, st);
+    std::vector<int> own_dof(full_off[np], -1);
+    for (int k : ref_patch)
+      for (int i = 0; i < pm[k]; ++i)
+        if (P.owned[P.ptr[k] + i]) own_dof[full_off[k] + i] = P.dof[P.ptr[k] + i];
+    L.d_own_dof = dupload(own_dof.data(), (int64_t)own_dof.size(), own, st);
+    L.yref0 = dalloc<float>(full_off[np], own);
+    L.yref1 = dalloc<float>(full_off[np], own);
+    // the blocks as one CSR over the refined rows: row full_off[k] + i,
+    // columns full_off[k] + local column
+    std::vector<int> growptr(full_off[np] + 1, 0), gcol(rcol.size());
+    for (int k : ref_patch) {
+      const int base = rptr_off[k];
+      for (int i = 0; i < pm[k]; ++i) {
+        growptr[full_off[k] + i + 1] = rptr[base + i + 1] - rptr[base + i];
+        for (int q = rptr[base + i]; q < rptr[base + i + 1]; ++q) gcol[q] = full_off[k] + rcol[q];
+      }
+    }
+    for (size_t r = 0; r + 1 < growptr.size(); ++r) growptr[r + 1] += growptr[r];
+    // rows were appended in the same order as the refined rows, so the
+    // entries keep their order: growptr[full_off[k] + i] == rptr[rptr_off[k] + i]
+    L.ref_nnz = (int)rcol.size();
+    L.ref_lpr = pick_lpr(L.ref_nnz, full_off[np]);
+    L.d_ref_growptr = dupload(growptr.data(), (int64_t)growptr.size(), own, st);
+    L.d_ref_gcol = dupload(gcol.data(), (int64_t)gcol.size(), own, st);
     L.d_ref_src = dupload(rsrc.data(), (int64_t)rsrc.size(), own, st);
+    L.bref = dalloc<float>(L.ref_nnz, own);
+    L.gref = dalloc<float>(full_off[np], own);
+    L.rhoref = dalloc<float>(full_off[np], own);
   }
   // extraction map: one slot per CSR entry of every block row
   if (L.boff_total >= ((int64_t)1 << 31))
@@ -445,27 +469,24 @@ static RasView ras_view_solid(const Level &L) {
 }
 static RefineView refine_view(const Level &L) {
   RefineView v;
-  v.nref = L.nref;
-  v.ref_patch = L.d_ref_patch;
-  v.pm = L.d_pm;
-  v.po = L.d_po;
-  v.pdof_off = L.d_pdof_off;
-  v.dof = L.d_dof;
-  v.woff_full = L.d_woff_full;
-  v.out_off = L.d_out_off;
-  v.own_local = L.d_own_local;
-  v.out_idx = L.d_out_idx;
-  v.rptr_off = L.d_ref_rptr_off;
-  v.rptr = L.d_ref_rptr;
-  v.col = L.d_ref_col;
-  v.src = L.d_ref_src;
-  v.jval = L.J.val32;
-  v.unowned = L.d_unowned;
-  v.nunowned = L.n_unowned;
+  v.ntask = L.nftask;
   v.w16_kind = L.w16_kind;
+  v.lpr = L.ref_lpr;
+  v.task_patch = L.d_ftask_patch;
+  v.task_row0 = L.d_ftask_row0;
+  v.pm = L.d_pm;
+  v.dof = L.d_dof;
   v.full_off = L.d_full_off;
+  v.own_dof = L.d_own_dof;
+  v.pdof_off = L.d_pdof_off;
+  v.woff_full = L.d_woff_full;
+  v.B = CsrView<float>{(int)L.full_rows, (int)L.full_rows, L.ref_nnz, L.d_ref_growptr, L.d_ref_gcol, L.bref};
+  v.gfull = L.gref;
+  v.rho = L.rhoref;
   v.rscale = L.Wscale_full;
   v.cscale = L.Cscale;
+  v.unowned = L.d_unowned;
+  v.nunowned = L.n_unowned;
   return v;
 }
 
@@ -631,7 +652,11 @@ void refactor(MG &mg, hipStream_t st) {
   // host's graph launch overlaps the extraction
   hip_check(hipEventRecord(mg.ev_fork, st), "fork");
   if (mg.mixed)
-    for (int l = 1; l < mg.nlevels; ++l) launch_cast_d2f(mg.lv[l].J.val, mg.lv[l].J.val32, mg.lv[l].J.nnz, st);
+    for (int l = 1; l < mg.nlevels; ++l) {
+      Level &L = mg.lv[l];
+      launch_cast_d2f(L.J.val, L.J.val32, L.J.nnz, st);
+      if (L.nref) launch_gather_f32(L.J.val32, L.d_ref_src, L.ref_nnz, L.bref, st);   // refined blocks' B_k
+    }
   if (mg.nlevels > 1) extract_blocks(mg, st);
   hip_check(hipStreamWaitEvent(mg.side_stream, mg.ev_fork, 0), "fork wait");
   if (mg.opts.use_graph) {
@@ -705,7 +730,8 @@ static void ras32(MG &mg, Level &L, const float *s, float *e, bool add, hipStrea
   // the solid blocks apart: FP32 owned rows, or refined local solves
   if (L.ntask_s) launch_ras_f32(ras_view_solid(L), L.Ws, s, e, omega, false, add, st);
   if (L.nref)
-    launch_ras_refine(refine_view(L), L.Wfull32, L.Wfull16, s, e, omega, add, mg.opts.refine_sweeps, st);
+    launch_ras_refine(refine_view(L), L.Wfull32, L.Wfull16, s, e, omega, add, mg.opts.refine_sweeps, L.yref0,
+                      L.yref1, st);
 }
 
 // One V-cycle on level l for e = M_l^{-1} r (r and e distinct; the finest
