@@ -168,6 +168,7 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
              hipStream_t own_st, DevicePool *pool = nullptr, hipStream_t side_st = nullptr);
 void destroy_mg(MG *mg);
 void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts);
+void validate_levels_light(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts);
 void apply_vcycle(MG &mg, const double *r, double *z, hipStream_t st);
 void run_vcycle(MG &mg, const double *r, double *z, hipStream_t st);
 fsi_status fgmres(MG &mg, const double *b, double *x, const fsi_krylov_opts &ko, fsi_solve_info *info,

@@ -862,9 +862,7 @@ void alloc_level_vectors(MG &mg, Level &L) {
   }
 }
 
-// host-side checks of the whole hierarchy (no device call)
-void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts) {
-  if (!levels || nlevels < 1) throw Error(FSI_E_INVALID, "no levels");
+static void validate_opts(const fsi_mg_opts *opts) {
   if (!opts) throw Error(FSI_E_INVALID, "no options");
   if (opts->nu_pre < 0 || opts->nu_post < 0 || !(opts->omega > 0.0) ||
       opts->precision < FSI_PREC_FP64 || opts->precision > FSI_PREC_MIXED_FP32)
@@ -876,14 +874,9 @@ void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *op
                 "solid_precision must be -1, equal to precision, or FSI_PREC_MIXED_FP32 in a mixed hierarchy");
   if (opts->refine_sweeps < 0 || opts->refine_sweeps > 4 || (opts->refine_sweeps > 0 && !mixed))
     throw Error(FSI_E_INVALID, "refine_sweeps must be 0..4, and 0 for an FP64 hierarchy");
-  std::vector<int64_t> n(nlevels);
-  for (int l = 0; l < nlevels; ++l) n[l] = levels[l].J.nrows;
-  if (n[0] > kMaxCoarse) {
-    char buf[160];
-    snprintf(buf, sizeof buf, "coarsest level has %lld unknowns; the dense direct solve takes at most %d",
-             (long long)n[0], kMaxCoarse);
-    throw Error(FSI_E_INVALID, buf);
-  }
+}
+
+static void validate_hierarchy(const fsi_level *levels, int nlevels, const std::vector<int64_t> &n) {
   for (int l = 0; l < nlevels; ++l) {
     if (n[l] < 1) throw Error(FSI_E_INVALID, "empty level");
     validate_csr(levels[l].J, n[l], n[l], "J", l);
@@ -895,6 +888,62 @@ void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *op
     if (levels[l].dirichlet) validate_dirichlet(levels[l], n[l], l);
   }
 }
+
+// The checks a server's submit makes before estimating the footprint and
+// copying: options, dimensions across levels, CSR row offsets (monotone,
+// spanning nnz) and patch offsets and dofs in range.  O(n + sum of patch
+// sizes); the entries themselves are checked by validate_levels at setup.
+void validate_levels_light(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts) {
+  if (!levels || nlevels < 1) throw Error(FSI_E_INVALID, "no levels");
+  validate_opts(opts);
+  auto rows = [&](const fsi_csr &A, int64_t nr, int64_t nc, const char *name, int l) {
+    char buf[200];
+    if (A.nrows != nr || A.ncols != nc || A.nnz < 0 || A.nnz >= ((int64_t)1 << 31) || !A.rowptr ||
+        (A.nnz > 0 && (!A.colind || !A.val)) || A.rowptr[0] != 0 || A.rowptr[A.nrows] != A.nnz) {
+      snprintf(buf, sizeof buf, "level %d %s: dimensions, arrays or row offsets invalid", l, name);
+      throw Error(FSI_E_INVALID, buf);
+    }
+    for (int64_t r = 0; r < A.nrows; ++r)
+      if (A.rowptr[r + 1] < A.rowptr[r]) {
+        snprintf(buf, sizeof buf, "level %d %s: row offsets not monotone", l, name);
+        throw Error(FSI_E_INVALID, buf);
+      }
+  };
+  for (int l = 0; l < nlevels; ++l) {
+    const int64_t n = levels[l].J.nrows;
+    if (n < 1) throw Error(FSI_E_INVALID, "empty level");
+    if (l == 0 && n > kMaxCoarse) throw Error(FSI_E_INVALID, "coarsest level too large for the direct solve");
+    rows(levels[l].J, n, n, "J", l);
+    if (l == 0) continue;
+    const int64_t nc = levels[l - 1].J.nrows;
+    rows(levels[l].P, n, nc, "P", l);
+    rows(levels[l].R, nc, n, "R", l);
+    const fsi_patches &P = levels[l].patches;
+    if (P.npatch <= 0 || !P.ptr || !P.dof || !P.owned || P.ptr[0] != 0)
+      throw Error(FSI_E_INVALID, "patches missing or malformed");
+    for (int k = 0; k < P.npatch; ++k)
+      if (P.ptr[k + 1] <= P.ptr[k] || P.ptr[k + 1] - P.ptr[k] > kMaxPatch)
+        throw Error(FSI_E_INVALID, "patch offsets invalid or a patch larger than the supported block size");
+    for (int64_t p = 0; p < P.ptr[P.npatch]; ++p)
+      if (P.dof[p] < 0 || P.dof[p] >= n) throw Error(FSI_E_INVALID, "patch dof out of range");
+  }
+}
+
+// host-side checks of the whole hierarchy (no device call)
+void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts) {
+  if (!levels || nlevels < 1) throw Error(FSI_E_INVALID, "no levels");
+  validate_opts(opts);
+  std::vector<int64_t> n(nlevels);
+  for (int l = 0; l < nlevels; ++l) n[l] = levels[l].J.nrows;
+  if (n[0] > kMaxCoarse) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "coarsest level has %lld unknowns; the dense direct solve takes at most %d",
+             (long long)n[0], kMaxCoarse);
+    throw Error(FSI_E_INVALID, buf);
+  }
+  validate_hierarchy(levels, nlevels, n);
+}
+
 
 int autotune(MG &mg, const char *db_path, hipStream_t st);
 

@@ -17,6 +17,8 @@
 #include <memory>
 #include <mutex>
 #include <set>
+#include <functional>
+#include <tuple>
 #include <thread>
 
 #include "fsi_internal.h"
@@ -26,13 +28,11 @@ namespace fsi {
 using Clock = std::chrono::steady_clock;
 constexpr int kSetupThreads = 6;   // concurrent setups (each on its system's stream)
 constexpr int kTickThreads = 2;    // threads that advance the active systems (each owns a share)
+constexpr int kCopyThreads = 4;    // threads that copy submitted requests (with the submitting thread)
 
 struct Request {
   uint64_t ticket = 0;
-  std::vector<std::vector<int64_t>> i64;
-  std::vector<std::vector<int32_t>> i32;
-  std::vector<std::vector<double>> f64;
-  std::vector<std::vector<uint8_t>> u8;
+  std::unique_ptr<char[]> buf;   // every array of the request, one uninitialised host block
   std::vector<fsi_level> levels;
   std::vector<double> b;
   fsi_mg_opts mo{};
@@ -60,9 +60,88 @@ struct Done {
   std::string msg;
 };
 
+// Copies of large requests are split in chunks over the server's copy
+// threads (and the submitting thread): one thread's memcpy bandwidth bounded
+// the serving rate.  Each submit waits for its own chunks only.
+struct CopyPool {
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<std::function<void()>> jobs;
+  std::vector<std::thread> th;
+  bool stop = false;
+  void start(int n) {
+    for (int i = 0; i < n; ++i)
+      th.emplace_back([this] {
+        while (true) {
+          std::function<void()> job;
+          {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return stop || !jobs.empty(); });
+            if (jobs.empty()) return;
+            job = std::move(jobs.front());
+            jobs.pop_front();
+          }
+          job();
+        }
+      });
+  }
+  // runs the copies (dst, src, bytes) in chunks; returns when all are done
+  void copy(const std::vector<std::tuple<void *, const void *, size_t>> &cps) {
+    constexpr size_t kChunk = 1u << 21;
+    struct Wait {
+      std::mutex mu;
+      std::condition_variable cv;
+      int left = 0;
+    };
+    auto w = std::make_shared<Wait>();
+    std::vector<std::function<void()>> mine;
+    for (auto &c : cps)
+      for (size_t off = 0; off < std::get<2>(c); off += kChunk) {
+        char *d = static_cast<char *>(std::get<0>(c)) + off;
+        const char *sp = static_cast<const char *>(std::get<1>(c)) + off;
+        const size_t nb = std::min(kChunk, std::get<2>(c) - off);
+        mine.push_back([d, sp, nb, w] {
+          std::memcpy(d, sp, nb);
+          std::lock_guard<std::mutex> lk(w->mu);
+          if (--w->left == 0) w->cv.notify_all();
+        });
+      }
+    w->left = (int)mine.size();
+    if (mine.empty()) return;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (size_t i = 1; i < mine.size(); ++i) jobs.push_back(mine[i]);
+    }
+    cv.notify_all();
+    mine[0]();   // the submitting thread copies too
+    for (;;) {   // and takes further chunks while any are queued
+      std::function<void()> job;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        if (jobs.empty()) break;
+        job = std::move(jobs.front());
+        jobs.pop_front();
+      }
+      job();
+    }
+    std::unique_lock<std::mutex> lk(w->mu);
+    w->cv.wait(lk, [&] { return w->left == 0; });
+  }
+  void shutdown() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv.notify_all();
+    for (auto &t : th)
+      if (t.joinable()) t.join();
+  }
+};
+
 struct Server {
   fsi_server_opts o{};
   DevicePool pool;   // destroyed after every system (declared first)
+  CopyPool copies;   // request copies at submit
   std::mutex mu;
   std::vector<std::pair<hipStream_t, hipStream_t>> free_streams;   // (main, side) pairs
   std::condition_variable cv;
@@ -134,48 +213,60 @@ static int64_t footprint(const fsi_level *lv, int nl, const fsi_mg_opts &mo,
   return res + transient + slack;
 }
 
+// The request's arrays in one host block (8-byte aligned pieces), copied by
+// the pool: J, P, R, patch lists and Dirichlet flags of every level, b.
 static std::unique_ptr<Request> copy_request(const fsi_level *lv, int nl, const double *b,
-                                             const fsi_mg_opts &mo, const fsi_krylov_opts &ko) {
+                                             const fsi_mg_opts &mo, const fsi_krylov_opts &ko,
+                                             CopyPool &pool) {
   std::unique_ptr<Request> r(new Request());
   r->levels.resize(nl);
-  auto cp_csr = [&](const fsi_csr &A) {
-    fsi_csr c = A;
-    r->i64.emplace_back(A.rowptr, A.rowptr + A.nrows + 1);
-    r->i32.emplace_back(A.colind, A.colind + A.nnz);
-    r->f64.emplace_back(A.val, A.val + A.nnz);
-    c.rowptr = r->i64.back().data();
-    c.colind = r->i32.back().data();
-    c.val = r->f64.back().data();
-    return c;
+  std::vector<std::tuple<void *, const void *, size_t>> cps;
+  size_t total = 0;
+  auto room = [&](size_t bytes) {
+    const size_t off = total;
+    total += (bytes + 7) / 8 * 8;
+    return off;
   };
-  // reserve so that data() pointers stay valid while emplacing
-  r->i64.reserve(4 * nl);
-  r->i32.reserve(4 * nl);
-  r->f64.reserve(4 * nl);
-  r->u8.reserve(2 * nl);   // owned and kind per level (the Dirichlet flags were checked at submit)
+  // first pass: offsets; second pass: pointers and copies
+  struct Piece {
+    const void *src;
+    size_t bytes, off;
+    const void **dst;
+  };
+  std::vector<Piece> pieces;
+  auto add = [&](const void *src, size_t bytes, const void **dst) {
+    if (src && bytes) pieces.push_back({src, bytes, room(bytes), dst});
+    else *dst = src;
+  };
   for (int l = 0; l < nl; ++l) {
     fsi_level &L = r->levels[l];
     std::memset(&L, 0, sizeof L);
-    L.J = cp_csr(lv[l].J);
+    auto csr = [&](const fsi_csr &A, fsi_csr &C) {
+      C = A;
+      add(A.rowptr, sizeof(int64_t) * (size_t)(A.nrows + 1), (const void **)&C.rowptr);
+      add(A.colind, sizeof(int32_t) * (size_t)A.nnz, (const void **)&C.colind);
+      add(A.val, sizeof(double) * (size_t)A.nnz, (const void **)&C.val);
+    };
+    csr(lv[l].J, L.J);
+    add(lv[l].dirichlet, (size_t)lv[l].J.nrows, (const void **)&L.dirichlet);
     if (l > 0) {
-      L.P = cp_csr(lv[l].P);
-      L.R = cp_csr(lv[l].R);
+      csr(lv[l].P, L.P);
+      csr(lv[l].R, L.R);
       const fsi_patches &P = lv[l].patches;
-      if (!P.ptr || P.npatch <= 0) throw Error(FSI_E_INVALID, "missing patches");
       const int64_t tot = P.ptr[P.npatch];
       L.patches.npatch = P.npatch;
-      r->i64.emplace_back(P.ptr, P.ptr + P.npatch + 1);
-      L.patches.ptr = r->i64.back().data();
-      r->i32.emplace_back(P.dof, P.dof + tot);
-      L.patches.dof = r->i32.back().data();
-      r->u8.emplace_back(P.owned, P.owned + tot);
-      L.patches.owned = r->u8.back().data();
-      if (P.kind) {
-        r->u8.emplace_back(P.kind, P.kind + P.npatch);
-        L.patches.kind = r->u8.back().data();
-      }
+      add(P.ptr, sizeof(int64_t) * (size_t)(P.npatch + 1), (const void **)&L.patches.ptr);
+      add(P.dof, sizeof(int32_t) * (size_t)tot, (const void **)&L.patches.dof);
+      add(P.owned, (size_t)tot, (const void **)&L.patches.owned);
+      add(P.kind, (size_t)P.npatch, (const void **)&L.patches.kind);
     }
   }
+  r->buf.reset(new char[std::max<size_t>(total, 8)]);
+  for (auto &pc : pieces) {
+    *pc.dst = r->buf.get() + pc.off;
+    cps.emplace_back(r->buf.get() + pc.off, pc.src, pc.bytes);
+  }
+  pool.copy(cps);
   r->b.assign(b, b + lv[nl - 1].J.nrows);
   r->mo = mo;
   r->mo.tuning_db = nullptr;   // served systems are not autotuned per request
@@ -367,6 +458,7 @@ fsi_status fsi_server_create(const fsi_server_opts *o, struct fsi_server **out) 
       }
       S->free_streams.push_back({a, b});
     }
+    S->copies.start(kCopyThreads);
     for (int i = 0; i < kSetupThreads; ++i) S->setup_threads.emplace_back(setup_loop, S);
     for (int i = 0; i < kTickThreads; ++i) S->tick_threads.emplace_back(tick_loop, S, i);
     *out = reinterpret_cast<fsi_server *>(S);
@@ -384,13 +476,16 @@ fsi_status fsi_serve_submit(struct fsi_server *h, const fsi_level *levels, int32
     Server *S = reinterpret_cast<Server *>(h);
     if (!S || !levels || nlevels < 1 || !b_host || !mo || !ko || !ticket)
       throw Error(FSI_E_INVALID, "null argument");
-    validate_levels(levels, nlevels, mo);
+    // the checks that the footprint estimate and the copy rely on; the full
+    // check of every CSR entry and patch list runs in a setup thread (a
+    // malformed request fails there and its ticket reports FSI_E_INVALID)
+    validate_levels_light(levels, nlevels, mo);
     validate_krylov(*ko);
     if (ko->x0_nonzero) throw Error(FSI_E_INVALID, "a served request starts from x0 = 0");
     int64_t transient = 0;
     const int64_t fp = footprint(levels, nlevels, *mo, *ko, &transient);
     if (fp > S->o.hbm_budget_bytes) throw Error(FSI_E_CAPACITY, "request larger than the memory budget");
-    std::unique_ptr<Request> r = copy_request(levels, nlevels, b_host, *mo, *ko);
+    std::unique_ptr<Request> r = copy_request(levels, nlevels, b_host, *mo, *ko, S->copies);
     r->footprint = fp;
     r->transient = transient;
     r->t_submit = Clock::now();
@@ -454,6 +549,7 @@ fsi_status fsi_server_destroy(struct fsi_server *h) {
     if (t.joinable()) t.join();
   for (auto &t : S->tick_threads)
     if (t.joinable()) t.join();
+  S->copies.shutdown();
   drain(S);
   for (auto &p : S->free_streams) {
     (void)hipStreamDestroy(p.first);

@@ -151,3 +151,29 @@ def test_recycled_memory_gives_identical_results():
     srv.close()
     assert np.array_equal(runs[0], runs[2])
     assert np.array_equal(runs[0], runs[4])
+
+
+def test_malformed_request_is_reported_at_poll():
+    """Submit checks options, sizes and offsets; the entries are checked by a
+    setup thread, and a malformed request fails alone with FSI_E_INVALID at
+    poll while the next request is served."""
+    from paper_1709_05660_amd import Server
+    probs = _problems()[:2]
+    bad = probs[0]
+    J = bad.levels[bad.nlevels - 1].J
+    ci = np.ctypeslib.as_array(J.colind, shape=(J.nnz,))
+    rp = np.ctypeslib.as_array(J.rowptr, shape=(J.nrows + 1,))
+    r = int(np.argmax(np.diff(rp) >= 3))
+    a = int(rp[r])
+    srv = Server(hbm_budget_bytes=8 << 30, max_slots=4)
+    ci[a], ci[a + 1] = ci[a + 1], ci[a]
+    try:
+        t_bad = srv.submit(bad, precision="bf16", rtol=1e-8)
+    finally:
+        ci[a], ci[a + 1] = ci[a + 1], ci[a]    # the request holds its own copy
+    t_good = srv.submit(probs[1], precision="bf16", rtol=1e-8)
+    st, x, info = _wait(srv, t_bad)
+    assert st == -1 and "strictly increasing" in info["error"]
+    st, x, info = _wait(srv, t_good)
+    assert st == 0
+    srv.close()
