@@ -269,12 +269,28 @@ def seeded_state(mesh, spec, coeffs):
     dofs are 0 and the solid pressure level is mu_s (stress-free solid at d = 0).
     """
     dim = mesh.dim
-    x = mesh.xnode
     flag, val = mesh.dirichlet(spec.u_peak)
     y = np.zeros(mesh.ndof)
-    K = coeffs.shape[1]
     prof = mesh.inflow_profile(spec.u_peak)
     free_f = mesh.nclass == FLUID
+    shapes = fourier_shapes(mesh, coeffs)
+    for c in range(dim):
+        du = spec.amp * shapes[c]
+        base = prof if c == 0 else 0.0
+        uc = np.where(free_f, base + du, 0.0)
+        y[mesh.u_dof(c, np.arange(mesh.N2))] = uc
+    y[mesh.solid_pressure_dofs()] = spec.mu_s
+    y[flag] = val[flag]
+    return y
+
+
+def fourier_shapes(mesh, coeffs):
+    """S_c / max|S_c| at the Q2 nodes, c = 0..dim-1, with
+    S_c = sum_{k,l(,m)=1..K} a_{c,k,l(,m)} / (k^2+l^2(+m^2)) prod sin(k pi x / L)."""
+    dim = mesh.dim
+    x = mesh.xnode
+    K = coeffs.shape[1]
+    out = []
     for c in range(dim):
         S = np.zeros(mesh.N2)
         for ks in itertools.product(range(1, K + 1), repeat=dim):
@@ -282,13 +298,24 @@ def seeded_state(mesh, spec, coeffs):
             for d in range(dim):
                 term = term * np.sin(ks[d] * np.pi * x[:, d] / mesh.L[d])
             S += term
-        du = spec.amp * S / np.max(np.abs(S))
-        base = prof if c == 0 else 0.0
-        uc = np.where(free_f, base + du, 0.0)
-        y[mesh.u_dof(c, np.arange(mesh.N2))] = uc
-    y[mesh.solid_pressure_dofs()] = spec.mu_s
-    y[flag] = val[flag]
-    return y
+        out.append(S / np.max(np.abs(S)))
+    return out
+
+
+def transient_states(mesh, spec, coeffs):
+    """States of one Crank-Nicolson time step: y_n = the seeded state, and the
+    Newton iterate y_{n+1} at which the Jacobian is taken: y_n with every free
+    displacement dof moved by amp_d * S_c / max|S_c| (the shape of the
+    velocity perturbation); Dirichlet dofs keep their boundary values."""
+    y0 = seeded_state(mesh, spec, coeffs)
+    y1 = y0.copy()
+    flag, _ = mesh.dirichlet(spec.u_peak)
+    shapes = fourier_shapes(mesh, coeffs)
+    nodes = np.arange(mesh.N2)
+    for c in range(mesh.dim):
+        dd = mesh.d_dof(c, nodes)
+        y1[dd] += np.where(flag[dd], 0.0, spec.amp_d * shapes[c])
+    return y0, y1
 
 
 # ------------------------------------------------------------- integrands
@@ -313,6 +340,79 @@ def _det_inv(F):
     det = F[..., 0, 0] * cof[..., 0, 0] + F[..., 0, 1] * cof[..., 0, 1] + F[..., 0, 2] * cof[..., 0, 2]
     inv = np.swapaxes(cof, -1, -2) / det[..., None, None]
     return det, inv
+
+
+def _kinematics(T, dim, Ue):
+    """Displacement/velocity/pressure fields of a batch of elements at the
+    quadrature points: d, u, p (nodal), grad_hat d, F, J, F^{-1}, p_q, u_q."""
+    na = T.N.shape[1]
+    E = Ue.shape[0]
+    d = Ue[:, : dim * na].reshape(E, dim, na)
+    u = Ue[:, dim * na: 2 * dim * na].reshape(E, dim, na)
+    p = Ue[:, 2 * dim * na:]
+    Gd = np.einsum("eca,qak->eqck", d, T.dN)
+    F = Gd + np.eye(dim)
+    Jd, Finv = _det_inv(F)
+    pq = np.einsum("ev,qv->eq", p, T.psi)
+    uq = np.einsum("eca,qa->eqc", u, T.N)
+    return d, u, p, Gd, F, Jd, Finv, pq, uq
+
+
+def element_residual_cn(mesh, spec, Ue, Ue0, solid, k_scale=1.0):
+    """Local residuals of one Crank-Nicolson step (section "Discretization of
+    the operator formulation", the time-discretized operators F_n, S_n):
+    the state at t_{n+1} is Ue (real or complex), the state at t_n is Ue0.
+    Fluid momentum: (rho/dt)(u1 J1 - u0 J0) phi, then half of each of
+    -rho div(w) u phi + rho ((u - w).grad) u phi + sigma : grad phi on the
+    configuration of t_{n+1} (from Ue) and of t_n (from Ue0), with the mesh
+    velocity w = (d1 - d0)/dt; continuity at t_{n+1}; mesh motion as in the
+    steady form, at t_{n+1}.  Solid momentum: (rho_s/dt)(J1 u1 - J0 u0) phi
+    plus half of each Piola stress term; incompressibility (J1 - 1) psi;
+    kinematics -(d1 - d0)/dt + (u1 + u0)/2 against phi.  Returns (mom, aux, pres)
+    as element_residual."""
+    dim = mesh.dim
+    T = mesh.tab
+    dt = spec.dt
+    w = T.w
+    eye = np.eye(dim)
+    d1, u1, p1, Gd1, F1, J1, Fi1, pq1, uq1 = _kinematics(T, dim, Ue)
+    d0, u0, p0, Gd0, F0, J0, Fi0, pq0, uq0 = _kinematics(T, dim, Ue0)
+    if not solid:
+        wq = np.einsum("eca,qa->eqc", (d1 - d0) / dt, T.N)          # mesh velocity
+        Gw = (Gd1 - Gd0) / dt                                        # grad_hat w
+        gu1 = np.einsum("eqck,eqkb->eqcb", np.einsum("eca,qak->eqck", u1, T.dN), Fi1)
+        gu0 = np.einsum("eqck,eqkb->eqcb", np.einsum("eca,qak->eqck", u0, T.dN), Fi0)
+        divw1 = np.einsum("eqck,eqkc->eq", Gw, Fi1)
+        divw0 = np.einsum("eqck,eqkc->eq", Gw, Fi0)
+        sig1 = -pq1[..., None, None] * eye + spec.mu * (gu1 + np.swapaxes(gu1, -1, -2))
+        sig0 = -pq0[..., None, None] * eye + spec.mu * (gu0 + np.swapaxes(gu0, -1, -2))
+        rho = spec.rho
+        v1 = (rho / dt) * uq1 - 0.5 * rho * divw1[..., None] * uq1 \
+            + 0.5 * rho * np.einsum("eqcb,eqb->eqc", gu1, uq1 - wq)
+        v0 = -(rho / dt) * uq0 - 0.5 * rho * divw0[..., None] * uq0 \
+            + 0.5 * rho * np.einsum("eqcb,eqb->eqc", gu0, uq0 - wq)
+        gphi1 = np.einsum("qak,eqkb->eqab", T.dN, Fi1)
+        gphi0 = np.einsum("qak,eqkb->eqab", T.dN, Fi0)
+        wJ1, wJ0 = w * J1, w * J0
+        mom = (np.einsum("eq,eqc,qa->eca", wJ1, v1, T.N) + np.einsum("eq,eqc,qa->eca", wJ0, v0, T.N)
+               + 0.5 * np.einsum("eq,eqcb,eqab->eca", wJ1, sig1, gphi1)
+               + 0.5 * np.einsum("eq,eqcb,eqab->eca", wJ0, sig0, gphi0))
+        pres = np.einsum("eq,qv->ev", wJ1 * np.einsum("eqcc->eq", gu1), T.psi)
+        k = k_scale / T.vol
+        aux = k * np.einsum("q,eqcb,qab->eca", w, Gd1, T.dN)
+    else:
+        def piola(F, J, Fi, pq):
+            sig = -pq[..., None, None] * eye + spec.mu_s * np.einsum("eqik,eqjk->eqij", F, F)
+            return J[..., None, None] * np.einsum("eqck,eqbk->eqcb", sig, Fi)
+        P1, P0 = piola(F1, J1, Fi1, pq1), piola(F0, J0, Fi0, pq0)
+        mass = (spec.rho_s / dt) * (J1[..., None] * uq1 - J0[..., None] * uq0)
+        mom = np.einsum("q,eqc,qa->eca", w, mass, T.N) + 0.5 * np.einsum("q,eqcb,qab->eca", w, P1 + P0, T.dN)
+        pres = np.einsum("q,eq,qv->ev", w, J1 - 1.0, T.psi)
+        dq1 = np.einsum("eca,qa->eqc", d1, T.N)
+        dq0 = np.einsum("eca,qa->eqc", d0, T.N)
+        kin = -(dq1 - dq0) / dt + 0.5 * (uq1 + uq0)
+        aux = np.einsum("q,eqc,qa->eca", w, kin, T.N)
+    return mom, aux, pres
 
 
 def element_residual(mesh, spec, Ue, solid, k_scale=1.0):
@@ -363,13 +463,17 @@ def element_residual(mesh, spec, Ue, solid, k_scale=1.0):
     return mom, aux, pres
 
 
-def local_rows(mesh, solid_mat):
+def local_rows(mesh, solid_mat, transient=False):
     """Structural dependency mask (nloc_rows x nloc_cols) of one element type.
 
     Local rows are [mom(c,a), aux(c,a), pres(v)], local columns [d(c,a), u(c,a), p(v)].
     Fluid: momentum depends on d, u, p; mesh motion (harmonic) on the same
     displacement component; continuity on d and u.  Solid (steady): momentum
     on d and p; kinematics on the same velocity component; incompressibility on d.
+    A Crank-Nicolson step adds the solid momentum's dependence on the same
+    velocity component (mass) and the kinematics' on the same displacement
+    component (section "Structure of the Jacobian": the blocks that vanish
+    only in the steady case).
     """
     dim = mesh.dim
     na = mesh.tab.N.shape[1]
@@ -392,6 +496,9 @@ def local_rows(mesh, solid_mat):
         M[0:nd, sl_p] = True
         M[nd:2 * nd, sl_u] = same
         M[2 * nd:, sl_d] = True
+        if transient:
+            M[0:nd, sl_u] = same
+            M[nd:2 * nd, sl_d] = same
     return M
 
 
@@ -421,7 +528,7 @@ def row_targets(mesh):
     return np.concatenate([tgt_mom.reshape(ne, -1), tgt_aux.reshape(ne, -1), mesh.epdofs()], axis=1)
 
 
-def assemble(mesh, spec, y, jacobian=True, h=1e-30, k_scale=1.0):
+def assemble(mesh, spec, y, jacobian=True, h=1e-30, k_scale=1.0, y_prev=None):
     """Residual r(y) (Dirichlet rows y_j - g_j) and the exact Jacobian (CSR, FP64).
 
     The Jacobian of every element is obtained column by column by the complex
@@ -429,7 +536,14 @@ def assemble(mesh, spec, y, jacobian=True, h=1e-30, k_scale=1.0):
     of `local_rows` are stored (values may be zero); Dirichlet rows become
     identity rows and Dirichlet columns are dropped.  `k_scale` multiplies
     the mesh-motion coefficient k = 1/V_el (used to evaluate k on another level).
+    With y_prev (the state at t_n) the residual is that of one Crank-Nicolson
+    step taken at the state y at t_{n+1} (element_residual_cn).
     """
+    def local(Ue, solid):
+        if y_prev is None:
+            return element_residual(mesh, spec, Ue, solid, k_scale)
+        return element_residual_cn(mesh, spec, Ue, y_prev[l2g[els]], solid, k_scale)
+
     flag, val = mesh.dirichlet(spec.u_peak)
     l2g = mesh.loc2glob()
     tgt = row_targets(mesh)
@@ -441,7 +555,7 @@ def assemble(mesh, spec, y, jacobian=True, h=1e-30, k_scale=1.0):
         if els.size == 0:
             continue
         Ue = y[l2g[els]]
-        mom, aux, pres = element_residual(mesh, spec, Ue, solid, k_scale)
+        mom, aux, pres = local(Ue, solid)
         Rl = np.concatenate([mom.reshape(len(els), -1), aux.reshape(len(els), -1), pres], axis=1)
         T = tgt[els]
         ok = T >= 0
@@ -453,9 +567,9 @@ def assemble(mesh, spec, y, jacobian=True, h=1e-30, k_scale=1.0):
         for j in range(nl):
             Up = Uc.copy()
             Up[:, j] += 1j * h
-            m2, a2, p2 = element_residual(mesh, spec, Up, solid, k_scale)
+            m2, a2, p2 = local(Up, solid)
             Jl[:, :, j] = np.concatenate([m2.reshape(len(els), -1), a2.reshape(len(els), -1), p2], axis=1).imag / h
-        M = local_rows(mesh, solid)
+        M = local_rows(mesh, solid, y_prev is not None)
         C = l2g[els]
         RR = np.broadcast_to(T[:, :, None], Jl.shape)
         CC = np.broadcast_to(C[:, None, :], Jl.shape)

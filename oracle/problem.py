@@ -40,8 +40,12 @@ def build(spec, coeffs, factor=True):
     meshes = [fem.Mesh(spec, s) for s in sizes]
     flags = [m.dirichlet(spec.u_peak)[0] for m in meshes]
     fine = meshes[-1]
-    y = fem.seeded_state(fine, spec, coeffs)
-    r, J = fem.assemble(fine, spec, y)
+    if getattr(spec, "transient", False):
+        y_prev, y = fem.transient_states(fine, spec, coeffs)
+        r, J = fem.assemble(fine, spec, y, y_prev=y_prev)
+    else:
+        y = fem.seeded_state(fine, spec, coeffs)
+        r, J = fem.assemble(fine, spec, y)
     b = -r
     b[flags[-1]] = 0.0
     levels = [None] * spec.levels

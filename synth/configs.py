@@ -32,6 +32,13 @@ class ProblemSpec:
     amp: float = 0.05            # velocity perturbation amplitude
     pressure: str = "p1disc"     # "p1disc" (the paper's Q2-P1disc) or "q1" (continuous per material)
     seed: int = 1
+    # Crank-Nicolson time step (transient): the linearisation is a Newton
+    # iterate at t_{n+1} whose displacement differs from the state at t_n by
+    # amp_d times the normalised Fourier shape of the velocity perturbation
+    transient: bool = False
+    dt: float = 0.01             # the paper's FSI3-T-2D time step
+    rho_s: float = 1000.0        # solid density
+    amp_d: float = 1.0e-3
     # solver settings
     nu_pre: int = 2
     nu_post: int = 2
@@ -60,6 +67,11 @@ CONFIGS = {
     # same system, mixed-precision V-cycle, target true residual 1e-8
     "c2_2d_128x32_mixed": ProblemSpec(dim=2, nx=128, ny=32, levels=4, patch=4, rtol=1e-8,
                                       name="2d_128x32_L4_p4_mixed"),
+    # one Crank-Nicolson time step of the 128x32 system and of the 16x4 system
+    "c4_2d_128x32_cn": ProblemSpec(dim=2, nx=128, ny=32, levels=4, patch=4, rtol=1e-10, transient=True,
+                                   name="2d_128x32_L4_p4_cn"),
+    "c5_2d_16x4_cn": ProblemSpec(dim=2, nx=16, ny=4, levels=2, patch=2, rtol=1e-10, transient=True,
+                                 name="2d_16x4_L2_p2_cn"),
     # 3D 32x8x8, 3 levels (coarsest 8x2x2), 2x2x2 patches, mixed, rtol 1e-8
     "c3_3d_32x8x8": ProblemSpec(dim=3, nx=32, ny=8, nz=8, levels=3, patch=2, rtol=1e-8,
                                 name="3d_32x8x8_L3_p2"),
