@@ -291,9 +291,12 @@ fsi_status fsi_server_create(const fsi_server_opts *o, struct fsi_server **out);
 /* Section "Details on the iterative solver" applied to independent systems
  * (the paper solves one system at a time; serving them together is this
  * library's).  Copies the request (levels, b; mo->tuning_db is ignored) and
- * queues it; returns a ticket.  Errors at submit: FSI_E_INVALID (malformed
- * hierarchy or options; ko->x0_nonzero must be 0), FSI_E_CAPACITY (the
- * request's estimated footprint exceeds the budget). */
+ * queues it; returns a ticket.  Errors at submit: FSI_E_INVALID (options,
+ * level dimensions, row or patch offsets, patch dofs out of range;
+ * ko->x0_nonzero must be 0), FSI_E_CAPACITY (the request's estimated
+ * footprint exceeds the budget).  The entries themselves (column order and
+ * range, patch partition, Dirichlet flags) are checked by the setup thread:
+ * such a request fails alone and its poll returns FSI_E_INVALID. */
 fsi_status fsi_serve_submit(struct fsi_server *s, const fsi_level *levels, int32_t nlevels,
                             const double *b_host, const fsi_mg_opts *mo, const fsi_krylov_opts *ko,
                             uint64_t *ticket);
