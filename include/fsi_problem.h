@@ -13,7 +13,8 @@
  *
  * Discretisation: Q2 displacement/velocity, P1disc pressure (the paper's
  * Q2-P1disc pair), harmonic mesh motion with k = 1/V_el, incompressible
- * neo-Hookean solid sigma = -p I + mu_s F F^T, Newtonian fluid; steady.
+ * neo-Hookean solid sigma = -p I + mu_s F F^T, Newtonian fluid; steady, or
+ * one Crank-Nicolson time step (spec.transient).
  * Dof order: d_c then u_c over the Q2 nodes (x fastest), then dim+1 pressure
  * dofs per element.  Dirichlet dofs are identity rows with dropped columns.
  *
@@ -46,6 +47,15 @@ typedef struct {
   double amp;              /* velocity perturbation amplitude */
   int32_t kmax;            /* Fourier modes per direction of the perturbation */
   const double *coeffs;    /* dim * kmax^dim coefficients in [-1,1], order (c, k, l[, m]) */
+  /* One Crank-Nicolson time step (section "Discretization of the operator
+   * formulation") instead of the steady problem when transient != 0: the
+   * state at t_n is the seeded state, the Jacobian is taken at the Newton
+   * iterate at t_{n+1} whose free displacements are moved by amp_d times the
+   * normalised Fourier shape of the velocity perturbation. */
+  int32_t transient;
+  double dt;               /* time step */
+  double rho_s;            /* solid density */
+  double amp_d;            /* displacement increment of the iterate */
 } fsi_problem_spec;
 
 struct fsi_problem;
@@ -58,7 +68,8 @@ fsi_status fsi_problem_levels(const struct fsi_problem *p, fsi_level *levels);
 fsi_status fsi_problem_vectors(const struct fsi_problem *p, const double **b, const double **y,
                                int64_t *n);
 fsi_status fsi_problem_dirichlet(const struct fsi_problem *p, int32_t level, const uint8_t **flags);
-/* element residual of the finest level at state y (for tests): r (n doubles) */
+/* residual of the finest level at state y (for tests): r (n doubles); for a
+ * transient problem the state at t_n is the seeded one */
 fsi_status fsi_problem_residual(const struct fsi_problem *p, const double *y, double *r);
 fsi_status fsi_problem_destroy(struct fsi_problem *p);
 /* thread-local message of the last failed fsi_problem_build of the calling thread */

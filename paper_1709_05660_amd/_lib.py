@@ -73,7 +73,8 @@ class ProblemSpecC(C.Structure):
                 ("solid_lo", C.c_double * 3), ("solid_hi", C.c_double * 3),
                 ("rho", C.c_double), ("mu", C.c_double), ("mu_s", C.c_double),
                 ("u_peak", C.c_double), ("amp", C.c_double), ("kmax", C.c_int32),
-                ("coeffs", C.POINTER(C.c_double))]
+                ("coeffs", C.POINTER(C.c_double)), ("transient", C.c_int32), ("dt", C.c_double),
+                ("rho_s", C.c_double), ("amp_d", C.c_double)]
 
 
 class ServerOpts(C.Structure):

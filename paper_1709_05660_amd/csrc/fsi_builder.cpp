@@ -1,6 +1,7 @@
 // Host-side problem builder (see include/fsi_problem.h): structured mesh,
-// Q2/P1disc spaces, steady monolithic ALE residual with its exact Jacobian by
-// forward-mode dual numbers, transfers, Galerkin products and patches.
+// Q2/P1disc spaces, monolithic ALE residual (steady, or one Crank-Nicolson
+// time step) with its exact Jacobian by forward-mode dual numbers, transfers,
+// Galerkin products and patches.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -219,154 +220,309 @@ static Tab make_tab(const Mesh &M) {
 }
 
 // ------------------------------------------------------------ element kernel
+// Plain-double forms of the dual helpers: the state at t_n of a time step is a
+// constant of the Jacobian and runs through the same kinematics code.
+inline void dzero(double &a) { a = 0.0; }
+inline void dconst(double &a, double c) { a = c; }
+inline void daxpy(double &a, double s, double b) { a += s * b; }
+inline void dmul(double &r, double a, double b) { r = a * b; }
+inline void dfma(double &a, double b, double c) { a += b * c; }
+inline void dfms(double &a, double b, double c) { a -= b * c; }
+inline void ddiv(double &r, double a, double b) { r = a / b; }
+inline void dneg(double &a) { a = -a; }
+inline void dscale(double &a, double s) { a *= s; }
+inline void dshift(double &a, double c) { a += c; }
+template <int N>
+inline void dneg(Dual<N> &a) {
+  a.v = -a.v;
+  for (int i = 0; i < N; ++i) a.g[i] = -a.g[i];
+}
+template <int N>
+inline void dscale(Dual<N> &a, double s) {
+  a.v *= s;
+  for (int i = 0; i < N; ++i) a.g[i] *= s;
+}
+// a += c for a constant c
+template <int N>
+inline void dshift(Dual<N> &a, double c) {
+  a.v += c;
+}
+
+// fields of one state at one quadrature point
+template <int DIM, typename V>
+struct Kin {
+  V Gd[DIM][DIM], F[DIM][DIM], Fi[DIM][DIM], det, pq, uq[DIM], dq[DIM], gu[DIM][DIM];
+};
+
+// grad_hat d, F = I + grad_hat d, J = det F, F^{-1} by cofactors, p, u and d
+// at the point and, for a fluid element, the Eulerian velocity gradient
+// grad u = grad_hat u F^{-1}
+template <int DIM, int NA, int NP, typename V, class FD, class FU, class FP>
+static void kinematics(const double *Nq, const double *dNq, const double *ps, FD D, FU U, FP Pp,
+                       bool fluid, Kin<DIM, V> &k) {
+  for (int c = 0; c < DIM; ++c)
+    for (int j = 0; j < DIM; ++j) {
+      dzero(k.Gd[c][j]);
+      for (int a = 0; a < NA; ++a) daxpy(k.Gd[c][j], dNq[a * DIM + j], D(c, a));
+      k.F[c][j] = k.Gd[c][j];
+      if (c == j) dshift(k.F[c][j], 1.0);
+    }
+  if constexpr (DIM == 2) {
+    dmul(k.det, k.F[0][0], k.F[1][1]);
+    dfms(k.det, k.F[0][1], k.F[1][0]);
+    ddiv(k.Fi[0][0], k.F[1][1], k.det);
+    ddiv(k.Fi[1][1], k.F[0][0], k.det);
+    ddiv(k.Fi[0][1], k.F[0][1], k.det);
+    ddiv(k.Fi[1][0], k.F[1][0], k.det);
+    dneg(k.Fi[0][1]);
+    dneg(k.Fi[1][0]);
+  } else {
+    V cof[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+        dmul(cof[i][j], k.F[i1 % DIM][j1 % DIM], k.F[i2 % DIM][j2 % DIM]);
+        dfms(cof[i][j], k.F[i1 % DIM][j2 % DIM], k.F[i2 % DIM][j1 % DIM]);
+      }
+    dmul(k.det, k.F[0][0], cof[0][0]);
+    dfma(k.det, k.F[0][1], cof[0][1]);
+    dfma(k.det, k.F[0][2 % DIM], cof[0][2]);
+    for (int i = 0; i < DIM; ++i)
+      for (int j = 0; j < DIM; ++j) ddiv(k.Fi[i][j], cof[j][i], k.det);
+  }
+  dconst(k.pq, 0.0);
+  for (int j = 0; j < NP; ++j) daxpy(k.pq, ps[j], Pp(j));
+  for (int c = 0; c < DIM; ++c) {
+    dzero(k.uq[c]);
+    dzero(k.dq[c]);
+    for (int a = 0; a < NA; ++a) {
+      daxpy(k.uq[c], Nq[a], U(c, a));
+      daxpy(k.dq[c], Nq[a], D(c, a));
+    }
+  }
+  if (!fluid) return;
+  V Gu[DIM][DIM];
+  for (int c = 0; c < DIM; ++c)
+    for (int j = 0; j < DIM; ++j) {
+      dzero(Gu[c][j]);
+      for (int a = 0; a < NA; ++a) daxpy(Gu[c][j], dNq[a * DIM + j], U(c, a));
+    }
+  for (int c = 0; c < DIM; ++c)
+    for (int b = 0; b < DIM; ++b) {
+      dzero(k.gu[c][b]);
+      for (int j = 0; j < DIM; ++j) dfma(k.gu[c][b], Gu[c][j], k.Fi[j][b]);
+    }
+}
+
+// fluid Cauchy stress -p I + mu (grad u + grad u^T) and, for the solid, the
+// first Piola stress J sigma F^{-T} with sigma = -p I + mu_s F F^T
+template <int DIM, typename V>
+static void fluid_stress(const Kin<DIM, V> &k, double mu, V (&sig)[DIM][DIM]) {
+  for (int c = 0; c < DIM; ++c)
+    for (int b = 0; b < DIM; ++b) {
+      dzero(sig[c][b]);
+      daxpy(sig[c][b], mu, k.gu[c][b]);
+      daxpy(sig[c][b], mu, k.gu[b][c]);
+      if (b == c) daxpy(sig[c][b], -1.0, k.pq);
+    }
+}
+template <int DIM, typename V>
+static void piola(const Kin<DIM, V> &k, double mu_s, V (&P)[DIM][DIM]) {
+  V sig[DIM][DIM], t;
+  for (int c = 0; c < DIM; ++c)
+    for (int b = 0; b < DIM; ++b) {
+      dzero(sig[c][b]);
+      for (int j = 0; j < DIM; ++j) dfma(sig[c][b], k.F[c][j], k.F[b][j]);
+      dscale(sig[c][b], mu_s);
+      if (b == c) daxpy(sig[c][b], -1.0, k.pq);
+    }
+  for (int c = 0; c < DIM; ++c)
+    for (int b = 0; b < DIM; ++b) {
+      dzero(t);
+      for (int j = 0; j < DIM; ++j) dfma(t, sig[c][j], k.Fi[b][j]);
+      dmul(P[c][b], k.det, t);
+    }
+}
+
 // Local dofs: [d_c(a)] c-major, [u_c(a)], [p_j]; local rows: [mom_c(a)], [aux_c(a)], [pres_j].
 template <int DIM, int NL>
 struct ElemOut {
   Dual<NL> rows[NL];
 };
 
+// Local residual rows of one element with their derivatives in the element's
+// dofs.  Steady form when ye0 is null; otherwise one Crank-Nicolson step from
+// the state ye0 at t_n to ye at t_{n+1} (section "Discretization of the
+// operator formulation"): fluid momentum (rho/dt)(J1 u1 - J0 u0) phi plus half
+// of each of -rho div(w) u phi + rho ((u - w).grad) u phi + sigma : grad phi
+// on the configurations of t_{n+1} and t_n, mesh velocity w = (d1 - d0)/dt;
+// continuity and mesh motion at t_{n+1}; solid momentum (rho_s/dt)(J1 u1 -
+// J0 u0) phi plus half of each Piola term; incompressibility at t_{n+1};
+// kinematics -(d1 - d0)/dt + (u1 + u0)/2 against phi.
 template <int DIM, int NL>
-static void element(const Mesh &M, const Tab &T, const fsi_problem_spec &s, bool solid,
-                    const double *ye, ElemOut<DIM, NL> &out, bool want_grad) {
+static void element(const Mesh &M, const Tab &T, const fsi_problem_spec &s, bool solid, const double *ye,
+                    const double *ye0, ElemOut<DIM, NL> &out, bool want_grad) {
   constexpr int NA = DIM == 3 ? 27 : 9;
   constexpr int NP = DIM + 1;
+  using DN = Dual<NL>;
   static_assert(NL == 2 * DIM * NA + NP, "local size");
   for (int r = 0; r < NL; ++r) dzero(out.rows[r]);
-  thread_local std::vector<Dual<NL>> dofs;
+  thread_local std::vector<DN> dofs;
   dofs.resize(NL);
   for (int i = 0; i < NL; ++i) {
     dconst(dofs[i], ye[i]);
     if (want_grad) dofs[i].g[i] = 1.0;
   }
-  auto D = [&](int c, int a) -> const Dual<NL> & { return dofs[c * NA + a]; };
-  auto U = [&](int c, int a) -> const Dual<NL> & { return dofs[(DIM + c) * NA + a]; };
-  auto Pp = [&](int j) -> const Dual<NL> & { return dofs[2 * DIM * NA + j]; };
-  Dual<NL> *mom = out.rows, *aux = out.rows + DIM * NA, *pres = out.rows + 2 * DIM * NA;
+  auto D = [&](int c, int a) -> const DN & { return dofs[c * NA + a]; };
+  auto U = [&](int c, int a) -> const DN & { return dofs[(DIM + c) * NA + a]; };
+  auto Pp = [&](int j) -> const DN & { return dofs[2 * DIM * NA + j]; };
+  auto D0 = [&](int c, int a) { return ye0[c * NA + a]; };
+  auto U0 = [&](int c, int a) { return ye0[(DIM + c) * NA + a]; };
+  auto P0 = [&](int j) { return ye0[2 * DIM * NA + j]; };
+  const bool cn = ye0 != nullptr;
+  const double dt = s.dt;
+  DN *mom = out.rows, *aux = out.rows + DIM * NA, *pres = out.rows + 2 * DIM * NA;
   const double k_ale = 1.0 / T.vol;
-  Dual<NL> Gd[DIM][DIM], F[DIM][DIM], Fi[DIM][DIM], det, uq[DIM], Gu[DIM][DIM], gu[DIM][DIM],
-      pq, sig[DIM][DIM], Tm[DIM][DIM], S[DIM], tmp, tmp2;
+  Kin<DIM, DN> k1;
+  Kin<DIM, double> k0;
+  DN sig1[DIM][DIM], Tm[DIM][DIM], S[DIM], t1, t2;
+  double sig0[DIM][DIM];
   for (int q = 0; q < T.nq; ++q) {
     const double *Nq = &T.N[q * NA];
     const double *dNq = &T.dN[q * NA * DIM];
     const double *ps = &T.psi[q * NP];
     const double w = T.w[q];
-    for (int c = 0; c < DIM; ++c)
-      for (int k = 0; k < DIM; ++k) {
-        dzero(Gd[c][k]);
-        for (int a = 0; a < NA; ++a) daxpy(Gd[c][k], dNq[a * DIM + k], D(c, a));
-        F[c][k] = Gd[c][k];
-        if (c == k) F[c][k].v += 1.0;
-      }
-    // determinant and inverse by cofactors
-    if constexpr (DIM == 2) {
-      dmul(det, F[0][0], F[1][1]);
-      dfms(det, F[0][1], F[1][0]);
-      ddiv(Fi[0][0], F[1][1], det);
-      ddiv(Fi[1][1], F[0][0], det);
-      ddiv(Fi[0][1], F[0][1], det);
-      ddiv(Fi[1][0], F[1][0], det);
-      for (int i = 0; i < NL; ++i) {
-        Fi[0][1].g[i] = -Fi[0][1].g[i];
-        Fi[1][0].g[i] = -Fi[1][0].g[i];
-      }
-      Fi[0][1].v = -Fi[0][1].v;
-      Fi[1][0].v = -Fi[1][0].v;
-    } else {
-      Dual<NL> cof[3][3];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-          dmul(cof[i][j], F[i1 % DIM][j1 % DIM], F[i2 % DIM][j2 % DIM]);
-          dfms(cof[i][j], F[i1 % DIM][j2 % DIM], F[i2 % DIM][j1 % DIM]);
-        }
-      dmul(det, F[0][0], cof[0][0]);
-      dfma(det, F[0][1], cof[0][1]);
-      dfma(det, F[0][2 % DIM], cof[0][2]);
-      for (int i = 0; i < DIM; ++i)
-        for (int j = 0; j < DIM; ++j) ddiv(Fi[i][j], cof[j][i], det);
-    }
-    dconst(pq, 0.0);
-    for (int j = 0; j < NP; ++j) daxpy(pq, ps[j], Pp(j));
+    kinematics<DIM, NA, NP>(Nq, dNq, ps, D, U, Pp, !solid, k1);
+    if (cn) kinematics<DIM, NA, NP>(Nq, dNq, ps, D0, U0, P0, !solid, k0);
     if (!solid) {
-      for (int c = 0; c < DIM; ++c) {
-        dzero(uq[c]);
-        for (int a = 0; a < NA; ++a) daxpy(uq[c], Nq[a], U(c, a));
-        for (int k = 0; k < DIM; ++k) {
-          dzero(Gu[c][k]);
-          for (int a = 0; a < NA; ++a) daxpy(Gu[c][k], dNq[a * DIM + k], U(c, a));
+      fluid_stress(k1, s.mu, sig1);
+      DN wJ1;
+      dconst(wJ1, 0.0);
+      daxpy(wJ1, w, k1.det);
+      if (!cn) {
+        // rho ((u . grad) u) and sigma against grad phi, weighted by w J
+        for (int c = 0; c < DIM; ++c) {
+          dzero(t1);
+          for (int b = 0; b < DIM; ++b) dfma(t1, k1.gu[c][b], k1.uq[b]);
+          dmul(S[c], wJ1, t1);
+          dscale(S[c], s.rho);
+          for (int j = 0; j < DIM; ++j) {
+            dzero(t2);
+            for (int b = 0; b < DIM; ++b) dfma(t2, sig1[c][b], k1.Fi[j][b]);
+            dmul(Tm[c][j], wJ1, t2);
+          }
         }
-      }
-      for (int c = 0; c < DIM; ++c)
-        for (int b = 0; b < DIM; ++b) {
-          dzero(gu[c][b]);
-          for (int k = 0; k < DIM; ++k) dfma(gu[c][b], Gu[c][k], Fi[k][b]);
+      } else {
+        fluid_stress(k0, s.mu, sig0);
+        const double wJ0 = w * k0.det;
+        DN wq[DIM], Gw[DIM][DIM], divw1, divw0;
+        for (int c = 0; c < DIM; ++c) {
+          dzero(wq[c]);
+          daxpy(wq[c], 1.0 / dt, k1.dq[c]);
+          dshift(wq[c], -k0.dq[c] / dt);
+          for (int j = 0; j < DIM; ++j) {
+            dzero(Gw[c][j]);
+            daxpy(Gw[c][j], 1.0 / dt, k1.Gd[c][j]);
+            dshift(Gw[c][j], -k0.Gd[c][j] / dt);
+          }
         }
-      for (int c = 0; c < DIM; ++c)
-        for (int b = 0; b < DIM; ++b) {
-          dzero(sig[c][b]);
-          daxpy(sig[c][b], s.mu, gu[c][b]);
-          daxpy(sig[c][b], s.mu, gu[b][c]);
-          if (b == c) daxpy(sig[c][b], -1.0, pq);
-        }
-      Dual<NL> wJ;
-      dconst(wJ, 0.0);
-      daxpy(wJ, w, det);
-      for (int c = 0; c < DIM; ++c) {
-        dzero(tmp);
-        for (int b = 0; b < DIM; ++b) dfma(tmp, gu[c][b], uq[b]);
-        dmul(S[c], wJ, tmp);
-        for (int i = 0; i < NL; ++i) S[c].g[i] *= s.rho;
-        S[c].v *= s.rho;
-        for (int k = 0; k < DIM; ++k) {
-          dzero(tmp2);
-          for (int b = 0; b < DIM; ++b) dfma(tmp2, sig[c][b], Fi[k][b]);
-          dmul(Tm[c][k], wJ, tmp2);
+        dzero(divw1);
+        dzero(divw0);
+        for (int c = 0; c < DIM; ++c)
+          for (int j = 0; j < DIM; ++j) {
+            dfma(divw1, Gw[c][j], k1.Fi[j][c]);
+            daxpy(divw0, k0.Fi[j][c], Gw[c][j]);
+          }
+        for (int c = 0; c < DIM; ++c) {
+          // t_{n+1}: (rho/dt) u1 + rho/2 (-div(w) u1 + grad u1 (u1 - w))
+          dzero(t1);
+          dfms(t1, divw1, k1.uq[c]);
+          for (int b = 0; b < DIM; ++b) {
+            dfma(t1, k1.gu[c][b], k1.uq[b]);
+            dfms(t1, k1.gu[c][b], wq[b]);
+          }
+          dscale(t1, 0.5 * s.rho);
+          daxpy(t1, s.rho / dt, k1.uq[c]);
+          dmul(S[c], wJ1, t1);
+          // t_n: -(rho/dt) u0 + rho/2 (-div(w) u0 + grad u0 (u0 - w))
+          dzero(t2);
+          daxpy(t2, -k0.uq[c], divw0);
+          for (int b = 0; b < DIM; ++b) {
+            dshift(t2, k0.gu[c][b] * k0.uq[b]);
+            daxpy(t2, -k0.gu[c][b], wq[b]);
+          }
+          dscale(t2, 0.5 * s.rho);
+          dshift(t2, -(s.rho / dt) * k0.uq[c]);
+          daxpy(S[c], wJ0, t2);
+          // half of each stress term
+          for (int j = 0; j < DIM; ++j) {
+            dzero(t2);
+            double c0 = 0.0;
+            for (int b = 0; b < DIM; ++b) {
+              dfma(t2, sig1[c][b], k1.Fi[j][b]);
+              c0 += sig0[c][b] * k0.Fi[j][b];
+            }
+            dmul(Tm[c][j], wJ1, t2);
+            dscale(Tm[c][j], 0.5);
+            dshift(Tm[c][j], 0.5 * wJ0 * c0);
+          }
         }
       }
       for (int c = 0; c < DIM; ++c)
         for (int a = 0; a < NA; ++a) {
-          Dual<NL> &R = mom[c * NA + a];
+          DN &R = mom[c * NA + a];
           daxpy(R, Nq[a], S[c]);
-          for (int k = 0; k < DIM; ++k) daxpy(R, dNq[a * DIM + k], Tm[c][k]);
-          Dual<NL> &A = aux[c * NA + a];
-          for (int b = 0; b < DIM; ++b) daxpy(A, w * k_ale * dNq[a * DIM + b], Gd[c][b]);
+          for (int j = 0; j < DIM; ++j) daxpy(R, dNq[a * DIM + j], Tm[c][j]);
+          DN &A = aux[c * NA + a];
+          for (int b = 0; b < DIM; ++b) daxpy(A, w * k_ale * dNq[a * DIM + b], k1.Gd[c][b]);
         }
-      dzero(tmp);
-      for (int c = 0; c < DIM; ++c) daxpy(tmp, 1.0, gu[c][c]);
-      dmul(tmp2, wJ, tmp);
-      for (int j = 0; j < NP; ++j) daxpy(pres[j], ps[j], tmp2);
+      dzero(t1);
+      for (int c = 0; c < DIM; ++c) daxpy(t1, 1.0, k1.gu[c][c]);
+      dmul(t2, wJ1, t1);
+      for (int j = 0; j < NP; ++j) daxpy(pres[j], ps[j], t2);
     } else {
-      // sigma = -p I + mu_s F F^T ; Piola = J sigma F^{-T}
-      for (int c = 0; c < DIM; ++c)
-        for (int b = 0; b < DIM; ++b) {
-          dzero(sig[c][b]);
-          for (int k = 0; k < DIM; ++k) dfma(sig[c][b], F[c][k], F[b][k]);
-          for (int i = 0; i < NL; ++i) sig[c][b].g[i] *= s.mu_s;
-          sig[c][b].v *= s.mu_s;
-          if (b == c) daxpy(sig[c][b], -1.0, pq);
+      piola(k1, s.mu_s, Tm);
+      double P0m[DIM][DIM] = {};
+      if (cn) piola(k0, s.mu_s, P0m);
+      const double half = cn ? 0.5 : 1.0;
+      for (int c = 0; c < DIM; ++c) {
+        // (rho_s/dt)(J1 u1 - J0 u0) in a time step
+        if (cn) {
+          dmul(S[c], k1.det, k1.uq[c]);
+          dshift(S[c], -k0.det * k0.uq[c]);
+          dscale(S[c], s.rho_s / dt);
         }
-      for (int c = 0; c < DIM; ++c)
-        for (int b = 0; b < DIM; ++b) {
-          dzero(tmp);
-          for (int k = 0; k < DIM; ++k) dfma(tmp, sig[c][k], Fi[b][k]);
-          dmul(Tm[c][b], det, tmp);
+        // kinematics: u (steady), -(d1 - d0)/dt + (u1 + u0)/2 (time step)
+        dzero(t1);
+        if (cn) {
+          daxpy(t1, -1.0 / dt, k1.dq[c]);
+          daxpy(t1, 0.5, k1.uq[c]);
+          dshift(t1, k0.dq[c] / dt + 0.5 * k0.uq[c]);
+        } else {
+          daxpy(t1, 1.0, k1.uq[c]);
         }
-      for (int c = 0; c < DIM; ++c)
         for (int a = 0; a < NA; ++a) {
-          Dual<NL> &R = mom[c * NA + a];
-          for (int b = 0; b < DIM; ++b) daxpy(R, w * dNq[a * DIM + b], Tm[c][b]);
-          Dual<NL> &A = aux[c * NA + a];
-          for (int b2 = 0; b2 < NA; ++b2) daxpy(A, w * Nq[a] * Nq[b2], U(c, b2));
+          DN &R = mom[c * NA + a];
+          if (cn) daxpy(R, w * Nq[a], S[c]);
+          for (int b = 0; b < DIM; ++b) {
+            daxpy(R, half * w * dNq[a * DIM + b], Tm[c][b]);
+            if (cn) dshift(R, half * w * dNq[a * DIM + b] * P0m[c][b]);
+          }
+          daxpy(aux[c * NA + a], w * Nq[a], t1);
         }
-      dconst(tmp, -1.0);
-      daxpy(tmp, 1.0, det);
-      for (int j = 0; j < NP; ++j) daxpy(pres[j], w * ps[j], tmp);
+      }
+      dconst(t1, -1.0);
+      daxpy(t1, 1.0, k1.det);
+      for (int j = 0; j < NP; ++j) daxpy(pres[j], w * ps[j], t1);
     }
   }
 }
 
-// structural coupling of local row lr with local column lc
-static bool coupled(int dim, int na, bool solid, int lr, int lc) {
+// Structural coupling of local row lr with local column lc.  A time step adds
+// the solid momentum's mass term on the same velocity component and the
+// kinematics' time difference on the same displacement component (the blocks
+// that vanish only in the steady case, section "Structure of the Jacobian").
+static bool coupled(int dim, int na, bool solid, bool transient, int lr, int lc) {
   const int nd = dim * na;
   const int rblk = lr < nd ? 0 : (lr < 2 * nd ? 1 : 2);   // mom, aux, pres
   const int cblk = lc < nd ? 0 : (lc < 2 * nd ? 1 : 2);   // d, u, p
@@ -376,8 +532,8 @@ static bool coupled(int dim, int na, bool solid, int lr, int lc) {
     if (rblk == 1) return cblk == 0 && rc == cc;
     return cblk != 2;
   }
-  if (rblk == 0) return cblk != 1;
-  if (rblk == 1) return cblk == 1 && rc == cc;
+  if (rblk == 0) return cblk != 1 || (transient && rc == cc);
+  if (rblk == 1) return (cblk == 1 || (transient && cblk == 0)) && rc == cc;
   return cblk == 0;
 }
 
@@ -412,7 +568,8 @@ struct Csr {
 // sparsity from the structural rule, then values by element colouring
 template <int DIM, int NL>
 static void assemble(const Mesh &M, const fsi_problem_spec &s, const std::vector<double> &y,
-                     std::vector<double> &r, Csr *J) {
+                     const std::vector<double> *y_prev, std::vector<double> &r, Csr *J) {
+  const bool tr = y_prev != nullptr;
   constexpr int NA = DIM == 3 ? 27 : 9;
   const Tab T = make_tab(M);
   std::vector<std::vector<int>> loc(M.ne);
@@ -427,10 +584,10 @@ static void assemble(const Mesh &M, const fsi_problem_spec &s, const std::vector
     for (int e = 0; e < M.ne; ++e) {
       l2g(e, g);
       for (int lr = 0; lr < NL; ++lr) {
-        const int tr = target_row(M, e, lr);
-        if (tr < 0 || M.dir[tr]) continue;
+        const int t = target_row(M, e, lr);
+        if (t < 0 || M.dir[t]) continue;
         for (int lc = 0; lc < NL; ++lc)
-          if (coupled(DIM, NA, M.solid[e], lr, lc) && !M.dir[g[lc]]) rows[tr].push_back(g[lc]);
+          if (coupled(DIM, NA, M.solid[e], tr, lr, lc) && !M.dir[g[lc]]) rows[t].push_back(g[lc]);
       }
     }
     for (int i = 0; i < M.ndof; ++i)
@@ -462,20 +619,22 @@ static void assemble(const Mesh &M, const fsi_problem_spec &s, const std::vector
     {
       std::unique_ptr<ElemOut<DIM, NL>> out(new ElemOut<DIM, NL>());
       std::vector<int> g;
-      std::vector<double> ye(NL);
+      std::vector<double> ye(NL), ye0(tr ? NL : 0);
 #pragma omp for schedule(dynamic, 4)
       for (size_t ii = 0; ii < els.size(); ++ii) {
         const int e = els[ii];
         for (int lc = 0; lc < NL; ++lc) ye[lc] = y[local_col_dof(M, e, lc)];
-        element<DIM, NL>(M, T, s, M.solid[e], ye.data(), *out, J != nullptr);
+        if (tr)
+          for (int lc = 0; lc < NL; ++lc) ye0[lc] = (*y_prev)[local_col_dof(M, e, lc)];
+        element<DIM, NL>(M, T, s, M.solid[e], ye.data(), tr ? ye0.data() : nullptr, *out, J != nullptr);
         for (int lr = 0; lr < NL; ++lr) {
-          const int tr = target_row(M, e, lr);
-          if (tr < 0) continue;
-          r[tr] += out->rows[lr].v;
-          if (!J || M.dir[tr]) continue;
-          const int64_t a = J->rp[tr], b = J->rp[tr + 1];
+          const int t = target_row(M, e, lr);
+          if (t < 0) continue;
+          r[t] += out->rows[lr].v;
+          if (!J || M.dir[t]) continue;
+          const int64_t a = J->rp[t], b = J->rp[t + 1];
           for (int lc = 0; lc < NL; ++lc) {
-            if (!coupled(DIM, NA, M.solid[e], lr, lc)) continue;
+            if (!coupled(DIM, NA, M.solid[e], tr, lr, lc)) continue;
             const int gc = local_col_dof(M, e, lc);
             if (M.dir[gc]) continue;
             const int64_t pos = std::lower_bound(J->ci.begin() + a, J->ci.begin() + b, gc) - J->ci.begin();
@@ -490,12 +649,15 @@ static void assemble(const Mesh &M, const fsi_problem_spec &s, const std::vector
 }
 
 // ------------------------------------------------------------ state
-static std::vector<double> make_state(const Mesh &M, const fsi_problem_spec &s) {
-  std::vector<double> y(M.ndof, 0.0);
+// S_c / max|S_c| at the Q2 nodes, c = 0..dim-1, with
+// S_c = sum_{k,l(,m)=1..K} a_{c,k,l(,m)} / (k^2+l^2(+m^2)) prod sin(k pi x / L)
+static std::vector<std::vector<double>> fourier_shapes(const Mesh &M, const fsi_problem_spec &s) {
   const int K = s.kmax;
   const int nmodes = (int)std::lround(std::pow((double)K, s.dim));
+  std::vector<std::vector<double>> out(s.dim);
   for (int c = 0; c < s.dim; ++c) {
-    std::vector<double> S(M.N2, 0.0);
+    std::vector<double> &S = out[c];
+    S.assign(M.N2, 0.0);
     for (int i = 0; i < M.N2; ++i) {
       int I, J, Kz;
       M.grid(i, I, J, Kz);
@@ -518,21 +680,42 @@ static std::vector<double> make_state(const Mesh &M, const fsi_problem_spec &s) 
     }
     double mx = 0.0;
     for (double v : S) mx = std::max(mx, std::fabs(v));
+    for (double &v : S) v /= mx;
+  }
+  return out;
+}
+
+// Seeded linearisation state: d = 0, fluid-only velocities carry the inflow
+// profile plus amp * S_c / max|S_c|, solid pressure mu_s (stress-free solid),
+// Dirichlet dofs their boundary values.  For a time step this is the state at
+// t_n and y1 (the Newton iterate at t_{n+1}) moves every free displacement by
+// amp_d * S_c / max|S_c|.
+static std::vector<double> make_state(const Mesh &M, const fsi_problem_spec &s, std::vector<double> *y1) {
+  std::vector<double> y(M.ndof, 0.0);
+  const auto shapes = fourier_shapes(M, s);
+  for (int c = 0; c < s.dim; ++c)
     for (int i = 0; i < M.N2; ++i) {
       double u = 0.0;
       if (M.ncls[i] == NF) {
         int I, J, Kz;
         M.grid(i, I, J, Kz);
-        u = s.amp * S[i] / mx;
+        u = s.amp * shapes[c][i];
         if (c == 0) u += inflow(M, s.u_peak, J * M.h[1] / 2, Kz * M.h[2] / 2);
       }
       y[M.u_dof(c, i)] = u;
     }
-  }
   for (int e = 0; e < M.ne; ++e)
     if (M.solid[e]) y[M.p_dof(e, 0)] = s.mu_s;
   for (int i = 0; i < M.ndof; ++i)
     if (M.dir[i]) y[i] = M.dval[i];
+  if (y1) {
+    *y1 = y;
+    for (int c = 0; c < s.dim; ++c)
+      for (int i = 0; i < M.N2; ++i) {
+        const int dd = M.d_dof(c, i);
+        if (!M.dir[dd]) (*y1)[dd] += s.amp_d * shapes[c][i];
+      }
+  }
   return y;
 }
 
@@ -770,19 +953,22 @@ struct Problem {
   std::vector<Csr> J, P, R;
   std::vector<Patches> patches;
   std::vector<double> y, b;
+  std::vector<double> y_prev;  // state at t_n of a time step (empty: steady)
 };
 
 static void residual_jacobian(const Mesh &M, const fsi_problem_spec &s, const std::vector<double> &y,
-                              std::vector<double> &r, Csr *J) {
+                              const std::vector<double> *y_prev, std::vector<double> &r, Csr *J) {
   if (M.dim == 2)
-    assemble<2, 39>(M, s, y, r, J);
+    assemble<2, 39>(M, s, y, y_prev, r, J);
   else
-    assemble<3, 166>(M, s, y, r, J);
+    assemble<3, 166>(M, s, y, y_prev, r, J);
 }
 
 static Problem *build(const fsi_problem_spec &s0) {
   if (s0.dim != 2 && s0.dim != 3) throw Err("dim must be 2 or 3");
   if (s0.levels < 1 || s0.patch < 1 || s0.kmax < 1 || !s0.coeffs) throw Err("invalid spec");
+  if (s0.transient && !(s0.dt > 0.0 && std::isfinite(s0.dt) && s0.rho_s >= 0.0 && std::isfinite(s0.amp_d)))
+    throw Err("a time step needs dt > 0, rho_s >= 0 and a finite amp_d");
   std::unique_ptr<Problem> pb(new Problem());
   pb->spec = s0;
   const int nmodes = (int)std::lround(std::pow((double)s0.kmax, s0.dim));
@@ -807,12 +993,18 @@ static Problem *build(const fsi_problem_spec &s0) {
     pb->meshes.push_back(std::move(M));
   }
   const Mesh &Fm = pb->meshes.back();
-  pb->y = make_state(Fm, s);
+  const std::vector<double> *yp = nullptr;
+  if (s.transient) {
+    pb->y_prev = make_state(Fm, s, &pb->y);
+    yp = &pb->y_prev;
+  } else {
+    pb->y = make_state(Fm, s, nullptr);
+  }
   pb->J.resize(L);
   pb->P.resize(L);
   pb->R.resize(L);
   std::vector<double> r;
-  residual_jacobian(Fm, s, pb->y, r, &pb->J[L - 1]);
+  residual_jacobian(Fm, s, pb->y, yp, r, &pb->J[L - 1]);
   pb->b.resize(Fm.ndof);
   for (int i = 0; i < Fm.ndof; ++i) pb->b[i] = Fm.dir[i] ? 0.0 : -r[i];
   for (int l = L - 1; l >= 1; --l) {
@@ -907,7 +1099,7 @@ fsi_status fsi_problem_residual(const struct fsi_problem *hp, const double *y, d
   if (!p || !y || !r) return FSI_E_INVALID;
   const Mesh &M = p->meshes.back();
   std::vector<double> yy(y, y + M.ndof), rr;
-  residual_jacobian(M, p->spec, yy, rr, nullptr);
+  residual_jacobian(M, p->spec, yy, p->spec.transient ? &p->y_prev : nullptr, rr, nullptr);
   std::copy(rr.begin(), rr.end(), r);
   return FSI_OK;
 }

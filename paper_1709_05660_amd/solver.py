@@ -88,6 +88,10 @@ class Problem:
         ps.rho, ps.mu, ps.mu_s, ps.u_peak, ps.amp = spec.rho, spec.mu, spec.mu_s, spec.u_peak, spec.amp
         ps.kmax = kmax
         ps.coeffs = L._ptr(c, C.c_double)
+        ps.transient = 1 if getattr(spec, "transient", False) else 0
+        ps.dt = getattr(spec, "dt", 0.0)
+        ps.rho_s = getattr(spec, "rho_s", 0.0)
+        ps.amp_d = getattr(spec, "amp_d", 0.0)
         h = C.c_void_p()
         st = lib.fsi_problem_build(C.byref(ps), C.byref(h))
         if st != 0:

@@ -48,7 +48,13 @@ def _csr(p, level, which="J"):
                                      ("c1_2d_128x32", dict(nx=32, ny=8, levels=3, mu_s=3.0e4, seed=7)),
                                      # the full-size workloads (the 3D checker assembly takes ~2 min)
                                      pytest.param("c1_2d_128x32", {}, marks=pytest.mark.slow),
-                                     pytest.param("c3_3d_32x8x8", {}, marks=pytest.mark.slow)])
+                                     pytest.param("c3_3d_32x8x8", {}, marks=pytest.mark.slow),
+                                     # one Crank-Nicolson time step
+                                     ("c5_2d_16x4_cn", {}),
+                                     ("c4_2d_128x32_cn", dict(nx=32, ny=8, levels=3, seed=7)),
+                                     ("c3_3d_32x8x8", dict(nx=16, ny=4, nz=4, levels=2, patch=2,
+                                                           transient=True)),
+                                     pytest.param("c4_2d_128x32_cn", {}, marks=pytest.mark.slow)])
 def test_builder_matches_checker(name, kw):
     """The native builder and the checker assemble the same hierarchy: P, R and
     the patch lists bit for bit, J and b to rounding (sums in another order)."""
@@ -94,12 +100,30 @@ def test_builder_residual_matches_checker_off_state():
     assert np.max(np.abs(r_nat - r_orc)) <= 1e-12 * np.max(np.abs(r_orc))
 
 
+def test_builder_cn_residual_matches_checker_off_state():
+    """Residual of the time step at a state away from both time levels."""
+    from paper_1709_05660_amd import Problem
+    s = config("c5_2d_16x4_cn")
+    a = fourier_coefficients(2, s.seed)
+    p = Problem(s, a)
+    mesh = fem.Mesh(s, (16, 4, 1))
+    y0, y1 = fem.transient_states(mesh, s, a)
+    rng = np.random.default_rng(13)
+    y = p.y + 1e-2 * rng.standard_normal(p.n)
+    r_nat = p.residual(y)
+    r_orc, _ = fem.assemble(mesh, s, y, jacobian=False, y_prev=y0)
+    assert np.max(np.abs(r_nat - r_orc)) <= 1e-12 * np.max(np.abs(r_orc))
+
+
 def test_builder_rejects_bad_spec():
     from paper_1709_05660_amd import FsiError, Problem
     s = config("c0_2d_16x4").with_(nx=18)          # not divisible by 2 * patch
     with pytest.raises(FsiError):
         Problem(s, fourier_coefficients(2, 1))
     s = config("c0_2d_16x4").with_(solid_lo=(1.1, 0.0, 0.0))   # solid not element-aligned
+    with pytest.raises(FsiError):
+        Problem(s, fourier_coefficients(2, 1))
+    s = config("c5_2d_16x4_cn").with_(dt=0.0)       # a time step needs dt > 0
     with pytest.raises(FsiError):
         Problem(s, fourier_coefficients(2, 1))
 

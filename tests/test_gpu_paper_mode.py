@@ -26,7 +26,7 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("name,graph", [("c0_2d_16x4", False), ("c0_2d_16x4", True),
-                                        ("c1_2d_128x32", True)])
+                                        ("c1_2d_128x32", True), ("c4_2d_128x32_cn", True)])
 def test_paper_mode_parity(name, graph):
     """Left GMRES(10) with one CGS pass to 1e-4: the GPU iterate after the
     checker's iteration count equals the checker's to 1e-10, the converged
@@ -45,7 +45,10 @@ def test_paper_mode_parity(name, graph):
          f"rho {ig['rho']:.4f} hist0 {ig['history'][0]:.6e} vs {io.history[0]:.6e}")
     assert ig["history"][0] == pytest.approx(io.history[0], rel=1e-10)
     assert rel <= 1e-10
-    assert ig["rho"] == pytest.approx(i_fix.rho, rel=1e-8)
+    # rho = (r_k / r_0)^(1/k): both estimates of r_k agree to the iterates'
+    # 1e-10 relative to r_0, so the rates agree to 1e-10 / (k rho^k), which
+    # for a fast solve (the time step: k = 3, rho^k ~ 1e-4) is above 1e-8
+    assert ig["rho"] == pytest.approx(i_fix.rho, rel=max(1e-8, 1e-10 / (k * i_fix.rho ** k)))
     x2, i2 = mg.fgmres(b, restart=10, rtol=1e-4, side="left", orth="cgs")
     assert i2["converged"] == 1 and abs(i2["iters"] - k) <= 1
     assert i2["est_relres"] <= 1e-4
