@@ -45,7 +45,7 @@ def ras_kernel_digest():
     body, not the host launchers): counter readings apply only to this code."""
     src = open(os.path.join(CSRC, "fsi_kernels.hip")).read()
     a = src.index("__device__ inline float w16val")
-    b = src.index("// Refined local solve of one solid block per workgroup")
+    b = src.index("static int ras_waves(int ntask);")
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
@@ -399,8 +399,9 @@ def gpu_leg(args):
 
 def serve_leg(args):
     """Served solves/s and latency percentiles for the stream of independent 2D
-    systems (mesh, solid stiffness and inflow drawn per request), mixed
-    precision, admission by device-memory budget, continuous batching."""
+    systems (mesh, solid stiffness, inflow and kind: sweep point or time step
+    drawn per request), mixed precision, admission by device-memory budget,
+    continuous batching; V-cycles on each system's stream, and batched."""
     import threading
     from concurrent.futures import ThreadPoolExecutor
 
@@ -411,7 +412,8 @@ def serve_leg(args):
     base = config("c2_2d_128x32_mixed")
 
     def make(r):
-        s = base.with_(nx=r.nx, ny=r.ny, levels=r.levels, mu_s=r.mu_s, u_peak=r.u_peak, seed=r.seed)
+        s = base.with_(nx=r.nx, ny=r.ny, levels=r.levels, mu_s=r.mu_s, u_peak=r.u_peak, seed=r.seed,
+                       transient=r.transient)
         return Problem(s, fourier_coefficients(2, r.seed))
 
     t = time.time()
@@ -420,10 +422,10 @@ def serve_leg(args):
     build_s = time.time() - t
     budget, slots = args.serve_budget_gb << 30, args.serve_slots
 
-    def run(arrivals, plist=None, precision=None):
+    def run(arrivals, plist=None, precision=None, batched=False):
         plist = probs if plist is None else plist
         precision = precision or args.mixed
-        srv = Server(hbm_budget_bytes=budget, max_slots=slots)
+        srv = Server(hbm_budget_bytes=budget, max_slots=slots, batch_vcycles=batched)
         done_at = {}
         sub_at = {}
         tickets = [None] * len(plist)
@@ -463,7 +465,9 @@ def serve_leg(args):
                 "p99_ms": round(float(np.percentile(lat, 99)), 2), "failed": int(bad),
                 "mean_iters": round(float(np.mean(iters)), 2) if iters else None,
                 "max_coresident": stats["max_coresident"], "peak_bytes": stats["peak_bytes"],
-                "pool_peak_in_use_bytes": stats["pool_peak_in_use_bytes"]}
+                "pool_peak_in_use_bytes": stats["pool_peak_in_use_bytes"],
+                "mean_vcycle_batch": (round(stats["batched_systems"] / stats["batched_groups"], 2)
+                                      if stats["batched_groups"] else None)}
 
     def sequential(plist, precision):
         """The same requests solved one at a time through the synchronous path,
@@ -485,11 +489,15 @@ def serve_leg(args):
            "budget_bytes": budget, "max_slots": slots, "host_build_s": round(build_s, 1),
            "each_request": "upload, setup (block and coarse inversion), solve, copy back",
            "closed_loop": closed,
+           # the V-cycles of the systems stepping together in batched launches
+           # (lockstep ticks) instead of each on its system's stream
+           "closed_loop_batched_vcycles": run([0.0] * len(probs), batched=True),
            # like for like: the same stream served in FP64, and the 128x32
            # systems alone, served and one at a time, setup included on both sides
            "closed_loop_fp64": run([0.0] * len(probs), precision="fp64")}
     big = [p for p in probs if p.spec.nx == 128][:32]
     out["only_128x32"] = {"systems": len(big), "served_closed_loop": run([0.0] * len(big), big),
+                          "served_closed_loop_batched_vcycles": run([0.0] * len(big), big, batched=True),
                           "one_at_a_time": sequential(big, args.mixed)}
     # the same Poisson stream scaled to 0.7 (the headline), 0.5 and 1.0 of
     # the measured closed-loop rate

@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define FSI_ABI_VERSION 2
+#define FSI_ABI_VERSION 3
 
 typedef int32_t fsi_status;
 enum {
@@ -175,6 +175,19 @@ fsi_status fsi_mg_setup(const fsi_level *levels, int32_t nlevels, const fsi_mg_o
  * argument), FSI_E_DEVICE (launch failure). */
 fsi_status fsi_mg_vcycle(struct fsi_mg *mg, const double *r_dev, double *z_dev, void *hip_stream);
 
+/* The V-cycles of count independent systems (the same section), each phase
+ * of the cycle (Schwarz step, residual, transfer, coarsest solve of one
+ * depth) as one batched launch over the systems that have it; each
+ * z_dev[i] = M_i^{-1} r_dev[i] equals what fsi_mg_vcycle gives for system i
+ * (the same arithmetic).  The handles must share nu_pre, nu_post, omega and
+ * the V-cycle's precision class (FP64, or mixed with more than one level),
+ * and r_dev[i] != z_dev[i]; a handle appears once (its level vectors are
+ * the cycle's workspace); all on hip_stream (NULL: the first handle's
+ * stream).  Errors: FSI_E_INVALID (null argument, count < 1, incompatible
+ * or repeated handles, aliased vectors), FSI_E_DEVICE. */
+fsi_status fsi_mg_vcycle_batch(struct fsi_mg *const *mgs, int32_t count, const double *const *r_dev,
+                               double *const *z_dev, void *hip_stream);
+
 /* Section "Details on the iterative solver" (GMRES preconditioned by one
  * V-cycle per step) for J_finest x = b, the linear system of a Newton step
  * (section "Structure of the Jacobian").  kopts->side picks flexible GMRES
@@ -278,11 +291,18 @@ int32_t fsi_stream_read_blocks(void);
  * the systems' kernels overlapping on the device; a converged system is
  * retired (result copied to host, device memory returned to the server's
  * cache, released when the server is destroyed) and the next request
- * admitted. */
+ * admitted.  With batch_vcycles the iterations advance in lockstep ticks:
+ * the V-cycles of the systems at an Arnoldi step in a tick run together,
+ * each phase of the cycle (Schwarz step, residual, transfer, coarsest solve
+ * of one depth) as one batched launch over up to 16 systems with the same
+ * smoothing options and V-cycle precision; each system's arithmetic is that
+ * of its own V-cycle. */
 typedef struct {
   int64_t hbm_budget_bytes; /* admission budget of device memory */
   int32_t max_slots;        /* maximum co-resident systems */
   int32_t device;           /* HIP device ordinal */
+  int32_t batch_vcycles;    /* 0: each system's V-cycles on its own stream; 1: batched (lockstep ticks) */
+  int32_t reserved;         /* must be 0 */
 } fsi_server_opts;
 
 struct fsi_server;
@@ -308,9 +328,10 @@ fsi_status fsi_serve_poll(struct fsi_server *s, uint64_t ticket, double *x_host,
  * [4] admitted footprint bytes, [5] peak admitted footprint bytes, [6] ticks,
  * [7] max co-resident, [8] device bytes the server's pool allocated (kept
  * until fsi_server_destroy), [9] peak device bytes handed out by the pool.
- * The admitted footprint is an estimate that includes the pool's rounding
- * slack; [9] is what the systems actually held. */
-fsi_status fsi_server_stats(struct fsi_server *s, int64_t out[10]);
+ * [10] batched V-cycle groups, [11] systems in them (batch_vcycles; the
+ * mean batch is [11] / [10]).  The admitted footprint is an estimate that
+ * includes the pool's rounding slack; [9] is what the systems actually held. */
+fsi_status fsi_server_stats(struct fsi_server *s, int64_t out[12]);
 fsi_status fsi_server_destroy(struct fsi_server *s);
 
 #ifdef __cplusplus

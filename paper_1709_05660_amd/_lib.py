@@ -78,12 +78,14 @@ class ProblemSpecC(C.Structure):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("device", C.c_int32)]
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("device", C.c_int32),
+                ("batch_vcycles", C.c_int32), ("reserved", C.c_int32)]
 
 
 # every symbol the headers declare (checked by the CPU tests)
 EXPORTS = [
     "fsi_abi_version", "fsi_status_string", "fsi_last_error", "fsi_mg_setup", "fsi_mg_vcycle",
+    "fsi_mg_vcycle_batch",
     "fsi_fgmres_solve", "fsi_fgmres_solve_noalloc", "fsi_mg_apply", "fsi_mg_export_patches", "fsi_mg_level_info",
     "fsi_mg_refactor", "fsi_mg_jvalues", "fsi_mg_profile", "fsi_mg_autotune",
     "fsi_mg_destroy", "fsi_server_create", "fsi_serve_submit", "fsi_serve_poll",
@@ -113,6 +115,7 @@ def lib():
         "fsi_last_error": (C.c_char_p, []),
         "fsi_mg_setup": (C.c_int32, [C.POINTER(LevelC), C.c_int32, C.POINTER(MgOpts), P, C.POINTER(P)]),
         "fsi_mg_vcycle": (C.c_int32, [P, P, P, P]),
+        "fsi_mg_vcycle_batch": (C.c_int32, [C.POINTER(P), C.c_int32, C.POINTER(P), C.POINTER(P), P]),
         "fsi_fgmres_solve": (C.c_int32, [P, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo), P]),
         "fsi_fgmres_solve_noalloc": (C.c_int32, [P, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo), P]),
         "fsi_mg_apply": (C.c_int32, [P, C.c_int32, C.c_int32, P, P, P, P]),

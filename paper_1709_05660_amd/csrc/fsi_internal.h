@@ -206,6 +206,11 @@ struct FgmresRun {
   void start(MG &mg, const double *b, double *x, const fsi_krylov_opts &ko, hipStream_t st,
              Krylov *ws = nullptr);
   void enqueue();
+  // a step split around a V-cycle applied by the caller (phase kIter):
+  // enqueue_step_pre, then z = M^{-1} vin into vout on any stream ordered
+  // between the two, then enqueue_step_post
+  void enqueue_step_pre(const double **vin, double **vout);
+  void enqueue_step_post();
   bool complete();
   void fill_info(fsi_solve_info *info) const;
  private:
@@ -217,6 +222,15 @@ struct FgmresRun {
   void add_hist(double v);
 };
 void validate_krylov(const fsi_krylov_opts &ko);
+// V-cycles of several systems in batched launches (z = M^{-1} r each, r != z);
+// the systems must be batch_compatible with each other
+struct BatchItem {
+  MG *mg;
+  const double *r;
+  double *z;
+};
+bool batch_compatible(const MG &a, const MG &b);
+void batched_vcycle(const std::vector<BatchItem> &items, hipStream_t st);
 // doubles of device memory the Krylov buffers of an n-row system with restart m take
 int64_t krylov_doubles(int n, int m);
 // points the buffers of K into base (krylov_doubles(n, m) doubles, 256-byte

@@ -172,6 +172,75 @@ void launch_dense_gemv(const double *W, int n, const double *x, double *y, hipSt
 constexpr int kStreamReadBlocks = 1024;
 void launch_stream_read(const double *x, int64_t n, double *out, hipStream_t st);
 
+// ---- batches: one launch applies an operation to up to kMaxBatch
+// independent systems (the server's co-resident systems), each entry on
+// workgroups [blk0[s], blk0[s + 1]) with the arithmetic of its single launch.
+// The launchers split longer lists and group entries by the single launch's
+// template shape (lanes per row, waves per Schwarz workgroup).
+constexpr int kMaxBatch = 16;
+template <typename T>
+struct SpmvItem {
+  CsrView<T> A;
+  const T *x, *r;
+  T *y;
+};
+template <typename T>
+struct SpmvBatch {
+  int count, mode;
+  int blk0[kMaxBatch + 1];
+  SpmvItem<T> it[kMaxBatch];
+};
+// lpr[i]: the lanes per row of entry i (as launch_spmv takes it)
+template <typename T>
+void launch_spmv_batch(const SpmvItem<T> *items, const int *lpr, int count, int mode, hipStream_t st);
+template <typename WT, typename VT>
+struct RasItem {
+  RasView v;
+  const WT *W;
+  int w16_kind;
+  const float *wscale;
+  const VT *s;
+  VT *e;
+};
+template <typename WT, typename VT>
+struct RasBatch {
+  int count;
+  int blk0[kMaxBatch + 1];
+  RasItem<WT, VT> it[kMaxBatch];
+};
+void launch_ras_batch_f64(const RasItem<double, double> *items, int count, double omega, bool add,
+                          hipStream_t st);
+void launch_ras_batch_f32(const RasItem<float, float> *items, int count, float omega, bool add,
+                          hipStream_t st);
+void launch_ras_batch_16(const RasItem<uint16_t, float> *items, int count, float omega, bool add,
+                         hipStream_t st);
+struct GemvItem {
+  const double *W;
+  int n;
+  const double *x;
+  double *y;
+};
+struct GemvBatch {
+  int count;
+  int blk0[kMaxBatch + 1];
+  GemvItem it[kMaxBatch];
+};
+void launch_dense_gemv_batch(const GemvItem *items, int count, hipStream_t st);
+template <typename A, typename B>
+struct CastItem {
+  const A *x;
+  B *y;
+  int n;
+};
+template <typename A, typename B>
+struct CastBatch {
+  int count;
+  int blk0[kMaxBatch + 1];
+  CastItem<A, B> it[kMaxBatch];
+};
+template <typename A, typename B>
+void launch_cast_batch(const CastItem<A, B> *items, int count, hipStream_t st);
+
 // ---- vectors
 void launch_cast_d2f(const double *x, float *y, int n, hipStream_t st);
 void launch_cast_f2d(const float *x, double *y, int n, hipStream_t st);

@@ -48,13 +48,13 @@ __device__ __forceinline__ T group_sum(T v) {
 // four at a time (their column and value loads issued together), summing
 // in the same order as a one-at-a-time loop.  Whole rows leave together, so
 // every group reduces with all its lanes active.
+// blk: the workgroup's index among the operator's own workgroups (256 threads)
 template <typename T, int LPR>
-__global__ __launch_bounds__(256) void k_spmv(int nrows, const int *__restrict__ rowptr,
-                                              const int *__restrict__ col,
-                                              const T *__restrict__ val, const T *__restrict__ x,
-                                              const T *__restrict__ r, T *__restrict__ y,
-                                              int mode) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void spmv_body(int blk, int nrows, const int *__restrict__ rowptr,
+                                          const int *__restrict__ col, const T *__restrict__ val,
+                                          const T *__restrict__ x, const T *__restrict__ r,
+                                          T *__restrict__ y, int mode) {
+  const int gid = blk * 256 + threadIdx.x;
   const int row = gid / LPR;
   const int lane = gid % LPR;
   const bool live = row < nrows;
@@ -82,6 +82,71 @@ __global__ __launch_bounds__(256) void k_spmv(int nrows, const int *__restrict__
       y[row] += acc;
   }
 }
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_spmv(int nrows, const int *__restrict__ rowptr,
+                                              const int *__restrict__ col,
+                                              const T *__restrict__ val, const T *__restrict__ x,
+                                              const T *__restrict__ r, T *__restrict__ y,
+                                              int mode) {
+  spmv_body<T, LPR>(blockIdx.x, nrows, rowptr, col, val, x, r, y, mode);
+}
+
+// the batch entry of workgroup b: blk0[s] <= b < blk0[s + 1] (count <= kMaxBatch)
+__device__ __forceinline__ int batch_entry(const int *blk0, int count, int b) {
+  int s = 0;
+  while (s + 1 < count && blk0[s + 1] <= b) ++s;
+  return s;
+}
+
+// one operator per entry of the batch, each on its own workgroups
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_spmv_batch(SpmvBatch<T> B) {
+  const int s = batch_entry(B.blk0, B.count, blockIdx.x);
+  const SpmvItem<T> &it = B.it[s];
+  spmv_body<T, LPR>(blockIdx.x - B.blk0[s], it.A.nrows, it.A.rowptr, it.A.col, it.A.val, it.x, it.r,
+                    it.y, B.mode);
+}
+
+template <typename T>
+void launch_spmv_batch(const SpmvItem<T> *items, const int *lpr, int count, int mode, hipStream_t st) {
+  for (int L : {2, 4, 8, 16, 32, 64}) {
+    SpmvBatch<T> B;
+    B.mode = mode;
+    B.count = 0;
+    B.blk0[0] = 0;
+    auto flush = [&] {
+      if (B.count == 0 || B.blk0[B.count] == 0) {
+        B.count = 0;
+        return;
+      }
+      const int grid = B.blk0[B.count];
+#define FSI_SPMVB_CASE(LL) \
+  case LL:                 \
+    k_spmv_batch<T, LL><<<grid, 256, 0, st>>>(B); break;
+      switch (L) {
+        FSI_SPMVB_CASE(2)
+        FSI_SPMVB_CASE(4)
+        FSI_SPMVB_CASE(8)
+        FSI_SPMVB_CASE(16)
+        FSI_SPMVB_CASE(32)
+        FSI_SPMVB_CASE(64)
+      }
+#undef FSI_SPMVB_CASE
+      B.count = 0;
+    };
+    for (int i = 0; i < count; ++i) {
+      // the single launch's lanes per row (unknown values run with 8, as there)
+      const int li = (lpr[i] == 2 || lpr[i] == 4 || lpr[i] == 16 || lpr[i] == 32 || lpr[i] == 64) ? lpr[i] : 8;
+      if (li != L || items[i].A.nrows == 0) continue;
+      B.it[B.count] = items[i];
+      B.blk0[B.count + 1] = B.blk0[B.count] + cdiv((int64_t)items[i].A.nrows * L, 256);
+      if (++B.count == kMaxBatch) flush();
+    }
+    flush();
+  }
+}
+template void launch_spmv_batch<double>(const SpmvItem<double> *, const int *, int, int, hipStream_t);
+template void launch_spmv_batch<float>(const SpmvItem<float> *, const int *, int, int, hipStream_t);
 
 template <typename T>
 void launch_spmv(const CsrView<T> &A, const T *x, const T *r, T *y, int mode, int lpr,
@@ -137,6 +202,33 @@ __global__ void k_cast_f2d(const float *x, double *y, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = (double)x[i];
 }
+// elementwise conversions of a batch of vectors (256 entries per workgroup)
+template <typename A, typename Bt>
+__global__ __launch_bounds__(256) void k_cast_batch(CastBatch<A, Bt> B) {
+  const int s = batch_entry(B.blk0, B.count, blockIdx.x);
+  const int i = (blockIdx.x - B.blk0[s]) * 256 + threadIdx.x;
+  if (i < B.it[s].n) B.it[s].y[i] = (Bt)B.it[s].x[i];
+}
+template <typename A, typename Bt>
+void launch_cast_batch(const CastItem<A, Bt> *items, int count, hipStream_t st) {
+  CastBatch<A, Bt> B;
+  B.count = 0;
+  B.blk0[0] = 0;
+  auto flush = [&] {
+    if (B.count && B.blk0[B.count]) k_cast_batch<A, Bt><<<B.blk0[B.count], 256, 0, st>>>(B);
+    B.count = 0;
+  };
+  for (int i = 0; i < count; ++i) {
+    if (items[i].n <= 0) continue;
+    B.it[B.count] = items[i];
+    B.blk0[B.count + 1] = B.blk0[B.count] + cdiv(items[i].n, 256);
+    if (++B.count == kMaxBatch) flush();
+  }
+  flush();
+}
+template void launch_cast_batch<double, float>(const CastItem<double, float> *, int, hipStream_t);
+template void launch_cast_batch<float, double>(const CastItem<float, double> *, int, hipStream_t);
+
 void launch_cast_d2f(const double *x, float *y, int n, hipStream_t st) {
   if (n > 0) k_cast_d2f<<<cdiv(n, 256), 256, 0, st>>>(x, y, n);
 }
@@ -439,16 +531,16 @@ __device__ inline AT wload(const WT *w, int64_t idx, int kind) {
     return (AT)w[idx];
 }
 
-template <typename WT, typename VT, typename AT, bool IS16, int TAG, int NWV>
-__global__ __launch_bounds__(64 * NWV) void k_ras(RasView v, const WT *__restrict__ W,
-                                                  int w16_kind, const float *__restrict__ wscale,
-                                                  const VT *__restrict__ s,
-                                                  VT *__restrict__ e, AT omega, int add) {
+// task: the workgroup's task of v (v.ntask workgroups per operator)
+template <typename WT, typename VT, typename AT, bool IS16, int NWV>
+__device__ __forceinline__ void ras_body(int task, const RasView &v, const WT *__restrict__ W,
+                                         int w16_kind, const float *__restrict__ wscale,
+                                         const VT *__restrict__ s, VT *__restrict__ e, AT omega,
+                                         int add) {
   __shared__ AT xs[kMaxPatch];
   __shared__ AT red[NWV - 1][64];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int task = blockIdx.x;
   const int k = v.task_patch[task];
   const int r0 = v.task_row0[task];
   const int m = v.pm[k], o = v.po[k];
@@ -476,7 +568,7 @@ __global__ __launch_bounds__(64 * NWV) void k_ras(RasView v, const WT *__restric
     for (int c = threadIdx.x; c < m; c += 64 * NWV) xs[c] = (AT)s[d[c]];
   }
   if (!add)
-    for (int i = blockIdx.x * 64 * NWV + threadIdx.x; i < v.nunowned; i += gridDim.x * 64 * NWV)
+    for (int i = task * 64 * NWV + threadIdx.x; i < v.nunowned; i += v.ntask * 64 * NWV)
       e[v.unowned[i]] = (VT)0;
   __syncthreads();
   AT a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -502,6 +594,21 @@ __global__ __launch_bounds__(64 * NWV) void k_ras(RasView v, const WT *__restric
     const VT upd = (VT)(omega * acc);
     e[g] = add ? e[g] + upd : upd;
   }
+}
+template <typename WT, typename VT, typename AT, bool IS16, int TAG, int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_ras(RasView v, const WT *__restrict__ W,
+                                                  int w16_kind, const float *__restrict__ wscale,
+                                                  const VT *__restrict__ s,
+                                                  VT *__restrict__ e, AT omega, int add) {
+  ras_body<WT, VT, AT, IS16, NWV>(blockIdx.x, v, W, w16_kind, wscale, s, e, omega, add);
+}
+// the Schwarz steps of a batch of systems (one level each), each on its own tasks
+template <typename WT, typename VT, typename AT, bool IS16, int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_ras_batch(RasBatch<WT, VT> B, AT omega, int add) {
+  const int s = batch_entry(B.blk0, B.count, blockIdx.x);
+  const RasItem<WT, VT> &it = B.it[s];
+  ras_body<WT, VT, AT, IS16, NWV>(blockIdx.x - B.blk0[s], it.v, it.W, it.w16_kind, it.wscale, it.s, it.e,
+                                  omega, add);
 }
 
 static int ras_waves(int ntask);
@@ -673,14 +780,55 @@ void launch_ras_16(const RasView &v, const uint16_t *W, int w16_kind, const floa
                                                st, ev0, ev1);
 }
 
+// batched Schwarz steps: entries grouped by the waves per workgroup that a
+// single launch of the same level would use (the same arithmetic per system)
+template <typename WT, typename VT, typename AT, bool IS16>
+static void launch_ras_batch_t(const RasItem<WT, VT> *items, int count, AT omega, bool add, hipStream_t st) {
+  for (int nw : {4, 8, 16}) {
+    RasBatch<WT, VT> B;
+    B.count = 0;
+    B.blk0[0] = 0;
+    auto flush = [&] {
+      const int grid = B.count ? B.blk0[B.count] : 0;
+      if (grid > 0) {
+        if (nw == 4)
+          k_ras_batch<WT, VT, AT, IS16, 4><<<grid, 256, 0, st>>>(B, omega, (int)add);
+        else if (nw == 8)
+          k_ras_batch<WT, VT, AT, IS16, 8><<<grid, 512, 0, st>>>(B, omega, (int)add);
+        else
+          k_ras_batch<WT, VT, AT, IS16, 16><<<grid, 1024, 0, st>>>(B, omega, (int)add);
+      }
+      B.count = 0;
+    };
+    for (int i = 0; i < count; ++i) {
+      if (items[i].v.ntask == 0 || ras_waves(items[i].v.ntask) != nw) continue;
+      B.it[B.count] = items[i];
+      B.blk0[B.count + 1] = B.blk0[B.count] + items[i].v.ntask;
+      if (++B.count == kMaxBatch) flush();
+    }
+    flush();
+  }
+}
+void launch_ras_batch_f64(const RasItem<double, double> *items, int count, double omega, bool add,
+                          hipStream_t st) {
+  launch_ras_batch_t<double, double, double, false>(items, count, omega, add, st);
+}
+void launch_ras_batch_f32(const RasItem<float, float> *items, int count, float omega, bool add,
+                          hipStream_t st) {
+  launch_ras_batch_t<float, float, float, false>(items, count, omega, add, st);
+}
+void launch_ras_batch_16(const RasItem<uint16_t, float> *items, int count, float omega, bool add,
+                         hipStream_t st) {
+  launch_ras_batch_t<uint16_t, float, float, true>(items, count, omega, add, st);
+}
+
 // ------------------------------------------------------------------ coarsest solve GEMV
 // y = W x with W row-major: one wave per row streams the row (64 consecutive
 // doubles per load, four loads in flight), then a fixed butterfly
-__global__ __launch_bounds__(256) void k_gemv_rows(const double *__restrict__ W, int n,
-                                                   const double *__restrict__ x,
-                                                   double *__restrict__ y) {
+__device__ __forceinline__ void gemv_rows_body(int blk, const double *__restrict__ W, int n,
+                                               const double *__restrict__ x, double *__restrict__ y) {
   const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int row = blk * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
   const double *w = W + (int64_t)row * n;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -697,8 +845,33 @@ __global__ __launch_bounds__(256) void k_gemv_rows(const double *__restrict__ W,
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (lane == 0) y[row] = acc;
 }
+__global__ __launch_bounds__(256) void k_gemv_rows(const double *__restrict__ W, int n,
+                                                   const double *__restrict__ x,
+                                                   double *__restrict__ y) {
+  gemv_rows_body(blockIdx.x, W, n, x, y);
+}
+__global__ __launch_bounds__(256) void k_gemv_batch(GemvBatch B) {
+  const int s = batch_entry(B.blk0, B.count, blockIdx.x);
+  gemv_rows_body(blockIdx.x - B.blk0[s], B.it[s].W, B.it[s].n, B.it[s].x, B.it[s].y);
+}
 void launch_dense_gemv(const double *W, int n, const double *x, double *y, hipStream_t st) {
   if (n > 0) k_gemv_rows<<<cdiv(n, 4), 256, 0, st>>>(W, n, x, y);
+}
+void launch_dense_gemv_batch(const GemvItem *items, int count, hipStream_t st) {
+  GemvBatch B;
+  B.count = 0;
+  B.blk0[0] = 0;
+  auto flush = [&] {
+    if (B.count && B.blk0[B.count]) k_gemv_batch<<<B.blk0[B.count], 256, 0, st>>>(B);
+    B.count = 0;
+  };
+  for (int i = 0; i < count; ++i) {
+    if (items[i].n <= 0) continue;
+    B.it[B.count] = items[i];
+    B.blk0[B.count + 1] = B.blk0[B.count] + cdiv(items[i].n, 4);
+    if (++B.count == kMaxBatch) flush();
+  }
+  flush();
 }
 
 // Arnoldi column j (one thread): H[:, j] = h, |w| and breakdown test, the

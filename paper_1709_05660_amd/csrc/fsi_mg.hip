@@ -829,6 +829,184 @@ void apply_vcycle(MG &mg, const double *r, double *z, hipStream_t st) {
   }
 }
 
+// ------------------------------------------------------------------ batched V-cycles
+// The V-cycles of several systems, phase by phase, each phase one batched
+// launch over the systems that have it (a system with fewer levels reaches
+// its coarsest solve at a smaller depth and then waits for the ascent).
+// Every system sees the operations of vcycle() in the same order with the
+// same kernels' arithmetic, so its result equals its own V-cycle's.
+template <typename T>
+struct BatchLevel {
+  MG *mg;
+  int l;
+  const T *r;
+  T *e;
+};
+
+template <typename T>
+static CsrView<T> csr_view(const DevCsr &A);
+template <>
+CsrView<double> csr_view<double>(const DevCsr &A) {
+  return A.v64();
+}
+template <>
+CsrView<float> csr_view<float>(const DevCsr &A) {
+  return A.v32();
+}
+
+// y = op x (Set), y = r - op x (Resid) or y += op x (Add) for every entry:
+// op = 0 J, 1 R, 2 P of the entry's level
+template <typename T>
+static void batch_spmv(const std::vector<BatchLevel<T>> &a, int op, const std::vector<const T *> &x,
+                       const std::vector<const T *> &r, const std::vector<T *> &y, int mode, hipStream_t st) {
+  std::vector<SpmvItem<T>> it(a.size());
+  std::vector<int> lpr(a.size());
+  for (size_t i = 0; i < a.size(); ++i) {
+    const Level &L = a[i].mg->lv[a[i].l];
+    const DevCsr &A = op == 0 ? L.J : (op == 1 ? L.R : L.P);
+    it[i] = SpmvItem<T>{csr_view<T>(A), x[i], r[i], y[i]};
+    lpr[i] = A.lpr;
+  }
+  launch_spmv_batch<T>(it.data(), lpr.data(), (int)it.size(), mode, st);
+}
+
+static void batch_ras(const std::vector<BatchLevel<double>> &a, const std::vector<const double *> &s,
+                      const std::vector<double *> &e, bool add, hipStream_t st) {
+  std::vector<RasItem<double, double>> it;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const Level &L = a[i].mg->lv[a[i].l];
+    it.push_back(RasItem<double, double>{ras_view(L), L.W64, 0, nullptr, s[i], e[i]});
+  }
+  launch_ras_batch_f64(it.data(), (int)it.size(), a[0].mg->opts.omega, add, st);
+}
+static void batch_ras(const std::vector<BatchLevel<float>> &a, const std::vector<const float *> &s,
+                      const std::vector<float *> &e, bool add, hipStream_t st) {
+  std::vector<RasItem<float, float>> i32;
+  std::vector<RasItem<uint16_t, float>> i16;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const Level &L = a[i].mg->lv[a[i].l];
+    if (L.W32)
+      i32.push_back(RasItem<float, float>{ras_view(L), L.W32, 0, nullptr, s[i], e[i]});
+    else
+      i16.push_back(RasItem<uint16_t, float>{ras_view(L), L.W16, L.w16_kind, L.Wscale, s[i], e[i]});
+  }
+  const float omega = (float)a[0].mg->opts.omega;
+  if (!i32.empty()) launch_ras_batch_f32(i32.data(), (int)i32.size(), omega, add, st);
+  if (!i16.empty()) launch_ras_batch_16(i16.data(), (int)i16.size(), omega, add, st);
+  // the solid blocks kept apart (FP32 owned rows, refined solves): their own
+  // launches, on owned dofs disjoint from the batched ones
+  for (size_t i = 0; i < a.size(); ++i) {
+    MG &mg = *a[i].mg;
+    Level &L = mg.lv[a[i].l];
+    if (L.ntask_s) launch_ras_f32(ras_view_solid(L), L.Ws, s[i], e[i], omega, false, add, st);
+    if (L.nref)
+      launch_ras_refine(refine_view(L), L.Wfull32, L.Wfull16, s[i], e[i], omega, add, mg.opts.refine_sweeps,
+                        L.yref0, L.yref1, st);
+  }
+}
+
+static void batch_coarse(const std::vector<BatchLevel<double>> &c, hipStream_t st) {
+  std::vector<GemvItem> g;
+  for (auto &b : c) g.push_back(GemvItem{b.mg->lv[0].C0, b.mg->lv[0].n, b.r, b.e});
+  launch_dense_gemv_batch(g.data(), (int)g.size(), st);
+}
+static void batch_coarse(const std::vector<BatchLevel<float>> &c, hipStream_t st) {
+  std::vector<CastItem<float, double>> up;
+  std::vector<GemvItem> g;
+  std::vector<CastItem<double, float>> down;
+  for (auto &b : c) {
+    Level &L = b.mg->lv[0];
+    up.push_back(CastItem<float, double>{b.r, L.r, L.n});
+    g.push_back(GemvItem{L.C0, L.n, L.r, L.e});
+    down.push_back(CastItem<double, float>{L.e, b.e, L.n});
+  }
+  launch_cast_batch<float, double>(up.data(), (int)up.size(), st);
+  launch_dense_gemv_batch(g.data(), (int)g.size(), st);
+  launch_cast_batch<double, float>(down.data(), (int)down.size(), st);
+}
+
+template <typename T>
+static void batch_vcycle_levels(const std::vector<BatchLevel<T>> &cur, hipStream_t st) {
+  using O = VOps<T>;
+  std::vector<BatchLevel<T>> a, c;
+  for (auto &b : cur) (b.l == 0 ? c : a).push_back(b);
+  if (!c.empty()) batch_coarse(c, st);
+  if (a.empty()) return;
+  const int nu_pre = a[0].mg->opts.nu_pre, nu_post = a[0].mg->opts.nu_post;
+  const size_t n = a.size();
+  std::vector<const T *> r(n), sc(n), none(n, nullptr), ce_c(n);
+  std::vector<T *> e(n), sv(n), cr(n);
+  std::vector<BatchLevel<T>> next(n);
+  for (size_t i = 0; i < n; ++i) {
+    Level &L = a[i].mg->lv[a[i].l];
+    Level &C = a[i].mg->lv[a[i].l - 1];
+    r[i] = a[i].r;
+    e[i] = a[i].e;
+    sv[i] = O::s(L);
+    sc[i] = O::s(L);
+    cr[i] = O::r(C);
+    ce_c[i] = O::e(C);
+    next[i] = BatchLevel<T>{a[i].mg, a[i].l - 1, O::r(C), O::e(C)};
+  }
+  std::vector<const T *> e_c(e.begin(), e.end());
+  for (int it = 0; it < nu_pre; ++it) {
+    if (it == 0) {
+      batch_ras(a, r, e, false, st);
+    } else {
+      batch_spmv<T>(a, 0, e_c, r, sv, kSpmvResid, st);
+      batch_ras(a, sc, e, true, st);
+    }
+  }
+  if (nu_pre == 0) {
+    batch_spmv<T>(a, 1, r, none, cr, kSpmvSet, st);
+  } else {
+    batch_spmv<T>(a, 0, e_c, r, sv, kSpmvResid, st);
+    batch_spmv<T>(a, 1, sc, none, cr, kSpmvSet, st);
+  }
+  batch_vcycle_levels<T>(next, st);
+  batch_spmv<T>(a, 2, ce_c, none, e, nu_pre == 0 ? kSpmvSet : kSpmvAdd, st);
+  for (int it = 0; it < nu_post; ++it) {
+    batch_spmv<T>(a, 0, e_c, r, sv, kSpmvResid, st);
+    batch_ras(a, sc, e, true, st);
+  }
+}
+
+bool batch_compatible(const MG &a, const MG &b) {
+  const bool fa = a.mixed && a.nlevels > 1, fb = b.mixed && b.nlevels > 1;
+  return fa == fb && a.opts.nu_pre == b.opts.nu_pre && a.opts.nu_post == b.opts.nu_post &&
+         a.opts.omega == b.opts.omega;
+}
+
+void batched_vcycle(const std::vector<BatchItem> &items, hipStream_t st) {
+  if (items.empty()) return;
+  for (size_t i = 0; i < items.size(); ++i) {
+    const BatchItem &b = items[i];
+    if (b.r == b.z || !batch_compatible(*b.mg, *items[0].mg))
+      throw Error(FSI_E_INVALID, "batched V-cycle: aliased vectors or incompatible systems");
+    for (size_t k = 0; k < i; ++k)   // one entry per system: its level vectors are the cycle's workspace
+      if (items[k].mg == b.mg) throw Error(FSI_E_INVALID, "batched V-cycle: a system appears twice");
+  }
+  if (items[0].mg->mixed && items[0].mg->nlevels > 1) {
+    std::vector<CastItem<double, float>> in;
+    std::vector<CastItem<float, double>> out;
+    std::vector<BatchLevel<float>> lv;
+    for (auto &b : items) {
+      Level &F = b.mg->lv.back();
+      in.push_back(CastItem<double, float>{b.r, F.r32, F.n});
+      out.push_back(CastItem<float, double>{F.e32, b.z, F.n});
+      lv.push_back(BatchLevel<float>{b.mg, b.mg->nlevels - 1, F.r32, F.e32});
+    }
+    launch_cast_batch<double, float>(in.data(), (int)in.size(), st);
+    batch_vcycle_levels<float>(lv, st);
+    launch_cast_batch<float, double>(out.data(), (int)out.size(), st);
+  } else {
+    std::vector<BatchLevel<double>> lv;
+    for (auto &b : items) lv.push_back(BatchLevel<double>{b.mg, b.mg->nlevels - 1, b.r, b.z});
+    batch_vcycle_levels<double>(lv, st);
+  }
+  hip_check(hipGetLastError(), "batched V-cycle launch");
+}
+
 void run_vcycle(MG &mg, const double *r, double *z, hipStream_t st) {
   if (mg.opts.use_graph && !mg.prof_on) {
     // one graph per (input, output) pair; the Krylov loop reuses a small set of pairs
@@ -1291,6 +1469,39 @@ void FgmresRun::enqueue_step() {
                       K.H, m + 1, j, K.cs, K.sn, K.g, K.flags, K.scal, K.pinned_dev, st, twice);
 }
 
+// the step in two parts around an externally applied V-cycle (the server's
+// batched V-cycles): the part before it, returning the V-cycle's input and
+// output vectors, and the part after it
+void FgmresRun::enqueue_step_pre(const double **vin, double **vout) {
+  Krylov &K = *this->K;
+  Level &F = mg->lv.back();
+  const int n = F.n, m = ko.restart;
+  reinterpret_cast<volatile double *>(K.pinned)[2] = 0.0;   // set again by the step's last kernel
+  if (j == 0) launch_start_cycle(n, K.w, K.nrm, K.V, K.g, m, st);
+  double *vj = K.V + (int64_t)j * n;
+  if (left) {
+    launch_spmv(F.J.v64(), vj, (const double *)nullptr, K.Z, kSpmvSet, F.J.lpr, st);
+    *vin = K.Z;
+    *vout = K.w;
+  } else {
+    *vin = vj;
+    *vout = K.Z + (int64_t)j * n;
+  }
+  hip_check(hipGetLastError(), "arnoldi launch");
+}
+void FgmresRun::enqueue_step_post() {
+  Krylov &K = *this->K;
+  Level &F = mg->lv.back();
+  const int n = F.n, m = ko.restart;
+  if (!left) {
+    double *zj = K.Z + (int64_t)j * n;
+    launch_spmv(F.J.v64(), zj, (const double *)nullptr, K.w, kSpmvSet, F.J.lpr, st);
+  }
+  launch_arnoldi_orth(n, K.V, n, j + 1, K.w, K.partial, K.h1, K.npart, K.V + (int64_t)(j + 1) * n,
+                      K.H, m + 1, j, K.cs, K.sn, K.g, K.flags, K.scal, K.pinned_dev, st, twice);
+  hip_check(hipGetLastError(), "arnoldi launch");
+}
+
 void FgmresRun::enqueue() {
   if (phase != kIter) return;
   Krylov &K = *this->K;
@@ -1694,6 +1905,22 @@ fsi_status fsi_mg_vcycle(struct fsi_mg *h, const double *r_dev, double *z_dev, v
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
     run_vcycle(*mg, r_dev, z_dev, st);
     hip_check(hipGetLastError(), "vcycle launch");
+    return FSI_OK;
+  })
+}
+
+fsi_status fsi_mg_vcycle_batch(struct fsi_mg *const *mgs, int32_t count, const double *const *r_dev,
+                               double *const *z_dev, void *hip_stream) {
+  FSI_GUARD({
+    if (!mgs || !r_dev || !z_dev || count < 1) throw Error(FSI_E_INVALID, "null argument or count < 1");
+    std::vector<BatchItem> items;
+    for (int i = 0; i < count; ++i) {
+      MG *mg = reinterpret_cast<MG *>(mgs[i]);
+      if (!mg || !r_dev[i] || !z_dev[i]) throw Error(FSI_E_INVALID, "null argument");
+      items.push_back(BatchItem{mg, r_dev[i], z_dev[i]});
+    }
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : items[0].mg->own_stream;
+    batched_vcycle(items, st);
     return FSI_OK;
   })
 }

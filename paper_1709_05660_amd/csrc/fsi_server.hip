@@ -2,11 +2,16 @@
 //
 // Setup threads admit queued requests in arrival order while a slot is free
 // and the estimated device footprint fits the budget and set them up; each
-// admitted hierarchy stays resident, and tick threads advance every active
+// admitted hierarchy stays resident.  Each system's Krylov work runs on its
+// own stream.  Its V-cycles run either there too (tick threads advance each
 // system by one unit of FGMRES work as soon as its previous unit finished,
-// each system on its own stream so that their kernels overlap on the device.  A system that finishes is retired (result
-// copied to host, device memory returned to the server's caching pool) and
-// the next request admitted.  Device memory and streams are recycled: while
+// the systems' kernels overlapping on the device) or, with batch_vcycles, in
+// lockstep ticks: every tick takes the systems whose previous unit finished,
+// and the V-cycles of those that are at an Arnoldi step run together, one
+// batched launch per phase of the cycle over all of them, on the server's
+// batch stream between the steps' two halves on the systems' own streams.
+// A system that finishes is retired (result copied to host, device memory
+// returned to the server's caching pool) and the next request admitted.  Device memory and streams are recycled: while
 // serving no hipFree (a device-wide synchronisation) and no stream creation
 // happens once the pool has warmed up.
 #include <atomic>
@@ -48,6 +53,7 @@ struct Active {
   size_t b_bytes = 0, x_bytes = 0;
   int owner = 0;   // the tick thread that advances this system
   hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;   // batched mode: the first half of a step on st is done
   double *d_b = nullptr, *d_x = nullptr;
   FgmresRun run;
   Clock::time_point t_ready;
@@ -156,6 +162,11 @@ struct Server {
   std::atomic<bool> stop{false};
   uint64_t next_ticket = 1;
   int64_t used = 0, peak = 0, submitted = 0, finished = 0, ticks = 0, max_coresident = 0;
+  // batched V-cycles, per tick thread: their stream and the event that ends a
+  // group's cycles; the number of groups and of the systems in them
+  hipStream_t bst[kTickThreads] = {};
+  hipEvent_t bev[kTickThreads] = {};
+  int64_t bgroups = 0, bsystems = 0;
 };
 
 // device bytes of one system: operators, block inverses, coarse inverse,
@@ -293,6 +304,7 @@ static void finish(Server &S, Active &a, fsi_status st, const std::string &msg, 
   d.info.setup_ms = std::chrono::duration<double, std::milli>(a.t_ready - a.req->t_submit).count();
   d.info.solve_ms = std::chrono::duration<double, std::milli>(now - a.t_ready).count();
   if (a.st) (void)hipStreamSynchronize(a.st);
+  if (a.ev) (void)hipEventDestroy(a.ev);
   if (a.mg) destroy_mg(a.mg);
   if (a.d_b) S.pool.put(a.d_b, a.b_bytes);
   if (a.d_x) S.pool.put(a.d_x, a.x_bytes);
@@ -345,6 +357,7 @@ static void setup_loop(Server *S) {
         hip_check(hipStreamCreate(&a->st), "stream");
         hip_check(hipStreamCreateWithFlags(&a->side, hipStreamNonBlocking), "stream");
       }
+      if (S->o.batch_vcycles) hip_check(hipEventCreateWithFlags(&a->ev, hipEventDisableTiming), "event");
       a->mg = mg_setup(a->req->levels.data(), (int)a->req->levels.size(), &a->req->mo, a->st, a->st,
                        &S->pool, a->side);
       a->d_b = static_cast<double *>(S->pool.get(sizeof(double) * n, &a->b_bytes));
@@ -426,7 +439,138 @@ static void tick_loop(Server *S, int me) {
   }
 }
 
+// Batched mode, one group of compatible systems at an Arnoldi step: each
+// system's first half on its stream, the group's V-cycles on the batch
+// stream after all of them, each second half after the V-cycles.
+static void run_group(Server *S, int me, const std::vector<Active *> &grp, std::vector<Active *> &retired) {
+  hipStream_t bst = S->bst[me];
+  hipEvent_t bev = S->bev[me];
+  std::vector<BatchItem> items;
+  std::vector<Active *> ok;
+  for (Active *a : grp) {
+    try {
+      const double *vin = nullptr;
+      double *vout = nullptr;
+      a->run.enqueue_step_pre(&vin, &vout);
+      hip_check(hipEventRecord(a->ev, a->st), "event");
+      hip_check(hipStreamWaitEvent(bst, a->ev, 0), "wait");
+      items.push_back(BatchItem{a->mg, vin, vout});
+      ok.push_back(a);
+    } catch (const Error &e) {
+      (void)hipStreamSynchronize(bst);
+      finish(*S, *a, e.code, e.msg, false);
+      retired.push_back(a);
+    }
+  }
+  if (items.empty()) return;
+  try {
+    batched_vcycle(items, bst);
+    hip_check(hipEventRecord(bev, bst), "event");
+  } catch (const Error &e) {
+    (void)hipStreamSynchronize(bst);
+    for (Active *a : ok) {
+      finish(*S, *a, e.code, e.msg, false);
+      retired.push_back(a);
+    }
+    return;
+  }
+  for (Active *a : ok) {
+    try {
+      hip_check(hipStreamWaitEvent(a->st, bev, 0), "wait");
+      a->run.enqueue_step_post();
+    } catch (const Error &e) {
+      (void)hipStreamSynchronize(bst);
+      finish(*S, *a, e.code, e.msg, false);
+      retired.push_back(a);
+    }
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->bgroups++;
+  S->bsystems += (int64_t)ok.size();
+}
+
+// Batched mode: each tick thread owns a share of the active systems (two
+// cohorts, so that one cohort's launches are issued while the other's run)
+// and advances its share in lockstep.  A tick first waits until the previous
+// unit of every system of the share has finished (at most kLockstepWait; a system still busy then joins
+// a later tick), so that systems stay in step and their V-cycles can run
+// together.  A finished system then either ends, has its next phase already
+// queued (the checks between cycles), or is at an Arnoldi step, and those
+// steps run in groups of batch-compatible systems.
+constexpr auto kLockstepWait = std::chrono::milliseconds(5);
+static void batch_tick_loop(Server *S, int me) {
+  (void)hipSetDevice(S->o.device);
+  while (!S->stop.load()) {
+    std::vector<Active *> cur;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      for (auto &p : S->active)
+        if (p->owner == me) cur.push_back(p.get());
+      if (cur.empty()) {
+        S->cv.wait_for(lk, std::chrono::milliseconds(2), [&] {
+          if (S->stop.load()) return true;
+          for (auto &p : S->active)
+            if (p->owner == me) return true;
+          return false;
+        });
+        continue;
+      }
+      S->ticks++;
+    }
+    const auto t_wait = Clock::now();
+    for (bool busy = true; busy && Clock::now() - t_wait < kLockstepWait;) {
+      busy = false;
+      for (Active *a : cur)
+        if (hipStreamQuery(a->st) == hipErrorNotReady) busy = true;
+      if (busy) std::this_thread::sleep_for(std::chrono::microseconds(10));
+    }
+    std::vector<Active *> retired, steps;
+    bool progressed = false;
+    for (Active *a : cur) {
+      try {
+        const hipError_t q = hipStreamQuery(a->st);
+        if (q == hipErrorNotReady) continue;
+        hip_check(q, "tick");
+        progressed = true;
+        if (a->run.complete()) {
+          finish(*S, *a, a->run.converged ? FSI_OK : FSI_NOT_CONVERGED, "", true);
+          retired.push_back(a);
+        } else if (a->run.phase == FgmresRun::kIter) {
+          steps.push_back(a);
+        }
+      } catch (const Error &e) {
+        finish(*S, *a, e.code, e.msg, false);
+        retired.push_back(a);
+      }
+    }
+    std::vector<char> taken(steps.size(), 0);
+    for (size_t i = 0; i < steps.size(); ++i) {
+      if (taken[i]) continue;
+      std::vector<Active *> grp;
+      for (size_t k = i; k < steps.size() && (int)grp.size() < kMaxBatch; ++k)
+        if (!taken[k] && batch_compatible(*steps[k]->mg, *steps[i]->mg)) {
+          taken[k] = 1;
+          grp.push_back(steps[k]);
+        }
+      run_group(S, me, grp, retired);
+    }
+    if (!retired.empty()) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (Active *r : retired)
+        for (size_t i = 0; i < S->active.size(); ++i)
+          if (S->active[i].get() == r) {
+            S->active.erase(S->active.begin() + i);
+            break;
+          }
+      S->cv.notify_all();
+    }
+    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+}
+
 static void drain(Server *S) {
+  for (hipStream_t b : S->bst)
+    if (b) (void)hipStreamSynchronize(b);
   for (auto &a : S->active) {
     (void)hipStreamSynchronize(a->st);
     finish(*S, *a, FSI_E_DEVICE, "server destroyed", false);
@@ -442,13 +586,24 @@ extern "C" {
 
 fsi_status fsi_server_create(const fsi_server_opts *o, struct fsi_server **out) {
   try {
-    if (!o || !out || o->max_slots < 1 || o->hbm_budget_bytes <= 0)
+    if (!o || !out || o->max_slots < 1 || o->hbm_budget_bytes <= 0 ||
+        (o->batch_vcycles != 0 && o->batch_vcycles != 1) || o->reserved != 0)
       throw Error(FSI_E_INVALID, "invalid server options");
     Server *S = new Server();
     S->o = *o;
+    (void)hipSetDevice(o->device);
+    for (int i = 0; o->batch_vcycles && i < kTickThreads; ++i)
+      if (hipStreamCreate(&S->bst[i]) != hipSuccess ||
+          hipEventCreateWithFlags(&S->bev[i], hipEventDisableTiming) != hipSuccess) {
+        for (int k = 0; k <= i; ++k) {
+          if (S->bst[k]) (void)hipStreamDestroy(S->bst[k]);
+          if (S->bev[k]) (void)hipEventDestroy(S->bev[k]);
+        }
+        delete S;
+        throw Error(FSI_E_DEVICE, "batch stream");
+      }
     // the slots' streams are created up front (a stream's first creation is
     // slow), then recycled
-    (void)hipSetDevice(o->device);
     for (int i = 0; i < o->max_slots; ++i) {
       hipStream_t a = nullptr, b = nullptr;
       if (hipStreamCreate(&a) != hipSuccess) break;
@@ -460,7 +615,8 @@ fsi_status fsi_server_create(const fsi_server_opts *o, struct fsi_server **out) 
     }
     S->copies.start(kCopyThreads);
     for (int i = 0; i < kSetupThreads; ++i) S->setup_threads.emplace_back(setup_loop, S);
-    for (int i = 0; i < kTickThreads; ++i) S->tick_threads.emplace_back(tick_loop, S, i);
+    for (int i = 0; i < kTickThreads; ++i)
+      S->tick_threads.emplace_back(o->batch_vcycles ? batch_tick_loop : tick_loop, S, i);
     *out = reinterpret_cast<fsi_server *>(S);
     return FSI_OK;
   } catch (const Error &e) {
@@ -519,7 +675,7 @@ fsi_status fsi_serve_poll(struct fsi_server *h, uint64_t ticket, double *x_host,
   return st;
 }
 
-fsi_status fsi_server_stats(struct fsi_server *h, int64_t out[10]) {
+fsi_status fsi_server_stats(struct fsi_server *h, int64_t out[12]) {
   Server *S = reinterpret_cast<Server *>(h);
   if (!S || !out) return FSI_E_INVALID;
   std::lock_guard<std::mutex> lk(S->mu);
@@ -534,6 +690,8 @@ fsi_status fsi_server_stats(struct fsi_server *h, int64_t out[10]) {
   std::lock_guard<std::mutex> lp(S->pool.mu);
   out[8] = S->pool.allocated;
   out[9] = S->pool.peak_in_use;
+  out[10] = S->bgroups;
+  out[11] = S->bsystems;
   return FSI_OK;
 }
 
@@ -554,6 +712,10 @@ fsi_status fsi_server_destroy(struct fsi_server *h) {
   for (auto &p : S->free_streams) {
     (void)hipStreamDestroy(p.first);
     (void)hipStreamDestroy(p.second);
+  }
+  for (int i = 0; i < kTickThreads; ++i) {
+    if (S->bev[i]) (void)hipEventDestroy(S->bev[i]);
+    if (S->bst[i]) (void)hipStreamDestroy(S->bst[i]);
   }
   delete S;
   return FSI_OK;

@@ -204,6 +204,21 @@ class MG:
                 "vcycle")
         return z
 
+    @staticmethod
+    def vcycle_batch(mgs, rs, zs=None):
+        """z_i = M_i^{-1} r_i for several systems in batched launches
+        (fsi_mg_vcycle_batch); each z_i equals mgs[i].vcycle(rs[i])."""
+        import torch
+        if not mgs or len(rs) != len(mgs) or (zs is not None and len(zs) != len(mgs)):
+            raise ValueError("vcycle_batch: one r (and z) per handle")
+        if zs is None:
+            zs = [torch.empty(m.n, dtype=torch.float64, device="cuda") for m in mgs]
+        hs = (C.c_void_p * len(mgs))(*[m.h.value for m in mgs])
+        rp = (C.c_void_p * len(mgs))(*[_vec(r, m.n, "r").value for m, r in zip(mgs, rs)])
+        zp = (C.c_void_p * len(mgs))(*[_vec(z, m.n, "z").value for m, z in zip(mgs, zs)])
+        L.check(L.lib().fsi_mg_vcycle_batch(hs, len(mgs), rp, zp, _stream()), "vcycle_batch")
+        return zs
+
     def apply(self, level, op, x, r=None, y=None):
         """One operator of a level (fsi_mg_apply): op 0 J x, 1 r - J x, 2 P x,
         3 R x, 4 one Schwarz application, 5 the coarsest direct solve."""
@@ -291,11 +306,13 @@ class Server:
 
     Requests are copied at submit; the server keeps admitted hierarchies on
     the device, admits in arrival order while the memory budget and a slot
-    allow, and advances all active systems one FGMRES step per tick.
+    allow, and advances all active systems one FGMRES step per tick.  With
+    batch_vcycles the V-cycles of the systems stepping in a tick run as
+    batched launches (one per phase of the cycle) over all of them.
     """
 
-    def __init__(self, hbm_budget_bytes=4 << 30, max_slots=16, device=0):
-        so = L.ServerOpts(int(hbm_budget_bytes), int(max_slots), int(device))
+    def __init__(self, hbm_budget_bytes=4 << 30, max_slots=16, device=0, batch_vcycles=False):
+        so = L.ServerOpts(int(hbm_budget_bytes), int(max_slots), int(device), 1 if batch_vcycles else 0, 0)
         h = C.c_void_p()
         L.check(L.lib().fsi_server_create(C.byref(so), C.byref(h)), "server create")
         self.h = h
@@ -330,10 +347,11 @@ class Server:
         return st, x[:n], info.as_dict()
 
     def stats(self):
-        out = (C.c_int64 * 10)()
+        out = (C.c_int64 * 12)()
         L.check(L.lib().fsi_server_stats(self.h, out))
         keys = ["submitted", "finished", "active", "queued", "bytes_in_use", "peak_bytes", "ticks",
-                "max_coresident", "pool_allocated_bytes", "pool_peak_in_use_bytes"]
+                "max_coresident", "pool_allocated_bytes", "pool_peak_in_use_bytes", "batched_groups",
+                "batched_systems"]
         return dict(zip(keys, list(out)))
 
     def close(self):

@@ -66,18 +66,21 @@ class Request:
     u_peak: float
     seed: int
     arrival_s: float
+    transient: bool = False
 
 
 def serving_stream(n: int = 256, seed_base: int = 1000, arrival_seed: int = 4242,
                    rate_per_s: float = 100.0,
                    meshes=((32, 8, 2), (64, 16, 3), (128, 32, 4))) -> list:
-    """The Poisson stream of independent 2D systems.
+    """The Poisson stream of independent 2D systems: sweep points (steady
+    systems) and time steps (one Crank-Nicolson step).
 
     System i draws, from splitmix64(seed_base + i): the mesh uniformly from
     ``meshes`` (nx, ny, levels; coarsest 16x4), the solid shear modulus
-    10**(4 + 2U) (log-uniform in [1e4, 1e6]) and the inflow peak 0.05 + 0.25U;
-    its state seed is seed_base + i.  Inter-arrival gaps are exponential with
-    the given rate, from splitmix64(arrival_seed).
+    10**(4 + 2U) (log-uniform in [1e4, 1e6]), the inflow peak 0.05 + 0.25U
+    and then the kind (a time step when U < 0.5); its state seed is
+    seed_base + i.  Inter-arrival gaps are exponential with the given rate,
+    from splitmix64(arrival_seed).
     """
     arr = SplitMix64(arrival_seed)
     t = 0.0
@@ -88,7 +91,8 @@ def serving_stream(n: int = 256, seed_base: int = 1000, arrival_seed: int = 4242
         nx, ny, lv = meshes[mi]
         mu_s = 10.0 ** (4.0 + 2.0 * g.uniform())
         u_peak = 0.05 + 0.25 * g.uniform()
+        transient = g.uniform() < 0.5
         gap = -math.log(1.0 - arr.uniform()) / rate_per_s
         t += gap
-        out.append(Request(i, nx, ny, lv, mu_s, u_peak, seed_base + i, t))
+        out.append(Request(i, nx, ny, lv, mu_s, u_peak, seed_base + i, t, transient))
     return out

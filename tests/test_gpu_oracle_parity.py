@@ -182,11 +182,15 @@ def test_patch_lists_bit_exact_c1(c1_oracle):
 
 # ------------------------------------------------------------ served requests
 def _one_per_mesh_class():
-    """The first request of each mesh size in the serving stream."""
-    seen = {}
-    for r in serving_stream(256):
-        seen.setdefault((r.nx, r.ny), r)
-    return [seen[k] for k in sorted(seen)]
+    """One request of each mesh size in the serving stream, alternately a
+    sweep point and a time step (32x8 steady, 64x16 a time step, 128x32
+    steady): the first of that kind and size."""
+    stream = serving_stream(256)
+    sizes = sorted({(r.nx, r.ny) for r in stream})
+    out = []
+    for i, sz in enumerate(sizes):
+        out.append(next(r for r in stream if (r.nx, r.ny) == sz and r.transient == bool(i % 2)))
+    return out
 
 
 def _wait(server, ticket, timeout=120.0):
@@ -201,20 +205,23 @@ def _wait(server, ticket, timeout=120.0):
         time.sleep(0.001)
 
 
-def test_served_results_match_checker():
-    """One request of each mesh class of the serving stream, served in FP64
-    for the checker's iteration count (1e-10 against the checker's iterate)
-    and in the mixed bf16 form to 1e-8 (host residual with the checker's
-    Jacobian <= 1e-8, error <= MIXED_ERR_BOUND)."""
+@pytest.mark.parametrize("batched", [False, True])
+def test_served_results_match_checker(batched):
+    """One request of each mesh class of the serving stream (sweep points and
+    a time step), served in FP64 for the checker's iteration count (1e-10
+    against the checker's iterate) and in the mixed bf16 form to 1e-8 (host
+    residual with the checker's Jacobian <= 1e-8, error <= MIXED_ERR_BOUND),
+    with each system's V-cycles on its own stream or batched."""
     from paper_1709_05660_amd import Problem, Server
     base = config("c2_2d_128x32_mixed")
-    srv = Server(hbm_budget_bytes=8 << 30, max_slots=4)
+    srv = Server(hbm_budget_bytes=8 << 30, max_slots=4, batch_vcycles=batched)
     try:
         for r in _one_per_mesh_class():
             s = base.with_(nx=r.nx, ny=r.ny, levels=r.levels, mu_s=r.mu_s, u_peak=r.u_peak, seed=r.seed,
-                           rtol=1e-10)
+                           rtol=1e-10, transient=r.transient)
             a = fourier_coefficients(2, r.seed)
-            _say(f"served {r.nx}x{r.ny} mu_s {r.mu_s:.3g} u_peak {r.u_peak:.3f}: checker hierarchy")
+            _say(f"served {r.nx}x{r.ny} {'time step' if r.transient else 'steady'} mu_s {r.mu_s:.3g} "
+                 f"u_peak {r.u_peak:.3f} batched {batched}: checker hierarchy")
             oh = oprob.build(s, a)
             x_o, io = oprob.solve(oh)
             k = io.iters

@@ -177,3 +177,42 @@ def test_malformed_request_is_reported_at_poll():
     st, x, info = _wait(srv, t_good)
     assert st == 0
     srv.close()
+
+
+def test_batched_vcycles_equal_per_system_results():
+    """Batched V-cycles (lockstep ticks, one launch per phase over the
+    stepping systems): each result is bit-identical alone and in the mix, and
+    to the per-stream server's, for bf16 and FP64 requests and for sweep
+    points and time steps."""
+    from paper_1709_05660_amd import Problem, Server
+    base = config("c1_2d_128x32")
+    specs = [base.with_(nx=32, ny=8, levels=2, mu_s=2.0e4, u_peak=0.1, seed=1001),
+             base.with_(nx=64, ny=16, levels=3, mu_s=3.0e5, u_peak=0.25, seed=1002, transient=True),
+             base.with_(nx=32, ny=8, levels=2, mu_s=8.0e5, u_peak=0.05, seed=1003, transient=True),
+             base.with_(nx=64, ny=16, levels=3, mu_s=1.0e4, u_peak=0.3, seed=1004),
+             base.with_(nx=128, ny=32, levels=4, mu_s=5.0e5, u_peak=0.2, seed=1005)]
+    probs = [Problem(s, fourier_coefficients(2, s.seed)) for s in specs]
+    results = {}
+    for prec in ("bf16", "fp64"):
+        for mode, slots in (("alone", 1), ("mixed", 8), ("streams", 8)):
+            srv = Server(hbm_budget_bytes=8 << 30, max_slots=slots, batch_vcycles=mode != "streams")
+            tickets = [srv.submit(p, precision=prec, rtol=1e-8) for p in probs]
+            out = [_wait(srv, t) for t in tickets]
+            stats = srv.stats()
+            srv.close()
+            _say(prec, mode, "stats", stats, "iters", [o[2]["iters"] for o in out])
+            for st, x, info in out:
+                assert st == 0, info
+            results[(prec, mode)] = [o[1] for o in out]
+            if mode == "mixed":
+                # how many systems share a group depends on timing; the
+                # batched launches over several systems are tested directly
+                # (tests/test_gpu_batch.py)
+                assert stats["batched_groups"] > 0
+            if mode == "streams":
+                assert stats["batched_groups"] == 0
+        for i, p in enumerate(probs):
+            xa, xm, xs = (results[(prec, m)][i] for m in ("alone", "mixed", "streams"))
+            assert np.array_equal(xa, xm), (prec, i)
+            assert np.array_equal(xa, xs), (prec, i)
+            assert _true_relres(p, xa) <= 1e-8 * 1.001
