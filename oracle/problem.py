@@ -62,7 +62,7 @@ def build(spec, coeffs, factor=True):
         lv.ptr, lv.dof, lv.owned, lv.kind = ptr, dof, owned, kind
     h = Hierarchy(spec, meshes, flags, levels, b, y, r)
     if factor:
-        solver.setup_factors(levels)
+        solver.setup_factors(levels, fluid_ilu=getattr(spec, "fluid_ilu", False))
     return h
 
 

@@ -3,7 +3,10 @@
 Test infrastructure only.
 
 * Local solves: LU with partial pivoting of B_k = J[I_k, I_k] (the paper's
-  exact local direct solve, mandatory on solid blocks), via LAPACK getrf.
+  exact local direct solve, mandatory on solid blocks), via LAPACK getrf; or,
+  on fluid blocks, ILU(0) (section "Richardson-Schwarz smoother": an
+  incomplete factorization suffices there): no pivoting, no fill beyond the
+  block's stored entries and its diagonal.
 * Smoother (section "Richardson-Schwarz smoother"): Richardson iteration
   e <- e - omega B^{-1}(J e + r) for J e = -r, i.e. e <- e + omega B^{-1}(r - J e)
   for J e = r, with the restricted additive Schwarz operator
@@ -43,8 +46,48 @@ class Level:
     lu: list = field(default_factory=list)
 
 
-def setup_factors(levels):
-    """LU factors of every patch block (levels >= 1) and of the coarsest operator."""
+def block_pattern(J, I):
+    """Positions of B_k = J[I_k, I_k] that hold a stored entry of J, and the
+    diagonal (a boolean m x m array)."""
+    B = J[I][:, I].tocoo()
+    pat = np.zeros((len(I), len(I)), dtype=bool)
+    pat[B.row, B.col] = True
+    np.fill_diagonal(pat, True)
+    return pat
+
+
+def ilu0_factor(B, pattern):
+    """ILU(0) of the dense block B on `pattern` (boolean, diagonal included):
+    L unit lower and U upper triangular, both zero off the pattern, with
+    (L U)_ij = B_ij on the pattern.  Row by row (i ascending): for each pattern
+    column k < i in ascending order, l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj
+    at the pattern columns j > k of row i.  Returns L (below the diagonal)
+    and U (on and above it) in one array."""
+    A = np.where(pattern, B, 0.0).astype(np.float64)
+    m = A.shape[0]
+    for i in range(1, m):
+        for k in np.nonzero(pattern[i, :i])[0]:
+            A[i, k] = A[i, k] / A[k, k]
+            A[i, k + 1:] -= np.where(pattern[i, k + 1:], A[i, k] * A[k, k + 1:], 0.0)
+    return A
+
+
+def ilu0_solve(F, g):
+    """(L U)^{-1} g for the combined factors F of ilu0_factor: L y = g by
+    forward substitution (unit diagonal), then U z = y backward."""
+    m = len(g)
+    y = np.array(g, dtype=np.float64)
+    for i in range(m):
+        y[i] -= F[i, :i] @ y[:i]
+    for i in range(m - 1, -1, -1):
+        y[i] = (y[i] - F[i, i + 1:] @ y[i + 1:]) / F[i, i]
+    return y
+
+
+def setup_factors(levels, fluid_ilu=False):
+    """LU factors of every patch block (levels >= 1) and of the coarsest
+    operator; with fluid_ilu, ILU(0) factors (tagged "ilu0") of the fluid
+    blocks (kind 0) instead."""
     levels[0].lu = [sla.lu_factor(levels[0].J.toarray(), check_finite=True)]
     for lv in levels[1:]:
         A = lv.J
@@ -52,7 +95,17 @@ def setup_factors(levels):
         for k in range(len(lv.ptr) - 1):
             I = lv.dof[lv.ptr[k]:lv.ptr[k + 1]]
             Bk = A[I][:, I].toarray()
-            lv.lu.append(sla.lu_factor(Bk, check_finite=True))
+            if fluid_ilu and lv.kind is not None and lv.kind[k] == 0:
+                lv.lu.append(("ilu0", ilu0_factor(Bk, block_pattern(A, I))))
+            else:
+                lv.lu.append(sla.lu_factor(Bk, check_finite=True))
+
+
+def local_solve(f, g):
+    """B_k^{-1} g with the block's factors (LU, or tagged ILU(0))."""
+    if isinstance(f[0], str):
+        return ilu0_solve(f[1], g)
+    return sla.lu_solve(f, g)
 
 
 def extract_block(J, I):
@@ -66,7 +119,7 @@ def ras(lv, s):
     for k in range(len(lv.ptr) - 1):
         a, b = lv.ptr[k], lv.ptr[k + 1]
         I = lv.dof[a:b]
-        y = sla.lu_solve(lv.lu[k], s[I])
+        y = local_solve(lv.lu[k], s[I])
         own = lv.owned[a:b].astype(bool)
         out[I[own]] += y[own]
     return out

@@ -39,6 +39,8 @@ class ProblemSpec:
     dt: float = 0.01             # the paper's FSI3-T-2D time step
     rho_s: float = 1000.0        # solid density
     amp_d: float = 1.0e-3
+    # local solves of the fluid blocks: ILU(0) instead of the exact inverse
+    fluid_ilu: bool = False
     # solver settings
     nu_pre: int = 2
     nu_post: int = 2
