@@ -74,14 +74,10 @@ def ilu0_factor(B, pattern):
 
 def ilu0_solve(F, g):
     """(L U)^{-1} g for the combined factors F of ilu0_factor: L y = g by
-    forward substitution (unit diagonal), then U z = y backward."""
-    m = len(g)
-    y = np.array(g, dtype=np.float64)
-    for i in range(m):
-        y[i] -= F[i, :i] @ y[:i]
-    for i in range(m - 1, -1, -1):
-        y[i] = (y[i] - F[i, i + 1:] @ y[i + 1:]) / F[i, i]
-    return y
+    forward substitution (unit diagonal), then U z = y by back substitution
+    (LAPACK's triangular solves)."""
+    y = sla.solve_triangular(F, np.asarray(g, dtype=np.float64), lower=True, unit_diagonal=True)
+    return sla.solve_triangular(F, y, lower=False)
 
 
 def setup_factors(levels, fluid_ilu=False):
