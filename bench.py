@@ -207,6 +207,55 @@ def three_d_leg(args):
     return res
 
 
+def time_step_leg(args):
+    """One Crank-Nicolson time step of the 128x32 system (section
+    "Discretization of the operator formulation"): the step (refactor +
+    solve) with exact local solves on every block and with ILU(0) on the
+    fluid blocks (section "Richardson-Schwarz smoother"), FP64 to 1e-10 and
+    the mixed form to 1e-8; factor bytes of the finest level."""
+    import torch
+
+    from paper_1709_05660_amd import MG, Problem
+    from synth import config, fourier_coefficients
+
+    spec = config("c4_2d_128x32_cn")
+    p = Problem(spec, fourier_coefficients(spec.dim, spec.seed))
+    stream = torch.cuda.Stream()
+    res = {"unknowns": p.n, "dt": spec.dt}
+    tune_db = tuning_db()
+    with torch.cuda.stream(stream):
+        b = torch.as_tensor(p.b).to("cuda")
+        x = torch.zeros_like(b)
+        for prec, ilu in (("fp64", False), ("fp64", True), (args.mixed, False), (args.mixed, True)):
+            rtol = spec.rtol if prec == "fp64" else 1e-8
+            mg = MG(p, precision=prec, use_graph=True, fluid_ilu=ilu)
+            mg.autotune(tune_db)
+            infos = []
+            for k in range(args.warmup + args.steps_3d):
+                if k == args.warmup:
+                    torch.cuda.synchronize()
+                    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    ev0.record(stream)
+                mg.refactor()
+                _, info = mg.fgmres(b, x, restart=spec.restart, rtol=rtol, maxit=spec.maxit)
+                infos.append(info)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / args.steps_3d
+            li = mg.level_info(p.nlevels - 1)
+            wb = {"fp64": 8, "fp32": 4}.get(prec, 2)
+            vb = 8 if prec == "fp64" else 4
+            res[f"{prec}{'_fluid_ilu' if ilu else ''}"] = {
+                "rtol": rtol, "ms_per_step": round(ms, 3), "solves_per_s": round(1e3 / ms, 2),
+                "iters": infos[-1]["iters"], "true_relres": float(f"{infos[-1]['true_relres']:.4g}"),
+                "converged": all(i["converged"] == 1 for i in infos),
+                "refactor_ms": round(infos[-1]["setup_ms"], 3), "solve_ms": round(infos[-1]["solve_ms"], 3),
+                "vcycle_ms": round(vcycle_times(mg, p.n, stream, 20), 4),
+                "finest_factor_bytes": int(li["sum_om"] * wb + li["ilu_entries"] * (vb + 2))}
+            mg.close()
+    return res
+
+
 def small_leg(args):
     """The 16x4 two-level system (1,380 unknowns): V-cycle and solve in FP64,
     where launch latency, not bandwidth, sets the time."""
@@ -618,6 +667,7 @@ def main():
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
+    ap.add_argument("--no-time-step", action="store_true")
     ap.add_argument("--steps-3d", type=int, default=5)
     ap.add_argument("--only-3d", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true")
@@ -662,6 +712,8 @@ def main():
         line["small_c0"] = small_leg(args)
     if not args.no_3d:
         line["three_d"] = three_d_leg(args)
+    if not args.no_time_step:
+        line["time_step"] = time_step_leg(args)
     if not args.no_paper:
         line["paper_mode"] = paper_leg(args)
     if not args.no_serve:

@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define FSI_ABI_VERSION 3
+#define FSI_ABI_VERSION 4
 
 typedef int32_t fsi_status;
 enum {
@@ -116,6 +116,14 @@ typedef struct {
   int32_t use_graph;       /* replay the V-cycle and each Arnoldi step from hipGraphs */
   const char *tuning_db;   /* NULL, or a text database path: setup then runs the
                               autotuner (fsi_mg_autotune) with it */
+  int32_t fluid_ilu;       /* 0, or 1: the fluid blocks (patch kind 0) are solved with
+                              ILU(0) factors (no pivoting, no fill beyond the block's
+                              stored entries and its diagonal) instead of their exact
+                              inverse; solid blocks stay exact.  Section "Richardson-
+                              Schwarz smoother": an incomplete factorization suffices on
+                              fluid subdomains.  Factored at every refactor (a zero pivot
+                              fails it with FSI_E_SINGULAR); applied by forward and
+                              backward substitution in the V-cycle's precision */
 } fsi_mg_opts;
 
 typedef struct {
@@ -267,8 +275,10 @@ fsi_status fsi_mg_profile(struct fsi_mg *mg, int32_t enable, double out[4]);
 fsi_status fsi_mg_autotune(struct fsi_mg *mg, const char *db_path, void *hip_stream,
                            int32_t *measured);
 
-/* Sizes of level `level`: n, nnz(J), npatch, sum m_k, sum m_k^2, sum owned_k * m_k. */
-fsi_status fsi_mg_level_info(struct fsi_mg *mg, int32_t level, int64_t out[6]);
+/* Sizes of level `level`: n, nnz(J), npatch, sum m_k, sum m_k^2, sum owned_k * m_k over the
+ * blocks kept as explicit inverses, number of ILU blocks, their factor entries (L, U and the
+ * diagonal; fluid_ilu). */
+fsi_status fsi_mg_level_info(struct fsi_mg *mg, int32_t level, int64_t out[8]);
 
 fsi_status fsi_mg_destroy(struct fsi_mg *mg);
 

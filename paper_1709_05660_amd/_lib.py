@@ -48,7 +48,8 @@ class LevelC(C.Structure):
 class MgOpts(C.Structure):
     _fields_ = [("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("omega", C.c_double),
                 ("precision", C.c_int32), ("solid_precision", C.c_int32),
-                ("refine_sweeps", C.c_int32), ("use_graph", C.c_int32), ("tuning_db", C.c_char_p)]
+                ("refine_sweeps", C.c_int32), ("use_graph", C.c_int32), ("tuning_db", C.c_char_p),
+                ("fluid_ilu", C.c_int32)]
 
 
 class KrylovOpts(C.Structure):

@@ -75,6 +75,20 @@ struct Level {
   uint16_t *W16 = nullptr;
   float *Wscale = nullptr, *Cscale = nullptr;
   int w16_kind = 0;
+  // ILU(0) of the fluid blocks (fluid_ilu): the nilu blocks, their rows'
+  // L/U patterns, the factors' positions in the dense blocks (level-relative)
+  // and values (FP64, or FP32 in a mixed hierarchy)
+  int nilu = 0, ilu_max_entries = 0;
+  int64_t ilu_nl = 0, ilu_nu = 0, ilu_rows = 0;
+  int *d_ilu_patch = nullptr, *d_ilu_row0 = nullptr, *d_ilu_lptr = nullptr, *d_ilu_uptr = nullptr,
+      *d_ilu_cptr = nullptr, *d_ilu_lpos = nullptr, *d_ilu_upos = nullptr, *d_ilu_dpos = nullptr,
+      *d_ilu_flev = nullptr, *d_ilu_flev_off = nullptr, *d_ilu_blev = nullptr, *d_ilu_blev_off = nullptr;
+  int16_t *d_ilu_lcol = nullptr, *d_ilu_ucol = nullptr, *d_ilu_crow = nullptr, *d_ilu_frow = nullptr,
+          *d_ilu_brow = nullptr;
+  uint32_t *d_ilu_mask = nullptr;
+  int64_t *d_ilu_moff = nullptr;
+  double *ilu_l64 = nullptr, *ilu_u64 = nullptr, *ilu_d64 = nullptr;
+  float *ilu_l32 = nullptr, *ilu_u32 = nullptr, *ilu_d32 = nullptr;
   // coarsest level: row-major inverse
   double *C0 = nullptr;
   // work vectors

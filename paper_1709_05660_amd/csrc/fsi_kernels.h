@@ -164,6 +164,49 @@ void launch_gather_f32(const float *val, const int *src, int n, float *out, hipS
 void launch_ras_refine(const RefineView &v, const float *W32, const uint16_t *W16, const float *s, float *e,
                        float omega, bool add, int sweeps, float *y0, float *y1, hipStream_t st);
 
+// ---- ILU(0) local solves of the fluid blocks (fluid_ilu): per ILU block b
+// (patch patch[b], m rows, index r = row0[b] + k for its row or column k),
+// L (unit lower) and U (upper) on the block's pattern, U's diagonal apart.
+// L's rows: columns lcol[lptr[r] .. lptr[r + 1]) (< k); U's rows: ucol[uptr[r]
+// .. uptr[r + 1]) (> k); L's columns: rows crow[cptr[r] .. cptr[r + 1])
+// (> k); local indices.  The factorization uses U's rows and L's columns
+// with the pattern as a bit mask (m x m bits at word moff[b]).  The
+// substitutions go level by level: the block's rows sorted by forward level
+// are frow[row0[b] ..), level f spanning frow[flev[f] .. flev[f + 1]) for f
+// in [flev_off[b], flev_off[b + 1]) (a row's L columns all lie in earlier
+// levels); backward levels likewise (brow, blev, blev_off; U columns in
+// earlier levels).  frow/brow hold local row numbers.
+struct IluView {
+  int nblk;
+  const int *patch, *row0;
+  const int *pm, *dof, *out_off, *own_local, *out_idx;
+  const int64_t *pdof_off, *boff;
+  const int *lptr, *uptr, *cptr;
+  const int16_t *lcol, *ucol, *crow;
+  const int16_t *frow, *brow;
+  const int *flev, *flev_off, *blev, *blev_off;
+  const uint32_t *mask;
+  const int64_t *moff;
+  const int *unowned;
+  int nunowned;
+  int max_entries;   // L + U entries of the largest block (LDS staging when they fit)
+};
+// in place on the dense blocks B_k (row-major at boff[k]; FP64 or FP32),
+// zero off the pattern on entry; status[status_base + patch] = 0, or 1 + the
+// step whose pivot is zero or not finite
+template <typename T>
+void launch_ilu_factor(const IluView &v, T *blocks, int *status, int status_base, hipStream_t st);
+// out[q] = (V) blocks[pos[q]] for q < n (the factors' values, compacted)
+template <typename T, typename V>
+void launch_ilu_gather(const T *blocks, const int *pos, int64_t n, V *out, hipStream_t st);
+// e[owned dofs of every ILU block] (+)= omega (L U)^{-1} s[I_k] (lval, uval:
+// the L and U values in row order; udiag: U's diagonal by row); with clear
+// (and add false) also e[unowned] = 0 (when no other Schwarz launch of the
+// level does)
+template <typename V>
+void launch_ilu_apply(const IluView &v, const V *lval, const V *uval, const V *udiag, const V *s, V *e,
+                      V omega, bool add, bool clear, hipStream_t st);
+
 // ---- coarsest solve (a7): y = W x, W row-major n x n FP64
 void launch_dense_gemv(const double *W, int n, const double *x, double *y, hipStream_t st);
 

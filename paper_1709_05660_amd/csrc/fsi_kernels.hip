@@ -822,6 +822,191 @@ void launch_ras_batch_16(const RasItem<uint16_t, float> *items, int count, float
   launch_ras_batch_t<uint16_t, float, float, true>(items, count, omega, add, st);
 }
 
+// ------------------------------------------------------------------ ILU(0) of fluid blocks
+// a failed attribute call must not leave its error for the next launch check
+static inline void hip_ok_or_clear(hipError_t e) {
+  if (e != hipSuccess) (void)hipGetLastError();
+}
+
+// Right-looking elimination on the dense block with the pattern as a mask,
+// one workgroup per block: step k updates a_ij -= (a_ik / a_kk) a_kj at the
+// pattern positions (i, j) with i, j > k, a_ik and a_kj in the pattern (the
+// L rows of column k times the U columns of row k, spread over the
+// threads), then scales the L column.  Every a_ij receives its updates in
+// ascending k, the order of the row-by-row formulation.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ilu_factor(IluView v, T *__restrict__ blocks, int *__restrict__ status,
+                                                    int status_base) {
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int k = v.patch[b], m = v.pm[k], r0 = v.row0[b];
+  T *A = blocks + v.boff[k];
+  const uint32_t *mk = v.mask + v.moff[b];
+  int fail = 0;
+  for (int kk = 0; kk < m; ++kk) {
+    const T akk = A[(int64_t)kk * m + kk];
+    if (!(akk != (T)0) || !isfinite((double)akk)) {
+      fail = kk + 1;
+      break;
+    }
+    const int ua = v.uptr[r0 + kk], nu = v.uptr[r0 + kk + 1] - ua;
+    const int ca = v.cptr[r0 + kk], nl = v.cptr[r0 + kk + 1] - ca;
+    for (int t = tid; t < nl * nu; t += 256) {
+      const int i = v.crow[ca + t / nu], j = v.ucol[ua + t % nu];
+      const int64_t bit = (int64_t)i * m + j;
+      if ((mk[bit >> 5] >> (bit & 31)) & 1u) {
+        const T l = A[(int64_t)i * m + kk] / akk;
+        A[(int64_t)i * m + j] -= l * A[(int64_t)kk * m + j];
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int t = tid; t < nl; t += 256) {
+      const int64_t q = (int64_t)v.crow[ca + t] * m + kk;
+      A[q] = A[q] / akk;
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  if (tid == 0) status[status_base + k] = fail;
+}
+template <typename T>
+void launch_ilu_factor(const IluView &v, T *blocks, int *status, int status_base, hipStream_t st) {
+  if (v.nblk > 0) k_ilu_factor<T><<<v.nblk, 256, 0, st>>>(v, blocks, status, status_base);
+}
+template void launch_ilu_factor<double>(const IluView &, double *, int *, int, hipStream_t);
+template void launch_ilu_factor<float>(const IluView &, float *, int *, int, hipStream_t);
+
+template <typename T, typename V>
+__global__ void k_ilu_gather(const T *__restrict__ blocks, const int *__restrict__ pos, int64_t n,
+                             V *__restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q < n) out[q] = (V)blocks[pos[q]];
+}
+template <typename T, typename V>
+void launch_ilu_gather(const T *blocks, const int *pos, int64_t n, V *out, hipStream_t st) {
+  if (n > 0) k_ilu_gather<T, V><<<cdiv(n, 256), 256, 0, st>>>(blocks, pos, n, out);
+}
+template void launch_ilu_gather<double, double>(const double *, const int *, int64_t, double *, hipStream_t);
+template void launch_ilu_gather<float, float>(const float *, const int *, int64_t, float *, hipStream_t);
+
+// Forward then backward substitution of one ILU block per wave, level by
+// level: the rows of a level depend only on earlier levels, so eight rows at
+// a time run side by side, eight lanes per row summing its products (in a
+// fixed order: lane-strided partial sums, then a fixed butterfly), with one
+// wave barrier per level.  The block's row offsets, columns and values are
+// staged in LDS first (STAGE, when they fit), else read from memory.
+template <typename V, bool STAGE>
+__global__ __launch_bounds__(64) void k_ilu_apply(IluView v, const V *__restrict__ lval, const V *__restrict__ uval,
+                                                  const V *__restrict__ udiag, const V *__restrict__ s,
+                                                  V *__restrict__ e, V omega, int add, int clear) {
+  extern __shared__ __align__(16) unsigned char ilu_lds[];
+  __shared__ V y[kMaxPatch];
+  __shared__ V dg[kMaxPatch];
+  __shared__ int lp[kMaxPatch + 1], upp[kMaxPatch + 1];
+  __shared__ int16_t fr[kMaxPatch], br[kMaxPatch];
+  __shared__ int16_t fl[kMaxPatch + 1], bl[kMaxPatch + 1];   // level starts (local)
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const int k = v.patch[b], m = v.pm[k], r0 = v.row0[b];
+  const int *d = v.dof + v.pdof_off[k];
+  const int la = v.lptr[r0], ua = v.uptr[r0];
+  const int f0 = v.flev_off[b], nf = v.flev_off[b + 1] - f0;
+  const int b0 = v.blev_off[b], nb = v.blev_off[b + 1] - b0;
+  for (int t = lane; t <= nf; t += 64) fl[t] = (int16_t)(v.flev[f0 + t] - r0);
+  for (int t = lane; t <= nb; t += 64) bl[t] = (int16_t)(v.blev[b0 + t] - r0);
+  for (int c = lane; c < m; c += 64) {
+    y[c] = s[d[c]];
+    dg[c] = udiag[r0 + c];
+    fr[c] = v.frow[r0 + c];
+    br[c] = v.brow[r0 + c];
+  }
+  for (int c = lane; c <= m; c += 64) {
+    lp[c] = v.lptr[r0 + c] - la;
+    upp[c] = v.uptr[r0 + c] - ua;
+  }
+  if (clear && !add)
+    for (int i = b * 64 + lane; i < v.nunowned; i += v.nblk * 64) e[v.unowned[i]] = (V)0;
+  const V *Lv = lval + la, *Uv = uval + ua;
+  const int16_t *Lc = v.lcol + la, *Uc = v.ucol + ua;
+  if constexpr (STAGE) {
+    // L values, U values, then the 16-bit columns
+    const int nl = v.lptr[r0 + m] - la, nu = v.uptr[r0 + m] - ua;
+    V *sv = reinterpret_cast<V *>(ilu_lds);
+    int16_t *sc = reinterpret_cast<int16_t *>(sv + nl + nu);
+    for (int q = lane; q < nl; q += 64) {
+      sv[q] = Lv[q];
+      sc[q] = Lc[q];
+    }
+    for (int q = lane; q < nu; q += 64) {
+      sv[nl + q] = Uv[q];
+      sc[nl + q] = Uc[q];
+    }
+    Lv = sv;
+    Uv = sv + nl;
+    Lc = sc;
+    Uc = sc + nl;
+  }
+  __syncthreads();
+  const int grp = lane >> 3, sub = lane & 7;
+  for (int f = 0; f < nf; ++f) {
+    const int a = fl[f], z = fl[f + 1];
+    for (int base = a; base < z; base += 8) {
+      const int rr = base + grp;
+      int row = 0;
+      V acc = 0;
+      if (rr < z) {
+        row = fr[rr];
+        for (int q = lp[row] + sub; q < lp[row + 1]; q += 8) acc += Lv[q] * y[Lc[q]];
+      }
+      acc = group_sum<V, 8>(acc);
+      if (rr < z && sub == 0) y[row] -= acc;
+    }
+    __syncthreads();
+  }
+  for (int f = 0; f < nb; ++f) {
+    const int a = bl[f], z = bl[f + 1];
+    for (int base = a; base < z; base += 8) {
+      const int rr = base + grp;
+      int row = 0;
+      V acc = 0;
+      if (rr < z) {
+        row = br[rr];
+        for (int q = upp[row] + sub; q < upp[row + 1]; q += 8) acc += Uv[q] * y[Uc[q]];
+      }
+      acc = group_sum<V, 8>(acc);
+      if (rr < z && sub == 0) y[row] = (y[row] - acc) / dg[row];
+    }
+    __syncthreads();
+  }
+  for (int t = v.out_off[k] + lane; t < v.out_off[k + 1]; t += 64) {
+    const int g = v.out_idx[t];
+    const V u = omega * y[v.own_local[t]];
+    e[g] = add ? e[g] + u : u;
+  }
+}
+template <typename V>
+void launch_ilu_apply(const IluView &v, const V *lval, const V *uval, const V *udiag, const V *s, V *e,
+                      V omega, bool add, bool clear, hipStream_t st) {
+  if (v.nblk == 0) return;
+  // staged when the factors fit beside the kernel's static LDS (about 23 KB)
+  constexpr size_t kStageMax = 128 * 1024;
+  const size_t stage = (size_t)v.max_entries * (sizeof(V) + sizeof(int16_t));
+  if (stage <= kStageMax) {
+    static bool attr = false;   // raise the dynamic LDS limit once per instance
+    if (!attr) {
+      hip_ok_or_clear(hipFuncSetAttribute((const void *)k_ilu_apply<V, true>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kStageMax));
+      attr = true;
+    }
+    k_ilu_apply<V, true><<<v.nblk, 64, stage, st>>>(v, lval, uval, udiag, s, e, omega, (int)add, (int)clear);
+  } else {
+    k_ilu_apply<V, false><<<v.nblk, 64, 0, st>>>(v, lval, uval, udiag, s, e, omega, (int)add, (int)clear);
+  }
+}
+template void launch_ilu_apply<double>(const IluView &, const double *, const double *, const double *,
+                                       const double *, double *, double, bool, bool, hipStream_t);
+template void launch_ilu_apply<float>(const IluView &, const float *, const float *, const float *,
+                                      const float *, float *, float, bool, bool, hipStream_t);
+
 // ------------------------------------------------------------------ coarsest solve GEMV
 // y = W x with W row-major: one wave per row streams the row (64 consecutive
 // doubles per load, four loads in flight), then a fixed butterfly

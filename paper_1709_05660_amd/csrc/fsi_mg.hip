@@ -2,6 +2,8 @@
 // V-cycle orchestration, FGMRES, and the C ABI declared in include/fsi_mg.h.
 #include "fsi_internal.h"
 
+#include <type_traits>
+
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -301,9 +303,14 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
   int64_t wmain = 0, wsolid = 0, wfull = 0;
   L.mmax = 0;
   L.sum_m = L.sum_m2 = L.sum_om = 0;
+  // fluid blocks with ILU(0) factors (fluid_ilu): no explicit inverse
+  const bool ilu = mg.opts.fluid_ilu != 0;
+  std::vector<int> ilu_patch;
   for (int k = 0; k < np; ++k) {
     const int64_t a = P.ptr[k], b = P.ptr[k + 1];
     const bool solid = split && L.h_kind[k] == 1;
+    const bool is_ilu = ilu && L.h_kind[k] == 0;
+    if (is_ilu) ilu_patch.push_back(k);
     pm[k] = (int)(b - a);
     pdof_off[k] = a;
     int o = 0;
@@ -318,7 +325,7 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
     // woff[k]: offset of the patch's owned rows in its class's storage
     int64_t &wcls = solid ? wsolid : wmain;
     woff[k] = wcls;
-    wcls += (int64_t)o * pm[k];
+    if (!is_ilu) wcls += (int64_t)o * pm[k];
     boff[k + 1] = boff[k] + (int64_t)pm[k] * pm[k];
     for (int i = 0; i < pm[k]; ++i) {
       row_patch.push_back(k);
@@ -337,7 +344,7 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
       }
     } else {
       full_off[k + 1] = full_off[k];
-      for (int r0 = 0; r0 < o; r0 += 64) {
+      for (int r0 = 0; r0 < o && !is_ilu; r0 += 64) {
         (solid ? task_patch_s : task_patch).push_back(k);
         (solid ? task_row0_s : task_row0).push_back(r0);
       }
@@ -345,7 +352,7 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
     L.mmax = std::max(L.mmax, pm[k]);
     L.sum_m += pm[k];
     L.sum_m2 += (int64_t)pm[k] * pm[k];
-    L.sum_om += (int64_t)o * pm[k];
+    if (!is_ilu) L.sum_om += (int64_t)o * pm[k];
   }
   woff[np] = wmain;
   L.total_owned = out_off[np];
@@ -444,6 +451,112 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
   // extraction map: one slot per CSR entry of every block row
   if (L.boff_total >= ((int64_t)1 << 31))
     throw Error(FSI_E_INVALID, "the blocks of one level exceed 2^31 entries");
+  if (!ilu_patch.empty()) {
+    // each ILU block's pattern (J's stored entries in the block, and the
+    // diagonal) as L and U rows of local columns, the L columns' row lists
+    // and a bit mask; the factors' positions in the dense blocks
+    std::vector<int> row0, lptr{0}, uptr{0}, cptr{0}, lpos, upos, dpos, flev, flev_off{0}, blev, blev_off{0};
+    std::vector<int16_t> lcol, ucol, crow, frow, brow;
+    std::vector<uint32_t> mask;
+    std::vector<int64_t> moff;
+    int maxe = 0, nrows = 0;
+    for (int k : ilu_patch) {
+      const int32_t *I = P.dof + P.ptr[k];
+      const int m = pm[k];
+      row0.push_back(nrows);
+      moff.push_back((int64_t)mask.size());
+      mask.resize(mask.size() + ((int64_t)m * m + 31) / 32, 0u);
+      uint32_t *mk = mask.data() + moff.back();
+      std::vector<std::vector<int16_t>> lcols(m);   // L's rows below each column
+      const int l0 = (int)lcol.size(), u0 = (int)ucol.size();
+      std::vector<int> row_cols, flevel(m, 0), blevel(m, 0);
+      for (int i = 0; i < m; ++i) {
+        row_cols.clear();
+        row_cols.push_back(i);
+        const int g = I[i];
+        for (int64_t q = J.rowptr[g]; q < J.rowptr[g + 1]; ++q) {
+          const int32_t *f = std::lower_bound(I, I + m, J.colind[q]);
+          if (f != I + m && *f == J.colind[q]) row_cols.push_back((int)(f - I));
+        }
+        std::sort(row_cols.begin(), row_cols.end());
+        row_cols.erase(std::unique(row_cols.begin(), row_cols.end()), row_cols.end());
+        for (int c : row_cols) {
+          const int64_t bit = (int64_t)i * m + c;
+          mk[bit >> 5] |= 1u << (bit & 31);
+          const int pos = (int)(L.h_boff[k] + (int64_t)i * m + c);
+          if (c < i) {
+            lcol.push_back((int16_t)c);
+            lpos.push_back(pos);
+            lcols[c].push_back((int16_t)i);
+            flevel[i] = std::max(flevel[i], flevel[c] + 1);
+          } else if (c > i) {
+            ucol.push_back((int16_t)c);
+            upos.push_back(pos);
+          } else {
+            dpos.push_back(pos);
+          }
+        }
+        lptr.push_back((int)lcol.size());
+        uptr.push_back((int)ucol.size());
+      }
+      // rows arrive in ascending order, so every column's list is sorted
+      for (int c = 0; c < m; ++c) {
+        crow.insert(crow.end(), lcols[c].begin(), lcols[c].end());
+        cptr.push_back((int)crow.size());
+      }
+      // levels: a row's L columns lie in earlier forward levels, its U
+      // columns in earlier backward levels
+      for (int i = m - 1; i >= 0; --i)
+        for (int q = uptr[nrows + i]; q < uptr[nrows + i + 1]; ++q)
+          blevel[i] = std::max(blevel[i], blevel[ucol[q]] + 1);
+      // the block's rows by level (its segment of frow/brow) and its level
+      // starts as indices into that array; a block's last level ends where
+      // the next block's first begins (a closing entry follows the last block)
+      auto order = [&](const std::vector<int> &lev, std::vector<int16_t> &rows, std::vector<int> &ptr,
+                       std::vector<int> &off) {
+        const int nlev = m ? *std::max_element(lev.begin(), lev.end()) + 1 : 0;
+        std::vector<int> cnt(nlev + 1, 0);
+        for (int i = 0; i < m; ++i) ++cnt[lev[i] + 1];
+        for (int t = 0; t < nlev; ++t) cnt[t + 1] += cnt[t];
+        std::vector<int16_t> byl(m);
+        std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+        for (int i = 0; i < m; ++i) byl[fill[lev[i]]++] = (int16_t)i;
+        rows.insert(rows.end(), byl.begin(), byl.end());
+        for (int t = 0; t < nlev; ++t) ptr.push_back(nrows + cnt[t]);
+        off.push_back((int)ptr.size());
+      };
+      order(flevel, frow, flev, flev_off);
+      order(blevel, brow, blev, blev_off);
+      nrows += m;
+      maxe = std::max(maxe, (int)(lcol.size() - l0 + ucol.size() - u0));
+    }
+    flev.push_back(nrows);
+    blev.push_back(nrows);
+    L.nilu = (int)ilu_patch.size();
+    L.ilu_rows = nrows;
+    L.ilu_nl = (int64_t)lcol.size();
+    L.ilu_nu = (int64_t)ucol.size();
+    L.ilu_max_entries = maxe;
+    L.d_ilu_patch = dupload(ilu_patch.data(), (int64_t)ilu_patch.size(), own, st);
+    L.d_ilu_row0 = dupload(row0.data(), (int64_t)row0.size(), own, st);
+    L.d_ilu_lptr = dupload(lptr.data(), (int64_t)lptr.size(), own, st);
+    L.d_ilu_uptr = dupload(uptr.data(), (int64_t)uptr.size(), own, st);
+    L.d_ilu_cptr = dupload(cptr.data(), (int64_t)cptr.size(), own, st);
+    L.d_ilu_lcol = dupload(lcol.data(), (int64_t)lcol.size(), own, st);
+    L.d_ilu_ucol = dupload(ucol.data(), (int64_t)ucol.size(), own, st);
+    L.d_ilu_crow = dupload(crow.data(), (int64_t)crow.size(), own, st);
+    L.d_ilu_frow = dupload(frow.data(), (int64_t)frow.size(), own, st);
+    L.d_ilu_brow = dupload(brow.data(), (int64_t)brow.size(), own, st);
+    L.d_ilu_flev = dupload(flev.data(), (int64_t)flev.size(), own, st);
+    L.d_ilu_blev = dupload(blev.data(), (int64_t)blev.size(), own, st);
+    L.d_ilu_flev_off = dupload(flev_off.data(), (int64_t)flev_off.size(), own, st);
+    L.d_ilu_blev_off = dupload(blev_off.data(), (int64_t)blev_off.size(), own, st);
+    L.d_ilu_lpos = dupload(lpos.data(), (int64_t)lpos.size(), own, st);
+    L.d_ilu_upos = dupload(upos.data(), (int64_t)upos.size(), own, st);
+    L.d_ilu_dpos = dupload(dpos.data(), (int64_t)dpos.size(), own, st);
+    L.d_ilu_mask = dupload(mask.data(), (int64_t)mask.size(), own, st);
+    L.d_ilu_moff = dupload(moff.data(), (int64_t)moff.size(), own, st);
+  }
   std::vector<int64_t> slot_off(row_patch.size() + 1, 0);
   for (size_t t = 0; t < row_patch.size(); ++t) {
     const int g = P.dof[pdof_off[row_patch[t]] + row_local[t]];
@@ -488,6 +601,60 @@ static RefineView refine_view(const Level &L) {
   v.unowned = L.d_unowned;
   v.nunowned = L.n_unowned;
   return v;
+}
+
+static IluView ilu_view(const Level &L) {
+  IluView v;
+  v.nblk = L.nilu;
+  v.patch = L.d_ilu_patch;
+  v.row0 = L.d_ilu_row0;
+  v.pm = L.d_pm;
+  v.dof = L.d_dof;
+  v.out_off = L.d_out_off;
+  v.own_local = L.d_own_local;
+  v.out_idx = L.d_out_idx;
+  v.pdof_off = L.d_pdof_off;
+  v.boff = L.d_boff;
+  v.lptr = L.d_ilu_lptr;
+  v.uptr = L.d_ilu_uptr;
+  v.cptr = L.d_ilu_cptr;
+  v.lcol = L.d_ilu_lcol;
+  v.ucol = L.d_ilu_ucol;
+  v.crow = L.d_ilu_crow;
+  v.frow = L.d_ilu_frow;
+  v.brow = L.d_ilu_brow;
+  v.flev = L.d_ilu_flev;
+  v.flev_off = L.d_ilu_flev_off;
+  v.blev = L.d_ilu_blev;
+  v.blev_off = L.d_ilu_blev_off;
+  v.mask = L.d_ilu_mask;
+  v.moff = L.d_ilu_moff;
+  v.unowned = L.d_unowned;
+  v.nunowned = L.n_unowned;
+  v.max_entries = L.ilu_max_entries;
+  return v;
+}
+
+// ILU(0) of the level's fluid blocks in the dense block scratch (after the
+// batched inversion, which skips them), then the factors compacted
+template <typename T>
+static void ilu_factor_level(MG &mg, Level &L, int l, T *blocks, hipStream_t st) {
+  if (!L.nilu) return;
+  int base = 0;
+  for (int q = 1; q < l; ++q) base += mg.lv[q].npatch;
+  launch_ilu_factor<T>(ilu_view(L), blocks, mg.status, base, st);
+  T *&lv = std::is_same<T, double>::value ? reinterpret_cast<T *&>(L.ilu_l64) : reinterpret_cast<T *&>(L.ilu_l32);
+  T *&uv = std::is_same<T, double>::value ? reinterpret_cast<T *&>(L.ilu_u64) : reinterpret_cast<T *&>(L.ilu_u32);
+  T *&dv = std::is_same<T, double>::value ? reinterpret_cast<T *&>(L.ilu_d64) : reinterpret_cast<T *&>(L.ilu_d32);
+  if (!lv) {
+    lv = dalloc<T>(std::max<int64_t>(L.ilu_nl, 1), mg.owned);
+    uv = dalloc<T>(std::max<int64_t>(L.ilu_nu, 1), mg.owned);
+    dv = dalloc<T>(std::max<int64_t>(L.ilu_rows, 1), mg.owned);
+  }
+  launch_ilu_gather<T, T>(blocks, L.d_ilu_lpos, L.ilu_nl, lv, st);
+  launch_ilu_gather<T, T>(blocks, L.d_ilu_upos, L.ilu_nu, uv, st);
+  launch_ilu_gather<T, T>(blocks, L.d_ilu_dpos, L.ilu_rows, dv, st);
+  hip_check(hipGetLastError(), "ilu launch");
 }
 
 RasView ras_view(const Level &L) {
@@ -677,7 +844,13 @@ void refactor(MG &mg, hipStream_t st) {
     hipEvent_t *ev = mg.prof_on ? prof_event_pair(mg.prof_gj_ev, mg.prof_gj_used) : nullptr;
     invert_blocks(mg, mg.gj_variant, st, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
     hip_check(hipGetLastError(), "gj launch");
-    for (int l = 1; l < mg.nlevels; ++l) pack_level(mg, mg.lv[l], st);
+    for (int l = 1; l < mg.nlevels; ++l) {
+      pack_level(mg, mg.lv[l], st);
+      if (mg.mixed)
+        ilu_factor_level(mg, mg.lv[l], l, reinterpret_cast<float *>(mg.blk_scratch) + mg.lv[l].blk_base, st);
+      else
+        ilu_factor_level(mg, mg.lv[l], l, mg.blk_scratch + mg.lv[l].blk_base, st);
+    }
   }
   hip_check(hipStreamWaitEvent(st, mg.ev_join, 0), "join wait");
   std::vector<int> hs(mg.npatch_all + 1, 0);
@@ -712,10 +885,17 @@ static hipEvent_t *prof_pair(MG &mg, Level &L) {
   }
   return &mg.prof_ev[mg.prof_used++].first;
 }
-static void ras64(MG &mg, Level &L, const double *s, double *e, bool add, hipStream_t st) {
+// one FP64 Schwarz application: the explicit inverses' owned rows, then the
+// ILU blocks (which clear the unowned dofs when no explicit block is left)
+static void ras64_omega(MG &mg, Level &L, const double *s, double *e, double omega, bool add, hipStream_t st) {
   hipEvent_t *ev = prof_pair(mg, L);
-  launch_ras_f64(ras_view(L), L.W64, s, e, mg.opts.omega, &L == &mg.lv.back(), add, st,
-                 ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
+  launch_ras_f64(ras_view(L), L.W64, s, e, omega, &L == &mg.lv.back(), add, st, ev ? ev[0] : nullptr,
+                 ev ? ev[1] : nullptr);
+  if (L.nilu)
+    launch_ilu_apply<double>(ilu_view(L), L.ilu_l64, L.ilu_u64, L.ilu_d64, s, e, omega, add, L.ntask == 0, st);
+}
+static void ras64(MG &mg, Level &L, const double *s, double *e, bool add, hipStream_t st) {
+  ras64_omega(mg, L, s, e, mg.opts.omega, add, st);
 }
 static void ras32(MG &mg, Level &L, const float *s, float *e, bool add, hipStream_t st,
                   double omega_d = -1.0) {
@@ -732,6 +912,8 @@ static void ras32(MG &mg, Level &L, const float *s, float *e, bool add, hipStrea
   if (L.nref)
     launch_ras_refine(refine_view(L), L.Wfull32, L.Wfull16, s, e, omega, add, mg.opts.refine_sweeps, L.yref0,
                       L.yref1, st);
+  if (L.nilu)
+    launch_ilu_apply<float>(ilu_view(L), L.ilu_l32, L.ilu_u32, L.ilu_d32, s, e, omega, add, L.ntask == 0, st);
 }
 
 // One V-cycle on level l for e = M_l^{-1} r (r and e distinct; the finest
@@ -878,6 +1060,12 @@ static void batch_ras(const std::vector<BatchLevel<double>> &a, const std::vecto
     it.push_back(RasItem<double, double>{ras_view(L), L.W64, 0, nullptr, s[i], e[i]});
   }
   launch_ras_batch_f64(it.data(), (int)it.size(), a[0].mg->opts.omega, add, st);
+  for (size_t i = 0; i < a.size(); ++i) {   // ILU blocks: their own launches
+    const Level &L = a[i].mg->lv[a[i].l];
+    if (L.nilu)
+      launch_ilu_apply<double>(ilu_view(L), L.ilu_l64, L.ilu_u64, L.ilu_d64, s[i], e[i], a[0].mg->opts.omega,
+                               add, L.ntask == 0, st);
+  }
 }
 static void batch_ras(const std::vector<BatchLevel<float>> &a, const std::vector<const float *> &s,
                       const std::vector<float *> &e, bool add, hipStream_t st) {
@@ -902,6 +1090,9 @@ static void batch_ras(const std::vector<BatchLevel<float>> &a, const std::vector
     if (L.nref)
       launch_ras_refine(refine_view(L), L.Wfull32, L.Wfull16, s[i], e[i], omega, add, mg.opts.refine_sweeps,
                         L.yref0, L.yref1, st);
+    if (L.nilu)
+      launch_ilu_apply<float>(ilu_view(L), L.ilu_l32, L.ilu_u32, L.ilu_d32, s[i], e[i], omega, add, L.ntask == 0,
+                              st);
   }
 }
 
@@ -1052,6 +1243,7 @@ static void validate_opts(const fsi_mg_opts *opts) {
                 "solid_precision must be -1, equal to precision, or FSI_PREC_MIXED_FP32 in a mixed hierarchy");
   if (opts->refine_sweeps < 0 || opts->refine_sweeps > 4 || (opts->refine_sweeps > 0 && !mixed))
     throw Error(FSI_E_INVALID, "refine_sweeps must be 0..4, and 0 for an FP64 hierarchy");
+  if (opts->fluid_ilu != 0 && opts->fluid_ilu != 1) throw Error(FSI_E_INVALID, "fluid_ilu must be 0 or 1");
 }
 
 static void validate_hierarchy(const fsi_level *levels, int nlevels, const std::vector<int64_t> &n) {
@@ -1165,7 +1357,9 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
       for (int k = 0; k < L.npatch; ++k) {
         all_boff.push_back(base + L.h_boff[k]);
         all_poff.push_back(pbase + L.h_ptr[k]);
-        all_pm.push_back((int)(L.h_ptr[k + 1] - L.h_ptr[k]));
+        // an ILU block is factored apart: no Gauss-Jordan work (size 0)
+        const bool is_ilu = mg->opts.fluid_ilu && L.h_kind[k] == 0;
+        all_pm.push_back(is_ilu ? 0 : (int)(L.h_ptr[k + 1] - L.h_ptr[k]));
       }
       base += L.boff_total;
       pbase += L.sum_m;
@@ -1986,10 +2180,9 @@ fsi_status fsi_mg_apply(struct fsi_mg *h, int32_t level, int32_t op, const doubl
         break;
       case 4:
         if (level == 0) throw Error(FSI_E_INVALID, "no patches on level 0");
-        if (!L.W64) throw Error(FSI_E_INVALID, "op 4 needs the FP64 precision");
+        if (mg->mixed) throw Error(FSI_E_INVALID, "op 4 needs the FP64 precision");
         launch_fill_f64(y_dev, L.n, 0.0, st);
-        launch_ras_f64(ras_view(L), L.W64, x_dev, y_dev, 1.0, level == mg->nlevels - 1, true,
-                       st);
+        ras64_omega(*mg, L, x_dev, y_dev, 1.0, true, st);
         break;
       case 5:
         if (level != 0) throw Error(FSI_E_INVALID, "direct solve only on level 0");
@@ -1999,7 +2192,7 @@ fsi_status fsi_mg_apply(struct fsi_mg *h, int32_t level, int32_t op, const doubl
         if (level == 0) throw Error(FSI_E_INVALID, "no patches on level 0");
         if (!mg->mixed) {
           launch_fill_f64(y_dev, L.n, 0.0, st);
-          launch_ras_f64(ras_view(L), L.W64, x_dev, y_dev, 1.0, false, true, st);
+          ras64_omega(*mg, L, x_dev, y_dev, 1.0, true, st);
         } else {
           launch_cast_d2f(x_dev, L.s32, L.n, st);
           ras32(*mg, L, L.s32, L.e32, false, st, 1.0);
@@ -2089,7 +2282,7 @@ fsi_status fsi_stream_read(const double *x_dev, int64_t n, double *out_dev, void
 
 int32_t fsi_stream_read_blocks(void) { return kStreamReadBlocks; }
 
-fsi_status fsi_mg_level_info(struct fsi_mg *h, int32_t level, int64_t out[6]) {
+fsi_status fsi_mg_level_info(struct fsi_mg *h, int32_t level, int64_t out[8]) {
   FSI_GUARD({
     MG *mg = reinterpret_cast<MG *>(h);
     if (!mg || !out || level < 0 || level >= mg->nlevels) throw Error(FSI_E_INVALID, "bad argument");
@@ -2100,6 +2293,8 @@ fsi_status fsi_mg_level_info(struct fsi_mg *h, int32_t level, int64_t out[6]) {
     out[3] = L.sum_m;
     out[4] = L.sum_m2;
     out[5] = L.sum_om;
+    out[6] = L.nilu;
+    out[7] = L.ilu_nl + L.ilu_nu + L.ilu_rows;
     return FSI_OK;
   })
 }

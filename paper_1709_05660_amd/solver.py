@@ -153,8 +153,9 @@ class Problem:
 
 
 def mg_opts(nu_pre=2, nu_post=2, omega=0.7, precision="fp64", solid_precision=None,
-            refine_sweeps=0, use_graph=False, tuning_db=None):
+            refine_sweeps=0, use_graph=False, tuning_db=None, fluid_ilu=False):
     o = L.MgOpts()
+    o.fluid_ilu = 1 if fluid_ilu else 0
     o.nu_pre, o.nu_post, o.omega = nu_pre, nu_post, omega
     o.precision = L.PREC[precision]
     o.solid_precision = -1 if solid_precision is None else L.PREC[solid_precision]
@@ -192,9 +193,9 @@ class MG:
         self.device = torch.device("cuda")
 
     def level_info(self, level):
-        out = (C.c_int64 * 6)()
+        out = (C.c_int64 * 8)()
         L.check(L.lib().fsi_mg_level_info(self.h, level, out))
-        return dict(zip(["n", "nnz", "npatch", "sum_m", "sum_m2", "sum_om"], list(out)))
+        return dict(zip(["n", "nnz", "npatch", "sum_m", "sum_m2", "sum_om", "nilu", "ilu_entries"], list(out)))
 
     def vcycle(self, r, z=None):
         import torch

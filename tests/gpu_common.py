@@ -35,16 +35,18 @@ def product_problem(name, **kw):
 
 
 @functools.lru_cache(maxsize=None)
-def oracle_hierarchy(name):
-    """The checker's own, independently assembled hierarchy."""
-    s = config(name)
+def oracle_hierarchy(name, fluid_ilu=False):
+    """The checker's own, independently assembled hierarchy (with ILU(0)
+    local solves on the fluid blocks when fluid_ilu)."""
+    s = config(name).with_(fluid_ilu=fluid_ilu)
     return oprob.build(s, fourier_coefficients(s.dim, s.seed))
 
 
 @functools.lru_cache(maxsize=None)
-def oracle_on_product(name):
-    """The checker's algorithm (LU local solves, V-cycle, FGMRES) run on the
-    product builder's matrices and patches."""
+def oracle_on_product(name, fluid_ilu=False):
+    """The checker's algorithm (LU local solves, or ILU(0) on the fluid
+    blocks, V-cycle, FGMRES) run on the product builder's matrices and
+    patches."""
     p = product_problem(name)
     levels = []
     for l in range(p.nlevels):
@@ -54,7 +56,7 @@ def oracle_on_product(name):
             lv.R = csr_of(p, l, "R")
             lv.ptr, lv.dof, lv.owned, lv.kind = p.patches(l)
         levels.append(lv)
-    osolver.setup_factors(levels)
-    s = config(name)
+    osolver.setup_factors(levels, fluid_ilu=fluid_ilu)
+    s = config(name).with_(fluid_ilu=fluid_ilu)
     h = oprob.Hierarchy(s, None, None, levels, p.b.copy(), p.y.copy(), None)
     return h

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
     for name in sorted(declared):
         assert hasattr(L, name), name
     assert set(_lib.EXPORTS) == declared
-    assert L.fsi_abi_version() == 3
+    assert L.fsi_abi_version() == 4
     assert L.fsi_status_string(-3) == b"singular block"
 
 
