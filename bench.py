@@ -212,7 +212,8 @@ def time_step_leg(args):
     "Discretization of the operator formulation"): the step (refactor +
     solve) with exact local solves on every block and with ILU(0) on the
     fluid blocks (section "Richardson-Schwarz smoother"), FP64 to 1e-10 and
-    the mixed form to 1e-8; factor bytes of the finest level."""
+    the mixed form to 1e-8; factor bytes of the finest level; the device
+    Galerkin product of the coarse operators (a new Jacobian's setup)."""
     import torch
 
     from paper_1709_05660_amd import MG, Problem
@@ -242,6 +243,17 @@ def time_step_leg(args):
             ev1.record(stream)
             torch.cuda.synchronize()
             ms = ev0.elapsed_time(ev1) / args.steps_3d
+            if prec == "fp64" and not ilu:
+                # a new Jacobian's coarse operators on the device (R J P per level)
+                mg.galerkin()
+                torch.cuda.synchronize()
+                g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                g0.record(stream)
+                for _ in range(5):
+                    mg.galerkin()
+                g1.record(stream)
+                torch.cuda.synchronize()
+                res["device_galerkin_ms"] = round(g0.elapsed_time(g1) / 5, 3)
             li = mg.level_info(p.nlevels - 1)
             wb = {"fp64": 8, "fp32": 4}.get(prec, 2)
             vb = 8 if prec == "fp64" else 4

@@ -258,6 +258,26 @@ fsi_status fsi_mg_refactor(struct fsi_mg *mg, void *hip_stream);
  * owned by the handle; callers may overwrite them before fsi_mg_refactor. */
 fsi_status fsi_mg_jvalues(struct fsi_mg *mg, int32_t level, double **val_dev);
 
+/* Copies nnz(J_level) FP64 values (the input CSR order) from the device
+ * array val_dev into the handle's operator of `level`, on hip_stream (the
+ * caller keeps val_dev alive until the stream passes the copy).  Errors:
+ * FSI_E_INVALID (bad argument), FSI_E_DEVICE. */
+fsi_status fsi_mg_set_jvalues(struct fsi_mg *mg, int32_t level, const double *val_dev, void *hip_stream);
+
+/* Section "Geometric Multigrid preconditioner" (Galerkin coarse operators,
+ * section "Monolithic Newton-Krylov solver with Multigrid-Richardson-Schwarz
+ * preconditioner": a new Jacobian every Newton step): recomputes every coarse
+ * operator J_{l-1} = R_l J_l P_l on the device from the current finest values
+ * (finest level first), on the coarse operators' given patterns, with a unit
+ * diagonal on their Dirichlet rows (the input flags, else the rows whose only
+ * entry is a unit diagonal).  A new Newton step then needs only the finest
+ * values: fsi_mg_set_jvalues, fsi_mg_galerkin, fsi_mg_refactor.  The first
+ * call builds the intermediate pattern of J_l P_l on the host (a one-time
+ * read-back of the patterns); every call is stream-ordered on hip_stream.
+ * Errors: FSI_E_INVALID (R J P has an entry outside a given coarse pattern, or
+ * a Dirichlet row holds no diagonal), FSI_E_OOM, FSI_E_DEVICE. */
+fsi_status fsi_mg_galerkin(struct fsi_mg *mg, void *hip_stream);
+
 /* Measurement hook: HIP events recorded at the own start and end of the
  * finest-level Schwarz kernel and of the batched block inversion, on the
  * streams they run on.  enable = 1 starts (V-cycles and Arnoldi steps then

@@ -86,7 +86,7 @@ class ServerOpts(C.Structure):
 # every symbol the headers declare (checked by the CPU tests)
 EXPORTS = [
     "fsi_abi_version", "fsi_status_string", "fsi_last_error", "fsi_mg_setup", "fsi_mg_vcycle",
-    "fsi_mg_vcycle_batch",
+    "fsi_mg_vcycle_batch", "fsi_mg_set_jvalues", "fsi_mg_galerkin",
     "fsi_fgmres_solve", "fsi_fgmres_solve_noalloc", "fsi_mg_apply", "fsi_mg_export_patches", "fsi_mg_level_info",
     "fsi_mg_refactor", "fsi_mg_jvalues", "fsi_mg_profile", "fsi_mg_autotune",
     "fsi_mg_destroy", "fsi_server_create", "fsi_serve_submit", "fsi_serve_poll",
@@ -117,6 +117,8 @@ def lib():
         "fsi_mg_setup": (C.c_int32, [C.POINTER(LevelC), C.c_int32, C.POINTER(MgOpts), P, C.POINTER(P)]),
         "fsi_mg_vcycle": (C.c_int32, [P, P, P, P]),
         "fsi_mg_vcycle_batch": (C.c_int32, [C.POINTER(P), C.c_int32, C.POINTER(P), C.POINTER(P), P]),
+        "fsi_mg_set_jvalues": (C.c_int32, [P, C.c_int32, P, P]),
+        "fsi_mg_galerkin": (C.c_int32, [P, P]),
         "fsi_fgmres_solve": (C.c_int32, [P, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo), P]),
         "fsi_fgmres_solve_noalloc": (C.c_int32, [P, P, P, C.POINTER(KrylovOpts), C.POINTER(SolveInfo), P]),
         "fsi_mg_apply": (C.c_int32, [P, C.c_int32, C.c_int32, P, P, P, P]),

@@ -89,6 +89,15 @@ struct Level {
   int64_t *d_ilu_moff = nullptr;
   double *ilu_l64 = nullptr, *ilu_u64 = nullptr, *ilu_d64 = nullptr;
   float *ilu_l32 = nullptr, *ilu_u32 = nullptr, *ilu_d32 = nullptr;
+  // device Galerkin product (fsi_mg_galerkin), on levels >= 1: T = J P on
+  // its pattern (prepared at the first call), and the positions of the next
+  // coarser level's Dirichlet diagonals; the Dirichlet rows of this level
+  // when the input flags them
+  int *d_t_rp = nullptr, *d_t_col = nullptr, *d_cdir_pos = nullptr;
+  double *d_t_val = nullptr;
+  int n_cdir = 0;
+  std::vector<int> h_dir;
+  bool dir_known = false;
   // coarsest level: row-major inverse
   double *C0 = nullptr;
   // work vectors
@@ -172,6 +181,7 @@ struct MG {
   bool prof_on = false;
   size_t prof_used = 0, prof_gj_used = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev, prof_gj_ev;   // Schwarz (finest), batched inversion
+  bool galerkin_ready = false;   // the device Galerkin product's patterns are prepared
 };
 
 extern thread_local std::string g_last_error;

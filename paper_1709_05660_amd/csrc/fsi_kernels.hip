@@ -1007,6 +1007,49 @@ template void launch_ilu_apply<double>(const IluView &, const double *, const do
 template void launch_ilu_apply<float>(const IluView &, const float *, const float *, const float *,
                                       const float *, float *, float, bool, bool, hipStream_t);
 
+// ------------------------------------------------------------------ Galerkin product
+// one wave per row of C, lanes over the row's entries
+__global__ __launch_bounds__(256) void k_spgemm_rowdot(int nrows, const int *__restrict__ arp,
+                                                       const int *__restrict__ acol, const double *__restrict__ aval,
+                                                       const int *__restrict__ brp, const int *__restrict__ bcol,
+                                                       const double *__restrict__ bval, const int *__restrict__ crp,
+                                                       const int *__restrict__ ccol, double *__restrict__ cval) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= nrows) return;
+  const int a0 = arp[row], a1 = arp[row + 1];
+  for (int q = crp[row] + lane; q < crp[row + 1]; q += 64) {
+    const int j = ccol[q];
+    double acc = 0.0;
+    for (int p = a0; p < a1; ++p) {
+      const int k = acol[p];
+      int lo = brp[k], hi = brp[k + 1];
+      const int end = hi;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (bcol[mid] < j)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (lo < end && bcol[lo] == j) acc += aval[p] * bval[lo];
+    }
+    cval[q] = acc;
+  }
+}
+void launch_spgemm_rowdot(const CsrView<double> &A, const CsrView<double> &B, int nrows_c, const int *c_rowptr,
+                          const int *c_col, double *c_val, hipStream_t st) {
+  if (nrows_c > 0)
+    k_spgemm_rowdot<<<cdiv(nrows_c, 4), 256, 0, st>>>(nrows_c, A.rowptr, A.col, A.val, B.rowptr, B.col, B.val,
+                                                       c_rowptr, c_col, c_val);
+}
+__global__ void k_add_at(double *val, const int *pos, int n, double v) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t < n) val[pos[t]] += v;
+}
+void launch_add_at(double *val, const int *pos, int n, double v, hipStream_t st) {
+  if (n > 0) k_add_at<<<cdiv(n, 256), 256, 0, st>>>(val, pos, n, v);
+}
+
 // ------------------------------------------------------------------ coarsest solve GEMV
 // y = W x with W row-major: one wave per row streams the row (64 consecutive
 // doubles per load, four loads in flight), then a fixed butterfly

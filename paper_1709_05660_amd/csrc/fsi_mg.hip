@@ -1219,6 +1219,93 @@ void run_vcycle(MG &mg, const double *r, double *z, hipStream_t st) {
   }
 }
 
+// ------------------------------------------------------------------ Galerkin product on the device
+// Section "Geometric Multigrid preconditioner": the coarse operators are the
+// Galerkin products J_{l-1} = R_l J_l P_l.  The first call reads the
+// patterns back and builds T_l = J_l P_l's pattern on the host, checks that
+// R_l T_l's pattern lies in the given J_{l-1}'s, and finds the positions of
+// J_{l-1}'s Dirichlet diagonals (the input flags, else the rows whose only
+// entry is a unit diagonal); then every call is two products per level on
+// the device, finest first, and a unit added on the Dirichlet diagonals
+// (whose rows and columns R and P leave empty), as the coarse operators were
+// formed.
+template <typename T>
+static std::vector<T> d2h(const T *d, int64_t n) {
+  std::vector<T> h(std::max<int64_t>(n, 0));
+  if (n > 0) hip_check(hipMemcpy(h.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost), "D2H");
+  return h;
+}
+static void galerkin_prepare(MG &mg, hipStream_t st) {
+  hip_check(hipStreamSynchronize(st), "galerkin");
+  for (int l = mg.nlevels - 1; l >= 1; --l) {
+    Level &L = mg.lv[l], &C = mg.lv[l - 1];
+    const auto jrp = d2h(L.J.rowptr, L.n + 1), jc = d2h(L.J.col, L.J.nnz);
+    const auto prp = d2h(L.P.rowptr, L.P.n + 1), pc = d2h(L.P.col, L.P.nnz);
+    const auto rrp = d2h(L.R.rowptr, L.R.n + 1), rc = d2h(L.R.col, L.R.nnz);
+    const auto crp = d2h(C.J.rowptr, C.n + 1), cc = d2h(C.J.col, C.J.nnz);
+    // T = J P: union of P's rows over each J row
+    std::vector<int> trp(L.n + 1, 0), tcol, mark(C.n, -1), list;
+    for (int i = 0; i < L.n; ++i) {
+      list.clear();
+      for (int p = jrp[i]; p < jrp[i + 1]; ++p)
+        for (int q = prp[jc[p]]; q < prp[jc[p] + 1]; ++q)
+          if (mark[pc[q]] != i) {
+            mark[pc[q]] = i;
+            list.push_back(pc[q]);
+          }
+      std::sort(list.begin(), list.end());
+      tcol.insert(tcol.end(), list.begin(), list.end());
+      trp[i + 1] = (int)tcol.size();
+    }
+    // R T must land on the given coarse pattern
+    std::fill(mark.begin(), mark.end(), -1);
+    for (int r = 0; r < C.n; ++r) {
+      for (int p = crp[r]; p < crp[r + 1]; ++p) mark[cc[p]] = r;
+      for (int p = rrp[r]; p < rrp[r + 1]; ++p)
+        for (int q = trp[rc[p]]; q < trp[rc[p] + 1]; ++q)
+          if (mark[tcol[q]] != r) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "level %d: R J P has an entry (%d, %d) outside the given coarse operator",
+                     l - 1, r, tcol[q]);
+            throw Error(FSI_E_INVALID, buf);
+          }
+    }
+    // the coarse level's Dirichlet diagonals
+    std::vector<int> dir = C.h_dir;
+    if (!C.dir_known) {
+      const auto cv = d2h(C.J.val, C.J.nnz);
+      for (int r = 0; r < C.n; ++r)
+        if (crp[r + 1] - crp[r] == 1 && cc[crp[r]] == r && cv[crp[r]] == 1.0) dir.push_back(r);
+    }
+    std::vector<int> pos;
+    for (int r : dir) {
+      const int *f = std::lower_bound(cc.data() + crp[r], cc.data() + crp[r + 1], r);
+      if (f == cc.data() + crp[r + 1] || *f != r)
+        throw Error(FSI_E_INVALID, "a Dirichlet row of a coarse operator holds no diagonal");
+      pos.push_back((int)(f - cc.data()));
+    }
+    L.d_t_rp = dupload(trp.data(), (int64_t)trp.size(), mg.owned, st);
+    L.d_t_col = dupload(tcol.data(), (int64_t)tcol.size(), mg.owned, st);
+    L.d_t_val = dalloc<double>(std::max<int64_t>((int64_t)tcol.size(), 1), mg.owned);
+    L.d_cdir_pos = dupload(pos.data(), (int64_t)pos.size(), mg.owned, st);
+    L.n_cdir = (int)pos.size();
+  }
+  stage_drain();
+  mg.galerkin_ready = true;
+}
+
+void galerkin(MG &mg, hipStream_t st) {
+  if (!mg.galerkin_ready) galerkin_prepare(mg, st);
+  for (int l = mg.nlevels - 1; l >= 1; --l) {
+    Level &L = mg.lv[l], &C = mg.lv[l - 1];
+    launch_spgemm_rowdot(L.J.v64(), L.P.v64(), L.n, L.d_t_rp, L.d_t_col, L.d_t_val, st);
+    const CsrView<double> T{L.n, C.n, 0, L.d_t_rp, L.d_t_col, L.d_t_val};
+    launch_spgemm_rowdot(L.R.v64(), T, C.n, C.J.rowptr, C.J.col, C.J.val, st);
+    launch_add_at(C.J.val, L.d_cdir_pos, L.n_cdir, 1.0, st);
+  }
+  hip_check(hipGetLastError(), "galerkin launch");
+}
+
 // ------------------------------------------------------------------ setup
 void alloc_level_vectors(MG &mg, Level &L) {
   L.r = dalloc<double>(L.n, mg.owned);
@@ -1344,6 +1431,11 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
         build_patch_layout(L, levels[l].patches, levels[l].J, *mg, st);
       }
       alloc_level_vectors(*mg, L);
+      if (levels[l].dirichlet) {
+        L.dir_known = true;
+        for (int64_t i = 0; i < n[l]; ++i)
+          if (levels[l].dirichlet[i]) L.h_dir.push_back((int)i);
+      }
     }
     // all levels' blocks in one scratch; one offset/size table for the batched inversion
     std::vector<int64_t> all_boff, all_poff;
@@ -2233,6 +2325,27 @@ fsi_status fsi_mg_jvalues(struct fsi_mg *h, int32_t level, double **val_dev) {
     MG *mg = reinterpret_cast<MG *>(h);
     if (!mg || !val_dev || level < 0 || level >= mg->nlevels) throw Error(FSI_E_INVALID, "bad argument");
     *val_dev = mg->lv[level].J.val;
+    return FSI_OK;
+  })
+}
+
+fsi_status fsi_mg_set_jvalues(struct fsi_mg *h, int32_t level, const double *val_dev, void *hip_stream) {
+  FSI_GUARD({
+    MG *mg = reinterpret_cast<MG *>(h);
+    if (!mg || !val_dev || level < 0 || level >= mg->nlevels) throw Error(FSI_E_INVALID, "bad argument");
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
+    Level &L = mg->lv[level];
+    hip_check(hipMemcpyAsync(L.J.val, val_dev, sizeof(double) * L.J.nnz, hipMemcpyDeviceToDevice, st),
+              "D2D values");
+    return FSI_OK;
+  })
+}
+
+fsi_status fsi_mg_galerkin(struct fsi_mg *h, void *hip_stream) {
+  FSI_GUARD({
+    MG *mg = reinterpret_cast<MG *>(h);
+    if (!mg) throw Error(FSI_E_INVALID, "null handle");
+    galerkin(*mg, hip_stream ? (hipStream_t)hip_stream : mg->own_stream);
     return FSI_OK;
   })
 }

@@ -262,6 +262,15 @@ class MG:
         """Re-run extraction, block inversion and coarse inversion on the device."""
         L.check(L.lib().fsi_mg_refactor(self.h, _stream()), "refactor")
 
+    def set_jvalues(self, level, values):
+        """Copy a device FP64 tensor of nnz(J_level) values into the operator."""
+        nnz = self.level_info(level)["nnz"]
+        L.check(L.lib().fsi_mg_set_jvalues(self.h, level, _vec(values, nnz, "values"), _stream()), "set_jvalues")
+
+    def galerkin(self):
+        """Recompute the coarse operators R J P on the device from the finest values."""
+        L.check(L.lib().fsi_mg_galerkin(self.h, _stream()), "galerkin")
+
     def autotune(self, db_path=None):
         """Pick SpMV lanes-per-row and the block-inversion panel width by timing;
         returns the number of new measurements (0 when db_path had them all)."""
