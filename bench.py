@@ -213,7 +213,8 @@ def time_step_leg(args):
     solve) with exact local solves on every block and with ILU(0) on the
     fluid blocks (section "Richardson-Schwarz smoother"), FP64 to 1e-10 and
     the mixed form to 1e-8; factor bytes of the finest level; the device
-    Galerkin product of the coarse operators (a new Jacobian's setup)."""
+    Galerkin product of the coarse operators (a new Jacobian's setup), the
+    device assembly of the residual and Jacobian, and Newton on the device."""
     import torch
 
     from paper_1709_05660_amd import MG, Problem
@@ -244,6 +245,29 @@ def time_step_leg(args):
             torch.cuda.synchronize()
             ms = ev0.elapsed_time(ev1) / args.steps_3d
             if prec == "fp64" and not ilu:
+                # the Newton step on the device: the element-parallel assembly of
+                # the residual and exact Jacobian, then Newton to |e| <= 1e-8 |y|
+                from paper_1709_05660_amd import Assembly
+                asm = Assembly(p)
+                y = torch.as_tensor(p.y).to("cuda")
+                asm.run(y)
+                torch.cuda.synchronize()
+                a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a0.record(stream)
+                for _ in range(5):
+                    asm.run(y)
+                a1.record(stream)
+                torch.cuda.synchronize()
+                res["device_assembly_ms"] = round(a0.elapsed_time(a1) / 5, 3)
+                t0 = time.perf_counter()
+                ninfo = asm.newton(mg, y, max_newton=12, tol=1e-8, rtol=1e-10)
+                torch.cuda.synchronize()
+                res["newton_on_device"] = {"ms": round((time.perf_counter() - t0) * 1e3, 2),
+                                           "steps": ninfo["steps"], "converged": bool(ninfo["converged"]),
+                                           "krylov_iters": ninfo["krylov_iters"],
+                                           "residual_first_last": [float(f"{ninfo['res0']:.4g}"),
+                                                                   float(f"{ninfo['res_last']:.4g}")]}
+                asm.close()
                 # a new Jacobian's coarse operators on the device (R J P per level)
                 mg.galerkin()
                 torch.cuda.synchronize()

@@ -1,0 +1,75 @@
+/* Device assembly and the Newton loop on the GPU (gfx950).
+ *
+ * Section "Monolithic Newton-Krylov solver with Multigrid-Richardson-Schwarz
+ * preconditioner": every Newton step assembles the residual and the exact
+ * Jacobian of the monolithic ALE system at the current iterate and solves
+ * J e = -r with the multigrid-preconditioned Krylov method; the iteration
+ * stops when |y^k - y^{k-1}| < tol |y^k|.  The residual is the one of section
+ * "Discretization of the operator formulation" (steady, or one Crank-Nicolson
+ * step), its Jacobian by forward-mode differentiation, element by element.
+ *
+ * The assembler takes the finest level's element data of include/fsi_problem.h
+ * (any producer of that layout) and the finest Jacobian's CSR pattern; the
+ * Newton loop drives an fsi_mg handle built for that pattern (its coarse
+ * operators recomputed on the device by fsi_mg_galerkin at every step). */
+#ifndef FSI_ASSEMBLY_H
+#define FSI_ASSEMBLY_H
+
+#include <stdint.h>
+
+#include "fsi_mg.h"
+#include "fsi_problem.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+struct fsi_assembly;
+
+/* Uploads the element data and the pattern (host arrays, copied) on the
+ * current HIP device.  J: the finest Jacobian's CSR (only rowptr, colind
+ * and the sizes are read), holding every coupled entry of the element
+ * residuals and the unit diagonal of every Dirichlet row.  Errors:
+ * FSI_E_INVALID (null or inconsistent sizes, dim not 2 or 3), FSI_E_OOM,
+ * FSI_E_DEVICE. */
+fsi_status fsi_assembly_create(const fsi_element_data *ed, const fsi_csr *J, void *hip_stream,
+                               struct fsi_assembly **out);
+
+/* r = R(y) (ndof doubles) and the values of J = dR/dy in the pattern's order
+ * (nnz doubles), all device arrays, stream-ordered on hip_stream.  Dirichlet
+ * rows: r_i = y_i - g_i and a unit diagonal.  One launch per element colour;
+ * each thread differentiates its element's residual along one local dof, so
+ * every entry is written once (no atomics, the same result every run).
+ * Errors: FSI_E_INVALID (null), FSI_E_DEVICE. */
+fsi_status fsi_assembly_run(struct fsi_assembly *a, const double *y_dev, double *r_dev, double *jval_dev,
+                            void *hip_stream);
+
+typedef struct {
+  int32_t max_newton;      /* Newton steps at most */
+  double tol;              /* stop when |e| <= tol |y| (the paper: 1e-8) */
+} fsi_newton_opts;
+
+typedef struct {
+  int32_t steps;           /* Newton steps taken */
+  int32_t converged;       /* 1 when |e| <= tol |y| */
+  int32_t krylov_iters;    /* Krylov iterations over all steps */
+  double last_update;      /* |e| / |y| of the last step */
+  double res0, res_last;   /* |r| at the start and before the last step */
+} fsi_newton_info;
+
+/* Newton's method for R(y) = 0 on the device, y_dev updated in place: per
+ * step the device assembly at y, b = -r, the finest values into mg
+ * (fsi_mg_set_jvalues), fsi_mg_galerkin, fsi_mg_refactor, the Krylov solve
+ * of J e = b with kopts (x0 = 0), y += e.  The host reads norms only.  mg
+ * must have been set up for the assembly's pattern.  Errors: those of the
+ * calls it makes; FSI_NOT_CONVERGED when max_newton steps end above tol. */
+fsi_status fsi_newton_solve(struct fsi_assembly *a, struct fsi_mg *mg, double *y_dev,
+                            const fsi_newton_opts *nopts, const fsi_krylov_opts *kopts,
+                            fsi_newton_info *info, void *hip_stream);
+
+fsi_status fsi_assembly_destroy(struct fsi_assembly *a);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSI_ASSEMBLY_H */

@@ -71,6 +71,31 @@ fsi_status fsi_problem_dirichlet(const struct fsi_problem *p, int32_t level, con
 /* residual of the finest level at state y (for tests): r (n doubles); for a
  * transient problem the state at t_n is the seeded one */
 fsi_status fsi_problem_residual(const struct fsi_problem *p, const double *y, double *r);
+/* The finest level's element data, for an assembler of the same residual
+ * elsewhere (the device assembly of include/fsi_assembly.h); arrays owned by
+ * the problem, valid until fsi_problem_destroy.  Local dofs of an element:
+ * [d_c(a)] component-major, [u_c(a)], [p_j] (nl = 2 dim na + dim + 1); local
+ * residual rows in the same order: [momentum_c(a)], [mesh motion (fluid) or
+ * kinematics (solid)_c(a)], [continuity / incompressibility_j]. */
+typedef struct {
+  int32_t dim, ne, nl, na, np, nq, ncolor;
+  int64_t ndof;
+  const int32_t *l2g;         /* ne * nl: global dof of each local dof */
+  const int32_t *tgt;         /* ne * nl: global row of each local residual row, -1 when dropped
+                                 (mesh motion at an interface node of a fluid element) */
+  const uint8_t *solid;       /* ne: 1 for a solid element */
+  const int32_t *color_ptr;   /* ncolor + 1 offsets into color_elems */
+  const int32_t *color_elems; /* ne element ids by colour; two elements of a colour share no node */
+  const double *N, *dN, *psi, *w; /* quadrature: N[q na + a], dN[(q na + a) dim + k] (physical
+                                     gradients on the structured mesh), psi[q np + j], w[q] */
+  double vol;                 /* element volume (mesh-motion stiffness 1 / vol) */
+  const uint8_t *dirichlet;   /* ndof flags */
+  const double *dval;         /* ndof Dirichlet values */
+  const double *y_prev;       /* ndof: the state at t_n of a time step, or NULL (steady) */
+  double mu, rho, mu_s, dt, rho_s;
+} fsi_element_data;
+fsi_status fsi_problem_element_data(const struct fsi_problem *p, fsi_element_data *out);
+
 fsi_status fsi_problem_destroy(struct fsi_problem *p);
 /* thread-local message of the last failed fsi_problem_build of the calling thread */
 const char *fsi_problem_last_error(void);

@@ -83,6 +83,30 @@ class ServerOpts(C.Structure):
                 ("batch_vcycles", C.c_int32), ("reserved", C.c_int32)]
 
 
+class ElementData(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("ne", C.c_int32), ("nl", C.c_int32), ("na", C.c_int32),
+                ("np", C.c_int32), ("nq", C.c_int32), ("ncolor", C.c_int32), ("ndof", C.c_int64),
+                ("l2g", C.POINTER(C.c_int32)), ("tgt", C.POINTER(C.c_int32)), ("solid", C.POINTER(C.c_uint8)),
+                ("color_ptr", C.POINTER(C.c_int32)), ("color_elems", C.POINTER(C.c_int32)),
+                ("N", C.POINTER(C.c_double)), ("dN", C.POINTER(C.c_double)), ("psi", C.POINTER(C.c_double)),
+                ("w", C.POINTER(C.c_double)), ("vol", C.c_double), ("dirichlet", C.POINTER(C.c_uint8)),
+                ("dval", C.POINTER(C.c_double)), ("y_prev", C.POINTER(C.c_double)),
+                ("mu", C.c_double), ("rho", C.c_double), ("mu_s", C.c_double), ("dt", C.c_double),
+                ("rho_s", C.c_double)]
+
+
+class NewtonOpts(C.Structure):
+    _fields_ = [("max_newton", C.c_int32), ("tol", C.c_double)]
+
+
+class NewtonInfo(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("converged", C.c_int32), ("krylov_iters", C.c_int32),
+                ("last_update", C.c_double), ("res0", C.c_double), ("res_last", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # every symbol the headers declare (checked by the CPU tests)
 EXPORTS = [
     "fsi_abi_version", "fsi_status_string", "fsi_last_error", "fsi_mg_setup", "fsi_mg_vcycle",
@@ -93,6 +117,8 @@ EXPORTS = [
     "fsi_server_stats", "fsi_server_destroy", "fsi_stream_read", "fsi_stream_read_blocks",
     "fsi_problem_build", "fsi_problem_nlevels", "fsi_problem_levels", "fsi_problem_vectors",
     "fsi_problem_dirichlet", "fsi_problem_residual", "fsi_problem_destroy", "fsi_problem_last_error",
+    "fsi_problem_element_data", "fsi_assembly_create", "fsi_assembly_run", "fsi_newton_solve",
+    "fsi_assembly_destroy",
 ]
 
 _lib = None
@@ -146,6 +172,12 @@ def lib():
         "fsi_problem_residual": (C.c_int32, [P, P, P]),
         "fsi_problem_destroy": (C.c_int32, [P]),
         "fsi_problem_last_error": (C.c_char_p, []),
+        "fsi_problem_element_data": (C.c_int32, [P, C.POINTER(ElementData)]),
+        "fsi_assembly_create": (C.c_int32, [C.POINTER(ElementData), C.POINTER(Csr), P, C.POINTER(P)]),
+        "fsi_assembly_run": (C.c_int32, [P, P, P, P, P]),
+        "fsi_newton_solve": (C.c_int32, [P, P, P, C.POINTER(NewtonOpts), C.POINTER(KrylovOpts),
+                                         C.POINTER(NewtonInfo), P]),
+        "fsi_assembly_destroy": (C.c_int32, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

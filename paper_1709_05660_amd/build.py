@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfsimg.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-HIP_SOURCES = ["fsi_kernels.hip", "fsi_gj.hip", "fsi_mg.hip", "fsi_server.hip"]
+HIP_SOURCES = ["fsi_kernels.hip", "fsi_gj.hip", "fsi_mg.hip", "fsi_server.hip", "fsi_assemble.hip"]
 CXX_SOURCES = ["fsi_builder.cpp"]
 
 # packed FP32 instructions are disabled (hipcc device flag); gfx950 only

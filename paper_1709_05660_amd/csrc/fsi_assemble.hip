@@ -1,0 +1,586 @@
+// Device assembly of the finest residual and its exact Jacobian, and the
+// Newton loop on the device (include/fsi_assembly.h).
+//
+// One workgroup per (element of one colour, range of threads); each thread
+// differentiates its element's residual along one local dof (a one-direction
+// dual number: value and derivative) for a chunk of the element's residual
+// rows, and writes its derivative column of the element Jacobian into the
+// CSR values (the column found by binary search in the row).  Elements of one
+// colour share no node, so every entry is written once per launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <vector>
+
+#include "../../include/fsi_assembly.h"
+#include "fsi_internal.h"
+
+namespace fsi {
+
+// ------------------------------------------------------------ one-direction duals
+struct D1 {
+  double v, g;
+};
+__device__ __forceinline__ D1 dc(double c) { return {c, 0.0}; }
+__device__ __forceinline__ D1 operator+(D1 a, D1 b) { return {a.v + b.v, a.g + b.g}; }
+__device__ __forceinline__ D1 operator-(D1 a, D1 b) { return {a.v - b.v, a.g - b.g}; }
+__device__ __forceinline__ D1 operator-(D1 a) { return {-a.v, -a.g}; }
+__device__ __forceinline__ D1 operator*(D1 a, D1 b) { return {a.v * b.v, a.g * b.v + a.v * b.g}; }
+__device__ __forceinline__ D1 operator*(double s, D1 b) { return {s * b.v, s * b.g}; }
+__device__ __forceinline__ D1 operator+(D1 a, double c) { return {a.v + c, a.g}; }
+__device__ __forceinline__ D1 operator/(D1 a, D1 b) {
+  const double q = a.v / b.v;
+  return {q, (a.g - q * b.g) / b.v};
+}
+__device__ __forceinline__ double val(double x) { return x; }
+__device__ __forceinline__ double val(D1 x) { return x.v; }
+
+struct AsmView {
+  int ne, ndof, ncolor;
+  const int *l2g, *tgt, *color_ptr, *color_elems, *rowptr, *col;
+  const uint8_t *solid, *dir;
+  const double *N, *dN, *psi, *w, *yprev;
+  double vol, mu, rho, mu_s, dt, rho_s;
+  int transient;
+};
+
+template <int DIM>
+struct Shape {
+  static constexpr int NA = DIM == 3 ? 27 : 9, NP = DIM + 1, NL = 2 * DIM * NA + NP, NQ = DIM == 3 ? 27 : 9;
+};
+
+// fields of one state at one quadrature point (as the host builder's Kin)
+template <int DIM, typename V>
+struct KinD {
+  V Gd[DIM][DIM], F[DIM][DIM], Fi[DIM][DIM], det, pq, uq[DIM], dq[DIM], gu[DIM][DIM];
+};
+
+// kinematics of the element state: value(i) gives local dof i as V
+template <int DIM, typename V, class Val>
+__device__ __forceinline__ void kin(const double *Nq, const double *dNq, const double *ps, Val dof, bool fluid,
+                                    KinD<DIM, V> &k) {
+  constexpr int NA = Shape<DIM>::NA, NP = Shape<DIM>::NP;
+  for (int c = 0; c < DIM; ++c)
+    for (int j = 0; j < DIM; ++j) {
+      V s = V{};
+      for (int a = 0; a < NA; ++a) s = s + dNq[a * DIM + j] * dof(c * NA + a);
+      k.Gd[c][j] = s;
+      k.F[c][j] = c == j ? s + 1.0 : s;
+    }
+  if constexpr (DIM == 2) {
+    k.det = k.F[0][0] * k.F[1][1] - k.F[0][1] * k.F[1][0];
+    k.Fi[0][0] = k.F[1][1] / k.det;
+    k.Fi[1][1] = k.F[0][0] / k.det;
+    k.Fi[0][1] = -(k.F[0][1] / k.det);
+    k.Fi[1][0] = -(k.F[1][0] / k.det);
+  } else {
+    V cof[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+        cof[i][j] = k.F[i1][j1] * k.F[i2][j2] - k.F[i1][j2] * k.F[i2][j1];
+      }
+    k.det = k.F[0][0] * cof[0][0] + k.F[0][1] * cof[0][1] + k.F[0][2] * cof[0][2];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) k.Fi[i][j] = cof[j][i] / k.det;
+  }
+  V p = V{};
+  for (int j = 0; j < NP; ++j) p = p + ps[j] * dof(2 * DIM * NA + j);
+  k.pq = p;
+  for (int c = 0; c < DIM; ++c) {
+    V u = V{}, d = V{};
+    for (int a = 0; a < NA; ++a) {
+      u = u + Nq[a] * dof((DIM + c) * NA + a);
+      d = d + Nq[a] * dof(c * NA + a);
+    }
+    k.uq[c] = u;
+    k.dq[c] = d;
+  }
+  if (!fluid) return;
+  for (int c = 0; c < DIM; ++c) {
+    V Gu[DIM];
+    for (int j = 0; j < DIM; ++j) {
+      V s = V{};
+      for (int a = 0; a < NA; ++a) s = s + dNq[a * DIM + j] * dof((DIM + c) * NA + a);
+      Gu[j] = s;
+    }
+    for (int b = 0; b < DIM; ++b) {
+      V s = V{};
+      for (int j = 0; j < DIM; ++j) s = s + Gu[j] * k.Fi[j][b];
+      k.gu[c][b] = s;
+    }
+  }
+}
+
+// structural coupling of local row lr with local column lc (the builder's rule)
+__device__ __forceinline__ bool coupled_d(int dim, int na, bool solid, bool transient, int lr, int lc) {
+  const int nd = dim * na;
+  const int rblk = lr < nd ? 0 : (lr < 2 * nd ? 1 : 2);
+  const int cblk = lc < nd ? 0 : (lc < 2 * nd ? 1 : 2);
+  const int rc = (lr % nd) / na, cc = (lc % nd) / na;
+  if (!solid) {
+    if (rblk == 0) return true;
+    if (rblk == 1) return cblk == 0 && rc == cc;
+    return cblk != 2;
+  }
+  if (rblk == 0) return cblk != 1 || (transient && rc == cc);
+  if (rblk == 1) return (cblk == 1 || (transient && cblk == 0)) && rc == cc;
+  return cblk == 0;
+}
+
+// Element residual rows [r0, r0 + RC) with their derivative along local dof
+// jd, the formulas of the host builder (steady, or one Crank-Nicolson step
+// from the state ye0 at t_n to ye at t_{n+1}).
+template <int DIM, int RC>
+__device__ void element_rows(const AsmView &v, bool solid, const double *ye, const double *ye0, int jd, int r0,
+                             const double *sN, const double *sdN, const double *spsi, const double *sw,
+                             D1 (&rows)[RC]) {
+  constexpr int NA = Shape<DIM>::NA, NP = Shape<DIM>::NP, NQ = Shape<DIM>::NQ;
+  const bool cn = ye0 != nullptr;
+  const double dt = v.dt, rho = v.rho, mu = v.mu;
+  const double k_ale = 1.0 / v.vol;
+#pragma unroll
+  for (int i = 0; i < RC; ++i) rows[i] = dc(0.0);
+  auto dof1 = [&](int i) -> D1 { return {ye[i], i == jd ? 1.0 : 0.0}; };
+  auto dof0 = [&](int i) -> double { return ye0[i]; };
+  for (int q = 0; q < NQ; ++q) {
+    const double *Nq = sN + q * NA, *dNq = sdN + q * NA * DIM, *ps = spsi + q * NP;
+    const double w = sw[q];
+    KinD<DIM, D1> k1;
+    kin<DIM>(Nq, dNq, ps, dof1, !solid, k1);
+    // per-point quantities of the rows: momentum (S, Tm), mesh motion /
+    // kinematics (A), continuity / incompressibility (Pr)
+    D1 S[DIM], Tm[DIM][DIM], A[DIM], Pr;
+    double Tm0[DIM][DIM];
+    bool with_S = true;
+    if (!solid) {
+      D1 sig1[DIM][DIM];
+      for (int c = 0; c < DIM; ++c)
+        for (int b = 0; b < DIM; ++b) {
+          sig1[c][b] = mu * (k1.gu[c][b] + k1.gu[b][c]);
+          if (b == c) sig1[c][b] = sig1[c][b] - k1.pq;
+        }
+      const D1 wJ1 = w * k1.det;
+      if (!cn) {
+        for (int c = 0; c < DIM; ++c) {
+          D1 t = dc(0.0);
+          for (int b = 0; b < DIM; ++b) t = t + k1.gu[c][b] * k1.uq[b];
+          S[c] = rho * (wJ1 * t);
+          for (int j = 0; j < DIM; ++j) {
+            D1 t2 = dc(0.0);
+            for (int b = 0; b < DIM; ++b) t2 = t2 + sig1[c][b] * k1.Fi[j][b];
+            Tm[c][j] = wJ1 * t2;
+            Tm0[c][j] = 0.0;
+          }
+        }
+      } else {
+        KinD<DIM, double> k0;
+        kin<DIM>(Nq, dNq, ps, dof0, true, k0);
+        double sig0[DIM][DIM];
+        for (int c = 0; c < DIM; ++c)
+          for (int b = 0; b < DIM; ++b) {
+            sig0[c][b] = mu * (k0.gu[c][b] + k0.gu[b][c]);
+            if (b == c) sig0[c][b] -= k0.pq;
+          }
+        const double wJ0 = w * k0.det;
+        D1 wq[DIM], Gw[DIM][DIM];
+        for (int c = 0; c < DIM; ++c) {
+          wq[c] = (1.0 / dt) * k1.dq[c] + (-k0.dq[c] / dt);
+          for (int j = 0; j < DIM; ++j) Gw[c][j] = (1.0 / dt) * k1.Gd[c][j] + (-k0.Gd[c][j] / dt);
+        }
+        D1 divw1 = dc(0.0), divw0 = dc(0.0);
+        for (int c = 0; c < DIM; ++c)
+          for (int j = 0; j < DIM; ++j) {
+            divw1 = divw1 + Gw[c][j] * k1.Fi[j][c];
+            divw0 = divw0 + k0.Fi[j][c] * Gw[c][j];
+          }
+        for (int c = 0; c < DIM; ++c) {
+          D1 t1 = -(divw1 * k1.uq[c]);
+          for (int b = 0; b < DIM; ++b) t1 = t1 + k1.gu[c][b] * k1.uq[b] - k1.gu[c][b] * wq[b];
+          t1 = (0.5 * rho) * t1 + (rho / dt) * k1.uq[c];
+          D1 t2 = (-k0.uq[c]) * divw0;
+          for (int b = 0; b < DIM; ++b) t2 = t2 + k0.gu[c][b] * k0.uq[b] + (-k0.gu[c][b]) * wq[b];
+          t2 = (0.5 * rho) * t2 + (-(rho / dt) * k0.uq[c]);
+          S[c] = wJ1 * t1 + wJ0 * t2;
+          for (int j = 0; j < DIM; ++j) {
+            D1 s1 = dc(0.0);
+            double c0 = 0.0;
+            for (int b = 0; b < DIM; ++b) {
+              s1 = s1 + sig1[c][b] * k1.Fi[j][b];
+              c0 += sig0[c][b] * k0.Fi[j][b];
+            }
+            Tm[c][j] = 0.5 * (wJ1 * s1);
+            Tm0[c][j] = 0.5 * wJ0 * c0;
+          }
+        }
+      }
+      for (int c = 0; c < DIM; ++c) A[c] = dc(0.0);   // the mesh motion uses Gd directly
+      D1 div = dc(0.0);
+      for (int c = 0; c < DIM; ++c) div = div + k1.gu[c][c];
+      Pr = wJ1 * div;
+    } else {
+      // Piola stress J sigma F^{-T}, sigma = -p I + mu_s F F^T
+      D1 sig[DIM][DIM];
+      for (int c = 0; c < DIM; ++c)
+        for (int b = 0; b < DIM; ++b) {
+          D1 s = dc(0.0);
+          for (int j = 0; j < DIM; ++j) s = s + k1.F[c][j] * k1.F[b][j];
+          sig[c][b] = v.mu_s * s;
+          if (b == c) sig[c][b] = sig[c][b] - k1.pq;
+        }
+      for (int c = 0; c < DIM; ++c)
+        for (int b = 0; b < DIM; ++b) {
+          D1 s = dc(0.0);
+          for (int j = 0; j < DIM; ++j) s = s + sig[c][j] * k1.Fi[b][j];
+          Tm[c][b] = k1.det * s;
+          Tm0[c][b] = 0.0;
+        }
+      with_S = cn;
+      if (cn) {
+        KinD<DIM, double> k0;
+        kin<DIM>(Nq, dNq, ps, dof0, false, k0);
+        double sg0[DIM][DIM];
+        for (int c = 0; c < DIM; ++c)
+          for (int b = 0; b < DIM; ++b) {
+            double s = 0.0;
+            for (int j = 0; j < DIM; ++j) s += k0.F[c][j] * k0.F[b][j];
+            sg0[c][b] = v.mu_s * s - (b == c ? k0.pq : 0.0);
+          }
+        for (int c = 0; c < DIM; ++c) {
+          for (int b = 0; b < DIM; ++b) {
+            double s = 0.0;
+            for (int j = 0; j < DIM; ++j) s += sg0[c][j] * k0.Fi[b][j];
+            Tm0[c][b] = k0.det * s;
+          }
+          S[c] = (v.rho_s / dt) * (k1.det * k1.uq[c] + (-k0.det * k0.uq[c]));
+          A[c] = (-1.0 / dt) * k1.dq[c] + 0.5 * k1.uq[c] + (k0.dq[c] / dt + 0.5 * k0.uq[c]);
+        }
+      } else {
+        for (int c = 0; c < DIM; ++c) {
+          S[c] = dc(0.0);
+          A[c] = k1.uq[c];
+        }
+      }
+      Pr = k1.det + (-1.0);
+    }
+    const double half = (solid && cn) ? 0.5 : 1.0;
+    // this thread's rows
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+      const int lr = r0 + i;
+      if (lr >= Shape<DIM>::NL) break;
+      if (lr < DIM * NA) {   // momentum
+        const int c = lr / NA, a = lr % NA;
+        D1 t = dc(0.0);
+        if (!solid) {
+          t = Nq[a] * S[c];
+          for (int j = 0; j < DIM; ++j) t = t + dNq[a * DIM + j] * Tm[c][j] + dNq[a * DIM + j] * Tm0[c][j];
+        } else {
+          if (with_S) t = (w * Nq[a]) * S[c];
+          for (int b = 0; b < DIM; ++b)
+            t = t + (half * w * dNq[a * DIM + b]) * Tm[c][b] + half * w * dNq[a * DIM + b] * Tm0[c][b];
+        }
+        rows[i] = rows[i] + t;
+      } else if (lr < 2 * DIM * NA) {   // mesh motion (fluid) / kinematics (solid)
+        const int c = (lr - DIM * NA) / NA, a = (lr - DIM * NA) % NA;
+        D1 t = dc(0.0);
+        if (!solid) {
+          for (int b = 0; b < DIM; ++b) t = t + (w * k_ale * dNq[a * DIM + b]) * k1.Gd[c][b];
+        } else {
+          t = (w * Nq[a]) * A[c];
+        }
+        rows[i] = rows[i] + t;
+      } else {   // continuity / incompressibility
+        const int j = lr - 2 * DIM * NA;
+        rows[i] = rows[i] + (solid ? (w * ps[j]) * Pr : ps[j] * Pr);
+      }
+    }
+  }
+}
+
+template <int DIM, int RC, int NT>
+__global__ __launch_bounds__(NT) void k_assemble(AsmView v, const double *__restrict__ y, double *__restrict__ r,
+                                                 double *__restrict__ jval, int cbase, int nsplit) {
+  constexpr int NA = Shape<DIM>::NA, NP = Shape<DIM>::NP, NL = Shape<DIM>::NL, NQ = Shape<DIM>::NQ;
+  constexpr int NCH = (NL + RC - 1) / RC;
+  __shared__ double ye[NL], ye0[NL];
+  __shared__ int g[NL], tg[NL];
+  __shared__ double sN[NQ * NA], sdN[NQ * NA * DIM], spsi[NQ * NP], sw[NQ];
+  const int e = v.color_elems[cbase + blockIdx.x / nsplit];
+  const int t = (blockIdx.x % nsplit) * NT + threadIdx.x;
+  const bool solid = v.solid[e] != 0;
+  for (int i = threadIdx.x; i < NL; i += NT) {
+    g[i] = v.l2g[(int64_t)e * NL + i];
+    tg[i] = v.tgt[(int64_t)e * NL + i];
+    ye[i] = y[g[i]];
+    ye0[i] = v.transient ? v.yprev[g[i]] : 0.0;
+  }
+  for (int i = threadIdx.x; i < NQ * NA; i += NT) sN[i] = v.N[i];
+  for (int i = threadIdx.x; i < NQ * NA * DIM; i += NT) sdN[i] = v.dN[i];
+  for (int i = threadIdx.x; i < NQ * NP; i += NT) spsi[i] = v.psi[i];
+  for (int i = threadIdx.x; i < NQ; i += NT) sw[i] = v.w[i];
+  __syncthreads();
+  if (t >= NL * NCH) return;
+  const int jd = t / NCH, r0 = (t % NCH) * RC;
+  D1 rows[RC];
+  element_rows<DIM, RC>(v, solid, ye, v.transient ? ye0 : nullptr, jd, r0, sN, sdN, spsi, sw, rows);
+  const int gc = g[jd];
+  const bool col_free = !v.dir[gc];
+#pragma unroll
+  for (int i = 0; i < RC; ++i) {
+    const int lr = r0 + i;
+    if (lr >= NL) break;
+    const int tr = tg[lr];
+    if (tr < 0) continue;
+    if (jd == 0) r[tr] += rows[i].v;
+    if (v.dir[tr] || !col_free || !coupled_d(DIM, NA, solid, v.transient != 0, lr, jd)) continue;
+    int lo = v.rowptr[tr], hi = v.rowptr[tr + 1];
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (v.col[mid] < gc)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    if (lo < v.rowptr[tr + 1] && v.col[lo] == gc) jval[lo] += rows[i].g;
+  }
+}
+
+// Dirichlet rows: r = y - g and a unit diagonal
+__global__ void k_dirichlet_rows(const int *rows, const int *diag, int n, const double *y, const double *gval,
+                                 double *r, double *jval) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const int i = rows[t];
+  r[i] = y[i] - gval[t];
+  jval[diag[t]] = 1.0;
+}
+__global__ void k_neg_free(const double *r, const uint8_t *dir, int n, double *b) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) b[i] = dir[i] ? 0.0 : -r[i];
+}
+
+// device memory of the assembler (plain allocations, freed at destroy)
+struct AsmMem {
+  std::vector<void *> v;
+  template <typename T>
+  T *alloc(int64_t n) {
+    void *p = nullptr;
+    if (n <= 0) return nullptr;
+    if (hipMalloc(&p, sizeof(T) * (size_t)n) != hipSuccess) throw Error(FSI_E_OOM, "device allocation");
+    v.push_back(p);
+    return static_cast<T *>(p);
+  }
+  template <typename T>
+  T *up(const T *h, int64_t n) {
+    T *d = alloc<T>(n);
+    if (n > 0) hip_check(hipMemcpy(d, h, sizeof(T) * (size_t)n, hipMemcpyHostToDevice), "H2D");
+    return d;
+  }
+};
+
+struct Assembly {
+  AsmView v{};
+  int dim = 2, nnz = 0;
+  std::vector<int> h_color_ptr;
+  int ndir = 0;
+  int *d_dir_rows = nullptr, *d_dir_diag = nullptr;
+  double *d_dir_val = nullptr;
+  double *b = nullptr, *x = nullptr, *r = nullptr, *partial = nullptr, *nrm = nullptr;
+  AsmMem mem;
+};
+
+template <int DIM, int RC, int NT>
+static void launch_assemble_dim(Assembly &A, const double *y, double *r, double *jval, hipStream_t st) {
+  constexpr int NL = Shape<DIM>::NL, NCH = (NL + RC - 1) / RC;
+  const int nsplit = (NL * NCH + NT - 1) / NT;
+  for (int c = 0; c < A.v.ncolor; ++c) {
+    const int n = A.h_color_ptr[c + 1] - A.h_color_ptr[c];
+    if (n > 0)
+      k_assemble<DIM, RC, NT><<<n * nsplit, NT, 0, st>>>(A.v, y, r, jval, A.h_color_ptr[c], nsplit);
+  }
+}
+
+static void assemble(Assembly &A, const double *y, double *r, double *jval, hipStream_t st) {
+  launch_fill_f64(r, A.v.ndof, 0.0, st);
+  launch_fill_f64(jval, A.nnz, 0.0, st);
+  if (A.dim == 2)
+    launch_assemble_dim<2, 39, 64>(A, y, r, jval, st);
+  else
+    launch_assemble_dim<3, 24, 256>(A, y, r, jval, st);
+  if (A.ndir)
+    k_dirichlet_rows<<<(A.ndir + 255) / 256, 256, 0, st>>>(A.d_dir_rows, A.d_dir_diag, A.ndir, y, A.d_dir_val, r,
+                                                            jval);
+  hip_check(hipGetLastError(), "assembly launch");
+}
+
+static Assembly *create(const fsi_element_data &ed, const fsi_csr &J, hipStream_t st) {
+  if ((ed.dim != 2 && ed.dim != 3) || ed.ne < 1 || !ed.l2g || !ed.tgt || !ed.solid || !ed.color_ptr ||
+      !ed.color_elems || !ed.N || !ed.dN || !ed.psi || !ed.w || !ed.dirichlet || !ed.dval)
+    throw Error(FSI_E_INVALID, "element data incomplete");
+  const int na = ed.dim == 3 ? 27 : 9, nl = 2 * ed.dim * na + ed.dim + 1, nq = ed.dim == 3 ? 27 : 9;
+  if (ed.na != na || ed.nl != nl || ed.nq != nq || ed.np != ed.dim + 1 || J.nrows != ed.ndof || J.ncols != ed.ndof ||
+      !J.rowptr || !J.colind || J.nnz >= ((int64_t)1 << 31) || ed.ndof >= ((int64_t)1 << 31))
+    throw Error(FSI_E_INVALID, "element data and pattern sizes do not match");
+  std::unique_ptr<Assembly> A(new Assembly());
+  A->dim = ed.dim;
+  A->nnz = (int)J.nnz;
+  A->h_color_ptr.assign(ed.color_ptr, ed.color_ptr + ed.ncolor + 1);
+  for (int64_t q = 0; q < (int64_t)ed.ne * nl; ++q)
+    if (ed.l2g[q] < 0 || ed.l2g[q] >= ed.ndof || ed.tgt[q] < -1 || ed.tgt[q] >= ed.ndof)
+      throw Error(FSI_E_INVALID, "element data: a dof out of range");
+  if (A->h_color_ptr.front() != 0 || A->h_color_ptr.back() != ed.ne)
+    throw Error(FSI_E_INVALID, "element data: colours do not list every element");
+  AsmMem &M = A->mem;
+  AsmView &v = A->v;
+  v.ne = ed.ne;
+  v.ndof = (int)ed.ndof;
+  v.ncolor = ed.ncolor;
+  v.l2g = M.up(ed.l2g, (int64_t)ed.ne * nl);
+  v.tgt = M.up(ed.tgt, (int64_t)ed.ne * nl);
+  v.color_ptr = M.up(ed.color_ptr, ed.ncolor + 1);
+  v.color_elems = M.up(ed.color_elems, ed.ne);
+  std::vector<int32_t> rp(J.nrows + 1);
+  for (int64_t i = 0; i <= J.nrows; ++i) rp[i] = (int32_t)J.rowptr[i];
+  v.rowptr = M.up(rp.data(), J.nrows + 1);
+  v.col = M.up(J.colind, J.nnz);
+  v.solid = M.up(ed.solid, ed.ne);
+  v.dir = M.up(ed.dirichlet, ed.ndof);
+  v.N = M.up(ed.N, (int64_t)nq * na);
+  v.dN = M.up(ed.dN, (int64_t)nq * na * ed.dim);
+  v.psi = M.up(ed.psi, (int64_t)nq * (ed.dim + 1));
+  v.w = M.up(ed.w, nq);
+  v.transient = ed.y_prev ? 1 : 0;
+  v.yprev = ed.y_prev ? M.up(ed.y_prev, ed.ndof) : nullptr;
+  v.vol = ed.vol;
+  v.mu = ed.mu;
+  v.rho = ed.rho;
+  v.mu_s = ed.mu_s;
+  v.dt = ed.dt;
+  v.rho_s = ed.rho_s;
+  std::vector<int> drows, ddiag;
+  std::vector<double> dvals;
+  for (int64_t i = 0; i < ed.ndof; ++i)
+    if (ed.dirichlet[i]) {
+      const int32_t *a = J.colind + J.rowptr[i], *b = J.colind + J.rowptr[i + 1];
+      const int32_t *f = std::lower_bound(a, b, (int32_t)i);
+      if (f == b || *f != i) throw Error(FSI_E_INVALID, "a Dirichlet row of the pattern holds no diagonal");
+      drows.push_back((int)i);
+      ddiag.push_back((int)(f - J.colind));
+      dvals.push_back(ed.dval[i]);
+    }
+  A->ndir = (int)drows.size();
+  A->d_dir_rows = M.up(drows.data(), (int64_t)drows.size());
+  A->d_dir_diag = M.up(ddiag.data(), (int64_t)ddiag.size());
+  A->d_dir_val = M.up(dvals.data(), (int64_t)dvals.size());
+  const int n = (int)ed.ndof;
+  A->b = M.alloc<double>(n);
+  A->x = M.alloc<double>(n);
+  A->r = M.alloc<double>(n);
+  A->partial = M.alloc<double>(krylov_blocks(n));
+  A->nrm = M.alloc<double>(4);
+  (void)st;
+  return A.release();
+}
+
+static double dev_norm(Assembly &A, const double *x, int n, hipStream_t st) {
+  launch_kdot(n, x, n, 1, x, A.partial, A.nrm, st);
+  double h = 0.0;
+  hip_check(hipMemcpyAsync(&h, A.nrm, sizeof(double), hipMemcpyDeviceToHost, st), "D2H norm");
+  hip_check(hipStreamSynchronize(st), "norm");
+  return std::sqrt(h);
+}
+
+static fsi_status newton(Assembly &A, MG &mg, double *y, const fsi_newton_opts &no, const fsi_krylov_opts &ko,
+                         fsi_newton_info *info, hipStream_t st) {
+  Level &F = mg.lv.back();
+  if (F.n != A.v.ndof || F.J.nnz != A.nnz) throw Error(FSI_E_INVALID, "the handle's finest pattern is not the assembly's");
+  if (no.max_newton < 1 || !(no.tol > 0.0)) throw Error(FSI_E_INVALID, "invalid Newton options");
+  fsi_newton_info inf{};
+  const int n = A.v.ndof;
+  fsi_status st_out = FSI_NOT_CONVERGED;
+  for (int k = 0; k < no.max_newton; ++k) {
+    assemble(A, y, A.r, F.J.val, st);   // the finest values go straight into the handle
+    const double rn = dev_norm(A, A.r, n, st);
+    if (k == 0) inf.res0 = rn;
+    inf.res_last = rn;
+    k_neg_free<<<(n + 255) / 256, 256, 0, st>>>(A.r, A.v.dir, n, A.b);
+    galerkin(mg, st);
+    refactor(mg, st);
+    fsi_krylov_opts kk = ko;
+    kk.x0_nonzero = 0;
+    fsi_solve_info si{};
+    const fsi_status s = fgmres(mg, A.b, A.x, kk, &si, st);
+    if (s < 0) return s;
+    inf.krylov_iters += si.iters;
+    launch_axpy_f64(n, 1.0, A.x, y, st);
+    const double en = dev_norm(A, A.x, n, st), yn = dev_norm(A, y, n, st);
+    inf.steps = k + 1;
+    inf.last_update = yn > 0 ? en / yn : en;
+    if (en <= no.tol * yn) {
+      inf.converged = 1;
+      st_out = FSI_OK;
+      break;
+    }
+  }
+  if (info) *info = inf;
+  return st_out;
+}
+
+}  // namespace fsi
+
+using namespace fsi;
+
+extern "C" {
+
+fsi_status fsi_assembly_create(const fsi_element_data *ed, const fsi_csr *J, void *hip_stream,
+                               struct fsi_assembly **out) {
+  try {
+    if (!ed || !J || !out) throw Error(FSI_E_INVALID, "null argument");
+    *out = reinterpret_cast<fsi_assembly *>(create(*ed, *J, (hipStream_t)hip_stream));
+    return FSI_OK;
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+fsi_status fsi_assembly_run(struct fsi_assembly *h, const double *y_dev, double *r_dev, double *jval_dev,
+                            void *hip_stream) {
+  try {
+    Assembly *A = reinterpret_cast<Assembly *>(h);
+    if (!A || !y_dev || !r_dev || !jval_dev) throw Error(FSI_E_INVALID, "null argument");
+    assemble(*A, y_dev, r_dev, jval_dev, (hipStream_t)hip_stream);
+    return FSI_OK;
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+fsi_status fsi_newton_solve(struct fsi_assembly *h, struct fsi_mg *mh, double *y_dev, const fsi_newton_opts *nopts,
+                            const fsi_krylov_opts *kopts, fsi_newton_info *info, void *hip_stream) {
+  try {
+    Assembly *A = reinterpret_cast<Assembly *>(h);
+    MG *mg = reinterpret_cast<MG *>(mh);
+    if (!A || !mg || !y_dev || !nopts || !kopts) throw Error(FSI_E_INVALID, "null argument");
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
+    return newton(*A, *mg, y_dev, *nopts, *kopts, info, st);
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+fsi_status fsi_assembly_destroy(struct fsi_assembly *h) {
+  Assembly *A = reinterpret_cast<Assembly *>(h);
+  if (!A) return FSI_OK;
+  (void)hipDeviceSynchronize();
+  for (void *p : A->mem.v) (void)hipFree(p);
+  delete A;
+  return FSI_OK;
+}
+
+}  // extern "C"

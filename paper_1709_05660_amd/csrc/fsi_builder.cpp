@@ -954,6 +954,9 @@ struct Problem {
   std::vector<Patches> patches;
   std::vector<double> y, b;
   std::vector<double> y_prev;  // state at t_n of a time step (empty: steady)
+  // the finest level's element data (fsi_problem_element_data)
+  std::vector<int32_t> l2g, tgt, color_ptr, color_elems;
+  Tab tab;
 };
 
 static void residual_jacobian(const Mesh &M, const fsi_problem_spec &s, const std::vector<double> &y,
@@ -1015,6 +1018,25 @@ static Problem *build(const fsi_problem_spec &s0) {
   }
   pb->patches.resize(L);
   for (int l = 1; l < L; ++l) pb->patches[l] = make_patches(pb->meshes[l], s.patch);
+  // element data of the finest level, colours by element parity as the assembly's
+  const int nl = 2 * Fm.dim * Fm.na + Fm.npe;
+  pb->l2g.resize((size_t)Fm.ne * nl);
+  pb->tgt.resize((size_t)Fm.ne * nl);
+  for (int e = 0; e < Fm.ne; ++e)
+    for (int q = 0; q < nl; ++q) {
+      pb->l2g[(size_t)e * nl + q] = local_col_dof(Fm, e, q);
+      pb->tgt[(size_t)e * nl + q] = target_row(Fm, e, q);
+    }
+  const int ncol = Fm.dim == 3 ? 8 : 4;
+  pb->color_ptr.assign(1, 0);
+  for (int color = 0; color < ncol; ++color) {
+    for (int e = 0; e < Fm.ne; ++e) {
+      const int ex = e % Fm.n[0], ey = (e / Fm.n[0]) % Fm.n[1], ez = e / (Fm.n[0] * Fm.n[1]);
+      if ((ex & 1) + 2 * (ey & 1) + 4 * (ez & 1) == color) pb->color_elems.push_back(e);
+    }
+    pb->color_ptr.push_back((int32_t)pb->color_elems.size());
+  }
+  pb->tab = make_tab(Fm);
   return pb.release();
 }
 
@@ -1101,6 +1123,40 @@ fsi_status fsi_problem_residual(const struct fsi_problem *hp, const double *y, d
   std::vector<double> yy(y, y + M.ndof), rr;
   residual_jacobian(M, p->spec, yy, p->spec.transient ? &p->y_prev : nullptr, rr, nullptr);
   std::copy(rr.begin(), rr.end(), r);
+  return FSI_OK;
+}
+
+fsi_status fsi_problem_element_data(const struct fsi_problem *hp, fsi_element_data *out) {
+  const Problem *p = reinterpret_cast<const Problem *>(hp);
+  if (!p || !out) return FSI_E_INVALID;
+  const Mesh &M = p->meshes.back();
+  fsi_element_data &d = *out;
+  d.dim = M.dim;
+  d.ne = M.ne;
+  d.na = M.na;
+  d.np = M.npe;
+  d.nl = 2 * M.dim * M.na + M.npe;
+  d.nq = p->tab.nq;
+  d.ncolor = (int32_t)p->color_ptr.size() - 1;
+  d.ndof = M.ndof;
+  d.l2g = p->l2g.data();
+  d.tgt = p->tgt.data();
+  d.solid = M.solid.data();
+  d.color_ptr = p->color_ptr.data();
+  d.color_elems = p->color_elems.data();
+  d.N = p->tab.N.data();
+  d.dN = p->tab.dN.data();
+  d.psi = p->tab.psi.data();
+  d.w = p->tab.w.data();
+  d.vol = p->tab.vol;
+  d.dirichlet = M.dir.data();
+  d.dval = M.dval.data();
+  d.y_prev = p->spec.transient ? p->y_prev.data() : nullptr;
+  d.mu = p->spec.mu;
+  d.rho = p->spec.rho;
+  d.mu_s = p->spec.mu_s;
+  d.dt = p->spec.dt;
+  d.rho_s = p->spec.rho_s;
   return FSI_OK;
 }
 

@@ -203,6 +203,8 @@ void clear_graphs(MG &mg);
 double *pinned_slot_acquire();
 void pinned_slot_release(double *s);
 void refactor(MG &mg, hipStream_t st);
+// coarse operators R J P on the device from the finest values (fsi_mg_galerkin)
+void galerkin(MG &mg, hipStream_t st);
 void release_setup_scratch(MG &mg);
 
 // GMRES(m) as a host state machine over the device work (section "Details on

@@ -374,3 +374,52 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class Assembly:
+    """Device assembly of a problem's finest residual and exact Jacobian
+    (fsi_assembly_*), and Newton's method on the device (fsi_newton_solve)."""
+
+    def __init__(self, problem):
+        self.problem = problem
+        ed = L.ElementData()
+        L.check(L.lib().fsi_problem_element_data(problem.h, C.byref(ed)), "element data")
+        self.ed = ed
+        self.n = int(ed.ndof)
+        J = problem.levels[problem.nlevels - 1].J
+        self.nnz = int(J.nnz)
+        h = C.c_void_p()
+        L.check(L.lib().fsi_assembly_create(C.byref(ed), C.byref(J), _stream(), C.byref(h)), "assembly create")
+        self.h = h
+
+    def run(self, y, r=None, jval=None):
+        """r = R(y) and the Jacobian's values at y (device float64 tensors)."""
+        import torch
+        if r is None:
+            r = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        if jval is None:
+            jval = torch.empty(self.nnz, dtype=torch.float64, device="cuda")
+        L.check(L.lib().fsi_assembly_run(self.h, _vec(y, self.n, "y"), _vec(r, self.n, "r"),
+                                         _vec(jval, self.nnz, "jval"), _stream()), "assembly run")
+        return r, jval
+
+    def newton(self, mg, y, max_newton=20, tol=1e-8, rtol=1e-8, restart=30, maxit=1000):
+        """Newton's method on the device from y (updated in place); returns the info."""
+        no = L.NewtonOpts(int(max_newton), float(tol))
+        ko = krylov_opts(restart, rtol, maxit)
+        info = L.NewtonInfo()
+        st = L.lib().fsi_newton_solve(self.h, mg.h, _vec(y, self.n, "y"), C.byref(no), C.byref(ko),
+                                      C.byref(info), _stream())
+        L.check(st, "newton")
+        return info.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.lib().fsi_assembly_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

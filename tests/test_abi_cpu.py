@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared_functions():
     names = set()
-    for h in ("fsi_mg.h", "fsi_problem.h"):
+    for h in ("fsi_mg.h", "fsi_problem.h", "fsi_assembly.h"):
         txt = open(os.path.join(ROOT, "include", h)).read()
         txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
         for m in re.finditer(r"\b(fsi_[a-z0-9_]+)\s*\(", txt):
