@@ -706,6 +706,7 @@ def main():
     ap.add_argument("--no-time-step", action="store_true")
     ap.add_argument("--steps-3d", type=int, default=5)
     ap.add_argument("--only-3d", action="store_true")
+    ap.add_argument("--only-time-step", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true")
     ap.add_argument("--serve-n", type=int, default=256)
     ap.add_argument("--serve-budget-gb", type=int, default=4)
@@ -718,6 +719,10 @@ def main():
     if args.only_3d:
         # profiling aid: the 3D leg alone, its own JSON line
         print(json.dumps({"three_d": three_d_leg(args)}), flush=True)
+        return
+    if args.only_time_step:
+        # profiling aid: the time-step leg alone, its own JSON line
+        print(json.dumps({"time_step": time_step_leg(args)}), flush=True)
         return
     g = gpu_leg(args)
     value = args.steps / (g["ms_per_step"] * args.steps * 1e-3)
