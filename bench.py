@@ -259,10 +259,15 @@ def time_step_leg(args):
                 a1.record(stream)
                 torch.cuda.synchronize()
                 res["device_assembly_ms"] = round(a0.elapsed_time(a1) / 5, 3)
+                # the first Galerkin call prepares the patterns of J P once (host
+                # work on read-back patterns); Newton is timed after it
+                mg.galerkin()
+                torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 ninfo = asm.newton(mg, y, max_newton=12, tol=1e-8, rtol=1e-10)
                 torch.cuda.synchronize()
-                res["newton_on_device"] = {"ms": round((time.perf_counter() - t0) * 1e3, 2),
+                nms = (time.perf_counter() - t0) * 1e3
+                res["newton_on_device"] = {"ms": round(nms, 2), "ms_per_newton_step": round(nms / max(1, ninfo["steps"]), 2),
                                            "steps": ninfo["steps"], "converged": bool(ninfo["converged"]),
                                            "krylov_iters": ninfo["krylov_iters"],
                                            "residual_first_last": [float(f"{ninfo['res0']:.4g}"),

@@ -40,6 +40,48 @@ def _coarse_products_match(mg, p, tol=1e-12):
         assert np.all(err <= bound)
 
 
+def _scipy_galerkin(p, finest):
+    """The plain definition, independent of both builders' SpGEMM: per level
+    A_{l-1} = R_l A_l P_l by scipy's sparse products, then unit diagonals on
+    the coarse Dirichlet rows (zero rows and columns there otherwise); with
+    |R| |A| |P| alongside, the scale of each product's rounding."""
+    import scipy.sparse as sp
+    ops, absops = {p.nlevels - 1: finest}, {p.nlevels - 1: abs(finest)}
+    for l in range(p.nlevels - 1, 0, -1):
+        R, P = csr_of(p, l, "R"), csr_of(p, l, "P")
+        A = (R @ ops[l] @ P).tocsr()
+        flags = p.dirichlet(l - 1).astype(bool)
+        keep = sp.diags((~flags).astype(float))
+        ops[l - 1] = (keep @ A + sp.diags(flags.astype(float))).tocsr()
+        absops[l - 1] = (abs(R) @ absops[l] @ abs(P) + sp.diags(flags.astype(float))).tocsr()
+    return ops, absops
+
+
+def test_galerkin_of_a_new_jacobian_equals_the_sparse_products():
+    """A different Jacobian of the same sparsity (another material, inflow and
+    seed) set as the finest values of a handle built for the first system's
+    time step: every coarse operator the device computes equals R J P by plain
+    sparse products within 1e-13 of |R| |J| |P| |x|."""
+    from paper_1709_05660_amd import MG
+    p0 = _problem(nx=64, ny=16, levels=3, transient=True)
+    p1 = _problem(nx=64, ny=16, levels=3, transient=True, mu_s=2.0e5, u_peak=0.3, seed=5)
+    f0, f1 = csr_of(p0, p0.nlevels - 1), csr_of(p1, p1.nlevels - 1)
+    assert np.array_equal(f0.indptr, f1.indptr) and np.array_equal(f0.indices, f1.indices)
+    mg = MG(p0, precision="fp64")
+    mg.set_jvalues(p0.nlevels - 1, dev(f1.data))
+    mg.galerkin()
+    ops, absops = _scipy_galerkin(p0, f1)
+    rng = np.random.default_rng(17)
+    for l in range(p0.nlevels - 1):
+        x = rng.standard_normal(ops[l].shape[1])
+        y = host(mg.apply(l, 0, dev(x)))
+        bound = 1e-13 * (absops[l] @ np.abs(x)) + 1e-300
+        err = np.abs(y - ops[l] @ x)
+        _say(f"  level {l}: max err / bound {float(np.max(err / bound)):.3f}")
+        assert np.all(err <= bound)
+    mg.close()
+
+
 def test_galerkin_reproduces_the_builders_coarse_operators():
     from paper_1709_05660_amd import MG
     p = _problem(nx=64, ny=16, levels=3)
