@@ -297,6 +297,61 @@ def time_step_leg(args):
     return res
 
 
+def fmg_leg(args):
+    """Full multigrid for the steady 128x32 system (section "Monolithic
+    Newton-Krylov solver with Multigrid-Richardson-Schwarz preconditioner"):
+    Newton on the nested meshes 16x4, 32x8, 64x16 and 128x32, each started
+    from the prolongation of the one below; FGMRES to 1e-10 in every Newton
+    step, the paper's stopping rule |e| <= 1e-8 |y|.  Timed after one untimed
+    run (the first Galerkin products prepare their patterns on the host); for
+    comparison, Newton from the seeded state on 128x32 alone (at most 120
+    Krylov iterations per step)."""
+    import torch
+
+    from paper_1709_05660_amd import MG, Assembly, Problem, fmg
+    from synth import config, fourier_coefficients
+
+    s0 = config("c1_2d_128x32")
+    coeffs = fourier_coefficients(2, s0.seed)
+    sizes = [(16, 4, 1), (32, 8, 2), (64, 16, 3), (128, 32, 4)]
+    caps = [12, 5, 12, 12]
+    stream = torch.cuda.Stream()
+    res = {"meshes": [f"{nx}x{ny}" for nx, ny, _ in sizes], "newton_step_limits": caps}
+    with torch.cuda.stream(stream):
+        probs = [Problem(s0.with_(nx=nx, ny=ny, levels=lv), coeffs) for nx, ny, lv in sizes]
+        asms = [Assembly(p) for p in probs]
+        mgs = [MG(p, precision="fp64", use_graph=True) for p in probs]
+        bases = [torch.as_tensor(p.y).to("cuda") for p in probs]
+        for k in range(2):
+            y0 = bases[0].clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ys, infos, st = fmg(asms, mgs, y0, bases=bases, max_newton=caps, tol=1e-8, rtol=1e-10)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+        res["ms"] = round(ms, 2)
+        res["finest_converged"] = st == 0
+        res["finest_newton_steps"] = infos[-1]["steps"]
+        res["per_mesh"] = [{"unknowns": p.n, "newton_steps": i["steps"], "converged": bool(i["converged"]),
+                            "krylov_iters": i["krylov_iters"],
+                            "residual_first_last": [float(f"{i['res0']:.4g}"), float(f"{i['res_last']:.4g}")]}
+                           for p, i in zip(probs, infos)]
+        # Newton on the finest mesh from its seeded state, without the coarse meshes
+        y = bases[-1].clone()
+        t0 = time.perf_counter()
+        ninfo = asms[-1].newton(mgs[-1], y, max_newton=12, tol=1e-8, rtol=1e-10, maxit=120)
+        torch.cuda.synchronize()
+        res["newton_from_seeded_state_only"] = {
+            "ms": round((time.perf_counter() - t0) * 1e3, 2), "steps": ninfo["steps"],
+            "converged": bool(ninfo["converged"]),
+            "residual_first_last": [float(f"{ninfo['res0']:.4g}"), float(f"{ninfo['res_last']:.4g}")]}
+        for m in mgs:
+            m.close()
+        for a in asms:
+            a.close()
+    return res
+
+
 def small_leg(args):
     """The 16x4 two-level system (1,380 unknowns): V-cycle and solve in FP64,
     where launch latency, not bandwidth, sets the time."""
@@ -709,6 +764,8 @@ def main():
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--no-time-step", action="store_true")
+    ap.add_argument("--no-fmg", action="store_true")
+    ap.add_argument("--only-fmg", action="store_true")
     ap.add_argument("--steps-3d", type=int, default=5)
     ap.add_argument("--only-3d", action="store_true")
     ap.add_argument("--only-time-step", action="store_true")
@@ -724,6 +781,10 @@ def main():
     if args.only_3d:
         # profiling aid: the 3D leg alone, its own JSON line
         print(json.dumps({"three_d": three_d_leg(args)}), flush=True)
+        return
+    if args.only_fmg:
+        # profiling aid: the full-multigrid leg alone, its own JSON line
+        print(json.dumps({"fmg": fmg_leg(args)}), flush=True)
         return
     if args.only_time_step:
         # profiling aid: the time-step leg alone, its own JSON line
@@ -760,6 +821,8 @@ def main():
         line["three_d"] = three_d_leg(args)
     if not args.no_time_step:
         line["time_step"] = time_step_leg(args)
+    if not args.no_fmg:
+        line["fmg"] = fmg_leg(args)
     if not args.no_paper:
         line["paper_mode"] = paper_leg(args)
     if not args.no_serve:

@@ -67,6 +67,38 @@ fsi_status fsi_newton_solve(struct fsi_assembly *a, struct fsi_mg *mg, double *y
                             const fsi_newton_opts *nopts, const fsi_krylov_opts *kopts,
                             fsi_newton_info *info, void *hip_stream);
 
+/* Full multigrid for the steady case (section "Monolithic Newton-Krylov
+ * solver with Multigrid-Richardson-Schwarz preconditioner": Newton wrapped
+ * in a full multigrid algorithm; section "Details on the iterative solver":
+ * the Newton count reported is the finest mesh's).  nlev nested meshes,
+ * coarsest first, each refining the one before; a[j] and mg[j] are mesh j's
+ * assembly and multigrid handle, and for j > 0 mesh j-1 is the level below
+ * the finest of mg[j] (the same dof numbering), so mg[j]'s finest
+ * prolongation P maps mesh j-1's dofs to mesh j's.
+ *   y_dev[0]   device, n_0 doubles: the coarsest mesh's initial iterate, on
+ *              return its last iterate; y_dev[j], j > 0 (n_j doubles each):
+ *              receive mesh j's iterates.
+ *   base_dev   NULL, or nlev device vectors: a state of each mesh that holds
+ *              its Dirichlet values (the seeded state, say).  The iterate of
+ *              mesh j > 0 starts as base_j + P (y_{j-1} - base_{j-1}): P has
+ *              zero columns at coarse Dirichlet dofs, and the difference is
+ *              zero there, so no boundary data is lost (y_{j-1} is restored).
+ *              NULL: P y_{j-1}.  In both cases the Dirichlet dofs are then
+ *              set to their values.
+ *   max_newton NULL, or nlev step limits (each >= 1); NULL: nopts->max_newton
+ *              on every mesh.
+ * Then Newton (fsi_newton_solve) from that iterate.  A mesh below the finest
+ * that ends above tol is not an error: its iterate only starts the next mesh.
+ * info (may be NULL) receives one record per mesh.  Stream-ordered on
+ * hip_stream; the host reads norms only.  Returns FSI_OK when the finest mesh
+ * converged, FSI_NOT_CONVERGED otherwise.  Errors: FSI_E_INVALID (nlev < 1, a
+ * null handle or vector, a step limit below 1, handles whose sizes do not
+ * chain as above), and those of the calls it makes. */
+fsi_status fsi_fmg_solve(int32_t nlev, struct fsi_assembly *const *a, struct fsi_mg *const *mg,
+                         double *const *y_dev, const double *const *base_dev, const int32_t *max_newton,
+                         const fsi_newton_opts *nopts, const fsi_krylov_opts *kopts, fsi_newton_info *info,
+                         void *hip_stream);
+
 fsi_status fsi_assembly_destroy(struct fsi_assembly *a);
 
 #ifdef __cplusplus

@@ -9,4 +9,4 @@ generates the linear systems; the device assembly and Newton loop
 """
 
 from ._lib import FsiError, lib  # noqa: F401
-from .solver import MG, Assembly, Problem, Server, krylov_opts, mg_opts, stream_read_gbps  # noqa: F401
+from .solver import MG, Assembly, Problem, Server, fmg, krylov_opts, mg_opts, stream_read_gbps  # noqa: F401

@@ -357,6 +357,12 @@ __global__ void k_dirichlet_rows(const int *rows, const int *diag, int n, const 
   r[i] = y[i] - gval[t];
   jval[diag[t]] = 1.0;
 }
+// Dirichlet dofs set to their values
+__global__ void k_set_dirichlet(const int *rows, const double *gval, int n, double *y) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[rows[i]] = gval[i];
+}
+
 __global__ void k_neg_free(const double *r, const uint8_t *dir, int n, double *b) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) b[i] = dir[i] ? 0.0 : -r[i];
@@ -529,6 +535,46 @@ static fsi_status newton(Assembly &A, MG &mg, double *y, const fsi_newton_opts &
   return st_out;
 }
 
+// full multigrid: Newton on each mesh, coarsest first, each mesh started from
+// the prolongation of the previous mesh's iterate (relative to a base state
+// that carries the boundary values, when one is given)
+static fsi_status fmg(int nlev, Assembly *const *A, MG *const *M, double *const *y, const double *const *base,
+                      const int32_t *caps, const fsi_newton_opts &no, const fsi_krylov_opts &ko,
+                      fsi_newton_info *info, hipStream_t st) {
+  for (int j = 0; j < nlev; ++j) {
+    if (!A[j] || !M[j] || !y[j] || (base && !base[j])) throw Error(FSI_E_INVALID, "null handle or vector");
+    if (caps && caps[j] < 1) throw Error(FSI_E_INVALID, "a Newton step limit below 1");
+    if (M[j]->lv.back().n != A[j]->v.ndof) throw Error(FSI_E_INVALID, "a handle's finest size is not its assembly's");
+    if (j > 0 && (M[j]->nlevels < 2 || M[j]->lv[M[j]->nlevels - 2].n != A[j - 1]->v.ndof))
+      throw Error(FSI_E_INVALID, "mesh j-1 is not the level below the finest of handle j");
+  }
+  fsi_status out = FSI_NOT_CONVERGED;
+  for (int j = 0; j < nlev; ++j) {
+    Assembly &a = *A[j];
+    MG &mg = *M[j];
+    if (j > 0) {
+      const Level &F = mg.lv.back();
+      const int nc = A[j - 1]->v.ndof;
+      if (base) launch_axpy_f64(nc, -1.0, base[j - 1], y[j - 1], st);
+      launch_spmv(F.P.v64(), y[j - 1], (const double *)nullptr, y[j], kSpmvSet, F.P.lpr, st);
+      if (base) {
+        launch_axpy_f64(nc, 1.0, base[j - 1], y[j - 1], st);
+        launch_axpy_f64(a.v.ndof, 1.0, base[j], y[j], st);
+      }
+      if (a.ndir) k_set_dirichlet<<<(a.ndir + 255) / 256, 256, 0, st>>>(a.d_dir_rows, a.d_dir_val, a.ndir, y[j]);
+      hip_check(hipGetLastError(), "fmg prolongation");
+    }
+    fsi_newton_opts o = no;
+    if (caps) o.max_newton = caps[j];
+    fsi_newton_info inf{};
+    const fsi_status s = newton(a, mg, y[j], o, ko, &inf, st);
+    if (info) info[j] = inf;
+    if (s < 0) return s;
+    if (j + 1 == nlev) out = s;
+  }
+  return out;
+}
+
 }  // namespace fsi
 
 using namespace fsi;
@@ -568,6 +614,22 @@ fsi_status fsi_newton_solve(struct fsi_assembly *h, struct fsi_mg *mh, double *y
     if (!A || !mg || !y_dev || !nopts || !kopts) throw Error(FSI_E_INVALID, "null argument");
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
     return newton(*A, *mg, y_dev, *nopts, *kopts, info, st);
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+fsi_status fsi_fmg_solve(int32_t nlev, struct fsi_assembly *const *a, struct fsi_mg *const *mg,
+                         double *const *y_dev, const double *const *base_dev, const int32_t *max_newton,
+                         const fsi_newton_opts *nopts, const fsi_krylov_opts *kopts, fsi_newton_info *info,
+                         void *hip_stream) {
+  try {
+    if (nlev < 1 || !a || !mg || !y_dev || !nopts || !kopts) throw Error(FSI_E_INVALID, "null argument or nlev < 1");
+    if (nopts->max_newton < 1 || !(nopts->tol > 0.0)) throw Error(FSI_E_INVALID, "invalid Newton options");
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : (mg[0] ? reinterpret_cast<MG *>(mg[0])->own_stream : nullptr);
+    return fmg(nlev, reinterpret_cast<Assembly *const *>(a), reinterpret_cast<MG *const *>(mg), y_dev, base_dev,
+               max_newton, *nopts, *kopts, info, st);
   } catch (const Error &e) {
     set_error(e.msg);
     return e.code;

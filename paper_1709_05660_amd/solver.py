@@ -423,3 +423,40 @@ class Assembly:
             self.close()
         except Exception:
             pass
+
+
+def fmg(assemblies, mgs, y0, bases=None, max_newton=20, tol=1e-8, rtol=1e-8, restart=30, maxit=1000):
+    """Full multigrid on the device (fsi_fmg_solve): Newton on each nested
+    mesh, coarsest first, each started from the prolongation of the mesh
+    below.  assemblies, mgs: one per mesh; y0: the coarsest mesh's initial
+    iterate (updated in place); bases: None or one state per mesh holding
+    its Dirichlet values (the transfer is then base_j + P (y_{j-1} -
+    base_{j-1})); max_newton: one limit for every mesh or a list per mesh.
+    Returns (iterates per mesh, infos per mesh, status: 0 when the finest
+    mesh converged, 1 otherwise)."""
+    import torch
+    n = len(assemblies)
+    if n < 1 or len(mgs) != n:
+        raise ValueError("one multigrid handle per assembly, at least one mesh")
+    if bases is not None and len(bases) != n:
+        raise ValueError("one base state per mesh")
+    caps = list(max_newton) if isinstance(max_newton, (list, tuple)) else [int(max_newton)] * n
+    if len(caps) != n:
+        raise ValueError("one Newton step limit per mesh")
+    ys = [y0] + [torch.empty(a.n, dtype=torch.float64, device="cuda") for a in assemblies[1:]]
+    ah = (C.c_void_p * n)(*[a.h for a in assemblies])
+    mh = (C.c_void_p * n)(*[m.h for m in mgs])
+    yh = (C.c_void_p * n)(*[_vec(y, a.n, "y") for y, a in zip(ys, assemblies)])
+    bh = None
+    if bases is not None:
+        bh = C.cast((C.c_void_p * n)(*[_vec(b, a.n, "base") for b, a in zip(bases, assemblies)]),
+                    C.POINTER(C.c_void_p))
+    ch = (C.c_int32 * n)(*caps)
+    no = L.NewtonOpts(int(max(caps)), float(tol))
+    ko = krylov_opts(restart, rtol, maxit)
+    infos = (L.NewtonInfo * n)()
+    st = L.lib().fsi_fmg_solve(n, C.cast(ah, C.POINTER(C.c_void_p)), C.cast(mh, C.POINTER(C.c_void_p)),
+                               C.cast(yh, C.POINTER(C.c_void_p)), bh, ch, C.byref(no), C.byref(ko), infos,
+                               _stream())
+    L.check(st, "fmg")
+    return ys, [i.as_dict() for i in infos], st

@@ -311,3 +311,20 @@ def test_dirichlet_flags_are_validated_on_the_host():
         flags[d] = 0
         J.nrows, J.rowptr, J.colind, J.val, J.nnz = saved
     assert st == -1 and "holds Dirichlet dof" in msg
+
+
+def test_newton_and_fmg_reject_bad_arguments_on_the_host():
+    """The Newton and full-multigrid entry points check their arguments
+    before any device call (FSI_E_INVALID)."""
+    from paper_1709_05660_amd import _lib
+    L = _lib.lib()
+    no = _lib.NewtonOpts(5, 1e-8)
+    ko = _lib.KrylovOpts()
+    st = L.fsi_fmg_solve(0, None, None, None, None, None, C.byref(no), C.byref(ko), None, None)
+    assert st == -1 and "nlev" in L.fsi_last_error().decode()
+    st = L.fsi_fmg_solve(2, None, None, None, None, None, C.byref(no), C.byref(ko), None, None)
+    assert st == -1
+    st = L.fsi_newton_solve(None, None, None, C.byref(no), C.byref(ko), None, None)
+    assert st == -1
+    st = L.fsi_assembly_create(None, None, None, None)
+    assert st == -1
