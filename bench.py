@@ -203,6 +203,8 @@ def three_d_leg(args):
                          "solve_ms": round(infos[-1]["solve_ms"], 3),
                          "vcycle_ms": round(vcycle_times(mg, p.n, stream, 20), 4),
                          "vcycle_ms_cold": round(vcycle_cold_ms(mg, p.n, stream, 10), 4)}
+            if prec == "fp64":
+                res["spmv_finest"] = spmv_roofline(mg, p)
             mg.close()
     return res
 
@@ -509,6 +511,7 @@ def gpu_leg(args):
             for _ in range(3):
                 dst.copy_(src)
             torch.cuda.synchronize()
+        out["spmv_finest"] = spmv_roofline(mg, p)
         mg.close()
         # ---- mixed precision forms: FP32 V-cycle, blocks inverted in FP32 on
         # the matrix cores and stored in 16 bits (or FP32), FP64 Krylov, true
@@ -527,6 +530,8 @@ def gpu_leg(args):
                 mgm.profile_start()
                 mgm.refactor()
                 _, _, gm, gc = mgm.profile_stop()
+                if key == "mixed" and q in ("bf16", "fp16"):
+                    out["roofline_16bit_schwarz"] = ras16_roofline(mgm, p, fine, b)
                 out["solutions"][key] = x.cpu().numpy()
                 out[key] = {
                     "precision": q, "policy": kw or "every block alike",
@@ -540,6 +545,87 @@ def gpu_leg(args):
                 mgm.close()
     out["n"] = p.n
     return out
+
+
+def ras16_roofline(mg, p, fine, b):
+    """The finest-level Schwarz kernel with 16-bit owned rows (four columns
+    per 8-byte load): event-timed inside FGMRES solves (warm: the 55 MB of
+    factors may stay in the 256 MB last-level cache between launches) and
+    alone after a 512 MiB read that evicts them (cold).  Algorithmic bytes:
+    2 per stored entry, the gathered residual (index, value, column scale)
+    and the owned corrections (index, row scale, read, write)."""
+    import torch
+
+    from paper_1709_05660_amd import stream_read_gbps
+    bpl = 2 * fine["sum_om"] + 12 * fine["sum_m"] + 16 * fine["n_owned"]
+    lv = p.nlevels - 1
+    mg.profile_start()
+    for _ in range(2):
+        mg.fgmres(b, rtol=1e-8)
+    wms, wcnt, _, _ = mg.profile_stop()
+    flush = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+    r = torch.randn(p.n, dtype=torch.float64, device="cuda")
+    mg.apply(lv, 6, r)
+    mg.profile_start()
+    for _ in range(20):
+        flush.sum()
+        mg.apply(lv, 6, r)
+    cms, ccnt, _, _ = mg.profile_stop()
+    torch.cuda.synchronize()
+    res = {"bound": "hbm", "kernel": "k_ras<uint16> (finest level, 16-bit owned rows)", "bytes_per_launch": int(bpl),
+           "peak": 8000.0, "unit": "GB/s"}
+    for tag, ms, cnt in (("warm", wms, wcnt), ("cold", cms, ccnt)):
+        avg = ms / max(cnt, 1)
+        gbs = bpl / (avg * 1e-3) / 1e9 if cnt else 0.0
+        ceil = stream_read_gbps(int(bpl), cold=(tag == "cold"))
+        res[tag] = {"avg_launch_us": round(avg * 1e3, 2), "launches": int(cnt), "achieved": round(gbs, 1),
+                    "frac": round(gbs / 8000.0, 4), "read_ceiling_gb_s": round(ceil, 1),
+                    "frac_of_ceiling": round(gbs / ceil, 4) if ceil else None}
+    res["read_ceiling"] = "fsi_stream_read: plain 16-byte streaming read of the same byte count, best of 20 (cold: each after a 512 MiB read)"
+    return res
+
+
+def spmv_roofline(mg, p):
+    """The finest-level Jacobian SpMV (y = J x, the autotuned lanes per row),
+    each launch between its own events: warm (back to back) and cold (each
+    after a 512 MiB read that evicts the matrix), beside a plain streaming
+    read of the same byte count.  Algorithmic bytes: 12 per nonzero (value
+    and column), the row offsets, x and y."""
+    import torch
+
+    from paper_1709_05660_amd import stream_read_gbps
+    lv = p.nlevels - 1
+    info = mg.level_info(lv)
+    n, nnz = info["n"], info["nnz"]
+    bpl = 12 * nnz + 4 * (n + 1) + 16 * n
+    x = torch.randn(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    flush = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    res = {"bound": "hbm", "kernel": "k_spmv<double> (finest-level J)", "unknowns": n, "nnz": nnz,
+           "bytes_per_launch": int(bpl), "peak": 8000.0, "unit": "GB/s"}
+    for tag in ("warm", "cold"):
+        ts = []
+        for k in range(23):
+            if tag == "cold":
+                flush.sum()
+            else:
+                # keep the device busy while the host enqueues the events and
+                # the launch, so that host time never falls between the events
+                torch.cuda._sleep(200000)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            mg.apply(lv, 0, x, y=y)
+            e1.record(st)
+            e1.synchronize()
+            if k >= 3:
+                ts.append(e0.elapsed_time(e1))
+        us = float(np.median(ts)) * 1e3
+        gbs = bpl / (us * 1e-6) / 1e9
+        ceil = stream_read_gbps(int(bpl), cold=(tag == "cold"))
+        res[tag] = {"median_launch_us": round(us, 2), "achieved": round(gbs, 1), "frac": round(gbs / 8000.0, 4),
+                    "read_ceiling_gb_s": round(ceil, 1), "frac_of_ceiling": round(gbs / ceil, 4)}
+    return res
 
 
 def serve_leg(args):
@@ -811,6 +897,9 @@ def main():
                      "choices": g["autotune_choices"]},
         "setup_with_upload_ms": round(g["setup_with_upload_ms"], 1),
     }
+    line["spmv_finest"] = g["spmv_finest"]
+    if "roofline_16bit_schwarz" in g:
+        line["roofline_16bit_schwarz"] = g["roofline_16bit_schwarz"]
     if "mixed" in g:
         line["mixed"] = {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in g["mixed"].items()}
     for key in sorted(k for k in g if k.startswith("mixed_")):

@@ -50,6 +50,10 @@ struct Level {
       *d_unowned = nullptr;
   int n_unowned = 0;
   int64_t *d_pdof_off = nullptr, *d_woff = nullptr, *d_boff = nullptr;
+  // 16-bit owned rows in groups of four columns (columns padded to m4 = a
+  // multiple of 4): per patch offsets, and the storage's length
+  int64_t *d_woff16 = nullptr;
+  int64_t woff16_total = 0;
   // block extraction map (launch_extract_map): nslots (entry, position) pairs
   int64_t ext_nslots = 0;
   int *d_ext_src = nullptr, *d_ext_dst = nullptr;

@@ -94,14 +94,17 @@ void gj_coarse(double *A, int nf, int64_t ld, const CoarseSplit &cs, double *C0,
 // Owned rows of Binv_k, column-major per (patch, 64 owned rows) task: task
 // (k, r0) with nr = min(64, o_k - r0) rows holds entry (c, r) at
 // W[woff_k + r0 m_k + c nr + r - r0]; optional FP32/16-bit copies; the
-// inverted blocks in FP64 or FP32 (TB)
+// inverted blocks in FP64 or FP32 (TB).  With woff16, the 16-bit copy groups
+// four columns per row instead: with m4 = m_k rounded up to a multiple of 4,
+// entry (c, r) at W16[woff16_k + r0 m4 + (c / 4) 4 nr + 4 (r - r0) + c % 4]
+// (the padding columns are never written: the caller zeroes them once)
 template <typename TB>
 void launch_pack_owned(const TB *blocks, const int64_t *boff, const int *pm, const int *po,
                        const int64_t *woff, const int *own_off, const int *own_local,
                        const int *task_patch, const int *task_row0, int ntask, double *W64,
                        float *W32, uint16_t *W16, int w16_kind, float *wscale,
                        const int64_t *pdof_off, const float *cscale, const int *perm,
-                       hipStream_t st);
+                       const int64_t *woff16, hipStream_t st);
 // 16-bit storage: per-column scales of the owned rows of every block inverse
 template <typename TB>
 void launch_colscale(const TB *blocks, const int64_t *boff, const int *pm, const int *po,
@@ -116,7 +119,7 @@ struct RasView {
   int ntask;
   const int *task_patch, *task_row0;
   const int *pm, *po;
-  const int64_t *pdof_off, *woff;
+  const int64_t *pdof_off, *woff;   // 16-bit storage: the grouped layout's offsets (woff16)
   const int *dof, *out_off, *out_idx;
   const float *cscale;   // 16-bit storage: column scales (per patch dof), else null
   const int *unowned;    // the dofs no patch owns (nunowned of them)

@@ -289,7 +289,7 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
   L.h_kind.assign(np, 0);
   if (P.kind) L.h_kind.assign(P.kind, P.kind + np);
   std::vector<int> pm(np), po(np), out_off(np + 1, 0), own_local, out_idx, task_patch, task_row0;
-  std::vector<int64_t> pdof_off(np), woff(np + 1, 0), boff(np + 1, 0);
+  std::vector<int64_t> pdof_off(np), woff(np + 1, 0), woff16(np + 1, 0), boff(np + 1, 0);
   std::vector<int> row_patch, row_local;
   // solid blocks (kind 1) apart when the options give them their own
   // storage: their owned rows in FP32 (task list _s, offsets into Ws), or,
@@ -300,7 +300,7 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
   std::vector<int> task_patch_s, task_row0_s, po_full(np, 0), full_off(np + 1, 0), full_local, ftask_patch,
       ftask_row0, ref_patch;
   std::vector<int64_t> woff_full(np, 0);
-  int64_t wmain = 0, wsolid = 0, wfull = 0;
+  int64_t wmain = 0, wsolid = 0, wfull = 0, wmain16 = 0;
   L.mmax = 0;
   L.sum_m = L.sum_m2 = L.sum_om = 0;
   // fluid blocks with ILU(0) factors (fluid_ilu): no explicit inverse
@@ -325,7 +325,9 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
     // woff[k]: offset of the patch's owned rows in its class's storage
     int64_t &wcls = solid ? wsolid : wmain;
     woff[k] = wcls;
+    woff16[k] = wmain16;
     if (!is_ilu) wcls += (int64_t)o * pm[k];
+    if (!is_ilu && !solid) wmain16 += (int64_t)o * ((pm[k] + 3) & ~3);
     boff[k + 1] = boff[k] + (int64_t)pm[k] * pm[k];
     for (int i = 0; i < pm[k]; ++i) {
       row_patch.push_back(k);
@@ -355,6 +357,7 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
     if (!is_ilu) L.sum_om += (int64_t)o * pm[k];
   }
   woff[np] = wmain;
+  woff16[np] = wmain16;
   L.total_owned = out_off[np];
   std::vector<char> is_owned(L.n, 0);
   for (int d : out_idx) is_owned[d] = 1;
@@ -368,6 +371,7 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
   L.d_po = dupload(po.data(), np, own, st);
   L.d_pdof_off = dupload(pdof_off.data(), np, own, st);
   L.d_woff = dupload(woff.data(), np + 1, own, st);
+  L.d_woff16 = dupload(woff16.data(), np + 1, own, st);
   L.d_boff = dupload(boff.data(), np + 1, own, st);
   L.d_dof = dupload(P.dof, P.ptr[np], own, st);
   L.d_out_off = dupload(out_off.data(), np + 1, own, st);
@@ -380,6 +384,7 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
   L.d_unowned = dupload(unowned.data(), (int64_t)unowned.size(), own, st);
   L.boff_total = boff[np];
   L.woff_total = wmain;
+  L.woff16_total = wmain16;
   L.woff_solid = wsolid;
   L.h_boff = boff;
   L.ntask_s = (int)task_patch_s.size();
@@ -657,6 +662,9 @@ static void ilu_factor_level(MG &mg, Level &L, int l, T *blocks, hipStream_t st)
   hip_check(hipGetLastError(), "ilu launch");
 }
 
+// the 16-bit owned rows' view: the grouped layout's offsets
+static RasView ras_view16(const Level &L);
+
 RasView ras_view(const Level &L) {
   RasView v;
   v.ntask = L.ntask;
@@ -675,6 +683,12 @@ RasView ras_view(const Level &L) {
   return v;
 }
 
+static RasView ras_view16(const Level &L) {
+  RasView v = ras_view(L);
+  v.woff = L.d_woff16;
+  return v;
+}
+
 static void free_list(DevList &owned) {
   while (!owned.v.empty()) free_one(owned, owned.v.size() - 1);
 }
@@ -690,7 +704,10 @@ static void pack_level_t(MG &mg, Level &L, const TB *B, hipStream_t st) {
     if (!L.W32) L.W32 = dalloc<float>(L.woff_total, mg.owned);
   } else {
     if (!L.W16) {
-      L.W16 = dalloc<uint16_t>(L.woff_total, mg.owned);
+      // the grouped layout's padding columns stay zero (the packer never writes them)
+      L.W16 = dalloc<uint16_t>(std::max<int64_t>(L.woff16_total, 1), mg.owned);
+      hip_check(hipMemsetAsync(L.W16, 0, sizeof(uint16_t) * std::max<int64_t>(L.woff16_total, 1), st),
+                "clear 16-bit storage");
       L.Wscale = dalloc<float>(L.total_owned, mg.owned);
       L.Cscale = dalloc<float>(L.sum_m, mg.owned);
     }
@@ -708,13 +725,13 @@ static void pack_level_t(MG &mg, Level &L, const TB *B, hipStream_t st) {
   }
   launch_pack_owned(B, L.d_boff, L.d_pm, L.d_po, L.d_woff, L.d_out_off, L.d_own_local,
                     L.d_task_patch, L.d_task_row0, L.ntask, L.W64, L.W32, L.W16, L.w16_kind,
-                    L.Wscale, L.d_pdof_off, L.Cscale, mg.gj_perm + L.pm_base, st);
+                    L.Wscale, L.d_pdof_off, L.Cscale, mg.gj_perm + L.pm_base, L.d_woff16, st);
   if (L.ntask_s) {   // solid blocks' owned rows in FP32
     if (!L.Ws) L.Ws = dalloc<float>(L.woff_solid, mg.owned);
     launch_pack_owned(B, L.d_boff, L.d_pm, L.d_po, L.d_woff, L.d_out_off, L.d_own_local,
                       L.d_task_patch_s, L.d_task_row0_s, L.ntask_s, (double *)nullptr, L.Ws,
                       (uint16_t *)nullptr, 0, (float *)nullptr, L.d_pdof_off, (const float *)nullptr,
-                      mg.gj_perm + L.pm_base, st);
+                      mg.gj_perm + L.pm_base, (const int64_t *)nullptr, st);
   }
   if (L.nftask) {    // refined solid blocks: every row of the inverse, FP32 or 16-bit
     const bool full16 = prec != FSI_PREC_MIXED_FP32 && mg.opts.solid_precision != FSI_PREC_MIXED_FP32;
@@ -729,7 +746,7 @@ static void pack_level_t(MG &mg, Level &L, const TB *B, hipStream_t st) {
     launch_pack_owned(B, L.d_boff, L.d_pm, L.d_po_full, L.d_woff_full, L.d_full_off, L.d_full_local,
                       L.d_ftask_patch, L.d_ftask_row0, L.nftask, (double *)nullptr, full16 ? nullptr : L.Wfull32,
                       full16 ? L.Wfull16 : nullptr, L.w16_kind, L.Wscale_full, L.d_pdof_off,
-                      full16 ? L.Cscale : nullptr, mg.gj_perm + L.pm_base, st);
+                      full16 ? L.Cscale : nullptr, mg.gj_perm + L.pm_base, (const int64_t *)nullptr, st);
   }
   hip_check(hipGetLastError(), "pack launch");
 }
@@ -905,7 +922,7 @@ static void ras32(MG &mg, Level &L, const float *s, float *e, bool add, hipStrea
     launch_ras_f32(ras_view(L), L.W32, s, e, omega, &L == &mg.lv.back(), add, st,
                    ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
   else
-    launch_ras_16(ras_view(L), L.W16, L.w16_kind, L.Wscale, s, e, omega,
+    launch_ras_16(ras_view16(L), L.W16, L.w16_kind, L.Wscale, s, e, omega,
                   &L == &mg.lv.back(), add, st, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
   // the solid blocks apart: FP32 owned rows, or refined local solves
   if (L.ntask_s) launch_ras_f32(ras_view_solid(L), L.Ws, s, e, omega, false, add, st);
@@ -1076,7 +1093,7 @@ static void batch_ras(const std::vector<BatchLevel<float>> &a, const std::vector
     if (L.W32)
       i32.push_back(RasItem<float, float>{ras_view(L), L.W32, 0, nullptr, s[i], e[i]});
     else
-      i16.push_back(RasItem<uint16_t, float>{ras_view(L), L.W16, L.w16_kind, L.Wscale, s[i], e[i]});
+      i16.push_back(RasItem<uint16_t, float>{ras_view16(L), L.W16, L.w16_kind, L.Wscale, s[i], e[i]});
   }
   const float omega = (float)a[0].mg->opts.omega;
   if (!i32.empty()) launch_ras_batch_f32(i32.data(), (int)i32.size(), omega, add, st);

@@ -41,17 +41,22 @@ def _vec(t, n, name):
     return C.c_void_p(t.data_ptr())
 
 
-def stream_read_gbps(nbytes, reps=20):
+def stream_read_gbps(nbytes, reps=20, cold=False):
     """Best rate (GB/s) of the library's plain streaming-read kernel over
     nbytes of device memory, timed with events on the current stream: the
-    read rate the HBM-bound kernels are compared with."""
+    read rate the HBM-bound kernels are compared with.  cold: each read
+    follows a 512 MiB read of another buffer (outside the events), which
+    evicts the data from the last-level cache."""
     import torch
     n = (nbytes // 16) * 2
     x = torch.ones(n, dtype=torch.float64, device="cuda")
     out = torch.empty(L.lib().fsi_stream_read_blocks(), dtype=torch.float64, device="cuda")
+    flush = torch.ones(64 << 20, dtype=torch.float64, device="cuda") if cold else None
     st = torch.cuda.current_stream()
     best = None
     for r in range(reps + 3):
+        if cold:
+            flush.sum()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(st)
