@@ -192,7 +192,7 @@ struct IluView {
   const int64_t *moff;
   const int *unowned;
   int nunowned;
-  int max_entries;   // L + U entries of the largest block (LDS staging when they fit)
+  int max_entries;   // entries of the largest single factor (L or U) of any block (LDS staging when they fit)
 };
 // in place on the dense blocks B_k (row-major at boff[k]; FP64 or FP32),
 // zero off the pattern on entry; status[status_base + patch] = 0, or 1 + the

@@ -987,67 +987,77 @@ void launch_ilu_gather(const T *blocks, const int *pos, int64_t n, V *out, hipSt
 template void launch_ilu_gather<double, double>(const double *, const int *, int64_t, double *, hipStream_t);
 template void launch_ilu_gather<float, float>(const float *, const int *, int64_t, float *, hipStream_t);
 
-// Forward then backward substitution of one ILU block per wave, level by
-// level: the rows of a level depend only on earlier levels, so eight rows at
-// a time run side by side, eight lanes per row summing its products (in a
-// fixed order: lane-strided partial sums, then a fixed butterfly), with one
-// wave barrier per level.  The block's row offsets, columns and values are
-// staged in LDS first (STAGE, when they fit), else read from memory.
+// Forward then backward substitution of one ILU block per workgroup (256
+// threads), level by level: the rows of a level depend only on earlier
+// levels, so up to 32 rows of a level run side by side, eight lanes per row
+// summing its products (in a fixed order: lane-strided partial sums, then a
+// fixed butterfly), with one barrier per level (measured: the sweeps in one
+// wave with wave-level ordering instead, eight rows at a time, were slower).
+// STAGE: each sweep's factor (L for the forward sweep, then U for the
+// backward one: values and 16-bit columns) is first copied to LDS by the
+// whole workgroup, four loads in flight per thread; else the factors are read
+// from memory.
 template <typename V, bool STAGE>
-__global__ __launch_bounds__(64) void k_ilu_apply(IluView v, const V *__restrict__ lval, const V *__restrict__ uval,
-                                                  const V *__restrict__ udiag, const V *__restrict__ s,
-                                                  V *__restrict__ e, V omega, int add, int clear) {
+__global__ __launch_bounds__(256) void k_ilu_apply(IluView v, const V *__restrict__ lval, const V *__restrict__ uval,
+                                                   const V *__restrict__ udiag, const V *__restrict__ s,
+                                                   V *__restrict__ e, V omega, int add, int clear) {
   extern __shared__ __align__(16) unsigned char ilu_lds[];
   __shared__ V y[kMaxPatch];
   __shared__ V dg[kMaxPatch];
   __shared__ int lp[kMaxPatch + 1], upp[kMaxPatch + 1];
   __shared__ int16_t fr[kMaxPatch], br[kMaxPatch];
   __shared__ int16_t fl[kMaxPatch + 1], bl[kMaxPatch + 1];   // level starts (local)
-  const int b = blockIdx.x, lane = threadIdx.x;
+  const int b = blockIdx.x, tid = threadIdx.x;
   const int k = v.patch[b], m = v.pm[k], r0 = v.row0[b];
   const int *d = v.dof + v.pdof_off[k];
   const int la = v.lptr[r0], ua = v.uptr[r0];
   const int f0 = v.flev_off[b], nf = v.flev_off[b + 1] - f0;
   const int b0 = v.blev_off[b], nb = v.blev_off[b + 1] - b0;
-  for (int t = lane; t <= nf; t += 64) fl[t] = (int16_t)(v.flev[f0 + t] - r0);
-  for (int t = lane; t <= nb; t += 64) bl[t] = (int16_t)(v.blev[b0 + t] - r0);
-  for (int c = lane; c < m; c += 64) {
+  for (int t = tid; t <= nf; t += 256) fl[t] = (int16_t)(v.flev[f0 + t] - r0);
+  for (int t = tid; t <= nb; t += 256) bl[t] = (int16_t)(v.blev[b0 + t] - r0);
+  for (int c = tid; c < m; c += 256) {
     y[c] = s[d[c]];
     dg[c] = udiag[r0 + c];
     fr[c] = v.frow[r0 + c];
     br[c] = v.brow[r0 + c];
   }
-  for (int c = lane; c <= m; c += 64) {
+  for (int c = tid; c <= m; c += 256) {
     lp[c] = v.lptr[r0 + c] - la;
     upp[c] = v.uptr[r0 + c] - ua;
   }
   if (clear && !add)
-    for (int i = b * 64 + lane; i < v.nunowned; i += v.nblk * 64) e[v.unowned[i]] = (V)0;
+    for (int i = b * 256 + tid; i < v.nunowned; i += v.nblk * 256) e[v.unowned[i]] = (V)0;
   const V *Lv = lval + la, *Uv = uval + ua;
   const int16_t *Lc = v.lcol + la, *Uc = v.ucol + ua;
-  if constexpr (STAGE) {
-    // L values, U values, then the 16-bit columns
-    const int nl = v.lptr[r0 + m] - la, nu = v.uptr[r0 + m] - ua;
-    V *sv = reinterpret_cast<V *>(ilu_lds);
-    int16_t *sc = reinterpret_cast<int16_t *>(sv + nl + nu);
-    for (int q = lane; q < nl; q += 64) {
-      sv[q] = Lv[q];
-      sc[q] = Lc[q];
+  V *sv = reinterpret_cast<V *>(ilu_lds);
+  // one factor's n values and columns into LDS (values, then the columns)
+  auto stage = [&](const V *gv, const int16_t *gc, int n, const V *&lv, const int16_t *&lc) {
+    int16_t *sc = reinterpret_cast<int16_t *>(sv + n);
+    for (int q0 = tid; q0 < n; q0 += 256 * 4) {
+      V a[4];
+      int16_t c[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = min(q0 + 256 * u, n - 1);
+        a[u] = gv[q];
+        c[u] = gc[q];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q0 + 256 * u < n) {
+          sv[q0 + 256 * u] = a[u];
+          sc[q0 + 256 * u] = c[u];
+        }
     }
-    for (int q = lane; q < nu; q += 64) {
-      sv[nl + q] = Uv[q];
-      sc[nl + q] = Uc[q];
-    }
-    Lv = sv;
-    Uv = sv + nl;
-    Lc = sc;
-    Uc = sc + nl;
-  }
+    lv = sv;
+    lc = sc;
+  };
+  if constexpr (STAGE) stage(Lv, Lc, v.lptr[r0 + m] - la, Lv, Lc);
   __syncthreads();
-  const int grp = lane >> 3, sub = lane & 7;
+  const int grp = tid >> 3, sub = tid & 7;
   for (int f = 0; f < nf; ++f) {
     const int a = fl[f], z = fl[f + 1];
-    for (int base = a; base < z; base += 8) {
+    for (int base = a; base < z; base += 32) {
       const int rr = base + grp;
       int row = 0;
       V acc = 0;
@@ -1060,9 +1070,13 @@ __global__ __launch_bounds__(64) void k_ilu_apply(IluView v, const V *__restrict
     }
     __syncthreads();
   }
+  if constexpr (STAGE) {
+    stage(Uv, Uc, v.uptr[r0 + m] - ua, Uv, Uc);   // the forward sweep's reads ended at its last barrier
+    __syncthreads();
+  }
   for (int f = 0; f < nb; ++f) {
     const int a = bl[f], z = bl[f + 1];
-    for (int base = a; base < z; base += 8) {
+    for (int base = a; base < z; base += 32) {
       const int rr = base + grp;
       int row = 0;
       V acc = 0;
@@ -1075,7 +1089,7 @@ __global__ __launch_bounds__(64) void k_ilu_apply(IluView v, const V *__restrict
     }
     __syncthreads();
   }
-  for (int t = v.out_off[k] + lane; t < v.out_off[k + 1]; t += 64) {
+  for (int t = v.out_off[k] + tid; t < v.out_off[k + 1]; t += 256) {
     const int g = v.out_idx[t];
     const V u = omega * y[v.own_local[t]];
     e[g] = add ? e[g] + u : u;
@@ -1085,7 +1099,8 @@ template <typename V>
 void launch_ilu_apply(const IluView &v, const V *lval, const V *uval, const V *udiag, const V *s, V *e,
                       V omega, bool add, bool clear, hipStream_t st) {
   if (v.nblk == 0) return;
-  // staged when the factors fit beside the kernel's static LDS (about 23 KB)
+  // staged when the larger factor of every block fits beside the kernel's
+  // static LDS (about 26 KB in FP64)
   constexpr size_t kStageMax = 128 * 1024;
   const size_t stage = (size_t)v.max_entries * (sizeof(V) + sizeof(int16_t));
   if (stage <= kStageMax) {
@@ -1095,9 +1110,9 @@ void launch_ilu_apply(const IluView &v, const V *lval, const V *uval, const V *u
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kStageMax));
       attr = true;
     }
-    k_ilu_apply<V, true><<<v.nblk, 64, stage, st>>>(v, lval, uval, udiag, s, e, omega, (int)add, (int)clear);
+    k_ilu_apply<V, true><<<v.nblk, 256, stage, st>>>(v, lval, uval, udiag, s, e, omega, (int)add, (int)clear);
   } else {
-    k_ilu_apply<V, false><<<v.nblk, 64, 0, st>>>(v, lval, uval, udiag, s, e, omega, (int)add, (int)clear);
+    k_ilu_apply<V, false><<<v.nblk, 256, 0, st>>>(v, lval, uval, udiag, s, e, omega, (int)add, (int)clear);
   }
 }
 template void launch_ilu_apply<double>(const IluView &, const double *, const double *, const double *,

@@ -533,7 +533,7 @@ static void build_patch_layout(Level &L, const fsi_patches &P, const fsi_csr &J,
       order(flevel, frow, flev, flev_off);
       order(blevel, brow, blev, blev_off);
       nrows += m;
-      maxe = std::max(maxe, (int)(lcol.size() - l0 + ucol.size() - u0));
+      maxe = std::max(maxe, (int)std::max(lcol.size() - l0, ucol.size() - u0));
     }
     flev.push_back(nrows);
     blev.push_back(nrows);
