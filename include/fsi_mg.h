@@ -165,12 +165,16 @@ const char *fsi_last_error(void);
  * the rows selected by R^0_k, and inverts the coarsest operator (its dofs
  * whose row and column hold only the diagonal, the eliminated Dirichlet dofs,
  * by a reciprocal, the others by Gauss-Jordan; the sparsity pattern decides,
- * so a refactor keeps the split).  levels: host array of nlevels views,
- * coarsest first, borrowed for the call; *out receives the handle (NULL on
- * error).  Errors: FSI_E_INVALID (malformed CSR/patch lists, dimension
- * mismatch, owned sets not a partition of the covered dofs, a Dirichlet flag
- * on a non-identity row or inside a patch), FSI_E_SINGULAR (message names
- * level and patch), FSI_E_OOM, FSI_E_DEVICE. */
+ * so a refactor keeps the split).  Blocks of up to 800 dofs are inverted
+ * together in one batched launch; larger ones (up to 6144 dofs, such as the
+ * 3D 64-element patches) one after another, each by a chain of launches over
+ * the whole device; ILU(0) blocks and blocks with refinement sweeps are
+ * limited to 800 dofs.  levels: host array of nlevels views, coarsest first,
+ * borrowed for the call; *out receives the handle (NULL on error).  Errors:
+ * FSI_E_INVALID (malformed CSR/patch lists, a patch above its size limit,
+ * dimension mismatch, owned sets not a partition of the covered dofs, a
+ * Dirichlet flag on a non-identity row or inside a patch), FSI_E_SINGULAR
+ * (message names level and patch), FSI_E_OOM, FSI_E_DEVICE. */
 fsi_status fsi_mg_setup(const fsi_level *levels, int32_t nlevels, const fsi_mg_opts *opts,
                         void *hip_stream, struct fsi_mg **out);
 

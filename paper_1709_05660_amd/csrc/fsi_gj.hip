@@ -992,6 +992,25 @@ void gj_coarse(double *A, int nf, int64_t ld, const CoarseSplit &cs, double *C0,
                                                              cs.rowptr, cs.val, status, C0);
 }
 
+__global__ void k_iota_i32(int *x, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] = i;
+}
+void launch_iota_i32(int *x, int n, hipStream_t st) {
+  if (n > 0) k_iota_i32<<<cdivg(n, 256), 256, 0, st>>>(x, n);
+}
+template <typename TS>
+__global__ void k_copy_block(const TS *__restrict__ src, int m, double *__restrict__ dst, int64_t ld) {
+  const int j = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+  if (j < m) dst[(int64_t)i * ld + j] = (double)src[(int64_t)i * m + j];
+}
+template <typename TS>
+void launch_copy_block(const TS *src, int m, double *dst, int64_t ld, hipStream_t st) {
+  if (m > 0) k_copy_block<TS><<<dim3(cdivg(m, 256), m), 256, 0, st>>>(src, m, dst, ld);
+}
+template void launch_copy_block<double>(const double *, int, double *, int64_t, hipStream_t);
+template void launch_copy_block<float>(const float *, int, double *, int64_t, hipStream_t);
+
 // one wave per row of F, its lanes over the row's entries
 __global__ __launch_bounds__(256) void k_csr_to_dense(int n, int64_t ld, const int *rowptr,
                                                       const int *col, const double *val,

@@ -148,12 +148,27 @@ struct GraphKey {
   bool operator<(const GraphKey &o) const { return r < o.r || (r == o.r && z < o.z); }
 };
 
+// a block above kMaxPatch dofs, inverted on its own by the Gauss-Jordan chain
+struct LargeBlock {
+  int q;            // index in the all-level block tables (status)
+  int m;            // its dofs
+  int64_t boff;     // its offset in the block scratch
+  int64_t poff;     // its offset in the permutation arrays
+};
 struct MG {
   int nlevels = 0;
   int device = 0;                 // HIP device current at setup
   double *static_ws = nullptr;    // that device's static Krylov workspace (fsi_fgmres_solve_noalloc)
   bool mixed = false;
   fsi_mg_opts opts{};
+  // blocks above kMaxPatch dofs (left out of the batched inversion): the
+  // padded FP64 working copy (large_ld columns), the FP64 inverse of the mixed
+  // forms before its cast, the identity dof map and the chain's int work
+  std::vector<LargeBlock> large;
+  int large_mmax = 0;
+  int64_t large_ld = 0;
+  double *large_A = nullptr, *large_C = nullptr;
+  int *large_iota = nullptr, *large_iwork = nullptr;
   std::vector<Level> lv;
   DevList owned;
   hipStream_t own_stream = nullptr;

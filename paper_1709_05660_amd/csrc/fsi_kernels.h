@@ -9,7 +9,8 @@
 namespace fsi {
 
 constexpr int kWave = 64;
-constexpr int kMaxPatch = 800;      // largest Schwarz block handled by one wave's LDS slice
+constexpr int kMaxPatch = 800;      // largest Schwarz block of the batched inversion, ILU and refinement
+constexpr int kMaxLargePatch = 6144;   // larger blocks: one Gauss-Jordan chain each (equal to kMaxCoarse)
 
 // CSR on the device: int32 offsets and columns (sizes checked at upload).
 template <typename T>
@@ -89,6 +90,11 @@ struct CoarseSplit {
 // 1 + failing step (the steps of D follow the nf of F)
 constexpr int kMaxCoarse = 6144;
 void launch_fill_i32(int *x, int n, int v, hipStream_t st);
+// x[i] = i for i < n
+void launch_iota_i32(int *x, int n, hipStream_t st);
+// dst[i ld + j] = (double) src[i m + j] for i, j < m (a block into a padded FP64 copy)
+template <typename TS>
+void launch_copy_block(const TS *src, int m, double *dst, int64_t ld, hipStream_t st);
 void gj_coarse(double *A, int nf, int64_t ld, const CoarseSplit &cs, double *C0, int *status,
                int *iwork, hipStream_t st);
 // Owned rows of Binv_k, column-major per (patch, 64 owned rows) task: task
@@ -110,7 +116,7 @@ template <typename TB>
 void launch_colscale(const TB *blocks, const int64_t *boff, const int *pm, const int *po,
                      const int *own_off, const int *own_local, const int64_t *pdof_off,
                      const int *task_patch, const int *task_row0, int ntask, int64_t total_cols,
-                     float *cscale, const int *perm, hipStream_t st, bool first = true,
+                     float *cscale, const int *perm, int mmax, hipStream_t st, bool first = true,
                      bool last = true);
 
 // ---- smoother (a5): e[out] += omega * W_k s[I_k] for every owned row
@@ -124,6 +130,7 @@ struct RasView {
   const float *cscale;   // 16-bit storage: column scales (per patch dof), else null
   const int *unowned;    // the dofs no patch owns (nunowned of them)
   int nunowned;
+  int mmax;              // the largest block (the gathered vector's LDS, sized at launch)
 };
 // e[owned dofs] (+= when add, else =) omega * (owned rows of B_k^{-1}) s_k; with
 // add false (a zero initial correction) the dofs no patch owns are set to 0,

@@ -366,7 +366,7 @@ __global__ __launch_bounds__(256) void k_colscale(const TB *__restrict__ blocks,
                                                   const int *__restrict__ task_patch,
                                                   const int *__restrict__ task_row0, float *cscale,
                                                   const int *__restrict__ perm) {
-  __shared__ unsigned cmax[kMaxPatch];
+  extern __shared__ unsigned cmax[];   // the largest block's columns (sized at launch)
   const int k = task_patch[blockIdx.x], r0 = task_row0[blockIdx.x];
   const int m = pm[k], nr = min(64, po[k] - r0);
   const int *pk = perm + pdof_off[k];
@@ -391,11 +391,11 @@ template <typename TB>
 void launch_colscale(const TB *blocks, const int64_t *boff, const int *pm, const int *po,
                      const int *own_off, const int *own_local, const int64_t *pdof_off,
                      const int *task_patch, const int *task_row0, int ntask, int64_t total_cols,
-                     float *cscale, const int *perm, hipStream_t st, bool first, bool last) {
+                     float *cscale, const int *perm, int mmax, hipStream_t st, bool first, bool last) {
   if (first) launch_fill_f32(cscale, total_cols, 0.0f, st);
   if (ntask)
-    k_colscale<<<ntask, 256, 0, st>>>(blocks, boff, pm, po, own_off, own_local, pdof_off, task_patch,
-                                      task_row0, cscale, perm);
+    k_colscale<<<ntask, 256, sizeof(unsigned) * mmax, st>>>(blocks, boff, pm, po, own_off, own_local, pdof_off,
+                                                            task_patch, task_row0, cscale, perm);
   if (last) k_scale_fix<<<cdiv(total_cols, 256), 256, 0, st>>>(cscale, total_cols);
 }
 
@@ -502,7 +502,7 @@ void launch_pack_owned(const TB *blocks, const int64_t *boff, const int *pm, con
 #define FSI_PACK_INST(TB)                                                                            \
   template void launch_colscale<TB>(const TB *, const int64_t *, const int *, const int *, const int *, \
                                     const int *, const int64_t *, const int *, const int *, int,       \
-                                    int64_t, float *, const int *, hipStream_t, bool, bool);           \
+                                    int64_t, float *, const int *, int, hipStream_t, bool, bool);      \
   template void launch_pack_owned<TB>(const TB *, const int64_t *, const int *, const int *,           \
                                       const int64_t *, const int *, const int *, const int *,          \
                                       const int *, int, double *, float *, uint16_t *, int, float *,   \
@@ -555,7 +555,8 @@ template <int KIND, int NWV, int CH = 8>
 __device__ __forceinline__ void ras_body16(int task, const RasView &v, const uint16_t *__restrict__ W,
                                            const float *__restrict__ wscale, const float *__restrict__ s,
                                            float *__restrict__ e, float omega, int add) {
-  __shared__ __align__(16) float xs[kMaxPatch];
+  extern __shared__ __align__(16) unsigned char ras_lds[];
+  float *xs = reinterpret_cast<float *>(ras_lds);   // the patch's m4 columns (sized at launch)
   __shared__ float red[NWV - 1][64];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -624,7 +625,8 @@ __device__ __forceinline__ void ras_body(int task, const RasView &v, const WT *_
                                          int w16_kind, const float *__restrict__ wscale,
                                          const VT *__restrict__ s, VT *__restrict__ e, AT omega,
                                          int add) {
-  __shared__ AT xs[kMaxPatch];
+  extern __shared__ __align__(16) unsigned char ras_lds[];
+  AT *xs = reinterpret_cast<AT *>(ras_lds);   // the patch's m columns (sized at launch)
   __shared__ AT red[NWV - 1][64];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -833,16 +835,23 @@ void launch_ras_refine(const RefineView &v, const float *W32, const uint16_t *W1
 // own start and end (hipExtLaunchKernelGGL), not around its launch
 static int ras_waves(int ntask) { return ntask >= 1024 ? 4 : (ntask >= 256 ? 8 : 16); }
 
+// dynamic LDS of a Schwarz launch: the gathered vector of the largest block
+// (16-bit storage: padded to a multiple of 4 columns)
+template <typename AT>
+static size_t ras_lds_bytes(int mmax) {
+  return sizeof(AT) * (size_t)((std::max(mmax, 1) + 3) & ~3);
+}
 template <typename WT, typename VT, typename AT, bool IS16, int NWV>
 static void launch_ras_nw(const RasView &v, const WT *W, int w16_kind, const float *wscale,
                           const VT *s, VT *e, AT omega, bool finest, bool add, hipStream_t st,
                           hipEvent_t ev0, hipEvent_t ev1) {
+  const size_t lds = ras_lds_bytes<AT>(v.mmax);
   if (finest)
-    hipExtLaunchKernelGGL(k_ras<WT, VT, AT, IS16, 1, NWV>, dim3(v.ntask), dim3(64 * NWV), 0, st,
+    hipExtLaunchKernelGGL(k_ras<WT, VT, AT, IS16, 1, NWV>, dim3(v.ntask), dim3(64 * NWV), lds, st,
                           ev0, ev1, 0, v, W, w16_kind, wscale, s, e, omega, (int)add);
   else
-    k_ras<WT, VT, AT, IS16, 0, NWV><<<v.ntask, 64 * NWV, 0, st>>>(v, W, w16_kind, wscale, s, e,
-                                                                 omega, (int)add);
+    k_ras<WT, VT, AT, IS16, 0, NWV><<<v.ntask, 64 * NWV, lds, st>>>(v, W, w16_kind, wscale, s, e,
+                                                                   omega, (int)add);
 }
 template <typename WT, typename VT, typename AT, bool IS16>
 static void launch_ras_any(const RasView &v, const WT *W, int w16_kind, const float *wscale,
@@ -889,12 +898,15 @@ static void launch_ras_batch_t(const RasItem<WT, VT> *items, int count, AT omega
     auto flush = [&] {
       const int grid = B.count ? B.blk0[B.count] : 0;
       if (grid > 0) {
+        int mmax = 1;
+        for (int q = 0; q < B.count; ++q) mmax = std::max(mmax, B.it[q].v.mmax);
+        const size_t lds = ras_lds_bytes<AT>(mmax);
         if (nw == 4)
-          k_ras_batch<WT, VT, AT, IS16, 4><<<grid, 256, 0, st>>>(B, omega, (int)add);
+          k_ras_batch<WT, VT, AT, IS16, 4><<<grid, 256, lds, st>>>(B, omega, (int)add);
         else if (nw == 8)
-          k_ras_batch<WT, VT, AT, IS16, 8><<<grid, 512, 0, st>>>(B, omega, (int)add);
+          k_ras_batch<WT, VT, AT, IS16, 8><<<grid, 512, lds, st>>>(B, omega, (int)add);
         else
-          k_ras_batch<WT, VT, AT, IS16, 16><<<grid, 1024, 0, st>>>(B, omega, (int)add);
+          k_ras_batch<WT, VT, AT, IS16, 16><<<grid, 1024, lds, st>>>(B, omega, (int)add);
       }
       B.count = 0;
     };

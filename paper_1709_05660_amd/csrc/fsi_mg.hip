@@ -92,7 +92,7 @@ static void validate_patches(const fsi_patches &P, int64_t n, int lev) {
   for (int k = 0; k < P.npatch; ++k) {
     const int64_t a = P.ptr[k], b = P.ptr[k + 1];
     if (b <= a) fail("empty patch", k);
-    if (b - a > kMaxPatch) fail("patch larger than the supported block size", k);
+    if (b - a > kMaxLargePatch) fail("patch larger than the supported block size (6144 dofs)", k);
     for (int64_t p = a; p < b; ++p) {
       const int32_t d = P.dof[p];
       if (d < 0 || d >= n) fail("dof out of range", k);
@@ -680,6 +680,7 @@ RasView ras_view(const Level &L) {
   v.cscale = L.Cscale;
   v.unowned = L.d_unowned;
   v.nunowned = L.n_unowned;
+  v.mmax = L.mmax;
   return v;
 }
 
@@ -717,11 +718,11 @@ static void pack_level_t(MG &mg, Level &L, const TB *B, hipStream_t st) {
     const bool full16 = L.nftask && mg.opts.solid_precision != FSI_PREC_MIXED_FP32;
     launch_colscale(B, L.d_boff, L.d_pm, L.d_po, L.d_out_off, L.d_own_local, L.d_pdof_off,
                     L.d_task_patch, L.d_task_row0, L.ntask, L.sum_m, L.Cscale, mg.gj_perm + L.pm_base,
-                    st, true, !full16);
+                    L.mmax, st, true, !full16);
     if (full16)
       launch_colscale(B, L.d_boff, L.d_pm, L.d_po_full, L.d_full_off, L.d_full_local, L.d_pdof_off,
                       L.d_ftask_patch, L.d_ftask_row0, L.nftask, L.sum_m, L.Cscale,
-                      mg.gj_perm + L.pm_base, st, false, true);
+                      mg.gj_perm + L.pm_base, L.mmax, st, false, true);
   }
   launch_pack_owned(B, L.d_boff, L.d_pm, L.d_po, L.d_woff, L.d_out_off, L.d_own_local,
                     L.d_task_patch, L.d_task_row0, L.ntask, L.W64, L.W32, L.W16, L.w16_kind,
@@ -811,6 +812,31 @@ static void invert_blocks(MG &mg, int variant, hipStream_t st, hipEvent_t ev0, h
                       ev1);
 }
 
+// the blocks above kMaxPatch dofs, one after another: a padded FP64 copy,
+// the Gauss-Jordan chain (the inverse written un-permuted, row-major, straight
+// into the block, or through an FP64 buffer for the FP32 working matrices of
+// the mixed forms), identity permutations for the packing.  Runs after the
+// batched launch, which wrote these blocks' statuses as 0.
+static void invert_large(MG &mg, hipStream_t st) {
+  for (const LargeBlock &b : mg.large) {
+    launch_fill_f64(mg.large_A, (int64_t)b.m * mg.large_ld, 0.0, st);
+    if (mg.mixed)
+      launch_copy_block(reinterpret_cast<const float *>(mg.blk_scratch) + b.boff, b.m, mg.large_A, mg.large_ld, st);
+    else
+      launch_copy_block(mg.blk_scratch + b.boff, b.m, mg.large_A, mg.large_ld, st);
+    CoarseSplit cs;
+    cs.n = b.m;
+    cs.fpos = mg.large_iota;
+    double *C = mg.mixed ? mg.large_C : mg.blk_scratch + b.boff;
+    gj_coarse(mg.large_A, b.m, mg.large_ld, cs, C, mg.status + b.q, mg.large_iwork, st);
+    if (mg.mixed)
+      launch_cast_d2f(mg.large_C, reinterpret_cast<float *>(mg.blk_scratch) + b.boff, (int)((int64_t)b.m * b.m), st);
+    launch_iota_i32(mg.gj_perm + b.poff, b.m, st);
+    launch_iota_i32(mg.gj_used + b.poff, b.m, st);
+  }
+  hip_check(hipGetLastError(), "large block launch");
+}
+
 // next event pair of a profiling list (created on first use)
 static hipEvent_t *prof_event_pair(std::vector<std::pair<hipEvent_t, hipEvent_t>> &evs, size_t &used) {
   if (used == evs.size()) {
@@ -861,6 +887,7 @@ void refactor(MG &mg, hipStream_t st) {
     hipEvent_t *ev = mg.prof_on ? prof_event_pair(mg.prof_gj_ev, mg.prof_gj_used) : nullptr;
     invert_blocks(mg, mg.gj_variant, st, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
     hip_check(hipGetLastError(), "gj launch");
+    invert_large(mg, st);
     for (int l = 1; l < mg.nlevels; ++l) {
       pack_level(mg, mg.lv[l], st);
       if (mg.mixed)
@@ -1367,6 +1394,26 @@ static void validate_hierarchy(const fsi_level *levels, int nlevels, const std::
 // copying: options, dimensions across levels, CSR row offsets (monotone,
 // spanning nnz) and patch offsets and dofs in range.  O(n + sum of patch
 // sizes); the entries themselves are checked by validate_levels at setup.
+// blocks above kMaxPatch dofs are inverted whole by the Gauss-Jordan chain;
+// the ILU(0) factorization and the refinement sweeps keep the smaller limit
+static void validate_large_blocks(const fsi_level *levels, int nlevels, const fsi_mg_opts &o) {
+  const bool refine = solid_split(o) && o.refine_sweeps > 0;
+  for (int l = 1; l < nlevels; ++l) {
+    const fsi_patches &P = levels[l].patches;
+    for (int k = 0; k < P.npatch; ++k) {
+      if (P.ptr[k + 1] - P.ptr[k] <= kMaxPatch) continue;
+      const int kind = P.kind ? P.kind[k] : 0;
+      const char *why = (o.fluid_ilu && kind == 0) ? "an ILU(0) block" : (refine && kind == 1) ? "a refined block" : nullptr;
+      if (why) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "level %d patch %d: %s of %lld dofs; at most %d", l, k, why,
+                 (long long)(P.ptr[k + 1] - P.ptr[k]), kMaxPatch);
+        throw Error(FSI_E_INVALID, buf);
+      }
+    }
+  }
+}
+
 void validate_levels_light(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts) {
   if (!levels || nlevels < 1) throw Error(FSI_E_INVALID, "no levels");
   validate_opts(opts);
@@ -1396,7 +1443,7 @@ void validate_levels_light(const fsi_level *levels, int nlevels, const fsi_mg_op
     if (P.npatch <= 0 || !P.ptr || !P.dof || !P.owned || P.ptr[0] != 0)
       throw Error(FSI_E_INVALID, "patches missing or malformed");
     for (int k = 0; k < P.npatch; ++k)
-      if (P.ptr[k + 1] <= P.ptr[k] || P.ptr[k + 1] - P.ptr[k] > kMaxPatch)
+      if (P.ptr[k + 1] <= P.ptr[k] || P.ptr[k + 1] - P.ptr[k] > kMaxLargePatch)
         throw Error(FSI_E_INVALID, "patch offsets invalid or a patch larger than the supported block size");
     for (int64_t p = 0; p < P.ptr[P.npatch]; ++p)
       if (P.dof[p] < 0 || P.dof[p] >= n) throw Error(FSI_E_INVALID, "patch dof out of range");
@@ -1416,6 +1463,7 @@ void validate_levels(const fsi_level *levels, int nlevels, const fsi_mg_opts *op
     throw Error(FSI_E_INVALID, buf);
   }
   validate_hierarchy(levels, nlevels, n);
+  validate_large_blocks(levels, nlevels, *opts);
 }
 
 
@@ -1466,13 +1514,19 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
       for (int k = 0; k < L.npatch; ++k) {
         all_boff.push_back(base + L.h_boff[k]);
         all_poff.push_back(pbase + L.h_ptr[k]);
-        // an ILU block is factored apart: no Gauss-Jordan work (size 0)
+        // an ILU block is factored apart, a block above kMaxPatch dofs is
+        // inverted on its own: no work in the batched launch (size 0)
         const bool is_ilu = mg->opts.fluid_ilu && L.h_kind[k] == 0;
-        all_pm.push_back(is_ilu ? 0 : (int)(L.h_ptr[k + 1] - L.h_ptr[k]));
+        const int m = (int)(L.h_ptr[k + 1] - L.h_ptr[k]);
+        if (!is_ilu && m > kMaxPatch) {
+          mg->large.push_back(LargeBlock{(int)all_pm.size(), m, base + L.h_boff[k], pbase + L.h_ptr[k]});
+          mg->large_mmax = std::max(mg->large_mmax, m);
+        }
+        all_pm.push_back(is_ilu || m > kMaxPatch ? 0 : m);
+        mg->mmax_all = std::max(mg->mmax_all, all_pm.back());
       }
       base += L.boff_total;
       pbase += L.sum_m;
-      mg->mmax_all = std::max(mg->mmax_all, L.mmax);
     }
     mg->blk_total = base;
     mg->npatch_all = (int)all_pm.size();
@@ -1514,6 +1568,15 @@ MG *mg_setup(const fsi_level *levels, int nlevels, const fsi_mg_opts *opts, hipS
       mg->coarse_nd = (int)dlist.size();
       mg->coarse_fpos = dupload(fpos.data(), n0, mg->owned, st);
       mg->coarse_dlist = dupload(dlist.data(), (int64_t)dlist.size(), mg->owned, st);
+    }
+    if (!mg->large.empty()) {
+      // the chain's working copy: rows padded to a multiple of 16 doubles, + 64 past the end
+      mg->large_ld = (mg->large_mmax + 15) / 16 * 16;
+      mg->large_A = dalloc<double>((int64_t)mg->large_mmax * mg->large_ld + 64, mg->owned);
+      if (mg->mixed) mg->large_C = dalloc<double>((int64_t)mg->large_mmax * mg->large_mmax, mg->owned);
+      mg->large_iota = dalloc<int>(mg->large_mmax, mg->owned);
+      launch_iota_i32(mg->large_iota, mg->large_mmax, st);
+      mg->large_iwork = dalloc<int>(2 * (int64_t)mg->large_mmax + 64, mg->owned);
     }
     mg->dense_ld = (std::max(mg->coarse_nf, 1) + 15) / 16 * 16;
     mg->dense_scratch = dalloc<double>(std::max(mg->coarse_nf, 1) * mg->dense_ld, mg->owned);

@@ -43,11 +43,11 @@ def oracle_hierarchy(name, fluid_ilu=False):
 
 
 @functools.lru_cache(maxsize=None)
-def oracle_on_product(name, fluid_ilu=False):
+def oracle_on_product(name, fluid_ilu=False, **kw):
     """The checker's algorithm (LU local solves, or ILU(0) on the fluid
     blocks, V-cycle, FGMRES) run on the product builder's matrices and
-    patches."""
-    p = product_problem(name)
+    patches (of the named workload, or of it with the fields kw changed)."""
+    p = product_problem(name, **kw)
     levels = []
     for l in range(p.nlevels):
         lv = osolver.Level(J=csr_of(p, l, "J"))
@@ -57,6 +57,6 @@ def oracle_on_product(name, fluid_ilu=False):
             lv.ptr, lv.dof, lv.owned, lv.kind = p.patches(l)
         levels.append(lv)
     osolver.setup_factors(levels, fluid_ilu=fluid_ilu)
-    s = config(name).with_(fluid_ilu=fluid_ilu)
+    s = config(name).with_(fluid_ilu=fluid_ilu, **kw)
     h = oprob.Hierarchy(s, None, None, levels, p.b.copy(), p.y.copy(), None)
     return h

@@ -328,3 +328,16 @@ def test_newton_and_fmg_reject_bad_arguments_on_the_host():
     assert st == -1
     st = L.fsi_assembly_create(None, None, None, None)
     assert st == -1
+
+
+def test_large_blocks_are_limited_where_the_kernels_need_it():
+    """Blocks above 800 dofs (3D patches of 4x4x4 elements) set up on the
+    host checks; ILU(0) on such a fluid block, or refinement sweeps on such
+    a solid block, are refused before any device call (FSI_E_INVALID)."""
+    from paper_1709_05660_amd import Problem
+    s = config("c3_3d_32x8x8").with_(nx=16, ny=4, nz=4, levels=2, patch=4)
+    p = Problem(s, fourier_coefficients(3, s.seed))
+    st, msg = _setup_status(p.levels, p.nlevels, fluid_ilu=1)
+    assert st == -1 and "ILU(0) block" in msg
+    st, msg = _setup_status(p.levels, p.nlevels, precision="bf16", refine_sweeps=1)
+    assert st == -1 and "refined block" in msg
