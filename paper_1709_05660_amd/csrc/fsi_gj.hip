@@ -983,6 +983,8 @@ void gj_coarse(double *A, int nf, int64_t ld, const CoarseSplit &cs, double *C0,
       gj_coarse_nb<16, 3, 512>(A, nf, ld, perm, used, status, st);
     else if (nf <= 3072)
       gj_coarse_nb<8, 6, 512>(A, nf, ld, perm, used, status, st);
+    else if (nf <= 4096)   // 8 columns, 8 rows a thread: 188 registers, no spill (10 rows spill)
+      gj_coarse_nb<8, 8, 512>(A, nf, ld, perm, used, status, st);
     else
       gj_coarse_nb<4, 12, 512>(A, nf, ld, perm, used, status, st);
   }
