@@ -212,7 +212,7 @@ def test_server_rejects_oversized_request():
                                   C.byref(bad), C.byref(t))
         assert st == -1 and word in lib.fsi_last_error(), lib.fsi_last_error()
     assert lib.fsi_serve_poll(h, 12345, None, None) == -7
-    stats = (C.c_int64 * 10)()
+    stats = (C.c_int64 * 12)()      # the header's out[12]
     assert lib.fsi_server_stats(h, stats) == 0 and stats[0] == 0
     assert lib.fsi_server_destroy(h) == 0
 
