@@ -11,6 +11,7 @@
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 #include <cmath>
 
@@ -1116,12 +1117,11 @@ void launch_ilu_apply(const IluView &v, const V *lval, const V *uval, const V *u
   constexpr size_t kStageMax = 128 * 1024;
   const size_t stage = (size_t)v.max_entries * (sizeof(V) + sizeof(int16_t));
   if (stage <= kStageMax) {
-    static bool attr = false;   // raise the dynamic LDS limit once per instance
-    if (!attr) {
+    static std::once_flag attr;   // raise the dynamic LDS limit once per instance (setup threads race here)
+    std::call_once(attr, [] {
       hip_ok_or_clear(hipFuncSetAttribute((const void *)k_ilu_apply<V, true>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kStageMax));
-      attr = true;
-    }
+    });
     k_ilu_apply<V, true><<<v.nblk, 256, stage, st>>>(v, lval, uval, udiag, s, e, omega, (int)add, (int)clear);
   } else {
     k_ilu_apply<V, false><<<v.nblk, 256, 0, st>>>(v, lval, uval, udiag, s, e, omega, (int)add, (int)clear);

@@ -191,9 +191,10 @@ static int64_t footprint(const fsi_level *lv, int nl, const fsi_mg_opts &mo,
     // or full FP32 inverses plus their local block rows
     const bool split = mixed && ((mo.solid_precision != -1 && mo.solid_precision != mo.precision) ||
                                  mo.refine_sweeps > 0);
-    int64_t om = 0, m2 = 0, slots = 0, solid_bytes = 0;
+    int64_t om = 0, m2 = 0, slots = 0, solid_bytes = 0, mlarge = 0;
     for (int k = 0; k < P.npatch; ++k) {
       const int64_t m = P.ptr[k + 1] - P.ptr[k];
+      if (m > kMaxPatch) mlarge = std::max(mlarge, m);
       int64_t o = 0, ks = 0;
       for (int64_t p = P.ptr[k]; p < P.ptr[k + 1]; ++p) {
         o += P.owned[p] ? 1 : 0;
@@ -210,6 +211,9 @@ static int64_t footprint(const fsi_level *lv, int nl, const fsi_mg_opts &mo,
     // all levels' dense blocks share one setup scratch; the extraction map
     // (two ints per slot, an offset per block row) is setup scratch too
     transient += m2 * 8 + slots * 8 + P.ptr[P.npatch] * 8;
+    // blocks above kMaxPatch dofs: the Gauss-Jordan chain's padded working
+    // copy and (mixed forms) the FP64 inverse before its cast
+    if (mlarge) res += mlarge * ((mlarge + 15) / 16 * 16) * 8 + (mixed ? mlarge * mlarge * 8 : 0) + mlarge * 12;
   }
   // Krylov: V (m+1 columns), Z (m), w, b and x; H and the rotations; the
   // reductions' chunk sums (two sets of kMaxKrylovCols columns) and norms
