@@ -4,9 +4,9 @@ infrastructure, never called by the GPU solver path).
 Section "Monolithic Newton-Krylov solver with Multigrid-Richardson-Schwarz
 preconditioner": every nonlinear step linearises the monolithic residual
 exactly (here the complex-step Jacobian of `fem.assemble`) and solves for the
-correction; in the steady case the Newton iteration is wrapped by a full
-multigrid algorithm, i.e. it is run on a sequence of nested meshes, coarsest
-first, each mesh started from the previous mesh's iterate carried over by the
+correction; for steady problems the paper places the Newton iteration inside
+full multigrid: Newton runs on a sequence of nested meshes, coarsest first,
+each mesh started from the previous mesh's iterate carried over by the
 prolongation.  Section "Details on the iterative solver": convergence at step
 k when ||y^k - y^{k-1}||_2 < eps ||y^k||_2 with eps = 1e-8.
 
