@@ -314,6 +314,18 @@ def time_step_leg(args):
                                            "krylov_iters": ninfo["krylov_iters"],
                                            "residual_first_last": [float(f"{ninfo['res0']:.4g}"),
                                                                    float(f"{ninfo['res_last']:.4g}")]}
+                # time integration: ten Crank-Nicolson steps on from the converged
+                # state, each by Newton on the device
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                tinfos, tst = asm.time_steps(mg, y, 10, max_newton=12, tol=1e-8, rtol=1e-10)
+                torch.cuda.synchronize()
+                tms = (time.perf_counter() - t0) * 1e3
+                res["time_integration_10_steps"] = {
+                    "ms_per_time_step": round(tms / 10, 2), "all_converged": tst == 0,
+                    "newton_steps": [i["steps"] for i in tinfos],
+                    "krylov_iters_per_newton_step": round(sum(i["krylov_iters"] for i in tinfos)
+                                                          / max(1, sum(i["steps"] for i in tinfos)), 2)}
                 asm.close()
                 # a new Jacobian's coarse operators on the device (R J P per level)
                 mg.galerkin()

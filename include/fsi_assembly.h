@@ -67,6 +67,21 @@ fsi_status fsi_newton_solve(struct fsi_assembly *a, struct fsi_mg *mg, double *y
                             const fsi_newton_opts *nopts, const fsi_krylov_opts *kopts,
                             fsi_newton_info *info, void *hip_stream);
 
+/* Time integration by Crank-Nicolson steps (section "Discretization of the
+ * operator formulation": the time-discrete system of one step; section
+ * "Details on the iterative solver": Newton's method in every step): nsteps
+ * steps from the state in y_dev (device, ndof doubles, updated in place).
+ * Each step makes the current state the assembly's state at t_n and runs
+ * fsi_newton_solve (nopts, kopts) from it for the state at t_{n+1}.  The
+ * assembly must have been created from a time step's element data (its
+ * y_prev).  info (may be NULL) receives one record per step.  Returns FSI_OK
+ * when every step converged, else FSI_NOT_CONVERGED after the first step that
+ * did not (the records up to it filled).  Errors: FSI_E_INVALID (null
+ * argument, nsteps < 1, a steady assembly), and those of the calls it makes. */
+fsi_status fsi_cn_steps(struct fsi_assembly *a, struct fsi_mg *mg, double *y_dev, int32_t nsteps,
+                        const fsi_newton_opts *nopts, const fsi_krylov_opts *kopts, fsi_newton_info *info,
+                        void *hip_stream);
+
 /* Full multigrid for the steady case (section "Monolithic Newton-Krylov
  * solver with Multigrid-Richardson-Schwarz preconditioner": Newton wrapped
  * in a full multigrid algorithm; section "Details on the iterative solver":

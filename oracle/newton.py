@@ -37,6 +37,21 @@ def newton(mesh, spec, y, tol=1e-8, max_steps=20, y_prev=None):
     return y, max_steps, False, hist
 
 
+def cn_steps(mesh, spec, y0, nsteps, tol=1e-8, max_steps=20):
+    """nsteps Crank-Nicolson steps from the state y0 (section "Discretization
+    of the operator formulation"): each step's residual takes the current
+    state as the state at t_n, and Newton from that state gives the state at
+    t_{n+1}.  Returns (final state, per-step list of (steps, converged,
+    history))."""
+    y = np.array(y0, dtype=np.float64, copy=True)
+    out = []
+    for _ in range(nsteps):
+        y_prev = y.copy()
+        y, steps, conv, hist = newton(mesh, spec, y, tol=tol, max_steps=max_steps, y_prev=y_prev)
+        out.append((steps, conv, hist))
+    return y, out
+
+
 def fmg(spec, coeffs, sizes, tol=1e-8, max_steps=20, seeded_base=True):
     """Full multigrid over the nested meshes `sizes` (coarsest first, each
     twice as fine per direction as the one before).  The coarsest mesh starts

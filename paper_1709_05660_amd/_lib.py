@@ -118,7 +118,7 @@ EXPORTS = [
     "fsi_problem_build", "fsi_problem_nlevels", "fsi_problem_levels", "fsi_problem_vectors",
     "fsi_problem_dirichlet", "fsi_problem_residual", "fsi_problem_destroy", "fsi_problem_last_error",
     "fsi_problem_element_data", "fsi_assembly_create", "fsi_assembly_run", "fsi_newton_solve",
-    "fsi_fmg_solve", "fsi_assembly_destroy",
+    "fsi_cn_steps", "fsi_fmg_solve", "fsi_assembly_destroy",
 ]
 
 _lib = None
@@ -177,6 +177,8 @@ def lib():
         "fsi_assembly_run": (C.c_int32, [P, P, P, P, P]),
         "fsi_newton_solve": (C.c_int32, [P, P, P, C.POINTER(NewtonOpts), C.POINTER(KrylovOpts),
                                          C.POINTER(NewtonInfo), P]),
+        "fsi_cn_steps": (C.c_int32, [P, P, P, C.c_int32, C.POINTER(NewtonOpts), C.POINTER(KrylovOpts),
+                                     C.POINTER(NewtonInfo), P]),
         "fsi_fmg_solve": (C.c_int32, [C.c_int32, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(P),
                                       C.POINTER(C.c_int32), C.POINTER(NewtonOpts), C.POINTER(KrylovOpts),
                                       C.POINTER(NewtonInfo), P]),

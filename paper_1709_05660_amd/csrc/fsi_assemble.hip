@@ -395,6 +395,7 @@ struct Assembly {
   int *d_dir_rows = nullptr, *d_dir_diag = nullptr;
   double *d_dir_val = nullptr;
   double *b = nullptr, *x = nullptr, *r = nullptr, *partial = nullptr, *nrm = nullptr;
+  double *yprev = nullptr;   // the state at t_n of a time step (the view reads it), else null
   AsmMem mem;
 };
 
@@ -459,7 +460,8 @@ static Assembly *create(const fsi_element_data &ed, const fsi_csr &J, hipStream_
   v.psi = M.up(ed.psi, (int64_t)nq * (ed.dim + 1));
   v.w = M.up(ed.w, nq);
   v.transient = ed.y_prev ? 1 : 0;
-  v.yprev = ed.y_prev ? M.up(ed.y_prev, ed.ndof) : nullptr;
+  A->yprev = ed.y_prev ? M.up(ed.y_prev, ed.ndof) : nullptr;
+  v.yprev = A->yprev;
   v.vol = ed.vol;
   v.mu = ed.mu;
   v.rho = ed.rho;
@@ -533,6 +535,22 @@ static fsi_status newton(Assembly &A, MG &mg, double *y, const fsi_newton_opts &
   }
   if (info) *info = inf;
   return st_out;
+}
+
+// Crank-Nicolson steps: the current state becomes the state at t_n, Newton
+// from it gives the state at t_{n+1}
+static fsi_status cn_steps(Assembly &A, MG &mg, double *y, int nsteps, const fsi_newton_opts &no,
+                           const fsi_krylov_opts &ko, fsi_newton_info *info, hipStream_t st) {
+  if (!A.v.transient || !A.yprev) throw Error(FSI_E_INVALID, "the assembly holds no state at t_n (a steady problem)");
+  if (nsteps < 1) throw Error(FSI_E_INVALID, "nsteps < 1");
+  for (int k = 0; k < nsteps; ++k) {
+    hip_check(hipMemcpyAsync(A.yprev, y, sizeof(double) * A.v.ndof, hipMemcpyDeviceToDevice, st), "state at t_n");
+    fsi_newton_info inf{};
+    const fsi_status r = newton(A, mg, y, no, ko, &inf, st);
+    if (info) info[k] = inf;
+    if (r != FSI_OK) return r;
+  }
+  return FSI_OK;
 }
 
 // full multigrid: Newton on each mesh, coarsest first, each mesh started from
@@ -614,6 +632,21 @@ fsi_status fsi_newton_solve(struct fsi_assembly *h, struct fsi_mg *mh, double *y
     if (!A || !mg || !y_dev || !nopts || !kopts) throw Error(FSI_E_INVALID, "null argument");
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
     return newton(*A, *mg, y_dev, *nopts, *kopts, info, st);
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+fsi_status fsi_cn_steps(struct fsi_assembly *h, struct fsi_mg *mh, double *y_dev, int32_t nsteps,
+                        const fsi_newton_opts *nopts, const fsi_krylov_opts *kopts, fsi_newton_info *info,
+                        void *hip_stream) {
+  try {
+    Assembly *A = reinterpret_cast<Assembly *>(h);
+    MG *mg = reinterpret_cast<MG *>(mh);
+    if (!A || !mg || !y_dev || !nopts || !kopts) throw Error(FSI_E_INVALID, "null argument");
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : mg->own_stream;
+    return cn_steps(*A, *mg, y_dev, nsteps, *nopts, *kopts, info, st);
   } catch (const Error &e) {
     set_error(e.msg);
     return e.code;

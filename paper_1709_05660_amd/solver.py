@@ -418,6 +418,18 @@ class Assembly:
         L.check(st, "newton")
         return info.as_dict()
 
+    def time_steps(self, mg, y, nsteps, max_newton=20, tol=1e-8, rtol=1e-8, restart=30, maxit=1000):
+        """nsteps Crank-Nicolson steps from the state y (updated in place;
+        fsi_cn_steps); returns (one Newton record per step, status: 0 when
+        every step converged, 1 otherwise)."""
+        no = L.NewtonOpts(int(max_newton), float(tol))
+        ko = krylov_opts(restart, rtol, maxit)
+        infos = (L.NewtonInfo * int(nsteps))()
+        st = L.lib().fsi_cn_steps(self.h, mg.h, _vec(y, self.n, "y"), int(nsteps), C.byref(no), C.byref(ko), infos,
+                                  _stream())
+        L.check(st, "time steps")
+        return [i.as_dict() for i in infos], st
+
     def close(self):
         if getattr(self, "h", None):
             L.lib().fsi_assembly_destroy(self.h)

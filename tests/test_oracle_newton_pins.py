@@ -57,3 +57,18 @@ def test_fmg_base_transfer_reproduces_the_seeded_state():
     y = sf + P @ (sc - sc)
     y[ff] = vf[ff]
     assert np.array_equal(y, sf)
+
+
+def test_time_steps_keep_a_steady_solution():
+    """A steady solution is a fixed point of the Crank-Nicolson step (at rest
+    the step's residual is the steady residual): the checker's time steps
+    from the converged 16x4 steady state stop after one Newton step with a
+    negligible update and leave the state where it was."""
+    s, a = _spec()
+    mesh = fem.Mesh(s, (16, 4))
+    y, _, conv, _ = onewton.newton(mesh, s, fem.seeded_state(mesh, s, a), tol=1e-12, max_steps=15)
+    assert conv
+    y2, out = onewton.cn_steps(mesh, s, y, 2, tol=1e-8)
+    for steps, conv, hist in out:
+        assert conv and steps == 1 and hist[0][1] <= 1e-9
+    assert np.linalg.norm(y2 - y) <= 1e-9 * np.linalg.norm(y)
