@@ -97,8 +97,14 @@ struct Level {
   // its pattern (prepared at the first call), and the positions of the next
   // coarser level's Dirichlet diagonals; the Dirichlet rows of this level
   // when the input flags them
-  int *d_t_rp = nullptr, *d_t_col = nullptr, *d_cdir_pos = nullptr;
-  double *d_t_val = nullptr;
+  // Galerkin products as gathers: for every entry q of T = J P (then of the
+  // coarse operator R T), its contributions t in [ptr[q], ptr[q+1]) are
+  // w[t] * x[idx[t]], x the variable operand's values (J, then T), w the
+  // constant one's (P, then R), listed in the order a row-by-column product
+  // sums them
+  int *d_gt_ptr = nullptr, *d_gt_idx = nullptr, *d_gc_ptr = nullptr, *d_gc_idx = nullptr, *d_cdir_pos = nullptr;
+  double *d_gt_w = nullptr, *d_gc_w = nullptr, *d_t_val = nullptr;
+  int64_t gt_n = 0, gc_n = 0;
   int n_cdir = 0;
   std::vector<int> h_dir;
   bool dir_known = false;

@@ -217,12 +217,13 @@ template <typename V>
 void launch_ilu_apply(const IluView &v, const V *lval, const V *uval, const V *udiag, const V *s, V *e,
                       V omega, bool add, bool clear, hipStream_t st);
 
-// ---- Galerkin product on the device: C = A B on C's given pattern (every
-// entry's sum over A's row in A's column order, the terms found in B's rows
-// by binary search; C's columns sorted per row); entries of C that no term
-// reaches are 0.  add_at: val[pos[t]] += v for t < n (Dirichlet diagonals).
-void launch_spgemm_rowdot(const CsrView<double> &A, const CsrView<double> &B, int nrows_c, const int *c_rowptr,
-                          const int *c_col, double *c_val, hipStream_t st);
+// ---- Galerkin product on the device: out[q] = sum of x[idx[t]] * w[t] over
+// t in [ptr[q], ptr[q+1]) in list order, for q < n (a sparse product C = A B
+// on C's given pattern, its terms listed once on the host; entries that no
+// term reaches are 0).  add_at: val[pos[t]] += v for t < n (Dirichlet
+// diagonals).
+void launch_gather_dot(int n, const int *ptr, const int *idx, const double *w, const double *x, double *out,
+                       hipStream_t st);
 void launch_add_at(double *val, const int *pos, int n, double v, hipStream_t st);
 
 // ---- coarsest solve (a7): y = W x, W row-major n x n FP64

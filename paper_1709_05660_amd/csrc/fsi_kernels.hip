@@ -1133,39 +1133,20 @@ template void launch_ilu_apply<float>(const IluView &, const float *, const floa
                                       const float *, float *, float, bool, bool, hipStream_t);
 
 // ------------------------------------------------------------------ Galerkin product
-// one wave per row of C, lanes over the row's entries
-__global__ __launch_bounds__(256) void k_spgemm_rowdot(int nrows, const int *__restrict__ arp,
-                                                       const int *__restrict__ acol, const double *__restrict__ aval,
-                                                       const int *__restrict__ brp, const int *__restrict__ bcol,
-                                                       const double *__restrict__ bval, const int *__restrict__ crp,
-                                                       const int *__restrict__ ccol, double *__restrict__ cval) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (row >= nrows) return;
-  const int a0 = arp[row], a1 = arp[row + 1];
-  for (int q = crp[row] + lane; q < crp[row + 1]; q += 64) {
-    const int j = ccol[q];
-    double acc = 0.0;
-    for (int p = a0; p < a1; ++p) {
-      const int k = acol[p];
-      int lo = brp[k], hi = brp[k + 1];
-      const int end = hi;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (bcol[mid] < j)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      if (lo < end && bcol[lo] == j) acc += aval[p] * bval[lo];
-    }
-    cval[q] = acc;
-  }
+// out[q] = sum over t in [ptr[q], ptr[q+1]) of x[idx[t]] * w[t], in list order
+// (one thread per output entry)
+__global__ __launch_bounds__(256) void k_gather_dot(int n, const int *__restrict__ ptr, const int *__restrict__ idx,
+                                                    const double *__restrict__ w, const double *__restrict__ x,
+                                                    double *__restrict__ out) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n) return;
+  double acc = 0.0;
+  for (int t = ptr[q]; t < ptr[q + 1]; ++t) acc += x[idx[t]] * w[t];
+  out[q] = acc;
 }
-void launch_spgemm_rowdot(const CsrView<double> &A, const CsrView<double> &B, int nrows_c, const int *c_rowptr,
-                          const int *c_col, double *c_val, hipStream_t st) {
-  if (nrows_c > 0)
-    k_spgemm_rowdot<<<cdiv(nrows_c, 4), 256, 0, st>>>(nrows_c, A.rowptr, A.col, A.val, B.rowptr, B.col, B.val,
-                                                       c_rowptr, c_col, c_val);
+void launch_gather_dot(int n, const int *ptr, const int *idx, const double *w, const double *x, double *out,
+                       hipStream_t st) {
+  if (n > 0) k_gather_dot<<<cdiv(n, 256), 256, 0, st>>>(n, ptr, idx, w, x, out);
 }
 __global__ void k_add_at(double *val, const int *pos, int n, double v) {
   const int t = blockIdx.x * 256 + threadIdx.x;

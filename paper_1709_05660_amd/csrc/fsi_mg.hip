@@ -1328,8 +1328,62 @@ static void galerkin_prepare(MG &mg, hipStream_t st) {
         throw Error(FSI_E_INVALID, "a Dirichlet row of a coarse operator holds no diagonal");
       pos.push_back((int)(f - cc.data()));
     }
-    L.d_t_rp = dupload(trp.data(), (int64_t)trp.size(), mg.owned, st);
-    L.d_t_col = dupload(tcol.data(), (int64_t)tcol.size(), mg.owned, st);
+    // the terms of every entry of T = J P, in the order a row-by-column product
+    // sums them (ascending entries of J's row), then those of R T
+    const auto pv = d2h(L.P.val, L.P.nnz), rv = d2h(L.R.val, L.R.nnz);
+    std::vector<int> tpos(C.n, -1);
+    std::vector<int> gt_ptr(tcol.size() + 1, 0), gt_idx;
+    std::vector<double> gt_w;
+    for (int i = 0; i < L.n; ++i) {
+      for (int q = trp[i]; q < trp[i + 1]; ++q) tpos[tcol[q]] = q;
+      for (int p = jrp[i]; p < jrp[i + 1]; ++p)
+        for (int q = prp[jc[p]]; q < prp[jc[p] + 1]; ++q) ++gt_ptr[tpos[pc[q]] + 1];
+    }
+    for (size_t q = 0; q < tcol.size(); ++q) gt_ptr[q + 1] += gt_ptr[q];
+    gt_idx.resize(gt_ptr.back());
+    gt_w.resize(gt_ptr.back());
+    {
+      std::vector<int> fill(gt_ptr.begin(), gt_ptr.end() - 1);
+      for (int i = 0; i < L.n; ++i) {
+        for (int q = trp[i]; q < trp[i + 1]; ++q) tpos[tcol[q]] = q;
+        for (int p = jrp[i]; p < jrp[i + 1]; ++p)
+          for (int q = prp[jc[p]]; q < prp[jc[p] + 1]; ++q) {
+            const int t = fill[tpos[pc[q]]]++;
+            gt_idx[t] = p;
+            gt_w[t] = pv[q];
+          }
+      }
+    }
+    std::vector<int> cpos(C.n, -1), gc_ptr(C.J.nnz + 1, 0), gc_idx;
+    std::vector<double> gc_w;
+    for (int r = 0; r < C.n; ++r) {
+      for (int q = crp[r]; q < crp[r + 1]; ++q) cpos[cc[q]] = q;
+      for (int p = rrp[r]; p < rrp[r + 1]; ++p)
+        for (int q = trp[rc[p]]; q < trp[rc[p] + 1]; ++q) ++gc_ptr[cpos[tcol[q]] + 1];
+    }
+    for (int64_t q = 0; q < C.J.nnz; ++q) gc_ptr[q + 1] += gc_ptr[q];
+    gc_idx.resize(gc_ptr.back());
+    gc_w.resize(gc_ptr.back());
+    {
+      std::vector<int> fill(gc_ptr.begin(), gc_ptr.end() - 1);
+      for (int r = 0; r < C.n; ++r) {
+        for (int q = crp[r]; q < crp[r + 1]; ++q) cpos[cc[q]] = q;
+        for (int p = rrp[r]; p < rrp[r + 1]; ++p)
+          for (int q = trp[rc[p]]; q < trp[rc[p] + 1]; ++q) {
+            const int t = fill[cpos[tcol[q]]]++;
+            gc_idx[t] = q;
+            gc_w[t] = rv[p];
+          }
+      }
+    }
+    L.gt_n = (int64_t)tcol.size();
+    L.gc_n = C.J.nnz;
+    L.d_gt_ptr = dupload(gt_ptr.data(), (int64_t)gt_ptr.size(), mg.owned, st);
+    L.d_gt_idx = dupload(gt_idx.data(), std::max<int64_t>((int64_t)gt_idx.size(), 1), mg.owned, st);
+    L.d_gt_w = dupload(gt_w.data(), std::max<int64_t>((int64_t)gt_w.size(), 1), mg.owned, st);
+    L.d_gc_ptr = dupload(gc_ptr.data(), (int64_t)gc_ptr.size(), mg.owned, st);
+    L.d_gc_idx = dupload(gc_idx.data(), std::max<int64_t>((int64_t)gc_idx.size(), 1), mg.owned, st);
+    L.d_gc_w = dupload(gc_w.data(), std::max<int64_t>((int64_t)gc_w.size(), 1), mg.owned, st);
     L.d_t_val = dalloc<double>(std::max<int64_t>((int64_t)tcol.size(), 1), mg.owned);
     L.d_cdir_pos = dupload(pos.data(), (int64_t)pos.size(), mg.owned, st);
     L.n_cdir = (int)pos.size();
@@ -1342,9 +1396,8 @@ void galerkin(MG &mg, hipStream_t st) {
   if (!mg.galerkin_ready) galerkin_prepare(mg, st);
   for (int l = mg.nlevels - 1; l >= 1; --l) {
     Level &L = mg.lv[l], &C = mg.lv[l - 1];
-    launch_spgemm_rowdot(L.J.v64(), L.P.v64(), L.n, L.d_t_rp, L.d_t_col, L.d_t_val, st);
-    const CsrView<double> T{L.n, C.n, 0, L.d_t_rp, L.d_t_col, L.d_t_val};
-    launch_spgemm_rowdot(L.R.v64(), T, C.n, C.J.rowptr, C.J.col, C.J.val, st);
+    launch_gather_dot((int)L.gt_n, L.d_gt_ptr, L.d_gt_idx, L.d_gt_w, L.J.val, L.d_t_val, st);
+    launch_gather_dot((int)L.gc_n, L.d_gc_ptr, L.d_gc_idx, L.d_gc_w, L.d_t_val, C.J.val, st);
     launch_add_at(C.J.val, L.d_cdir_pos, L.n_cdir, 1.0, st);
   }
   hip_check(hipGetLastError(), "galerkin launch");
