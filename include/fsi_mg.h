@@ -276,8 +276,11 @@ fsi_status fsi_mg_set_jvalues(struct fsi_mg *mg, int32_t level, const double *va
  * diagonal on their Dirichlet rows (the input flags, else the rows whose only
  * entry is a unit diagonal).  A new Newton step then needs only the finest
  * values: fsi_mg_set_jvalues, fsi_mg_galerkin, fsi_mg_refactor.  The first
- * call builds the intermediate pattern of J_l P_l on the host (a one-time
- * read-back of the patterns); every call is stream-ordered on hip_stream.
+ * call builds, on the host from read-back patterns and the constant P and R
+ * values, the intermediate pattern of J_l P_l and the list of every entry's
+ * terms (device memory of about 12 bytes per term); every call is
+ * stream-ordered on hip_stream and gives a row-by-column product's sums bit
+ * for bit.
  * Errors: FSI_E_INVALID (R J P has an entry outside a given coarse pattern, or
  * a Dirichlet row holds no diagonal), FSI_E_OOM, FSI_E_DEVICE. */
 fsi_status fsi_mg_galerkin(struct fsi_mg *mg, void *hip_stream);
