@@ -206,6 +206,20 @@ def three_d_leg(args):
             if prec == "fp64":
                 res["spmv_finest"] = spmv_roofline(mg, p)
             mg.close()
+        # the element-parallel assembly of the 3D residual and exact Jacobian
+        from paper_1709_05660_amd import Assembly
+        asm = Assembly(p)
+        y = torch.as_tensor(p.y).to("cuda")
+        asm.run(y)
+        torch.cuda.synchronize()
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        for _ in range(3):
+            asm.run(y)
+        a1.record(stream)
+        torch.cuda.synchronize()
+        res["device_assembly_ms"] = round(a0.elapsed_time(a1) / 3, 3)
+        asm.close()
         res["patches_4x4x4"] = three_d_large_patches(args, spec, stream)
     return res
 

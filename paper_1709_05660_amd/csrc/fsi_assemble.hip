@@ -57,14 +57,21 @@ struct KinD {
   V Gd[DIM][DIM], F[DIM][DIM], Fi[DIM][DIM], det, pq, uq[DIM], dq[DIM], gu[DIM][DIM];
 };
 
-// kinematics of the element state: value(i) gives local dof i as V
+// kinematics of the element state: value(i) gives local dof i as V.  In 3D
+// the loops over the element's 27 nodes stay rolled (unrolled, they kept many
+// table reads live and the kernel spilled several KB a lane); the 2D ones and
+// the small loops over components are unrolled
 template <int DIM, typename V, class Val>
 __device__ __forceinline__ void kin(const double *Nq, const double *dNq, const double *ps, Val dof, bool fluid,
                                     KinD<DIM, V> &k) {
   constexpr int NA = Shape<DIM>::NA, NP = Shape<DIM>::NP;
+  constexpr int UNR = DIM == 3 ? 1 : NA;
+#pragma unroll
   for (int c = 0; c < DIM; ++c)
+#pragma unroll
     for (int j = 0; j < DIM; ++j) {
       V s = V{};
+#pragma unroll UNR
       for (int a = 0; a < NA; ++a) s = s + dNq[a * DIM + j] * dof(c * NA + a);
       k.Gd[c][j] = s;
       k.F[c][j] = c == j ? s + 1.0 : s;
@@ -77,20 +84,26 @@ __device__ __forceinline__ void kin(const double *Nq, const double *dNq, const d
     k.Fi[1][0] = -(k.F[1][0] / k.det);
   } else {
     V cof[3][3];
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
       for (int j = 0; j < 3; ++j) {
         const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
         cof[i][j] = k.F[i1][j1] * k.F[i2][j2] - k.F[i1][j2] * k.F[i2][j1];
       }
     k.det = k.F[0][0] * cof[0][0] + k.F[0][1] * cof[0][1] + k.F[0][2] * cof[0][2];
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
       for (int j = 0; j < 3; ++j) k.Fi[i][j] = cof[j][i] / k.det;
   }
   V p = V{};
   for (int j = 0; j < NP; ++j) p = p + ps[j] * dof(2 * DIM * NA + j);
   k.pq = p;
+#pragma unroll
   for (int c = 0; c < DIM; ++c) {
     V u = V{}, d = V{};
+#pragma unroll UNR
     for (int a = 0; a < NA; ++a) {
       u = u + Nq[a] * dof((DIM + c) * NA + a);
       d = d + Nq[a] * dof(c * NA + a);
@@ -99,15 +112,20 @@ __device__ __forceinline__ void kin(const double *Nq, const double *dNq, const d
     k.dq[c] = d;
   }
   if (!fluid) return;
+#pragma unroll
   for (int c = 0; c < DIM; ++c) {
     V Gu[DIM];
+#pragma unroll
     for (int j = 0; j < DIM; ++j) {
       V s = V{};
+#pragma unroll UNR
       for (int a = 0; a < NA; ++a) s = s + dNq[a * DIM + j] * dof((DIM + c) * NA + a);
       Gu[j] = s;
     }
+#pragma unroll
     for (int b = 0; b < DIM; ++b) {
       V s = V{};
+#pragma unroll
       for (int j = 0; j < DIM; ++j) s = s + Gu[j] * k.Fi[j][b];
       k.gu[c][b] = s;
     }
@@ -134,7 +152,7 @@ __device__ __forceinline__ bool coupled_d(int dim, int na, bool solid, bool tran
 // jd, the formulas of the host builder (steady, or one Crank-Nicolson step
 // from the state ye0 at t_n to ye at t_{n+1}).
 template <int DIM, int RC>
-__device__ void element_rows(const AsmView &v, bool solid, const double *ye, const double *ye0, int jd, int r0,
+__device__ __forceinline__ void element_rows(const AsmView &v, bool solid, const double *ye, const double *ye0, int jd, int r0,
                              const double *sN, const double *sdN, const double *spsi, const double *sw,
                              D1 (&rows)[RC]) {
   constexpr int NA = Shape<DIM>::NA, NP = Shape<DIM>::NP, NQ = Shape<DIM>::NQ;
@@ -266,31 +284,42 @@ __device__ void element_rows(const AsmView &v, bool solid, const double *ye, con
       Pr = k1.det + (-1.0);
     }
     const double half = (solid && cn) ? 0.5 : 1.0;
+
     // this thread's rows
 #pragma unroll
     for (int i = 0; i < RC; ++i) {
       const int lr = r0 + i;
       if (lr >= Shape<DIM>::NL) break;
       if (lr < DIM * NA) {   // momentum
-        const int c = lr / NA, a = lr % NA;
+        const int cl = lr / NA, a = lr % NA;
         D1 t = dc(0.0);
-        if (!solid) {
-          t = Nq[a] * S[c];
-          for (int j = 0; j < DIM; ++j) t = t + dNq[a * DIM + j] * Tm[c][j] + dNq[a * DIM + j] * Tm0[c][j];
-        } else {
-          if (with_S) t = (w * Nq[a]) * S[c];
-          for (int b = 0; b < DIM; ++b)
-            t = t + (half * w * dNq[a * DIM + b]) * Tm[c][b] + half * w * dNq[a * DIM + b] * Tm0[c][b];
-        }
+        // the component as a compile-time constant in each branch, so that
+        // every per-point array is indexed by constants and stays in registers
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+          if (c == cl) {
+            if (!solid) {
+              t = Nq[a] * S[c];
+              for (int j = 0; j < DIM; ++j) t = t + dNq[a * DIM + j] * Tm[c][j] + dNq[a * DIM + j] * Tm0[c][j];
+            } else {
+              if (with_S) t = (w * Nq[a]) * S[c];
+              for (int b = 0; b < DIM; ++b)
+                t = t + (half * w * dNq[a * DIM + b]) * Tm[c][b] + half * w * dNq[a * DIM + b] * Tm0[c][b];
+            }
+          }
         rows[i] = rows[i] + t;
       } else if (lr < 2 * DIM * NA) {   // mesh motion (fluid) / kinematics (solid)
-        const int c = (lr - DIM * NA) / NA, a = (lr - DIM * NA) % NA;
+        const int cl = (lr - DIM * NA) / NA, a = (lr - DIM * NA) % NA;
         D1 t = dc(0.0);
-        if (!solid) {
-          for (int b = 0; b < DIM; ++b) t = t + (w * k_ale * dNq[a * DIM + b]) * k1.Gd[c][b];
-        } else {
-          t = (w * Nq[a]) * A[c];
-        }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+          if (c == cl) {
+            if (!solid) {
+              for (int b = 0; b < DIM; ++b) t = t + (w * k_ale * dNq[a * DIM + b]) * k1.Gd[c][b];
+            } else {
+              t = (w * Nq[a]) * A[c];
+            }
+          }
         rows[i] = rows[i] + t;
       } else {   // continuity / incompressibility
         const int j = lr - 2 * DIM * NA;
@@ -416,7 +445,7 @@ static void assemble(Assembly &A, const double *y, double *r, double *jval, hipS
   if (A.dim == 2)
     launch_assemble_dim<2, 39, 64>(A, y, r, jval, st);
   else
-    launch_assemble_dim<3, 24, 256>(A, y, r, jval, st);
+    launch_assemble_dim<3, 10, 256>(A, y, r, jval, st);   // 10 rows a thread: the most without spilling
   if (A.ndir)
     k_dirichlet_rows<<<(A.ndir + 255) / 256, 256, 0, st>>>(A.d_dir_rows, A.d_dir_diag, A.ndir, y, A.d_dir_val, r,
                                                             jval);
