@@ -1,12 +1,14 @@
 // Device assembly of the finest residual and its exact Jacobian, and the
 // Newton loop on the device (include/fsi_assembly.h).
 //
-// One workgroup per (element of one colour, range of threads); each thread
-// differentiates its element's residual along one local dof (a one-direction
-// dual number: value and derivative) for a chunk of the element's residual
-// rows, and writes its derivative column of the element Jacobian into the
-// CSR values (the column found by binary search in the row).  Elements of one
-// colour share no node, so every entry is written once per launch.
+// One workgroup per (element of one colour, range of Jacobian columns).  The
+// element residual's rows are sums over quadrature points of test functions
+// weighted by a few coefficients per point; the workgroup differentiates
+// those coefficients along each of its columns' local dofs (one-direction
+// dual numbers: value and derivative), then contracts them with the
+// test-function tables and adds the element Jacobian's entries into the CSR
+// values at positions found once, when the assembly is created.  Elements of
+// one colour share no node, so every entry is written once per launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,24 +59,52 @@ struct KinD {
   V Gd[DIM][DIM], F[DIM][DIM], Fi[DIM][DIM], det, pq, uq[DIM], dq[DIM], gu[DIM][DIM];
 };
 
-// kinematics of the element state: value(i) gives local dof i as V.  In 3D
-// the loops over the element's 27 nodes stay rolled (unrolled, they kept many
-// table reads live and the kernel spilled several KB a lane); the 2D ones and
-// the small loops over components are unrolled
-template <int DIM, typename V, class Val>
-__device__ __forceinline__ void kin(const double *Nq, const double *dNq, const double *ps, Val dof, bool fluid,
-                                    KinD<DIM, V> &k) {
+// The sums over the element's nodes at one quadrature point: the reference
+// gradients of displacement and velocity, velocity, displacement and
+// pressure.  They are linear in the element state, and a thread's dual state
+// differs from the element's value by one unit entry (its local dof), so the
+// value sums are taken once per element and point and shared through LDS, and
+// each thread adds its single-term derivative; only the nonlinear part
+// (deformation gradient, determinant, inverse, stresses) runs in duals.
+template <int DIM>
+struct Sums {
+  // per point: Gd[c][j], Gu[c][j], uq[c], dq[c], pq
+  static constexpr int GD = 0, GU = DIM * DIM, UQ = 2 * DIM * DIM, DQ = UQ + DIM, PQ = DQ + DIM, NS = PQ + 1;
+};
+
+// sum s of point q for the element state ye
+template <int DIM>
+__device__ __forceinline__ double point_sum(const double *sN, const double *sdN, const double *spsi, const double *ye,
+                                            int q, int s) {
   constexpr int NA = Shape<DIM>::NA, NP = Shape<DIM>::NP;
-  constexpr int UNR = DIM == 3 ? 1 : NA;
+  using S = Sums<DIM>;
+  const double *Nq = sN + q * NA, *dNq = sdN + q * NA * DIM;
+  double acc = 0.0;
+  if (s < S::UQ) {
+    const int c = (s % (DIM * DIM)) / DIM, j = s % DIM;
+    const double *yc = ye + (s < S::GU ? c : DIM + c) * NA;
+    for (int a = 0; a < NA; ++a) acc += dNq[a * DIM + j] * yc[a];
+  } else if (s < S::PQ) {
+    const double *yc = ye + (s < S::DQ ? DIM + s - S::UQ : s - S::DQ) * NA;
+    for (int a = 0; a < NA; ++a) acc += Nq[a] * yc[a];
+  } else {
+    for (int j = 0; j < NP; ++j) acc += spsi[q * NP + j] * ye[2 * DIM * NA + j];
+  }
+  return acc;
+}
+
+// the rest of the kinematics from the gradients (F = I + Gd, its determinant
+// and inverse, and for the fluid the velocity gradient in current coordinates
+// gu = Gu F^{-1}); uq, dq and pq are set by the caller
+template <int DIM, typename V>
+__device__ __forceinline__ void kin_finish(const V (&Gd)[DIM][DIM], const V (&Gu)[DIM][DIM], bool fluid,
+                                           KinD<DIM, V> &k) {
 #pragma unroll
   for (int c = 0; c < DIM; ++c)
 #pragma unroll
     for (int j = 0; j < DIM; ++j) {
-      V s = V{};
-#pragma unroll UNR
-      for (int a = 0; a < NA; ++a) s = s + dNq[a * DIM + j] * dof(c * NA + a);
-      k.Gd[c][j] = s;
-      k.F[c][j] = c == j ? s + 1.0 : s;
+      k.Gd[c][j] = Gd[c][j];
+      k.F[c][j] = c == j ? Gd[c][j] + 1.0 : Gd[c][j];
     }
   if constexpr (DIM == 2) {
     k.det = k.F[0][0] * k.F[1][1] - k.F[0][1] * k.F[1][0];
@@ -97,39 +127,64 @@ __device__ __forceinline__ void kin(const double *Nq, const double *dNq, const d
 #pragma unroll
       for (int j = 0; j < 3; ++j) k.Fi[i][j] = cof[j][i] / k.det;
   }
-  V p = V{};
-  for (int j = 0; j < NP; ++j) p = p + ps[j] * dof(2 * DIM * NA + j);
-  k.pq = p;
-#pragma unroll
-  for (int c = 0; c < DIM; ++c) {
-    V u = V{}, d = V{};
-#pragma unroll UNR
-    for (int a = 0; a < NA; ++a) {
-      u = u + Nq[a] * dof((DIM + c) * NA + a);
-      d = d + Nq[a] * dof(c * NA + a);
-    }
-    k.uq[c] = u;
-    k.dq[c] = d;
-  }
   if (!fluid) return;
 #pragma unroll
-  for (int c = 0; c < DIM; ++c) {
-    V Gu[DIM];
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) {
-      V s = V{};
-#pragma unroll UNR
-      for (int a = 0; a < NA; ++a) s = s + dNq[a * DIM + j] * dof((DIM + c) * NA + a);
-      Gu[j] = s;
-    }
+  for (int c = 0; c < DIM; ++c)
 #pragma unroll
     for (int b = 0; b < DIM; ++b) {
       V s = V{};
 #pragma unroll
-      for (int j = 0; j < DIM; ++j) s = s + Gu[j] * k.Fi[j][b];
+      for (int j = 0; j < DIM; ++j) s = s + Gu[c][j] * k.Fi[j][b];
       k.gu[c][b] = s;
     }
+}
+
+// kinematics of the state at t_n from its shared sums
+template <int DIM>
+__device__ __forceinline__ void kin_value(const double *S, bool fluid, KinD<DIM, double> &k) {
+  using SS = Sums<DIM>;
+  double Gd[DIM][DIM], Gu[DIM][DIM];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      Gd[c][j] = S[SS::GD + c * DIM + j];
+      Gu[c][j] = S[SS::GU + c * DIM + j];
+    }
+    k.uq[c] = S[SS::UQ + c];
+    k.dq[c] = S[SS::DQ + c];
   }
+  k.pq = S[SS::PQ];
+  kin_finish<DIM>(Gd, Gu, fluid, k);
+}
+
+// kinematics of the current state differentiated along local dof jd: the
+// shared value sums plus the one term that dof contributes to each
+template <int DIM>
+__device__ __forceinline__ void kin_dual(const double *S, const double *Nq, const double *dNq, const double *ps,
+                                         int jd, bool fluid, KinD<DIM, D1> &k) {
+  constexpr int NA = Shape<DIM>::NA;
+  using SS = Sums<DIM>;
+  const bool isd = jd < DIM * NA, isv = !isd && jd < 2 * DIM * NA, isp = jd >= 2 * DIM * NA;
+  const int tc = isd ? jd / NA : (isv ? (jd - DIM * NA) / NA : -1);
+  const int ta = isp ? 0 : jd % NA;
+  const double nq = Nq[ta], pp = isp ? ps[jd - 2 * DIM * NA] : 0.0;
+  double dn[DIM];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) dn[j] = dNq[ta * DIM + j];
+  D1 Gd[DIM][DIM], Gu[DIM][DIM];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      Gd[c][j] = {S[SS::GD + c * DIM + j], isd && c == tc ? dn[j] : 0.0};
+      Gu[c][j] = {S[SS::GU + c * DIM + j], isv && c == tc ? dn[j] : 0.0};
+    }
+    k.uq[c] = {S[SS::UQ + c], isv && c == tc ? nq : 0.0};
+    k.dq[c] = {S[SS::DQ + c], isd && c == tc ? nq : 0.0};
+  }
+  k.pq = {S[SS::PQ], pp};
+  kin_finish<DIM>(Gd, Gu, fluid, k);
 }
 
 // structural coupling of local row lr with local column lc (the builder's rule)
@@ -148,223 +203,279 @@ __device__ __forceinline__ bool coupled_d(int dim, int na, bool solid, bool tran
   return cblk == 0;
 }
 
-// Element residual rows [r0, r0 + RC) with their derivative along local dof
-// jd, the formulas of the host builder (steady, or one Crank-Nicolson step
-// from the state ye0 at t_n to ye at t_{n+1}).
-template <int DIM, int RC>
-__device__ __forceinline__ void element_rows(const AsmView &v, bool solid, const double *ye, const double *ye0, int jd, int r0,
-                             const double *sN, const double *sdN, const double *spsi, const double *sw,
-                             D1 (&rows)[RC]) {
-  constexpr int NA = Shape<DIM>::NA, NP = Shape<DIM>::NP, NQ = Shape<DIM>::NQ;
-  const bool cn = ye0 != nullptr;
+// Every element residual row is a sum over the quadrature points of one test
+// function (N_a, or psi_j for the pressure rows) and its reference gradient
+// weighted by a few per-point coefficients: for the momentum rows of
+// component c the coefficients of N_a and of dN_a/dX_j, likewise for the mesh
+// motion (fluid) or kinematic (solid) rows, and one coefficient for the
+// pressure rows.  Their derivatives along a local dof follow from the
+// point's dual kinematics; the element Jacobian is then the contraction of
+// the test-function tables with these derivatives.
+template <int DIM>
+struct Terms {
+  static constexpr int K = 1 + DIM;   // N_a, dN_a/dX_0 .. dN_a/dX_{DIM-1}
+  static constexpr int MOM = 0, MESH = DIM * K, PR = 2 * DIM * K, NK = PR + 1;
+};
+
+// The coefficients of one point for one column of the element: their
+// derivatives along local dof jd, or with value set their values (the
+// residual), the formulas of the host builder (steady, or one Crank-Nicolson
+// step when sums0, the sums of the state at t_n, is given).
+template <int DIM>
+__device__ __forceinline__ void point_terms(const AsmView &v, bool solid, const double *sums, const double *sums0,
+                                            const double *Nq, const double *dNq, const double *ps, double w, int jd,
+                                            bool value, double *out) {
+  using T = Terms<DIM>;
+  const bool cn = sums0 != nullptr;
   const double dt = v.dt, rho = v.rho, mu = v.mu;
   const double k_ale = 1.0 / v.vol;
-#pragma unroll
-  for (int i = 0; i < RC; ++i) rows[i] = dc(0.0);
-  auto dof1 = [&](int i) -> D1 { return {ye[i], i == jd ? 1.0 : 0.0}; };
-  auto dof0 = [&](int i) -> double { return ye0[i]; };
-  for (int q = 0; q < NQ; ++q) {
-    const double *Nq = sN + q * NA, *dNq = sdN + q * NA * DIM, *ps = spsi + q * NP;
-    const double w = sw[q];
-    KinD<DIM, D1> k1;
-    kin<DIM>(Nq, dNq, ps, dof1, !solid, k1);
-    // per-point quantities of the rows: momentum (S, Tm), mesh motion /
-    // kinematics (A), continuity / incompressibility (Pr)
-    D1 S[DIM], Tm[DIM][DIM], A[DIM], Pr;
-    double Tm0[DIM][DIM];
-    bool with_S = true;
-    if (!solid) {
-      D1 sig1[DIM][DIM];
-      for (int c = 0; c < DIM; ++c)
-        for (int b = 0; b < DIM; ++b) {
-          sig1[c][b] = mu * (k1.gu[c][b] + k1.gu[b][c]);
-          if (b == c) sig1[c][b] = sig1[c][b] - k1.pq;
-        }
-      const D1 wJ1 = w * k1.det;
-      if (!cn) {
-        for (int c = 0; c < DIM; ++c) {
-          D1 t = dc(0.0);
-          for (int b = 0; b < DIM; ++b) t = t + k1.gu[c][b] * k1.uq[b];
-          S[c] = rho * (wJ1 * t);
-          for (int j = 0; j < DIM; ++j) {
-            D1 t2 = dc(0.0);
-            for (int b = 0; b < DIM; ++b) t2 = t2 + sig1[c][b] * k1.Fi[j][b];
-            Tm[c][j] = wJ1 * t2;
-            Tm0[c][j] = 0.0;
-          }
-        }
-      } else {
-        KinD<DIM, double> k0;
-        kin<DIM>(Nq, dNq, ps, dof0, true, k0);
-        double sig0[DIM][DIM];
-        for (int c = 0; c < DIM; ++c)
-          for (int b = 0; b < DIM; ++b) {
-            sig0[c][b] = mu * (k0.gu[c][b] + k0.gu[b][c]);
-            if (b == c) sig0[c][b] -= k0.pq;
-          }
-        const double wJ0 = w * k0.det;
-        D1 wq[DIM], Gw[DIM][DIM];
-        for (int c = 0; c < DIM; ++c) {
-          wq[c] = (1.0 / dt) * k1.dq[c] + (-k0.dq[c] / dt);
-          for (int j = 0; j < DIM; ++j) Gw[c][j] = (1.0 / dt) * k1.Gd[c][j] + (-k0.Gd[c][j] / dt);
-        }
-        D1 divw1 = dc(0.0), divw0 = dc(0.0);
-        for (int c = 0; c < DIM; ++c)
-          for (int j = 0; j < DIM; ++j) {
-            divw1 = divw1 + Gw[c][j] * k1.Fi[j][c];
-            divw0 = divw0 + k0.Fi[j][c] * Gw[c][j];
-          }
-        for (int c = 0; c < DIM; ++c) {
-          D1 t1 = -(divw1 * k1.uq[c]);
-          for (int b = 0; b < DIM; ++b) t1 = t1 + k1.gu[c][b] * k1.uq[b] - k1.gu[c][b] * wq[b];
-          t1 = (0.5 * rho) * t1 + (rho / dt) * k1.uq[c];
-          D1 t2 = (-k0.uq[c]) * divw0;
-          for (int b = 0; b < DIM; ++b) t2 = t2 + k0.gu[c][b] * k0.uq[b] + (-k0.gu[c][b]) * wq[b];
-          t2 = (0.5 * rho) * t2 + (-(rho / dt) * k0.uq[c]);
-          S[c] = wJ1 * t1 + wJ0 * t2;
-          for (int j = 0; j < DIM; ++j) {
-            D1 s1 = dc(0.0);
-            double c0 = 0.0;
-            for (int b = 0; b < DIM; ++b) {
-              s1 = s1 + sig1[c][b] * k1.Fi[j][b];
-              c0 += sig0[c][b] * k0.Fi[j][b];
-            }
-            Tm[c][j] = 0.5 * (wJ1 * s1);
-            Tm0[c][j] = 0.5 * wJ0 * c0;
-          }
+  KinD<DIM, D1> k1;
+  kin_dual<DIM>(sums, Nq, dNq, ps, jd, !solid, k1);
+  // per-point quantities of the rows: momentum (S, Tm), mesh motion /
+  // kinematics (A), continuity / incompressibility (Pr)
+  D1 S[DIM], Tm[DIM][DIM], A[DIM], Pr;
+  double Tm0[DIM][DIM];
+  bool with_S = true;
+  if (!solid) {
+    D1 sig1[DIM][DIM];
+    for (int c = 0; c < DIM; ++c)
+      for (int b = 0; b < DIM; ++b) {
+        sig1[c][b] = mu * (k1.gu[c][b] + k1.gu[b][c]);
+        if (b == c) sig1[c][b] = sig1[c][b] - k1.pq;
+      }
+    const D1 wJ1 = w * k1.det;
+    if (!cn) {
+      for (int c = 0; c < DIM; ++c) {
+        D1 t = dc(0.0);
+        for (int b = 0; b < DIM; ++b) t = t + k1.gu[c][b] * k1.uq[b];
+        S[c] = rho * (wJ1 * t);
+        for (int j = 0; j < DIM; ++j) {
+          D1 t2 = dc(0.0);
+          for (int b = 0; b < DIM; ++b) t2 = t2 + sig1[c][b] * k1.Fi[j][b];
+          Tm[c][j] = wJ1 * t2;
+          Tm0[c][j] = 0.0;
         }
       }
-      for (int c = 0; c < DIM; ++c) A[c] = dc(0.0);   // the mesh motion uses Gd directly
-      D1 div = dc(0.0);
-      for (int c = 0; c < DIM; ++c) div = div + k1.gu[c][c];
-      Pr = wJ1 * div;
     } else {
-      // Piola stress J sigma F^{-T}, sigma = -p I + mu_s F F^T
-      D1 sig[DIM][DIM];
+      KinD<DIM, double> k0;
+      kin_value<DIM>(sums0, true, k0);
+      double sig0[DIM][DIM];
       for (int c = 0; c < DIM; ++c)
         for (int b = 0; b < DIM; ++b) {
-          D1 s = dc(0.0);
-          for (int j = 0; j < DIM; ++j) s = s + k1.F[c][j] * k1.F[b][j];
-          sig[c][b] = v.mu_s * s;
-          if (b == c) sig[c][b] = sig[c][b] - k1.pq;
+          sig0[c][b] = mu * (k0.gu[c][b] + k0.gu[b][c]);
+          if (b == c) sig0[c][b] -= k0.pq;
         }
+      const double wJ0 = w * k0.det;
+      D1 wq[DIM], Gw[DIM][DIM];
+      for (int c = 0; c < DIM; ++c) {
+        wq[c] = (1.0 / dt) * k1.dq[c] + (-k0.dq[c] / dt);
+        for (int j = 0; j < DIM; ++j) Gw[c][j] = (1.0 / dt) * k1.Gd[c][j] + (-k0.Gd[c][j] / dt);
+      }
+      D1 divw1 = dc(0.0), divw0 = dc(0.0);
       for (int c = 0; c < DIM; ++c)
-        for (int b = 0; b < DIM; ++b) {
-          D1 s = dc(0.0);
-          for (int j = 0; j < DIM; ++j) s = s + sig[c][j] * k1.Fi[b][j];
-          Tm[c][b] = k1.det * s;
-          Tm0[c][b] = 0.0;
+        for (int j = 0; j < DIM; ++j) {
+          divw1 = divw1 + Gw[c][j] * k1.Fi[j][c];
+          divw0 = divw0 + k0.Fi[j][c] * Gw[c][j];
         }
-      with_S = cn;
-      if (cn) {
-        KinD<DIM, double> k0;
-        kin<DIM>(Nq, dNq, ps, dof0, false, k0);
-        double sg0[DIM][DIM];
-        for (int c = 0; c < DIM; ++c)
+      for (int c = 0; c < DIM; ++c) {
+        D1 t1 = -(divw1 * k1.uq[c]);
+        for (int b = 0; b < DIM; ++b) t1 = t1 + k1.gu[c][b] * k1.uq[b] - k1.gu[c][b] * wq[b];
+        t1 = (0.5 * rho) * t1 + (rho / dt) * k1.uq[c];
+        D1 t2 = (-k0.uq[c]) * divw0;
+        for (int b = 0; b < DIM; ++b) t2 = t2 + k0.gu[c][b] * k0.uq[b] + (-k0.gu[c][b]) * wq[b];
+        t2 = (0.5 * rho) * t2 + (-(rho / dt) * k0.uq[c]);
+        S[c] = wJ1 * t1 + wJ0 * t2;
+        for (int j = 0; j < DIM; ++j) {
+          D1 s1 = dc(0.0);
+          double c0 = 0.0;
           for (int b = 0; b < DIM; ++b) {
-            double s = 0.0;
-            for (int j = 0; j < DIM; ++j) s += k0.F[c][j] * k0.F[b][j];
-            sg0[c][b] = v.mu_s * s - (b == c ? k0.pq : 0.0);
+            s1 = s1 + sig1[c][b] * k1.Fi[j][b];
+            c0 += sig0[c][b] * k0.Fi[j][b];
           }
-        for (int c = 0; c < DIM; ++c) {
-          for (int b = 0; b < DIM; ++b) {
-            double s = 0.0;
-            for (int j = 0; j < DIM; ++j) s += sg0[c][j] * k0.Fi[b][j];
-            Tm0[c][b] = k0.det * s;
-          }
-          S[c] = (v.rho_s / dt) * (k1.det * k1.uq[c] + (-k0.det * k0.uq[c]));
-          A[c] = (-1.0 / dt) * k1.dq[c] + 0.5 * k1.uq[c] + (k0.dq[c] / dt + 0.5 * k0.uq[c]);
-        }
-      } else {
-        for (int c = 0; c < DIM; ++c) {
-          S[c] = dc(0.0);
-          A[c] = k1.uq[c];
+          Tm[c][j] = 0.5 * (wJ1 * s1);
+          Tm0[c][j] = 0.5 * wJ0 * c0;
         }
       }
-      Pr = k1.det + (-1.0);
     }
-    const double half = (solid && cn) ? 0.5 : 1.0;
-
-    // this thread's rows
+    for (int c = 0; c < DIM; ++c) A[c] = dc(0.0);   // the mesh motion uses Gd directly
+    D1 div = dc(0.0);
+    for (int c = 0; c < DIM; ++c) div = div + k1.gu[c][c];
+    Pr = wJ1 * div;
+  } else {
+    // Piola stress J sigma F^{-T}, sigma = -p I + mu_s F F^T
+    D1 sig[DIM][DIM];
+    for (int c = 0; c < DIM; ++c)
+      for (int b = 0; b < DIM; ++b) {
+        D1 s = dc(0.0);
+        for (int j = 0; j < DIM; ++j) s = s + k1.F[c][j] * k1.F[b][j];
+        sig[c][b] = v.mu_s * s;
+        if (b == c) sig[c][b] = sig[c][b] - k1.pq;
+      }
+    for (int c = 0; c < DIM; ++c)
+      for (int b = 0; b < DIM; ++b) {
+        D1 s = dc(0.0);
+        for (int j = 0; j < DIM; ++j) s = s + sig[c][j] * k1.Fi[b][j];
+        Tm[c][b] = k1.det * s;
+        Tm0[c][b] = 0.0;
+      }
+    with_S = cn;
+    if (cn) {
+      KinD<DIM, double> k0;
+      kin_value<DIM>(sums0, false, k0);
+      double sg0[DIM][DIM];
+      for (int c = 0; c < DIM; ++c)
+        for (int b = 0; b < DIM; ++b) {
+          double s = 0.0;
+          for (int j = 0; j < DIM; ++j) s += k0.F[c][j] * k0.F[b][j];
+          sg0[c][b] = v.mu_s * s - (b == c ? k0.pq : 0.0);
+        }
+      for (int c = 0; c < DIM; ++c) {
+        for (int b = 0; b < DIM; ++b) {
+          double s = 0.0;
+          for (int j = 0; j < DIM; ++j) s += sg0[c][j] * k0.Fi[b][j];
+          Tm0[c][b] = k0.det * s;
+        }
+        S[c] = (v.rho_s / dt) * (k1.det * k1.uq[c] + (-k0.det * k0.uq[c]));
+        A[c] = (-1.0 / dt) * k1.dq[c] + 0.5 * k1.uq[c] + (k0.dq[c] / dt + 0.5 * k0.uq[c]);
+      }
+    } else {
+      for (int c = 0; c < DIM; ++c) {
+        S[c] = dc(0.0);
+        A[c] = k1.uq[c];
+      }
+    }
+    Pr = k1.det + (-1.0);
+  }
+  const double half = (solid && cn) ? 0.5 : 1.0;
+  auto put = [&](int i, D1 x) { out[i] = value ? x.v : x.g; };
 #pragma unroll
-    for (int i = 0; i < RC; ++i) {
-      const int lr = r0 + i;
-      if (lr >= Shape<DIM>::NL) break;
-      if (lr < DIM * NA) {   // momentum
-        const int cl = lr / NA, a = lr % NA;
-        D1 t = dc(0.0);
-        // the component as a compile-time constant in each branch, so that
-        // every per-point array is indexed by constants and stays in registers
+  for (int c = 0; c < DIM; ++c) {
+    if (!solid) {
+      put(T::MOM + c * T::K, S[c]);
+      put(T::MESH + c * T::K, dc(0.0));
 #pragma unroll
-        for (int c = 0; c < DIM; ++c)
-          if (c == cl) {
-            if (!solid) {
-              t = Nq[a] * S[c];
-              for (int j = 0; j < DIM; ++j) t = t + dNq[a * DIM + j] * Tm[c][j] + dNq[a * DIM + j] * Tm0[c][j];
-            } else {
-              if (with_S) t = (w * Nq[a]) * S[c];
-              for (int b = 0; b < DIM; ++b)
-                t = t + (half * w * dNq[a * DIM + b]) * Tm[c][b] + half * w * dNq[a * DIM + b] * Tm0[c][b];
-            }
-          }
-        rows[i] = rows[i] + t;
-      } else if (lr < 2 * DIM * NA) {   // mesh motion (fluid) / kinematics (solid)
-        const int cl = (lr - DIM * NA) / NA, a = (lr - DIM * NA) % NA;
-        D1 t = dc(0.0);
+      for (int j = 0; j < DIM; ++j) {
+        put(T::MOM + c * T::K + 1 + j, Tm[c][j] + Tm0[c][j]);
+        put(T::MESH + c * T::K + 1 + j, (w * k_ale) * k1.Gd[c][j]);
+      }
+    } else {
+      put(T::MOM + c * T::K, with_S ? w * S[c] : dc(0.0));
+      put(T::MESH + c * T::K, w * A[c]);
 #pragma unroll
-        for (int c = 0; c < DIM; ++c)
-          if (c == cl) {
-            if (!solid) {
-              for (int b = 0; b < DIM; ++b) t = t + (w * k_ale * dNq[a * DIM + b]) * k1.Gd[c][b];
-            } else {
-              t = (w * Nq[a]) * A[c];
-            }
-          }
-        rows[i] = rows[i] + t;
-      } else {   // continuity / incompressibility
-        const int j = lr - 2 * DIM * NA;
-        rows[i] = rows[i] + (solid ? (w * ps[j]) * Pr : ps[j] * Pr);
+      for (int j = 0; j < DIM; ++j) {
+        put(T::MOM + c * T::K + 1 + j, (half * w) * (Tm[c][j] + Tm0[c][j]));
+        put(T::MESH + c * T::K + 1 + j, dc(0.0));
       }
     }
   }
+  put(T::PR, solid ? w * Pr : Pr);
 }
 
-template <int DIM, int RC, int NT>
+// Assembly of one element, columns [c0, c0 + DC) of its Jacobian, column NL
+// standing for the residual.  Phase 1: the point sums of the element state
+// (and of the state at t_n).  Phase 2: the coefficients of every (column,
+// point) pair into LDS.  Phase 3: each thread contracts one row's test
+// function with CPT columns' coefficients and adds the results at the
+// positions the map gives (-1: not stored).  Elements of one colour share no
+// node, so no two threads of a launch add to one entry.
+template <int DIM, int DC, int CPT, int NT>
 __global__ __launch_bounds__(NT) void k_assemble(AsmView v, const double *__restrict__ y, double *__restrict__ r,
-                                                 double *__restrict__ jval, int cbase, int nsplit) {
+                                                 double *__restrict__ jval, const int *__restrict__ map, int cbase,
+                                                 int nsplit) {
   constexpr int NA = Shape<DIM>::NA, NP = Shape<DIM>::NP, NL = Shape<DIM>::NL, NQ = Shape<DIM>::NQ;
-  constexpr int NCH = (NL + RC - 1) / RC;
+  constexpr int NS = Sums<DIM>::NS, NK = Terms<DIM>::NK, K = Terms<DIM>::K;
+  static_assert(DC % CPT == 0, "columns per thread must divide the columns per block");
   __shared__ double ye[NL], ye0[NL];
-  __shared__ int g[NL], tg[NL];
+  __shared__ int tg[NL];
   __shared__ double sN[NQ * NA], sdN[NQ * NA * DIM], spsi[NQ * NP], sw[NQ];
+  __shared__ double sums[NQ * NS], sums0[NQ * NS];
+  __shared__ double terms[DC * NQ * NK];
   const int e = v.color_elems[cbase + blockIdx.x / nsplit];
-  const int t = (blockIdx.x % nsplit) * NT + threadIdx.x;
+  const int c0 = (blockIdx.x % nsplit) * DC;
   const bool solid = v.solid[e] != 0;
   for (int i = threadIdx.x; i < NL; i += NT) {
-    g[i] = v.l2g[(int64_t)e * NL + i];
+    const int g = v.l2g[(int64_t)e * NL + i];
     tg[i] = v.tgt[(int64_t)e * NL + i];
-    ye[i] = y[g[i]];
-    ye0[i] = v.transient ? v.yprev[g[i]] : 0.0;
+    ye[i] = y[g];
+    ye0[i] = v.transient ? v.yprev[g] : 0.0;
   }
   for (int i = threadIdx.x; i < NQ * NA; i += NT) sN[i] = v.N[i];
   for (int i = threadIdx.x; i < NQ * NA * DIM; i += NT) sdN[i] = v.dN[i];
   for (int i = threadIdx.x; i < NQ * NP; i += NT) spsi[i] = v.psi[i];
   for (int i = threadIdx.x; i < NQ; i += NT) sw[i] = v.w[i];
   __syncthreads();
-  if (t >= NL * NCH) return;
-  const int jd = t / NCH, r0 = (t % NCH) * RC;
-  D1 rows[RC];
-  element_rows<DIM, RC>(v, solid, ye, v.transient ? ye0 : nullptr, jd, r0, sN, sdN, spsi, sw, rows);
-  const int gc = g[jd];
-  const bool col_free = !v.dir[gc];
+  for (int i = threadIdx.x; i < NQ * NS; i += NT) {
+    sums[i] = point_sum<DIM>(sN, sdN, spsi, ye, i / NS, i % NS);
+    if (v.transient) sums0[i] = point_sum<DIM>(sN, sdN, spsi, ye0, i / NS, i % NS);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < DC * NQ; i += NT) {
+    const int cl = i / NQ, q = i % NQ, col = c0 + cl;
+    if (col > NL) continue;
+    point_terms<DIM>(v, solid, sums + q * NS, v.transient ? sums0 + q * NS : nullptr, sN + q * NA,
+                     sdN + q * NA * DIM, spsi + q * NP, sw[q], col == NL ? 0 : col, col == NL, terms + i * NK);
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < NL * (DC / CPT); it += NT) {
+    const int lr = it % NL, cg = (it / NL) * CPT;
+    // the row's test function: offset of its coefficients, node, and how many
+    int off, a, nk;
+    if (lr < 2 * DIM * NA) {
+      const int blk = lr / (DIM * NA), c = (lr % (DIM * NA)) / NA;
+      off = (blk == 0 ? Terms<DIM>::MOM : Terms<DIM>::MESH) + c * K;
+      a = lr % NA;
+      nk = K;
+    } else {
+      off = Terms<DIM>::PR;
+      a = lr - 2 * DIM * NA;
+      nk = 1;
+    }
+    double acc[CPT];
 #pragma unroll
-  for (int i = 0; i < RC; ++i) {
-    const int lr = r0 + i;
-    if (lr >= NL) break;
+    for (int k = 0; k < CPT; ++k) acc[k] = 0.0;
+    for (int q = 0; q < NQ; ++q) {
+      const double *tq = terms + (cg * NQ + q) * NK + off;
+      if (nk == 1) {
+        const double f = spsi[q * NP + a];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) acc[k] += f * tq[k * NQ * NK];
+      } else {
+        double f[K];
+        f[0] = sN[q * NA + a];
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) f[1 + j] = sdN[(q * NA + a) * DIM + j];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+#pragma unroll
+          for (int j = 0; j < K; ++j) acc[k] += f[j] * tq[k * NQ * NK + j];
+      }
+    }
     const int tr = tg[lr];
-    if (tr < 0) continue;
-    if (jd == 0) r[tr] += rows[i].v;
-    if (v.dir[tr] || !col_free || !coupled_d(DIM, NA, solid, v.transient != 0, lr, jd)) continue;
+    const int *mrow = map + ((int64_t)e * NL + lr) * NL;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int col = c0 + cg + k;
+      if (col < NL) {
+        const int pos = mrow[col];
+        if (pos >= 0) jval[pos] += acc[k];
+      } else if (col == NL && tr >= 0) {
+        r[tr] += acc[k];
+      }
+    }
+  }
+}
+
+// CSR position of every (element, local row, local column) entry of the
+// element Jacobian that the assembly stores, else -1: rows without a target,
+// Dirichlet rows and columns, and structurally uncoupled pairs are not stored.
+__global__ void k_asm_map(AsmView v, int dim, int na, int nl, int64_t total, int *map) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= total) return;
+  const int64_t el = idx / nl;
+  const int e = (int)(el / nl), lr = (int)(el % nl), jd = (int)(idx % nl);
+  const int tr = v.tgt[(int64_t)e * nl + lr], gc = v.l2g[(int64_t)e * nl + jd];
+  int pos = -1;
+  if (tr >= 0 && !v.dir[tr] && !v.dir[gc] && coupled_d(dim, na, v.solid[e] != 0, v.transient != 0, lr, jd)) {
     int lo = v.rowptr[tr], hi = v.rowptr[tr + 1];
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
@@ -373,8 +484,9 @@ __global__ __launch_bounds__(NT) void k_assemble(AsmView v, const double *__rest
       else
         hi = mid;
     }
-    if (lo < v.rowptr[tr + 1] && v.col[lo] == gc) jval[lo] += rows[i].g;
+    if (lo < v.rowptr[tr + 1] && v.col[lo] == gc) pos = lo;
   }
+  map[idx] = pos;
 }
 
 // Dirichlet rows: r = y - g and a unit diagonal
@@ -425,17 +537,19 @@ struct Assembly {
   double *d_dir_val = nullptr;
   double *b = nullptr, *x = nullptr, *r = nullptr, *partial = nullptr, *nrm = nullptr;
   double *yprev = nullptr;   // the state at t_n of a time step (the view reads it), else null
+  int *map = nullptr;        // CSR positions of the element Jacobians' entries (ne x nl x nl), -1 if not stored
   AsmMem mem;
 };
 
-template <int DIM, int RC, int NT>
+template <int DIM, int DC, int CPT, int NT>
 static void launch_assemble_dim(Assembly &A, const double *y, double *r, double *jval, hipStream_t st) {
-  constexpr int NL = Shape<DIM>::NL, NCH = (NL + RC - 1) / RC;
-  const int nsplit = (NL * NCH + NT - 1) / NT;
+  constexpr int NL = Shape<DIM>::NL;
+  const int nsplit = (NL + 1 + DC - 1) / DC;   // the element's columns and the residual
   for (int c = 0; c < A.v.ncolor; ++c) {
     const int n = A.h_color_ptr[c + 1] - A.h_color_ptr[c];
     if (n > 0)
-      k_assemble<DIM, RC, NT><<<n * nsplit, NT, 0, st>>>(A.v, y, r, jval, A.h_color_ptr[c], nsplit);
+      k_assemble<DIM, DC, CPT, NT>
+          <<<n * nsplit, NT, 0, st>>>(A.v, y, r, jval, A.map, A.h_color_ptr[c], nsplit);
   }
 }
 
@@ -443,9 +557,9 @@ static void assemble(Assembly &A, const double *y, double *r, double *jval, hipS
   launch_fill_f64(r, A.v.ndof, 0.0, st);
   launch_fill_f64(jval, A.nnz, 0.0, st);
   if (A.dim == 2)
-    launch_assemble_dim<2, 39, 64>(A, y, r, jval, st);
+    launch_assemble_dim<2, 40, 10, 192>(A, y, r, jval, st);   // the whole element in one workgroup
   else
-    launch_assemble_dim<3, 10, 256>(A, y, r, jval, st);   // 10 rows a thread: the most without spilling
+    launch_assemble_dim<3, 16, 8, 256>(A, y, r, jval, st);
   if (A.ndir)
     k_dirichlet_rows<<<(A.ndir + 255) / 256, 256, 0, st>>>(A.d_dir_rows, A.d_dir_diag, A.ndir, y, A.d_dir_val, r,
                                                             jval);
@@ -518,7 +632,11 @@ static Assembly *create(const fsi_element_data &ed, const fsi_csr &J, hipStream_
   A->r = M.alloc<double>(n);
   A->partial = M.alloc<double>(krylov_blocks(n));
   A->nrm = M.alloc<double>(4);
-  (void)st;
+  const int64_t nmap = (int64_t)ed.ne * nl * nl;
+  A->map = M.alloc<int>(nmap);
+  k_asm_map<<<(unsigned)((nmap + 255) / 256), 256, 0, st>>>(v, ed.dim, na, nl, nmap, A->map);
+  hip_check(hipGetLastError(), "assembly map");
+  hip_check(hipStreamSynchronize(st), "assembly map");
   return A.release();
 }
 
