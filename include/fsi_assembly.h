@@ -29,17 +29,22 @@ struct fsi_assembly;
 /* Uploads the element data and the pattern (host arrays, copied) on the
  * current HIP device.  J: the finest Jacobian's CSR (only rowptr, colind
  * and the sizes are read), holding every coupled entry of the element
- * residuals and the unit diagonal of every Dirichlet row.  Errors:
- * FSI_E_INVALID (null or inconsistent sizes, dim not 2 or 3), FSI_E_OOM,
- * FSI_E_DEVICE. */
+ * residuals and the unit diagonal of every Dirichlet row.  Besides copies of
+ * the inputs the assembler holds the CSR position of every element Jacobian
+ * entry (4 * ne * nl^2 bytes: 25 MB for 4,096 2D elements, 226 MB for 2,048
+ * 3D ones), found once here; the call returns after that work is done on
+ * hip_stream.  Errors: FSI_E_INVALID (null or inconsistent sizes, dim not 2
+ * or 3), FSI_E_OOM, FSI_E_DEVICE. */
 fsi_status fsi_assembly_create(const fsi_element_data *ed, const fsi_csr *J, void *hip_stream,
                                struct fsi_assembly **out);
 
 /* r = R(y) (ndof doubles) and the values of J = dR/dy in the pattern's order
  * (nnz doubles), all device arrays, stream-ordered on hip_stream.  Dirichlet
- * rows: r_i = y_i - g_i and a unit diagonal.  One launch per element colour;
- * each thread differentiates its element's residual along one local dof, so
- * every entry is written once (no atomics, the same result every run).
+ * rows: r_i = y_i - g_i and a unit diagonal.  One launch per element colour:
+ * the element residual's per-point coefficients differentiated along each
+ * local dof (forward mode), then contracted with the test functions; every
+ * entry is written by one thread per colour (no atomics, the same result
+ * every run).
  * Errors: FSI_E_INVALID (null), FSI_E_DEVICE. */
 fsi_status fsi_assembly_run(struct fsi_assembly *a, const double *y_dev, double *r_dev, double *jval_dev,
                             void *hip_stream);
