@@ -57,10 +57,11 @@ def gj_kernel_digest():
     return hashlib.sha256(src[:b].encode()).hexdigest()[:16]
 
 
-def measured_traffic(path=TRAFFIC_PROFILE, digest=ras_kernel_digest):
+def measured_traffic(path=TRAFFIC_PROFILE, digest=ras_kernel_digest, variant=None):
     """HBM bytes per launch of a kernel from a committed counter summary
     (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None when the
-    summary was taken on other kernel code."""
+    summary was taken on other kernel code (or, given variant, on another
+    kernel variant than the one that ran)."""
     try:
         txt = open(path).read()
     except OSError:
@@ -69,6 +70,10 @@ def measured_traffic(path=TRAFFIC_PROFILE, digest=ras_kernel_digest):
     d = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", txt)
     if not b or not d or d.group(1) != digest():
         return None
+    if variant is not None:
+        v = re.search(r"^variant:\s*(\d+)", txt, re.M)
+        if not v or int(v.group(1)) != variant:
+            return None
     return int(b.group(1))
 
 
@@ -76,7 +81,9 @@ def measured_traffic(path=TRAFFIC_PROFILE, digest=ras_kernel_digest):
 # the trailing block once per panel: 2 sizeof(T) m^3 / NB bytes per block)
 GJ_VARIANTS = {1: ("NB16 x 256, FP64", 16, 8), 2: ("NB16 x 512, FP64", 16, 8),
                3: ("NB32 x 512, LDS panel, FP64", 32, 8), 4: ("wide panel from the block, FP64", 32, 8),
-               5: ("NB24 x 512, LDS panel, FP64", 24, 8), 11: ("NB64 x 512, FP32", 64, 4),
+               5: ("NB24 x 512, LDS panel, FP64", 24, 8),
+               6: ("NB32 pairs x 512, FP64", 64, 8),
+               11: ("NB64 x 512, FP32", 64, 4),
                12: ("NB32 x 512, FP32", 32, 4), 13: ("NB32 x 256 (2 rows/thread), FP32", 32, 4),
                14: ("NB32 x 512 (2 rows/thread), FP32", 32, 4), 15: ("NB48 x 512 (2 rows/thread), FP32", 48, 4)}
 
@@ -533,10 +540,10 @@ def gpu_leg(args):
         nb, wsize = GJ_VARIANTS[vid][1], GJ_VARIANTS[vid][2]
         gj_tflops = lu_flops / (gj_avg_ms * 1e-3) / 1e12 if gcnt else 0.0
         out["roofline"] = {
-            "bound": "mfma", "kernel": "k_gj_batched<double> (Gauss-Jordan inverse of all 336 Schwarz blocks, "
-                                       "FP64 matrix cores)",
+            "bound": "mfma", "kernel": ("k_gj_paired<double>" if vid == 6 else "k_gj_batched<double>") +
+                                      " (Gauss-Jordan inverse of all 336 Schwarz blocks, FP64 matrix cores)",
             "achieved": round(gj_tflops, 3), "peak": 78.6, "unit": "TFLOP/s",
-            "frac": round(gj_tflops / 78.6, 4), "traffic": measured_traffic(GJ_TRAFFIC_PROFILE, gj_kernel_digest),
+            "frac": round(gj_tflops / 78.6, 4), "traffic": measured_traffic(GJ_TRAFFIC_PROFILE, gj_kernel_digest, vid),
             "flops_per_launch": lu_flops, "flop_count": "2/3 sum m_k^3 (LU-equivalent work of the local solves)",
             "gauss_jordan_flops_per_launch": gj_flops,
             "frac_on_gauss_jordan_flops": round(gj_flops / (gj_avg_ms * 1e-3) / 1e12 / 78.6, 4) if gcnt else None,

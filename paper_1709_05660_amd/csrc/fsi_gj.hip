@@ -443,6 +443,208 @@ __global__ __launch_bounds__(NT) void k_gj_batched(T *__restrict__ blocks,
   }
 }
 
+// Applies a factored panel (steps [kb, kb + kw), its columns in the block,
+// pivot rows xrows[0..kw)) to a set of columns of an m x m block: the
+// columns [c_lo, c_lo + cn) when inside, else every column outside that
+// range.  Each wave owns the 16-row tiles wave, wave + NW, ... (at most RT)
+// and holds their panel rows (the A operand) in registers for the whole
+// update.  The columns go by chunks of CW; the chunk's X (the pivot rows'
+// old values) sits in LDS (Xs: two buffers of 4 KCX x CW, the next chunk's
+// read from the block while the current one is computed), and every wave
+// loads all its C tiles of the chunk, zeroes the pivot rows and accumulates
+// on the matrix cores.  One barrier per chunk.  Called by all NT threads;
+// ends with a barrier.
+template <typename T, int KCX, int NT, int RT, int CW>
+__device__ __forceinline__ void gj_apply_rows(T *__restrict__ A, int m, int kb, int kw, const int *xrows,
+                                              int c_lo, int cn, bool inside, const short *s_used, T *Xs) {
+  typedef Mfma16<T> MM;
+  typedef typename MM::acc acc;
+  constexpr int NW = NT / 64, NCT = CW / 16, KR = 4 * KCX, XE = (KR * CW + NT - 1) / NT;
+  static_assert(RT * KCX <= 64, "the panel rows of a wave's tiles must fit in registers");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int jl = lane & 15, kq = lane >> 4;
+  const int mp = inside ? cn : m - cn;
+  const int nrt = (m + 15) >> 4;
+  auto col = [&](int q) { return inside ? c_lo + q : (q < c_lo ? q : q + cn); };
+  T ah[RT][KCX];
+  unsigned keep = 0;   // bit 4 u + r: C row r of tile u is kept (exists, not a pivot row of the panel)
+#pragma unroll
+  for (int u = 0; u < RT; ++u) {
+    const int rt = wave + NW * u;
+    const int ia = min(rt * 16 + jl, m - 1);
+#pragma unroll
+    for (int kk = 0; kk < KCX; ++kk) {
+      const T x = A[ia * m + kb + min(kk * 4 + kq, kw - 1)];
+      ah[u][kk] = (rt * 16 + jl < m && kk * 4 + kq < kw) ? x : (T)0;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = rt * 16 + MM::row(r, kq);
+      const int su = s_used[min(i, m - 1)];
+      if (i < m && (su < kb || su >= kb + kw)) keep |= 1u << (4 * u + r);
+    }
+  }
+  // this thread's share of a chunk's X: element e = tid + x NT is (t, c) =
+  // (e / CW, e % CW); clamped loads, zeroed outside
+  auto load_x = [&](int q0, T (&xv)[XE]) {
+#pragma unroll
+    for (int x = 0; x < XE; ++x) {
+      const int e = tid + x * NT, t = e / CW, q = q0 + e % CW;
+      const T v = A[xrows[min(t, kw - 1)] * m + col(min(q, mp - 1))];
+      xv[x] = (e < KR * CW && t < kw && q < mp) ? v : (T)0;
+    }
+  };
+  auto store_x = [&](int buf, const T (&xv)[XE]) {
+#pragma unroll
+    for (int x = 0; x < XE; ++x) {
+      const int e = tid + x * NT;
+      if (e < KR * CW) Xs[buf * KR * CW + e] = xv[x];
+    }
+  };
+  {
+    T xv[XE];
+    load_x(0, xv);
+    store_x(0, xv);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int q0 = 0; q0 < mp; q0 += CW, buf ^= 1) {
+    int jc[NCT];
+    bool cok[NCT];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      const int q = q0 + ct * 16 + jl;
+      cok[ct] = q < mp;
+      jc[ct] = cok[ct] ? col(q) : c_lo;
+    }
+    acc c[RT][NCT];
+#pragma unroll
+    for (int u = 0; u < RT; ++u)
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          c[u][ct][r] = A[min((wave + NW * u) * 16 + MM::row(r, kq), m - 1) * m + jc[ct]];
+    // the next chunk's X: its columns are not touched by this chunk
+    const bool more = q0 + CW < mp;
+    T xv[XE];
+    if (more) load_x(q0 + CW, xv);
+    const T *X = Xs + buf * KR * CW;
+#pragma unroll
+    for (int u = 0; u < RT; ++u) {
+      if (wave + NW * u >= nrt) continue;
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) {
+        acc cc = c[u][ct];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (!((keep >> (4 * u + r)) & 1u)) cc[r] = 0;
+#pragma unroll
+        for (int kk = 0; kk < KCX; ++kk) cc = MM::mma(ah[u][kk], X[(kk * 4 + kq) * CW + ct * 16 + jl], cc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = (wave + NW * u) * 16 + MM::row(r, kq);
+          if (cok[ct] && i < m) A[i * m + jc[ct]] = cc[r];
+        }
+      }
+    }
+    if (more) store_x(buf ^ 1, xv);
+    __syncthreads();
+  }
+}
+
+// The batched inversion with paired panels: two panels of NB columns are
+// factored one after the other, each applied at once only to the other's
+// columns, and the pair then acts on the rest of the block as one panel of
+// 2 NB columns (its pivot rows' old values as X).  The block is streamed once
+// per 2 NB pivots instead of once per NB, with the same matrix-core work;
+// the result is the same elimination up to rounding (the rest columns take
+// the pair's two rank-NB products as one sum).  Schedule, layouts and
+// outputs as k_gj_batched.
+template <typename T, int NB, int R, int NT>
+__global__ __launch_bounds__(NT) void k_gj_paired(T *__restrict__ blocks, const int64_t *__restrict__ boff,
+                                                  const int *__restrict__ pm, const int64_t *__restrict__ poff,
+                                                  int *__restrict__ perm_all, int *__restrict__ used_all,
+                                                  int *__restrict__ status, const int *__restrict__ sched) {
+  constexpr int KC = NB / 4;
+  __shared__ PivotLds<NB, NT / 64, T> sh;
+  __shared__ short s_used[R * NT];
+  __shared__ int piv2[2 * NB];
+  constexpr int CW = 16, RT = (R * NT / 16 + NT / 64 - 1) / (NT / 64);
+  __shared__ T Xs[2 * 2 * NB * CW];
+  const int tid = threadIdx.x;
+  const int *list = sched + gridDim.x + 1;
+  for (int t = sched[blockIdx.x]; t < sched[blockIdx.x + 1]; ++t) {
+    const int k = list[t];
+    const int m = pm[k];
+    T *A = blocks + boff[k];
+    int *perm = perm_all + poff[k];
+    for (int i = tid; i < m; i += NT) s_used[i] = -1;
+    __syncthreads();
+    int fail = 0;
+    for (int P0 = 0; P0 < m && !fail; P0 += 2 * NB) {
+      const int W = min(2 * NB, m - P0);
+      for (int sub = 0; sub < 2; ++sub) {
+        const int p0 = P0 + sub * NB;
+        if (p0 >= P0 + W) break;
+        const int w = min(NB, P0 + W - p0);
+        T v[R][NB];
+        int stp[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = tid + q * NT;
+          stp[q] = i < m ? s_used[i] : kNoRow;
+          const T *row = A + min(i, m - 1) * m + p0;
+#pragma unroll
+          for (int c = 0; c < NB; ++c) v[q][c] = row[c];
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+          for (int c = 0; c < NB; ++c)
+            if (c >= w) v[q][c] = 0;
+        int mypiv = 0;
+        fail = reg_panel<NB, R, NT, true, false>(v, stp, m, p0, w, sh, mypiv);
+        if (fail) break;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = tid + q * NT;
+          if (i < m) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+              if (c < w) A[i * m + p0 + c] = v[q][c];
+            if (stp[q] >= p0) s_used[i] = (short)stp[q];
+          }
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (tid < w) {
+          perm[p0 + tid] = sh.piv[tid];
+          piv2[sub * NB + tid] = sh.piv[tid];
+        }
+        // the pair's other columns: the second panel's after the first, the
+        // first's after the second
+        const int o0 = sub == 0 ? P0 + NB : P0, on = sub == 0 ? W - NB : NB;
+        if (on > 0) gj_apply_rows<T, KC, NT, RT, CW>(A, m, p0, w, sh.piv, o0, on, true, s_used, Xs);
+        __threadfence_block();
+        __syncthreads();
+      }
+      if (fail) break;
+      // the rest of the block: one update by the pair's 2 NB columns
+      gj_apply_rows<T, 2 * KC, NT, RT, CW>(A, m, P0, W, piv2, P0, W, false, s_used, Xs);
+      __threadfence_block();
+      __syncthreads();
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += NT) {
+      used_all[poff[k] + i] = fail ? i : s_used[i];
+      if (fail) perm[i] = i;
+    }
+    if (tid == 0) status[k] = fail;
+    __syncthreads();
+  }
+}
+
 static size_t gj_batched_lds(int mmax, int nb, size_t elem = sizeof(double)) {
   return (size_t)mmax * (nb + 1) * elem;
 }
@@ -465,8 +667,21 @@ static bool gj_lds_fits(int mmax) {
   return mmax <= R * NT && st >= 0 && st + (int64_t)gj_batched_lds(mmax, NB, sizeof(T)) <= 160 * 1024;
 }
 
+template <typename T, int NB, int R, int NT>
+static bool gj_paired_fits(int mmax) {
+  static const int64_t st = [] {
+    hipFuncAttributes a;
+    return hipFuncGetAttributes(&a, (const void *)k_gj_paired<T, NB, R, NT>) == hipSuccess
+               ? (int64_t)a.sharedSizeBytes
+               : (int64_t)-1;
+  }();
+  return mmax <= R * NT && st >= 0 && st <= 160 * 1024;
+}
+
 bool gj_variant_ok(int variant, int mmax) {
   switch (variant) {
+    case kGjP32x512:
+      return gj_paired_fits<double, 32, 1, 512>(mmax);
     case kGj16x256:
     case kGj16x512:
       return mmax <= 1024;
@@ -544,6 +759,15 @@ static void launch_gj_nbr(T *blocks, const int64_t *boff, const int *pm, const i
                         blocks, boff, pm, poff, perm, used, status, sched);
 }
 
+template <int NB, int R, int NT, typename T>
+static void launch_gj_paired(T *blocks, const int64_t *boff, const int *pm, const int64_t *poff, int *perm,
+                             int *used, int grid, const int *sched, int mmax, int *status, hipStream_t st,
+                             hipEvent_t ev0, hipEvent_t ev1) {
+  (void)mmax;
+  hipExtLaunchKernelGGL(k_gj_paired<T, NB, R, NT>, dim3(grid), dim3(NT), 0, st, ev0, ev1, 0, blocks, boff, pm,
+                        poff, perm, used, status, sched);
+}
+
 void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
                        int *perm, int *used, int npatch, int mmax, int *status, int grid,
                        const int *sched, hipStream_t st, int variant, hipEvent_t ev0, hipEvent_t ev1) {
@@ -558,7 +782,9 @@ void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const
   // update loads in flight per compute unit.  NB 32 (24 for two rows per
   // thread, the most that stays in registers): 1/2 (2/3) of the update
   // traffic of NB 16, the panel in LDS or read from the block.
-  if (variant == kGj32x512)
+  if (variant == kGjP32x512)
+    launch_gj_paired<32, 1, 512>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
+  else if (variant == kGj32x512)
     launch_gj_nbr<32, 1, 512, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
   else if (variant == kGjWideG && small)
     launch_gj_nbr<32, 1, 512, true, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax,

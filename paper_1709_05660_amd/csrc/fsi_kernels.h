@@ -52,7 +52,11 @@ void launch_extract(const double *val, int64_t nslots, const int *src, const int
 // (where m 25 doubles fit beside the static LDS, m <= ~790).  An
 // unsupported or zero variant falls back to the first that fits of NB 32,
 // NB 24 (both with the LDS panel) and NB 16 on 256 threads
+// Paired panels (k_gj_paired, blocks up to 512 dofs): two panels of NB 32
+// (one row per thread) factored in turn, the rest of the block updated once
+// per pair.
 enum GjVariant { kGjAuto = 0, kGj16x256 = 1, kGj16x512 = 2, kGj32x512 = 3, kGjWideG = 4, kGj24x512 = 5,
+                 kGjP32x512 = 6,
                  // FP32 working matrices (mixed forms): panel width x threads (x rows per thread)
                  kGjF64x512 = 11, kGjF32x512 = 12, kGjF32x256 = 13, kGjF32x512r2 = 14, kGjF48x512r2 = 15 };
 bool gj_variant_ok(int variant, int mmax);

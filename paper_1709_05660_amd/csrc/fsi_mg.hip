@@ -2200,7 +2200,7 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
       }
       const std::vector<int> vars =
           mg.mixed ? std::vector<int>{kGjF64x512, kGjF32x512, kGjF32x256, kGjF32x512r2, kGjF48x512r2}
-                   : std::vector<int>{kGj16x256, kGj16x512, kGj32x512, kGjWideG, kGj24x512};
+                   : std::vector<int>{kGj16x256, kGj16x512, kGj32x512, kGjWideG, kGj24x512, kGjP32x512};
       std::vector<std::tuple<float, int, int>> timed;   // (ms, variant, grid)
       for (int var : vars) {
         if (!gj_variant_ok(var, mg.mmax_all)) continue;

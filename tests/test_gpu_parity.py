@@ -325,7 +325,8 @@ def _forced_variant_vcycle(p, db, variant, r):
 @pytest.mark.parametrize("name", ["c1_2d_128x32", "c3_3d_32x8x8"])
 def test_every_block_inversion_variant(name, tmp_path):
     """Each batched Gauss-Jordan variant the autotuner may pick (panel width x
-    threads per block, panel in LDS or read from the block) gives the
+    threads per block, panel in LDS or read from the block, single or paired
+    panels) gives the
     checker's V-cycle; variants doing the same arithmetic in the same order
     (the two 16-column ones; the two 32-column ones) agree bit for bit."""
     from paper_1709_05660_amd import MG
@@ -341,7 +342,8 @@ def test_every_block_inversion_variant(name, tmp_path):
     r = rng.standard_normal(p.n)
     ref = osolver.vcycle(oh.levels, len(oh.levels) - 1, r, s.nu_pre, s.nu_post, s.omega)
     mmax = max(int(np.diff(p.patches(l)[0]).max()) for l in range(1, p.nlevels))
-    variants = [1, 2, 4, 5] + ([3] if mmax <= 512 else [])
+    # 6: paired panels of 32 columns (blocks up to 512 dofs)
+    variants = [1, 2, 4, 5] + ([3, 6] if mmax <= 512 else [])
     zs = {}
     for v in variants:
         _say(name, "variant", v, "mmax", mmax)
