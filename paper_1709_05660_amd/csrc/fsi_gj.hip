@@ -452,8 +452,9 @@ __global__ __launch_bounds__(NT) void k_gj_batched(T *__restrict__ blocks,
 // old values) sits in LDS (Xs: two buffers of 4 KCX x CW, the next chunk's
 // read from the block while the current one is computed), and every wave
 // loads all its C tiles of the chunk, zeroes the pivot rows and accumulates
-// on the matrix cores.  One barrier per chunk.  Called by all NT threads;
-// ends with a barrier.
+// on the matrix cores.  One barrier per chunk.  Called by all NT threads
+// (the early return for an empty column set is uniform); ends with a barrier
+// when it updates anything.
 template <typename T, int KCX, int NT, int RT, int CW>
 __device__ __forceinline__ void gj_apply_rows(T *__restrict__ A, int m, int kb, int kw, const int *xrows,
                                               int c_lo, int cn, bool inside, const short *s_used, T *Xs) {
@@ -464,6 +465,7 @@ __device__ __forceinline__ void gj_apply_rows(T *__restrict__ A, int m, int kb, 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int jl = lane & 15, kq = lane >> 4;
   const int mp = inside ? cn : m - cn;
+  if (mp <= 0) return;   // no column to update (a block of at most 2 NB dofs)
   const int nrt = (m + 15) >> 4;
   auto col = [&](int q) { return inside ? c_lo + q : (q < c_lo ? q : q + cn); };
   T ah[RT][KCX];

@@ -322,16 +322,20 @@ def _forced_variant_vcycle(p, db, variant, r):
     return z
 
 
-@pytest.mark.parametrize("name", ["c1_2d_128x32", "c3_3d_32x8x8"])
-def test_every_block_inversion_variant(name, tmp_path):
+@pytest.mark.parametrize("name,kw", [("c0_2d_16x4", {}), ("c0_2d_16x4", {"patch": 1}),
+                                     ("c1_2d_128x32", {}), ("c3_3d_32x8x8", {})])
+def test_every_block_inversion_variant(name, kw, tmp_path):
     """Each batched Gauss-Jordan variant the autotuner may pick (panel width x
     threads per block, panel in LDS or read from the block, single or paired
     panels) gives the
     checker's V-cycle; variants doing the same arithmetic in the same order
-    (the two 16-column ones; the two 32-column ones) agree bit for bit."""
+    (the two 16-column ones; the two 32-column ones) agree bit for bit.  The
+    16x4 system's blocks (73-89 dofs) end in a pair with one partial panel
+    or a single panel; with one-element patches (19-39 dofs) every block is
+    one pair and nothing is left for the pair's update of the rest."""
     from paper_1709_05660_amd import MG
-    p = product_problem(name)
-    oh = oracle_on_product(name)
+    p = product_problem(name, **kw)
+    oh = oracle_on_product(name, **kw)
     s = oh.spec
     db = str(tmp_path / "tune.db")
     mg = MG(p, precision="fp64")
