@@ -3,7 +3,8 @@ on the device (include/fsi_assembly.h; section "Monolithic Newton-Krylov
 solver with Multigrid-Richardson-Schwarz preconditioner").
 
 * The device assembly at the seeded state equals the host builder's finest
-  Jacobian and residual (steady and Crank-Nicolson, 2D and 3D); at a state
+  Jacobian and residual (steady and Crank-Nicolson, 2D and 3D, small and at
+  the bench's full sizes); at a state
   away from it, the checker's own assembly (complex-step Jacobian) is the
   reference.
 * Newton on the device (assembly, Galerkin products, refactor, FGMRES, update)
@@ -40,7 +41,12 @@ def _setup(name, kw):
     return s, a, p, Assembly(p)
 
 
-@pytest.mark.parametrize("name,kw", CASES)
+# the full-size systems of the bench's 2D, time-step and 3D legs (4,096 and
+# 2,048 elements), in the launch configuration the bench times
+FULL = [("c1_2d_128x32", {}), ("c4_2d_128x32_cn", {}), ("c3_3d_32x8x8", {})]
+
+
+@pytest.mark.parametrize("name,kw", CASES + FULL)
 def test_device_assembly_equals_the_builders(name, kw):
     s, coeffs, p, asm = _setup(name, kw)
     r, jv = asm.run(dev(p.y))
