@@ -36,8 +36,6 @@ __device__ __forceinline__ D1 operator/(D1 a, D1 b) {
   const double q = a.v / b.v;
   return {q, (a.g - q * b.g) / b.v};
 }
-__device__ __forceinline__ double val(double x) { return x; }
-__device__ __forceinline__ double val(D1 x) { return x.v; }
 
 struct AsmView {
   int ne, ndof, ncolor;
