@@ -1178,7 +1178,7 @@ __global__ __launch_bounds__(256) void k_cgj_dcheck(const int *__restrict__ dlis
   smin[threadIdx.x] = mine;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) smin[threadIdx.x] = min(smin[threadIdx.x], smin[threadIdx.x + h]);
+    if ((int)threadIdx.x < h) smin[threadIdx.x] = min(smin[threadIdx.x], smin[threadIdx.x + h]);
     __syncthreads();
   }
   if (threadIdx.x == 0 && status[0] == 0 && smin[0] != INT_MAX) status[0] = 1 + nf + smin[0];
