@@ -1352,7 +1352,7 @@ __global__ __launch_bounds__(kKrylovThreads) void k_kupdate_dot(
   chunk_range(n, r0, r1);
   finish_cols(pin, gridDim.x, k, hs);
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x < k) h1[threadIdx.x] = hs[threadIdx.x];
+  if (blockIdx.x == 0 && (int)threadIdx.x < k) h1[threadIdx.x] = hs[threadIdx.x];
   (void)chunk_update(V, ldv, k, hs, w, r0, r1, ws);
   __syncthreads();
   chunk_dots<true>(V, ldv, k, ws, r0, r1, pout);
@@ -1370,7 +1370,7 @@ __global__ __launch_bounds__(kKrylovThreads) void k_kupdate_norm(
   chunk_range(n, r0, r1);
   finish_cols(pin, gridDim.x, k, hs);
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x < k) h1[threadIdx.x] = SET ? hs[threadIdx.x] : h1[threadIdx.x] + hs[threadIdx.x];
+  if (blockIdx.x == 0 && (int)threadIdx.x < k) h1[threadIdx.x] = SET ? hs[threadIdx.x] : h1[threadIdx.x] + hs[threadIdx.x];
   const double nacc = wave_sum(chunk_update(V, ldv, k, hs, w, r0, r1, nullptr));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nacc;
   __syncthreads();
@@ -1439,7 +1439,7 @@ void launch_backsolve(const double *H, int ldh, const double *g, int k, double *
 __global__ void k_zupdate(int n, const double *__restrict__ Z, int64_t ldz, int k,
                           const double *__restrict__ y, double *__restrict__ x) {
   __shared__ double ys[64];
-  if (threadIdx.x < k) ys[threadIdx.x] = y[threadIdx.x];
+  if ((int)threadIdx.x < k) ys[threadIdx.x] = y[threadIdx.x];
   __syncthreads();
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
