@@ -360,7 +360,7 @@ struct ElemOut {
 // J0 u0) phi plus half of each Piola term; incompressibility at t_{n+1};
 // kinematics -(d1 - d0)/dt + (u1 + u0)/2 against phi.
 template <int DIM, int NL>
-static void element(const Mesh &M, const Tab &T, const fsi_problem_spec &s, bool solid, const double *ye,
+static void element(const Mesh &, const Tab &T, const fsi_problem_spec &s, bool solid, const double *ye,
                     const double *ye0, ElemOut<DIM, NL> &out, bool want_grad) {
   constexpr int NA = DIM == 3 ? 27 : 9;
   constexpr int NP = DIM + 1;
