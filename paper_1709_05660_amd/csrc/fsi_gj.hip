@@ -710,6 +710,8 @@ bool gj_variant_ok(int variant, int mmax) {
 
 bool gj_variant_f32(int variant) { return variant >= kGjF64x512; }
 
+int gj_variant_threads(int variant) { return variant == kGj16x256 || variant == kGjF32x256 ? 256 : 512; }
+
 int gj_batched_grid(int npatch) {
   // as many workgroups as the fewest rounds over the compute units need:
   // the rest of the device stays free for the coarsest inversion

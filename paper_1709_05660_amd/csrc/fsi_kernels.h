@@ -61,6 +61,7 @@ enum GjVariant { kGjAuto = 0, kGj16x256 = 1, kGj16x512 = 2, kGj32x512 = 3, kGjWi
                  kGjF64x512 = 11, kGjF32x512 = 12, kGjF32x256 = 13, kGjF32x512r2 = 14, kGjF48x512r2 = 15 };
 bool gj_variant_ok(int variant, int mmax);
 bool gj_variant_f32(int variant);
+int gj_variant_threads(int variant);   // threads per workgroup of a variant
 // workgroups of the batched inversion for npatch blocks (the fewest rounds
 // over the compute units), and the host-built schedule: grid + 1 offsets
 // into the block list that follows them (grid + 1 + npatch ints)

@@ -2202,9 +2202,18 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
           mg.mixed ? std::vector<int>{kGjF64x512, kGjF32x512, kGjF32x256, kGjF32x512r2, kGjF48x512r2}
                    : std::vector<int>{kGj16x256, kGj16x512, kGj32x512, kGjWideG, kGj24x512, kGjP32x512};
       std::vector<std::tuple<float, int, int>> timed;   // (ms, variant, grid)
+      // a 512-thread workgroup fills a compute unit: such variants keep at
+      // least 40 units free for the coarsest inversion's chain on the side
+      // stream.  With more workgroups than units the batched launch holds
+      // every unit until its last block is dispatched, and whether the chain
+      // overlaps it then depends on which launch reaches the device first
+      // (back to back here it often does; after a solve it did not, and the
+      // refactor took the two one after the other)
+      auto grid_ok = [&](int var, int g) { return gj_variant_threads(var) < 512 || g <= ncu - 40; };
       for (int var : vars) {
         if (!gj_variant_ok(var, mg.mmax_all)) continue;
         for (int g : grids) {
+          if (!grid_ok(var, g)) continue;
           set_gj_grid(mg, g, st);
           const float ms = time_events(st, [&] {
             extract_blocks(mg, st);
@@ -2223,7 +2232,8 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
         if (std::find(top_vars.begin(), top_vars.end(), std::get<1>(t)) == top_vars.end() && top_vars.size() < 2)
           top_vars.push_back(std::get<1>(t));
       for (int v : top_vars)
-        for (int g : grids) finals.push_back({v, g});
+        for (int g : grids)
+          if (grid_ok(v, g)) finals.push_back({v, g});
       double best_ms = 1e300;
       for (auto &fg : finals) {
         mg.gj_variant = fg.first;
