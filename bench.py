@@ -763,6 +763,8 @@ def serve_leg(args):
         srv.close()
         lat = np.array([done_at[i] - sub_at[i] for i in range(len(plist))]) * 1e3
         span = max(done_at.values()) - min(sub_at.values())
+        print(f"served {len(plist)} systems ({precision}{', batched' if batched else ''}) in {span:.2f} s",
+              file=sys.stderr, flush=True)
         return {"solves_per_s": round(len(plist) / span, 2),
                 "dof_per_s": round(sum(p.n for p in plist) / span, 1),
                 "p50_ms": round(float(np.percentile(lat, 50)), 2),
@@ -928,6 +930,7 @@ def main():
     ap.add_argument("--steps-3d", type=int, default=5)
     ap.add_argument("--only-3d", action="store_true")
     ap.add_argument("--only-time-step", action="store_true")
+    ap.add_argument("--only-serve", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true")
     ap.add_argument("--serve-n", type=int, default=256)
     ap.add_argument("--serve-budget-gb", type=int, default=4)
@@ -948,6 +951,10 @@ def main():
     if args.only_time_step:
         # profiling aid: the time-step leg alone, its own JSON line
         print(json.dumps({"time_step": time_step_leg(args)}), flush=True)
+        return
+    if args.only_serve:
+        # profiling aid: the serving leg alone, its own JSON line
+        print(json.dumps({"served": serve_leg(args)}), flush=True)
         return
     g = gpu_leg(args)
     value = args.steps / (g["ms_per_step"] * args.steps * 1e-3)
