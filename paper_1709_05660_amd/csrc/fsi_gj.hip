@@ -777,7 +777,8 @@ void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const
                        const int *sched, hipStream_t st, int variant, hipEvent_t ev0, hipEvent_t ev1) {
   if (npatch == 0) return;
   if (!gj_variant_ok(variant, mmax))
-    variant = gj_variant_ok(kGj32x512, mmax)   ? kGj32x512
+    variant = gj_variant_ok(kGjP32x512, mmax)  ? kGjP32x512
+              : gj_variant_ok(kGj32x512, mmax) ? kGj32x512
               : gj_variant_ok(kGj24x512, mmax) ? kGj24x512
                                                : kGj16x256;
   const bool small = mmax <= 512;

@@ -50,8 +50,8 @@ void launch_extract(const double *val, int64_t nslots, const int *src, const int
 // a wide panel read back from the block itself (NB 32 for m <= 512, 24 for
 // m <= 1024, 512 threads), and NB 24 on 512 threads with the panel in LDS
 // (where m 25 doubles fit beside the static LDS, m <= ~790).  An
-// unsupported or zero variant falls back to the first that fits of NB 32,
-// NB 24 (both with the LDS panel) and NB 16 on 256 threads
+// unsupported or zero variant falls back to the first that fits of NB 32
+// pairs, NB 32, NB 24 (both with the LDS panel) and NB 16 on 256 threads
 // Paired panels (k_gj_paired, blocks up to 512 dofs): two panels of NB 32
 // (one row per thread) factored in turn, the rest of the block updated once
 // per pair.
