@@ -85,7 +85,8 @@ GJ_VARIANTS = {1: ("NB16 x 256, FP64", 16, 8), 2: ("NB16 x 512, FP64", 16, 8),
                6: ("NB32 pairs x 512, FP64", 64, 8),
                11: ("NB64 x 512, FP32", 64, 4),
                12: ("NB32 x 512, FP32", 32, 4), 13: ("NB32 x 256 (2 rows/thread), FP32", 32, 4),
-               14: ("NB32 x 512 (2 rows/thread), FP32", 32, 4), 15: ("NB48 x 512 (2 rows/thread), FP32", 48, 4)}
+               14: ("NB32 x 512 (2 rows/thread), FP32", 32, 4), 15: ("NB48 x 512 (2 rows/thread), FP32", 48, 4),
+               16: ("NB32 pairs x 512, FP32", 64, 4)}
 
 
 _TUNING_DB = None

@@ -684,6 +684,8 @@ bool gj_variant_ok(int variant, int mmax) {
   switch (variant) {
     case kGjP32x512:
       return gj_paired_fits<double, 32, 1, 512>(mmax);
+    case kGjPF32x512:
+      return gj_paired_fits<float, 32, 1, 512>(mmax);
     case kGj16x256:
     case kGj16x512:
       return mmax <= 1024;
@@ -709,8 +711,6 @@ bool gj_variant_ok(int variant, int mmax) {
 }
 
 bool gj_variant_f32(int variant) { return variant >= kGjF64x512; }
-
-int gj_variant_threads(int variant) { return variant == kGj16x256 || variant == kGjF32x256 ? 256 : 512; }
 
 int gj_batched_grid(int npatch) {
   // as many workgroups as the fewest rounds over the compute units need:
@@ -829,6 +829,9 @@ void launch_gj_batched_f32(float *blocks, const int64_t *boff, const int *pm, co
       }
   }
   switch (variant) {
+    case kGjPF32x512:
+      launch_gj_paired<32, 1, 512>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
+      break;
     case kGjF64x512:
       launch_gj_nbr<64, 1, 512, false>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
       break;

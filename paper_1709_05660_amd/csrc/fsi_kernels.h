@@ -58,10 +58,10 @@ void launch_extract(const double *val, int64_t nslots, const int *src, const int
 enum GjVariant { kGjAuto = 0, kGj16x256 = 1, kGj16x512 = 2, kGj32x512 = 3, kGjWideG = 4, kGj24x512 = 5,
                  kGjP32x512 = 6,
                  // FP32 working matrices (mixed forms): panel width x threads (x rows per thread)
-                 kGjF64x512 = 11, kGjF32x512 = 12, kGjF32x256 = 13, kGjF32x512r2 = 14, kGjF48x512r2 = 15 };
+                 kGjF64x512 = 11, kGjF32x512 = 12, kGjF32x256 = 13, kGjF32x512r2 = 14, kGjF48x512r2 = 15,
+                 kGjPF32x512 = 16 };
 bool gj_variant_ok(int variant, int mmax);
 bool gj_variant_f32(int variant);
-int gj_variant_threads(int variant);   // threads per workgroup of a variant
 // workgroups of the batched inversion for npatch blocks (the fewest rounds
 // over the compute units), and the host-built schedule: grid + 1 offsets
 // into the block list that follows them (grid + 1 + npatch ints)

@@ -2199,17 +2199,22 @@ int autotune(MG &mg, const char *db_path, hipStream_t st) {
         if (std::find(grids.begin(), grids.end(), g) == grids.end()) grids.push_back(g);
       }
       const std::vector<int> vars =
-          mg.mixed ? std::vector<int>{kGjF64x512, kGjF32x512, kGjF32x256, kGjF32x512r2, kGjF48x512r2}
+          mg.mixed ? std::vector<int>{kGjF64x512, kGjF32x512, kGjF32x256, kGjF32x512r2, kGjF48x512r2, kGjPF32x512}
                    : std::vector<int>{kGj16x256, kGj16x512, kGj32x512, kGjWideG, kGj24x512, kGjP32x512};
       std::vector<std::tuple<float, int, int>> timed;   // (ms, variant, grid)
-      // a 512-thread workgroup fills a compute unit: such variants keep at
-      // least 40 units free for the coarsest inversion's chain on the side
-      // stream.  With more workgroups than units the batched launch holds
-      // every unit until its last block is dispatched, and whether the chain
-      // overlaps it then depends on which launch reaches the device first
-      // (back to back here it often does; after a solve it did not, and the
-      // refactor took the two one after the other)
-      auto grid_ok = [&](int var, int g) { return gj_variant_threads(var) < 512 || g <= ncu - 40; };
+      // every variant keeps at least 40 compute units free for the coarsest
+      // inversion's chain on the side stream.  With more workgroups than
+      // units the batched launch occupies every unit (the first ncu
+      // workgroups go one to a unit, 256-thread ones too) until its last
+      // block is dispatched, and whether the chain overlaps it then depends
+      // on which launch reaches the device first: back to back here it
+      // often does, after a solve it did not, and the refactor took the two
+      // one after the other
+      // (on a small device: at most half the units, and the smallest grid is
+      // always allowed)
+      const int gcap = std::max(ncu - 40, (ncu + 1) / 2);
+      const int gmin = *std::min_element(grids.begin(), grids.end());
+      auto grid_ok = [&](int, int g) { return g <= gcap || g == gmin; };
       for (int var : vars) {
         if (!gj_variant_ok(var, mg.mmax_all)) continue;
         for (int g : grids) {

@@ -360,3 +360,45 @@ def test_every_block_inversion_variant(name, kw, tmp_path):
         assert np.array_equal(zs[3], zs[4])
     else:                        # NB 24 likewise (blocks above 512 dofs)
         assert np.array_equal(zs[4], zs[5])
+
+
+@pytest.mark.parametrize("name", ["c0_2d_16x4", "c1_2d_128x32"])
+def test_every_fp32_inversion_variant(name, tmp_path):
+    """Each batched Gauss-Jordan variant of the mixed forms (FP32 working
+    matrices: panel width x threads, rows per thread, single or paired
+    panels), forced through the tuning database, gives a bf16 solve that
+    reaches a true relative residual of 1e-8 and agrees with the FP64 solve
+    to 1e-7 (the blocks of both systems fit every variant)."""
+    from paper_1709_05660_amd import MG
+    p = product_problem(name)
+    mg64 = MG(p, precision="fp64")
+    x64, _ = mg64.fgmres(dev(p.b), restart=30, rtol=1e-10)
+    x64 = host(x64)
+    mg64.close()
+    db = str(tmp_path / "tune.db")
+    mg = MG(p, precision="bf16")
+    mg.autotune(db)
+    mg.close()
+    lines = [l for l in open(db).read().split("\n") if l]
+    assert any(l.startswith("gj3:f32:") for l in lines)
+    # 11: NB 64; 12: NB 32; 13: NB 32 on 256 threads; 14, 15: NB 32, 48 with
+    # two rows per thread; 16: paired NB 32
+    for v in (11, 12, 13, 14, 15, 16):
+        forced = db + f".v{v}"
+        with open(forced, "w") as f:
+            for l in lines:
+                k, val = l.split()
+                if k.startswith("gj3:f32:"):
+                    val = v
+                elif k.startswith("gjg:f32:"):
+                    k = k.rsplit(":", 1)[0] + f":{v}"
+                f.write(f"{k} {val}\n")
+        mg = MG(p, precision="bf16")
+        assert mg.autotune(forced) == 0
+        mg.refactor()
+        x, info = mg.fgmres(dev(p.b), restart=30, rtol=1e-8)
+        err = np.linalg.norm(host(x) - x64) / np.linalg.norm(x64)
+        _say(name, "fp32 variant", v, "iters", info["iters"], "true", info["true_relres"], "err vs fp64", err)
+        assert info["converged"] == 1 and info["true_relres"] <= 1e-8
+        assert err <= 1e-7
+        mg.close()
