@@ -810,11 +810,13 @@ void launch_gj_batched(double *blocks, const int64_t *boff, const int *pm, const
     launch_gj_nbr<16, 4, 256, true>(blocks, boff, pm, poff, perm, used, grid, sched, mmax, status, st, ev0, ev1);
 }
 
-// FP32 working matrices (the mixed forms): NB 64 on 512 threads (one row per
-// thread), NB 32 on 512 or on 256 threads (two rows per thread: two
-// workgroups fit a compute unit), NB 32 or 48 on 512 threads with two rows
-// per thread (blocks up to 1024 dofs); every variant keeps the panel in LDS.
-// An unsupported variant falls back to the first that fits of these.
+// FP32 working matrices (the mixed forms): paired NB 32 panels on 512
+// threads (blocks up to 512 dofs, the panel read back from the block), NB 64
+// on 512 threads (one row per thread), NB 32 on 512 or on 256 threads (two
+// rows per thread: two workgroups fit a compute unit), NB 32 or 48 on 512
+// threads with two rows per thread (blocks up to 1024 dofs), these with the
+// panel in LDS.  An unsupported variant falls back to the first that fits of
+// paired NB 32, NB 64, NB 32, NB 48 and NB 32 with two rows per thread.
 void launch_gj_batched_f32(float *blocks, const int64_t *boff, const int *pm, const int64_t *poff,
                            int *perm, int *used, int npatch, int mmax, int *status, int grid,
                            const int *sched, hipStream_t st, int variant, hipEvent_t ev0,
@@ -822,7 +824,7 @@ void launch_gj_batched_f32(float *blocks, const int64_t *boff, const int *pm, co
   if (npatch == 0) return;
   if (!gj_variant_f32(variant) || !gj_variant_ok(variant, mmax)) {
     variant = kGjF32x512r2;
-    for (int v : {kGjF64x512, kGjF32x512, kGjF48x512r2, kGjF32x512r2})
+    for (int v : {kGjPF32x512, kGjF64x512, kGjF32x512, kGjF48x512r2, kGjF32x512r2})
       if (gj_variant_ok(v, mmax)) {
         variant = v;
         break;
