@@ -616,6 +616,13 @@ def gpu_leg(args):
                     "true_relres": im[-1]["true_relres"], "err_vs_fp64": err,
                     "refactor_ms": im[-1]["setup_ms"], "block_inversion_ms": gm / max(gc, 1),
                     "solve_ms": im[-1]["solve_ms"], "vcycle_ms": vcycle_ms(mgm)}
+                if key == "mixed":
+                    # the FP32 inversion's variant and grid as the autotuner chose them
+                    ch = tuning_choices(tune_db)
+                    out[key]["inversion_variant"] = {k: v for k, v in ch.get("gj_variant", {}).items()
+                                                     if k.startswith("gj3:f32:")}
+                    out[key]["inversion_grid"] = {k: v for k, v in ch.get("gj_grid", {}).items()
+                                                  if k.startswith("gjg:f32:")}
                 mgm.close()
     out["n"] = p.n
     return out
