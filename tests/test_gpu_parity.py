@@ -362,15 +362,16 @@ def test_every_block_inversion_variant(name, kw, tmp_path):
         assert np.array_equal(zs[4], zs[5])
 
 
-@pytest.mark.parametrize("name", ["c0_2d_16x4", "c1_2d_128x32"])
-def test_every_fp32_inversion_variant(name, tmp_path):
+@pytest.mark.parametrize("name,kw", [("c0_2d_16x4", {}), ("c0_2d_16x4", {"patch": 1}), ("c1_2d_128x32", {})])
+def test_every_fp32_inversion_variant(name, kw, tmp_path):
     """Each batched Gauss-Jordan variant of the mixed forms (FP32 working
     matrices: panel width x threads, rows per thread, single or paired
     panels), forced through the tuning database, gives a bf16 solve that
     reaches a true relative residual of 1e-8 and agrees with the FP64 solve
-    to 1e-7 (the blocks of both systems fit every variant)."""
+    to 1e-7 (the blocks of these systems fit every variant; with one-element
+    patches every block is one pair of panels)."""
     from paper_1709_05660_amd import MG
-    p = product_problem(name)
+    p = product_problem(name, **kw)
     mg64 = MG(p, precision="fp64")
     x64, _ = mg64.fgmres(dev(p.b), restart=30, rtol=1e-10)
     x64 = host(x64)
