@@ -507,9 +507,17 @@ __global__ void k_neg_free(const double *r, const uint8_t *dir, int n, double *b
   if (i < n) b[i] = dir[i] ? 0.0 : -r[i];
 }
 
-// device memory of the assembler (plain allocations, freed at destroy)
+// device memory of the assembler: plain allocations owned here, freed when
+// the assembler is destroyed or when its creation fails part way
 struct AsmMem {
   std::vector<void *> v;
+  AsmMem() = default;
+  AsmMem(const AsmMem &) = delete;
+  AsmMem &operator=(const AsmMem &) = delete;
+  ~AsmMem() {
+    if (!v.empty()) (void)hipDeviceSynchronize();   // no kernel of a failed creation still reads them
+    for (void *p : v) (void)hipFree(p);
+  }
   template <typename T>
   T *alloc(int64_t n) {
     void *p = nullptr;
@@ -818,8 +826,7 @@ fsi_status fsi_assembly_destroy(struct fsi_assembly *h) {
   Assembly *A = reinterpret_cast<Assembly *>(h);
   if (!A) return FSI_OK;
   (void)hipDeviceSynchronize();
-  for (void *p : A->mem.v) (void)hipFree(p);
-  delete A;
+  delete A;   // frees its device memory
   return FSI_OK;
 }
 

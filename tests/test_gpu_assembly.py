@@ -112,3 +112,44 @@ def test_newton_on_the_device_solves_the_time_step(name):
     assert np.all(y[flags] == p.y[flags])           # Dirichlet values kept
     mg.close()
     asm.close()
+
+
+def test_failed_creation_frees_its_memory():
+    """A creation that fails after uploading the element data (here: a
+    Dirichlet row of the pattern without its diagonal) returns FSI_E_INVALID
+    and frees what it allocated: ten such failures hold no more device memory
+    than one (the runtime may keep freed blocks for reuse), where each would
+    otherwise keep about 14 MB; a valid assembler beside them still equals
+    the builder."""
+    import ctypes as C
+
+    import torch
+
+    from paper_1709_05660_amd import _lib as L
+    from paper_1709_05660_amd.solver import _stream
+    s, coeffs, p, asm = _setup("c1_2d_128x32", {})
+    ed, J = asm.ed, p.levels[p.nlevels - 1].J
+    rp = np.ctypeslib.as_array(J.rowptr, shape=(J.nrows + 1,))
+    col = np.ctypeslib.as_array(J.colind, shape=(J.nnz,)).copy()
+    dirf = np.ctypeslib.as_array(ed.dirichlet, shape=(ed.ndof,))
+    i = int(np.flatnonzero(dirf)[0])
+    pos = int(rp[i] + np.flatnonzero(col[rp[i]:rp[i + 1]] == i)[0])
+    col[pos] = i + 1 if i + 1 < J.ncols else i - 1
+    bad = L.Csr(J.nrows, J.ncols, J.nnz, J.rowptr, col.ctypes.data_as(C.POINTER(C.c_int32)), J.val)
+
+    def fail_once():
+        h = C.c_void_p()
+        st = L.lib().fsi_assembly_create(C.byref(ed), C.byref(bad), _stream(), C.byref(h))
+        assert st == L.FSI_E_INVALID and not h.value
+        torch.cuda.synchronize()
+        return torch.cuda.mem_get_info()[0]
+
+    free1 = fail_once()
+    for _ in range(9):
+        free10 = fail_once()
+    _say(f"device memory held by nine more failed creations: {(free1 - free10) / 2**20:.1f} MiB")
+    assert free1 - free10 < 4 << 20
+    r, jv = asm.run(dev(p.y))
+    Jh = csr_of(p, p.nlevels - 1)
+    assert np.abs(host(jv) - Jh.data).max() <= 1e-12 * np.abs(Jh.data).max()
+    asm.close()
